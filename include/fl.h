@@ -1,0 +1,233 @@
+/*
+ * fl.h -- C ABI of the MI355X (gfx950) Faugere-Lachartre reduction library.
+ *
+ * The library implements the FL reduction of a sparse matrix M over F_p,
+ * p prime, 2 <= p <= 65521, stored as uint16 residues, following the GBLA
+ * paper (Boyer, Eder, Faugere, Lachartre, Martani, arXiv 1602.06097),
+ * Sec. 4.1 ("The reduction by Faugere and Lachartre"):
+ *
+ *   step 1  fl_split      splice M into [A B; C D] by pivot columns
+ *   step 2  fl_trsm       X = A^{-1} B                      (the TRSM)
+ *   step 3  fl_reduce_cd  Dt = D - C X                       (the AXPY step)
+ *   step 4  fl_echelon_d  RREF of Dt: rank r, pivot columns P_D
+ *   step 5  fl_rref       second pass X' = X - X[:,P_D] RREF(Dt), then
+ *                         fl_rref_csr_size / fl_rref_to_csr read off RREF(M)
+ *                         in original column order (column rearrangement).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer, allocated and owned by the
+ *    caller; the library allocates no device memory and keeps no pointer
+ *    after the enqueued work completes.  Pointers to the fl_split_info and
+ *    fl_split_out structs themselves, and h_* arguments, are HOST pointers.
+ *  - Work is enqueued on the caller's `stream` (0 = the null stream).  Only
+ *    fl_split and fl_rref_csr_size synchronise that stream (once each, to
+ *    return sizes to the host).
+ *  - Residues are canonical: every value is in [0, p).
+ *  - Dense matrices are row-major uint16 with a leading dimension (row
+ *    stride, in elements) `ld` that must satisfy ld >= cols and ld % 4 == 0;
+ *    base pointers must be 8-byte aligned.  Columns in [cols, ld) are
+ *    padding: they are read but never written, and never affect results.
+ *  - Workspace: every call that needs scratch memory takes `ws`/`ws_bytes`
+ *    (device memory, no alignment beyond 256 bytes required); the matching
+ *    fl_*_workspace() function returns the required size.
+ *  - Errors: host-checkable problems (NULL pointers, p out of range, bad
+ *    dimensions, ld too small or misaligned, ml_width not in {1,2,4,8},
+ *    workspace too small) return immediately with nothing enqueued.  Data
+ *    errors in M are detected by fl_split's validation pass and reported at
+ *    its synchronisation; later calls assume validated, split data.  HIP
+ *    runtime failures return FL_ERR_HIP; fl_last_error() then holds the HIP
+ *    error string (thread-local).  p must be prime; this is not checked.
+ */
+#ifndef FL_H
+#define FL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FL_OK = 0,
+    FL_ERR_ARG = 1,            /* invalid argument (host-checked)            */
+    FL_ERR_WORKSPACE = 2,      /* ws_bytes smaller than fl_*_workspace()     */
+    FL_ERR_DATA_ROWPTR = 3,    /* row_ptr[0] != 0, decreasing, or != nnz     */
+    FL_ERR_DATA_COL_RANGE = 4, /* a column index >= n                        */
+    FL_ERR_DATA_COL_ORDER = 5, /* columns of a row not strictly increasing   */
+    FL_ERR_DATA_VALUE = 6,     /* a value == 0 or >= p                       */
+    FL_ERR_HIP = 7             /* HIP runtime error, see fl_last_error()     */
+} fl_status;
+
+/* Arithmetic form of the dense contractions.  Both give bit-identical
+ * results.  FL_PLAIN: 32-bit VALU multiply-adds with delayed reduction.
+ * FL_MFMA_I8: centred residues split into two signed 8-bit limbs, products
+ * on the int8 matrix cores with exact int32 accumulation, recombined and
+ * reduced mod p. */
+typedef enum { FL_PLAIN = 0, FL_MFMA_I8 = 1 } fl_mode;
+
+/* Sparse input (Sec. 3.2, Format 1 is this CSR layout).  Device pointers. */
+typedef struct {
+    uint32_t rows, cols;
+    uint64_t nnz;
+    const uint64_t *row_ptr; /* [rows + 1], row_ptr[0] = 0, row_ptr[rows] = nnz */
+    const uint32_t *col;     /* [nnz], strictly increasing within each row       */
+    const uint16_t *val;     /* [nnz], in [1, p-1]                               */
+} fl_csr;
+
+/*
+ * Outputs of fl_split (device buffers, caller-allocated with the capacities
+ * given, which depend only on m, n, nnz(M) and ml_width w -- the pivot count
+ * is not known in advance).
+ *
+ * A and C are stored as w-multiline vectors (Sec. 4.2, the multiline
+ * Definition): rows are grouped w at a time (group g = rows g*w .. g*w+w-1);
+ * pos[gptr[g] .. gptr[g+1]) lists, ascending, every column where one of the
+ * group's rows is nonzero, and val[w*k + q] is row q's entry at pos[k]
+ * (zero allowed).  A holds only the strictly upper part of the unit upper
+ * triangular npiv x npiv block (its unit diagonal is implicit).  B and D are
+ * CSR.  Column indices of A, C are in [0, npiv); of B, D in [0, n - npiv).
+ */
+typedef struct {
+    uint32_t *row_perm;  /* [m]  new row position -> input row               */
+    uint32_t *col_perm;  /* [n]  new column position -> input column         */
+    uint64_t *a_gptr;    /* [ceil(m/w) + 1]                                   */
+    uint32_t *a_pos;     /* [nnz]                                             */
+    uint16_t *a_val;     /* [w * nnz]                                         */
+    uint64_t *b_ptr;     /* [m + 1]                                           */
+    uint32_t *b_col;     /* [nnz]                                             */
+    uint16_t *b_val;     /* [nnz]                                             */
+    uint64_t *c_gptr;    /* [ceil(m/w) + 1]                                   */
+    uint32_t *c_pos;     /* [nnz]                                             */
+    uint16_t *c_val;     /* [w * nnz]                                         */
+    uint64_t *d_ptr;     /* [m + 1]                                           */
+    uint32_t *d_col;     /* [nnz]                                             */
+    uint16_t *d_val;     /* [nnz]                                             */
+} fl_split_out;
+
+/* Sizes returned by fl_split (host struct). */
+typedef struct {
+    uint32_t p, m, n, ml_width;
+    uint32_t npiv;        /* number of pivot columns = rows of A and B        */
+    uint32_t nB;          /* n - npiv                                          */
+    uint32_t mD;          /* m - npiv                                          */
+    uint32_t status;      /* fl_status of the validation pass                  */
+    uint64_t nnz;         /* nnz(M)                                            */
+    uint64_t nnzA;        /* strictly upper entries of A                       */
+    uint64_t nnzB, nnzC, nnzD;
+    uint64_t lenA, lenC;  /* multiline lengths: gptr[last] of A and C          */
+} fl_split_info;
+
+/* ---- step 1 --------------------------------------------------------------
+ * fl_split -- Sec. 3.1 (pivoting candidates, pivot columns, pivot-row
+ * selection keeping A sparse) and Sec. 4.1 step 1 (the splice [A B; C D]).
+ *   - validates M (columns < n and strictly increasing, values in [1, p-1],
+ *     row_ptr monotone from 0 to nnz);
+ *   - the pivoting candidate of a row is its first entry; pivot columns are
+ *     the columns holding a candidate;
+ *   - pivot row of a pivot column: the candidate row with the fewest
+ *     nonzeros, ties to the lowest input row index;
+ *   - column order: pivot columns ascending, then the others ascending;
+ *     row order: pivot rows by pivot column, then the other rows (including
+ *     empty rows) in input order;
+ *   - pivot rows are scaled by the inverse of their leading coefficient
+ *     (a no-op for monic rows); other rows are copied unchanged.
+ * ml_width w in {1, 2, 4, 8} is the multiline width of A and C.
+ * Synchronises `stream` once and fills *h_info.  Returns the validation
+ * status (FL_ERR_DATA_*) if M is malformed; outputs are then undefined. */
+fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width, const fl_split_out *out,
+                   fl_split_info *h_info, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint32_t ml_width);
+
+/* ---- step 2 --------------------------------------------------------------
+ * fl_trsm -- Sec. 4.1 step 2: X = A^{-1} B mod p, A unit upper triangular,
+ * by back substitution over blocks of rows from the bottom up, using the
+ * multiline rows of A (Sec. 4.2: one read of a row of X serves the w rows of
+ * a multiline).  X: dense npiv x nB (ld = ldx).  B is read from out->b_*. */
+fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
+                  void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_trsm_workspace(const fl_split_info *info);
+
+/* ---- step 3 --------------------------------------------------------------
+ * fl_reduce_cd -- Sec. 4.1 step 3: Dt = D - C X mod p (C reduced to zero by
+ * the identity, the same operations applied to D).  Dt: dense mD x nB
+ * (ld = ldd).  FL_PLAIN multiplies the sparse multiline rows of C; FL_MFMA_I8
+ * multiplies C as a dense int8-limb operand on the matrix cores. */
+fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out *s, const uint16_t *X,
+                       uint64_t ldx, uint16_t *Dt, uint64_t ldd, fl_mode mode, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode);
+
+/* ---- step 4 --------------------------------------------------------------
+ * fl_echelon_d -- Sec. 4.1 step 4 / Sec. 4.4, read as the REDUCED row
+ * echelon form of the dense rows x cols matrix Dt, in place: on return rows
+ * 0..r-1 hold RREF(Dt) with pivot columns ascending, rows r.. are zero,
+ * *d_rank = r and d_pivcol[0..r) the pivot columns (device outputs;
+ * d_pivcol capacity min(rows, cols)).  Blocked Gauss-Jordan over column
+ * panels: pivot search in the panel, then a rank-k update of all other rows. */
+fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt, uint64_t ldd,
+                       uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+size_t fl_echelon_d_workspace(uint32_t rows, uint32_t cols, fl_mode mode);
+
+/* ---- step 5 --------------------------------------------------------------
+ * fl_rref -- end of Sec. 4.1: the FL reduction run a second time on the
+ * right part [A^{-1}B ; D'], which for D' = RREF(Dt) amounts to
+ *     X' = X - X[:, P_D] * RREF(Dt)   (in place on X; X'[:, P_D] = 0).
+ * Then [Id X'; 0 RREF(Dt)] is RREF(M) in the permuted column order.
+ * RD: the output of fl_echelon_d (ld = ldd); d_rank/d_pivcol as returned. */
+fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
+                  const uint16_t *RD, uint64_t ldd, const uint32_t *d_rank,
+                  const uint32_t *d_pivcol, fl_mode mode, void *ws, size_t ws_bytes,
+                  hipStream_t stream);
+size_t fl_rref_workspace(const fl_split_info *info, fl_mode mode);
+
+/* Sec. 4.1 step 5 (column rearrangement and read-off) as canonical CSR of
+ * RREF(M) in the ORIGINAL column order: one row per pivot (rank = npiv + r
+ * rows), rows sorted by pivot column, columns ascending, no zero entries,
+ * leading entry 1.
+ * fl_rref_csr_size writes row_ptr[rank + 1] (device, capacity
+ * npiv + min(mD, nB) + 1), synchronises `stream` and returns the rank and
+ * the nonzero count through h_rank / h_nnz.
+ * fl_rref_to_csr then fills col[nnz] and val[nnz] (device) given row_ptr. */
+fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                           uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                           const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
+                           uint32_t *h_rank, uint64_t *h_nnz, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                         uint64_t ldx, const uint16_t *RD, uint64_t ldd, const uint32_t *d_rank,
+                         const uint32_t *d_pivcol, const uint64_t *row_ptr, uint32_t *col,
+                         uint16_t *val, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_rref_csr_workspace(const fl_split_info *info);
+
+/* ---- dense contraction ------------------------------------------------------
+ * fl_matmul_sub -- the dense form of the step-3 contraction:
+ *     Dm = Dm - Cm * Xm mod p,  Cm: M x K (ld ldc), Xm: K x N (ld ldx),
+ *     Dm: M x N (ld ldd), all dense uint16 residues, in place on Dm.
+ * Used when C is dense; bit-identical in both modes. */
+fl_status fl_matmul_sub(uint32_t p, uint32_t M, uint32_t N, uint32_t K, const uint16_t *Cm,
+                        uint64_t ldc, const uint16_t *Xm, uint64_t ldx, uint16_t *Dm,
+                        uint64_t ldd, fl_mode mode, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+size_t fl_matmul_sub_workspace(uint32_t M, uint32_t N, uint32_t K, fl_mode mode);
+
+/* ---- helpers ----------------------------------------------------------------- */
+const char *fl_status_string(fl_status s);
+const char *fl_last_error(void);   /* thread-local; "" if none */
+/* Version string of the device library ("fl-gfx950 <semver>"). */
+const char *fl_version(void);
+
+/* Device self-check of the modular reduction used by every kernel: for each
+ * prime in p_list, compares the kernels' reduction of every x in [0, 2^32)
+ * against the remainder x % p and returns the number of mismatches through
+ * d_mismatch (device, one uint64 per prime).  Diagnostic only. */
+fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count, uint64_t *d_mismatch,
+                        hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FL_H */

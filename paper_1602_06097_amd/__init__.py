@@ -1,0 +1,288 @@
+"""Python binding of libfl, the gfx950 Faugere-Lachartre reduction library.
+
+Argument marshalling only: every step of the reduction runs in the device
+library's HIP kernels.  PyTorch provides device memory (``torch.empty`` on
+``cuda``, which is HIP on ROCm) and the current stream handle.  If libfl.so
+is missing the import of any entry point raises -- there is no CPU fallback.
+
+The function names mirror the C ABI in include/fl.h:
+
+    sp = split(M, p, ml_width)            # FL step 1 (syncs once)
+    X  = trsm(sp)                         # step 2: X = A^{-1} B
+    Dt = reduce_cd(sp, X, mode)           # step 3: Dt = D - C X
+    ech = echelon_d(Dt, p, mD, nB, mode)  # step 4: RREF(Dt) in place
+    rref(sp, X, Dt, ech, mode)            # second pass: X <- X'
+    R = rref_to_csr(sp, X, Dt, ech)       # step 5: RREF(M) as CSR
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd",
+           "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp",
+           "version", "Split", "Echelon"]
+
+FL_PLAIN, FL_MFMA_I8 = 0, 1
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libfl.so")
+_lib = None
+
+c_u32, c_u64, c_vp, c_sz = ct.c_uint32, ct.c_uint64, ct.c_void_p, ct.c_size_t
+
+
+class FlError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class FlCsr(ct.Structure):
+    _fields_ = [("rows", c_u32), ("cols", c_u32), ("nnz", c_u64), ("row_ptr", c_vp),
+                ("col", c_vp), ("val", c_vp)]
+
+
+class FlSplitOut(ct.Structure):
+    _fields_ = [(n, c_vp) for n in ("row_perm", "col_perm", "a_gptr", "a_pos", "a_val", "b_ptr",
+                                    "b_col", "b_val", "c_gptr", "c_pos", "c_val", "d_ptr", "d_col",
+                                    "d_val")]
+
+
+class FlSplitInfo(ct.Structure):
+    _fields_ = [("p", c_u32), ("m", c_u32), ("n", c_u32), ("ml_width", c_u32), ("npiv", c_u32),
+                ("nB", c_u32), ("mD", c_u32), ("status", c_u32), ("nnz", c_u64), ("nnzA", c_u64),
+                ("nnzB", c_u64), ("nnzC", c_u64), ("nnzD", c_u64), ("lenA", c_u64),
+                ("lenC", c_u64)]
+
+
+def load():
+    """Load libfl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(f"{lib_path} not built: run __graft_entry__.build() "
+                          "or python -m paper_1602_06097_amd.build")
+    lib = ct.CDLL(lib_path)
+    P = ct.POINTER
+    sigs = {
+        "fl_split": (ct.c_int, [P(FlCsr), c_u32, c_u32, P(FlSplitOut), P(FlSplitInfo), c_vp, c_sz, c_vp]),
+        "fl_split_workspace": (c_sz, [c_u32, c_u32, c_u64, c_u32]),
+        "fl_trsm": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_sz, c_vp]),
+        "fl_trsm_workspace": (c_sz, [P(FlSplitInfo)]),
+        "fl_reduce_cd": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
+                                    c_vp, c_sz, c_vp]),
+        "fl_reduce_cd_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_echelon_d": (ct.c_int, [c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_vp, ct.c_int, c_vp, c_sz,
+                                    c_vp]),
+        "fl_echelon_d_workspace": (c_sz, [c_u32, c_u32, ct.c_int]),
+        "fl_rref": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp, c_vp,
+                               ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_rref_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_rref_csr_size": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
+                                        c_vp, c_vp, P(c_u32), P(c_u64), c_vp, c_sz, c_vp]),
+        "fl_rref_to_csr": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
+                                      c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+        "fl_rref_csr_workspace": (c_sz, [P(FlSplitInfo)]),
+        "fl_matmul_sub": (ct.c_int, [c_u32, c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_u64, c_vp, c_u64,
+                                     ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_matmul_sub_workspace": (c_sz, [c_u32, c_u32, c_u32, ct.c_int]),
+        "fl_status_string": (ct.c_char_p, [ct.c_int]),
+        "fl_last_error": (ct.c_char_p, []),
+        "fl_version": (ct.c_char_p, []),
+        "fl_check_modp": (ct.c_int, [P(c_u32), c_u32, c_vp, c_vp]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().fl_version().decode()
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        lib = load()
+        raise FlError(st, where, f"{lib.fl_status_string(st).decode()}; {lib.fl_last_error().decode()}")
+
+
+def _stream():
+    return c_vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return c_vp(t.data_ptr()) if t is not None and t.numel() else c_vp(None)
+
+
+def _dev():
+    return torch.device("cuda")
+
+
+def _ws(nbytes: int):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=_dev())
+
+
+def _ld(cols: int) -> int:
+    """Leading dimension used for dense buffers: a multiple of 64 elements."""
+    return max(64, (cols + 63) // 64 * 64)
+
+
+@dataclass
+class Split:
+    info: FlSplitInfo
+    out: FlSplitOut
+    bufs: dict
+
+    @property
+    def npiv(self): return self.info.npiv
+
+    @property
+    def mD(self): return self.info.mD
+
+    @property
+    def nB(self): return self.info.nB
+
+    @property
+    def p(self): return self.info.p
+
+
+@dataclass
+class Echelon:
+    rank: torch.Tensor    # device uint32 [1]
+    pivcol: torch.Tensor  # device uint32 [min(rows, cols)]
+    rows: int
+    cols: int
+
+
+def split(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, m: int, n: int, p: int,
+          ml_width: int = 2) -> Split:
+    """FL step 1 on a device CSR matrix (row_ptr uint64 [m+1], col uint32/int32
+    [nnz], val uint16/int16 [nnz]).  Allocates the outputs at their upper-bound
+    capacities and returns the sizes after the library's single sync."""
+    lib = load()
+    nnz = int(col.numel())
+    w = int(ml_width)
+    G = (m + w - 1) // w + 1
+    d = _dev()
+
+    def e(n_, dt):
+        return torch.empty(max(n_, 1), dtype=dt, device=d)
+
+    bufs = dict(row_perm=e(m, torch.int32), col_perm=e(n, torch.int32),
+                a_gptr=e(G, torch.int64), a_pos=e(nnz, torch.int32), a_val=e(w * nnz, torch.int16),
+                b_ptr=e(m + 1, torch.int64), b_col=e(nnz, torch.int32), b_val=e(nnz, torch.int16),
+                c_gptr=e(G, torch.int64), c_pos=e(nnz, torch.int32), c_val=e(w * nnz, torch.int16),
+                d_ptr=e(m + 1, torch.int64), d_col=e(nnz, torch.int32), d_val=e(nnz, torch.int16))
+    out = FlSplitOut(**{k: c_vp(v.data_ptr()) for k, v in bufs.items()})
+    M = FlCsr(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val))
+    info = FlSplitInfo()
+    ws = _ws(lib.fl_split_workspace(m, n, nnz, w))
+    st = lib.fl_split(ct.byref(M), p, w, ct.byref(out), ct.byref(info), _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_split")
+    bufs["_input"] = (row_ptr, col, val)
+    return Split(info=info, out=out, bufs=bufs)
+
+
+def trsm(sp: Split) -> torch.Tensor:
+    """X = A^{-1} B as a dense (npiv x ld) uint16 tensor (int16 storage)."""
+    lib = load()
+    ld = _ld(sp.nB)
+    X = torch.empty((max(sp.npiv, 1), ld), dtype=torch.int16, device=_dev())
+    ws = _ws(lib.fl_trsm_workspace(ct.byref(sp.info)))
+    st = lib.fl_trsm(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), ld, _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_trsm")
+    return X
+
+
+def reduce_cd(sp: Split, X: torch.Tensor, mode: int = FL_PLAIN) -> torch.Tensor:
+    lib = load()
+    ld = _ld(sp.nB)
+    Dt = torch.empty((max(sp.mD, 1), ld), dtype=torch.int16, device=_dev())
+    ws = _ws(lib.fl_reduce_cd_workspace(ct.byref(sp.info), mode))
+    st = lib.fl_reduce_cd(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), X.shape[1], _ptr(Dt), ld,
+                          mode, _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_reduce_cd")
+    return Dt
+
+
+def echelon_d(Dt: torch.Tensor, p: int, rows: int, cols: int, mode: int = FL_PLAIN) -> Echelon:
+    lib = load()
+    d = _dev()
+    rank = torch.zeros(1, dtype=torch.int32, device=d)
+    piv = torch.zeros(max(min(rows, cols), 1), dtype=torch.int32, device=d)
+    ws = _ws(lib.fl_echelon_d_workspace(rows, cols, mode))
+    st = lib.fl_echelon_d(p, rows, cols, _ptr(Dt), Dt.shape[1], _ptr(rank), _ptr(piv), mode,
+                          _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_echelon_d")
+    return Echelon(rank=rank, pivcol=piv, rows=rows, cols=cols)
+
+
+def rref(sp: Split, X: torch.Tensor, Dt: torch.Tensor, ech: Echelon, mode: int = FL_PLAIN) -> None:
+    lib = load()
+    ws = _ws(lib.fl_rref_workspace(ct.byref(sp.info), mode))
+    st = lib.fl_rref(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), X.shape[1], _ptr(Dt), Dt.shape[1],
+                     _ptr(ech.rank), _ptr(ech.pivcol), mode, _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_rref")
+
+
+def rref_to_csr(sp: Split, Xp: torch.Tensor, Dt: torch.Tensor, ech: Echelon):
+    """RREF(M) in original column order: (row_ptr int64, col int32, val int16, rank)."""
+    lib = load()
+    maxr = min(sp.mD, sp.nB)
+    row_ptr = torch.empty(sp.npiv + maxr + 1, dtype=torch.int64, device=_dev())
+    ws = _ws(lib.fl_rref_csr_workspace(ct.byref(sp.info)))
+    h_rank, h_nnz = c_u32(0), c_u64(0)
+    args = (ct.byref(sp.info), ct.byref(sp.out), _ptr(Xp), Xp.shape[1], _ptr(Dt), Dt.shape[1],
+            _ptr(ech.rank), _ptr(ech.pivcol))
+    st = lib.fl_rref_csr_size(*args, _ptr(row_ptr), ct.byref(h_rank), ct.byref(h_nnz), _ptr(ws),
+                              ws.numel(), _stream())
+    _check(st, "fl_rref_csr_size")
+    nnz = int(h_nnz.value)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=_dev())
+    val = torch.empty(max(nnz, 1), dtype=torch.int16, device=_dev())
+    st = lib.fl_rref_to_csr(*args, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_rref_to_csr")
+    rank = int(h_rank.value)
+    return row_ptr[:rank + 1], col[:nnz], val[:nnz], rank
+
+
+def matmul_sub(p: int, C: torch.Tensor, X: torch.Tensor, D: torch.Tensor, M: int, N: int, K: int,
+               mode: int = FL_PLAIN) -> None:
+    """D[:M, :N] -= C[:M, :K] X[:K, :N] mod p, in place (dense uint16 in int16 storage)."""
+    lib = load()
+    ws = _ws(lib.fl_matmul_sub_workspace(M, N, K, mode))
+    st = lib.fl_matmul_sub(p, M, N, K, _ptr(C), C.shape[1], _ptr(X), X.shape[1], _ptr(D), D.shape[1],
+                           mode, _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_matmul_sub")
+
+
+def fl_reduce(row_ptr, col, val, m: int, n: int, p: int, mode: int = FL_PLAIN, ml_width: int = 2,
+              keep: bool = False) -> dict:
+    """The whole hot path on one matrix already resident on the device.
+    With keep=True, copies of X = A^{-1}B and Dt = D - C X are returned too."""
+    sp = split(row_ptr, col, val, m, n, p, ml_width)
+    X = trsm(sp)
+    Dt = reduce_cd(sp, X, mode)
+    res = dict(split=sp)
+    if keep:
+        res["X"], res["Dt"] = X.clone(), Dt.clone()
+    ech = echelon_d(Dt, p, sp.mD, sp.nB, mode)
+    rref(sp, X, Dt, ech, mode)
+    res.update(echelon=ech, Xp=X, RD=Dt, rref=rref_to_csr(sp, X, Dt, ech))
+    return res
+
+
+def check_modp(primes) -> list:
+    lib = load()
+    arr = (c_u32 * len(primes))(*primes)
+    out = torch.zeros(len(primes), dtype=torch.int64, device=_dev())
+    st = lib.fl_check_modp(arr, len(primes), _ptr(out), _stream())
+    _check(st, "fl_check_modp")
+    torch.cuda.synchronize()
+    return [int(x) for x in out.cpu()]

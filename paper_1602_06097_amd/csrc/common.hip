@@ -1,0 +1,208 @@
+// common.hip -- error plumbing, device scan and fill kernels, self-checks.
+#include "fl_internal.h"
+
+#include <string>
+
+static thread_local std::string g_last_error;
+
+void fl_set_error(const char *msg) { g_last_error = msg ? msg : ""; }
+
+fl_status fl_hip_fail(hipError_t e, const char *where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return FL_ERR_HIP;
+}
+
+extern "C" const char *fl_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *fl_version(void) { return "fl-gfx950 0.1.0"; }
+
+extern "C" const char *fl_status_string(fl_status s) {
+    switch (s) {
+    case FL_OK: return "ok";
+    case FL_ERR_ARG: return "invalid argument";
+    case FL_ERR_WORKSPACE: return "workspace too small";
+    case FL_ERR_DATA_ROWPTR: return "row_ptr not monotone from 0 to nnz";
+    case FL_ERR_DATA_COL_RANGE: return "column index out of range";
+    case FL_ERR_DATA_COL_ORDER: return "columns of a row not strictly increasing";
+    case FL_ERR_DATA_VALUE: return "value zero or not reduced mod p";
+    case FL_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+// ---- exclusive scan (uint64) ----------------------------------------------------
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr size_t kScanTile = (size_t)kScanThreads * kScanPer;
+
+__device__ inline uint64_t shfl_up_u64(uint64_t v, int d) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_up(lo, d, 64);
+    hi = __shfl_up(hi, d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan of one value per thread over the block; returns the
+// inclusive prefix, *block_total receives the sum of the block.
+__device__ inline uint64_t block_incl_scan(uint64_t v, uint64_t *block_total) {
+    __shared__ uint64_t wave_tot[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t o = shfl_up_u64(v, d);
+        if (lane >= d) v += o;
+    }
+    if (lane == 63) wave_tot[wave] = v;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; w++) {
+        if (w < wave) before += wave_tot[w];
+        tot += wave_tot[w];
+    }
+    __syncthreads();
+    *block_total = tot;
+    return v + before;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sum(const uint64_t *in, size_t n,
+                                                           uint64_t *sums) {
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
+    uint64_t s = 0;
+    for (int k = 0; k < kScanPer; k++)
+        if (base + k < n) s += in[base + k];
+    uint64_t tot;
+    block_incl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const uint64_t *in, uint64_t *out,
+                                                            size_t n, const uint64_t *offsets,
+                                                            uint64_t *total) {
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t s = 0;
+    for (int k = 0; k < kScanPer; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    uint64_t tot;
+    uint64_t incl = block_incl_scan(s, &tot);
+    uint64_t off = offsets ? offsets[blockIdx.x] : 0;
+    uint64_t run = off + incl - s;
+    for (int k = 0; k < kScanPer; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) *total = off + tot;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// One block row-chunk per blockIdx.y, columns in 4-element (8-byte) steps.
+__global__ void k_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t cols) {
+    for (uint32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        uint16_t *row = p + (uint64_t)r * ld;
+        for (uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) * 4; c < cols;
+             c += gridDim.x * blockDim.x * 4) {
+            if (c + 4 <= cols) *(uint64_t *)(row + c) = 0;
+            else
+                for (uint32_t k = c; k < cols; k++) row[k] = 0;
+        }
+    }
+}
+
+inline unsigned grid_for(size_t n, unsigned threads, unsigned cap = 65536) {
+    size_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    return (unsigned)(g > cap ? cap : g);
+}
+}  // namespace
+
+size_t fl_scan_tmp_elems(size_t n) {
+    size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) return 1;
+    return nb + fl_scan_tmp_elems(nb);
+}
+
+hipError_t fl_exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *tmp,
+                                 uint64_t *total_out, hipStream_t s) {
+    if (n == 0) {
+        if (total_out) return fl_fill_u64(total_out, 0, 1, s);
+        return hipSuccess;
+    }
+    size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, s, in, out, n,
+                           (const uint64_t *)nullptr, total_out);
+        return hipGetLastError();
+    }
+    uint64_t *sums = tmp, *rest = tmp + nb;
+    hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = fl_exclusive_scan_u64(sums, sums, nb, rest, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const uint64_t *)sums, total_out);
+    return hipGetLastError();
+}
+
+hipError_t fl_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t fl_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t cols,
+                            hipStream_t s) {
+    if (rows == 0 || cols == 0) return hipSuccess;
+    unsigned gx = (unsigned)((cols / 4 + 255) / 256);
+    if (gx < 1) gx = 1;
+    unsigned gy = rows < 4096 ? rows : 4096;
+    hipLaunchKernelGGL(k_zero_rows_u16, dim3(gx, gy), dim3(256), 0, s, p, ld, rows, cols);
+    return hipGetLastError();
+}
+
+// ---- self-check of the 32-bit reduction ------------------------------------------
+namespace {
+__global__ void k_check_modp(fl::Mod m, uint64_t *mismatch) {
+    const uint64_t total = (uint64_t)1 << 32;
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t bad = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += nthreads) {
+        uint32_t v = (uint32_t)x;
+        if (fl::reduce32(v, m) != v % m.p) bad++;
+    }
+    if (bad) atomicAdd((unsigned long long *)mismatch, (unsigned long long)bad);
+}
+}  // namespace
+
+extern "C" fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count,
+                                   uint64_t *d_mismatch, hipStream_t stream) {
+    FL_ARG(h_p_list && d_mismatch, "fl_check_modp: NULL pointer");
+    hipError_t e = fl_fill_u64(d_mismatch, 0, count, stream);
+    if (e != hipSuccess) return fl_hip_fail(e, "fl_check_modp fill");
+    for (uint32_t i = 0; i < count; i++) {
+        FL_ARG(h_p_list[i] >= 2 && h_p_list[i] <= 65521, "fl_check_modp: p out of range");
+        hipLaunchKernelGGL(k_check_modp, dim3(4096), dim3(256), 0, stream,
+                           fl::make_mod(h_p_list[i]), d_mismatch + i);
+        FL_LAUNCH_CHECK("k_check_modp");
+    }
+    return FL_OK;
+}

@@ -1,0 +1,125 @@
+// fl_internal.h -- shared device/host helpers of the gfx950 FL library.
+//
+// Modular arithmetic model (all exact, no floating point):
+//  * residues are uint16 in [0, p), p <= 65521;
+//  * reduction of a 32-bit value uses Barrett with mu = floor(2^32 / p):
+//    q = umulhi(x, mu) is floor(x/p) or floor(x/p) - 1 for every x < 2^32
+//    (x/p - q < x/2^32 + 1 < 2), so one conditional subtraction finishes;
+//  * multiply-accumulate of a coefficient a against many residues x keeps two
+//    32-bit accumulators, splitting a = 256*a_h + a_l (a_h, a_l < 256): each
+//    product a_h*x, a_l*x < 2^24 fits the 24-bit multiplier, and 256 such
+//    products plus a residue stay below 2^32 (256*255*65535 + 65535 < 2^32),
+//    so accumulators are folded at least every 256 terms.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "../../include/fl.h"
+
+#define FL_FOLD_TERMS 256u
+
+namespace fl {
+
+struct Mod {
+    uint32_t p;
+    uint32_t mu;  // floor(2^32 / p)
+};
+
+__host__ __device__ inline Mod make_mod(uint32_t p) {
+    Mod m;
+    m.p = p;
+    m.mu = (uint32_t)(((uint64_t)1 << 32) / p);
+    return m;
+}
+
+__device__ __forceinline__ uint32_t reduce32(uint32_t x, const Mod &m) {
+    uint32_t q = __umulhi(x, m.mu);
+    uint32_t r = x - q * m.p;
+    return r >= m.p ? r - m.p : r;
+}
+
+// (a * b) mod p for residues a, b < 2^16.
+__device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const Mod &m) {
+    return reduce32(a * b, m);
+}
+
+// (a - b) mod p for residues.
+__device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t p) {
+    return a >= b ? a - b : a + p - b;
+}
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t p) {
+    uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+
+// 24-bit multiply-add: a, b < 2^24.
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+    return __umul24(a, b) + c;
+}
+
+// Fold a split accumulator pair (hi counts 256x) into one residue.
+__device__ __forceinline__ uint32_t fold_pair(uint32_t hi, uint32_t lo, const Mod &m) {
+    uint32_t h = reduce32(hi, m);
+    uint32_t l = reduce32(lo, m);
+    return reduce32(h * 256u + l, m);
+}
+
+// Modular inverse by Fermat's little theorem (x != 0, p prime).
+__device__ inline uint32_t invmod(uint32_t x, const Mod &m) {
+    uint32_t r = 1, b = x, e = m.p - 2;
+    while (e) {
+        if (e & 1) r = mulmod(r, b, m);
+        b = mulmod(b, b, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+}  // namespace fl
+
+// ---- host-side error plumbing -------------------------------------------------
+void fl_set_error(const char *msg);
+fl_status fl_hip_fail(hipError_t e, const char *where);
+
+#define FL_HIP(call)                                                    \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return fl_hip_fail(e_, #call);            \
+    } while (0)
+
+#define FL_LAUNCH_CHECK(where)                                          \
+    do {                                                                \
+        hipError_t e_ = hipGetLastError();                              \
+        if (e_ != hipSuccess) return fl_hip_fail(e_, where);            \
+    } while (0)
+
+#define FL_ARG(cond, msg)                                               \
+    do {                                                                \
+        if (!(cond)) { fl_set_error(msg); return FL_ERR_ARG; }          \
+    } while (0)
+
+// Workspace carving: 256-byte aligned slices.
+struct WsCarve {
+    char *base;
+    size_t off;
+    explicit WsCarve(void *b) : base((char *)b), off(0) {}
+    template <class T> T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Exclusive scans on the device (three-phase: tile reduce, scan of tile sums,
+// tile scan).  `tmp` must hold fl_scan_tmp_elems(n) elements.  out may alias in.
+size_t fl_scan_tmp_elems(size_t n);
+hipError_t fl_exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, uint64_t *tmp,
+                                 uint64_t *total_out, hipStream_t s);
+
+// Fill a device buffer with a 32-bit / 16-bit pattern by a kernel (kept out
+// of hipMemsetAsync so that calls stay safe under stream capture).
+hipError_t fl_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t fl_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t cols, hipStream_t s);

@@ -1,0 +1,241 @@
+// gemm_mfma.hip -- dense C = C - A B mod p on the int8 matrix cores (gfx950).
+//
+// Every residue x in [0, p), p <= 65521, is centred into
+//     r = x            if x <= 32639
+//     r = x - p        otherwise            (r in [-32881, 32639])
+// and split into two signed 8-bit limbs r = 256 h + l with
+//     h = floor((r + 128) / 256) in [-128, 127],  l = r - 256 h in [-128, 127].
+// Then  sum_k A B = 65536 S_hh + 256 (S_hl + S_lh) + S_ll  with four int8 GEMMs
+// accumulated exactly in int32 (v_mfma_i32_16x16x64_i8): |h h'| <= 2^14, so a
+// K-chunk of at most kKChunk = 65472 terms keeps |S_hh|, |S_ll| < 2^30 and the
+// shared middle accumulator |S_hl + S_lh| < 2^31.  Each partial is biased to
+// a non-negative 32-bit value (a multiple of p added), Barrett-reduced, and
+// recombined with 2^16 mod p and 2^8.  No floating point anywhere.
+//
+// Operands are first converted to limb planes in the workspace, both stored
+// K-contiguous (A as M x Kp, B transposed as N x Kp, zero padded to the tile
+// sizes), so the GEMM kernel streams int8 rows with 16-byte loads and needs no
+// bounds checks in its main loop.
+#include "fl_internal.h"
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr uint32_t kKChunk = 65472;  // multiple of BK, < 65536
+constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conflicts
+
+__device__ __forceinline__ void split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
+    const int r = x <= 32639u ? (int)x : (int)x - (int)p;
+    h = (r + 128) >> 8;  // arithmetic shift: floor
+    l = r - (h << 8);
+}
+
+// A (rows x K, row-major u16, lda) -> Ah, Al (Rp x Kp int8, K-contiguous).
+// Rows >= rows or k >= K (K read from Kdev when non-NULL) are zero.
+__global__ __launch_bounds__(256) void k_limbs_rows(uint32_t p, const uint16_t *__restrict__ A,
+                                                    uint64_t lda, uint32_t rows, uint32_t Kh,
+                                                    const uint32_t *__restrict__ Kdev,
+                                                    int8_t *Ah, int8_t *Al, uint32_t Rp,
+                                                    uint32_t Kp) {
+    const uint32_t K = Kdev ? *Kdev : Kh;
+    const uint32_t k4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (k4 >= Kp) return;
+    for (uint32_t i = blockIdx.y; i < Rp; i += gridDim.y) {
+        uint32_t hv = 0, lv = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t k = k4 + e;
+            int h = 0, l = 0;
+            if (i < rows && k < K) split_limbs(A[(uint64_t)i * lda + k], p, h, l);
+            hv |= (uint32_t)(h & 0xff) << (8 * e);
+            lv |= (uint32_t)(l & 0xff) << (8 * e);
+        }
+        *(uint32_t *)(Ah + (uint64_t)i * Kp + k4) = hv;
+        *(uint32_t *)(Al + (uint64_t)i * Kp + k4) = lv;
+    }
+}
+
+// B (K x cols, row-major u16, ldb) -> Bh, Bl transposed (Cp x Kp int8).
+__global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *__restrict__ B,
+                                                    uint64_t ldb, uint32_t cols, uint32_t Kh,
+                                                    const uint32_t *__restrict__ Kdev,
+                                                    int8_t *Bh, int8_t *Bl, uint32_t Kp) {
+    __shared__ int8_t th[64][65], tl[64][65];
+    const uint32_t K = Kdev ? *Kdev : Kh;
+    const uint32_t k0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (uint32_t kk = ty; kk < 64; kk += 4) {
+        const uint32_t k = k0 + kk, c = c0 + tx;
+        int h = 0, l = 0;
+        if (k < K && c < cols) split_limbs(B[(uint64_t)k * ldb + c], p, h, l);
+        th[kk][tx] = (int8_t)h;
+        tl[kk][tx] = (int8_t)l;
+    }
+    __syncthreads();
+    for (uint32_t cc = ty; cc < 64; cc += 4) {
+        const uint32_t c = c0 + cc;
+        Bh[(uint64_t)c * Kp + k0 + tx] = th[tx][cc];
+        Bl[(uint64_t)c * Kp + k0 + tx] = tl[tx][cc];
+    }
+}
+
+__device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint32_t bias) {
+    return fl::reduce32((uint32_t)s + bias, md);
+}
+
+// C[M x N] -= (Ah,Al)[M x Kp] * (Bh,Bl)[N x Kp]^T over k in [kbeg, kend).
+// 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 outputs per wave as
+// 4 x 4 tiles of 16 x 16.
+__global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                   const int8_t *__restrict__ Ah,
+                                                   const int8_t *__restrict__ Al,
+                                                   const int8_t *__restrict__ Bh,
+                                                   const int8_t *__restrict__ Bl, uint32_t Kp,
+                                                   uint32_t kbeg, uint32_t kend,
+                                                   const uint32_t *__restrict__ Kdev,
+                                                   uint16_t *C, uint64_t ldc, uint32_t M,
+                                                   uint32_t N) {
+    __shared__ __attribute__((aligned(16))) int8_t sAh[BM * kLdsRow], sAl[BM * kLdsRow];
+    __shared__ __attribute__((aligned(16))) int8_t sBh[BN * kLdsRow], sBl[BN * kLdsRow];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wm = wave >> 1, wn = wave & 1;
+    const uint32_t m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (Kdev) {
+        const uint32_t kd = (*Kdev + BK - 1) / BK * BK;
+        if (kend > kd) kend = kd;
+    }
+    v4i acc_hh[4][4], acc_mid[4][4], acc_ll[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            acc_hh[i][j] = v4i{0, 0, 0, 0};
+            acc_mid[i][j] = v4i{0, 0, 0, 0};
+            acc_ll[i][j] = v4i{0, 0, 0, 0};
+        }
+    // global -> LDS: each plane tile is 128 rows x 64 bytes = 512 x 16 B;
+    // thread t moves 16 B chunks t and t + 256 of each of the four planes.
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const uint32_t chunk = tid + u * 256;
+            const uint32_t r = chunk >> 2, q = (chunk & 3) * 16;
+            const uint64_t ga = (uint64_t)(m0 + r) * Kp + k0 + q;
+            const uint64_t gb = (uint64_t)(n0 + r) * Kp + k0 + q;
+            *(v4i *)(sAh + r * kLdsRow + q) = *(const v4i *)(Ah + ga);
+            *(v4i *)(sAl + r * kLdsRow + q) = *(const v4i *)(Al + ga);
+            *(v4i *)(sBh + r * kLdsRow + q) = *(const v4i *)(Bh + gb);
+            *(v4i *)(sBl + r * kLdsRow + q) = *(const v4i *)(Bl + gb);
+        }
+        __syncthreads();
+        v4i ah[4], al[4], bh[4], bl[4];
+        const uint32_t kq = (lane >> 4) * 16;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
+            const uint32_t rb = wn * 64 + t * 16 + (lane & 15);
+            ah[t] = *(const v4i *)(sAh + ra * kLdsRow + kq);
+            al[t] = *(const v4i *)(sAl + ra * kLdsRow + kq);
+            bh[t] = *(const v4i *)(sBh + rb * kLdsRow + kq);
+            bl[t] = *(const v4i *)(sBl + rb * kLdsRow + kq);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
+                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
+                acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    // epilogue: output element (row 4*(lane/16) + e, column lane%16) of each tile
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                if (row < M && col < N) {
+                    const uint32_t rhh = signed_to_res(acc_hh[i][j][e], md, bias);
+                    const uint32_t rmid = signed_to_res(acc_mid[i][j][e], md, bias);
+                    const uint32_t rll = signed_to_res(acc_ll[i][j][e], md, bias);
+                    uint32_t v = fl::reduce32(rhh * c16 + rll, md);
+                    v = fl::reduce32(v + rmid * 256u, md);
+                    uint16_t *o = C + (uint64_t)row * ldc + col;
+                    *o = (uint16_t)fl::submod(*o, v, md.p);
+                }
+            }
+        }
+}
+
+inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+
+struct MfmaWs {
+    int8_t *Ah, *Al, *Bh, *Bl;
+    uint32_t Mp, Np, Kp;
+};
+
+size_t mfma_layout(uint32_t M, uint32_t N, uint32_t Kmax, void *ws, MfmaWs *w) {
+    WsCarve c(ws);
+    MfmaWs t;
+    t.Mp = round_up(M ? M : 1, BM);
+    t.Np = round_up(N ? N : 1, BN);
+    t.Kp = round_up(Kmax ? Kmax : 1, BK);
+    t.Ah = c.take<int8_t>((size_t)t.Mp * t.Kp);
+    t.Al = c.take<int8_t>((size_t)t.Mp * t.Kp);
+    t.Bh = c.take<int8_t>((size_t)t.Np * t.Kp);
+    t.Bl = c.take<int8_t>((size_t)t.Np * t.Kp);
+    if (w) *w = t;
+    return c.off;
+}
+
+}  // namespace
+
+size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax) {
+    return mfma_layout(M, N, Kmax, nullptr, nullptr);
+}
+
+// C[M x N] -= A[M x K] B[K x N] (mod p) on the matrix cores.  K = *Kdev when
+// Kdev is non-NULL (then K <= Kmax), else Kmax.  Bit-identical to
+// fl_gemm_sub_plain.
+hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
+                            const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s) {
+    if (M == 0 || N == 0 || Kmax == 0) return hipSuccess;
+    MfmaWs w;
+    if (mfma_layout(M, N, Kmax, ws, &w) > ws_bytes || !ws) return hipErrorInvalidValue;
+    const fl::Mod md = fl::make_mod(p);
+    // bias: the smallest multiple of p that is >= 2^31, so s + bias >= 0 and
+    // s + bias < 2^32 for |s| < 2^31 - 2^16.
+    const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
+    const uint32_t c16 = (uint32_t)((1u << 16) % p);
+    {
+        dim3 g(w.Kp / 4 / 256 + 1, w.Mp < 65535 ? w.Mp : 65535);
+        hipLaunchKernelGGL(k_limbs_rows, g, dim3(256), 0, s, p, A, lda, M, Kmax, Kdev, w.Ah, w.Al,
+                           w.Mp, w.Kp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        dim3 g(w.Np / 64, w.Kp / 64);
+        hipLaunchKernelGGL(k_limbs_cols, g, dim3(256), 0, s, p, B, ldb, N, Kmax, Kdev, w.Bh, w.Bl,
+                           w.Kp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid(w.Np / BN, w.Mp / BM);
+    for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {
+        const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
+        hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, w.Ah, w.Al, w.Bh,
+                           w.Bl, w.Kp, kb, ke, Kdev, C, ldc, M, N);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

@@ -1,0 +1,270 @@
+// rref.hip -- the second FL pass (end of paper Sec. 4.1: run the reduction
+// again on [A^{-1}B ; D']) and FL step 5 (column rearrangement / read-off).
+//
+// With R_D = RREF(Dt) of rank r and pivot columns P_D, the second pass is
+//     X' = X - X[:, P_D] R_D :
+//   k_gather_pivcols   L = X[:, P_D]   (npiv x r, saved before X is updated)
+//   dense GEMM         X -= L R_D      (VALU or int8 MFMA form)
+// Then [Id X'; 0 R_D] is the reduced row echelon form of M under col_perm,
+// read off as canonical CSR in the original column order:
+//   k_csr_count        nonzeros of every output row, stored at the row's
+//                      position in pivot-column order; exclusive scan
+//   k_csr_emit         one wave per output row: pivot 1, then the nonzeros of
+//                      the X' or R_D row (both ascending in original order).
+#include "fl_internal.h"
+
+hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
+                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
+                             uint16_t *C, uint64_t ldc, hipStream_t s);
+hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
+                            const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s);
+size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
+fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
+
+namespace {
+
+// L[i][t] = X[i][pivcol[t]] for t < r (L row stride ldl).
+__global__ __launch_bounds__(256) void k_gather_pivcols(const uint16_t *__restrict__ X, uint64_t ldx,
+                                                        uint32_t npiv,
+                                                        const uint32_t *__restrict__ d_rank,
+                                                        const uint32_t *__restrict__ pivcol,
+                                                        uint16_t *L, uint64_t ldl) {
+    const uint32_t r = *d_rank;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= r) return;
+    const uint32_t c = pivcol[t];
+    for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) L[(uint64_t)i * ldl + t] = X[(uint64_t)i * ldx + c];
+}
+
+// Number of entries of p_list[0..cnt) strictly below x (p_list ascending).
+__device__ __forceinline__ uint32_t count_below(const uint32_t *list, uint32_t cnt, uint32_t x,
+                                                const uint32_t *map) {
+    uint32_t lo = 0, hi = cnt;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        uint32_t v = map ? map[list[mid]] : list[mid];
+        if (v < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct OutRow {
+    bool top;          // a row of [Id X'] (else a row of R_D)
+    uint32_t src;      // row index within X' or R_D
+    uint32_t pos;      // output row position
+    uint32_t pivot;    // original pivot column
+};
+
+// Output row j of the wave: j < npiv -> top row j, else R_D row j - npiv.
+// col_perm[0..npiv) are the pivot columns of A ascending; col_perm[npiv + c]
+// the non-pivot columns ascending; R_D's pivots col_perm[npiv + pivcol[t]]
+// are ascending in t.
+__device__ __forceinline__ OutRow out_row(uint32_t j, uint32_t npiv, uint32_t r,
+                                          const uint32_t *col_perm, const uint32_t *pivcol) {
+    OutRow o;
+    if (j < npiv) {
+        o.top = true; o.src = j; o.pivot = col_perm[j];
+        o.pos = j + count_below(pivcol, r, o.pivot, col_perm + npiv);
+    } else {
+        o.top = false; o.src = j - npiv; o.pivot = col_perm[npiv + pivcol[o.src]];
+        o.pos = o.src + count_below(col_perm, npiv, o.pivot, nullptr);
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(256) void k_csr_count(uint32_t npiv, uint32_t nB,
+                                                   const uint32_t *__restrict__ col_perm,
+                                                   const uint16_t *__restrict__ Xp, uint64_t ldx,
+                                                   const uint16_t *__restrict__ RD, uint64_t ldd,
+                                                   const uint32_t *__restrict__ d_rank,
+                                                   const uint32_t *__restrict__ pivcol,
+                                                   uint64_t *cnt) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t r = *d_rank;
+    if (j >= npiv + r) return;
+    OutRow o = out_row(j, npiv, r, col_perm, pivcol);
+    const uint16_t *row = o.top ? Xp + (uint64_t)o.src * ldx : RD + (uint64_t)o.src * ldd;
+    uint32_t c = 0;
+    for (uint32_t k = lane; k < nB; k += 64) c += row[k] != 0 ? 1 : 0;
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) cnt[o.pos] = c + (o.top ? 1 : 0);
+}
+
+__global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
+                                                  const uint32_t *__restrict__ col_perm,
+                                                  const uint16_t *__restrict__ Xp, uint64_t ldx,
+                                                  const uint16_t *__restrict__ RD, uint64_t ldd,
+                                                  const uint32_t *__restrict__ d_rank,
+                                                  const uint32_t *__restrict__ pivcol,
+                                                  const uint64_t *__restrict__ row_ptr,
+                                                  uint32_t *ocol, uint16_t *oval) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t r = *d_rank;
+    if (j >= npiv + r) return;
+    OutRow o = out_row(j, npiv, r, col_perm, pivcol);
+    const uint16_t *row = o.top ? Xp + (uint64_t)o.src * ldx : RD + (uint64_t)o.src * ldd;
+    uint64_t out = row_ptr[o.pos];
+    if (o.top) {
+        if (lane == 0) { ocol[out] = o.pivot; oval[out] = 1; }
+        out++;
+    }
+    for (uint32_t k0 = 0; k0 < nB; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const uint32_t x = k < nB ? row[k] : 0;
+        const uint64_t mask = __ballot(x != 0);
+        const uint64_t below = lane == 0 ? 0 : (mask & (~(uint64_t)0 >> (64 - lane)));
+        if (x) {
+            const uint64_t at = out + __popcll(below);
+            ocol[at] = col_perm[npiv + k];
+            oval[at] = (uint16_t)x;
+        }
+        out += __popcll(mask);
+    }
+}
+
+struct CsrWs {
+    uint64_t *cnt;
+    uint64_t *scantmp;
+    uint64_t *dinfo;
+};
+
+size_t csr_layout(uint32_t npiv, uint32_t maxr, void *ws, CsrWs *c) {
+    WsCarve w(ws);
+    CsrWs t;
+    size_t n = (size_t)npiv + maxr + 1;
+    t.cnt = w.take<uint64_t>(n);
+    t.scantmp = w.take<uint64_t>(fl_scan_tmp_elems(n));
+    t.dinfo = w.take<uint64_t>(4);
+    if (c) *c = t;
+    return w.off;
+}
+
+struct RrefWs {
+    uint16_t *L;
+    uint64_t ldl;
+    void *gemm_ws;
+    size_t gemm_ws_bytes;
+};
+
+size_t rref_layout(const fl_split_info *info, fl_mode mode, void *ws, RrefWs *r) {
+    WsCarve w(ws);
+    RrefWs t;
+    const uint32_t maxr = info->mD < info->nB ? info->mD : info->nB;
+    t.ldl = ((uint64_t)maxr + 7) & ~(uint64_t)7;
+    t.L = w.take<uint16_t>((size_t)(info->npiv ? info->npiv : 1) * (t.ldl ? t.ldl : 1));
+    t.gemm_ws_bytes = mode == FL_MFMA_I8 ? fl_gemm_sub_mfma_ws(info->npiv, info->nB, maxr) : 0;
+    t.gemm_ws = t.gemm_ws_bytes ? (void *)w.take<char>(t.gemm_ws_bytes) : nullptr;
+    if (r) *r = t;
+    return w.off;
+}
+
+}  // namespace
+
+extern "C" size_t fl_rref_workspace(const fl_split_info *info, fl_mode mode) {
+    if (!info) return 0;
+    return rref_layout(info, mode, nullptr, nullptr);
+}
+
+extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, uint16_t *X,
+                             uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                             const uint32_t *d_rank, const uint32_t *d_pivcol, fl_mode mode,
+                             void *ws, size_t ws_bytes, hipStream_t stream) {
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_rref: bad mode");
+    const uint32_t npiv = info->npiv, nB = info->nB;
+    const uint32_t maxr = info->mD < nB ? info->mD : nB;
+    if (npiv == 0 || nB == 0 || maxr == 0) return FL_OK;
+    FL_ARG(X && RD && d_rank && d_pivcol, "fl_rref: NULL array");
+    FL_ARG(ldx >= nB && ldx % 4 == 0 && ldd >= nB && ldd % 4 == 0,
+           "fl_rref: ldx/ldd must be >= nB and multiples of 4");
+    FL_ARG(((uintptr_t)X & 7) == 0 && ((uintptr_t)RD & 7) == 0, "fl_rref: X, RD must be 8-byte aligned");
+    RrefWs r;
+    size_t need = rref_layout(info, mode, ws, &r);
+    if (!ws || ws_bytes < need) {
+        fl_set_error("fl_rref: workspace too small");
+        return FL_ERR_WORKSPACE;
+    }
+    dim3 g((maxr + 255) / 256, npiv < 1024 ? npiv : 1024);
+    hipLaunchKernelGGL(k_gather_pivcols, g, dim3(256), 0, stream, (const uint16_t *)X, ldx, npiv,
+                       d_rank, d_pivcol, r.L, r.ldl);
+    FL_LAUNCH_CHECK("k_gather_pivcols");
+    if (mode == FL_MFMA_I8) {
+        FL_HIP(fl_gemm_sub_mfma(info->p, npiv, nB, maxr, d_rank, r.L, r.ldl, RD, ldd, X, ldx,
+                                r.gemm_ws, r.gemm_ws_bytes, stream));
+    } else {
+        FL_HIP(fl_gemm_sub_plain(info->p, npiv, nB, 0, d_rank, r.L, r.ldl, RD, ldd, X, ldx, stream));
+    }
+    return FL_OK;
+}
+
+extern "C" size_t fl_rref_csr_workspace(const fl_split_info *info) {
+    if (!info) return 0;
+    const uint32_t maxr = info->mD < info->nB ? info->mD : info->nB;
+    return csr_layout(info->npiv, maxr, nullptr, nullptr);
+}
+
+extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_out *s,
+                                      const uint16_t *Xp, uint64_t ldx, const uint16_t *RD,
+                                      uint64_t ldd, const uint32_t *d_rank,
+                                      const uint32_t *d_pivcol, uint64_t *row_ptr,
+                                      uint32_t *h_rank, uint64_t *h_nnz, void *ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    FL_ARG(row_ptr && h_rank && h_nnz && d_rank, "fl_rref_csr_size: NULL argument");
+    const uint32_t npiv = info->npiv, nB = info->nB;
+    const uint32_t maxr = info->mD < nB ? info->mD : nB;
+    FL_ARG(npiv == 0 || nB == 0 || (Xp && ldx >= nB), "fl_rref_csr_size: bad X'");
+    FL_ARG(maxr == 0 || (RD && d_pivcol && ldd >= nB), "fl_rref_csr_size: bad R_D");
+    CsrWs c;
+    size_t need = csr_layout(npiv, maxr, ws, &c);
+    if (!ws || ws_bytes < need) {
+        fl_set_error("fl_rref_csr_size: workspace too small");
+        return FL_ERR_WORKSPACE;
+    }
+    const size_t nrows_max = (size_t)npiv + maxr;
+    FL_HIP(fl_fill_u64(c.cnt, 0, nrows_max + 1, stream));
+    if (nrows_max) {
+        hipLaunchKernelGGL(k_csr_count, dim3((unsigned)((nrows_max + 3) / 4)), dim3(256), 0, stream,
+                           npiv, nB, (const uint32_t *)s->col_perm, Xp, ldx, RD, ldd, d_rank,
+                           d_pivcol, c.cnt);
+        FL_LAUNCH_CHECK("k_csr_count");
+    }
+    // rows beyond npiv + r have count 0, so the scan over the upper bound
+    // yields row_ptr[rank] = nnz for every rank
+    FL_HIP(fl_exclusive_scan_u64(c.cnt, row_ptr, nrows_max + 1, c.scantmp, c.dinfo, stream));
+    uint32_t r = 0;
+    uint64_t tot = 0;
+    if (maxr) FL_HIP(hipMemcpyAsync(&r, d_rank, sizeof(r), hipMemcpyDeviceToHost, stream));
+    FL_HIP(hipMemcpyAsync(&tot, c.dinfo, sizeof(tot), hipMemcpyDeviceToHost, stream));
+    FL_HIP(hipStreamSynchronize(stream));
+    *h_rank = npiv + r;
+    *h_nnz = tot;
+    return FL_OK;
+}
+
+extern "C" fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_out *s,
+                                    const uint16_t *Xp, uint64_t ldx, const uint16_t *RD,
+                                    uint64_t ldd, const uint32_t *d_rank, const uint32_t *d_pivcol,
+                                    const uint64_t *row_ptr, uint32_t *col, uint16_t *val,
+                                    void *ws, size_t ws_bytes, hipStream_t stream) {
+    (void)ws; (void)ws_bytes;
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    FL_ARG(row_ptr && d_rank, "fl_rref_to_csr: NULL argument");
+    const uint32_t npiv = info->npiv, nB = info->nB;
+    const uint32_t maxr = info->mD < nB ? info->mD : nB;
+    const size_t nrows_max = (size_t)npiv + maxr;
+    if (nrows_max == 0) return FL_OK;
+    FL_ARG(col && val, "fl_rref_to_csr: NULL col/val");
+    hipLaunchKernelGGL(k_csr_emit, dim3((unsigned)((nrows_max + 3) / 4)), dim3(256), 0, stream, npiv,
+                       nB, (const uint32_t *)s->col_perm, Xp, ldx, RD, ldd, d_rank, d_pivcol,
+                       row_ptr, col, val);
+    FL_LAUNCH_CHECK("k_csr_emit");
+    return FL_OK;
+}

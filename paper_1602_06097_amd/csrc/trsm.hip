@@ -1,0 +1,388 @@
+// trsm.hip -- FL step 2 (X = A^{-1} B, paper Sec. 4.1 step 2) and the sparse
+// form of FL step 3 (Dt = D - C X, Sec. 4.1 step 3), both built on one
+// kernel: a w-multiline row group times a dense matrix (Sec. 4.2: the w rows
+// of a multiline share one pass over the positions, so each row of X that is
+// read serves all w rows -- the GPU analogue of the paper's multiline AXPY).
+//
+// TRSM schedule: rows of A are cut into blocks of kTrsmBlock rows; blocks
+// are solved from the bottom up.  For block [r0, r1):
+//   k_ml_spmm  (update)  X[r0:r1] -= A[r0:r1, r1:] X[r1:]   -- fully parallel
+//                        over (multiline group, 256-column tile)
+//   k_trsm_solve         back substitution inside the block, one wave per
+//                        64-column stripe, the block's finished rows kept in
+//                        LDS; each multiline group is solved with the 2x2 /
+//                        wxw triangular correction between its own rows.
+// Arithmetic: coefficients are split a = 256 a_h + a_l and multiplied with
+// 24-bit multiply-adds into two 32-bit accumulators, folded mod p at most
+// every 256 terms (see fl_internal.h for the bound).
+#include "fl_internal.h"
+
+namespace {
+
+constexpr uint32_t kTrsmBlock = 128;  // rows per TRSM block (multiple of 8)
+constexpr int kTile = 256;            // columns per wave in k_ml_spmm (4 per lane)
+
+// ---- CSR rows -> dense rows (out zeroed beforehand) ------------------------------
+__global__ __launch_bounds__(256) void k_csr_scatter(uint32_t rows, const uint64_t *__restrict__ rp,
+                                                     const uint32_t *__restrict__ ci,
+                                                     const uint16_t *__restrict__ v, uint16_t *out,
+                                                     uint64_t ld) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= rows) return;
+    uint16_t *row = out + (uint64_t)i * ld;
+    for (uint64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) row[ci[k]] = v[k];
+}
+
+// ---- metadata of one multiline position, broadcast from lane j --------------------
+template <int W> struct MlVals;
+template <> struct MlVals<1> {
+    uint32_t v;
+    __device__ void load(const uint16_t *val, uint64_t k) { v = val[k]; }
+    __device__ uint32_t get(int j, int q) const {
+        (void)q;
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+    }
+};
+template <> struct MlVals<2> {
+    uint32_t v;
+    __device__ void load(const uint16_t *val, uint64_t k) { v = *(const uint32_t *)(val + 2 * k); }
+    __device__ uint32_t get(int j, int q) const {
+        uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+        return q ? s >> 16 : s & 0xffffu;
+    }
+};
+template <> struct MlVals<4> {
+    uint32_t v0, v1;
+    __device__ void load(const uint16_t *val, uint64_t k) {
+        uint64_t x = *(const uint64_t *)(val + 4 * k);
+        v0 = (uint32_t)x; v1 = (uint32_t)(x >> 32);
+    }
+    __device__ uint32_t get(int j, int q) const {
+        uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)(q < 2 ? v0 : v1), j);
+        return (q & 1) ? s >> 16 : s & 0xffffu;
+    }
+};
+template <> struct MlVals<8> {
+    uint32_t v[4];
+    __device__ void load(const uint16_t *val, uint64_t k) {
+        uint4 x = *(const uint4 *)(val + 8 * k);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
+    __device__ uint32_t get(int j, int q) const {
+        uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)v[q >> 1], j);
+        return (q & 1) ? s >> 16 : s & 0xffffu;
+    }
+};
+
+// First index k in [kb, ke) with pos[k] >= lo (pos ascending), wave-cooperative.
+__device__ __forceinline__ uint64_t first_at_least(const uint32_t *__restrict__ pos, uint64_t kb,
+                                                   uint64_t ke, uint32_t lo) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t k = kb;
+    while (k < ke) {
+        uint64_t kk = k + lane;
+        bool below = kk < ke && pos[kk] < lo;
+        uint64_t mask = __ballot(below);
+        if (mask != ~(uint64_t)0) return k + __popcll(mask);
+        k += 64;
+    }
+    return ke;
+}
+
+// out[g*W+q][c] = out[...][c] - sum_{k: pos[k] >= pos_lo} val[W*k+q] * X[pos[k]][c]  (mod p)
+// for groups g in [g0, g0 + ngroups), rows < row_limit, columns < ncols.
+// One wave per (group, 256-column tile); blockIdx.y picks 4 consecutive groups.
+template <int W>
+__global__ __launch_bounds__(256) void k_ml_spmm(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                 const uint32_t *__restrict__ pos,
+                                                 const uint16_t *__restrict__ val, uint32_t g0,
+                                                 uint32_t ngroups, uint32_t row_limit,
+                                                 uint32_t pos_lo, const uint16_t *X, uint64_t ldx,
+                                                 uint16_t *out, uint64_t ldo, uint32_t ncols) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gi = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (gi >= ngroups) return;
+    const uint32_t g = g0 + gi;
+    const uint32_t c0 = blockIdx.x * kTile + lane * 4;
+    const bool colok = c0 < ncols;
+    uint64_t kb = gptr[g], ke = gptr[g + 1];
+    if (pos_lo) kb = first_at_least(pos, kb, ke, pos_lo);
+    if (kb >= ke) return;  // nothing to subtract
+
+    uint32_t ah[W][4], al[W][4];
+#pragma unroll
+    for (int q = 0; q < W; q++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) ah[q][c] = al[q][c] = 0;
+
+    uint32_t terms = 0;
+    for (uint64_t k = kb; k < ke; k += 64) {
+        const int batch = (int)((ke - k) < 64 ? (ke - k) : 64);
+        uint32_t mypos = 0;
+        MlVals<W> mv;
+        if ((int)lane < batch) {
+            mypos = pos[k + lane];
+            mv.load(val, k + lane);
+        }
+        int j = 0;
+        for (; j + 4 <= batch; j += 4) {
+            uint64_t xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)mypos, j + u);
+                xv[u] = colok ? *(const uint64_t *)(X + (uint64_t)pj * ldx + c0) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                uint32_t x[4] = {(uint32_t)xv[u] & 0xffffu, (uint32_t)(xv[u] >> 16) & 0xffffu,
+                                 (uint32_t)(xv[u] >> 32) & 0xffffu, (uint32_t)(xv[u] >> 48)};
+#pragma unroll
+                for (int q = 0; q < W; q++) {
+                    uint32_t a = mv.get(j + u, q);
+                    uint32_t a_h = a >> 8, a_l = a & 0xffu;
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        ah[q][c] = fl::mad24(a_h, x[c], ah[q][c]);
+                        al[q][c] = fl::mad24(a_l, x[c], al[q][c]);
+                    }
+                }
+            }
+        }
+        for (; j < batch; j++) {
+            uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)mypos, j);
+            uint64_t xv = colok ? *(const uint64_t *)(X + (uint64_t)pj * ldx + c0) : 0;
+            uint32_t x[4] = {(uint32_t)xv & 0xffffu, (uint32_t)(xv >> 16) & 0xffffu,
+                             (uint32_t)(xv >> 32) & 0xffffu, (uint32_t)(xv >> 48)};
+#pragma unroll
+            for (int q = 0; q < W; q++) {
+                uint32_t a = mv.get(j, q);
+                uint32_t a_h = a >> 8, a_l = a & 0xffu;
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    ah[q][c] = fl::mad24(a_h, x[c], ah[q][c]);
+                    al[q][c] = fl::mad24(a_l, x[c], al[q][c]);
+                }
+            }
+        }
+        terms += (uint32_t)batch;
+        if (terms > FL_FOLD_TERMS - 64) {
+#pragma unroll
+            for (int q = 0; q < W; q++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    al[q][c] = fl::fold_pair(ah[q][c], al[q][c], md);
+                    ah[q][c] = 0;
+                }
+            terms = 0;
+        }
+    }
+    if (!colok) return;
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        const uint32_t row = g * W + q;
+        if (row >= row_limit) break;
+        uint16_t *o = out + (uint64_t)row * ldo + c0;
+        uint32_t s[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) s[c] = fl::fold_pair(ah[q][c], al[q][c], md);
+        if (c0 + 4 <= ncols) {
+            uint64_t ov = *(const uint64_t *)o;
+            uint64_t nv = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu, s[c], md.p) << (16 * c);
+            *(uint64_t *)o = nv;
+        } else {
+            for (int c = 0; c < 4 && c0 + c < ncols; c++) o[c] = (uint16_t)fl::submod(o[c], s[c], md.p);
+        }
+    }
+}
+
+// Back substitution inside one TRSM block [r0, r1): one wave per 64-column
+// stripe (one column per lane).  Rows of the block are finished from the
+// bottom up and kept in LDS; A-entries at positions >= r1 were applied by the
+// preceding update launch.
+template <int W>
+__global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                   const uint32_t *__restrict__ pos,
+                                                   const uint16_t *__restrict__ val, uint32_t r0,
+                                                   uint32_t r1, uint16_t *X, uint64_t ldx,
+                                                   uint32_t ncols) {
+    __shared__ uint16_t blk[kTrsmBlock][64];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t c = blockIdx.x * 64 + lane;
+    const bool colok = c < ncols;
+    const uint32_t gfirst = r0 / W, glast = (r1 + W - 1) / W;  // groups [gfirst, glast)
+    for (uint32_t g = glast; g-- > gfirst;) {
+        const uint32_t gr0 = g * W;
+        const uint32_t gend = gr0 + W;  // first position outside the group
+        uint64_t kb = gptr[g], ke = gptr[g + 1];
+        uint32_t ah[W], al[W];
+#pragma unroll
+        for (int q = 0; q < W; q++) ah[q] = al[q] = 0;
+        // intra-group entries come first (positions in [gr0, gend)), then the
+        // near entries of the block (positions in [gend, r1))
+        uint64_t kin = first_at_least(pos, kb, ke, gend);
+        uint64_t kfar = first_at_least(pos, kin, ke, r1);
+        uint32_t terms = 0;
+        for (uint64_t k = kin; k < kfar; k += 64) {
+            const int batch = (int)((kfar - k) < 64 ? (kfar - k) : 64);
+            uint32_t mypos = 0;
+            MlVals<W> mv;
+            if ((int)lane < batch) {
+                mypos = pos[k + lane];
+                mv.load(val, k + lane);
+            }
+            for (int j = 0; j < batch; j++) {
+                uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)mypos, j);
+                uint32_t x = blk[pj - r0][lane];
+#pragma unroll
+                for (int q = 0; q < W; q++) {
+                    uint32_t a = mv.get(j, q);
+                    ah[q] = fl::mad24(a >> 8, x, ah[q]);
+                    al[q] = fl::mad24(a & 0xffu, x, al[q]);
+                }
+            }
+            terms += (uint32_t)batch;
+            if (terms > FL_FOLD_TERMS - 64) {
+#pragma unroll
+                for (int q = 0; q < W; q++) {
+                    al[q] = fl::fold_pair(ah[q], al[q], md);
+                    ah[q] = 0;
+                }
+                terms = 0;
+            }
+        }
+        // T_q = X[row] - near sum, then the triangular correction inside the group
+        uint32_t t[W];
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            uint32_t row = gr0 + q;
+            uint32_t cur = (row < r1 && colok) ? X[(uint64_t)row * ldx + c] : 0;
+            t[q] = fl::submod(cur, fl::fold_pair(ah[q], al[q], md), md.p);
+        }
+#pragma unroll
+        for (int q = W - 1; q >= 0; q--) {
+            const uint32_t row = gr0 + q;
+            if (row < r1) {
+                // subtract a[q][j] * v[j] for j > q (rows of the group already final)
+                for (uint64_t k = kb; k < kin; k++) {
+                    const uint32_t qq = pos[k] - gr0;
+                    const uint32_t a = val[(uint64_t)W * k + q];
+#pragma unroll
+                    for (int j = q + 1; j < W; j++)
+                        if (qq == (uint32_t)j && a) t[q] = fl::submod(t[q], fl::mulmod(a, t[j], md), md.p);
+                }
+                blk[row - r0][lane] = (uint16_t)t[q];
+                if (colok) X[(uint64_t)row * ldx + c] = (uint16_t)t[q];
+            }
+        }
+    }
+}
+
+template <int W>
+hipError_t launch_ml_spmm(const fl::Mod &md, const uint64_t *gptr, const uint32_t *pos,
+                          const uint16_t *val, uint32_t g0, uint32_t ngroups, uint32_t row_limit,
+                          uint32_t pos_lo, const uint16_t *X, uint64_t ldx, uint16_t *out,
+                          uint64_t ldo, uint32_t ncols, hipStream_t s) {
+    if (ngroups == 0 || ncols == 0) return hipSuccess;
+    dim3 grid((ncols + kTile - 1) / kTile, (ngroups + 3) / 4);
+    hipLaunchKernelGGL(k_ml_spmm<W>, grid, dim3(256), 0, s, md, gptr, pos, val, g0, ngroups,
+                       row_limit, pos_lo, X, ldx, out, ldo, ncols);
+    return hipGetLastError();
+}
+
+hipError_t ml_spmm(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const uint32_t *pos,
+                   const uint16_t *val, uint32_t g0, uint32_t ngroups, uint32_t row_limit,
+                   uint32_t pos_lo, const uint16_t *X, uint64_t ldx, uint16_t *out, uint64_t ldo,
+                   uint32_t ncols, hipStream_t s) {
+    switch (w) {
+    case 1: return launch_ml_spmm<1>(md, gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx, out, ldo, ncols, s);
+    case 2: return launch_ml_spmm<2>(md, gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx, out, ldo, ncols, s);
+    case 4: return launch_ml_spmm<4>(md, gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx, out, ldo, ncols, s);
+    default: return launch_ml_spmm<8>(md, gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx, out, ldo, ncols, s);
+    }
+}
+
+hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const uint32_t *pos,
+                      const uint16_t *val, uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx,
+                      uint32_t ncols, hipStream_t s) {
+    dim3 grid((ncols + 63) / 64);
+    switch (w) {
+    case 1: hipLaunchKernelGGL(k_trsm_solve<1>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
+    case 2: hipLaunchKernelGGL(k_trsm_solve<2>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
+    case 4: hipLaunchKernelGGL(k_trsm_solve<4>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
+    default: hipLaunchKernelGGL(k_trsm_solve<8>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
+                        const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipError_t e = fl_zero_rows_u16(out, ld, rows, cols, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csr_scatter, dim3((rows + 3) / 4), dim3(256), 0, s, rows, rp, ci, v, out, ld);
+    return hipGetLastError();
+}
+
+fl_status check_split_info(const fl_split_info *info, const fl_split_out *s) {
+    FL_ARG(info && s, "NULL split info/output");
+    FL_ARG(info->status == FL_OK, "split info carries an error status");
+    FL_ARG(info->p >= 2 && info->p <= 65521, "split info: bad p");
+    FL_ARG(info->ml_width == 1 || info->ml_width == 2 || info->ml_width == 4 || info->ml_width == 8,
+           "split info: bad ml_width");
+    FL_ARG(info->npiv + info->nB == info->n && info->npiv + info->mD == info->m,
+           "split info: inconsistent sizes");
+    return FL_OK;
+}
+
+}  // namespace
+
+// Exposed to the other translation units of the library.
+hipError_t fl_ml_spmm(uint32_t w, uint32_t p, const uint64_t *gptr, const uint32_t *pos,
+                      const uint16_t *val, uint32_t g0, uint32_t ngroups, uint32_t row_limit,
+                      uint32_t pos_lo, const uint16_t *X, uint64_t ldx, uint16_t *out,
+                      uint64_t ldo, uint32_t ncols, hipStream_t s) {
+    return ml_spmm(w, fl::make_mod(p), gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx,
+                   out, ldo, ncols, s);
+}
+hipError_t fl_csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
+                           const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s) {
+    return csr_to_dense(rows, cols, rp, ci, v, out, ld, s);
+}
+fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s) {
+    return check_split_info(info, s);
+}
+
+extern "C" size_t fl_trsm_workspace(const fl_split_info *info) {
+    (void)info;
+    return 0;
+}
+
+extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X,
+                             uint64_t ldx, void *ws, size_t ws_bytes, hipStream_t stream) {
+    (void)ws; (void)ws_bytes;
+    fl_status st = check_split_info(info, s);
+    if (st != FL_OK) return st;
+    const uint32_t npiv = info->npiv, nB = info->nB, w = info->ml_width;
+    if (npiv == 0 || nB == 0) return FL_OK;
+    FL_ARG(X, "fl_trsm: NULL X");
+    FL_ARG(ldx >= nB && ldx % 4 == 0, "fl_trsm: ldx must be >= nB and a multiple of 4");
+    FL_ARG(((uintptr_t)X & 7) == 0, "fl_trsm: X must be 8-byte aligned");
+    const fl::Mod md = fl::make_mod(info->p);
+    FL_HIP(csr_to_dense(npiv, nB, s->b_ptr, s->b_col, s->b_val, X, ldx, stream));
+    const uint32_t nblk = (npiv + kTrsmBlock - 1) / kTrsmBlock;
+    for (uint32_t I = nblk; I-- > 0;) {
+        const uint32_t r0 = I * kTrsmBlock;
+        const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
+        if (r1 < npiv) {
+            const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
+            FL_HIP(ml_spmm(w, md, s->a_gptr, s->a_pos, s->a_val, g0, g1 - g0, r1, r1, X, ldx, X,
+                           ldx, nB, stream));
+        }
+        FL_HIP(trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream));
+    }
+    return FL_OK;
+}
