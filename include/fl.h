@@ -227,6 +227,18 @@ const char *fl_version(void);
 fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count, uint64_t *d_mismatch,
                         hipStream_t stream);
 
+/* Launch profiler (diagnostic).  While enabled, the library records HIP
+ * events on the launch stream around its hot kernels (the multiline SpMM, the
+ * TRSM block solve, the dense GEMMs, the echelon panel kernels);
+ * fl_prof_report waits for them and writes a JSON object
+ * {"<site>": {"count": N, "total_ms": T}, ...} into buf (at most len bytes,
+ * NUL-terminated) and returns the length it needs including the NUL.
+ * fl_prof_reset drops the records.  Not thread-safe across concurrent calls
+ * on different streams beyond record bookkeeping. */
+void fl_prof_enable(int on);
+void fl_prof_reset(void);
+size_t fl_prof_report(char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

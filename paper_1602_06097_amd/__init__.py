@@ -23,7 +23,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd",
-           "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp",
+           "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp", "prof_report",
            "version", "Split", "Echelon"]
 
 FL_PLAIN, FL_MFMA_I8 = 0, 1
@@ -94,6 +94,9 @@ def load():
         "fl_last_error": (ct.c_char_p, []),
         "fl_version": (ct.c_char_p, []),
         "fl_check_modp": (ct.c_int, [P(c_u32), c_u32, c_vp, c_vp]),
+        "fl_prof_enable": (None, [ct.c_int]),
+        "fl_prof_reset": (None, []),
+        "fl_prof_report": (c_sz, [ct.c_char_p, c_sz]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -276,6 +279,20 @@ def fl_reduce(row_ptr, col, val, m: int, n: int, p: int, mode: int = FL_PLAIN, m
     rref(sp, X, Dt, ech, mode)
     res.update(echelon=ech, Xp=X, RD=Dt, rref=rref_to_csr(sp, X, Dt, ech))
     return res
+
+
+def prof_report() -> dict:
+    """Per-site launch profile collected while fl_prof_enable(1) was set:
+    {site: {"count": launches, "total_ms": summed HIP-event time}}."""
+    import json
+    lib = load()
+    need = lib.fl_prof_report(None, 0)
+    buf = ct.create_string_buffer(need)
+    lib.fl_prof_report(buf, need)
+    out = json.loads(buf.value.decode())
+    for v in out.values():
+        v["avg_ms"] = v["total_ms"] / max(v["count"], 1)
+    return out
 
 
 def check_modp(primes) -> list:

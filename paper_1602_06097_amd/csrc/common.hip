@@ -1,7 +1,13 @@
 // common.hip -- error plumbing, device scan and fill kernels, self-checks.
 #include "fl_internal.h"
 
+#include <cstdio>
+#include <cstring>
+
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 static thread_local std::string g_last_error;
 
@@ -205,4 +211,90 @@ extern "C" fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count,
         FL_LAUNCH_CHECK("k_check_modp");
     }
     return FL_OK;
+}
+
+// ---- launch profiler ---------------------------------------------------------------
+// When enabled, selected kernel launches are bracketed by HIP events recorded
+// on the launch stream; fl_prof_report aggregates elapsed times per site.
+namespace {
+struct ProfRec {
+    std::string site;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t prof_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+int fl_prof_begin(const char *site, hipStream_t s) {
+    if (!g_prof_on) return -1;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r;
+    r.site = site;
+    r.a = prof_event();
+    r.b = prof_event();
+    if (!r.a || !r.b) return -1;
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    g_prof.push_back(r);
+    return (int)g_prof.size() - 1;
+}
+
+void fl_prof_end(int tok, hipStream_t s) {
+    if (tok < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if ((size_t)tok < g_prof.size()) (void)hipEventRecord(g_prof[tok].b, s);
+}
+
+extern "C" void fl_prof_enable(int on) { g_prof_on = on != 0; }
+
+extern "C" void fl_prof_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_prof.clear();
+}
+
+extern "C" size_t fl_prof_report(char *buf, size_t len) {
+    std::map<std::string, std::pair<uint64_t, double>> agg;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (auto &r : g_prof) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) != hipSuccess) continue;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+            auto &e = agg[r.site];
+            e.first += 1;
+            e.second += ms;
+        }
+    }
+    std::string out = "{";
+    bool first = true;
+    for (auto &kv : agg) {
+        char tmp[256];
+        snprintf(tmp, sizeof tmp, "%s\"%s\": {\"count\": %llu, \"total_ms\": %.6f}", first ? "" : ", ",
+                 kv.first.c_str(), (unsigned long long)kv.second.first, kv.second.second);
+        out += tmp;
+        first = false;
+    }
+    out += "}";
+    if (buf && len) {
+        size_t n = out.size() < len - 1 ? out.size() : len - 1;
+        memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return out.size() + 1;
 }

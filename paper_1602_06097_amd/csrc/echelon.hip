@@ -26,10 +26,11 @@
 
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
                              const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s);
+                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s);
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
+                            const char *site);
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 
 namespace {
@@ -333,17 +334,18 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
     for (uint32_t P = 0; P < npanels; P++) {
         const uint32_t c0 = P * kPanel;
         const uint32_t pw = cols - c0 < kPanel ? cols - c0 : kPanel;
-        hipLaunchKernelGGL(k_ech_greedy<false>, dim3(nchunks), dim3(kGreedyThreads), 0, stream, md,
+        FL_PROF("echelon.greedy", stream, hipLaunchKernelGGL(k_ech_greedy<false>, dim3(nchunks), dim3(kGreedyThreads), 0, stream, md,
                            (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.cand, e.cand_cnt,
-                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank);
+                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank));
         FL_LAUNCH_CHECK("k_ech_greedy<local>");
-        hipLaunchKernelGGL(k_ech_greedy<true>, dim3(1), dim3(kGreedyThreads), 0, stream, md,
+        FL_PROF("echelon.greedy", stream, hipLaunchKernelGGL(k_ech_greedy<true>, dim3(1), dim3(kGreedyThreads), 0, stream, md,
                            (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.cand, e.cand_cnt,
-                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank);
+                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank));
         FL_LAUNCH_CHECK("k_ech_greedy<merge>");
         const uint32_t ucols = cols - c0;
-        hipLaunchKernelGGL(k_ech_U, dim3((ucols + 255) / 256), dim3(256), 0, stream, md,
-                           (const uint16_t *)Dt, ldd, c0, cols, (const PanelState *)e.ps, e.U, e.ldu);
+        FL_PROF("echelon.U", stream,
+                hipLaunchKernelGGL(k_ech_U, dim3((ucols + 255) / 256), dim3(256), 0, stream, md,
+                                   (const uint16_t *)Dt, ldd, c0, cols, (const PanelState *)e.ps, e.U, e.ldu));
         FL_LAUNCH_CHECK("k_ech_U");
         hipLaunchKernelGGL(k_ech_gather_L, dim3((rows + 3) / 4), dim3(256), 0, stream,
                            (const uint16_t *)Dt, ldd, rows, (const PanelState *)e.ps, e.L);
@@ -351,10 +353,10 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
         const uint32_t *kdev = &e.ps->k;
         if (mode == FL_MFMA_I8) {
             FL_HIP(fl_gemm_sub_mfma(p, rows, ucols, kPanel, kdev, e.L, 64, e.U + c0, e.ldu,
-                                    Dt + c0, ldd, e.gemm_ws, e.gemm_ws_bytes, stream));
+                                    Dt + c0, ldd, e.gemm_ws, e.gemm_ws_bytes, stream, "echelon"));
         } else {
             FL_HIP(fl_gemm_sub_plain(p, rows, ucols, 0, kdev, e.L, 64, e.U + c0, e.ldu, Dt + c0,
-                                     ldd, stream));
+                                     ldd, stream, "echelon.plain"));
         }
         hipLaunchKernelGGL(k_ech_setq, dim3((ucols + 255) / 256, kPanel), dim3(256), 0, stream, Dt,
                            ldd, c0, cols, (const PanelState *)e.ps, (const uint16_t *)e.U, e.ldu);

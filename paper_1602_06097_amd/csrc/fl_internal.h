@@ -123,3 +123,16 @@ hipError_t fl_exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, ui
 hipError_t fl_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t fl_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t cols, hipStream_t s);
+
+// Launch profiler (see fl_prof_* in fl.h): returns a token for fl_prof_end,
+// or -1 when profiling is off.
+int fl_prof_begin(const char *site, hipStream_t s);
+void fl_prof_end(int tok, hipStream_t s);
+
+// Bracket one launch statement with profiler events (no-op when disabled).
+#define FL_PROF(site, stream, ...)                                      \
+    do {                                                                \
+        int tok_ = fl_prof_begin(site, stream);                         \
+        __VA_ARGS__;                                                    \
+        fl_prof_end(tok_, stream);                                      \
+    } while (0)

@@ -18,6 +18,8 @@
 // bounds checks in its main loop.
 #include "fl_internal.h"
 
+#include <cstdio>
+
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -206,7 +208,11 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax) {
 // fl_gemm_sub_plain.
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s) {
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
+                            const char *site) {
+    char site_limbs[64], site_mfma[64];
+    snprintf(site_limbs, sizeof site_limbs, "%s.limbs", site ? site : "gemm");
+    snprintf(site_mfma, sizeof site_mfma, "%s.mfma", site ? site : "gemm");
     if (M == 0 || N == 0 || Kmax == 0) return hipSuccess;
     MfmaWs w;
     if (mfma_layout(M, N, Kmax, ws, &w) > ws_bytes || !ws) return hipErrorInvalidValue;
@@ -217,23 +223,23 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
     const uint32_t c16 = (uint32_t)((1u << 16) % p);
     {
         dim3 g(w.Kp / 4 / 256 + 1, w.Mp < 65535 ? w.Mp : 65535);
-        hipLaunchKernelGGL(k_limbs_rows, g, dim3(256), 0, s, p, A, lda, M, Kmax, Kdev, w.Ah, w.Al,
-                           w.Mp, w.Kp);
+        FL_PROF(site_limbs, s, hipLaunchKernelGGL(k_limbs_rows, g, dim3(256), 0, s, p, A, lda, M, Kmax, Kdev,
+                                                  w.Ah, w.Al, w.Mp, w.Kp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     {
         dim3 g(w.Np / 64, w.Kp / 64);
-        hipLaunchKernelGGL(k_limbs_cols, g, dim3(256), 0, s, p, B, ldb, N, Kmax, Kdev, w.Bh, w.Bl,
-                           w.Kp);
+        FL_PROF(site_limbs, s, hipLaunchKernelGGL(k_limbs_cols, g, dim3(256), 0, s, p, B, ldb, N, Kmax, Kdev,
+                                                  w.Bh, w.Bl, w.Kp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     dim3 grid(w.Np / BN, w.Mp / BM);
     for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
-        hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, w.Ah, w.Al, w.Bh,
-                           w.Bl, w.Kp, kb, ke, Kdev, C, ldc, M, N);
+        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, w.Ah,
+                                                 w.Al, w.Bh, w.Bl, w.Kp, kb, ke, Kdev, C, ldc, M, N));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -116,10 +116,11 @@ __global__ __launch_bounds__(256) void k_gemm_sub(fl::Mod md, uint32_t M, uint32
 // C 8-byte aligned; A needs no alignment.
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
                              const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s) {
+                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site) {
     if (M == 0 || N == 0) return hipSuccess;
     dim3 grid((N + kColsPerWave - 1) / kColsPerWave, (M + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave));
-    hipLaunchKernelGGL(k_gemm_sub, grid, dim3(256), 0, s, fl::make_mod(p), M, N, Kh, Kdev, A, lda,
-                       B, ldb, C, ldc);
+    FL_PROF(site ? site : "gemm.plain", s,
+            hipLaunchKernelGGL(k_gemm_sub, grid, dim3(256), 0, s, fl::make_mod(p), M, N, Kh, Kdev, A,
+                               lda, B, ldb, C, ldc));
     return hipGetLastError();
 }

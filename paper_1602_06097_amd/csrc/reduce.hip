@@ -12,16 +12,17 @@
 hipError_t fl_ml_spmm(uint32_t w, uint32_t p, const uint64_t *gptr, const uint32_t *pos,
                       const uint16_t *val, uint32_t g0, uint32_t ngroups, uint32_t row_limit,
                       uint32_t pos_lo, const uint16_t *X, uint64_t ldx, uint16_t *out,
-                      uint64_t ldo, uint32_t ncols, hipStream_t s);
+                      uint64_t ldo, uint32_t ncols, hipStream_t s, const char *site);
 hipError_t fl_csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
                            const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s);
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
                              const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s);
+                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s);
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
+                            const char *site);
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 
 namespace {
@@ -95,7 +96,7 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
     const uint32_t ngroups = (mD + w - 1) / w;
     if (mode == FL_PLAIN) {
         FL_HIP(fl_ml_spmm(w, info->p, s->c_gptr, s->c_pos, s->c_val, 0, ngroups, mD, 0, X, ldx, Dt,
-                          ldd, nB, stream));
+                          ldd, nB, stream, "reduce.spmm"));
         return FL_OK;
     }
     FL_HIP(fl_zero_rows_u16(r.Cd, r.ldc, mD, npiv, stream));
@@ -104,7 +105,7 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
                        (const uint16_t *)s->c_val, r.Cd, r.ldc);
     FL_LAUNCH_CHECK("k_ml_to_dense");
     FL_HIP(fl_gemm_sub_mfma(info->p, mD, nB, npiv, nullptr, r.Cd, r.ldc, X, ldx, Dt, ldd, r.gemm_ws,
-                            r.gemm_ws_bytes, stream));
+                            r.gemm_ws_bytes, stream, "reduce"));
     return FL_OK;
 }
 
@@ -125,7 +126,7 @@ extern "C" fl_status fl_matmul_sub(uint32_t p, uint32_t M, uint32_t N, uint32_t 
     FL_ARG(((uintptr_t)Xm & 7) == 0 && ((uintptr_t)Dm & 7) == 0,
            "fl_matmul_sub: Xm, Dm must be 8-byte aligned");
     if (mode == FL_PLAIN) {
-        FL_HIP(fl_gemm_sub_plain(p, M, N, K, nullptr, Cm, ldc, Xm, ldx, Dm, ldd, stream));
+        FL_HIP(fl_gemm_sub_plain(p, M, N, K, nullptr, Cm, ldc, Xm, ldx, Dm, ldd, stream, "matmul.plain"));
         return FL_OK;
     }
     size_t need = fl_gemm_sub_mfma_ws(M, N, K);
@@ -133,6 +134,6 @@ extern "C" fl_status fl_matmul_sub(uint32_t p, uint32_t M, uint32_t N, uint32_t 
         fl_set_error("fl_matmul_sub: workspace too small");
         return FL_ERR_WORKSPACE;
     }
-    FL_HIP(fl_gemm_sub_mfma(p, M, N, K, nullptr, Cm, ldc, Xm, ldx, Dm, ldd, ws, ws_bytes, stream));
+    FL_HIP(fl_gemm_sub_mfma(p, M, N, K, nullptr, Cm, ldc, Xm, ldx, Dm, ldd, ws, ws_bytes, stream, "matmul"));
     return FL_OK;
 }

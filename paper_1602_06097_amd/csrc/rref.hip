@@ -15,10 +15,11 @@
 
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
                              const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s);
+                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s);
+                            uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
+                            const char *site);
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 
@@ -195,9 +196,10 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
     FL_LAUNCH_CHECK("k_gather_pivcols");
     if (mode == FL_MFMA_I8) {
         FL_HIP(fl_gemm_sub_mfma(info->p, npiv, nB, maxr, d_rank, r.L, r.ldl, RD, ldd, X, ldx,
-                                r.gemm_ws, r.gemm_ws_bytes, stream));
+                                r.gemm_ws, r.gemm_ws_bytes, stream, "rref"));
     } else {
-        FL_HIP(fl_gemm_sub_plain(info->p, npiv, nB, 0, d_rank, r.L, r.ldl, RD, ldd, X, ldx, stream));
+        FL_HIP(fl_gemm_sub_plain(info->p, npiv, nB, 0, d_rank, r.L, r.ldl, RD, ldd, X, ldx, stream,
+                                 "rref.plain"));
     }
     return FL_OK;
 }

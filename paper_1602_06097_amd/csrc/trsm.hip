@@ -344,9 +344,11 @@ fl_status check_split_info(const fl_split_info *info, const fl_split_out *s) {
 hipError_t fl_ml_spmm(uint32_t w, uint32_t p, const uint64_t *gptr, const uint32_t *pos,
                       const uint16_t *val, uint32_t g0, uint32_t ngroups, uint32_t row_limit,
                       uint32_t pos_lo, const uint16_t *X, uint64_t ldx, uint16_t *out,
-                      uint64_t ldo, uint32_t ncols, hipStream_t s) {
-    return ml_spmm(w, fl::make_mod(p), gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx,
-                   out, ldo, ncols, s);
+                      uint64_t ldo, uint32_t ncols, hipStream_t s, const char *site) {
+    hipError_t e;
+    FL_PROF(site, s, e = ml_spmm(w, fl::make_mod(p), gptr, pos, val, g0, ngroups, row_limit, pos_lo,
+                                 X, ldx, out, ldo, ncols, s));
+    return e;
 }
 hipError_t fl_csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
                            const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s) {
@@ -372,17 +374,25 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
     FL_ARG(ldx >= nB && ldx % 4 == 0, "fl_trsm: ldx must be >= nB and a multiple of 4");
     FL_ARG(((uintptr_t)X & 7) == 0, "fl_trsm: X must be 8-byte aligned");
     const fl::Mod md = fl::make_mod(info->p);
-    FL_HIP(csr_to_dense(npiv, nB, s->b_ptr, s->b_col, s->b_val, X, ldx, stream));
+    hipError_t e0;
+    FL_PROF("trsm.densify", stream, e0 = csr_to_dense(npiv, nB, s->b_ptr, s->b_col, s->b_val, X, ldx, stream));
+    FL_HIP(e0);
     const uint32_t nblk = (npiv + kTrsmBlock - 1) / kTrsmBlock;
     for (uint32_t I = nblk; I-- > 0;) {
         const uint32_t r0 = I * kTrsmBlock;
         const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
         if (r1 < npiv) {
             const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
-            FL_HIP(ml_spmm(w, md, s->a_gptr, s->a_pos, s->a_val, g0, g1 - g0, r1, r1, X, ldx, X,
-                           ldx, nB, stream));
+            hipError_t e;
+            FL_PROF("trsm.update", stream,
+                    e = ml_spmm(w, md, s->a_gptr, s->a_pos, s->a_val, g0, g1 - g0, r1, r1, X, ldx, X,
+                                ldx, nB, stream));
+            FL_HIP(e);
         }
-        FL_HIP(trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream));
+        hipError_t e;
+        FL_PROF("trsm.solve", stream,
+                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream));
+        FL_HIP(e);
     }
     return FL_OK;
 }
