@@ -3,23 +3,25 @@
 // blocked Gauss-Jordan elimination over 64-column panels.
 //
 // For a panel [c0, c0+64):
-//  1. k_ech_greedy<false>  one block per chunk of 1024 rows: the chunk's rows
-//     that are independent on the panel columns (a greedy basis in reduced
-//     form kept in LDS; every wave reduces one row against the basis with
-//     v_readlane broadcasts, insertions are serialised) -> candidate rows.
-//  2. k_ech_greedy<true>   one block: the same over all candidates, tracking
-//     the coefficients G with  G * Dt[Q, panel] = RREF(Dt[Q, panel]),
-//     Q = selected rows.  This yields the panel's pivot columns C (ascending)
-//     and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
-//     This plays the role of the paper's parallel structured Gaussian
-//     elimination (Sec. 5.1: rows reduced in parallel against the known
-//     pivots, a new pivot added only by one worker at a time).
-//  3. k_ech_U              U = G * Dt[Q, c0:]   (unit vectors at C)
-//  4. k_ech_gather_L       L = Dt[:, C]          (multipliers, saved before
+//  1. k_ech_probe   one block: a greedy basis of the first 256 remaining rows
+//     restricted to the panel, in reduced form in LDS.  Every wave reduces one
+//     row against the basis (multipliers broadcast with v_readlane); rows
+//     that stay nonzero are inserted one wave at a time.  The coefficients G
+//     with  G * Dt[Q, panel] = basis  are tracked (Q = selected rows).
+//     This is the paper's parallel structured Gaussian elimination (Sec. 5.1:
+//     rows reduced in parallel against the known pivots, a new pivot added by
+//     one worker at a time) applied to a panel.
+//  2. k_ech_check   every remaining row is reduced against that basis in
+//     parallel; rows outside its span are flagged.
+//  3. k_ech_merge   only if a row was flagged: the greedy pass continues over
+//     the flagged rows.  The result: pivot columns C (ascending) of the
+//     panel, rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
+//  4. k_ech_U              U = G * Dt[Q, c0:]   (unit vectors at C)
+//  5. k_ech_gather_L       L = Dt[:, C]          (multipliers, saved before
 //                                                 the update overwrites them)
-//  5. fl_gemm_sub_plain    Dt[:, c0:] -= L U    (every row: Gauss-Jordan
-//     (or the int8 MFMA form)                   clears C above and below)
-//  6. k_ech_setq           Dt[Q_t, c0:] = U_t
+//  6. rank-k update        Dt[:, c0:] -= L U    (every row: Gauss-Jordan
+//     (VALU or int8 MFMA)                       clears C above and below)
+//  7. k_ech_setq           Dt[Q_t, c0:] = U_t
 // After the last panel the pivot rows are gathered to rows 0..r-1 in pivot
 // order and the other rows (now zero) are cleared.
 #include "fl_internal.h"
@@ -36,23 +38,27 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 namespace {
 
 constexpr uint32_t kPanel = 64;
-constexpr uint32_t kChunk = 1024;
+constexpr uint32_t kProbe = 256;  // rows in the probe basis pass
 constexpr int kGreedyThreads = 1024;
 
 struct PanelState {
-    uint32_t k;            // pivots found in this panel
-    uint32_t pad[3];
+    uint32_t k;            // pivots found in this panel (final)
+    uint32_t rank0;        // rank before this panel
+    uint32_t nflag;        // rows outside the probe basis' span
+    uint32_t kb;           // raw basis size (insertion order)
     uint32_t Qs[64];       // selected rows, by insertion slot
     uint32_t Phys[64];     // row that receives U_t
     uint32_t Ccol[64];     // absolute pivot column of U_t (ascending)
+    uint32_t Cc[64];       // raw: relative pivot column of basis row j
     uint16_t G[64 * 64];   // G[t][s]: U_t = sum_s G[t][s] Dt[Qs[s]]
+    uint16_t Bv[64 * 64];  // raw basis rows (panel part), insertion order
+    uint16_t Bg[64 * 64];  // raw basis rows (coefficient part)
 };
 
 struct EchWs {
     uint32_t *is_piv;   // [rows] 1 once the row is a pivot row
+    uint32_t *flags;    // [rows] 1 if the row is outside the probe basis' span
     uint32_t *piv_row;  // [min(rows, cols)]
-    uint32_t *cand;     // [nchunks * 64]
-    uint32_t *cand_cnt; // [nchunks]
     PanelState *ps;
     uint16_t *U;        // [64 x ldu]
     uint16_t *L;        // [rows x 64]
@@ -90,118 +96,225 @@ __device__ inline void reduce_against(const fl::Mod &md, uint32_t &v, uint32_t &
     if (track) g = fl::submod(g, fl::fold_pair(gh, gl, md), md.p);
 }
 
-template <bool MERGE>
-__global__ __launch_bounds__(kGreedyThreads) void k_ech_greedy(
-    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
-    uint32_t pw, uint32_t *is_piv, uint32_t *cand, uint32_t *cand_cnt, uint32_t nchunks,
-    PanelState *ps, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
-    __shared__ uint16_t Bv[64][64];
-    __shared__ uint16_t Bg[64][64];
-    __shared__ uint32_t Cc[64];
-    __shared__ uint32_t Qo[64];
-    __shared__ uint32_t kb_s;
-    __shared__ uint32_t list_s[64];
+// Greedy basis of the panel rows in LDS: reduced form over the panel
+// columns (Bv, pivots Cc), with the coefficients G of every basis row on the
+// selected input rows Qo (Bg), so that  Bv_j = sum_s Bg_j[s] Dt[Qo[s], panel].
+struct GreedyLds {
+    uint16_t Bv[64][64];
+    uint16_t Bg[64][64];
+    uint32_t Cc[64];
+    uint32_t Qo[64];
+    uint32_t kb;
+    uint32_t cnt;
+    uint32_t list[kGreedyThreads];
+};
+
+// Process rows S.list[0..S.cnt) in order: each wave reduces one row against
+// the basis; rows still nonzero are inserted one wave at a time (a new pivot
+// is the first nonzero column; it is cleared from the other basis rows).
+// This is the paper's parallel structured elimination (Sec. 5.1) in
+// miniature: reductions in parallel, insertion of a new pivot serialised.
+__device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, uint64_t ld,
+                            uint32_t c0, uint32_t pw, GreedyLds &S) {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
-    if (threadIdx.x == 0) kb_s = 0;
-    __syncthreads();
-
-    // Work list: LOCAL = rows of chunk blockIdx.x; MERGE = candidates of all
-    // chunks, in chunk order.
-    const uint32_t nlists = MERGE ? nchunks : 1;
-    for (uint32_t li = 0; li < nlists; li++) {
-        uint32_t lo, cnt;
-        if (MERGE) {
-            cnt = cand_cnt[li];
-            if (threadIdx.x < cnt) list_s[threadIdx.x] = cand[li * 64 + threadIdx.x];
-            __syncthreads();
-            lo = 0;
-        } else {
-            lo = blockIdx.x * kChunk;
-            cnt = lo < rows ? (rows - lo < kChunk ? rows - lo : kChunk) : 0;
-        }
-        for (uint32_t base = 0; base < cnt; base += nw) {
-            if (kb_s >= pw) break;  // panel full: every further row reduces to 0
-            uint32_t item = base + wave;
-            uint32_t row = 0xffffffffu;
-            if (item < cnt) {
-                row = MERGE ? list_s[item] : lo + item;
-                if (!MERGE && is_piv[row]) row = 0xffffffffu;
-            }
-            const bool have = row != 0xffffffffu;
-            uint32_t v = (have && lane < pw) ? D[(uint64_t)row * ld + c0 + lane] : 0;
-            uint32_t g = 0;
-            const uint32_t ks = kb_s;
-            reduce_against(md, v, g, 0, ks, Bv, Bg, Cc, lane, MERGE);
-            bool nz = have && __ballot(v != 0) != 0;
-            int any = __syncthreads_or(nz ? 1 : 0);
-            if (any) {
-                for (uint32_t w = 0; w < nw; w++) {
-                    if (w == wave && nz) {
-                        const uint32_t kb = kb_s;
-                        reduce_against(md, v, g, ks, kb, Bv, Bg, Cc, lane, MERGE);
-                        uint64_t mask = __ballot(v != 0);
-                        if (mask != 0 && kb < pw) {
-                            const int c = __ffsll((long long)mask) - 1;
-                            if (lane == kb) g = 1;
-                            uint32_t piv = (uint32_t)__builtin_amdgcn_readlane((int)v, c);
-                            uint32_t inv = fl::invmod(piv, md);
-                            v = fl::mulmod(v, inv, md);
-                            g = fl::mulmod(g, inv, md);
-                            for (uint32_t t = 0; t < kb; t++) {
-                                uint32_t f = Bv[t][c];
-                                if (f) {
-                                    Bv[t][lane] = (uint16_t)fl::submod(Bv[t][lane], fl::mulmod(f, v, md), md.p);
-                                    Bg[t][lane] = (uint16_t)fl::submod(Bg[t][lane], fl::mulmod(f, g, md), md.p);
-                                }
-                            }
-                            Bv[kb][lane] = (uint16_t)v;
-                            Bg[kb][lane] = (uint16_t)g;
-                            if (lane == 0) {
-                                Cc[kb] = (uint32_t)c;
-                                Qo[kb] = row;
-                                kb_s = kb + 1;
-                            }
+    const uint32_t cnt = S.cnt;
+    for (uint32_t base = 0; base < cnt; base += nw) {
+        if (S.kb >= pw) break;  // panel full: every further row reduces to 0
+        const uint32_t item = base + wave;
+        const bool have = item < cnt;
+        const uint32_t row = have ? S.list[item] : 0;
+        uint32_t v = (have && lane < pw) ? D[(uint64_t)row * ld + c0 + lane] : 0;
+        uint32_t g = 0;
+        const uint32_t ks = S.kb;
+        reduce_against(md, v, g, 0, ks, S.Bv, S.Bg, S.Cc, lane, true);
+        const bool nz = have && __ballot(v != 0) != 0;
+        const int any = __syncthreads_or(nz ? 1 : 0);
+        if (!any) continue;
+        for (uint32_t w = 0; w < nw; w++) {
+            if (w == wave && nz) {
+                const uint32_t kb = S.kb;
+                reduce_against(md, v, g, ks, kb, S.Bv, S.Bg, S.Cc, lane, true);
+                const uint64_t mask = __ballot(v != 0);
+                if (mask != 0 && kb < pw) {
+                    const int c = __ffsll((long long)mask) - 1;
+                    if (lane == kb) g = 1;
+                    const uint32_t piv = (uint32_t)__builtin_amdgcn_readlane((int)v, c);
+                    const uint32_t inv = fl::invmod(piv, md);
+                    v = fl::mulmod(v, inv, md);
+                    g = fl::mulmod(g, inv, md);
+                    for (uint32_t t = 0; t < kb; t++) {
+                        const uint32_t f = S.Bv[t][c];
+                        if (f) {
+                            S.Bv[t][lane] = (uint16_t)fl::submod(S.Bv[t][lane], fl::mulmod(f, v, md), md.p);
+                            S.Bg[t][lane] = (uint16_t)fl::submod(S.Bg[t][lane], fl::mulmod(f, g, md), md.p);
                         }
                     }
-                    __syncthreads();
+                    S.Bv[kb][lane] = (uint16_t)v;
+                    S.Bg[kb][lane] = (uint16_t)g;
+                    if (lane == 0) {
+                        S.Cc[kb] = (uint32_t)c;
+                        S.Qo[kb] = row;
+                        S.kb = kb + 1;
+                    }
                 }
             }
+            __syncthreads();
         }
+    }
+    __syncthreads();
+}
+
+// Collect up to kGreedyThreads row indices r >= *next with pred(r) into
+// S.list (ascending); *next is advanced past the rows examined.
+template <class Pred>
+__device__ void collect_rows(uint32_t rows, uint32_t &next, uint32_t want, GreedyLds &S, Pred pred) {
+    __shared__ uint32_t wave_cnt[kGreedyThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) S.cnt = 0;
+    __syncthreads();
+    while (next < rows && S.cnt < want) {
+        const uint32_t r = next + threadIdx.x;
+        const bool ok = r < rows && pred(r);
+        const uint64_t mask = __ballot(ok);
+        if (lane == 0) wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        uint32_t before = S.cnt;
+        for (uint32_t w = 0; w < wave; w++) before += wave_cnt[w];
+        const uint64_t below = lane == 0 ? 0 : (mask & (~(uint64_t)0 >> (64 - lane)));
+        const uint32_t at = before + __popcll(below);
+        if (ok && at < want) S.list[at] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = S.cnt;
+            for (uint32_t w = 0; w < blockDim.x / 64; w++) tot += wave_cnt[w];
+            S.cnt = tot < want ? tot : want;
+        }
+        next += blockDim.x;
         __syncthreads();
     }
+}
 
-    const uint32_t kb = kb_s;
-    if (!MERGE) {
-        if (threadIdx.x < kb) cand[blockIdx.x * 64 + threadIdx.x] = Qo[threadIdx.x];
-        if (threadIdx.x == 0) cand_cnt[blockIdx.x] = kb;
-        return;
+__device__ void save_raw(const GreedyLds &S, PanelState *ps) {
+    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+        ps->Bv[i] = S.Bv[i >> 6][i & 63];
+        ps->Bg[i] = S.Bg[i >> 6][i & 63];
     }
+    if (threadIdx.x < 64) {
+        ps->Cc[threadIdx.x] = S.Cc[threadIdx.x];
+        ps->Qs[threadIdx.x] = S.Qo[threadIdx.x];
+    }
+    if (threadIdx.x == 0) ps->kb = S.kb;
+}
+
+// Publish the panel result: basis rows ordered by pivot column, G, and the
+// global pivot bookkeeping (rank0 = rank before this panel).
+__device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32_t rank0,
+                         uint32_t *is_piv, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (wave != 0) return;
-    // order basis rows by pivot column
+    const uint32_t kb = S.kb;
     uint32_t my_t = 0;
     if (lane < kb) {
-        uint32_t cj = Cc[lane];
-        for (uint32_t j = 0; j < kb; j++) my_t += Cc[j] < cj ? 1 : 0;
+        const uint32_t cj = S.Cc[lane];
+        for (uint32_t j = 0; j < kb; j++) my_t += S.Cc[j] < cj ? 1 : 0;
     }
-    const uint32_t rank0 = *d_rank;
     for (uint32_t j = 0; j < kb; j++) {
-        uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)my_t, (int)j);
-        ps->G[t * 64 + lane] = lane < kb ? Bg[j][lane] : 0;
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)my_t, (int)j);
+        ps->G[t * 64 + lane] = lane < kb ? S.Bg[j][lane] : 0;
     }
     if (lane < kb) {
         const uint32_t t = my_t;
-        ps->Qs[lane] = Qo[lane];
-        ps->Phys[t] = Qo[lane];
-        ps->Ccol[t] = c0 + Cc[lane];
-        piv_row[rank0 + t] = Qo[lane];
-        piv_col[rank0 + t] = c0 + Cc[lane];
-        is_piv[Qo[lane]] = 1;  // later panels skip this row
+        ps->Phys[t] = S.Qo[lane];
+        ps->Ccol[t] = c0 + S.Cc[lane];
+        piv_row[rank0 + t] = S.Qo[lane];
+        piv_col[rank0 + t] = c0 + S.Cc[lane];
+        is_piv[S.Qo[lane]] = 1;  // later panels skip this row
     }
     if (lane == 0) {
         ps->k = kb;
         *d_rank = rank0 + kb;
     }
+}
+
+// Panel step 1: greedy basis of the first kProbe remaining rows.
+__global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
+    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
+    uint32_t pw, uint32_t *is_piv, PanelState *ps, uint32_t *piv_row, uint32_t *piv_col,
+    uint32_t *d_rank) {
+    __shared__ GreedyLds S;
+    __shared__ uint32_t rank0_s;
+    if (threadIdx.x == 0) {
+        S.kb = 0;
+        rank0_s = *d_rank;
+        ps->nflag = 0;
+        ps->rank0 = rank0_s;
+    }
+    __syncthreads();
+    const uint32_t rank0 = rank0_s;
+    uint32_t next = 0;
+    collect_rows(rows, next, kProbe, S, [&](uint32_t r) { return is_piv[r] == 0; });
+    greedy_rows(md, D, ld, c0, pw, S);
+    save_raw(S, ps);
+    finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
+}
+
+// Panel step 2: every remaining row is reduced against the probe basis in
+// parallel; rows with a nonzero remainder (outside the basis' span) are
+// flagged.  One wave per row, 4 rows per wave.
+__global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const uint16_t *__restrict__ D,
+                                                   uint64_t ld, uint32_t rows, uint32_t c0,
+                                                   uint32_t pw, const uint32_t *__restrict__ is_piv,
+                                                   PanelState *ps, uint32_t *flags) {
+    __shared__ uint16_t Bv[64][64];
+    __shared__ uint32_t Cc[64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t kb = ps->kb;
+    for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) Bv[i >> 6][i & 63] = ps->Bv[i];
+    if (threadIdx.x < 64) Cc[threadIdx.x] = ps->Cc[threadIdx.x];
+    __syncthreads();
+    for (uint32_t u = 0; u < 4; u++) {
+        const uint32_t i = (blockIdx.x * 4 + wave) * 4 + u;
+        if (i >= rows) break;
+        uint32_t flag = 0;
+        if (!is_piv[i] && kb < pw) {
+            uint32_t v = lane < pw ? D[(uint64_t)i * ld + c0 + lane] : 0, g = 0;
+            reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
+            flag = __ballot(v != 0) != 0 ? 1u : 0u;
+        }
+        if (lane == 0) {
+            flags[i] = flag;
+            if (flag) atomicAdd(&ps->nflag, 1u);
+        }
+    }
+}
+
+// Panel step 3 (only when some row was flagged): continue the greedy basis
+// with the flagged rows in row order and publish the final result.
+__global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
+    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
+    uint32_t pw, const uint32_t *__restrict__ flags, uint32_t *is_piv, PanelState *ps,
+    uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+    __shared__ GreedyLds S;
+    if (ps->nflag == 0) return;
+    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+        S.Bv[i >> 6][i & 63] = ps->Bv[i];
+        S.Bg[i >> 6][i & 63] = ps->Bg[i];
+    }
+    if (threadIdx.x < 64) {
+        S.Cc[threadIdx.x] = ps->Cc[threadIdx.x];
+        S.Qo[threadIdx.x] = ps->Qs[threadIdx.x];
+    }
+    if (threadIdx.x == 0) S.kb = ps->kb;
+    __syncthreads();
+    const uint32_t rank0 = ps->rank0;
+    uint32_t next = 0;
+    while (next < rows && S.kb < pw) {
+        collect_rows(rows, next, kGreedyThreads, S, [&](uint32_t r) { return flags[r] != 0; });
+        greedy_rows(md, D, ld, c0, pw, S);
+    }
+    save_raw(S, ps);
+    finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
 }
 
 // U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k.
@@ -282,13 +395,11 @@ __global__ __launch_bounds__(256) void k_ech_place_rows(uint16_t *D, uint64_t ld
 size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e) {
     WsCarve c(ws);
     const uint32_t mn = rows < cols ? rows : cols;
-    const uint32_t nchunks = (rows + kChunk - 1) / kChunk;
     const uint64_t ldu = ((uint64_t)cols + 63) & ~(uint64_t)63;
     EchWs t;
     t.is_piv = c.take<uint32_t>(rows ? rows : 1);
+    t.flags = c.take<uint32_t>(rows ? rows : 1);
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
-    t.cand = c.take<uint32_t>((size_t)(nchunks ? nchunks : 1) * 64);
-    t.cand_cnt = c.take<uint32_t>(nchunks ? nchunks : 1);
     t.ps = c.take<PanelState>(1);
     t.U = c.take<uint16_t>((size_t)64 * ldu);
     t.L = c.take<uint16_t>((size_t)(rows ? rows : 1) * 64);
@@ -327,21 +438,27 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
         return FL_ERR_WORKSPACE;
     }
     const fl::Mod md = fl::make_mod(p);
-    const uint32_t nchunks = (rows + kChunk - 1) / kChunk;
     FL_HIP(fl_fill_u32(e.is_piv, 0, rows, stream));
     FL_HIP(fl_fill_u32(d_rank, 0, 1, stream));
     const uint32_t npanels = (cols + kPanel - 1) / kPanel;
     for (uint32_t P = 0; P < npanels; P++) {
         const uint32_t c0 = P * kPanel;
         const uint32_t pw = cols - c0 < kPanel ? cols - c0 : kPanel;
-        FL_PROF("echelon.greedy", stream, hipLaunchKernelGGL(k_ech_greedy<false>, dim3(nchunks), dim3(kGreedyThreads), 0, stream, md,
-                           (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.cand, e.cand_cnt,
-                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank));
-        FL_LAUNCH_CHECK("k_ech_greedy<local>");
-        FL_PROF("echelon.greedy", stream, hipLaunchKernelGGL(k_ech_greedy<true>, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                           (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.cand, e.cand_cnt,
-                           nchunks, e.ps, e.piv_row, d_pivcol, d_rank));
-        FL_LAUNCH_CHECK("k_ech_greedy<merge>");
+        FL_PROF("echelon.probe", stream,
+                hipLaunchKernelGGL(k_ech_probe, dim3(1), dim3(kGreedyThreads), 0, stream, md,
+                                   (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.ps, e.piv_row,
+                                   d_pivcol, d_rank));
+        FL_LAUNCH_CHECK("k_ech_probe");
+        FL_PROF("echelon.check", stream,
+                hipLaunchKernelGGL(k_ech_check, dim3((rows + 15) / 16), dim3(256), 0, stream, md,
+                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.is_piv,
+                                   e.ps, e.flags));
+        FL_LAUNCH_CHECK("k_ech_check");
+        FL_PROF("echelon.merge", stream,
+                hipLaunchKernelGGL(k_ech_merge, dim3(1), dim3(kGreedyThreads), 0, stream, md,
+                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.flags,
+                                   e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
+        FL_LAUNCH_CHECK("k_ech_merge");
         const uint32_t ucols = cols - c0;
         FL_PROF("echelon.U", stream,
                 hipLaunchKernelGGL(k_ech_U, dim3((ucols + 255) / 256), dim3(256), 0, stream, md,

@@ -27,6 +27,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int BM = 128, BN = 128, BK = 64;
 constexpr uint32_t kKChunk = 65472;  // multiple of BK, < 65536
 constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conflicts
+constexpr int kOutLd = BN + 4;       // u16 row stride of the epilogue tile (8-byte aligned rows)
 
 __device__ __forceinline__ void split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
     const int r = x <= 32639u ? (int)x : (int)x - (int)p;
@@ -99,8 +100,10 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
                                                    const uint32_t *__restrict__ Kdev,
                                                    uint16_t *C, uint64_t ldc, uint32_t M,
                                                    uint32_t N) {
-    __shared__ __attribute__((aligned(16))) int8_t sAh[BM * kLdsRow], sAl[BM * kLdsRow];
-    __shared__ __attribute__((aligned(16))) int8_t sBh[BN * kLdsRow], sBl[BN * kLdsRow];
+    __shared__ __attribute__((aligned(16))) int8_t smem[4 * BM * kLdsRow];
+    static_assert(BM * kOutLd * 2 <= 4 * BM * kLdsRow, "epilogue tile must fit the operand buffers");
+    int8_t *sAh = smem, *sAl = smem + BM * kLdsRow;
+    int8_t *sBh = smem + 2 * BM * kLdsRow, *sBl = smem + 3 * BM * kLdsRow;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t wm = wave >> 1, wn = wave & 1;
     const uint32_t m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -154,26 +157,48 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
             }
         __syncthreads();
     }
-    // epilogue: output element (row 4*(lane/16) + e, column lane%16) of each tile
+    // epilogue: residues of the 128 x 128 tile go through LDS (the operand
+    // buffers are free now), then C is read, reduced and written back with
+    // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
+    // column lane%16) of each 16 x 16 tile is held by the wave.
+    uint16_t *sOut = (uint16_t *)sAh;  // 128 x kOutLd u16 spans sAh..sBl
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            const uint32_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+            const uint32_t col = wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const uint32_t row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
-                if (row < M && col < N) {
-                    const uint32_t rhh = signed_to_res(acc_hh[i][j][e], md, bias);
-                    const uint32_t rmid = signed_to_res(acc_mid[i][j][e], md, bias);
-                    const uint32_t rll = signed_to_res(acc_ll[i][j][e], md, bias);
-                    uint32_t v = fl::reduce32(rhh * c16 + rll, md);
-                    v = fl::reduce32(v + rmid * 256u, md);
-                    uint16_t *o = C + (uint64_t)row * ldc + col;
-                    *o = (uint16_t)fl::submod(*o, v, md.p);
-                }
+                const uint32_t row = wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                const uint32_t rhh = signed_to_res(acc_hh[i][j][e], md, bias);
+                const uint32_t rmid = signed_to_res(acc_mid[i][j][e], md, bias);
+                const uint32_t rll = signed_to_res(acc_ll[i][j][e], md, bias);
+                uint32_t v = fl::reduce32(rhh * c16 + rll, md);
+                v = fl::reduce32(v + rmid * 256u, md);
+                sOut[row * kOutLd + col] = (uint16_t)v;
             }
         }
+    __syncthreads();
+    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each
+    for (uint32_t ch = tid; ch < BM * (BN / 4); ch += 256) {
+        const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+        const uint32_t row = m0 + r, col = n0 + c4;
+        if (row >= M || col >= N) continue;
+        uint16_t *o = C + (uint64_t)row * ldc + col;
+        const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
+        if (col + 4 <= N) {
+            const uint64_t ov = *(const uint64_t *)o;
+            uint64_t nv = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
+                                           (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+            *(uint64_t *)o = nv;
+        } else {
+            for (uint32_t c = 0; col + c < N; c++)
+                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
+        }
+    }
 }
 
 inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
