@@ -3,8 +3,9 @@
 // blocked Gauss-Jordan elimination over 64-column panels.
 //
 // For a panel [c0, c0+64):
-//  1. k_ech_probe   one block: a greedy basis of the first 256 remaining rows
-//     restricted to the panel, in reduced form in LDS.  Every wave reduces one
+//  0. k_ech_check   flags the remaining rows that are nonzero on the panel.
+//  1. k_ech_probe   one block: a greedy basis of the first (>= 256) flagged
+//     rows restricted to the panel, in reduced form in LDS.  Every wave reduces one
 //     row against the basis (multipliers broadcast with v_readlane); rows
 //     that stay nonzero are inserted one wave at a time.  The coefficients G
 //     with  G * Dt[Q, panel] = basis  are tracked (Q = selected rows).
@@ -38,7 +39,8 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 namespace {
 
 constexpr uint32_t kPanel = 64;
-constexpr uint32_t kProbe = 256;  // rows in the probe basis pass
+constexpr uint32_t kProbe = 256;  // rows in the probe basis pass (at least)
+constexpr uint32_t kListCap = 2048;  // LDS row list: room for two 1024-row windows
 constexpr int kGreedyThreads = 1024;
 
 struct PanelState {
@@ -57,6 +59,7 @@ struct PanelState {
 
 struct EchWs {
     uint32_t *is_piv;   // [rows] 1 once the row is a pivot row
+    uint32_t *nzflag;   // [rows] 1 if the remaining row is nonzero on the panel
     uint32_t *flags;    // [rows] 1 if the row is outside the probe basis' span
     uint32_t *piv_row;  // [min(rows, cols)]
     PanelState *ps;
@@ -106,7 +109,7 @@ struct GreedyLds {
     uint32_t Qo[64];
     uint32_t kb;
     uint32_t cnt;
-    uint32_t list[kGreedyThreads];
+    uint32_t list[kListCap];
 };
 
 // Process rows S.list[0..S.cnt) in order: each wave reduces one row against
@@ -165,15 +168,17 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
     __syncthreads();
 }
 
-// Collect up to kGreedyThreads row indices r >= *next with pred(r) into
-// S.list (ascending); *next is advanced past the rows examined.
+// Append to S.list, in ascending order, the rows r >= next with pred(r),
+// scanning 1024-row windows while fewer than `want` rows are listed and a
+// whole window still fits the list (so no selected row is ever dropped);
+// `next` is advanced past the windows scanned.
 template <class Pred>
 __device__ void collect_rows(uint32_t rows, uint32_t &next, uint32_t want, GreedyLds &S, Pred pred) {
     __shared__ uint32_t wave_cnt[kGreedyThreads / 64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) S.cnt = 0;
     __syncthreads();
-    while (next < rows && S.cnt < want) {
+    while (next < rows && S.cnt < want && S.cnt + blockDim.x <= kListCap) {
         const uint32_t r = next + threadIdx.x;
         const bool ok = r < rows && pred(r);
         const uint64_t mask = __ballot(ok);
@@ -182,13 +187,12 @@ __device__ void collect_rows(uint32_t rows, uint32_t &next, uint32_t want, Greed
         uint32_t before = S.cnt;
         for (uint32_t w = 0; w < wave; w++) before += wave_cnt[w];
         const uint64_t below = lane == 0 ? 0 : (mask & (~(uint64_t)0 >> (64 - lane)));
-        const uint32_t at = before + __popcll(below);
-        if (ok && at < want) S.list[at] = r;
+        if (ok) S.list[before + __popcll(below)] = r;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t tot = S.cnt;
             for (uint32_t w = 0; w < blockDim.x / 64; w++) tot += wave_cnt[w];
-            S.cnt = tot < want ? tot : want;
+            S.cnt = tot;
         }
         next += blockDim.x;
         __syncthreads();
@@ -237,11 +241,12 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
     }
 }
 
-// Panel step 1: greedy basis of the first kProbe remaining rows.
+// Panel step 1: greedy basis of the first (at least kProbe) remaining rows
+// that are nonzero on the panel.
 __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
     fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
-    uint32_t pw, uint32_t *is_piv, PanelState *ps, uint32_t *piv_row, uint32_t *piv_col,
-    uint32_t *d_rank) {
+    uint32_t pw, const uint32_t *__restrict__ nzflag, uint32_t *is_piv, PanelState *ps,
+    uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
     if (threadIdx.x == 0) {
@@ -253,38 +258,42 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
     __syncthreads();
     const uint32_t rank0 = rank0_s;
     uint32_t next = 0;
-    collect_rows(rows, next, kProbe, S, [&](uint32_t r) { return is_piv[r] == 0; });
+    collect_rows(rows, next, kProbe, S, [&](uint32_t r) { return nzflag[r] != 0; });
+    if (threadIdx.x == 0 && S.cnt > kProbe) S.cnt = kProbe;  // the check pass covers the rest
+    __syncthreads();
     greedy_rows(md, D, ld, c0, pw, S);
     save_raw(S, ps);
     finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
 }
 
-// Panel step 2: every remaining row is reduced against the probe basis in
-// parallel; rows with a nonzero remainder (outside the basis' span) are
-// flagged.  One wave per row, 4 rows per wave.
+// Panel steps 0 and 2: every remaining row (restricted to rows with
+// in_flags[i] != 0 when in_flags is given) is reduced against the basis in
+// ps (step 2) or against nothing (step 0, use_basis = 0); rows left nonzero
+// are flagged in out_flags.  One wave per row, 4 rows per wave.
 __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const uint16_t *__restrict__ D,
                                                    uint64_t ld, uint32_t rows, uint32_t c0,
                                                    uint32_t pw, const uint32_t *__restrict__ is_piv,
-                                                   PanelState *ps, uint32_t *flags) {
+                                                   PanelState *ps, const uint32_t *__restrict__ in_flags,
+                                                   uint32_t *out_flags, int use_basis) {
     __shared__ uint16_t Bv[64][64];
     __shared__ uint32_t Cc[64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t kb = ps->kb;
+    const uint32_t kb = use_basis ? ps->kb : 0;
     for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) Bv[i >> 6][i & 63] = ps->Bv[i];
-    if (threadIdx.x < 64) Cc[threadIdx.x] = ps->Cc[threadIdx.x];
+    if (threadIdx.x < 64) Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
     __syncthreads();
     for (uint32_t u = 0; u < 4; u++) {
         const uint32_t i = (blockIdx.x * 4 + wave) * 4 + u;
         if (i >= rows) break;
         uint32_t flag = 0;
-        if (!is_piv[i] && kb < pw) {
+        if (!is_piv[i] && kb < pw && (!in_flags || in_flags[i])) {
             uint32_t v = lane < pw ? D[(uint64_t)i * ld + c0 + lane] : 0, g = 0;
-            reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
+            if (kb) reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
             flag = __ballot(v != 0) != 0 ? 1u : 0u;
         }
         if (lane == 0) {
-            flags[i] = flag;
-            if (flag) atomicAdd(&ps->nflag, 1u);
+            out_flags[i] = flag;
+            if (flag && use_basis) atomicAdd(&ps->nflag, 1u);
         }
     }
 }
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
     const uint32_t rank0 = ps->rank0;
     uint32_t next = 0;
     while (next < rows && S.kb < pw) {
-        collect_rows(rows, next, kGreedyThreads, S, [&](uint32_t r) { return flags[r] != 0; });
+        collect_rows(rows, next, kListCap, S, [&](uint32_t r) { return flags[r] != 0; });
         greedy_rows(md, D, ld, c0, pw, S);
     }
     save_raw(S, ps);
@@ -398,6 +407,7 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     const uint64_t ldu = ((uint64_t)cols + 63) & ~(uint64_t)63;
     EchWs t;
     t.is_piv = c.take<uint32_t>(rows ? rows : 1);
+    t.nzflag = c.take<uint32_t>(rows ? rows : 1);
     t.flags = c.take<uint32_t>(rows ? rows : 1);
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
     t.ps = c.take<PanelState>(1);
@@ -444,16 +454,21 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
     for (uint32_t P = 0; P < npanels; P++) {
         const uint32_t c0 = P * kPanel;
         const uint32_t pw = cols - c0 < kPanel ? cols - c0 : kPanel;
+        FL_PROF("echelon.check", stream,
+                hipLaunchKernelGGL(k_ech_check, dim3((rows + 15) / 16), dim3(256), 0, stream, md,
+                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.is_piv,
+                                   e.ps, (const uint32_t *)nullptr, e.nzflag, 0));
+        FL_LAUNCH_CHECK("k_ech_check<nonzero>");
         FL_PROF("echelon.probe", stream,
                 hipLaunchKernelGGL(k_ech_probe, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, rows, c0, pw, e.is_piv, e.ps, e.piv_row,
-                                   d_pivcol, d_rank));
+                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.nzflag,
+                                   e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
         FL_LAUNCH_CHECK("k_ech_probe");
         FL_PROF("echelon.check", stream,
                 hipLaunchKernelGGL(k_ech_check, dim3((rows + 15) / 16), dim3(256), 0, stream, md,
                                    (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.is_piv,
-                                   e.ps, e.flags));
-        FL_LAUNCH_CHECK("k_ech_check");
+                                   e.ps, (const uint32_t *)e.nzflag, e.flags, 1));
+        FL_LAUNCH_CHECK("k_ech_check<basis>");
         FL_PROF("echelon.merge", stream,
                 hipLaunchKernelGGL(k_ech_merge, dim3(1), dim3(kGreedyThreads), 0, stream, md,
                                    (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.flags,

@@ -201,6 +201,58 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
     }
 }
 
+// Rank-k update, k <= 64 (the Gauss-Jordan panel updates): one MFMA K-step,
+// so the kernel is bound by the read-modify-write of C.  Each wave owns 16
+// rows x 128 columns (eight 16 x 16 tiles); its C elements are loaded at the
+// start so their latency overlaps the operand loads and the 32 MFMAs, and
+// operand fragments come straight from the (L2-resident) limb planes.  Small
+// register footprint -> several waves per SIMD to keep HBM busy.
+__global__ __launch_bounds__(256) void k_mfma_rank64(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                     const int8_t *__restrict__ Ah,
+                                                     const int8_t *__restrict__ Al,
+                                                     const int8_t *__restrict__ Bh,
+                                                     const int8_t *__restrict__ Bl,
+                                                     const uint32_t *__restrict__ Kdev,
+                                                     uint16_t *C, uint64_t ldc, uint32_t M,
+                                                     uint32_t N) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t row0 = blockIdx.y * 64 + wave * 16;
+    const uint32_t col0 = blockIdx.x * 128;
+    if (Kdev && *Kdev == 0) return;
+    const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
+    uint32_t cv[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t row = row0 + rq + e, col = col0 + j * 16 + cl;
+            cv[j][e] = (row < M && col < N) ? C[(uint64_t)row * ldc + col] : 0;
+        }
+    const v4i ah = *(const v4i *)(Ah + (uint64_t)(row0 + cl) * 64 + kq);
+    const v4i al = *(const v4i *)(Al + (uint64_t)(row0 + cl) * 64 + kq);
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const uint64_t b = (uint64_t)(col0 + j * 16 + cl) * 64 + kq;
+        const v4i bh = *(const v4i *)(Bh + b);
+        const v4i bl = *(const v4i *)(Bl + b);
+        v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+        hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bh, hh, 0, 0, 0);
+        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bl, mid, 0, 0, 0);
+        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bh, mid, 0, 0, 0);
+        ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bl, ll, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t row = row0 + rq + e, col = col0 + j * 16 + cl;
+            const uint32_t rhh = signed_to_res(hh[e], md, bias);
+            const uint32_t rmid = signed_to_res(mid[e], md, bias);
+            const uint32_t rll = signed_to_res(ll[e], md, bias);
+            uint32_t v = fl::reduce32(rhh * c16 + rll, md);
+            v = fl::reduce32(v + rmid * 256u, md);
+            if (row < M && col < N) C[(uint64_t)row * ldc + col] = (uint16_t)fl::submod(cv[j][e], v, md.p);
+        }
+    }
+}
+
 inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 struct MfmaWs {
@@ -259,6 +311,12 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
                                                   w.Bh, w.Bl, w.Kp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (w.Kp == BK) {  // one K-step: rank-k update kernel
+        dim3 g(w.Np / 128, w.Mp / 64);
+        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_rank64, g, dim3(256), 0, s, md, bias, c16, w.Ah,
+                                                 w.Al, w.Bh, w.Bl, Kdev, C, ldc, M, N));
+        return hipGetLastError();
     }
     dim3 grid(w.Np / BN, w.Mp / BM);
     for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {

@@ -278,3 +278,59 @@ def test_repeat_runs_identical():
     torch.cuda.synchronize()
     for x, y in zip(a["rref"][:3], b["rref"][:3]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_echelon_probe_misses_rows(mode):
+    """The first rows span only a 3-dimensional space, so the probe basis of
+    each panel is incomplete and the flagged-row merge must finish the panel
+    (more than 1024 flagged rows: several collection rounds)."""
+    p = 65521
+    rng = np.random.default_rng(31)
+    rows, cols = 2600, 200
+    base = rng.integers(0, p, size=(3, cols))
+    D = np.zeros((rows, cols), np.int64)
+    D[:400] = (rng.integers(0, p, size=(400, 3)) @ base) % p
+    D[400:] = rng.integers(0, p, size=(rows - 400, cols))
+    R, r, pc = oracle.rref_dense(D.astype(np.uint16), p)
+    T = torch.zeros((rows, 200), dtype=torch.int16)
+    T[:] = torch.from_numpy(D.astype(np.uint16).view(np.int16))
+    T = T.cuda()
+    ech = fl.echelon_d(T, p, rows, cols, mode)
+    torch.cuda.synchronize()
+    rank = int(u32(ech.rank)[0])
+    assert rank == r == 200
+    assert np.array_equal(u32(ech.pivcol)[:rank], pc)
+    assert np.array_equal(u16(T)[:rank], R[:rank])
+    assert not u16(T)[rank:].any()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_echelon_flagged_rows_never_dropped(mode):
+    """Regression: the merge lists flagged rows window by window; a window
+    that overflowed the list used to be skipped past.  Rows [0, 1024) are
+    multiples of v0 (the probe basis), 500 rows of the next window and 900 of
+    the one after are in span(v0, v1), and one row deep in the third window is
+    the only one with a third direction."""
+    p = 65521
+    rng = np.random.default_rng(41)
+    rows, cols = 3100, 64
+    v0, v1, w = (rng.integers(1, p, size=cols) for _ in range(3))
+    D = np.zeros((rows, cols), np.int64)
+    D[:1024] = np.outer(rng.integers(1, p, size=1024), v0) % p
+    r1 = 1024 + np.sort(rng.choice(1024, 500, replace=False))
+    r2 = 2048 + np.sort(rng.choice(1024, 900, replace=False))
+    for idx in (r1, r2):
+        D[idx] = (np.outer(rng.integers(1, p, size=len(idx)), v0)
+                  + np.outer(rng.integers(1, p, size=len(idx)), v1)) % p
+    D[r2[699]] = w
+    R, r, pc = oracle.rref_dense(D.astype(np.uint16), p)
+    assert r == 3
+    T = torch.from_numpy(D.astype(np.uint16).view(np.int16)).cuda()
+    ech = fl.echelon_d(T, p, rows, cols, mode)
+    torch.cuda.synchronize()
+    rank = int(u32(ech.rank)[0])
+    assert rank == 3
+    assert np.array_equal(u32(ech.pivcol)[:rank], pc)
+    assert np.array_equal(u16(T)[:rank], R[:rank])
+    assert not u16(T)[rank:].any()
