@@ -143,12 +143,18 @@ size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint32_t ml_widt
 
 /* ---- step 2 --------------------------------------------------------------
  * fl_trsm -- Sec. 4.1 step 2: X = A^{-1} B mod p, A unit upper triangular,
- * by back substitution over blocks of rows from the bottom up, using the
+ * by back substitution over blocks of 128 rows from the bottom up, using the
  * multiline rows of A (Sec. 4.2: one read of a row of X serves the w rows of
- * a multiline).  X: dense npiv x nB (ld = ldx).  B is read from out->b_*. */
+ * a multiline).  X: dense npiv x nB (ld = ldx).  B is read from s->b_*.
+ * FL_PLAIN: the part of each block's rows that refers to finished rows below
+ * the block is applied by the multiline sparse-times-dense kernel on the
+ * vector ALUs.  FL_MFMA_I8: that part is an int8-limb GEMM on the matrix
+ * cores (A's band expanded into dense limb planes in the workspace).  The
+ * in-block back substitution is on the vector ALUs in both forms; results are
+ * bit-identical. */
 fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
-                  void *ws, size_t ws_bytes, hipStream_t stream);
-size_t fl_trsm_workspace(const fl_split_info *info);
+                  fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode);
 
 /* ---- step 3 --------------------------------------------------------------
  * fl_reduce_cd -- Sec. 4.1 step 3: Dt = D - C X mod p (C reduced to zero by

@@ -71,8 +71,8 @@ def load():
     sigs = {
         "fl_split": (ct.c_int, [P(FlCsr), c_u32, c_u32, P(FlSplitOut), P(FlSplitInfo), c_vp, c_sz, c_vp]),
         "fl_split_workspace": (c_sz, [c_u32, c_u32, c_u64, c_u32]),
-        "fl_trsm": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_sz, c_vp]),
-        "fl_trsm_workspace": (c_sz, [P(FlSplitInfo)]),
+        "fl_trsm": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_trsm_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
         "fl_reduce_cd": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
                                     c_vp, c_sz, c_vp]),
         "fl_reduce_cd_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
@@ -192,13 +192,14 @@ def split(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, m: int, n
     return Split(info=info, out=out, bufs=bufs)
 
 
-def trsm(sp: Split) -> torch.Tensor:
+def trsm(sp: Split, mode: int = FL_PLAIN) -> torch.Tensor:
     """X = A^{-1} B as a dense (npiv x ld) uint16 tensor (int16 storage)."""
     lib = load()
     ld = _ld(sp.nB)
     X = torch.empty((max(sp.npiv, 1), ld), dtype=torch.int16, device=_dev())
-    ws = _ws(lib.fl_trsm_workspace(ct.byref(sp.info)))
-    st = lib.fl_trsm(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), ld, _ptr(ws), ws.numel(), _stream())
+    ws = _ws(lib.fl_trsm_workspace(ct.byref(sp.info), mode))
+    st = lib.fl_trsm(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), ld, mode, _ptr(ws), ws.numel(),
+                     _stream())
     _check(st, "fl_trsm")
     return X
 
@@ -270,7 +271,7 @@ def fl_reduce(row_ptr, col, val, m: int, n: int, p: int, mode: int = FL_PLAIN, m
     """The whole hot path on one matrix already resident on the device.
     With keep=True, copies of X = A^{-1}B and Dt = D - C X are returned too."""
     sp = split(row_ptr, col, val, m, n, p, ml_width)
-    X = trsm(sp)
+    X = trsm(sp, mode)
     Dt = reduce_cd(sp, X, mode)
     res = dict(split=sp)
     if keep:

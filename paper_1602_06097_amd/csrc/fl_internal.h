@@ -136,3 +136,29 @@ void fl_prof_end(int tok, hipStream_t s);
         __VA_ARGS__;                                                    \
         fl_prof_end(tok_, stream);                                      \
     } while (0)
+
+// One int8-limb-plane GEMM on the matrix cores (gemm_mfma.hip):
+//   C[rows x N] -= A B   with A row m (k = 0..) at Ah/Al + m*lda + a_k0 + k and
+//   B column n at Bh/Bl + n*ldb + b_k0 + k (B transposed), k in [kbeg, kend)
+//   (multiples of 64; kend capped by round_up(*klen_dev, 64) when given);
+//   optional per-128-row-block ranges krange[2*mb..2*mb+1] and output row map.
+// A must have round_up(M, 128) readable rows, B round_up(N, 128).
+struct GemmPlanes {
+    const int8_t *Ah, *Al, *Bh, *Bl;
+    uint64_t lda, ldb;
+    uint32_t a_k0, b_k0;
+    uint32_t kbeg, kend;
+    const uint32_t *klen_dev;
+    const uint32_t *krange;
+    const uint32_t *row_map;
+    uint16_t *C;
+    uint64_t ldc;
+    uint32_t M, N;
+};
+hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
+// Residue x -> signed int8 limbs (h, l) with centred r = 256 h + l.
+__device__ __forceinline__ void fl_split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
+    const int r = x <= 32639u ? (int)x : (int)x - (int)p;
+    h = (r + 128) >> 8;  // arithmetic shift: floor
+    l = r - (h << 8);
+}

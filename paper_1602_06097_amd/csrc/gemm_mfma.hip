@@ -30,9 +30,7 @@ constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conf
 constexpr int kOutLd = BN + 4;       // u16 row stride of the epilogue tile (8-byte aligned rows)
 
 __device__ __forceinline__ void split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
-    const int r = x <= 32639u ? (int)x : (int)x - (int)p;
-    h = (r + 128) >> 8;  // arithmetic shift: floor
-    l = r - (h << 8);
+    fl_split_limbs(x, p, h, l);
 }
 
 // A (rows x K, row-major u16, lda) -> Ah, Al (Rp x Kp int8, K-contiguous).
@@ -88,18 +86,11 @@ __device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint
     return fl::reduce32((uint32_t)s + bias, md);
 }
 
-// C[M x N] -= (Ah,Al)[M x Kp] * (Bh,Bl)[N x Kp]^T over k in [kbeg, kend).
 // 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 outputs per wave as
-// 4 x 4 tiles of 16 x 16.
+// 4 x 4 tiles of 16 x 16.  The next K-tile is loaded into registers while
+// the current one is multiplied, so global latency overlaps the MFMAs.
 __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
-                                                   const int8_t *__restrict__ Ah,
-                                                   const int8_t *__restrict__ Al,
-                                                   const int8_t *__restrict__ Bh,
-                                                   const int8_t *__restrict__ Bl, uint32_t Kp,
-                                                   uint32_t kbeg, uint32_t kend,
-                                                   const uint32_t *__restrict__ Kdev,
-                                                   uint16_t *C, uint64_t ldc, uint32_t M,
-                                                   uint32_t N) {
+                                                   GemmPlanes g) {
     __shared__ __attribute__((aligned(16))) int8_t smem[4 * BM * kLdsRow];
     static_assert(BM * kOutLd * 2 <= 4 * BM * kLdsRow, "epilogue tile must fit the operand buffers");
     int8_t *sAh = smem, *sAl = smem + BM * kLdsRow;
@@ -107,8 +98,13 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t wm = wave >> 1, wn = wave & 1;
     const uint32_t m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    if (Kdev) {
-        const uint32_t kd = (*Kdev + BK - 1) / BK * BK;
+    uint32_t kbeg = g.kbeg, kend = g.kend;
+    if (g.krange) {
+        kbeg = g.krange[2 * blockIdx.y];
+        kend = g.krange[2 * blockIdx.y + 1];
+    }
+    if (g.klen_dev) {
+        const uint32_t kd = (*g.klen_dev + BK - 1) / BK * BK;
         if (kend > kd) kend = kd;
     }
     v4i acc_hh[4][4], acc_mid[4][4], acc_ll[4][4];
@@ -120,21 +116,37 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
             acc_mid[i][j] = v4i{0, 0, 0, 0};
             acc_ll[i][j] = v4i{0, 0, 0, 0};
         }
-    // global -> LDS: each plane tile is 128 rows x 64 bytes = 512 x 16 B;
-    // thread t moves 16 B chunks t and t + 256 of each of the four planes.
+    // each plane tile is 128 rows x 64 bytes = 512 chunks of 16 B; thread t
+    // moves chunks t and t + 256 of each of the four planes
+    const uint32_t r_lo = tid >> 2, q = (tid & 3) * 16;
+    const uint64_t a_off0 = (uint64_t)(m0 + r_lo) * g.lda + g.a_k0 + q;
+    const uint64_t a_off1 = (uint64_t)(m0 + r_lo + 64) * g.lda + g.a_k0 + q;
+    const uint64_t b_off0 = (uint64_t)(n0 + r_lo) * g.ldb + g.b_k0 + q;
+    const uint64_t b_off1 = (uint64_t)(n0 + r_lo + 64) * g.ldb + g.b_k0 + q;
+    v4i pf[8];
+    auto gload = [&](uint32_t k0) {
+        pf[0] = *(const v4i *)(g.Ah + a_off0 + k0);
+        pf[1] = *(const v4i *)(g.Al + a_off0 + k0);
+        pf[2] = *(const v4i *)(g.Bh + b_off0 + k0);
+        pf[3] = *(const v4i *)(g.Bl + b_off0 + k0);
+        pf[4] = *(const v4i *)(g.Ah + a_off1 + k0);
+        pf[5] = *(const v4i *)(g.Al + a_off1 + k0);
+        pf[6] = *(const v4i *)(g.Bh + b_off1 + k0);
+        pf[7] = *(const v4i *)(g.Bl + b_off1 + k0);
+    };
+    if (kbeg < kend) gload(kbeg);
+    const uint32_t s0 = r_lo * kLdsRow + q, s1 = (r_lo + 64) * kLdsRow + q;
     for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-        for (int u = 0; u < 2; u++) {
-            const uint32_t chunk = tid + u * 256;
-            const uint32_t r = chunk >> 2, q = (chunk & 3) * 16;
-            const uint64_t ga = (uint64_t)(m0 + r) * Kp + k0 + q;
-            const uint64_t gb = (uint64_t)(n0 + r) * Kp + k0 + q;
-            *(v4i *)(sAh + r * kLdsRow + q) = *(const v4i *)(Ah + ga);
-            *(v4i *)(sAl + r * kLdsRow + q) = *(const v4i *)(Al + ga);
-            *(v4i *)(sBh + r * kLdsRow + q) = *(const v4i *)(Bh + gb);
-            *(v4i *)(sBl + r * kLdsRow + q) = *(const v4i *)(Bl + gb);
-        }
+        *(v4i *)(sAh + s0) = pf[0];
+        *(v4i *)(sAl + s0) = pf[1];
+        *(v4i *)(sBh + s0) = pf[2];
+        *(v4i *)(sBl + s0) = pf[3];
+        *(v4i *)(sAh + s1) = pf[4];
+        *(v4i *)(sAl + s1) = pf[5];
+        *(v4i *)(sBh + s1) = pf[6];
+        *(v4i *)(sBl + s1) = pf[7];
         __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);
         v4i ah[4], al[4], bh[4], bl[4];
         const uint32_t kq = (lane >> 4) * 16;
 #pragma unroll
@@ -157,11 +169,12 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
             }
         __syncthreads();
     }
+    if (kbeg >= kend) return;  // nothing to subtract
     // epilogue: residues of the 128 x 128 tile go through LDS (the operand
     // buffers are free now), then C is read, reduced and written back with
     // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
     // column lane%16) of each 16 x 16 tile is held by the wave.
-    uint16_t *sOut = (uint16_t *)sAh;  // 128 x kOutLd u16 spans sAh..sBl
+    uint16_t *sOut = (uint16_t *)smem;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -179,15 +192,31 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
             }
         }
     __syncthreads();
-    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each
-    for (uint32_t ch = tid; ch < BM * (BN / 4); ch += 256) {
+    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each; the
+    // C loads of all 16 chunks are issued before any store
+    uint64_t cvals[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const uint32_t ch = tid + u * 256;
         const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
         const uint32_t row = m0 + r, col = n0 + c4;
-        if (row >= M || col >= N) continue;
-        uint16_t *o = C + (uint64_t)row * ldc + col;
+        cvals[u] = 0;
+        if (row < g.M && col + 4 <= g.N) {
+            const uint32_t orow = g.row_map ? g.row_map[row] : row;
+            cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orow * g.ldc + col);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const uint32_t ch = tid + u * 256;
+        const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+        const uint32_t row = m0 + r, col = n0 + c4;
+        if (row >= g.M || col >= g.N) continue;
+        const uint32_t orow = g.row_map ? g.row_map[row] : row;
+        uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
         const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
-        if (col + 4 <= N) {
-            const uint64_t ov = *(const uint64_t *)o;
+        if (col + 4 <= g.N) {
+            const uint64_t ov = cvals[u];
             uint64_t nv = 0;
 #pragma unroll
             for (int c = 0; c < 4; c++)
@@ -195,7 +224,7 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
                                            (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
             *(uint64_t *)o = nv;
         } else {
-            for (uint32_t c = 0; col + c < N; c++)
+            for (uint32_t c = 0; col + c < g.N; c++)
                 o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
         }
     }
@@ -276,6 +305,16 @@ size_t mfma_layout(uint32_t M, uint32_t N, uint32_t Kmax, void *ws, MfmaWs *w) {
 
 }  // namespace
 
+hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, const char *site) {
+    if (gp.M == 0 || gp.N == 0) return hipSuccess;
+    const fl::Mod md = fl::make_mod(p);
+    const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
+    const uint32_t c16 = (uint32_t)((1u << 16) % p);
+    dim3 grid((gp.N + BN - 1) / BN, (gp.M + BM - 1) / BM);
+    FL_PROF(site, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, gp));
+    return hipGetLastError();
+}
+
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax) {
     return mfma_layout(M, N, Kmax, nullptr, nullptr);
 }
@@ -321,8 +360,9 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
     dim3 grid(w.Np / BN, w.Mp / BM);
     for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
-        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, w.Ah,
-                                                 w.Al, w.Bh, w.Bl, w.Kp, kb, ke, Kdev, C, ldc, M, N));
+        GemmPlanes gp = {w.Ah, w.Al, w.Bh, w.Bl, w.Kp, w.Kp, 0, 0, kb, ke, Kdev, nullptr, nullptr,
+                         C, ldc, M, N};
+        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, gp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

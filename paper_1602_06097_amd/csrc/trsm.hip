@@ -208,7 +208,8 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
                                                    const uint32_t *__restrict__ pos,
                                                    const uint16_t *__restrict__ val, uint32_t r0,
                                                    uint32_t r1, uint16_t *X, uint64_t ldx,
-                                                   uint32_t ncols) {
+                                                   uint32_t ncols, int8_t *Xth, int8_t *Xtl,
+                                                   uint64_t kp) {
     __shared__ uint16_t blk[kTrsmBlock][64];
     const uint32_t lane = threadIdx.x;
     const uint32_t c = blockIdx.x * 64 + lane;
@@ -279,6 +280,94 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
             }
         }
     }
+    // MFMA form: the finished rows, as transposed int8 limb planes (column c
+    // of X is row c of the planes, K-contiguous), for the updates of the
+    // blocks above
+    if (Xth && colok) {
+        int8_t *dh = Xth + (uint64_t)c * kp + r0, *dl = Xtl + (uint64_t)c * kp + r0;
+        const uint32_t nrow = r1 - r0;
+        for (uint32_t i0 = 0; i0 < nrow; i0 += 16) {
+            uint32_t hw[4] = {0, 0, 0, 0}, lw[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                int h = 0, l = 0;
+                if (i0 + k < nrow) fl_split_limbs(blk[i0 + k][lane], md.p, h, l);
+                hw[k >> 2] |= (uint32_t)(h & 0xff) << (8 * (k & 3));
+                lw[k >> 2] |= (uint32_t)(l & 0xff) << (8 * (k & 3));
+            }
+            if (i0 + 16 <= nrow) {
+                *(uint4 *)(dh + i0) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+                *(uint4 *)(dl + i0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            } else {
+                for (uint32_t k = 0; i0 + k < nrow; k++) {
+                    dh[i0 + k] = (int8_t)((hw[k >> 2] >> (8 * (k & 3))) & 0xff);
+                    dl[i0 + k] = (int8_t)((lw[k >> 2] >> (8 * (k & 3))) & 0xff);
+                }
+            }
+        }
+    }
+}
+
+// ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
+
+// kext[I] = (last A column used by block I's rows) + 1 - r1, or 0.
+__global__ void k_trsm_kext(uint32_t w, uint32_t npiv, uint32_t nblk, const uint64_t *__restrict__ gptr,
+                            const uint32_t *__restrict__ pos, uint32_t *kext) {
+    const uint32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nblk) return;
+    const uint32_t r0 = I * kTrsmBlock;
+    const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
+    uint32_t kend = r1;
+    for (uint32_t g = r0 / w; g < (r1 + w - 1) / w; g++) {
+        const uint64_t b = gptr[g], e = gptr[g + 1];
+        if (e > b) {
+            const uint32_t last = pos[e - 1] + 1;
+            kend = last > kend ? last : kend;
+        }
+    }
+    kext[I] = kend - r1;
+}
+
+// Zero the band [r1, r1 + round_up(kext, 64)) of the A limb planes for every
+// row of block blockIdx.x (row blockIdx.y within the block).
+__global__ __launch_bounds__(256) void k_trsm_zero_band(uint32_t npiv, const uint32_t *__restrict__ kext,
+                                                        int8_t *Ah, int8_t *Al, uint64_t kp) {
+    const uint32_t I = blockIdx.x, row = I * kTrsmBlock + blockIdx.y;
+    if (row >= npiv) return;
+    const uint32_t r1 = (I + 1) * kTrsmBlock < npiv ? (I + 1) * kTrsmBlock : npiv;
+    const uint32_t kb = (kext[I] + 63) / 64 * 64;
+    int8_t *h = Ah + (uint64_t)row * kp + r1, *l = Al + (uint64_t)row * kp + r1;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (uint32_t k = threadIdx.x * 16; k < kb; k += blockDim.x * 16) {
+        *(uint4 *)(h + k) = z;
+        *(uint4 *)(l + k) = z;
+    }
+}
+
+// Far entries (column >= r1 of the row's block) of A -> dense limb planes.
+__global__ __launch_bounds__(256) void k_trsm_scatter_far(uint32_t w, uint32_t p, uint32_t npiv,
+                                                          uint32_t ngroups,
+                                                          const uint64_t *__restrict__ gptr,
+                                                          const uint32_t *__restrict__ pos,
+                                                          const uint16_t *__restrict__ val,
+                                                          int8_t *Ah, int8_t *Al, uint64_t kp) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= ngroups) return;
+    const uint32_t I = (g * w) / kTrsmBlock;
+    const uint32_t r1 = (I + 1) * kTrsmBlock < npiv ? (I + 1) * kTrsmBlock : npiv;
+    for (uint64_t k = gptr[g] + lane; k < gptr[g + 1]; k += 64) {
+        const uint32_t c = pos[k];
+        if (c < r1) continue;
+        for (uint32_t q = 0; q < w; q++) {
+            const uint32_t row = g * w + q;
+            if (row >= npiv) break;
+            int h, l;
+            fl_split_limbs(val[(uint64_t)w * k + q], p, h, l);
+            Ah[(uint64_t)row * kp + c] = (int8_t)h;
+            Al[(uint64_t)row * kp + c] = (int8_t)l;
+        }
+    }
 }
 
 template <int W>
@@ -307,15 +396,39 @@ hipError_t ml_spmm(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const ui
 
 hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const uint32_t *pos,
                       const uint16_t *val, uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx,
-                      uint32_t ncols, hipStream_t s) {
+                      uint32_t ncols, hipStream_t s, int8_t *Xth = nullptr, int8_t *Xtl = nullptr,
+                      uint64_t kp = 0) {
     dim3 grid((ncols + 63) / 64);
     switch (w) {
-    case 1: hipLaunchKernelGGL(k_trsm_solve<1>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
-    case 2: hipLaunchKernelGGL(k_trsm_solve<2>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
-    case 4: hipLaunchKernelGGL(k_trsm_solve<4>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
-    default: hipLaunchKernelGGL(k_trsm_solve<8>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols); break;
+    case 1: hipLaunchKernelGGL(k_trsm_solve<1>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    case 2: hipLaunchKernelGGL(k_trsm_solve<2>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    case 4: hipLaunchKernelGGL(k_trsm_solve<4>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    default: hipLaunchKernelGGL(k_trsm_solve<8>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
     }
     return hipGetLastError();
+}
+
+struct TrsmWs {
+    int8_t *Ah, *Al, *Xh, *Xl;
+    uint32_t *kext;
+    uint64_t kp;
+};
+
+size_t trsm_layout(const fl_split_info *info, fl_mode mode, void *ws, TrsmWs *t) {
+    WsCarve c(ws);
+    TrsmWs r = {};
+    if (mode == FL_MFMA_I8 && info->npiv && info->nB) {
+        const uint64_t mp = ((uint64_t)info->npiv + 127) / 128 * 128;
+        const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
+        r.kp = ((uint64_t)info->npiv + 63) / 64 * 64 + 64;
+        r.Ah = c.take<int8_t>(mp * r.kp);
+        r.Al = c.take<int8_t>(mp * r.kp);
+        r.Xh = c.take<int8_t>(np * r.kp);
+        r.Xl = c.take<int8_t>(np * r.kp);
+        r.kext = c.take<uint32_t>((info->npiv + kTrsmBlock - 1) / kTrsmBlock);
+    }
+    if (t) *t = r;
+    return c.off;
 }
 
 hipError_t csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
@@ -358,40 +471,69 @@ fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s) {
     return check_split_info(info, s);
 }
 
-extern "C" size_t fl_trsm_workspace(const fl_split_info *info) {
-    (void)info;
-    return 0;
+extern "C" size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode) {
+    if (!info) return 0;
+    return trsm_layout(info, mode, nullptr, nullptr);
 }
 
 extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X,
-                             uint64_t ldx, void *ws, size_t ws_bytes, hipStream_t stream) {
-    (void)ws; (void)ws_bytes;
+                             uint64_t ldx, fl_mode mode, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
     fl_status st = check_split_info(info, s);
     if (st != FL_OK) return st;
+    FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_trsm: bad mode");
     const uint32_t npiv = info->npiv, nB = info->nB, w = info->ml_width;
     if (npiv == 0 || nB == 0) return FL_OK;
     FL_ARG(X, "fl_trsm: NULL X");
     FL_ARG(ldx >= nB && ldx % 4 == 0, "fl_trsm: ldx must be >= nB and a multiple of 4");
     FL_ARG(((uintptr_t)X & 7) == 0, "fl_trsm: X must be 8-byte aligned");
+    TrsmWs tw;
+    const size_t need = trsm_layout(info, mode, ws, &tw);
+    if (need && (!ws || ws_bytes < need)) {
+        fl_set_error("fl_trsm: workspace too small");
+        return FL_ERR_WORKSPACE;
+    }
     const fl::Mod md = fl::make_mod(info->p);
     hipError_t e0;
     FL_PROF("trsm.densify", stream, e0 = csr_to_dense(npiv, nB, s->b_ptr, s->b_col, s->b_val, X, ldx, stream));
     FL_HIP(e0);
     const uint32_t nblk = (npiv + kTrsmBlock - 1) / kTrsmBlock;
+    const bool mfma = mode == FL_MFMA_I8;
+    if (mfma) {
+        const uint32_t ngroups = (npiv + w - 1) / w;
+        FL_PROF("trsm.tiles", stream, {
+            hipLaunchKernelGGL(k_trsm_kext, dim3((nblk + 255) / 256), dim3(256), 0, stream, w, npiv,
+                               nblk, (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.kext);
+            hipLaunchKernelGGL(k_trsm_zero_band, dim3(nblk, kTrsmBlock), dim3(256), 0, stream, npiv,
+                               (const uint32_t *)tw.kext, tw.Ah, tw.Al, tw.kp);
+            hipLaunchKernelGGL(k_trsm_scatter_far, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w,
+                               info->p, npiv, ngroups, (const uint64_t *)s->a_gptr,
+                               (const uint32_t *)s->a_pos, (const uint16_t *)s->a_val, tw.Ah, tw.Al, tw.kp);
+        });
+        FL_LAUNCH_CHECK("trsm tiles");
+    }
     for (uint32_t I = nblk; I-- > 0;) {
         const uint32_t r0 = I * kTrsmBlock;
         const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
         if (r1 < npiv) {
-            const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
             hipError_t e;
-            FL_PROF("trsm.update", stream,
-                    e = ml_spmm(w, md, s->a_gptr, s->a_pos, s->a_val, g0, g1 - g0, r1, r1, X, ldx, X,
-                                ldx, nB, stream));
+            if (mfma) {
+                GemmPlanes gp = {tw.Ah + (uint64_t)r0 * tw.kp, tw.Al + (uint64_t)r0 * tw.kp, tw.Xh, tw.Xl,
+                                 tw.kp, tw.kp, r1, r1, 0, (uint32_t)(tw.kp - r1), tw.kext + I, nullptr,
+                                 nullptr, X + (uint64_t)r0 * ldx, ldx, r1 - r0, nB};
+                e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
+            } else {
+                const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
+                FL_PROF("trsm.update", stream,
+                        e = ml_spmm(w, md, s->a_gptr, s->a_pos, s->a_val, g0, g1 - g0, r1, r1, X, ldx, X,
+                                    ldx, nB, stream));
+            }
             FL_HIP(e);
         }
         hipError_t e;
         FL_PROF("trsm.solve", stream,
-                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream));
+                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream,
+                               mfma ? tw.Xh : nullptr, mfma ? tw.Xl : nullptr, tw.kp));
         FL_HIP(e);
     }
     return FL_OK;

@@ -141,9 +141,10 @@ def runs():
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("w", [1, 2, 8])
-def test_trsm_parity(name, w, runs):
+@pytest.mark.parametrize("mode", MODES)
+def test_trsm_parity(name, w, mode, runs):
     r = ref(name)
-    res = runs(name, fl.FL_PLAIN, w)
+    res = runs(name, mode, w)
     s = r["split"]
     if s["npiv"] and s["nB"]:
         assert np.array_equal(u16(res["X"])[:s["npiv"], :s["nB"]], r["X"])
@@ -268,6 +269,18 @@ def test_split_reports_unsorted_columns():
     with pytest.raises(fl.FlError) as e:
         fl.split(*up(g), g["m"], g["n"], g["p"])
     assert e.value.status == 5
+
+
+def test_trsm_many_blocks_both_forms():
+    """Several 128-row TRSM blocks with bands reaching far right (long rows)."""
+    g = flgen.fl_matrix(m=1400, n=1700, npiv=1100, rank_d=150, density=0.12, p=65521, seed=51)
+    r = oracle.fl_rref(g)
+    for mode in MODES:
+        for w in (2, 4):
+            sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=w)
+            X = fl.trsm(sp, mode)
+            torch.cuda.synchronize()
+            assert np.array_equal(u16(X)[:sp.npiv, :sp.nB], r["X"]), (mode, w)
 
 
 def test_repeat_runs_identical():
