@@ -48,6 +48,8 @@ struct PanelState {
     uint32_t rank0;        // rank before this panel
     uint32_t nflag;        // rows outside the probe basis' span
     uint32_t kb;           // raw basis size (insertion order)
+    uint32_t nupd;         // rows with a nonzero multiplier (listed in upd_rows)
+    uint32_t pad_[3];
     uint32_t Qs[64];       // selected rows, by insertion slot
     uint32_t Phys[64];     // row that receives U_t
     uint32_t Ccol[64];     // absolute pivot column of U_t (ascending)
@@ -66,6 +68,9 @@ struct EchWs {
     uint16_t *U;        // [64 x ldu]
     uint16_t *L;        // [rows x 64]
     uint16_t *T;        // [min(rows, cols) x ldu]
+    int8_t *Lh, *Ll;    // [rows x 64] limb planes of L (MFMA form)
+    int8_t *Uh, *Ul;    // [(cols + 128) x 64] limb planes of U transposed (MFMA form)
+    uint32_t *upd_rows; // [rows] rows with a nonzero multiplier
     void *gemm_ws;
     size_t gemm_ws_bytes;
     uint64_t ldu;
@@ -253,6 +258,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
         S.kb = 0;
         rank0_s = *d_rank;
         ps->nflag = 0;
+        ps->nupd = 0;
         ps->rank0 = rank0_s;
     }
     __syncthreads();
@@ -326,11 +332,13 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
     finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
 }
 
-// U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k.
+// U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k; with
+// limb planes, also U transposed as int8 limbs: Uh/Ul[(c - c0) * 64 + t]
+// (zero for t >= k), the B operand of the matrix-core rank-k update.
 __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__restrict__ D,
                                                uint64_t ld, uint32_t c0, uint32_t cols,
                                                const PanelState *__restrict__ ps, uint16_t *U,
-                                               uint64_t ldu) {
+                                               uint64_t ldu, int8_t *Uh, int8_t *Ul) {
     __shared__ uint16_t Gs[64 * 64];
     __shared__ uint16_t xs[64][256];
     const uint32_t k = ps->k;
@@ -341,6 +349,9 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__res
     for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)ps->Qs[s] * ld + c] : 0;
     __syncthreads();
     if (!ok) return;
+    uint32_t hw[16], lw[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) hw[i] = lw[i] = 0;
     for (uint32_t t = 0; t < k; t++) {
         uint32_t h = 0, l = 0;
         for (uint32_t s = 0; s < k; s++) {
@@ -349,20 +360,50 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__res
             h = fl::mad24(gts >> 8, x, h);
             l = fl::mad24(gts & 0xffu, x, l);
         }
-        U[(uint64_t)t * ldu + c] = (uint16_t)fl::fold_pair(h, l, md);
+        const uint32_t u = fl::fold_pair(h, l, md);
+        U[(uint64_t)t * ldu + c] = (uint16_t)u;
+        if (Uh) {
+            int lh, ll;
+            fl_split_limbs(u, md.p, lh, ll);
+#pragma unroll
+            for (int i = 0; i < 16; i++)
+                if ((uint32_t)i == (t >> 2)) {
+                    hw[i] |= (uint32_t)(lh & 0xff) << (8 * (t & 3));
+                    lw[i] |= (uint32_t)(ll & 0xff) << (8 * (t & 3));
+                }
+        }
+    }
+    if (Uh) {
+        uint4 *dh = (uint4 *)(Uh + (uint64_t)(c - c0) * 64), *dl = (uint4 *)(Ul + (uint64_t)(c - c0) * 64);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            dh[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
+            dl[i] = make_uint4(lw[4 * i], lw[4 * i + 1], lw[4 * i + 2], lw[4 * i + 3]);
+        }
     }
 }
 
-// L[i][t] = Dt[i][Ccol[t]] (0 for t >= k).
+// L[i][t] = Dt[i][Ccol[t]] (0 for t >= k); with limb planes, also L as
+// int8 limbs (64 bytes per row) and the list of rows with a nonzero
+// multiplier (rows whose update is zero are skipped by the rank-k update).
 __global__ __launch_bounds__(256) void k_ech_gather_L(const uint16_t *__restrict__ D, uint64_t ld,
-                                                      uint32_t rows,
-                                                      const PanelState *__restrict__ ps,
-                                                      uint16_t *L) {
+                                                      uint32_t rows, PanelState *ps, uint16_t *L,
+                                                      uint32_t p, int8_t *Lh, int8_t *Ll,
+                                                      uint32_t *upd_rows) {
     const uint32_t t = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= rows) return;
     const uint32_t k = ps->k;
-    L[(uint64_t)i * 64 + t] = t < k ? D[(uint64_t)i * ld + ps->Ccol[t]] : 0;
+    const uint32_t x = t < k ? D[(uint64_t)i * ld + ps->Ccol[t]] : 0;
+    L[(uint64_t)i * 64 + t] = (uint16_t)x;
+    if (Lh) {
+        int h = 0, l = 0;
+        fl_split_limbs(x, p, h, l);
+        Lh[(uint64_t)i * 64 + t] = (int8_t)h;
+        Ll[(uint64_t)i * 64 + t] = (int8_t)l;
+        const uint64_t nz = __ballot(x != 0);
+        if (nz && t == 0) upd_rows[atomicAdd(&ps->nupd, 1u)] = i;
+    }
 }
 
 // Rows of Q receive U (after the rank-k update touched them).
@@ -415,8 +456,17 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     t.L = c.take<uint16_t>((size_t)(rows ? rows : 1) * 64);
     t.T = c.take<uint16_t>((size_t)(mn ? mn : 1) * ldu);
     t.ldu = ldu;
-    t.gemm_ws_bytes = mode == FL_MFMA_I8 ? fl_gemm_sub_mfma_ws(rows, cols, 64) : 0;
-    t.gemm_ws = t.gemm_ws_bytes ? (void *)c.take<char>(t.gemm_ws_bytes) : nullptr;
+    t.gemm_ws_bytes = 0;
+    t.gemm_ws = nullptr;
+    t.Lh = t.Ll = t.Uh = t.Ul = nullptr;
+    t.upd_rows = nullptr;
+    if (mode == FL_MFMA_I8) {
+        t.Lh = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
+        t.Ll = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
+        t.Uh = c.take<int8_t>(((size_t)cols + 256) * 64);
+        t.Ul = c.take<int8_t>(((size_t)cols + 256) * 64);
+        t.upd_rows = c.take<uint32_t>(rows ? rows : 1);
+    }
     if (e) *e = t;
     return c.off;
 }
@@ -477,15 +527,17 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
         const uint32_t ucols = cols - c0;
         FL_PROF("echelon.U", stream,
                 hipLaunchKernelGGL(k_ech_U, dim3((ucols + 255) / 256), dim3(256), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, c0, cols, (const PanelState *)e.ps, e.U, e.ldu));
+                                   (const uint16_t *)Dt, ldd, c0, cols, (const PanelState *)e.ps, e.U, e.ldu,
+                                   e.Uh, e.Ul));
         FL_LAUNCH_CHECK("k_ech_U");
-        hipLaunchKernelGGL(k_ech_gather_L, dim3((rows + 3) / 4), dim3(256), 0, stream,
-                           (const uint16_t *)Dt, ldd, rows, (const PanelState *)e.ps, e.L);
+        FL_PROF("echelon.L", stream,
+                hipLaunchKernelGGL(k_ech_gather_L, dim3((rows + 3) / 4), dim3(256), 0, stream,
+                                   (const uint16_t *)Dt, ldd, rows, e.ps, e.L, p, e.Lh, e.Ll, e.upd_rows));
         FL_LAUNCH_CHECK("k_ech_gather_L");
         const uint32_t *kdev = &e.ps->k;
         if (mode == FL_MFMA_I8) {
-            FL_HIP(fl_gemm_sub_mfma(p, rows, ucols, kPanel, kdev, e.L, 64, e.U + c0, e.ldu,
-                                    Dt + c0, ldd, e.gemm_ws, e.gemm_ws_bytes, stream, "echelon"));
+            FL_HIP(fl_mfma_rank64_planes(p, e.Lh, e.Ll, e.Uh, e.Ul, kdev, e.upd_rows, &e.ps->nupd, rows,
+                                         Dt + c0, ldd, ucols, stream, "echelon.mfma"));
         } else {
             FL_HIP(fl_gemm_sub_plain(p, rows, ucols, 0, kdev, e.L, 64, e.U + c0, e.ldu, Dt + c0,
                                      ldd, stream, "echelon.plain"));

@@ -156,6 +156,12 @@ struct GemmPlanes {
     uint32_t M, N;
 };
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
+// Rank-k (k <= 64) update C[row_map[i], :N] -= A[row_map[i]] B^T for
+// i < *Mdev (<= Mmax); A planes: 64 bytes per C row; B planes: N_pad x 64.
+hipError_t fl_mfma_rank64_planes(uint32_t p, const int8_t *Ah, const int8_t *Al, const int8_t *Bh,
+                                 const int8_t *Bl, const uint32_t *Kdev, const uint32_t *row_map,
+                                 const uint32_t *Mdev, uint32_t Mmax, uint16_t *C, uint64_t ldc,
+                                 uint32_t N, hipStream_t s, const char *site);
 // Residue x -> signed int8 limbs (h, l) with centred r = 256 h + l.
 __device__ __forceinline__ void fl_split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
     const int r = x <= 32639u ? (int)x : (int)x - (int)p;

@@ -231,37 +231,54 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
 }
 
 // Rank-k update, k <= 64 (the Gauss-Jordan panel updates): one MFMA K-step,
-// so the kernel is bound by the read-modify-write of C.  Each wave owns 16
-// rows x 128 columns (eight 16 x 16 tiles); its C elements are loaded at the
-// start so their latency overlaps the operand loads and the 32 MFMAs, and
-// operand fragments come straight from the (L2-resident) limb planes.  Small
-// register footprint -> several waves per SIMD to keep HBM busy.
+// so the kernel is bound by the read-modify-write of C and its epilogue.  A
+// block owns 64 rows x 128 columns; rows are taken through an optional row
+// list (row_map, count *Mdev: only rows with nonzero multipliers), the C tile
+// is loaded first with row-contiguous 8-byte accesses (latency overlapping
+// the operand loads and MFMAs), residues are staged through LDS and C is
+// written back with 8-byte accesses.  A planes are indexed by the C row.
+// With K <= 64, |S_hh|, |S_ll| <= 2^20 and |S_mid| <= 2^21, so
+// 256 S_mid + S_ll fits 32 bits and the recombination needs three Barrett
+// reductions instead of five.
 __global__ __launch_bounds__(256) void k_mfma_rank64(fl::Mod md, uint32_t bias, uint32_t c16,
                                                      const int8_t *__restrict__ Ah,
                                                      const int8_t *__restrict__ Al,
                                                      const int8_t *__restrict__ Bh,
                                                      const int8_t *__restrict__ Bl,
                                                      const uint32_t *__restrict__ Kdev,
-                                                     uint16_t *C, uint64_t ldc, uint32_t M,
+                                                     const uint32_t *__restrict__ row_map,
+                                                     const uint32_t *__restrict__ Mdev,
+                                                     uint16_t *C, uint64_t ldc, uint32_t Mh,
                                                      uint32_t N) {
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t row0 = blockIdx.y * 64 + wave * 16;
-    const uint32_t col0 = blockIdx.x * 128;
-    if (Kdev && *Kdev == 0) return;
+    constexpr int kLd = 128 + 4;  // u16 row stride of the residue tile
+    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * kLd];
+    __shared__ uint32_t rows_s[64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 128;
+    const uint32_t M = Mdev ? *Mdev : Mh;
+    if (m0 >= M || (Kdev && *Kdev == 0)) return;
+    if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
+    __syncthreads();
+    // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread
+    uint64_t cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t row = rows_s[r], col = n0 + c4;
+        cv[u] = 0;
+        if (row != 0xffffffffu && col + 4 <= N) cv[u] = *(const uint64_t *)(C + (uint64_t)row * ldc + col);
+    }
     const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
-    uint32_t cv[8][4];
-#pragma unroll
-    for (int j = 0; j < 8; j++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const uint32_t row = row0 + rq + e, col = col0 + j * 16 + cl;
-            cv[j][e] = (row < M && col < N) ? C[(uint64_t)row * ldc + col] : 0;
-        }
-    const v4i ah = *(const v4i *)(Ah + (uint64_t)(row0 + cl) * 64 + kq);
-    const v4i al = *(const v4i *)(Al + (uint64_t)(row0 + cl) * 64 + kq);
+    const uint32_t arow = rows_s[wave * 16 + cl];
+    v4i ah = {0, 0, 0, 0}, al = {0, 0, 0, 0};
+    if (arow != 0xffffffffu) {
+        ah = *(const v4i *)(Ah + (uint64_t)arow * 64 + kq);
+        al = *(const v4i *)(Al + (uint64_t)arow * 64 + kq);
+    }
+    const uint32_t bias2 = (uint32_t)(((1u << 30) + md.p - 1) / md.p * md.p);  // >= 2^30, multiple of p
 #pragma unroll
     for (int j = 0; j < 8; j++) {
-        const uint64_t b = (uint64_t)(col0 + j * 16 + cl) * 64 + kq;
+        const uint64_t b = (uint64_t)(n0 + j * 16 + cl) * 64 + kq;
         const v4i bh = *(const v4i *)(Bh + b);
         const v4i bl = *(const v4i *)(Bl + b);
         v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
@@ -271,13 +288,30 @@ __global__ __launch_bounds__(256) void k_mfma_rank64(fl::Mod md, uint32_t bias, 
         ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bl, ll, 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const uint32_t row = row0 + rq + e, col = col0 + j * 16 + cl;
             const uint32_t rhh = signed_to_res(hh[e], md, bias);
-            const uint32_t rmid = signed_to_res(mid[e], md, bias);
-            const uint32_t rll = signed_to_res(ll[e], md, bias);
-            uint32_t v = fl::reduce32(rhh * c16 + rll, md);
-            v = fl::reduce32(v + rmid * 256u, md);
-            if (row < M && col < N) C[(uint64_t)row * ldc + col] = (uint16_t)fl::submod(cv[j][e], v, md.p);
+            const uint32_t rlo = fl::reduce32((uint32_t)(mid[e] * 256 + ll[e]) + bias2, md);
+            const uint32_t v = fl::reduce32(rhh * c16 + rlo, md);
+            sv[(wave * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t row = rows_s[r], col = n0 + c4;
+        if (row == 0xffffffffu || col >= N) continue;
+        const uint64_t s4 = *(const uint64_t *)(sv + r * kLd + c4);
+        uint16_t *o = C + (uint64_t)row * ldc + col;
+        if (col + 4 <= N) {
+            uint64_t nv = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                nv |= (uint64_t)fl::submod((uint32_t)(cv[u] >> (16 * c)) & 0xffffu,
+                                           (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+            *(uint64_t *)o = nv;
+        } else {
+            for (uint32_t c = 0; col + c < N; c++)
+                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p);
         }
     }
 }
@@ -304,6 +338,22 @@ size_t mfma_layout(uint32_t M, uint32_t N, uint32_t Kmax, void *ws, MfmaWs *w) {
 }
 
 }  // namespace
+
+// Rank-k (k <= 64) update on prepared limb planes: A rows indexed by the C
+// row (64 bytes each), B transposed (N_pad x 64); rows from row_map[0..*Mdev).
+hipError_t fl_mfma_rank64_planes(uint32_t p, const int8_t *Ah, const int8_t *Al, const int8_t *Bh,
+                                 const int8_t *Bl, const uint32_t *Kdev, const uint32_t *row_map,
+                                 const uint32_t *Mdev, uint32_t Mmax, uint16_t *C, uint64_t ldc,
+                                 uint32_t N, hipStream_t s, const char *site) {
+    if (Mmax == 0 || N == 0) return hipSuccess;
+    const fl::Mod md = fl::make_mod(p);
+    const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
+    const uint32_t c16 = (uint32_t)((1u << 16) % p);
+    dim3 g((N + 127) / 128, (Mmax + 63) / 64);
+    FL_PROF(site, s, hipLaunchKernelGGL(k_mfma_rank64, g, dim3(256), 0, s, md, bias, c16, Ah, Al, Bh, Bl,
+                                        Kdev, row_map, Mdev, C, ldc, Mmax, N));
+    return hipGetLastError();
+}
 
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, const char *site) {
     if (gp.M == 0 || gp.N == 0) return hipSuccess;
@@ -354,7 +404,8 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
     if (w.Kp == BK) {  // one K-step: rank-k update kernel
         dim3 g(w.Np / 128, w.Mp / 64);
         FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_rank64, g, dim3(256), 0, s, md, bias, c16, w.Ah,
-                                                 w.Al, w.Bh, w.Bl, Kdev, C, ldc, M, N));
+                                                 w.Al, w.Bh, w.Bl, Kdev, (const uint32_t *)nullptr,
+                                                 (const uint32_t *)nullptr, C, ldc, M, N));
         return hipGetLastError();
     }
     dim3 grid(w.Np / BN, w.Mp / BM);
