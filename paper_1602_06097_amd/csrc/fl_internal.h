@@ -141,7 +141,9 @@ void fl_prof_end(int tok, hipStream_t s);
 //   C[rows x N] -= A B   with A row m (k = 0..) at Ah/Al + m*lda + a_k0 + k and
 //   B column n at Bh/Bl + n*ldb + b_k0 + k (B transposed), k in [kbeg, kend)
 //   (multiples of 64; kend capped by round_up(*klen_dev, 64) when given);
-//   optional per-128-row-block ranges krange[2*mb..2*mb+1] and output row map.
+//   optional per-128-row-block ranges krange[2*mb..2*mb+1], per-128-column-
+//   block ranges krange_n[2*nb..2*nb+1] (intersected; all-zero blocks of the
+//   operands are skipped), and output row map (~0u = no output row).
 // A must have round_up(M, 128) readable rows, B round_up(N, 128).
 struct GemmPlanes {
     const int8_t *Ah, *Al, *Bh, *Bl;
@@ -150,6 +152,7 @@ struct GemmPlanes {
     uint32_t kbeg, kend;
     const uint32_t *klen_dev;
     const uint32_t *krange;
+    const uint32_t *krange_n;
     const uint32_t *row_map;
     uint16_t *C;
     uint64_t ldc;

@@ -103,6 +103,11 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
         kbeg = g.krange[2 * blockIdx.y];
         kend = g.krange[2 * blockIdx.y + 1];
     }
+    if (g.krange_n) {  // per column block: intersect
+        const uint32_t b = g.krange_n[2 * blockIdx.x], e = g.krange_n[2 * blockIdx.x + 1];
+        kbeg = b > kbeg ? b : kbeg;
+        kend = e < kend ? e : kend;
+    }
     if (g.klen_dev) {
         const uint32_t kd = (*g.klen_dev + BK - 1) / BK * BK;
         if (kend > kd) kend = kd;
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
         cvals[u] = 0;
         if (row < g.M && col + 4 <= g.N) {
             const uint32_t orow = g.row_map ? g.row_map[row] : row;
-            cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orow * g.ldc + col);
+            if (orow != 0xffffffffu) cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orow * g.ldc + col);
         }
     }
 #pragma unroll
@@ -213,6 +218,7 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
         const uint32_t row = m0 + r, col = n0 + c4;
         if (row >= g.M || col >= g.N) continue;
         const uint32_t orow = g.row_map ? g.row_map[row] : row;
+        if (orow == 0xffffffffu) continue;
         uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
         const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
         if (col + 4 <= g.N) {
@@ -365,6 +371,13 @@ hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, 
     return hipGetLastError();
 }
 
+// The transposing limb conversion, for other translation units: B (K x cols,
+// ld ldb) -> Bh, Bl (cols_pad x Kp); launch with grid (cols_pad/64, Kp/64),
+// 256 threads.
+typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+fl_limbs_cols_fn fl_limbs_cols_kernel() { return k_limbs_cols; }
+
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax) {
     return mfma_layout(M, N, Kmax, nullptr, nullptr);
 }
@@ -412,7 +425,7 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
     for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
         GemmPlanes gp = {w.Ah, w.Al, w.Bh, w.Bl, w.Kp, w.Kp, 0, 0, kb, ke, Kdev, nullptr, nullptr,
-                         C, ldc, M, N};
+                         nullptr, C, ldc, M, N};
         FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, gp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

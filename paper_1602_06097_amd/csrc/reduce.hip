@@ -27,45 +27,139 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 
 namespace {
 
-// Dense rows of C from its multiline groups: out[g*w+q][pos[k]] = val[w*k+q].
-__global__ __launch_bounds__(256) void k_ml_to_dense(uint32_t w, uint32_t ngroups, uint32_t rows,
-                                                     const uint64_t *__restrict__ gptr,
-                                                     const uint32_t *__restrict__ pos,
-                                                     const uint16_t *__restrict__ val,
-                                                     uint16_t *out, uint64_t ld) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+
+// ---- MFMA form: C's multiline groups sorted by first column, so that each
+// 128-row tile of the dense C operand is nonzero only on a short K range ----
+
+constexpr uint32_t kBucketShift = 6;  // groups bucketed by first column / 64
+
+// Bucket of every group (empty groups go to the last bucket) and histogram.
+__global__ void k_grp_bucket(uint32_t ngroups, uint32_t nbuckets, const uint64_t *__restrict__ gptr,
+                             const uint32_t *__restrict__ pos, uint32_t *bucket, uint64_t *hist) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups) return;
+    const uint64_t b = gptr[g], e = gptr[g + 1];
+    const uint32_t k = e > b ? (pos[b] >> kBucketShift) : nbuckets - 1;
+    bucket[g] = k;
+    atomicAdd((unsigned long long *)&hist[k], 1ull);
+}
+
+// order[off[bucket] + rank within bucket] = group (rank by atomic fill).
+__global__ void k_grp_scatter(uint32_t ngroups, const uint32_t *__restrict__ bucket,
+                              const uint64_t *__restrict__ off, uint32_t *fill, uint32_t *order) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    const uint32_t k = bucket[g];
+    order[off[k] + atomicAdd(&fill[k], 1u)] = g;
+}
+
+// Per tile of 128 sorted rows (gpt = 128 / w groups): the K range spanned by
+// its groups' columns, and the output row of every sorted row.
+__global__ void k_tile_krange(uint32_t w, uint32_t ngroups, uint32_t mD, uint32_t ntiles,
+                              const uint64_t *__restrict__ gptr, const uint32_t *__restrict__ pos,
+                              const uint32_t *__restrict__ order, uint32_t kp, uint32_t *krange,
+                              uint32_t *row_map) {
+    const uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const uint32_t gpt = 128 / w;
+    uint32_t lo = 0xffffffffu, hi = 0;
+    for (uint32_t j = 0; j < gpt; j++) {
+        const uint32_t sg = tile * gpt + j;
+        const uint32_t g = sg < ngroups ? order[sg] : 0xffffffffu;
+        for (uint32_t q = 0; q < w; q++)
+            row_map[sg * w + q] = (g != 0xffffffffu && g * w + q < mD) ? g * w + q : 0xffffffffu;
+        if (g == 0xffffffffu) continue;
+        const uint64_t b = gptr[g], e = gptr[g + 1];
+        if (e > b) {
+            lo = pos[b] < lo ? pos[b] : lo;
+            hi = pos[e - 1] + 1 > hi ? pos[e - 1] + 1 : hi;
+        }
+    }
+    uint32_t kb = 0, ke = 0;
+    if (lo != 0xffffffffu) {
+        kb = lo / 64 * 64;
+        ke = (hi + 63) / 64 * 64;
+        if (ke > kp) ke = kp;
+    }
+    krange[2 * tile] = kb;
+    krange[2 * tile + 1] = ke;
+}
+
+// Zero the K range of every sorted row of tile blockIdx.x (row blockIdx.y).
+__global__ __launch_bounds__(256) void k_tile_zero(const uint32_t *__restrict__ krange, int8_t *Ah,
+                                                   int8_t *Al, uint64_t kp) {
+    const uint32_t tile = blockIdx.x, row = tile * 128 + blockIdx.y;
+    const uint32_t kb = krange[2 * tile], ke = krange[2 * tile + 1];
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (uint32_t k = kb + threadIdx.x * 16; k < ke; k += blockDim.x * 16) {
+        *(uint4 *)(Ah + (uint64_t)row * kp + k) = z;
+        *(uint4 *)(Al + (uint64_t)row * kp + k) = z;
+    }
+}
+
+// Entries of sorted group sg -> its w rows of the limb planes.
+__global__ __launch_bounds__(256) void k_tile_scatter(uint32_t w, uint32_t p, uint32_t ngroups,
+                                                      const uint64_t *__restrict__ gptr,
+                                                      const uint32_t *__restrict__ pos,
+                                                      const uint16_t *__restrict__ val,
+                                                      const uint32_t *__restrict__ order, int8_t *Ah,
+                                                      int8_t *Al, uint64_t kp) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t sg = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sg >= ngroups) return;
+    const uint32_t g = order[sg];
     for (uint64_t k = gptr[g] + lane; k < gptr[g + 1]; k += 64) {
         const uint32_t c = pos[k];
         for (uint32_t q = 0; q < w; q++) {
-            const uint32_t row = g * w + q;
-            if (row < rows) out[(uint64_t)row * ld + c] = val[(uint64_t)w * k + q];
+            int h, l;
+            fl_split_limbs(val[(uint64_t)w * k + q], p, h, l);
+            Ah[(uint64_t)(sg * w + q) * kp + c] = (int8_t)h;
+            Al[(uint64_t)(sg * w + q) * kp + c] = (int8_t)l;
         }
     }
 }
 
 struct ReduceWs {
-    uint16_t *Cd;
-    uint64_t ldc;
-    void *gemm_ws;
-    size_t gemm_ws_bytes;
+    int8_t *Ah, *Al, *Xh, *Xl;
+    uint32_t *bucket, *fill, *order, *krange, *row_map;
+    uint64_t *hist, *scantmp;
+    uint64_t kp;
+    uint32_t ntiles, nbuckets;
 };
 
 size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs *r) {
     WsCarve c(ws);
     ReduceWs t = {};
-    if (mode == FL_MFMA_I8) {
-        t.ldc = ((uint64_t)info->npiv + 63) & ~(uint64_t)63;
-        t.Cd = c.take<uint16_t>((size_t)(info->mD ? info->mD : 1) * (t.ldc ? t.ldc : 64));
-        t.gemm_ws_bytes = fl_gemm_sub_mfma_ws(info->mD, info->nB, info->npiv);
-        t.gemm_ws = c.take<char>(t.gemm_ws_bytes);
+    if (mode == FL_MFMA_I8 && info->mD && info->nB && info->npiv) {
+        const uint32_t w = info->ml_width ? info->ml_width : 1;
+        const uint32_t ngroups = (info->mD + w - 1) / w;
+        const uint32_t gpt = 128 / w;
+        t.ntiles = (ngroups + gpt - 1) / gpt;
+        t.nbuckets = (info->npiv >> kBucketShift) + 2;
+        t.kp = ((uint64_t)info->npiv + 63) / 64 * 64;
+        const uint64_t mp = (uint64_t)t.ntiles * 128;
+        const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
+        t.Ah = c.take<int8_t>(mp * t.kp);
+        t.Al = c.take<int8_t>(mp * t.kp);
+        t.Xh = c.take<int8_t>(np * t.kp);
+        t.Xl = c.take<int8_t>(np * t.kp);
+        t.bucket = c.take<uint32_t>(ngroups);
+        t.fill = c.take<uint32_t>(t.nbuckets);
+        t.order = c.take<uint32_t>(ngroups);
+        t.krange = c.take<uint32_t>(2 * (size_t)t.ntiles);
+        t.row_map = c.take<uint32_t>(mp);
+        t.hist = c.take<uint64_t>(t.nbuckets);
+        t.scantmp = c.take<uint64_t>(fl_scan_tmp_elems(t.nbuckets));
     }
     if (r) *r = t;
     return c.off;
 }
 
 }  // namespace
+
+fl_limbs_cols_fn fl_limbs_cols_kernel();
 
 extern "C" size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode) {
     if (!info) return 0;
@@ -99,13 +193,36 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
                           ldd, nB, stream, "reduce.spmm"));
         return FL_OK;
     }
-    FL_HIP(fl_zero_rows_u16(r.Cd, r.ldc, mD, npiv, stream));
-    hipLaunchKernelGGL(k_ml_to_dense, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, ngroups, mD,
-                       (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
-                       (const uint16_t *)s->c_val, r.Cd, r.ldc);
-    FL_LAUNCH_CHECK("k_ml_to_dense");
-    FL_HIP(fl_gemm_sub_mfma(info->p, mD, nB, npiv, nullptr, r.Cd, r.ldc, X, ldx, Dt, ldd, r.gemm_ws,
-                            r.gemm_ws_bytes, stream, "reduce"));
+    const uint32_t gpt = 128 / w;
+    const uint32_t nthreads_g = (ngroups + 255) / 256;
+    FL_HIP(fl_fill_u64(r.hist, 0, r.nbuckets, stream));
+    FL_HIP(fl_fill_u32(r.fill, 0, r.nbuckets, stream));
+    FL_PROF("reduce.sort", stream, {
+        hipLaunchKernelGGL(k_grp_bucket, dim3(nthreads_g), dim3(256), 0, stream, ngroups, r.nbuckets,
+                           (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos, r.bucket, r.hist);
+        (void)fl_exclusive_scan_u64(r.hist, r.hist, r.nbuckets, r.scantmp, nullptr, stream);
+        hipLaunchKernelGGL(k_grp_scatter, dim3(nthreads_g), dim3(256), 0, stream, ngroups,
+                           (const uint32_t *)r.bucket, (const uint64_t *)r.hist, r.fill, r.order);
+        hipLaunchKernelGGL(k_tile_krange, dim3((r.ntiles + 255) / 256), dim3(256), 0, stream, w, ngroups, mD,
+                           r.ntiles, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
+                           (const uint32_t *)r.order, (uint32_t)r.kp, r.krange, r.row_map);
+    });
+    FL_LAUNCH_CHECK("reduce sort");
+    FL_PROF("reduce.limbs", stream, {
+        hipLaunchKernelGGL(k_tile_zero, dim3(r.ntiles, 128), dim3(256), 0, stream, (const uint32_t *)r.krange,
+                           r.Ah, r.Al, r.kp);
+        hipLaunchKernelGGL(k_tile_scatter, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, info->p, ngroups,
+                           (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos, (const uint16_t *)s->c_val,
+                           (const uint32_t *)r.order, r.Ah, r.Al, r.kp);
+        const uint32_t np = (nB + 127) / 128 * 128;
+        hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(np / 64, (unsigned)(r.kp / 64)), dim3(256), 0, stream,
+                           info->p, X, ldx, nB, npiv, (const uint32_t *)nullptr, r.Xh, r.Xl, (uint32_t)r.kp);
+    });
+    FL_LAUNCH_CHECK("reduce limbs");
+    (void)gpt;
+    GemmPlanes gp = {r.Ah, r.Al, r.Xh, r.Xl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
+                     nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
+    FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "reduce.mfma"));
     return FL_OK;
 }
 

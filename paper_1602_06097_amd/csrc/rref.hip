@@ -21,6 +21,9 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
                             uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
                             const char *site);
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
+typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+fl_limbs_cols_fn fl_limbs_cols_kernel();
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 
 namespace {
@@ -36,6 +39,63 @@ __global__ __launch_bounds__(256) void k_gather_pivcols(const uint16_t *__restri
     if (t >= r) return;
     const uint32_t c = pivcol[t];
     for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) L[(uint64_t)i * ldl + t] = X[(uint64_t)i * ldx + c];
+}
+
+// MFMA form: L = X[:, P_D] directly as int8 limb planes (Kp bytes per row,
+// zero for t >= r).
+__global__ __launch_bounds__(256) void k_gather_pivcols_limbs(uint32_t p, const uint16_t *__restrict__ X,
+                                                              uint64_t ldx, uint32_t npiv,
+                                                              const uint32_t *__restrict__ d_rank,
+                                                              const uint32_t *__restrict__ pivcol,
+                                                              int8_t *Lh, int8_t *Ll, uint64_t kp) {
+    const uint32_t r = *d_rank;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kp) return;
+    const uint32_t c = t < r ? pivcol[t] : 0;
+    for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) {
+        int h = 0, l = 0;
+        if (t < r) fl_split_limbs(X[(uint64_t)i * ldx + c], p, h, l);
+        Lh[(uint64_t)i * kp + t] = (int8_t)h;
+        Ll[(uint64_t)i * kp + t] = (int8_t)l;
+    }
+}
+
+// For every row t < r of R_D: the 128-column output tiles its nonzeros span
+// (from its pivot column to its last nonzero); per tile, the smallest and
+// largest such t.  All-zero (tile, t-range) blocks of the product are skipped.
+__global__ __launch_bounds__(256) void k_rd_tile_ranges(const uint16_t *__restrict__ RD, uint64_t ldd,
+                                                        uint32_t nB, const uint32_t *__restrict__ d_rank,
+                                                        const uint32_t *__restrict__ pivcol,
+                                                        uint32_t *tmin, uint32_t *tmax) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= *d_rank) return;
+    const uint32_t q = pivcol[t];
+    const uint16_t *row = RD + (uint64_t)t * ldd;
+    uint32_t last = q;
+    for (uint32_t c0 = q; c0 < nB; c0 += 64) {
+        const uint32_t c = c0 + lane;
+        const uint64_t m = __ballot(c < nB && row[c] != 0);
+        if (m) last = c0 + 63 - __clzll(m);
+    }
+    for (uint32_t tile = q / 128 + lane; tile <= last / 128; tile += 64) {
+        atomicMin(&tmin[tile], t);
+        atomicMax(&tmax[tile], t);
+    }
+}
+
+__global__ void k_krange_from_t(uint32_t ntiles, const uint32_t *__restrict__ tmin,
+                                const uint32_t *__restrict__ tmax, uint32_t kp, uint32_t *krange) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntiles) return;
+    uint32_t b = 0, e = 0;
+    if (tmin[j] <= tmax[j] && tmin[j] != 0xffffffffu) {
+        b = tmin[j] / 64 * 64;
+        e = (tmax[j] + 1 + 63) / 64 * 64;
+        if (e > kp) e = kp;
+    }
+    krange[2 * j] = b;
+    krange[2 * j + 1] = e;
 }
 
 // Number of entries of p_list[0..cnt) strictly below x (p_list ascending).
@@ -147,18 +207,33 @@ size_t csr_layout(uint32_t npiv, uint32_t maxr, void *ws, CsrWs *c) {
 struct RrefWs {
     uint16_t *L;
     uint64_t ldl;
-    void *gemm_ws;
-    size_t gemm_ws_bytes;
+    int8_t *Lh, *Ll, *Rh, *Rl;
+    uint32_t *tmin, *tmax, *krange;
+    uint64_t kp;
+    uint32_t ntiles;
 };
 
 size_t rref_layout(const fl_split_info *info, fl_mode mode, void *ws, RrefWs *r) {
     WsCarve w(ws);
-    RrefWs t;
+    RrefWs t = {};
     const uint32_t maxr = info->mD < info->nB ? info->mD : info->nB;
-    t.ldl = ((uint64_t)maxr + 7) & ~(uint64_t)7;
-    t.L = w.take<uint16_t>((size_t)(info->npiv ? info->npiv : 1) * (t.ldl ? t.ldl : 1));
-    t.gemm_ws_bytes = mode == FL_MFMA_I8 ? fl_gemm_sub_mfma_ws(info->npiv, info->nB, maxr) : 0;
-    t.gemm_ws = t.gemm_ws_bytes ? (void *)w.take<char>(t.gemm_ws_bytes) : nullptr;
+    if (mode == FL_MFMA_I8) {
+        const uint64_t mp = ((uint64_t)info->npiv + 127) / 128 * 128;
+        const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
+        t.kp = ((uint64_t)maxr + 63) / 64 * 64;
+        if (t.kp == 0) t.kp = 64;
+        t.ntiles = (uint32_t)(np / 128);
+        t.Lh = w.take<int8_t>(mp * t.kp);
+        t.Ll = w.take<int8_t>(mp * t.kp);
+        t.Rh = w.take<int8_t>(np * t.kp);
+        t.Rl = w.take<int8_t>(np * t.kp);
+        t.tmin = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
+        t.tmax = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
+        t.krange = w.take<uint32_t>(2 * (size_t)(t.ntiles ? t.ntiles : 1));
+    } else {
+        t.ldl = ((uint64_t)maxr + 7) & ~(uint64_t)7;
+        t.L = w.take<uint16_t>((size_t)(info->npiv ? info->npiv : 1) * (t.ldl ? t.ldl : 1));
+    }
     if (r) *r = t;
     return w.off;
 }
@@ -190,14 +265,34 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
         fl_set_error("fl_rref: workspace too small");
         return FL_ERR_WORKSPACE;
     }
-    dim3 g((maxr + 255) / 256, npiv < 1024 ? npiv : 1024);
-    hipLaunchKernelGGL(k_gather_pivcols, g, dim3(256), 0, stream, (const uint16_t *)X, ldx, npiv,
-                       d_rank, d_pivcol, r.L, r.ldl);
-    FL_LAUNCH_CHECK("k_gather_pivcols");
     if (mode == FL_MFMA_I8) {
-        FL_HIP(fl_gemm_sub_mfma(info->p, npiv, nB, maxr, d_rank, r.L, r.ldl, RD, ldd, X, ldx,
-                                r.gemm_ws, r.gemm_ws_bytes, stream, "rref"));
+        // L = X[:, P_D] and R_D as limb planes; per 128-column tile of X the
+        // range of R_D rows that are nonzero there
+        dim3 g((unsigned)((r.kp + 255) / 256), npiv < 1024 ? npiv : 1024);
+        FL_PROF("rref.limbs", stream, {
+            hipLaunchKernelGGL(k_gather_pivcols_limbs, g, dim3(256), 0, stream, info->p, (const uint16_t *)X,
+                               ldx, npiv, d_rank, d_pivcol, r.Lh, r.Ll, r.kp);
+            hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(r.ntiles * 2, (unsigned)(r.kp / 64)), dim3(256), 0,
+                               stream, info->p, RD, ldd, nB, maxr, d_rank, r.Rh, r.Rl, (uint32_t)r.kp);
+        });
+        FL_LAUNCH_CHECK("rref limbs");
+        FL_HIP(fl_fill_u32(r.tmin, 0xffffffffu, r.ntiles, stream));
+        FL_HIP(fl_fill_u32(r.tmax, 0, r.ntiles, stream));
+        FL_PROF("rref.ranges", stream, {
+            hipLaunchKernelGGL(k_rd_tile_ranges, dim3((maxr + 3) / 4), dim3(256), 0, stream, RD, ldd, nB,
+                               d_rank, d_pivcol, r.tmin, r.tmax);
+            hipLaunchKernelGGL(k_krange_from_t, dim3((r.ntiles + 255) / 256), dim3(256), 0, stream, r.ntiles,
+                               (const uint32_t *)r.tmin, (const uint32_t *)r.tmax, (uint32_t)r.kp, r.krange);
+        });
+        FL_LAUNCH_CHECK("rref ranges");
+        GemmPlanes gp = {r.Lh, r.Ll, r.Rh, r.Rl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, d_rank, nullptr,
+                         r.krange, nullptr, X, ldx, npiv, nB};
+        FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "rref.mfma"));
     } else {
+        dim3 g((maxr + 255) / 256, npiv < 1024 ? npiv : 1024);
+        hipLaunchKernelGGL(k_gather_pivcols, g, dim3(256), 0, stream, (const uint16_t *)X, ldx, npiv,
+                           d_rank, d_pivcol, r.L, r.ldl);
+        FL_LAUNCH_CHECK("k_gather_pivcols");
         FL_HIP(fl_gemm_sub_plain(info->p, npiv, nB, 0, d_rank, r.L, r.ldl, RD, ldd, X, ldx, stream,
                                  "rref.plain"));
     }

@@ -520,7 +520,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
             if (mfma) {
                 GemmPlanes gp = {tw.Ah + (uint64_t)r0 * tw.kp, tw.Al + (uint64_t)r0 * tw.kp, tw.Xh, tw.Xl,
                                  tw.kp, tw.kp, r1, r1, 0, (uint32_t)(tw.kp - r1), tw.kext + I, nullptr,
-                                 nullptr, X + (uint64_t)r0 * ldx, ldx, r1 - r0, nB};
+                                 nullptr, nullptr, X + (uint64_t)r0 * ldx, ldx, r1 - r0, nB};
                 e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
             } else {
                 const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
