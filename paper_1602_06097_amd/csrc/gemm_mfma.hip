@@ -197,41 +197,45 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, ui
             }
         }
     __syncthreads();
-    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each; the
-    // C loads of all 16 chunks are issued before any store
-    uint64_t cvals[16];
+    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each, in
+    // batches of 4 whose C loads are issued before their stores
+#pragma unroll 1
+    for (int u0 = 0; u0 < 16; u0 += 4) {
+        uint64_t cvals[4];
+        uint32_t orows[4];
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        const uint32_t ch = tid + u * 256;
-        const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-        const uint32_t row = m0 + r, col = n0 + c4;
-        cvals[u] = 0;
-        if (row < g.M && col + 4 <= g.N) {
-            const uint32_t orow = g.row_map ? g.row_map[row] : row;
-            if (orow != 0xffffffffu) cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orow * g.ldc + col);
+        for (int u = 0; u < 4; u++) {
+            const uint32_t ch = tid + (u0 + u) * 256;
+            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+            const uint32_t row = m0 + r, col = n0 + c4;
+            cvals[u] = 0;
+            orows[u] = 0xffffffffu;
+            if (row < g.M && col < g.N) {
+                orows[u] = g.row_map ? g.row_map[row] : row;
+                if (orows[u] != 0xffffffffu && col + 4 <= g.N)
+                    cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orows[u] * g.ldc + col);
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        const uint32_t ch = tid + u * 256;
-        const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-        const uint32_t row = m0 + r, col = n0 + c4;
-        if (row >= g.M || col >= g.N) continue;
-        const uint32_t orow = g.row_map ? g.row_map[row] : row;
-        if (orow == 0xffffffffu) continue;
-        uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
-        const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
-        if (col + 4 <= g.N) {
-            const uint64_t ov = cvals[u];
-            uint64_t nv = 0;
+        for (int u = 0; u < 4; u++) {
+            const uint32_t ch = tid + (u0 + u) * 256;
+            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+            const uint32_t col = n0 + c4;
+            if (orows[u] == 0xffffffffu) continue;
+            uint16_t *o = g.C + (uint64_t)orows[u] * g.ldc + col;
+            const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
+            if (col + 4 <= g.N) {
+                const uint64_t ov = cvals[u];
+                uint64_t nv = 0;
 #pragma unroll
-            for (int c = 0; c < 4; c++)
-                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
-                                           (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
-            *(uint64_t *)o = nv;
-        } else {
-            for (uint32_t c = 0; col + c < g.N; c++)
-                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
+                for (int c = 0; c < 4; c++)
+                    nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
+                                               (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+                *(uint64_t *)o = nv;
+            } else {
+                for (uint32_t c = 0; col + c < g.N; c++)
+                    o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
+            }
         }
     }
 }

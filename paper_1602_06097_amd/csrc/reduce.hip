@@ -33,49 +33,71 @@ typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t,
 // ---- MFMA form: C's multiline groups sorted by first column, so that each
 // 128-row tile of the dense C operand is nonzero only on a short K range ----
 
-constexpr uint32_t kBucketShift = 6;  // groups bucketed by first column / 64
+constexpr uint32_t kBucketShift = 6;  // rows bucketed by first column / 64
 
-// Bucket of every group (empty groups go to the last bucket) and histogram.
-__global__ void k_grp_bucket(uint32_t ngroups, uint32_t nbuckets, const uint64_t *__restrict__ gptr,
-                             const uint32_t *__restrict__ pos, uint32_t *bucket, uint64_t *hist) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+// First and last column of every row of C (from its multiline group, one wave
+// per group), its bucket (empty rows go to the last bucket) and the histogram.
+__global__ __launch_bounds__(256) void k_row_extent(uint32_t w, uint32_t ngroups, uint32_t mD,
+                                                    uint32_t nbuckets, const uint64_t *__restrict__ gptr,
+                                                    const uint32_t *__restrict__ pos,
+                                                    const uint16_t *__restrict__ val, uint32_t *first,
+                                                    uint32_t *last, uint32_t *bucket, uint64_t *hist) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (g >= ngroups) return;
     const uint64_t b = gptr[g], e = gptr[g + 1];
-    const uint32_t k = e > b ? (pos[b] >> kBucketShift) : nbuckets - 1;
-    bucket[g] = k;
-    atomicAdd((unsigned long long *)&hist[k], 1ull);
+    for (uint32_t q = 0; q < w; q++) {
+        const uint32_t row = g * w + q;
+        if (row >= mD) break;
+        uint32_t lo = 0xffffffffu, hi = 0;
+        for (uint64_t k0 = b; k0 < e; k0 += 64) {
+            const uint64_t k = k0 + lane;
+            const bool nz = k < e && val[(uint64_t)w * k + q] != 0;
+            const uint64_t m = __ballot(nz);
+            if (m) {
+                const uint32_t fpos = pos[k0 + __ffsll((long long)m) - 1];
+                const uint32_t lpos = pos[k0 + 63 - __clzll(m)];
+                lo = fpos < lo ? fpos : lo;
+                hi = lpos + 1;
+            }
+        }
+        if (lane == 0) {
+            first[row] = lo;
+            last[row] = hi;
+            const uint32_t bk = lo != 0xffffffffu ? (lo >> kBucketShift) : nbuckets - 1;
+            bucket[row] = bk;
+            atomicAdd((unsigned long long *)&hist[bk], 1ull);
+        }
+    }
 }
 
-// order[off[bucket] + rank within bucket] = group (rank by atomic fill).
-__global__ void k_grp_scatter(uint32_t ngroups, const uint32_t *__restrict__ bucket,
-                              const uint64_t *__restrict__ off, uint32_t *fill, uint32_t *order) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
-    const uint32_t k = bucket[g];
-    order[off[k] + atomicAdd(&fill[k], 1u)] = g;
+// order[off[bucket] + rank within bucket] = row; rank_of[row] = its position.
+__global__ void k_row_scatter(uint32_t mD, const uint32_t *__restrict__ bucket,
+                              const uint64_t *__restrict__ off, uint32_t *fill, uint32_t *order,
+                              uint32_t *rank_of) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= mD) return;
+    const uint32_t k = bucket[r];
+    const uint32_t at = (uint32_t)off[k] + atomicAdd(&fill[k], 1u);
+    order[at] = r;
+    rank_of[r] = at;
 }
 
-// Per tile of 128 sorted rows (gpt = 128 / w groups): the K range spanned by
-// its groups' columns, and the output row of every sorted row.
-__global__ void k_tile_krange(uint32_t w, uint32_t ngroups, uint32_t mD, uint32_t ntiles,
-                              const uint64_t *__restrict__ gptr, const uint32_t *__restrict__ pos,
-                              const uint32_t *__restrict__ order, uint32_t kp, uint32_t *krange,
-                              uint32_t *row_map) {
+// Per tile of 128 sorted rows: the K range spanned by its rows' columns, and
+// the output row of every sorted row (~0u past the last row).
+__global__ void k_tile_krange(uint32_t mD, uint32_t ntiles, const uint32_t *__restrict__ order,
+                              const uint32_t *__restrict__ first, const uint32_t *__restrict__ last,
+                              uint32_t kp, uint32_t *krange, uint32_t *row_map) {
     const uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
-    const uint32_t gpt = 128 / w;
     uint32_t lo = 0xffffffffu, hi = 0;
-    for (uint32_t j = 0; j < gpt; j++) {
-        const uint32_t sg = tile * gpt + j;
-        const uint32_t g = sg < ngroups ? order[sg] : 0xffffffffu;
-        for (uint32_t q = 0; q < w; q++)
-            row_map[sg * w + q] = (g != 0xffffffffu && g * w + q < mD) ? g * w + q : 0xffffffffu;
-        if (g == 0xffffffffu) continue;
-        const uint64_t b = gptr[g], e = gptr[g + 1];
-        if (e > b) {
-            lo = pos[b] < lo ? pos[b] : lo;
-            hi = pos[e - 1] + 1 > hi ? pos[e - 1] + 1 : hi;
-        }
+    for (uint32_t j = 0; j < 128; j++) {
+        const uint32_t s = tile * 128 + j;
+        const uint32_t r = s < mD ? order[s] : 0xffffffffu;
+        row_map[s] = r;
+        if (r == 0xffffffffu || first[r] == 0xffffffffu) continue;
+        lo = first[r] < lo ? first[r] : lo;
+        hi = last[r] > hi ? last[r] : hi;
     }
     uint32_t kb = 0, ke = 0;
     if (lo != 0xffffffffu) {
@@ -99,31 +121,34 @@ __global__ __launch_bounds__(256) void k_tile_zero(const uint32_t *__restrict__ 
     }
 }
 
-// Entries of sorted group sg -> its w rows of the limb planes.
+// Nonzero entries of group g's rows -> their sorted rows of the limb planes.
 __global__ __launch_bounds__(256) void k_tile_scatter(uint32_t w, uint32_t p, uint32_t ngroups,
-                                                      const uint64_t *__restrict__ gptr,
+                                                      uint32_t mD, const uint64_t *__restrict__ gptr,
                                                       const uint32_t *__restrict__ pos,
                                                       const uint16_t *__restrict__ val,
-                                                      const uint32_t *__restrict__ order, int8_t *Ah,
+                                                      const uint32_t *__restrict__ rank_of, int8_t *Ah,
                                                       int8_t *Al, uint64_t kp) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t sg = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (sg >= ngroups) return;
-    const uint32_t g = order[sg];
-    for (uint64_t k = gptr[g] + lane; k < gptr[g + 1]; k += 64) {
-        const uint32_t c = pos[k];
-        for (uint32_t q = 0; q < w; q++) {
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= ngroups) return;
+    for (uint32_t q = 0; q < w; q++) {
+        const uint32_t row = g * w + q;
+        if (row >= mD) break;
+        const uint64_t srow = rank_of[row];
+        for (uint64_t k = gptr[g] + lane; k < gptr[g + 1]; k += 64) {
+            const uint32_t v = val[(uint64_t)w * k + q];
+            if (!v) continue;
             int h, l;
-            fl_split_limbs(val[(uint64_t)w * k + q], p, h, l);
-            Ah[(uint64_t)(sg * w + q) * kp + c] = (int8_t)h;
-            Al[(uint64_t)(sg * w + q) * kp + c] = (int8_t)l;
+            fl_split_limbs(v, p, h, l);
+            Ah[srow * kp + pos[k]] = (int8_t)h;
+            Al[srow * kp + pos[k]] = (int8_t)l;
         }
     }
 }
 
 struct ReduceWs {
     int8_t *Ah, *Al, *Xh, *Xl;
-    uint32_t *bucket, *fill, *order, *krange, *row_map;
+    uint32_t *first, *last, *bucket, *fill, *order, *rank_of, *krange, *row_map;
     uint64_t *hist, *scantmp;
     uint64_t kp;
     uint32_t ntiles, nbuckets;
@@ -133,10 +158,7 @@ size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs
     WsCarve c(ws);
     ReduceWs t = {};
     if (mode == FL_MFMA_I8 && info->mD && info->nB && info->npiv) {
-        const uint32_t w = info->ml_width ? info->ml_width : 1;
-        const uint32_t ngroups = (info->mD + w - 1) / w;
-        const uint32_t gpt = 128 / w;
-        t.ntiles = (ngroups + gpt - 1) / gpt;
+        t.ntiles = (info->mD + 127) / 128;
         t.nbuckets = (info->npiv >> kBucketShift) + 2;
         t.kp = ((uint64_t)info->npiv + 63) / 64 * 64;
         const uint64_t mp = (uint64_t)t.ntiles * 128;
@@ -145,9 +167,12 @@ size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs
         t.Al = c.take<int8_t>(mp * t.kp);
         t.Xh = c.take<int8_t>(np * t.kp);
         t.Xl = c.take<int8_t>(np * t.kp);
-        t.bucket = c.take<uint32_t>(ngroups);
+        t.first = c.take<uint32_t>(info->mD);
+        t.last = c.take<uint32_t>(info->mD);
+        t.bucket = c.take<uint32_t>(info->mD);
         t.fill = c.take<uint32_t>(t.nbuckets);
-        t.order = c.take<uint32_t>(ngroups);
+        t.order = c.take<uint32_t>(info->mD);
+        t.rank_of = c.take<uint32_t>(info->mD);
         t.krange = c.take<uint32_t>(2 * (size_t)t.ntiles);
         t.row_map = c.take<uint32_t>(mp);
         t.hist = c.take<uint64_t>(t.nbuckets);
@@ -193,33 +218,31 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
                           ldd, nB, stream, "reduce.spmm"));
         return FL_OK;
     }
-    const uint32_t gpt = 128 / w;
-    const uint32_t nthreads_g = (ngroups + 255) / 256;
     FL_HIP(fl_fill_u64(r.hist, 0, r.nbuckets, stream));
     FL_HIP(fl_fill_u32(r.fill, 0, r.nbuckets, stream));
     FL_PROF("reduce.sort", stream, {
-        hipLaunchKernelGGL(k_grp_bucket, dim3(nthreads_g), dim3(256), 0, stream, ngroups, r.nbuckets,
-                           (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos, r.bucket, r.hist);
+        hipLaunchKernelGGL(k_row_extent, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, ngroups, mD,
+                           r.nbuckets, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
+                           (const uint16_t *)s->c_val, r.first, r.last, r.bucket, r.hist);
         (void)fl_exclusive_scan_u64(r.hist, r.hist, r.nbuckets, r.scantmp, nullptr, stream);
-        hipLaunchKernelGGL(k_grp_scatter, dim3(nthreads_g), dim3(256), 0, stream, ngroups,
-                           (const uint32_t *)r.bucket, (const uint64_t *)r.hist, r.fill, r.order);
-        hipLaunchKernelGGL(k_tile_krange, dim3((r.ntiles + 255) / 256), dim3(256), 0, stream, w, ngroups, mD,
-                           r.ntiles, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
-                           (const uint32_t *)r.order, (uint32_t)r.kp, r.krange, r.row_map);
+        hipLaunchKernelGGL(k_row_scatter, dim3((mD + 255) / 256), dim3(256), 0, stream, mD,
+                           (const uint32_t *)r.bucket, (const uint64_t *)r.hist, r.fill, r.order, r.rank_of);
+        hipLaunchKernelGGL(k_tile_krange, dim3((r.ntiles + 255) / 256), dim3(256), 0, stream, mD, r.ntiles,
+                           (const uint32_t *)r.order, (const uint32_t *)r.first, (const uint32_t *)r.last,
+                           (uint32_t)r.kp, r.krange, r.row_map);
     });
     FL_LAUNCH_CHECK("reduce sort");
     FL_PROF("reduce.limbs", stream, {
         hipLaunchKernelGGL(k_tile_zero, dim3(r.ntiles, 128), dim3(256), 0, stream, (const uint32_t *)r.krange,
                            r.Ah, r.Al, r.kp);
         hipLaunchKernelGGL(k_tile_scatter, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, info->p, ngroups,
-                           (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos, (const uint16_t *)s->c_val,
-                           (const uint32_t *)r.order, r.Ah, r.Al, r.kp);
+                           mD, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
+                           (const uint16_t *)s->c_val, (const uint32_t *)r.rank_of, r.Ah, r.Al, r.kp);
         const uint32_t np = (nB + 127) / 128 * 128;
         hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(np / 64, (unsigned)(r.kp / 64)), dim3(256), 0, stream,
                            info->p, X, ldx, nB, npiv, (const uint32_t *)nullptr, r.Xh, r.Xl, (uint32_t)r.kp);
     });
     FL_LAUNCH_CHECK("reduce limbs");
-    (void)gpt;
     GemmPlanes gp = {r.Ah, r.Al, r.Xh, r.Xl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
                      nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "reduce.mfma"));
