@@ -199,54 +199,78 @@ __global__ __launch_bounds__(256) void k_ml_spmm(fl::Mod md, const uint64_t *__r
     }
 }
 
-// Back substitution inside one TRSM block [r0, r1): one wave per 64-column
-// stripe (one column per lane).  Rows of the block are finished from the
-// bottom up and kept in LDS; A-entries at positions >= r1 were applied by the
-// preceding update launch.
-template <int W>
-__global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *__restrict__ gptr,
-                                                   const uint32_t *__restrict__ pos,
-                                                   const uint16_t *__restrict__ val, uint32_t r0,
-                                                   uint32_t r1, uint16_t *X, uint64_t ldx,
-                                                   uint32_t ncols, int8_t *Xth, int8_t *Xtl,
-                                                   uint64_t kp) {
-    __shared__ uint16_t blk[kTrsmBlock][64];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t c = blockIdx.x * 64 + lane;
-    const bool colok = c < ncols;
-    const uint32_t gfirst = r0 / W, glast = (r1 + W - 1) / W;  // groups [gfirst, glast)
-    for (uint32_t g = glast; g-- > gfirst;) {
-        const uint32_t gr0 = g * W;
-        const uint32_t gend = gr0 + W;  // first position outside the group
-        uint64_t kb = gptr[g], ke = gptr[g + 1];
+// For every multiline group g of A: nin[g] = number of its entries inside
+// the group (positions < (g+1)w, the w x w triangle), nnear[g] = number of
+// entries before the first position >= r1 of its TRSM block.  One wave per
+// group, computed once per TRSM.
+__global__ __launch_bounds__(256) void k_trsm_bounds(uint32_t w, uint32_t npiv, uint32_t ngroups,
+                                                     const uint64_t *__restrict__ gptr,
+                                                     const uint32_t *__restrict__ pos, uint32_t *nin,
+                                                     uint32_t *nnear) {
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= ngroups) return;
+    const uint32_t I = (g * w) / kTrsmBlock;
+    const uint32_t r1 = (I + 1) * kTrsmBlock < npiv ? (I + 1) * kTrsmBlock : npiv;
+    const uint64_t kb = gptr[g], ke = gptr[g + 1];
+    const uint64_t kin = first_at_least(pos, kb, ke, (g + 1) * w);
+    const uint64_t kfar = first_at_least(pos, kin, ke, r1);
+    if ((threadIdx.x & 63) == 0) {
+        nin[g] = (uint32_t)(kin - kb);
+        nnear[g] = (uint32_t)(kfar - kb);
+    }
+}
+
+constexpr uint32_t kNearCap = 2048;  // staged intra+near entries per block
+
+// Entry j of group gi: from the LDS copy (STAGED) or from global memory.
+template <int W, bool STAGED> struct Entries {
+    const uint32_t *s_pos;
+    const uint16_t *s_val;
+    const uint32_t *s_off;
+    const uint64_t *s_kb;
+    const uint32_t *pos;
+    const uint16_t *val;
+    __device__ uint32_t p(uint32_t gi, uint32_t j) const {
+        return STAGED ? s_pos[s_off[gi] + j] : pos[s_kb[gi] + j];
+    }
+    __device__ uint32_t v(uint32_t gi, uint32_t j, int q) const {
+        return STAGED ? s_val[(s_off[gi] + j) * W + q] : val[(uint64_t)W * (s_kb[gi] + j) + q];
+    }
+};
+
+// Solve the block's groups from the bottom up on the LDS tile blk.
+template <int W, bool STAGED>
+__device__ void solve_groups(const fl::Mod &md, const Entries<W, STAGED> &E, uint16_t (*blk)[64],
+                             const uint32_t *s_nin, const uint32_t *s_off, uint32_t gfirst,
+                             uint32_t ng, uint32_t r0, uint32_t r1, uint32_t lane) {
+    for (uint32_t gi = ng; gi-- > 0;) {
+        const uint32_t gr0 = (gfirst + gi) * W;
+        const uint32_t nin = s_nin[gi], nend = s_off[gi + 1] - s_off[gi];
         uint32_t ah[W], al[W];
 #pragma unroll
         for (int q = 0; q < W; q++) ah[q] = al[q] = 0;
-        // intra-group entries come first (positions in [gr0, gend)), then the
-        // near entries of the block (positions in [gend, r1))
-        uint64_t kin = first_at_least(pos, kb, ke, gend);
-        uint64_t kfar = first_at_least(pos, kin, ke, r1);
         uint32_t terms = 0;
-        for (uint64_t k = kin; k < kfar; k += 64) {
-            const int batch = (int)((kfar - k) < 64 ? (kfar - k) : 64);
-            uint32_t mypos = 0;
-            MlVals<W> mv;
-            if ((int)lane < batch) {
-                mypos = pos[k + lane];
-                mv.load(val, k + lane);
+        uint32_t j = nin;
+        // 8 entries at a time: their reads are independent and overlap
+        for (; j + 8 <= nend; j += 8) {
+            uint32_t pj[8], x[8], a[8][W];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                pj[u] = E.p(gi, j + u);
+#pragma unroll
+                for (int q = 0; q < W; q++) a[u][q] = E.v(gi, j + u, q);
             }
-            for (int j = 0; j < batch; j++) {
-                uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)mypos, j);
-                uint32_t x = blk[pj - r0][lane];
+#pragma unroll
+            for (int u = 0; u < 8; u++) x[u] = blk[pj[u] - r0][lane];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
 #pragma unroll
                 for (int q = 0; q < W; q++) {
-                    uint32_t a = mv.get(j, q);
-                    ah[q] = fl::mad24(a >> 8, x, ah[q]);
-                    al[q] = fl::mad24(a & 0xffu, x, al[q]);
+                    ah[q] = fl::mad24(a[u][q] >> 8, x[u], ah[q]);
+                    al[q] = fl::mad24(a[u][q] & 0xffu, x[u], al[q]);
                 }
-            }
-            terms += (uint32_t)batch;
-            if (terms > FL_FOLD_TERMS - 64) {
+            terms += 8;
+            if (terms > FL_FOLD_TERMS - 8) {
 #pragma unroll
                 for (int q = 0; q < W; q++) {
                     al[q] = fl::fold_pair(ah[q], al[q], md);
@@ -255,30 +279,120 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
                 terms = 0;
             }
         }
+        for (; j < nend; j++) {
+            const uint32_t x = blk[E.p(gi, j) - r0][lane];
+#pragma unroll
+            for (int q = 0; q < W; q++) {
+                const uint32_t a = E.v(gi, j, q);
+                ah[q] = fl::mad24(a >> 8, x, ah[q]);
+                al[q] = fl::mad24(a & 0xffu, x, al[q]);
+            }
+        }
         // T_q = X[row] - near sum, then the triangular correction inside the group
-        uint32_t t[W];
+        uint32_t tq[W];
 #pragma unroll
         for (int q = 0; q < W; q++) {
-            uint32_t row = gr0 + q;
-            uint32_t cur = (row < r1 && colok) ? X[(uint64_t)row * ldx + c] : 0;
-            t[q] = fl::submod(cur, fl::fold_pair(ah[q], al[q], md), md.p);
+            const uint32_t row = gr0 + q;
+            const uint32_t cur = row < r1 ? blk[row - r0][lane] : 0;
+            tq[q] = fl::submod(cur, fl::fold_pair(ah[q], al[q], md), md.p);
         }
 #pragma unroll
         for (int q = W - 1; q >= 0; q--) {
             const uint32_t row = gr0 + q;
             if (row < r1) {
-                // subtract a[q][j] * v[j] for j > q (rows of the group already final)
-                for (uint64_t k = kb; k < kin; k++) {
-                    const uint32_t qq = pos[k] - gr0;
-                    const uint32_t a = val[(uint64_t)W * k + q];
+                // subtract a[q][jj] * v[jj] for jj > q (rows of the group already final)
+                for (uint32_t e = 0; e < nin; e++) {
+                    const uint32_t qq = E.p(gi, e) - gr0;
+                    const uint32_t a = E.v(gi, e, q);
 #pragma unroll
-                    for (int j = q + 1; j < W; j++)
-                        if (qq == (uint32_t)j && a) t[q] = fl::submod(t[q], fl::mulmod(a, t[j], md), md.p);
+                    for (int jj = q + 1; jj < W; jj++)
+                        if (qq == (uint32_t)jj && a) tq[q] = fl::submod(tq[q], fl::mulmod(a, tq[jj], md), md.p);
                 }
-                blk[row - r0][lane] = (uint16_t)t[q];
-                if (colok) X[(uint64_t)row * ldx + c] = (uint16_t)t[q];
+                blk[row - r0][lane] = (uint16_t)tq[q];
             }
         }
+    }
+}
+
+// Back substitution inside one TRSM block [r0, r1): one wave per 64-column
+// stripe (one column per lane).  The block's intra-group and near entries of
+// A (positions < r1) and the block's rows of X (after the far update) are
+// staged in LDS with independent, vectorised loads; rows are then finished
+// from the bottom up in LDS, each multiline group with the w x w triangular
+// correction between its own rows.  Entries at positions >= r1 were applied
+// by the preceding update launch.
+template <int W>
+__global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                   const uint32_t *__restrict__ pos,
+                                                   const uint16_t *__restrict__ val,
+                                                   const uint32_t *__restrict__ nin_a,
+                                                   const uint32_t *__restrict__ nnear_a, uint32_t r0,
+                                                   uint32_t r1, uint16_t *X, uint64_t ldx,
+                                                   uint32_t ncols, int8_t *Xth, int8_t *Xtl,
+                                                   uint64_t kp) {
+    constexpr uint32_t kG = kTrsmBlock / W;
+    __shared__ __attribute__((aligned(16))) uint16_t blk[kTrsmBlock][64];
+    __shared__ uint32_t s_off[kG + 1];
+    __shared__ uint32_t s_nin[kG];
+    __shared__ uint64_t s_kb[kG];
+    __shared__ uint32_t s_pos[kNearCap];
+    __shared__ uint16_t s_val[kNearCap * W];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t c0 = blockIdx.x * 64;
+    const uint32_t c = c0 + lane;
+    const bool colok = c < ncols;
+    const uint32_t gfirst = r0 / W, glast = (r1 + W - 1) / W, ng = glast - gfirst;
+    const uint32_t nrow = r1 - r0;
+    // group metadata and offsets of the staged entries
+    for (uint32_t gi = lane; gi < ng; gi += 64) {
+        s_kb[gi] = gptr[gfirst + gi];
+        s_nin[gi] = nin_a[gfirst + gi];
+        s_off[gi + 1] = nnear_a[gfirst + gi];
+    }
+    // X tile: 128 rows x 64 columns; lane l moves 4 columns (8 bytes) of rows
+    // l/16, l/16 + 4, ... (16 lanes per row)
+    const uint32_t tr = lane >> 4, tc = (lane & 15) * 4;
+    const bool vec = c0 + tc + 4 <= ncols;
+    for (uint32_t r = tr; r < nrow; r += 4) {
+        const uint16_t *src = X + (uint64_t)(r0 + r) * ldx + c0 + tc;
+        if (vec) *(uint64_t *)&blk[r][tc] = *(const uint64_t *)src;
+        else
+            for (uint32_t k = 0; k < 4; k++) blk[r][tc + k] = c0 + tc + k < ncols ? src[k] : 0;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        s_off[0] = 0;
+        for (uint32_t gi = 0; gi < ng; gi++) s_off[gi + 1] += s_off[gi];
+    }
+    __syncthreads();
+    const uint32_t total = s_off[ng];
+    if (total <= kNearCap) {
+        for (uint32_t f = lane; f < total; f += 64) {
+            uint32_t lo = 0, hi = ng;  // group of staged entry f
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_off[mid] <= f) lo = mid;
+                else hi = mid;
+            }
+            const uint64_t k = s_kb[lo] + (f - s_off[lo]);
+            s_pos[f] = pos[k];
+#pragma unroll
+            for (int q = 0; q < W; q++) s_val[f * W + q] = val[(uint64_t)W * k + q];
+        }
+        __syncthreads();
+        Entries<W, true> E{s_pos, s_val, s_off, s_kb, pos, val};
+        solve_groups<W, true>(md, E, blk, s_nin, s_off, gfirst, ng, r0, r1, lane);
+    } else {
+        Entries<W, false> E{s_pos, s_val, s_off, s_kb, pos, val};
+        solve_groups<W, false>(md, E, blk, s_nin, s_off, gfirst, ng, r0, r1, lane);
+    }
+    __syncthreads();
+    for (uint32_t r = tr; r < nrow; r += 4) {
+        uint16_t *dst = X + (uint64_t)(r0 + r) * ldx + c0 + tc;
+        if (vec) *(uint64_t *)dst = *(const uint64_t *)&blk[r][tc];
+        else
+            for (uint32_t k = 0; k < 4; k++)
+                if (c0 + tc + k < ncols) dst[k] = blk[r][tc + k];
     }
     // MFMA form: the finished rows, as transposed int8 limb planes (column c
     // of X is row c of the planes, K-contiguous), for the updates of the
@@ -395,15 +509,15 @@ hipError_t ml_spmm(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const ui
 }
 
 hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const uint32_t *pos,
-                      const uint16_t *val, uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx,
-                      uint32_t ncols, hipStream_t s, int8_t *Xth = nullptr, int8_t *Xtl = nullptr,
-                      uint64_t kp = 0) {
+                      const uint16_t *val, const uint32_t *nin, const uint32_t *nnear, uint32_t r0,
+                      uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t ncols, hipStream_t s,
+                      int8_t *Xth, int8_t *Xtl, uint64_t kp) {
     dim3 grid((ncols + 63) / 64);
     switch (w) {
-    case 1: hipLaunchKernelGGL(k_trsm_solve<1>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
-    case 2: hipLaunchKernelGGL(k_trsm_solve<2>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
-    case 4: hipLaunchKernelGGL(k_trsm_solve<4>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
-    default: hipLaunchKernelGGL(k_trsm_solve<8>, grid, dim3(64), 0, s, md, gptr, pos, val, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    case 1: hipLaunchKernelGGL(k_trsm_solve<1>, grid, dim3(64), 0, s, md, gptr, pos, val, nin, nnear, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    case 2: hipLaunchKernelGGL(k_trsm_solve<2>, grid, dim3(64), 0, s, md, gptr, pos, val, nin, nnear, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    case 4: hipLaunchKernelGGL(k_trsm_solve<4>, grid, dim3(64), 0, s, md, gptr, pos, val, nin, nnear, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
+    default: hipLaunchKernelGGL(k_trsm_solve<8>, grid, dim3(64), 0, s, md, gptr, pos, val, nin, nnear, r0, r1, X, ldx, ncols, Xth, Xtl, kp); break;
     }
     return hipGetLastError();
 }
@@ -411,12 +525,19 @@ hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const
 struct TrsmWs {
     int8_t *Ah, *Al, *Xh, *Xl;
     uint32_t *kext;
+    uint32_t *nin, *nnear;
     uint64_t kp;
 };
 
 size_t trsm_layout(const fl_split_info *info, fl_mode mode, void *ws, TrsmWs *t) {
     WsCarve c(ws);
     TrsmWs r = {};
+    if (info->npiv && info->nB) {
+        const uint32_t w = info->ml_width ? info->ml_width : 1;
+        const uint32_t ngroups = (info->npiv + w - 1) / w;
+        r.nin = c.take<uint32_t>(ngroups);
+        r.nnear = c.take<uint32_t>(ngroups);
+    }
     if (mode == FL_MFMA_I8 && info->npiv && info->nB) {
         const uint64_t mp = ((uint64_t)info->npiv + 127) / 128 * 128;
         const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
@@ -489,7 +610,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
     FL_ARG(((uintptr_t)X & 7) == 0, "fl_trsm: X must be 8-byte aligned");
     TrsmWs tw;
     const size_t need = trsm_layout(info, mode, ws, &tw);
-    if (need && (!ws || ws_bytes < need)) {
+    if (!ws || ws_bytes < need) {
         fl_set_error("fl_trsm: workspace too small");
         return FL_ERR_WORKSPACE;
     }
@@ -499,8 +620,12 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
     FL_HIP(e0);
     const uint32_t nblk = (npiv + kTrsmBlock - 1) / kTrsmBlock;
     const bool mfma = mode == FL_MFMA_I8;
+    const uint32_t ngroups = (npiv + w - 1) / w;
+    FL_PROF("trsm.bounds", stream,
+            hipLaunchKernelGGL(k_trsm_bounds, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, npiv, ngroups,
+                               (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.nin, tw.nnear));
+    FL_LAUNCH_CHECK("k_trsm_bounds");
     if (mfma) {
-        const uint32_t ngroups = (npiv + w - 1) / w;
         FL_PROF("trsm.tiles", stream, {
             hipLaunchKernelGGL(k_trsm_kext, dim3((nblk + 255) / 256), dim3(256), 0, stream, w, npiv,
                                nblk, (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.kext);
@@ -532,8 +657,8 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         }
         hipError_t e;
         FL_PROF("trsm.solve", stream,
-                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, r0, r1, X, ldx, nB, stream,
-                               mfma ? tw.Xh : nullptr, mfma ? tw.Xl : nullptr, tw.kp));
+                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, r0, r1, X, ldx, nB,
+                               stream, mfma ? tw.Xh : nullptr, mfma ? tw.Xl : nullptr, tw.kp));
         FL_HIP(e);
     }
     return FL_OK;
