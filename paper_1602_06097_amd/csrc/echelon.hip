@@ -3,19 +3,19 @@
 // blocked Gauss-Jordan elimination over 64-column panels.
 //
 // For a panel [c0, c0+64):
-//  0. k_ech_check   flags the remaining rows that are nonzero on the panel.
-//  1. k_ech_probe   one block: a greedy basis of the first (>= 256) flagged
-//     rows restricted to the panel, in reduced form in LDS.  Every wave reduces one
+//  0. k_ech_check   lists the remaining rows that are nonzero on the panel.
+//  1. k_ech_probe   one block: a greedy basis of (up to 256 of) those rows
+//     restricted to the panel, in reduced form in LDS.  Every wave reduces one
 //     row against the basis (multipliers broadcast with v_readlane); rows
 //     that stay nonzero are inserted one wave at a time.  The coefficients G
 //     with  G * Dt[Q, panel] = basis  are tracked (Q = selected rows).
 //     This is the paper's parallel structured Gaussian elimination (Sec. 5.1:
 //     rows reduced in parallel against the known pivots, a new pivot added by
 //     one worker at a time) applied to a panel.
-//  2. k_ech_check   every remaining row is reduced against that basis in
-//     parallel; rows outside its span are flagged.
-//  3. k_ech_merge   only if a row was flagged: the greedy pass continues over
-//     the flagged rows.  The result: pivot columns C (ascending) of the
+//  2. k_ech_check   every listed row is reduced against that basis in
+//     parallel; rows outside its span are listed again.
+//  3. k_ech_merge   only if a row was listed: the greedy pass continues over
+//     those rows.  The result: pivot columns C (ascending) of the
 //     panel, rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
 //  4. k_ech_U              U = G * Dt[Q, c0:]   (unit vectors at C)
 //  5. k_ech_gather_L       L = Dt[:, C]          (multipliers, saved before
@@ -61,8 +61,6 @@ struct PanelState {
 
 struct EchWs {
     uint32_t *is_piv;   // [rows] 1 once the row is a pivot row
-    uint32_t *nzflag;   // [rows] 1 if the remaining row is nonzero on the panel
-    uint32_t *flags;    // [rows] 1 if the row is outside the probe basis' span
     uint32_t *piv_row;  // [min(rows, cols)]
     PanelState *ps;
     uint16_t *U;        // [64 x ldu]
@@ -71,6 +69,9 @@ struct EchWs {
     int8_t *Lh, *Ll;    // [rows x 64] limb planes of L (MFMA form)
     int8_t *Uh, *Ul;    // [(cols + 128) x 64] limb planes of U transposed (MFMA form)
     uint32_t *upd_rows; // [rows] rows with a nonzero multiplier
+    uint32_t *nzlist;   // [rows] remaining rows nonzero on the panel
+    uint32_t *flist;    // [rows] rows outside the probe basis' span
+    uint32_t *counts;   // [3 * npanels] per panel: nonzero, flagged, update rows
     void *gemm_ws;
     size_t gemm_ws_bytes;
     uint64_t ldu;
@@ -102,6 +103,22 @@ __device__ inline void reduce_against(const fl::Mod &md, uint32_t &v, uint32_t &
     // at most 64 terms: no intermediate fold needed
     v = fl::submod(v, fl::fold_pair(vh, vl, md), md.p);
     if (track) g = fl::submod(g, fl::fold_pair(gh, gl, md), md.p);
+}
+
+// Append the rows with flag set (one candidate row per wave) to a global
+// list: positions are claimed with one LDS atomic per row and one global
+// atomic per block.  All threads of the block must call it.
+__device__ void block_append(bool flag, uint32_t row, uint32_t *list, uint32_t *count) {
+    __shared__ uint32_t s_n, s_base;
+    const uint32_t lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    uint32_t local = 0;
+    if (flag && lane == 0) local = atomicAdd(&s_n, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(count, s_n) : 0;
+    __syncthreads();
+    if (flag && lane == 0) list[s_base + local] = row;
 }
 
 // Greedy basis of the panel rows in LDS: reduced form over the panel
@@ -173,37 +190,6 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
     __syncthreads();
 }
 
-// Append to S.list, in ascending order, the rows r >= next with pred(r),
-// scanning 1024-row windows while fewer than `want` rows are listed and a
-// whole window still fits the list (so no selected row is ever dropped);
-// `next` is advanced past the windows scanned.
-template <class Pred>
-__device__ void collect_rows(uint32_t rows, uint32_t &next, uint32_t want, GreedyLds &S, Pred pred) {
-    __shared__ uint32_t wave_cnt[kGreedyThreads / 64];
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) S.cnt = 0;
-    __syncthreads();
-    while (next < rows && S.cnt < want && S.cnt + blockDim.x <= kListCap) {
-        const uint32_t r = next + threadIdx.x;
-        const bool ok = r < rows && pred(r);
-        const uint64_t mask = __ballot(ok);
-        if (lane == 0) wave_cnt[wave] = __popcll(mask);
-        __syncthreads();
-        uint32_t before = S.cnt;
-        for (uint32_t w = 0; w < wave; w++) before += wave_cnt[w];
-        const uint64_t below = lane == 0 ? 0 : (mask & (~(uint64_t)0 >> (64 - lane)));
-        if (ok) S.list[before + __popcll(below)] = r;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t tot = S.cnt;
-            for (uint32_t w = 0; w < blockDim.x / 64; w++) tot += wave_cnt[w];
-            S.cnt = tot;
-        }
-        next += blockDim.x;
-        __syncthreads();
-    }
-}
-
 __device__ void save_raw(const GreedyLds &S, PanelState *ps) {
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
         ps->Bv[i] = S.Bv[i >> 6][i & 63];
@@ -246,72 +232,76 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
     }
 }
 
-// Panel step 1: greedy basis of the first (at least kProbe) remaining rows
-// that are nonzero on the panel.
+// Panel step 1: greedy basis of (at most kProbe of) the rows nonzero on the
+// panel, taken from the list built by step 0.
 __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
-    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
-    uint32_t pw, const uint32_t *__restrict__ nzflag, uint32_t *is_piv, PanelState *ps,
-    uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t c0, uint32_t pw,
+    const uint32_t *__restrict__ nzlist, const uint32_t *__restrict__ nzcount, uint32_t *is_piv,
+    PanelState *ps, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
+    const uint32_t n = *nzcount;
+    const uint32_t take = n < kProbe ? n : kProbe;
     if (threadIdx.x == 0) {
         S.kb = 0;
+        S.cnt = take;
         rank0_s = *d_rank;
         ps->nflag = 0;
-        ps->nupd = 0;
         ps->rank0 = rank0_s;
     }
+    if (threadIdx.x < take) S.list[threadIdx.x] = nzlist[threadIdx.x];
     __syncthreads();
     const uint32_t rank0 = rank0_s;
-    uint32_t next = 0;
-    collect_rows(rows, next, kProbe, S, [&](uint32_t r) { return nzflag[r] != 0; });
-    if (threadIdx.x == 0 && S.cnt > kProbe) S.cnt = kProbe;  // the check pass covers the rest
-    __syncthreads();
     greedy_rows(md, D, ld, c0, pw, S);
     save_raw(S, ps);
     finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
 }
 
-// Panel steps 0 and 2: every remaining row (restricted to rows with
-// in_flags[i] != 0 when in_flags is given) is reduced against the basis in
-// ps (step 2) or against nothing (step 0, use_basis = 0); rows left nonzero
-// are flagged in out_flags.  One wave per row, 4 rows per wave.
+// Panel steps 0 and 2.  Step 0 (use_basis = 0): every remaining row that is
+// nonzero on the panel goes to out_list.  Step 2: every row of in_list is
+// reduced against the probe basis in ps; rows left nonzero (outside its span)
+// go to out_list.  One wave per row, 8 rows per wave, 32 rows per block.
 __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const uint16_t *__restrict__ D,
                                                    uint64_t ld, uint32_t rows, uint32_t c0,
                                                    uint32_t pw, const uint32_t *__restrict__ is_piv,
-                                                   PanelState *ps, const uint32_t *__restrict__ in_flags,
-                                                   uint32_t *out_flags, int use_basis) {
+                                                   PanelState *ps, const uint32_t *__restrict__ in_list,
+                                                   const uint32_t *__restrict__ in_count,
+                                                   uint32_t *out_list, uint32_t *out_count, int use_basis) {
     __shared__ uint16_t Bv[64][64];
     __shared__ uint32_t Cc[64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t kb = use_basis ? ps->kb : 0;
+    const uint32_t n = in_list ? *in_count : rows;
+    if (blockIdx.x * 32 >= n) return;
     for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) Bv[i >> 6][i & 63] = ps->Bv[i];
     if (threadIdx.x < 64) Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
     __syncthreads();
-    for (uint32_t u = 0; u < 4; u++) {
-        const uint32_t i = (blockIdx.x * 4 + wave) * 4 + u;
-        if (i >= rows) break;
-        uint32_t flag = 0;
-        if (!is_piv[i] && kb < pw && (!in_flags || in_flags[i])) {
-            uint32_t v = lane < pw ? D[(uint64_t)i * ld + c0 + lane] : 0, g = 0;
-            if (kb) reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
-            flag = __ballot(v != 0) != 0 ? 1u : 0u;
+    for (uint32_t u = 0; u < 8; u++) {
+        const uint32_t idx = (blockIdx.x * 4 + wave) * 8 + u;
+        bool flag = false;
+        uint32_t i = 0;
+        if (idx < n) {
+            i = in_list ? in_list[idx] : idx;
+            if (!is_piv[i] && kb < pw) {
+                uint32_t v = lane < pw ? D[(uint64_t)i * ld + c0 + lane] : 0, g = 0;
+                if (kb) reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
+                flag = __ballot(v != 0) != 0;
+            }
         }
-        if (lane == 0) {
-            out_flags[i] = flag;
-            if (flag && use_basis) atomicAdd(&ps->nflag, 1u);
-        }
+        block_append(flag, i, out_list, out_count);
     }
+    if (use_basis && threadIdx.x == 0) __threadfence();
 }
 
 // Panel step 3 (only when some row was flagged): continue the greedy basis
-// with the flagged rows in row order and publish the final result.
+// with the flagged rows and publish the final result.
 __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
-    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t rows, uint32_t c0,
-    uint32_t pw, const uint32_t *__restrict__ flags, uint32_t *is_piv, PanelState *ps,
-    uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t c0, uint32_t pw,
+    const uint32_t *__restrict__ flist, const uint32_t *__restrict__ fcount, uint32_t *is_piv,
+    PanelState *ps, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
     __shared__ GreedyLds S;
-    if (ps->nflag == 0) return;
+    const uint32_t n = *fcount;
+    if (n == 0) return;
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
         S.Bv[i >> 6][i & 63] = ps->Bv[i];
         S.Bg[i >> 6][i & 63] = ps->Bg[i];
@@ -323,9 +313,11 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
     if (threadIdx.x == 0) S.kb = ps->kb;
     __syncthreads();
     const uint32_t rank0 = ps->rank0;
-    uint32_t next = 0;
-    while (next < rows && S.kb < pw) {
-        collect_rows(rows, next, kListCap, S, [&](uint32_t r) { return flags[r] != 0; });
+    for (uint32_t base = 0; base < n && S.kb < pw; base += kGreedyThreads) {
+        const uint32_t cnt = n - base < kGreedyThreads ? n - base : kGreedyThreads;
+        if (threadIdx.x < cnt) S.list[threadIdx.x] = flist[base + threadIdx.x];
+        if (threadIdx.x == 0) S.cnt = cnt;
+        __syncthreads();
         greedy_rows(md, D, ld, c0, pw, S);
     }
     save_raw(S, ps);
@@ -341,12 +333,16 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__res
                                                uint64_t ldu, int8_t *Uh, int8_t *Ul) {
     __shared__ uint16_t Gs[64 * 64];
     __shared__ uint16_t xs[64][256];
+    __shared__ uint32_t qs[64];
     const uint32_t k = ps->k;
     if (k == 0) return;
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) Gs[i] = ps->G[i];
+    if (threadIdx.x < 64) qs[threadIdx.x] = ps->Qs[threadIdx.x];
+    __syncthreads();
     const uint32_t c = c0 + blockIdx.x * 256 + threadIdx.x;
     const bool ok = c < cols;
-    for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)ps->Qs[s] * ld + c] : 0;
+#pragma unroll 8
+    for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)qs[s] * ld + c] : 0;
     __syncthreads();
     if (!ok) return;
     uint32_t hw[16], lw[16];
@@ -386,23 +382,32 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__res
 // L[i][t] = Dt[i][Ccol[t]] (0 for t >= k); with limb planes, also L as
 // int8 limbs (64 bytes per row) and the list of rows with a nonzero
 // multiplier (rows whose update is zero are skipped by the rank-k update).
+// One wave per row, 8 rows per wave.
 __global__ __launch_bounds__(256) void k_ech_gather_L(const uint16_t *__restrict__ D, uint64_t ld,
-                                                      uint32_t rows, PanelState *ps, uint16_t *L,
-                                                      uint32_t p, int8_t *Lh, int8_t *Ll,
-                                                      uint32_t *upd_rows) {
-    const uint32_t t = threadIdx.x & 63;
-    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= rows) return;
+                                                      uint32_t rows, const PanelState *__restrict__ ps,
+                                                      uint16_t *L, uint32_t p, int8_t *Lh, int8_t *Ll,
+                                                      uint32_t *upd_rows, uint32_t *upd_count) {
+    __shared__ uint32_t ccol[64];
+    const uint32_t t = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (blockIdx.x * 32 >= rows) return;
     const uint32_t k = ps->k;
-    const uint32_t x = t < k ? D[(uint64_t)i * ld + ps->Ccol[t]] : 0;
-    L[(uint64_t)i * 64 + t] = (uint16_t)x;
-    if (Lh) {
-        int h = 0, l = 0;
-        fl_split_limbs(x, p, h, l);
-        Lh[(uint64_t)i * 64 + t] = (int8_t)h;
-        Ll[(uint64_t)i * 64 + t] = (int8_t)l;
-        const uint64_t nz = __ballot(x != 0);
-        if (nz && t == 0) upd_rows[atomicAdd(&ps->nupd, 1u)] = i;
+    if (threadIdx.x < 64) ccol[threadIdx.x] = ps->Ccol[threadIdx.x];
+    __syncthreads();
+    for (uint32_t u = 0; u < 8; u++) {
+        const uint32_t i = (blockIdx.x * 4 + wave) * 8 + u;
+        bool nz = false;
+        if (i < rows) {
+            const uint32_t x = t < k ? D[(uint64_t)i * ld + ccol[t]] : 0;
+            L[(uint64_t)i * 64 + t] = (uint16_t)x;
+            if (Lh) {
+                int h = 0, l = 0;
+                fl_split_limbs(x, p, h, l);
+                Lh[(uint64_t)i * 64 + t] = (int8_t)h;
+                Ll[(uint64_t)i * 64 + t] = (int8_t)l;
+                nz = __ballot(x != 0) != 0;
+            }
+        }
+        if (Lh) block_append(nz, i, upd_rows, upd_count);
     }
 }
 
@@ -448,8 +453,9 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     const uint64_t ldu = ((uint64_t)cols + 63) & ~(uint64_t)63;
     EchWs t;
     t.is_piv = c.take<uint32_t>(rows ? rows : 1);
-    t.nzflag = c.take<uint32_t>(rows ? rows : 1);
-    t.flags = c.take<uint32_t>(rows ? rows : 1);
+    t.nzlist = c.take<uint32_t>(rows ? rows : 1);
+    t.flist = c.take<uint32_t>(rows ? rows : 1);
+    t.counts = c.take<uint32_t>(3 * (size_t)((cols + kPanel - 1) / kPanel + 1));
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
     t.ps = c.take<PanelState>(1);
     t.U = c.take<uint16_t>((size_t)64 * ldu);
@@ -459,14 +465,13 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     t.gemm_ws_bytes = 0;
     t.gemm_ws = nullptr;
     t.Lh = t.Ll = t.Uh = t.Ul = nullptr;
-    t.upd_rows = nullptr;
     if (mode == FL_MFMA_I8) {
         t.Lh = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
         t.Ll = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
         t.Uh = c.take<int8_t>(((size_t)cols + 256) * 64);
         t.Ul = c.take<int8_t>(((size_t)cols + 256) * 64);
-        t.upd_rows = c.take<uint32_t>(rows ? rows : 1);
     }
+    t.upd_rows = c.take<uint32_t>(rows ? rows : 1);
     if (e) *e = t;
     return c.off;
 }
@@ -498,31 +503,34 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
         return FL_ERR_WORKSPACE;
     }
     const fl::Mod md = fl::make_mod(p);
+    const uint32_t npanels = (cols + kPanel - 1) / kPanel;
     FL_HIP(fl_fill_u32(e.is_piv, 0, rows, stream));
     FL_HIP(fl_fill_u32(d_rank, 0, 1, stream));
-    const uint32_t npanels = (cols + kPanel - 1) / kPanel;
+    FL_HIP(fl_fill_u32(e.counts, 0, 3 * (size_t)npanels, stream));
+    const unsigned row_blocks = (rows + 31) / 32;  // 32 rows per block (8 per wave)
     for (uint32_t P = 0; P < npanels; P++) {
         const uint32_t c0 = P * kPanel;
         const uint32_t pw = cols - c0 < kPanel ? cols - c0 : kPanel;
+        uint32_t *n_nz = e.counts + 3 * P, *n_flag = n_nz + 1, *n_upd = n_nz + 2;
         FL_PROF("echelon.check", stream,
-                hipLaunchKernelGGL(k_ech_check, dim3((rows + 15) / 16), dim3(256), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.is_piv,
-                                   e.ps, (const uint32_t *)nullptr, e.nzflag, 0));
+                hipLaunchKernelGGL(k_ech_check, dim3(row_blocks), dim3(256), 0, stream, md, (const uint16_t *)Dt,
+                                   ldd, rows, c0, pw, (const uint32_t *)e.is_piv, e.ps,
+                                   (const uint32_t *)nullptr, (const uint32_t *)nullptr, e.nzlist, n_nz, 0));
         FL_LAUNCH_CHECK("k_ech_check<nonzero>");
         FL_PROF("echelon.probe", stream,
                 hipLaunchKernelGGL(k_ech_probe, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.nzflag,
-                                   e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
+                                   (const uint16_t *)Dt, ldd, c0, pw, (const uint32_t *)e.nzlist,
+                                   (const uint32_t *)n_nz, e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
         FL_LAUNCH_CHECK("k_ech_probe");
         FL_PROF("echelon.check", stream,
-                hipLaunchKernelGGL(k_ech_check, dim3((rows + 15) / 16), dim3(256), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.is_piv,
-                                   e.ps, (const uint32_t *)e.nzflag, e.flags, 1));
+                hipLaunchKernelGGL(k_ech_check, dim3(row_blocks), dim3(256), 0, stream, md, (const uint16_t *)Dt,
+                                   ldd, rows, c0, pw, (const uint32_t *)e.is_piv, e.ps,
+                                   (const uint32_t *)e.nzlist, (const uint32_t *)n_nz, e.flist, n_flag, 1));
         FL_LAUNCH_CHECK("k_ech_check<basis>");
         FL_PROF("echelon.merge", stream,
                 hipLaunchKernelGGL(k_ech_merge, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, rows, c0, pw, (const uint32_t *)e.flags,
-                                   e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
+                                   (const uint16_t *)Dt, ldd, c0, pw, (const uint32_t *)e.flist,
+                                   (const uint32_t *)n_flag, e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
         FL_LAUNCH_CHECK("k_ech_merge");
         const uint32_t ucols = cols - c0;
         FL_PROF("echelon.U", stream,
@@ -531,19 +539,20 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
                                    e.Uh, e.Ul));
         FL_LAUNCH_CHECK("k_ech_U");
         FL_PROF("echelon.L", stream,
-                hipLaunchKernelGGL(k_ech_gather_L, dim3((rows + 3) / 4), dim3(256), 0, stream,
-                                   (const uint16_t *)Dt, ldd, rows, e.ps, e.L, p, e.Lh, e.Ll, e.upd_rows));
+                hipLaunchKernelGGL(k_ech_gather_L, dim3(row_blocks), dim3(256), 0, stream, (const uint16_t *)Dt,
+                                   ldd, rows, (const PanelState *)e.ps, e.L, p, e.Lh, e.Ll, e.upd_rows, n_upd));
         FL_LAUNCH_CHECK("k_ech_gather_L");
         const uint32_t *kdev = &e.ps->k;
         if (mode == FL_MFMA_I8) {
-            FL_HIP(fl_mfma_rank64_planes(p, e.Lh, e.Ll, e.Uh, e.Ul, kdev, e.upd_rows, &e.ps->nupd, rows,
-                                         Dt + c0, ldd, ucols, stream, "echelon.mfma"));
+            FL_HIP(fl_mfma_rank64_planes(p, e.Lh, e.Ll, e.Uh, e.Ul, kdev, e.upd_rows, n_upd, rows, Dt + c0, ldd,
+                                         ucols, stream, "echelon.mfma"));
         } else {
             FL_HIP(fl_gemm_sub_plain(p, rows, ucols, 0, kdev, e.L, 64, e.U + c0, e.ldu, Dt + c0,
                                      ldd, stream, "echelon.plain"));
         }
-        hipLaunchKernelGGL(k_ech_setq, dim3((ucols + 255) / 256, kPanel), dim3(256), 0, stream, Dt,
-                           ldd, c0, cols, (const PanelState *)e.ps, (const uint16_t *)e.U, e.ldu);
+        FL_PROF("echelon.setq", stream,
+                hipLaunchKernelGGL(k_ech_setq, dim3((ucols + 255) / 256, kPanel), dim3(256), 0, stream, Dt,
+                                   ldd, c0, cols, (const PanelState *)e.ps, (const uint16_t *)e.U, e.ldu));
         FL_LAUNCH_CHECK("k_ech_setq");
     }
     const uint32_t mn = rows < cols ? rows : cols;
