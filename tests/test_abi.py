@@ -94,6 +94,45 @@ def test_dense_entry_points_reject_bad_arguments():
     assert lib.fl_matmul_sub(7, 4, 4, 4, ct.c_void_p(8), 4, ct.c_void_p(8), 2, ct.c_void_p(8), 4, 0, None, 0, None) == 1
     assert lib.fl_matmul_sub(7, 4, 4, 4, ct.c_void_p(8), 4, ct.c_void_p(8), 4, ct.c_void_p(8), 4, 1, None, 0, None) == 2
     info = fl.FlSplitInfo(p=7, m=10, n=12, ml_width=2, npiv=6, nB=6, mD=4, status=3)
-    assert lib.fl_trsm(ct.byref(info), ct.byref(fl.FlSplitOut()), ct.c_void_p(8), 8, None, 0, None) == 1
+    assert lib.fl_trsm(ct.byref(info), ct.byref(fl.FlSplitOut()), ct.c_void_p(8), 8, 0, None, 0, None) == 1
     info.status = 0
-    assert lib.fl_trsm(ct.byref(info), ct.byref(fl.FlSplitOut()), ct.c_void_p(8), 6, None, 0, None) == 1
+    assert lib.fl_trsm(ct.byref(info), ct.byref(fl.FlSplitOut()), ct.c_void_p(8), 6, 0, None, 0, None) == 1
+    assert lib.fl_trsm(ct.byref(info), ct.byref(fl.FlSplitOut()), ct.c_void_p(8), 8, 7, None, 0, None) == 1
+
+
+def _batch_csr(count=3):
+    arr = (fl.FlCsr * count)()
+    for i in range(count):
+        arr[i] = fl.FlCsr(100 + 50 * i, 150 + 60 * i, 1000 * (i + 1), ct.c_void_p(8), ct.c_void_p(8),
+                          ct.c_void_p(8))
+    return arr
+
+
+def test_batch_split_workspace_is_host_computable():
+    lib = fl.load()
+    arr = _batch_csr()
+    w1, w2, w4 = (lib.fl_batch_split_workspace(arr, 3, w) for w in (1, 2, 4))
+    assert 0 < w1 < w2 < w4
+    assert lib.fl_batch_split_workspace(arr, 0, 2) == 0
+
+
+def test_batch_host_argument_errors():
+    lib = fl.load()
+    arr = _batch_csr()
+    h = ct.c_void_p()
+    need = lib.fl_batch_split_workspace(arr, 3, 2)
+    cfg = fl.FlBatchConfig(2, 4, 0)
+    ARG, WS = 1, 2
+    assert lib.fl_batch_plan(arr, 0, 65521, ct.byref(cfg), ct.c_void_p(256), need, ct.byref(h), None) == ARG
+    assert lib.fl_batch_plan(arr, 3, 1, ct.byref(cfg), ct.c_void_p(256), need, ct.byref(h), None) == ARG
+    bad_w = fl.FlBatchConfig(3, 4, 0)
+    assert lib.fl_batch_plan(arr, 3, 65521, ct.byref(bad_w), ct.c_void_p(256), need, ct.byref(h), None) == ARG
+    bad_s = fl.FlBatchConfig(2, 17, 0)
+    assert lib.fl_batch_plan(arr, 3, 65521, ct.byref(bad_s), ct.c_void_p(256), need, ct.byref(h), None) == ARG
+    assert lib.fl_batch_plan(arr, 3, 65521, ct.byref(cfg), ct.c_void_p(256), need - 1, ct.byref(h), None) == WS
+    assert lib.fl_batch_plan(arr, 3, 65521, ct.byref(cfg), None, need, ct.byref(h), None) == WS
+    assert not h.value
+    assert lib.fl_batch_run(None, ct.c_void_p(256), 1 << 20, None) == ARG
+    assert lib.fl_batch_graph_launch(None, None) == ARG
+    assert lib.fl_batch_run_workspace(None) == 0
+    lib.fl_batch_free(None)
