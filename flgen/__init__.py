@@ -28,8 +28,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["CONFIGS", "fl_matrix", "random_sparse", "dense_planted_rank",
-           "csr_to_dense", "config_matrix"]
+__all__ = ["CONFIGS", "BATCH_CONFIGS", "fl_matrix", "random_sparse", "dense_planted_rank",
+           "csr_to_dense", "config_matrix", "batch_matrices", "config_batch"]
 
 # Sizes of the workloads (rows x cols, pivot rows, planted rank of D, density).
 CONFIGS = {
@@ -41,6 +41,13 @@ CONFIGS = {
     "c5": dict(m=120000, n=150000, npiv=100000, rank_d=15000, density=0.015),
 }
 BASE_SEED = 160206097
+
+# Batches of F4-step matrices of uneven sizes: rows log-uniform in [m_lo,
+# m_hi], cols U[1.3, 1.6] x rows, pivot rows U[0.70, 0.85] x rows, density
+# U[2%, 15%], planted rank U[0.5, 0.95] x min(rows of D, cols of D).
+BATCH_CONFIGS = {
+    "c4": dict(count=256, m_lo=500, m_hi=20000),
+}
 
 
 def _segment_arange(lengths: np.ndarray) -> np.ndarray:
@@ -349,3 +356,28 @@ def csr_to_dense(mat: dict) -> np.ndarray:
     for i in range(m):
         out[i, mat["col"][rp[i]:rp[i + 1]]] = mat["val"][rp[i]:rp[i + 1]]
     return out
+
+
+def batch_matrices(count: int, m_lo: int, m_hi: int, p: int, seed: int) -> list:
+    """``count`` planted FL matrices with the batch size distribution (see
+    ``BATCH_CONFIGS``); matrix i is drawn from seed ``seed ^ (i << 32)``."""
+    out = []
+    for i in range(count):
+        s = seed ^ (i << 32)
+        rng = np.random.default_rng(s)
+        m = int(round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi)))))
+        n = int(round(rng.uniform(1.3, 1.6) * m))
+        npiv = int(round(rng.uniform(0.70, 0.85) * m))
+        density = float(rng.uniform(0.02, 0.15))
+        mD, nB = m - npiv, n - npiv
+        r = int(np.floor(rng.uniform(0.5, 0.95) * min(mD, nB)))
+        out.append(fl_matrix(m=m, n=n, npiv=npiv, rank_d=r, density=density, p=p, seed=s + 1))
+    return out
+
+
+def config_batch(name: str, p: int = 65521, seed: int | None = None) -> list:
+    """The named batch workload (``c4``) with its default seed."""
+    cfg = BATCH_CONFIGS[name]
+    if seed is None:
+        seed = BASE_SEED + int(name[1:])
+    return batch_matrices(p=p, seed=seed, **cfg)

@@ -220,6 +220,100 @@ fl_status fl_matmul_sub(uint32_t p, uint32_t M, uint32_t N, uint32_t K, const ui
                         hipStream_t stream);
 size_t fl_matmul_sub_workspace(uint32_t M, uint32_t N, uint32_t K, fl_mode mode);
 
+/* ---- batched form -------------------------------------------------------------
+ * An F4 run produces a sequence of matrices of very uneven sizes (Sec. 6.2
+ * and its tables); one small matrix cannot fill the GPU, and Sec. 5.2 found
+ * the cost of scheduling many small tasks decisive on CPUs.  The batched form
+ * reduces `count` independent matrices M_0..M_{count-1} over one F_p:
+ *
+ *   fl_batch_plan   splits every matrix (fl_split) on `stream`, with ONE host
+ *                   synchronisation for the whole batch, and returns a host
+ *                   plan object that fixes every size, the arena layout and
+ *                   each matrix's arithmetic form;
+ *   fl_batch_run    enqueues steps 2-5 of every matrix (fl_trsm ..
+ *                   read-off) with no host synchronisation, spread over
+ *                   `streams` concurrent branches forked from and joined
+ *                   back into `stream`; capturable;
+ *   fl_batch_graph_build / fl_batch_graph_launch
+ *                   capture fl_batch_run into a hipGraph once and replay it
+ *                   (each replay recomputes every result from the split);
+ *   fl_batch_autotune
+ *                   times candidate configurations (multiline width, branch
+ *                   count, MFMA size threshold) on the given batch and
+ *                   remembers the best one for batches of the same shape.
+ *
+ * Memory: the caller allocates two device arenas: the split arena
+ * (fl_batch_split_workspace, known from the CSR shapes alone; it holds every
+ * matrix's fl_split outputs and must stay alive as long as the plan) and the
+ * run arena (fl_batch_run_workspace(plan): dense X and Dt of every matrix,
+ * per-branch workspaces, the CSR outputs at their upper bound
+ * (npiv + min(mD, nB)) * (nB + 1) entries, and the summary table).  Both are
+ * 256-byte aligned device memory.  The plan object itself is host memory
+ * owned by the library until fl_batch_free.
+ *
+ * Results: after the run (or a graph replay) completes, fl_batch_summary's
+ * device table holds per matrix {rank of M, nnz of RREF(M), status, 0}
+ * (uint64 each), and fl_batch_matrix gives the device pointers of matrix i's
+ * CSR of RREF(M) (same canonical form as fl_rref_to_csr).  A matrix whose
+ * split found a data error is skipped by the run; its status is the error
+ * code and its rank and nnz are 0.  Results are bit-identical to the
+ * single-matrix entry points for every configuration. */
+typedef struct {
+    uint32_t ml_width;         /* 1, 2, 4 or 8; 0 = default (2) */
+    uint32_t streams;          /* concurrent branches, 1..16; 0 = default (8) */
+    uint64_t mfma_min_entries; /* a matrix runs its dense steps (TRSM band updates,
+                                  C X, echelon updates, second pass) on int8 MFMA
+                                  when (npiv + mD) * nB >= this; 0 = default (2^22);
+                                  UINT64_MAX = always the VALU form */
+} fl_batch_config;
+
+typedef struct fl_batch fl_batch;   /* opaque host object */
+
+typedef struct {
+    uint64_t *row_ptr;   /* [rank_max + 1], device */
+    uint32_t *col;       /* [nnz_cap], device */
+    uint16_t *val;       /* [nnz_cap], device */
+    uint64_t nnz_cap;
+    uint32_t rank_max;   /* npiv + min(mD, nB) */
+    uint32_t npiv, mD, nB;
+    fl_mode mode;        /* arithmetic form chosen for this matrix */
+    fl_status status;    /* the matrix's split status */
+} fl_batch_matrix;
+
+/* Bytes of the split arena for this batch at multiline width ml_width. */
+size_t fl_batch_split_workspace(const fl_csr *Ms, uint32_t count, uint32_t ml_width);
+/* cfg may be NULL: the configuration fl_batch_autotune found for a batch of
+ * this shape, else the defaults.  Errors: FL_ERR_ARG (bad arguments, count
+ * 0), FL_ERR_WORKSPACE (split arena too small), FL_ERR_HIP.  Per-matrix data
+ * errors do not fail the plan (see fl_batch_matrix.status). */
+fl_status fl_batch_plan(const fl_csr *Ms, uint32_t count, uint32_t p, const fl_batch_config *cfg,
+                        void *split_arena, size_t split_bytes, fl_batch **plan,
+                        hipStream_t stream);
+size_t fl_batch_run_workspace(const fl_batch *plan);
+fl_status fl_batch_run(fl_batch *plan, void *run_arena, size_t run_bytes, hipStream_t stream);
+/* Captures fl_batch_run(plan, run_arena, ...) on `stream` into a graph kept in
+ * the plan (replacing an earlier one).  Nothing is executed.  With the null
+ * stream (which cannot be captured) the capture uses a stream of the plan,
+ * after synchronising the null stream. */
+fl_status fl_batch_graph_build(fl_batch *plan, void *run_arena, size_t run_bytes,
+                               hipStream_t stream);
+fl_status fl_batch_graph_launch(fl_batch *plan, hipStream_t stream);
+/* Device pointer of the summary table (count x 4 uint64) in run_arena. */
+uint64_t *fl_batch_summary(const fl_batch *plan, void *run_arena);
+fl_status fl_batch_matrix_info(const fl_batch *plan, uint32_t i, void *run_arena,
+                               fl_batch_matrix *out);
+void fl_batch_get_config(const fl_batch *plan, fl_batch_config *out);
+/* Runs each candidate (plan + run, eagerly, timed with HIP events after one
+ * warm-up) in the given arenas; candidates that do not fit are skipped.
+ * Writes the fastest to *best (and its time to *best_ms) and records it for
+ * fl_batch_plan(cfg = NULL) on batches of the same shape (count, p, and the
+ * rounded log2 of the total nonzeros and of the largest row count).  The
+ * split arena must be sized for ml_width 4. */
+fl_status fl_batch_autotune(const fl_csr *Ms, uint32_t count, uint32_t p, void *split_arena,
+                            size_t split_bytes, void *run_arena, size_t run_bytes,
+                            fl_batch_config *best, double *best_ms, hipStream_t stream);
+void fl_batch_free(fl_batch *plan);
+
 /* ---- helpers ----------------------------------------------------------------- */
 const char *fl_status_string(fl_status s);
 const char *fl_last_error(void);   /* thread-local; "" if none */

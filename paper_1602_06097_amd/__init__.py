@@ -24,7 +24,8 @@ import torch
 
 __all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd",
            "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp", "prof_report",
-           "version", "Split", "Echelon"]
+           "version", "Split", "Echelon", "Batch", "batch_plan", "batch_run", "batch_graph_build",
+           "batch_graph_launch", "batch_results", "batch_autotune", "batch_config"]
 
 FL_PLAIN, FL_MFMA_I8 = 0, 1
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +57,15 @@ class FlSplitInfo(ct.Structure):
                 ("nB", c_u32), ("mD", c_u32), ("status", c_u32), ("nnz", c_u64), ("nnzA", c_u64),
                 ("nnzB", c_u64), ("nnzC", c_u64), ("nnzD", c_u64), ("lenA", c_u64),
                 ("lenC", c_u64)]
+
+
+class FlBatchConfig(ct.Structure):
+    _fields_ = [("ml_width", c_u32), ("streams", c_u32), ("mfma_min_entries", c_u64)]
+
+
+class FlBatchMatrix(ct.Structure):
+    _fields_ = [("row_ptr", c_vp), ("col", c_vp), ("val", c_vp), ("nnz_cap", c_u64), ("rank_max", c_u32),
+                ("npiv", c_u32), ("mD", c_u32), ("nB", c_u32), ("mode", ct.c_int), ("status", ct.c_int)]
 
 
 def load():
@@ -94,6 +104,18 @@ def load():
         "fl_last_error": (ct.c_char_p, []),
         "fl_version": (ct.c_char_p, []),
         "fl_check_modp": (ct.c_int, [P(c_u32), c_u32, c_vp, c_vp]),
+        "fl_batch_split_workspace": (c_sz, [P(FlCsr), c_u32, c_u32]),
+        "fl_batch_plan": (ct.c_int, [P(FlCsr), c_u32, c_u32, P(FlBatchConfig), c_vp, c_sz, P(c_vp), c_vp]),
+        "fl_batch_run_workspace": (c_sz, [c_vp]),
+        "fl_batch_run": (ct.c_int, [c_vp, c_vp, c_sz, c_vp]),
+        "fl_batch_graph_build": (ct.c_int, [c_vp, c_vp, c_sz, c_vp]),
+        "fl_batch_graph_launch": (ct.c_int, [c_vp, c_vp]),
+        "fl_batch_summary": (c_vp, [c_vp, c_vp]),
+        "fl_batch_matrix_info": (ct.c_int, [c_vp, c_u32, c_vp, P(FlBatchMatrix)]),
+        "fl_batch_get_config": (None, [c_vp, P(FlBatchConfig)]),
+        "fl_batch_autotune": (ct.c_int, [P(FlCsr), c_u32, c_u32, c_vp, c_sz, c_vp, c_sz, P(FlBatchConfig),
+                                         P(ct.c_double), c_vp]),
+        "fl_batch_free": (None, [c_vp]),
         "fl_prof_enable": (None, [ct.c_int]),
         "fl_prof_reset": (None, []),
         "fl_prof_report": (c_sz, [ct.c_char_p, c_sz]),
@@ -280,6 +302,128 @@ def fl_reduce(row_ptr, col, val, m: int, n: int, p: int, mode: int = FL_PLAIN, m
     rref(sp, X, Dt, ech, mode)
     res.update(echelon=ech, Xp=X, RD=Dt, rref=rref_to_csr(sp, X, Dt, ech))
     return res
+
+
+class Batch:
+    """A planned batch: the library's plan object plus the two device arenas
+    (the split arena must outlive the plan; the run arena holds every
+    result)."""
+
+    def __init__(self, handle, count, split_arena, run_arena, inputs):
+        self.handle, self.count = handle, count
+        self.split_arena, self.run_arena, self._inputs = split_arena, run_arena, inputs
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fl_batch_free(self.handle)
+            self.handle = None
+
+
+def _csr_array(mats):
+    arr = (FlCsr * len(mats))()
+    for i, (rp, ci, vv, m, n) in enumerate(mats):
+        arr[i] = FlCsr(m, n, int(ci.numel()) if m else 0, _ptr(rp), _ptr(ci), _ptr(vv))
+    return arr
+
+
+def _config(cfg):
+    if cfg is None:
+        return None
+    return FlBatchConfig(int(cfg.get("ml_width", 0)), int(cfg.get("streams", 0)),
+                         int(cfg.get("mfma_min_entries", 0)))
+
+
+def batch_plan(mats, p: int, config: dict | None = None) -> Batch:
+    """Plan a batch of device CSR matrices [(row_ptr, col, val, m, n), ...]:
+    splits all of them with one synchronisation.  config: dict with
+    ml_width / streams / mfma_min_entries (0 = default); None = the autotuned
+    configuration for batches of this shape, else the defaults."""
+    lib = load()
+    arr = _csr_array(mats)
+    cfg = _config(config)
+    w_alloc = (cfg.ml_width or 2) if cfg is not None else 4
+    split_arena = _ws(lib.fl_batch_split_workspace(arr, len(mats), w_alloc))
+    h = c_vp()
+    st = lib.fl_batch_plan(arr, len(mats), p, ct.byref(cfg) if cfg is not None else None,
+                           _ptr(split_arena), split_arena.numel(), ct.byref(h), _stream())
+    _check(st, "fl_batch_plan")
+    run_arena = _ws(lib.fl_batch_run_workspace(h))
+    return Batch(h, len(mats), split_arena, run_arena, list(mats))
+
+
+def batch_run(b: Batch) -> None:
+    lib = load()
+    _check(lib.fl_batch_run(b.handle, _ptr(b.run_arena), b.run_arena.numel(), _stream()), "fl_batch_run")
+
+
+def batch_graph_build(b: Batch) -> None:
+    lib = load()
+    _check(lib.fl_batch_graph_build(b.handle, _ptr(b.run_arena), b.run_arena.numel(), _stream()),
+           "fl_batch_graph_build")
+
+
+def batch_graph_launch(b: Batch) -> None:
+    lib = load()
+    _check(lib.fl_batch_graph_launch(b.handle, _stream()), "fl_batch_graph_launch")
+
+
+def batch_config(b: Batch) -> dict:
+    lib = load()
+    c = FlBatchConfig()
+    lib.fl_batch_get_config(b.handle, ct.byref(c))
+    return dict(ml_width=c.ml_width, streams=c.streams, mfma_min_entries=c.mfma_min_entries)
+
+
+def batch_results(b: Batch) -> list:
+    """Per matrix: dict(rank, nnz, status, mode, row_ptr, col, val) with the
+    CSR of RREF(M) as views of the run arena (synchronises the stream)."""
+    lib = load()
+    torch.cuda.current_stream().synchronize()
+    base = b.run_arena.data_ptr()
+    sp = lib.fl_batch_summary(b.handle, _ptr(b.run_arena))
+    off = sp - base
+    summ = b.run_arena[off:off + 32 * b.count].view(torch.int64).view(b.count, 4).cpu().numpy()
+    out = []
+    for i in range(b.count):
+        info = FlBatchMatrix()
+        _check(lib.fl_batch_matrix_info(b.handle, i, _ptr(b.run_arena), ct.byref(info)),
+               "fl_batch_matrix_info")
+        rank, nnz, status = int(summ[i, 0]), int(summ[i, 1]), int(summ[i, 2])
+        d = dict(rank=rank, nnz=nnz, status=status, mode=int(info.mode), npiv=info.npiv, mD=info.mD,
+                 nB=info.nB)
+        if info.row_ptr:
+            o = info.row_ptr - base
+            d["row_ptr"] = b.run_arena[o:o + 8 * (rank + 1)].view(torch.int64)
+            o = info.col - base
+            d["col"] = b.run_arena[o:o + 4 * nnz].view(torch.int32)
+            o = info.val - base
+            d["val"] = b.run_arena[o:o + 2 * nnz].view(torch.int16)
+        out.append(d)
+    return out
+
+
+def batch_autotune(mats, p: int, run_bytes: int | None = None):
+    """Time candidate configurations on this batch; returns (config, ms).
+    The choice is remembered for batch_plan(config=None) on batches of the
+    same shape."""
+    lib = load()
+    arr = _csr_array(mats)
+    split_arena = _ws(lib.fl_batch_split_workspace(arr, len(mats), 4))
+    if run_bytes is None:
+        # the largest run arena among the candidates: plan the all-MFMA,
+        # 16-branch configuration to size it
+        h = c_vp()
+        cfg = FlBatchConfig(2, 16, 1)
+        _check(lib.fl_batch_plan(arr, len(mats), p, ct.byref(cfg), _ptr(split_arena), split_arena.numel(),
+                                 ct.byref(h), _stream()), "fl_batch_plan")
+        run_bytes = int(lib.fl_batch_run_workspace(h) * 1.25)
+        lib.fl_batch_free(h)
+    run_arena = _ws(run_bytes)
+    best, ms = FlBatchConfig(), ct.c_double(0)
+    st = lib.fl_batch_autotune(arr, len(mats), p, _ptr(split_arena), split_arena.numel(), _ptr(run_arena),
+                               run_arena.numel(), ct.byref(best), ct.byref(ms), _stream())
+    _check(st, "fl_batch_autotune")
+    return dict(ml_width=best.ml_width, streams=best.streams, mfma_min_entries=best.mfma_min_entries), ms.value
 
 
 def prof_report() -> dict:

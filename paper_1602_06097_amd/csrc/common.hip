@@ -259,6 +259,12 @@ void fl_prof_end(int tok, hipStream_t s) {
 
 extern "C" void fl_prof_enable(int on) { g_prof_on = on != 0; }
 
+bool fl_prof_set(bool on) {
+    const bool old = g_prof_on;
+    g_prof_on = on;
+    return old;
+}
+
 extern "C" void fl_prof_reset(void) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : g_prof) {

@@ -128,6 +128,8 @@ hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t co
 // or -1 when profiling is off.
 int fl_prof_begin(const char *site, hipStream_t s);
 void fl_prof_end(int tok, hipStream_t s);
+// Switches the profiler on or off; returns the previous state.
+bool fl_prof_set(bool on);
 
 // Bracket one launch statement with profiler events (no-op when disabled).
 #define FL_PROF(site, stream, ...)                                      \
@@ -171,3 +173,17 @@ __device__ __forceinline__ void fl_split_limbs(uint32_t x, uint32_t p, int &h, i
     h = (r + 128) >> 8;  // arithmetic shift: floor
     l = r - (h << 8);
 }
+
+// fl_split without its sync: enqueue everything (size words to dinfo_out, 8
+// u64, when non-NULL), then turn the synced size words into fl_split_info.
+fl_status fl_split_enqueue(const fl_csr *M, uint32_t p, uint32_t ml_width, const fl_split_out *o,
+                           void *ws, size_t ws_bytes, uint64_t *dinfo_out, hipStream_t stream);
+fl_status fl_split_finish(const fl_csr *M, uint32_t p, uint32_t ml_width, const uint64_t hinf[8],
+                          fl_split_info *h_info);
+// fl_rref_csr_size + fl_rref_to_csr without a host sync; col/val hold the
+// upper bound (npiv + min(mD, nB)) * (nB + 1) entries.
+fl_status fl_rref_csr_enqueue(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                              uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                              const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
+                              uint32_t *col, uint16_t *val, void *ws, size_t ws_bytes,
+                              hipStream_t stream);

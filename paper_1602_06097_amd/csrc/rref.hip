@@ -11,6 +11,8 @@
 //                      position in pivot-column order; exclusive scan
 //   k_csr_emit         one wave per output row: pivot 1, then the nonzeros of
 //                      the X' or R_D row (both ascending in original order).
+#include <string>
+
 #include "fl_internal.h"
 
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
@@ -305,15 +307,16 @@ extern "C" size_t fl_rref_csr_workspace(const fl_split_info *info) {
     return csr_layout(info->npiv, maxr, nullptr, nullptr);
 }
 
-extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_out *s,
-                                      const uint16_t *Xp, uint64_t ldx, const uint16_t *RD,
-                                      uint64_t ldd, const uint32_t *d_rank,
-                                      const uint32_t *d_pivcol, uint64_t *row_ptr,
-                                      uint32_t *h_rank, uint64_t *h_nnz, void *ws, size_t ws_bytes,
-                                      hipStream_t stream) {
+// Row counts of RREF(M) and their exclusive scan into row_ptr (device), no
+// sync; c.dinfo[0] receives the total.
+static fl_status csr_count_scan(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                                uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                                const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
+                                void *ws, size_t ws_bytes, const char *who, CsrWs *cout,
+                                hipStream_t stream) {
     fl_status st = fl_check_split(info, s);
     if (st != FL_OK) return st;
-    FL_ARG(row_ptr && h_rank && h_nnz && d_rank, "fl_rref_csr_size: NULL argument");
+    FL_ARG(row_ptr && d_rank, "fl_rref_csr_size: NULL argument");
     const uint32_t npiv = info->npiv, nB = info->nB;
     const uint32_t maxr = info->mD < nB ? info->mD : nB;
     FL_ARG(npiv == 0 || nB == 0 || (Xp && ldx >= nB), "fl_rref_csr_size: bad X'");
@@ -321,7 +324,7 @@ extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_
     CsrWs c;
     size_t need = csr_layout(npiv, maxr, ws, &c);
     if (!ws || ws_bytes < need) {
-        fl_set_error("fl_rref_csr_size: workspace too small");
+        fl_set_error((std::string(who) + ": workspace too small").c_str());
         return FL_ERR_WORKSPACE;
     }
     const size_t nrows_max = (size_t)npiv + maxr;
@@ -335,14 +338,45 @@ extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_
     // rows beyond npiv + r have count 0, so the scan over the upper bound
     // yields row_ptr[rank] = nnz for every rank
     FL_HIP(fl_exclusive_scan_u64(c.cnt, row_ptr, nrows_max + 1, c.scantmp, c.dinfo, stream));
+    *cout = c;
+    return FL_OK;
+}
+
+extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_out *s,
+                                      const uint16_t *Xp, uint64_t ldx, const uint16_t *RD,
+                                      uint64_t ldd, const uint32_t *d_rank,
+                                      const uint32_t *d_pivcol, uint64_t *row_ptr,
+                                      uint32_t *h_rank, uint64_t *h_nnz, void *ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+    FL_ARG(h_rank && h_nnz, "fl_rref_csr_size: NULL argument");
+    CsrWs c;
+    fl_status st = csr_count_scan(info, s, Xp, ldx, RD, ldd, d_rank, d_pivcol, row_ptr, ws, ws_bytes,
+                                  "fl_rref_csr_size", &c, stream);
+    if (st != FL_OK) return st;
+    const uint32_t maxr = info->mD < info->nB ? info->mD : info->nB;
     uint32_t r = 0;
     uint64_t tot = 0;
     if (maxr) FL_HIP(hipMemcpyAsync(&r, d_rank, sizeof(r), hipMemcpyDeviceToHost, stream));
     FL_HIP(hipMemcpyAsync(&tot, c.dinfo, sizeof(tot), hipMemcpyDeviceToHost, stream));
     FL_HIP(hipStreamSynchronize(stream));
-    *h_rank = npiv + r;
+    *h_rank = info->npiv + r;
     *h_nnz = tot;
     return FL_OK;
+}
+
+// Count, scan and emit without a host sync: col/val must hold the upper bound
+// (npiv + min(mD, nB)) * (nB + 1) entries.
+fl_status fl_rref_csr_enqueue(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                              uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                              const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
+                              uint32_t *col, uint16_t *val, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    CsrWs c;
+    fl_status st = csr_count_scan(info, s, Xp, ldx, RD, ldd, d_rank, d_pivcol, row_ptr, ws, ws_bytes,
+                                  "fl_rref_csr_enqueue", &c, stream);
+    if (st != FL_OK) return st;
+    return fl_rref_to_csr(info, s, Xp, ldx, RD, ldd, d_rank, d_pivcol, row_ptr, col, val, ws, ws_bytes,
+                          stream);
 }
 
 extern "C" fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_out *s,

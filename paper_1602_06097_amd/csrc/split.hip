@@ -486,10 +486,13 @@ extern "C" size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint3
     return split_ws_layout(m, n, ml_width, nullptr, nullptr, nullptr);
 }
 
-extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
-                              const fl_split_out *o, fl_split_info *h_info, void *ws,
-                              size_t ws_bytes, hipStream_t stream) {
-    FL_ARG(M && o && h_info, "fl_split: NULL argument");
+// Everything of fl_split but the final sync: validation, permutations, A, B,
+// C, D.  The eight size words (see k_info) go to dinfo_out when it is
+// non-NULL, else to the workspace.  With m == 0 nothing but col_perm is
+// written and the size words are left alone.
+fl_status fl_split_enqueue(const fl_csr *M, uint32_t p, uint32_t ml_width, const fl_split_out *o,
+                           void *ws, size_t ws_bytes, uint64_t *dinfo_out, hipStream_t stream) {
+    FL_ARG(M && o, "fl_split: NULL argument");
     FL_ARG(p >= 2 && p <= 65521, "fl_split: p must be in [2, 65521]");
     FL_ARG(ml_width == 1 || ml_width == 2 || ml_width == 4 || ml_width == 8,
            "fl_split: ml_width must be 1, 2, 4 or 8");
@@ -510,15 +513,12 @@ extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
         fl_set_error("fl_split: workspace too small");
         return FL_ERR_WORKSPACE;
     }
-    fl_split_info info = {};
-    info.p = p; info.m = m; info.n = n; info.ml_width = w; info.nnz = M->nnz;
+    if (dinfo_out) dinfo = dinfo_out;
     if (m == 0) {  // no rows: no pivots, every column is a non-pivot column
-        info.nB = n;
         if (n) {
             hipLaunchKernelGGL(k_iota, dim3(blocks(n, 256)), dim3(256), 0, stream, n, o->col_perm);
             FL_LAUNCH_CHECK("k_iota");
         }
-        *h_info = info;
         return FL_OK;
     }
     const uint64_t *rp = M->row_ptr;
@@ -569,9 +569,19 @@ extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
     hipLaunchKernelGGL(k_info, dim3(1), dim3(1), 0, stream, m, n, w, d, dinfo);
     FL_LAUNCH_CHECK("k_info");
 
-    uint64_t hinf[8];
-    FL_HIP(hipMemcpyAsync(hinf, dinfo, sizeof(hinf), hipMemcpyDeviceToHost, stream));
-    FL_HIP(hipStreamSynchronize(stream));
+    return FL_OK;
+}
+
+// Host side of fl_split after the sync: the size words -> h_info.
+fl_status fl_split_finish(const fl_csr *M, uint32_t p, uint32_t ml_width, const uint64_t hinf[8],
+                          fl_split_info *h_info) {
+    fl_split_info info = {};
+    info.p = p; info.m = M->rows; info.n = M->cols; info.ml_width = ml_width; info.nnz = M->nnz;
+    if (M->rows == 0) {
+        info.nB = M->cols;
+        *h_info = info;
+        return FL_OK;
+    }
     if (hinf[0] != ~(uint64_t)0) {
         static const fl_status codes[4] = {FL_ERR_DATA_ROWPTR, FL_ERR_DATA_COL_RANGE,
                                            FL_ERR_DATA_COL_ORDER, FL_ERR_DATA_VALUE};
@@ -582,8 +592,8 @@ extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
         return st;
     }
     info.npiv = (uint32_t)hinf[1];
-    info.nB = n - info.npiv;
-    info.mD = m - info.npiv;
+    info.nB = info.n - info.npiv;
+    info.mD = info.m - info.npiv;
     info.nnzB = hinf[2];
     info.nnzD = hinf[3];
     info.lenA = hinf[4];
@@ -592,4 +602,21 @@ extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
     info.nnzC = hinf[7];
     *h_info = info;
     return FL_OK;
+}
+
+extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
+                              const fl_split_out *o, fl_split_info *h_info, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+    FL_ARG(M && o && h_info, "fl_split: NULL argument");
+    fl_status st = fl_split_enqueue(M, p, ml_width, o, ws, ws_bytes, nullptr, stream);
+    if (st != FL_OK) return st;
+    uint64_t hinf[8] = {~(uint64_t)0, 0, 0, 0, 0, 0, 0, 0};
+    if (M->rows) {
+        SplitDev d;
+        uint64_t *dinfo;
+        split_ws_layout(M->rows, M->cols, ml_width, ws, &d, &dinfo);
+        FL_HIP(hipMemcpyAsync(hinf, dinfo, sizeof(hinf), hipMemcpyDeviceToHost, stream));
+        FL_HIP(hipStreamSynchronize(stream));
+    }
+    return fl_split_finish(M, p, ml_width, hinf, h_info);
 }
