@@ -31,6 +31,12 @@
 namespace {
 
 constexpr uint32_t kMaxStreams = 16;
+
+#define FL_CHECK_ST(call)                      \
+    do {                                       \
+        fl_status st_ = (call);                \
+        if (st_ != FL_OK) return st_;          \
+    } while (0)
 constexpr uint64_t kDefaultMfmaMin = (uint64_t)1 << 22;
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -115,7 +121,8 @@ struct MatrixRun {
     fl_mode mode;
     uint32_t branch;
     uint64_t ldx, ldd, maxr, nnz_cap;
-    uint64_t off_X, off_Dt, off_rank, off_piv, off_rowptr, off_col, off_val;
+    uint64_t off_X, off_Dt, off_rank, off_piv, off_rowptr, off_col, off_val, off_ws, ws_bytes;
+    uint32_t nblk, npanels;  // TRSM blocks and echelon panels
     double cost;  // rough work estimate, for dealing matrices to branches
 };
 
@@ -155,8 +162,11 @@ struct fl_batch {
     uint32_t count = 0, p = 0;
     fl_batch_config cfg = {};
     std::vector<MatrixRun> mats;
-    std::vector<uint64_t> ws_off, ws_bytes;  // per branch
     uint64_t summary_off = 0, run_bytes = 0;
+    // device tables of the stepped loops (TRSM blocks, echelon panels)
+    uint64_t off_ttask = 0, off_tids = 0, off_tpre = 0;  // 3 lists each: all, mfma, plain
+    uint64_t off_etask = 0, off_eids = 0, off_epre_rows = 0, off_epre = 0;
+    uint32_t max_blk = 0, max_panels = 0;
     hipStream_t streams[kMaxStreams] = {};
     hipStream_t capture = nullptr;  // graph capture when the caller passes the null stream
     hipEvent_t fork = nullptr, join[kMaxStreams] = {};
@@ -177,12 +187,14 @@ fl_status batch_init_streams(fl_batch *b) {
 }
 
 // Lays out the run arena from the split sizes and deals matrices to branches.
+// Every matrix has its own workspace: the stepped loops keep the state of all
+// matrices alive at once.
 void batch_layout(fl_batch *b) {
     const uint32_t S = b->cfg.streams;
-    std::vector<uint64_t> ws_need(S, 0);
     std::vector<double> load(S, 0.0);
     std::vector<uint32_t> order(b->count);
     for (uint32_t i = 0; i < b->count; i++) order[i] = i;
+    b->max_blk = b->max_panels = 0;
     for (auto &mr : b->mats) {
         const fl_split_info &f = mr.info;
         mr.maxr = std::min(f.mD, f.nB);
@@ -191,6 +203,11 @@ void batch_layout(fl_batch *b) {
                   (double)f.npiv * f.nB * (double)mr.maxr * 0.25 + (double)f.nnz;
         const uint64_t dense = ((uint64_t)f.npiv + f.mD) * f.nB;
         mr.mode = dense >= b->cfg.mfma_min_entries ? FL_MFMA_I8 : FL_PLAIN;
+        const bool ok = mr.status == FL_OK;
+        mr.nblk = ok && f.npiv && f.nB ? (f.npiv + kFlTrsmBlock - 1) / kFlTrsmBlock : 0;
+        mr.npanels = ok && f.mD && f.nB ? (f.nB + 63) / 64 : 0;
+        b->max_blk = std::max(b->max_blk, mr.nblk);
+        b->max_panels = std::max(b->max_panels, mr.npanels);
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t x, uint32_t y) { return b->mats[x].cost > b->mats[y].cost; });
@@ -199,14 +216,6 @@ void batch_layout(fl_batch *b) {
         uint32_t k = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
         mr.branch = k;
         load[k] += mr.cost + 2e6;  // per-matrix launch overhead, in work units
-        if (mr.status != FL_OK) continue;
-        const fl_split_info *f = &mr.info;
-        size_t w = fl_trsm_workspace(f, mr.mode);
-        w = std::max(w, fl_reduce_cd_workspace(f, mr.mode));
-        w = std::max(w, fl_echelon_d_workspace(f->mD, f->nB, mr.mode));
-        w = std::max(w, fl_rref_workspace(f, mr.mode));
-        w = std::max(w, fl_rref_csr_workspace(f));
-        ws_need[k] = std::max<uint64_t>(ws_need[k], w);
     }
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
@@ -214,7 +223,15 @@ void batch_layout(fl_batch *b) {
         o = align256(o + (bytes ? bytes : 1));
         return at;
     };
-    b->summary_off = take(32ull * b->count);
+    const uint64_t n = b->count;
+    b->summary_off = take(32 * n);
+    b->off_ttask = take(sizeof(FlTrsmTask) * n);
+    b->off_tids = take(4 * 3 * n);
+    b->off_tpre = take(4 * 3 * (n + 1));
+    b->off_etask = take(sizeof(FlEchTask) * n);
+    b->off_eids = take(4 * 3 * n);
+    b->off_epre_rows = take(4 * (n + 1));
+    b->off_epre = take(4 * 3 * (uint64_t)b->max_panels * (n + 1));
     for (auto &mr : b->mats) {
         const fl_split_info &f = mr.info;
         mr.ldx = ld64(f.nB);
@@ -222,8 +239,17 @@ void batch_layout(fl_batch *b) {
         mr.nnz_cap = ((uint64_t)f.npiv + mr.maxr) * ((uint64_t)f.nB + 1);
         if (mr.status != FL_OK) {
             mr.off_X = mr.off_Dt = mr.off_rank = mr.off_piv = mr.off_rowptr = mr.off_col = mr.off_val = 0;
+            mr.off_ws = mr.ws_bytes = 0;
             continue;
         }
+        const fl_split_info *fi = &mr.info;
+        size_t w = fl_trsm_workspace(fi, mr.mode);
+        w = std::max(w, fl_reduce_cd_workspace(fi, mr.mode));
+        w = std::max(w, fl_echelon_d_workspace(fi->mD, fi->nB, mr.mode));
+        w = std::max(w, fl_rref_workspace(fi, mr.mode));
+        w = std::max(w, fl_rref_csr_workspace(fi));
+        mr.ws_bytes = std::max<uint64_t>(w, 256);
+        mr.off_ws = take(mr.ws_bytes);
         mr.off_X = take(2 * mr.ldx * std::max<uint64_t>(f.npiv, 1));
         mr.off_Dt = take(2 * mr.ldd * std::max<uint64_t>(f.mD, 1));
         mr.off_rank = take(4);
@@ -231,12 +257,6 @@ void batch_layout(fl_batch *b) {
         mr.off_rowptr = take(8 * ((uint64_t)f.npiv + mr.maxr + 1));
         mr.off_col = take(4 * mr.nnz_cap);
         mr.off_val = take(2 * mr.nnz_cap);
-    }
-    b->ws_off.assign(S, 0);
-    b->ws_bytes.assign(S, 0);
-    for (uint32_t k = 0; k < S; k++) {
-        b->ws_bytes[k] = std::max<uint64_t>(ws_need[k], 256);
-        b->ws_off[k] = take(b->ws_bytes[k]);
     }
     b->run_bytes = o;
 }
@@ -246,36 +266,137 @@ T *at(void *arena, uint64_t off) {
     return (T *)((char *)arena + off);
 }
 
-// Steps 2-5 of one matrix on stream s.
-fl_status run_one(fl_batch *b, const MatrixRun &mr, void *arena, hipStream_t s) {
-    uint64_t *sum = at<uint64_t>(arena, b->summary_off) + 4 * (size_t)(&mr - b->mats.data());
-    if (mr.status != FL_OK) {
-        hipLaunchKernelGGL(k_batch_skip, dim3(1), dim3(64), 0, s, sum, (uint64_t)mr.status);
-        FL_LAUNCH_CHECK("k_batch_skip");
-        return FL_OK;
+fl_status fork(fl_batch *b, hipStream_t stream) {
+    FL_HIP(hipEventRecord(b->fork, stream));
+    for (uint32_t k = 0; k < b->cfg.streams; k++) FL_HIP(hipStreamWaitEvent(b->streams[k], b->fork, 0));
+    return FL_OK;
+}
+
+fl_status join(fl_batch *b, hipStream_t stream) {
+    for (uint32_t k = 0; k < b->cfg.streams; k++) {
+        FL_HIP(hipEventRecord(b->join[k], b->streams[k]));
+        FL_HIP(hipStreamWaitEvent(stream, b->join[k], 0));
     }
-    const fl_split_info *f = &mr.info;
-    uint16_t *X = at<uint16_t>(arena, mr.off_X);
-    uint16_t *Dt = at<uint16_t>(arena, mr.off_Dt);
-    uint32_t *rank = at<uint32_t>(arena, mr.off_rank);
-    uint32_t *piv = at<uint32_t>(arena, mr.off_piv);
-    uint64_t *rp = at<uint64_t>(arena, mr.off_rowptr);
-    void *ws = at<char>(arena, b->ws_off[mr.branch]);
-    const size_t wsb = b->ws_bytes[mr.branch];
-    fl_status st;
-    if ((st = fl_trsm(f, &mr.out, X, mr.ldx, mr.mode, ws, wsb, s)) != FL_OK) return st;
-    if ((st = fl_reduce_cd(f, &mr.out, X, mr.ldx, Dt, mr.ldd, mr.mode, ws, wsb, s)) != FL_OK) return st;
-    if ((st = fl_echelon_d(b->p, f->mD, f->nB, Dt, mr.ldd, rank, piv, mr.mode, ws, wsb, s)) != FL_OK)
-        return st;
-    if ((st = fl_rref(f, &mr.out, X, mr.ldx, Dt, mr.ldd, rank, piv, mr.mode, ws, wsb, s)) != FL_OK)
-        return st;
-    if ((st = fl_rref_csr_enqueue(f, &mr.out, X, mr.ldx, Dt, mr.ldd, rank, piv, rp,
-                                  at<uint32_t>(arena, mr.off_col), at<uint16_t>(arena, mr.off_val), ws,
-                                  wsb, s)) != FL_OK)
-        return st;
-    hipLaunchKernelGGL(k_batch_summary, dim3(1), dim3(64), 0, s, sum, f->npiv, (uint32_t)mr.maxr,
-                       (const uint32_t *)rank, (const uint64_t *)rp, (uint64_t)FL_OK);
-    FL_LAUNCH_CHECK("k_batch_summary");
+    return FL_OK;
+}
+
+// Indices of the matrices with key(i) > 0, largest key first (stable).
+template <class F>
+std::vector<uint32_t> sorted_ids(const fl_batch *b, F key, int mode_filter) {
+    std::vector<uint32_t> ids;
+    for (uint32_t i = 0; i < b->count; i++)
+        if (key(b->mats[i]) > 0 && (mode_filter < 0 || (int)b->mats[i].mode == mode_filter)) ids.push_back(i);
+    std::stable_sort(ids.begin(), ids.end(), [&](uint32_t x, uint32_t y) { return key(b->mats[x]) > key(b->mats[y]); });
+    return ids;
+}
+
+fl_status upload_ids(void *dst, const std::vector<uint32_t> &v, hipStream_t s) {
+    if (!v.empty()) FL_HIP(fl_upload(dst, v.data(), 4 * v.size(), s));
+    return FL_OK;
+}
+
+// Workgroup prefix over ids of per-matrix counts.
+template <class F>
+std::vector<uint32_t> prefix_of(const fl_batch *b, const std::vector<uint32_t> &ids, F count) {
+    std::vector<uint32_t> pre(ids.size() + 1, 0);
+    for (size_t i = 0; i < ids.size(); i++) pre[i + 1] = pre[i] + count(b->mats[ids[i]]);
+    return pre;
+}
+
+// The batched TRSM: per-matrix set-up on the branches, then one launch per
+// step and kind for all matrices (step s solves block nblk - 1 - s of each).
+fl_status run_trsm(fl_batch *b, void *arena, hipStream_t stream) {
+    const uint32_t n = b->count, w = b->cfg.ml_width;
+    std::vector<FlTrsmTask> tasks(n);
+    FL_CHECK_ST(fork(b, stream));
+    for (uint32_t i = 0; i < n; i++) {
+        MatrixRun &mr = b->mats[i];
+        tasks[i] = FlTrsmTask{};
+        if (mr.status != FL_OK) continue;
+        FL_CHECK_ST(fl_trsm_prepare(&mr.info, &mr.out, at<uint16_t>(arena, mr.off_X), mr.ldx, mr.mode,
+                                    at<char>(arena, mr.off_ws), mr.ws_bytes, b->streams[mr.branch], &tasks[i]));
+    }
+    FL_CHECK_ST(join(b, stream));
+    if (b->max_blk == 0) return FL_OK;
+    auto nblk = [](const MatrixRun &m) { return m.nblk; };
+    const std::vector<uint32_t> ids[3] = {sorted_ids(b, nblk, -1), sorted_ids(b, nblk, FL_MFMA_I8),
+                                          sorted_ids(b, nblk, FL_PLAIN)};
+    const std::vector<uint32_t> pre[3] = {
+        prefix_of(b, ids[0], [](const MatrixRun &m) { return (m.info.nB + 63) / 64; }),
+        prefix_of(b, ids[1], [](const MatrixRun &m) { return (m.info.nB + 127) / 128; }),
+        prefix_of(b, ids[2], [&](const MatrixRun &m) { return (m.info.nB + 255) / 256 * (kFlTrsmBlock / w / 4); })};
+    FlTrsmTask *d_tasks = at<FlTrsmTask>(arena, b->off_ttask);
+    FL_HIP(fl_upload(d_tasks, tasks.data(), sizeof(FlTrsmTask) * n, stream));
+    uint32_t *d_ids[3], *d_pre[3];
+    for (int k = 0; k < 3; k++) {
+        d_ids[k] = at<uint32_t>(arena, b->off_tids) + (size_t)k * n;
+        d_pre[k] = at<uint32_t>(arena, b->off_tpre) + (size_t)k * (n + 1);
+        FL_CHECK_ST(upload_ids(d_ids[k], ids[k], stream));
+        FL_CHECK_ST(upload_ids(d_pre[k], pre[k], stream));
+    }
+    const int kind_of[3] = {2, 1, 0};  // solve over all, MFMA update, VALU update
+    std::vector<uint32_t> active(3);
+    for (int k = 0; k < 3; k++) active[k] = (uint32_t)ids[k].size();
+    for (uint32_t step = 0; step < b->max_blk; step++) {
+        for (int k : {1, 2, 0}) {  // updates of the step, then its solves
+            while (active[k] && b->mats[ids[k][active[k] - 1]].nblk <= step) active[k]--;
+            if (!active[k]) continue;
+            FL_HIP(fl_trsm_batch_launch(kind_of[k], b->p, w, d_tasks, d_ids[k], d_pre[k], active[k],
+                                        pre[k][active[k]], step, stream));
+        }
+    }
+    return FL_OK;
+}
+
+// The batched echelon: set-up per matrix, one launch per panel and kernel for
+// all matrices, then the final row placement per matrix on the branches.
+fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, hipStream_t stream) {
+    const uint32_t n = b->count;
+    if (b->max_panels == 0) return FL_OK;
+    auto npan = [](const MatrixRun &m) { return m.npanels; };
+    const std::vector<uint32_t> ids[3] = {sorted_ids(b, npan, -1), sorted_ids(b, npan, FL_MFMA_I8),
+                                          sorted_ids(b, npan, FL_PLAIN)};
+    const std::vector<uint32_t> pre_rows =
+        prefix_of(b, ids[0], [](const MatrixRun &m) { return (m.info.mD + 31) / 32; });
+    FlEchTask *d_tasks = at<FlEchTask>(arena, b->off_etask);
+    FL_HIP(fl_upload(d_tasks, tasks.data(), sizeof(FlEchTask) * n, stream));
+    uint32_t *d_ids[3];
+    for (int k = 0; k < 3; k++) {
+        d_ids[k] = at<uint32_t>(arena, b->off_eids) + (size_t)k * n;
+        FL_CHECK_ST(upload_ids(d_ids[k], ids[k], stream));
+    }
+    uint32_t *d_pre_rows = at<uint32_t>(arena, b->off_epre_rows);
+    FL_CHECK_ST(upload_ids(d_pre_rows, pre_rows, stream));
+    const uint32_t Pm = b->max_panels;
+    uint32_t *pre_base = at<uint32_t>(arena, b->off_epre);
+    FlEchLists L = {};
+    L.ids_all = d_ids[0];
+    L.ids_mfma = d_ids[1];
+    L.ids_plain = d_ids[2];
+    L.n_all = (uint32_t)ids[0].size();
+    L.n_mfma = (uint32_t)ids[1].size();
+    L.n_plain = (uint32_t)ids[2].size();
+    L.pre_rows = d_pre_rows;
+    uint32_t *pc = pre_base, *pm = pre_base + (size_t)Pm * (n + 1), *pp = pre_base + 2 * (size_t)Pm * (n + 1);
+    L.pre_c256 = pc;
+    L.pre_m128 = pm;
+    L.pre_p256 = pp;
+    FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, pc, pm, pp, stream));
+    uint32_t active = L.n_all;
+    for (uint32_t P = 0; P < Pm; P++) {
+        while (active && b->mats[ids[0][active - 1]].npanels <= P) active--;
+        if (!active) break;
+        uint32_t g256 = 0, g128 = 0, gp = 0, mrows = 0;
+        for (uint32_t i : ids[0]) g256 += fl_ech_tiles(b->mats[i].info.nB, P, 256);
+        for (uint32_t i : ids[1]) {
+            const uint32_t t = fl_ech_tiles(b->mats[i].info.nB, P, 128);
+            g128 += t;
+            if (t) mrows = std::max(mrows, b->mats[i].info.mD);
+        }
+        for (uint32_t i : ids[2]) gp += fl_ech_tiles(b->mats[i].info.nB, P, 256);
+        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, active, pre_rows[active], g256, g128, gp, mrows,
+                                      stream));
+    }
     return FL_OK;
 }
 
@@ -285,25 +406,54 @@ fl_status batch_run(fl_batch *b, void *arena, size_t bytes, hipStream_t stream) 
         fl_set_error("fl_batch_run: run arena too small");
         return FL_ERR_WORKSPACE;
     }
-    const uint32_t S = b->cfg.streams;
-    FL_HIP(hipEventRecord(b->fork, stream));
-    for (uint32_t k = 0; k < S; k++) FL_HIP(hipStreamWaitEvent(b->streams[k], b->fork, 0));
-    // largest matrices first on each branch, as dealt
-    std::vector<uint32_t> order(b->count);
-    for (uint32_t i = 0; i < b->count; i++) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return b->mats[x].cost > b->mats[y].cost; });
-    fl_status first = FL_OK;
-    for (uint32_t i : order) {
-        const MatrixRun &mr = b->mats[i];
-        fl_status st = run_one(b, mr, arena, b->streams[mr.branch]);
-        if (st != FL_OK && first == FL_OK) first = st;
+    const uint32_t n = b->count;
+    // step 2: X = A^-1 B for every matrix
+    FL_CHECK_ST(run_trsm(b, arena, stream));
+    // step 3 and the echelon set-up, per matrix on the branches
+    std::vector<FlEchTask> etasks(n);
+    FL_CHECK_ST(fork(b, stream));
+    for (uint32_t i = 0; i < n; i++) {
+        MatrixRun &mr = b->mats[i];
+        etasks[i] = FlEchTask{};
+        if (mr.status != FL_OK) continue;
+        const fl_split_info *f = &mr.info;
+        hipStream_t s = b->streams[mr.branch];
+        void *ws = at<char>(arena, mr.off_ws);
+        uint16_t *X = at<uint16_t>(arena, mr.off_X), *Dt = at<uint16_t>(arena, mr.off_Dt);
+        FL_CHECK_ST(fl_reduce_cd(f, &mr.out, X, mr.ldx, Dt, mr.ldd, mr.mode, ws, mr.ws_bytes, s));
+        FL_CHECK_ST(fl_echelon_prepare(b->p, f->mD, f->nB, Dt, mr.ldd, at<uint32_t>(arena, mr.off_rank),
+                                       at<uint32_t>(arena, mr.off_piv), mr.mode, ws, mr.ws_bytes, s, &etasks[i]));
     }
-    for (uint32_t k = 0; k < S; k++) {
-        FL_HIP(hipEventRecord(b->join[k], b->streams[k]));
-        FL_HIP(hipStreamWaitEvent(stream, b->join[k], 0));
+    FL_CHECK_ST(join(b, stream));
+    // step 4: the panel loop for every matrix
+    FL_CHECK_ST(run_echelon(b, arena, etasks, stream));
+    // placement, second pass, read-off and summary, per matrix
+    FL_CHECK_ST(fork(b, stream));
+    for (uint32_t i = 0; i < n; i++) {
+        MatrixRun &mr = b->mats[i];
+        hipStream_t s = b->streams[mr.branch];
+        uint64_t *sum = at<uint64_t>(arena, b->summary_off) + 4 * (size_t)i;
+        if (mr.status != FL_OK) {
+            hipLaunchKernelGGL(k_batch_skip, dim3(1), dim3(64), 0, s, sum, (uint64_t)mr.status);
+            FL_LAUNCH_CHECK("k_batch_skip");
+            continue;
+        }
+        const fl_split_info *f = &mr.info;
+        void *ws = at<char>(arena, mr.off_ws);
+        uint16_t *X = at<uint16_t>(arena, mr.off_X), *Dt = at<uint16_t>(arena, mr.off_Dt);
+        uint32_t *rank = at<uint32_t>(arena, mr.off_rank), *piv = at<uint32_t>(arena, mr.off_piv);
+        uint64_t *rp = at<uint64_t>(arena, mr.off_rowptr);
+        FL_CHECK_ST(fl_echelon_finish(etasks[i], s));
+        FL_CHECK_ST(fl_rref(f, &mr.out, X, mr.ldx, Dt, mr.ldd, rank, piv, mr.mode, ws, mr.ws_bytes, s));
+        FL_CHECK_ST(fl_rref_csr_enqueue(f, &mr.out, X, mr.ldx, Dt, mr.ldd, rank, piv, rp,
+                                        at<uint32_t>(arena, mr.off_col), at<uint16_t>(arena, mr.off_val), ws,
+                                        mr.ws_bytes, s));
+        hipLaunchKernelGGL(k_batch_summary, dim3(1), dim3(64), 0, s, sum, f->npiv, (uint32_t)mr.maxr,
+                           (const uint32_t *)rank, (const uint64_t *)rp, (uint64_t)FL_OK);
+        FL_LAUNCH_CHECK("k_batch_summary");
     }
-    return first;
+    FL_CHECK_ST(join(b, stream));
+    return FL_OK;
 }
 
 void batch_destroy(fl_batch *b) {

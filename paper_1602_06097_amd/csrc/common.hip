@@ -304,3 +304,31 @@ extern "C" size_t fl_prof_report(char *buf, size_t len) {
     }
     return out.size() + 1;
 }
+
+// ---- host -> device copies through kernel arguments ----------------------------
+namespace {
+struct UploadChunk {
+    uint32_t n;          // 32-bit words in w
+    uint32_t w[255];
+};
+
+__global__ void k_upload(uint32_t *dst, UploadChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+}  // namespace
+
+hipError_t fl_upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if ((bytes & 3) || ((uintptr_t)dst & 3)) return hipErrorInvalidValue;
+    const uint32_t *in = (const uint32_t *)src;
+    uint32_t *out = (uint32_t *)dst;
+    size_t words = bytes / 4;
+    for (size_t o = 0; o < words; o += 255) {
+        UploadChunk c;
+        c.n = (uint32_t)(words - o < 255 ? words - o : 255);
+        memcpy(c.w, in + o, 4 * (size_t)c.n);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, out + o, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

@@ -26,6 +26,8 @@
 // After the last panel the pivot rows are gathered to rows 0..r-1 in pivot
 // order and the other rows (now zero) are cleared.
 #include "fl_internal.h"
+#include "mfma_tile.h"
+#include "valu_tile.h"
 
 hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
                              const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
@@ -75,6 +77,11 @@ struct EchWs {
     void *gemm_ws;
     size_t gemm_ws_bytes;
     uint64_t ldu;
+    // one-entry task table for the single-matrix call
+    FlEchTask *task;
+    uint32_t *ids;       // [1] = 0
+    uint32_t *pre_rows;  // [2]
+    uint32_t *pre;       // 3 x [npanels][2]
 };
 
 // Reduce the wave's vector (v: panel part, g: coefficient part, lane = column
@@ -233,57 +240,67 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
 }
 
 // Panel step 1: greedy basis of (at most kProbe of) the rows nonzero on the
-// panel, taken from the list built by step 0.
-__global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(
-    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t c0, uint32_t pw,
-    const uint32_t *__restrict__ nzlist, const uint32_t *__restrict__ nzcount, uint32_t *is_piv,
-    PanelState *ps, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+// panel, taken from the list built by step 0.  One workgroup per matrix.
+__global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                              const uint32_t *__restrict__ ids, uint32_t P) {
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
-    const uint32_t n = *nzcount;
+    const FlEchTask &t = tasks[ids[blockIdx.x]];
+    if (P >= t.npanels) return;
+    const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
+    PanelState *ps = (PanelState *)t.ps;
+    const uint32_t n = t.counts[3 * P];
     const uint32_t take = n < kProbe ? n : kProbe;
     if (threadIdx.x == 0) {
         S.kb = 0;
         S.cnt = take;
-        rank0_s = *d_rank;
+        rank0_s = *t.d_rank;
         ps->nflag = 0;
         ps->rank0 = rank0_s;
     }
-    if (threadIdx.x < take) S.list[threadIdx.x] = nzlist[threadIdx.x];
+    if (threadIdx.x < take) S.list[threadIdx.x] = t.nzlist[threadIdx.x];
     __syncthreads();
     const uint32_t rank0 = rank0_s;
-    greedy_rows(md, D, ld, c0, pw, S);
+    greedy_rows(md, t.D, t.ld, c0, pw, S);
     save_raw(S, ps);
-    finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
+    finalize(S, ps, c0, rank0, t.is_piv, t.piv_row, t.piv_col, t.d_rank);
 }
 
 // Panel steps 0 and 2.  Step 0 (use_basis = 0): every remaining row that is
-// nonzero on the panel goes to out_list.  Step 2: every row of in_list is
-// reduced against the probe basis in ps; rows left nonzero (outside its span)
-// go to out_list.  One wave per row, 8 rows per wave, 32 rows per block.
-__global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const uint16_t *__restrict__ D,
-                                                   uint64_t ld, uint32_t rows, uint32_t c0,
-                                                   uint32_t pw, const uint32_t *__restrict__ is_piv,
-                                                   PanelState *ps, const uint32_t *__restrict__ in_list,
-                                                   const uint32_t *__restrict__ in_count,
-                                                   uint32_t *out_list, uint32_t *out_count, int use_basis) {
+// nonzero on the panel goes to the nonzero list.  Step 2: every row of that
+// list is reduced against the probe basis in ps; rows left nonzero (outside
+// its span) go to the flagged list.  One wave per row, 8 rows per wave, 32
+// rows per workgroup.
+__global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                   const uint32_t *__restrict__ ids,
+                                                   const uint32_t *__restrict__ pre_rows, uint32_t ntask,
+                                                   uint32_t P, int use_basis) {
     __shared__ uint16_t Bv[64][64];
     __shared__ uint32_t Cc[64];
+    const uint32_t ti = fl_task_of(pre_rows, ntask, blockIdx.x);
+    const FlEchTask &t = tasks[ids[ti]];
+    if (P >= t.npanels) return;
+    const uint32_t bx = blockIdx.x - pre_rows[ti];
+    const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
+    const PanelState *ps = (const PanelState *)t.ps;
+    const uint32_t *in_list = use_basis ? t.nzlist : nullptr;
+    uint32_t *out_list = use_basis ? t.flist : t.nzlist;
+    uint32_t *out_count = t.counts + 3 * P + (use_basis ? 1 : 0);
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t kb = use_basis ? ps->kb : 0;
-    const uint32_t n = in_list ? *in_count : rows;
-    if (blockIdx.x * 32 >= n) return;
+    const uint32_t n = in_list ? t.counts[3 * P] : t.rows;
+    if (bx * 32 >= n) return;
     for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) Bv[i >> 6][i & 63] = ps->Bv[i];
     if (threadIdx.x < 64) Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
     __syncthreads();
     for (uint32_t u = 0; u < 8; u++) {
-        const uint32_t idx = (blockIdx.x * 4 + wave) * 8 + u;
+        const uint32_t idx = (bx * 4 + wave) * 8 + u;
         bool flag = false;
         uint32_t i = 0;
         if (idx < n) {
             i = in_list ? in_list[idx] : idx;
-            if (!is_piv[i] && kb < pw) {
-                uint32_t v = lane < pw ? D[(uint64_t)i * ld + c0 + lane] : 0, g = 0;
+            if (!t.is_piv[i] && kb < pw) {
+                uint32_t v = lane < pw ? t.D[(uint64_t)i * t.ld + c0 + lane] : 0, g = 0;
                 if (kb) reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
                 flag = __ballot(v != 0) != 0;
             }
@@ -294,14 +311,17 @@ __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const uint16_t *_
 }
 
 // Panel step 3 (only when some row was flagged): continue the greedy basis
-// with the flagged rows and publish the final result.
-__global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
-    fl::Mod md, const uint16_t *__restrict__ D, uint64_t ld, uint32_t c0, uint32_t pw,
-    const uint32_t *__restrict__ flist, const uint32_t *__restrict__ fcount, uint32_t *is_piv,
-    PanelState *ps, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
+// with the flagged rows and publish the final result.  One workgroup per
+// matrix.
+__global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                              const uint32_t *__restrict__ ids, uint32_t P) {
     __shared__ GreedyLds S;
-    const uint32_t n = *fcount;
+    const FlEchTask &t = tasks[ids[blockIdx.x]];
+    if (P >= t.npanels) return;
+    const uint32_t n = t.counts[3 * P + 1];
     if (n == 0) return;
+    const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
+    PanelState *ps = (PanelState *)t.ps;
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
         S.Bv[i >> 6][i & 63] = ps->Bv[i];
         S.Bg[i >> 6][i & 63] = ps->Bg[i];
@@ -315,31 +335,40 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(
     const uint32_t rank0 = ps->rank0;
     for (uint32_t base = 0; base < n && S.kb < pw; base += kGreedyThreads) {
         const uint32_t cnt = n - base < kGreedyThreads ? n - base : kGreedyThreads;
-        if (threadIdx.x < cnt) S.list[threadIdx.x] = flist[base + threadIdx.x];
+        if (threadIdx.x < cnt) S.list[threadIdx.x] = t.flist[base + threadIdx.x];
         if (threadIdx.x == 0) S.cnt = cnt;
         __syncthreads();
-        greedy_rows(md, D, ld, c0, pw, S);
+        greedy_rows(md, t.D, t.ld, c0, pw, S);
     }
     save_raw(S, ps);
-    finalize(S, ps, c0, rank0, is_piv, piv_row, piv_col, d_rank);
+    finalize(S, ps, c0, rank0, t.is_piv, t.piv_row, t.piv_col, t.d_rank);
 }
 
 // U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k; with
 // limb planes, also U transposed as int8 limbs: Uh/Ul[(c - c0) * 64 + t]
 // (zero for t >= k), the B operand of the matrix-core rank-k update.
-__global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__restrict__ D,
-                                               uint64_t ld, uint32_t c0, uint32_t cols,
-                                               const PanelState *__restrict__ ps, uint16_t *U,
-                                               uint64_t ldu, int8_t *Uh, int8_t *Ul) {
+// 256 columns per workgroup.
+__global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                               const uint32_t *__restrict__ ids,
+                                               const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P) {
     __shared__ uint16_t Gs[64 * 64];
     __shared__ uint16_t xs[64][256];
     __shared__ uint32_t qs[64];
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const FlEchTask &tk = tasks[ids[ti]];
+    if (P >= tk.npanels) return;
+    const PanelState *ps = (const PanelState *)tk.ps;
+    const uint32_t c0 = P * kPanel, cols = tk.cols;
+    const uint16_t *D = tk.D;
+    const uint64_t ld = tk.ld, ldu = tk.ldu;
+    uint16_t *U = tk.U;
+    int8_t *Uh = tk.Uh, *Ul = tk.Ul;
     const uint32_t k = ps->k;
     if (k == 0) return;
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) Gs[i] = ps->G[i];
     if (threadIdx.x < 64) qs[threadIdx.x] = ps->Qs[threadIdx.x];
     __syncthreads();
-    const uint32_t c = c0 + blockIdx.x * 256 + threadIdx.x;
+    const uint32_t c = c0 + (blockIdx.x - pre[ti]) * 256 + threadIdx.x;
     const bool ok = c < cols;
 #pragma unroll 8
     for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)qs[s] * ld + c] : 0;
@@ -383,18 +412,28 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const uint16_t *__res
 // int8 limbs (64 bytes per row) and the list of rows with a nonzero
 // multiplier (rows whose update is zero are skipped by the rank-k update).
 // One wave per row, 8 rows per wave.
-__global__ __launch_bounds__(256) void k_ech_gather_L(const uint16_t *__restrict__ D, uint64_t ld,
-                                                      uint32_t rows, const PanelState *__restrict__ ps,
-                                                      uint16_t *L, uint32_t p, int8_t *Lh, int8_t *Ll,
-                                                      uint32_t *upd_rows, uint32_t *upd_count) {
+__global__ __launch_bounds__(256) void k_ech_gather_L(uint32_t p, const FlEchTask *__restrict__ tasks,
+                                                      const uint32_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ pre_rows, uint32_t ntask,
+                                                      uint32_t P) {
     __shared__ uint32_t ccol[64];
+    const uint32_t ti = fl_task_of(pre_rows, ntask, blockIdx.x);
+    const FlEchTask &tk = tasks[ids[ti]];
+    if (P >= tk.npanels) return;
+    const uint32_t bx = blockIdx.x - pre_rows[ti];
+    const PanelState *ps = (const PanelState *)tk.ps;
+    const uint32_t rows = tk.rows;
+    const uint16_t *D = tk.D;
+    const uint64_t ld = tk.ld;
+    uint16_t *L = tk.L;
+    int8_t *Lh = tk.Lh, *Ll = tk.Ll;
     const uint32_t t = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (blockIdx.x * 32 >= rows) return;
+    if (bx * 32 >= rows) return;
     const uint32_t k = ps->k;
     if (threadIdx.x < 64) ccol[threadIdx.x] = ps->Ccol[threadIdx.x];
     __syncthreads();
     for (uint32_t u = 0; u < 8; u++) {
-        const uint32_t i = (blockIdx.x * 4 + wave) * 8 + u;
+        const uint32_t i = (bx * 4 + wave) * 8 + u;
         bool nz = false;
         if (i < rows) {
             const uint32_t x = t < k ? D[(uint64_t)i * ld + ccol[t]] : 0;
@@ -407,19 +446,76 @@ __global__ __launch_bounds__(256) void k_ech_gather_L(const uint16_t *__restrict
                 nz = __ballot(x != 0) != 0;
             }
         }
-        if (Lh) block_append(nz, i, upd_rows, upd_count);
+        if (Lh) block_append(nz, i, tk.upd_rows, tk.counts + 3 * P + 2);
     }
 }
 
-// Rows of Q receive U (after the rank-k update touched them).
-__global__ __launch_bounds__(256) void k_ech_setq(uint16_t *D, uint64_t ld, uint32_t c0,
-                                                  uint32_t cols, const PanelState *__restrict__ ps,
-                                                  const uint16_t *__restrict__ U, uint64_t ldu) {
+// Rank-k update of the rows with a nonzero multiplier, int8 MFMA form: one
+// 64-row x 128-column tile per workgroup (column block from the prefix, row
+// block blockIdx.y of the row list; blocks beyond the list exit at once).
+__global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                         const FlEchTask *__restrict__ tasks,
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint32_t *__restrict__ pre, uint32_t ntask,
+                                                         uint32_t P) {
+    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
+    __shared__ uint32_t rows_s[64];
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const FlEchTask &t = tasks[ids[ti]];
+    if (P >= t.npanels) return;
+    const uint32_t M = t.counts[3 * P + 2];
+    if (blockIdx.y * 64 >= M || ((const PanelState *)t.ps)->k == 0) return;
+    const uint32_t c0 = P * kPanel;
+    fl_mfma::mfma_rank64_tile(md, bias, c16, t.Lh, t.Ll, t.Uh, t.Ul, t.upd_rows, M, t.D + c0, t.ld, t.cols - c0,
+                              blockIdx.x - pre[ti], blockIdx.y, sv, rows_s);
+}
+
+// Rank-k update of every row, VALU form: column block (of 256) from the
+// prefix, row blocks (of 32) blockIdx.y, blockIdx.y + gridDim.y, ...
+__global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint32_t *__restrict__ pre, uint32_t ntask,
+                                                         uint32_t P) {
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const FlEchTask &t = tasks[ids[ti]];
+    if (P >= t.npanels) return;
+    const PanelState *ps = (const PanelState *)t.ps;
+    const uint32_t c0 = P * kPanel, bx = blockIdx.x - pre[ti];
+    for (uint32_t by = blockIdx.y; by * 32 < t.rows; by += gridDim.y)
+        fl_valu::valu_gemm_tile(md, t.rows, t.cols - c0, 0, &ps->k, t.L, 64, t.U + c0, t.ldu, t.D + c0, t.ld,
+                                bx, by);
+}
+
+// Rows of Q receive U (after the rank-k update touched them): 256 columns
+// per workgroup from the prefix, pivot t = blockIdx.y.
+__global__ __launch_bounds__(256) void k_ech_setq(const FlEchTask *__restrict__ tasks,
+                                                  const uint32_t *__restrict__ ids,
+                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P) {
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const FlEchTask &tk = tasks[ids[ti]];
+    if (P >= tk.npanels) return;
+    const PanelState *ps = (const PanelState *)tk.ps;
     const uint32_t t = blockIdx.y;
     if (t >= ps->k) return;
     const uint32_t row = ps->Phys[t];
-    for (uint32_t c = c0 + blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += gridDim.x * blockDim.x)
-        D[(uint64_t)row * ld + c] = U[(uint64_t)t * ldu + c];
+    const uint32_t c = P * kPanel + (blockIdx.x - pre[ti]) * 256 + threadIdx.x;
+    if (c < tk.cols) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
+}
+
+// Per-panel workgroup prefixes of the column-tiled kernels (one thread per
+// panel and table).
+__global__ void k_ech_prefixes(const FlEchTask *__restrict__ tasks, const uint32_t *__restrict__ ids,
+                               uint32_t n, uint32_t panels, uint32_t tile, uint32_t *out) {
+    for (uint32_t P = blockIdx.x * blockDim.x + threadIdx.x; P < panels; P += gridDim.x * blockDim.x) {
+        uint32_t *o = out + (uint64_t)P * (n + 1);
+        uint32_t acc = 0;
+        o[0] = 0;
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t cols = tasks[ids[i]].cols, c0 = 64 * P;
+            acc += cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
+            o[i + 1] = acc;
+        }
+    }
 }
 
 // Final placement: T[t] = Dt[piv_row[t]] for t < rank, then Dt[t] = T[t] and
@@ -451,11 +547,12 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     WsCarve c(ws);
     const uint32_t mn = rows < cols ? rows : cols;
     const uint64_t ldu = ((uint64_t)cols + 63) & ~(uint64_t)63;
+    const uint32_t npanels = (cols + kPanel - 1) / kPanel;
     EchWs t;
     t.is_piv = c.take<uint32_t>(rows ? rows : 1);
     t.nzlist = c.take<uint32_t>(rows ? rows : 1);
     t.flist = c.take<uint32_t>(rows ? rows : 1);
-    t.counts = c.take<uint32_t>(3 * (size_t)((cols + kPanel - 1) / kPanel + 1));
+    t.counts = c.take<uint32_t>(3 * (size_t)(npanels + 1));
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
     t.ps = c.take<PanelState>(1);
     t.U = c.take<uint16_t>((size_t)64 * ldu);
@@ -472,6 +569,10 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
         t.Ul = c.take<int8_t>(((size_t)cols + 256) * 64);
     }
     t.upd_rows = c.take<uint32_t>(rows ? rows : 1);
+    t.task = c.take<FlEchTask>(1);
+    t.ids = c.take<uint32_t>(1);
+    t.pre_rows = c.take<uint32_t>(2);
+    t.pre = c.take<uint32_t>(3 * 2 * (size_t)(npanels ? npanels : 1));
     if (e) *e = t;
     return c.off;
 }
@@ -482,15 +583,21 @@ extern "C" size_t fl_echelon_d_workspace(uint32_t rows, uint32_t cols, fl_mode m
     return ech_layout(rows, cols, mode, nullptr, nullptr);
 }
 
-extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt,
-                                  uint64_t ldd, uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode,
-                                  void *ws, size_t ws_bytes, hipStream_t stream) {
+fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt, uint64_t ldd,
+                             uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws,
+                             size_t ws_bytes, hipStream_t stream, FlEchTask *task) {
     FL_ARG(p >= 2 && p <= 65521, "fl_echelon_d: p must be in [2, 65521]");
     FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_echelon_d: bad mode");
     FL_ARG(d_rank, "fl_echelon_d: NULL d_rank");
     FL_ARG(rows < (1u << 31) && cols < (1u << 31), "fl_echelon_d: dimensions must be < 2^31");
+    FlEchTask t = {};
+    t.rows = rows;
+    t.cols = cols;
+    t.d_rank = d_rank;
+    t.mfma = mode == FL_MFMA_I8;
     if (rows == 0 || cols == 0) {
         FL_HIP(fl_fill_u32(d_rank, 0, 1, stream));
+        *task = t;
         return FL_OK;
     }
     FL_ARG(Dt && d_pivcol, "fl_echelon_d: NULL array");
@@ -502,67 +609,157 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
         fl_set_error("fl_echelon_d: workspace too small");
         return FL_ERR_WORKSPACE;
     }
-    const fl::Mod md = fl::make_mod(p);
     const uint32_t npanels = (cols + kPanel - 1) / kPanel;
     FL_HIP(fl_fill_u32(e.is_piv, 0, rows, stream));
     FL_HIP(fl_fill_u32(d_rank, 0, 1, stream));
     FL_HIP(fl_fill_u32(e.counts, 0, 3 * (size_t)npanels, stream));
-    const unsigned row_blocks = (rows + 31) / 32;  // 32 rows per block (8 per wave)
-    for (uint32_t P = 0; P < npanels; P++) {
-        const uint32_t c0 = P * kPanel;
-        const uint32_t pw = cols - c0 < kPanel ? cols - c0 : kPanel;
-        uint32_t *n_nz = e.counts + 3 * P, *n_flag = n_nz + 1, *n_upd = n_nz + 2;
-        FL_PROF("echelon.check", stream,
-                hipLaunchKernelGGL(k_ech_check, dim3(row_blocks), dim3(256), 0, stream, md, (const uint16_t *)Dt,
-                                   ldd, rows, c0, pw, (const uint32_t *)e.is_piv, e.ps,
-                                   (const uint32_t *)nullptr, (const uint32_t *)nullptr, e.nzlist, n_nz, 0));
-        FL_LAUNCH_CHECK("k_ech_check<nonzero>");
-        FL_PROF("echelon.probe", stream,
-                hipLaunchKernelGGL(k_ech_probe, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, c0, pw, (const uint32_t *)e.nzlist,
-                                   (const uint32_t *)n_nz, e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
-        FL_LAUNCH_CHECK("k_ech_probe");
-        FL_PROF("echelon.check", stream,
-                hipLaunchKernelGGL(k_ech_check, dim3(row_blocks), dim3(256), 0, stream, md, (const uint16_t *)Dt,
-                                   ldd, rows, c0, pw, (const uint32_t *)e.is_piv, e.ps,
-                                   (const uint32_t *)e.nzlist, (const uint32_t *)n_nz, e.flist, n_flag, 1));
-        FL_LAUNCH_CHECK("k_ech_check<basis>");
-        FL_PROF("echelon.merge", stream,
-                hipLaunchKernelGGL(k_ech_merge, dim3(1), dim3(kGreedyThreads), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, c0, pw, (const uint32_t *)e.flist,
-                                   (const uint32_t *)n_flag, e.is_piv, e.ps, e.piv_row, d_pivcol, d_rank));
-        FL_LAUNCH_CHECK("k_ech_merge");
-        const uint32_t ucols = cols - c0;
+    t.D = Dt;
+    t.ld = ldd;
+    t.npanels = npanels;
+    t.is_piv = e.is_piv;
+    t.piv_row = e.piv_row;
+    t.piv_col = d_pivcol;
+    t.ps = e.ps;
+    t.U = e.U;
+    t.L = e.L;
+    t.T = e.T;
+    t.ldu = e.ldu;
+    t.Lh = e.Lh;
+    t.Ll = e.Ll;
+    t.Uh = e.Uh;
+    t.Ul = e.Ul;
+    t.upd_rows = e.upd_rows;
+    t.nzlist = e.nzlist;
+    t.flist = e.flist;
+    t.counts = e.counts;
+    *task = t;
+    return FL_OK;
+}
+
+hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint32_t panels,
+                               uint32_t *pre_c256, uint32_t *pre_m128, uint32_t *pre_p256,
+                               hipStream_t stream) {
+    if (panels == 0) return hipSuccess;
+    const unsigned g = (panels + 255) / 256;
+    hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_all, L.n_all, panels, 256u,
+                       pre_c256);
+    if (L.n_mfma)
+        hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_mfma, L.n_mfma, panels,
+                           128u, pre_m128);
+    if (L.n_plain)
+        hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_plain, L.n_plain, panels,
+                           256u, pre_p256);
+    return hipGetLastError();
+}
+
+hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t P,
+                                  uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
+                                  uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
+                                  hipStream_t stream) {
+    if (n_active == 0) return hipSuccess;
+    const fl::Mod md = fl::make_mod(p);
+    const uint32_t *c256 = L.pre_c256 + (uint64_t)P * (L.n_all + 1);
+    hipError_t e;
+    FL_PROF("echelon.check", stream,
+            hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                               L.pre_rows, n_active, P, 0));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    FL_PROF("echelon.probe", stream,
+            hipLaunchKernelGGL(k_ech_probe, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
+                               P));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    FL_PROF("echelon.check", stream,
+            hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                               L.pre_rows, n_active, P, 1));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    FL_PROF("echelon.merge", stream,
+            hipLaunchKernelGGL(k_ech_merge, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
+                               P));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (grid_c256) {
         FL_PROF("echelon.U", stream,
-                hipLaunchKernelGGL(k_ech_U, dim3((ucols + 255) / 256), dim3(256), 0, stream, md,
-                                   (const uint16_t *)Dt, ldd, c0, cols, (const PanelState *)e.ps, e.U, e.ldu,
-                                   e.Uh, e.Ul));
-        FL_LAUNCH_CHECK("k_ech_U");
-        FL_PROF("echelon.L", stream,
-                hipLaunchKernelGGL(k_ech_gather_L, dim3(row_blocks), dim3(256), 0, stream, (const uint16_t *)Dt,
-                                   ldd, rows, (const PanelState *)e.ps, e.L, p, e.Lh, e.Ll, e.upd_rows, n_upd));
-        FL_LAUNCH_CHECK("k_ech_gather_L");
-        const uint32_t *kdev = &e.ps->k;
-        if (mode == FL_MFMA_I8) {
-            FL_HIP(fl_mfma_rank64_planes(p, e.Lh, e.Ll, e.Uh, e.Ul, kdev, e.upd_rows, n_upd, rows, Dt + c0, ldd,
-                                         ucols, stream, "echelon.mfma"));
-        } else {
-            FL_HIP(fl_gemm_sub_plain(p, rows, ucols, 0, kdev, e.L, 64, e.U + c0, e.ldu, Dt + c0,
-                                     ldd, stream, "echelon.plain"));
-        }
-        FL_PROF("echelon.setq", stream,
-                hipLaunchKernelGGL(k_ech_setq, dim3((ucols + 255) / 256, kPanel), dim3(256), 0, stream, Dt,
-                                   ldd, c0, cols, (const PanelState *)e.ps, (const uint16_t *)e.U, e.ldu));
-        FL_LAUNCH_CHECK("k_ech_setq");
+                hipLaunchKernelGGL(k_ech_U, dim3(grid_c256), dim3(256), 0, stream, md, tasks, L.ids_all, c256,
+                                   L.n_all, P));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    FL_PROF("echelon.L", stream,
+            hipLaunchKernelGGL(k_ech_gather_L, dim3(grid_rows), dim3(256), 0, stream, p, tasks, L.ids_all,
+                               L.pre_rows, n_active, P));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (grid_m128) {
+        const uint32_t *m128 = L.pre_m128 + (uint64_t)P * (L.n_mfma + 1);
+        FL_PROF("echelon.mfma", stream,
+                hipLaunchKernelGGL(k_ech_update_mfma, dim3(grid_m128, (mfma_rows + 63) / 64), dim3(256), 0, stream, md,
+                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, m128,
+                                   L.n_mfma, P));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grid_p256) {
+        const uint32_t *p256 = L.pre_p256 + (uint64_t)P * (L.n_plain + 1);
+        FL_PROF("echelon.plain", stream,
+                hipLaunchKernelGGL(k_ech_update_valu, dim3(grid_p256, 64), dim3(256), 0, stream, md, tasks,
+                                   L.ids_plain, p256, L.n_plain, P));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grid_c256) {
+        FL_PROF("echelon.setq", stream,
+                hipLaunchKernelGGL(k_ech_setq, dim3(grid_c256, kPanel), dim3(256), 0, stream, tasks, L.ids_all,
+                                   c256, L.n_all, P));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
+    if (t.npanels == 0) return FL_OK;
+    const uint32_t rows = t.rows, cols = t.cols;
     const uint32_t mn = rows < cols ? rows : cols;
     const unsigned gx = (cols + 255) / 256 < 64 ? (cols + 255) / 256 : 64;
-    hipLaunchKernelGGL(k_ech_gather_rows, dim3(gx, mn < 65535 ? mn : 65535), dim3(256), 0, stream, (const uint16_t *)Dt,
-                       ldd, cols, (const uint32_t *)e.piv_row, (const uint32_t *)d_rank, e.T, e.ldu);
+    hipLaunchKernelGGL(k_ech_gather_rows, dim3(gx, mn < 65535 ? mn : 65535), dim3(256), 0, stream,
+                       (const uint16_t *)t.D, t.ld, cols, (const uint32_t *)t.piv_row, (const uint32_t *)t.d_rank,
+                       t.T, t.ldu);
     FL_LAUNCH_CHECK("k_ech_gather_rows");
     const unsigned gy = rows < 65535 ? rows : 65535;
-    hipLaunchKernelGGL(k_ech_place_rows, dim3(gx, gy), dim3(256), 0, stream, Dt, ldd, rows, cols,
-                       (const uint32_t *)d_rank, (const uint16_t *)e.T, e.ldu);
+    hipLaunchKernelGGL(k_ech_place_rows, dim3(gx, gy), dim3(256), 0, stream, t.D, t.ld, rows, cols,
+                       (const uint32_t *)t.d_rank, (const uint16_t *)t.T, t.ldu);
     FL_LAUNCH_CHECK("k_ech_place_rows");
     return FL_OK;
+}
+
+extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt,
+                                  uint64_t ldd, uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode,
+                                  void *ws, size_t ws_bytes, hipStream_t stream) {
+    FlEchTask t;
+    fl_status st = fl_echelon_prepare(p, rows, cols, Dt, ldd, d_rank, d_pivcol, mode, ws, ws_bytes, stream, &t);
+    if (st != FL_OK || t.npanels == 0) return st;
+    EchWs e;
+    ech_layout(rows, cols, mode, ws, &e);
+    // a one-entry task table
+    const uint32_t zero = 0, pre_rows[2] = {0, (rows + 31) / 32};
+    FL_HIP(fl_upload(e.task, &t, sizeof t, stream));
+    FL_HIP(fl_upload(e.ids, &zero, 4, stream));
+    FL_HIP(fl_upload(e.pre_rows, pre_rows, 8, stream));
+    const uint32_t np = t.npanels;
+    FlEchLists L = {};
+    L.ids_all = e.ids;
+    L.pre_rows = e.pre_rows;
+    L.pre_c256 = e.pre;
+    L.n_all = 1;
+    uint32_t *pre_m = e.pre + 2 * (size_t)np, *pre_p = e.pre + 4 * (size_t)np;
+    if (t.mfma) {
+        L.ids_mfma = e.ids;
+        L.pre_m128 = pre_m;
+        L.n_mfma = 1;
+    } else {
+        L.ids_plain = e.ids;
+        L.pre_p256 = pre_p;
+        L.n_plain = 1;
+    }
+    FL_HIP(fl_echelon_prefixes(e.task, L, np, e.pre, pre_m, pre_p, stream));
+    for (uint32_t P = 0; P < np; P++) {
+        const uint32_t g256 = fl_ech_tiles(cols, P, 256), g128 = fl_ech_tiles(cols, P, 128);
+        FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, 1, pre_rows[1], g256, t.mfma ? g128 : 0,
+                                      t.mfma ? 0 : g256, rows, stream));
+    }
+    return fl_echelon_finish(t, stream);
 }

@@ -187,3 +187,100 @@ fl_status fl_rref_csr_enqueue(const fl_split_info *info, const fl_split_out *s, 
                               const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
                               uint32_t *col, uint16_t *val, void *ws, size_t ws_bytes,
                               hipStream_t stream);
+
+// ---- many problems per launch --------------------------------------------------
+// A launch that serves several problems gives problem i the workgroups
+// [prefix[i], prefix[i+1]) of its 1-D grid; fl_task_of finds i for workgroup
+// bx (binary search over the n entries; prefix[0] = 0, ascending).
+__device__ __forceinline__ uint32_t fl_task_of(const uint32_t *__restrict__ prefix, uint32_t n,
+                                               uint32_t bx) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= bx) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Copies `bytes` from host memory into device memory through kernel
+// arguments (1 KiB per launch), so that the copy can be captured in a graph
+// without referring to host memory at replay time.
+hipError_t fl_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// One matrix's TRSM as the step kernels see it (device-side table entry).
+struct FlTrsmTask {
+    const uint64_t *gptr;   // A multiline groups
+    const uint32_t *pos;
+    const uint16_t *val;
+    const uint32_t *nin, *nnear;
+    uint16_t *X;
+    uint64_t ldx;
+    uint32_t npiv, nB, nblk, mfma;
+    int8_t *Ah, *Al, *Xh, *Xl;  // int8-MFMA form only
+    const uint32_t *kext;
+    uint64_t kp;
+};
+constexpr uint32_t kFlTrsmBlock = 128;
+// fl_trsm's set-up (dense B into X, group bounds, MFMA band planes) for one
+// matrix, enqueued on `stream`; *task receives its table entry.
+fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
+                          fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream, FlTrsmTask *task);
+// Step `step` (block nblk - 1 - step of each listed matrix): the far update
+// (kind 0: VALU, 1: int8 MFMA; no-op at step 0) or the block solve (kind 2),
+// over tasks[ids[0..n)] with workgroup prefix `prefix` and `grid` workgroups.
+// Workgroups per matrix: solve ceil(nB / 64); VALU update
+// ceil(nB / 256) * (128 / w / 4); MFMA update ceil(nB / 128).
+hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
+                                const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,
+                                uint32_t step, hipStream_t stream);
+
+// One matrix's Gauss-Jordan elimination of the Schur complement as the panel
+// kernels see it (device-side table entry).
+struct FlEchTask {
+    uint16_t *D;
+    uint64_t ld;
+    uint32_t rows, cols, npanels, mfma;
+    uint32_t *is_piv, *piv_row, *piv_col, *d_rank;
+    void *ps;               // panel state
+    uint16_t *U, *L, *T;
+    uint64_t ldu;
+    int8_t *Lh, *Ll, *Uh, *Ul;  // int8-MFMA form only
+    uint32_t *upd_rows, *nzlist, *flist, *counts;
+};
+// Device tables for a panel loop over several matrices: ids sorted by panel
+// count (descending); per-panel workgroup prefixes for the column-tiled
+// kernels (n + 1 entries per panel, matrices already finished count 0).
+struct FlEchLists {
+    const uint32_t *ids_all, *ids_mfma, *ids_plain;
+    const uint32_t *pre_rows;   // [n_all + 1]: ceil(rows / 32)
+    const uint32_t *pre_c256;   // [P][n_all + 1]: ceil((cols - 64 P) / 256)
+    const uint32_t *pre_m128;   // [P][n_mfma + 1]: ceil((cols - 64 P) / 128)
+    const uint32_t *pre_p256;   // [P][n_plain + 1]: ceil((cols - 64 P) / 256)
+    uint32_t n_all, n_mfma, n_plain;
+};
+// fl_echelon_d's set-up for one matrix (clears its bookkeeping on `stream`);
+// *task receives its table entry (npanels = 0 when there is nothing to do).
+fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt, uint64_t ldd,
+                             uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws,
+                             size_t ws_bytes, hipStream_t stream, FlEchTask *task);
+// Fills the three per-panel prefix tables of `lists` (device, P panels) from
+// the task table.
+hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &lists, uint32_t panels,
+                               uint32_t *pre_c256, uint32_t *pre_m128, uint32_t *pre_p256,
+                               hipStream_t stream);
+// Host mirror of the prefix tables' totals: workgroups of a column-tiled
+// kernel at panel P for a matrix with `cols` columns.
+inline uint32_t fl_ech_tiles(uint32_t cols, uint32_t P, uint32_t tile) {
+    const uint32_t c0 = 64 * P;
+    return cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
+}
+// Panel P of every listed matrix: the seven panel kernels.  n_active: the
+// leading entries of ids_all with more than P panels; grid_*: the prefix
+// totals at P; mfma_rows: the largest row count among the MFMA-form matrices.
+hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &lists,
+                                   uint32_t P, uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
+                                   uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
+                                   hipStream_t stream);
+// Moves the pivot rows of one matrix to the top in pivot order, clears the rest.
+fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream);

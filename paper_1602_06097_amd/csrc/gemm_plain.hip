@@ -1,112 +1,18 @@
-// gemm_plain.hip -- dense C = C - A B mod p on the vector ALUs.
-//
-// The dense contractions of the reduction (the rank-k trailing updates of the
-// Gauss-Jordan elimination of the Schur complement, the second FL pass, and
-// the dense form of C X) all have this shape.  One wave computes 8 rows x 256
-// columns (4 columns per lane).  The K dimension is walked in chunks of 64:
-// lane t holds A[row][k0 + t] for the wave's 8 rows, and each step broadcasts
-// one coefficient per row with v_readlane while every lane loads 4 residues of
-// one row of B.  Products use the split-coefficient 24-bit multiply-add with
-// folding at most every 256 terms.
+// gemm_plain.hip -- dense C = C - A B mod p on the vector ALUs (the tile is
+// in valu_tile.h).
 #include "fl_internal.h"
+#include "valu_tile.h"
 
 namespace {
 
-constexpr int kRowsPerWave = 8;
-constexpr int kColsPerWave = 256;
+using namespace fl_valu;
 
 __global__ __launch_bounds__(256) void k_gemm_sub(fl::Mod md, uint32_t M, uint32_t N, uint32_t Kh,
                                                   const uint32_t *__restrict__ Kdev,
                                                   const uint16_t *__restrict__ A, uint64_t lda,
                                                   const uint16_t *__restrict__ B, uint64_t ldb,
                                                   uint16_t *C, uint64_t ldc) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t row0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kRowsPerWave;
-    if (row0 >= M) return;
-    const uint32_t K = Kdev ? *Kdev : Kh;
-    if (K == 0) return;
-    const uint32_t c0 = blockIdx.x * kColsPerWave + lane * 4;
-    const bool colok = c0 < N;
-    uint32_t ah[kRowsPerWave][4], al[kRowsPerWave][4];
-#pragma unroll
-    for (int r = 0; r < kRowsPerWave; r++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) ah[r][c] = al[r][c] = 0;
-    uint32_t terms = 0;
-    for (uint32_t k0 = 0; k0 < K; k0 += 64) {
-        const uint32_t chunk = K - k0 < 64 ? K - k0 : 64;
-        uint32_t a[kRowsPerWave];
-#pragma unroll
-        for (int r = 0; r < kRowsPerWave; r++)
-            a[r] = (row0 + r < M && lane < chunk) ? A[(uint64_t)(row0 + r) * lda + k0 + lane] : 0;
-        uint32_t t = 0;
-        for (; t + 2 <= chunk; t += 2) {
-            uint64_t bv[2];
-#pragma unroll
-            for (int u = 0; u < 2; u++)
-                bv[u] = colok ? *(const uint64_t *)(B + (uint64_t)(k0 + t + u) * ldb + c0) : 0;
-#pragma unroll
-            for (int u = 0; u < 2; u++) {
-                uint32_t x[4] = {(uint32_t)bv[u] & 0xffffu, (uint32_t)(bv[u] >> 16) & 0xffffu,
-                                 (uint32_t)(bv[u] >> 32) & 0xffffu, (uint32_t)(bv[u] >> 48)};
-#pragma unroll
-                for (int r = 0; r < kRowsPerWave; r++) {
-                    uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)a[r], (int)(t + u));
-                    uint32_t lh = lam >> 8, ll = lam & 0xffu;
-#pragma unroll
-                    for (int c = 0; c < 4; c++) {
-                        ah[r][c] = fl::mad24(lh, x[c], ah[r][c]);
-                        al[r][c] = fl::mad24(ll, x[c], al[r][c]);
-                    }
-                }
-            }
-        }
-        for (; t < chunk; t++) {
-            uint64_t bv = colok ? *(const uint64_t *)(B + (uint64_t)(k0 + t) * ldb + c0) : 0;
-            uint32_t x[4] = {(uint32_t)bv & 0xffffu, (uint32_t)(bv >> 16) & 0xffffu,
-                             (uint32_t)(bv >> 32) & 0xffffu, (uint32_t)(bv >> 48)};
-#pragma unroll
-            for (int r = 0; r < kRowsPerWave; r++) {
-                uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)a[r], (int)t);
-                uint32_t lh = lam >> 8, ll = lam & 0xffu;
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    ah[r][c] = fl::mad24(lh, x[c], ah[r][c]);
-                    al[r][c] = fl::mad24(ll, x[c], al[r][c]);
-                }
-            }
-        }
-        terms += chunk;
-        if (terms > FL_FOLD_TERMS - 64) {
-#pragma unroll
-            for (int r = 0; r < kRowsPerWave; r++)
-#pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    al[r][c] = fl::fold_pair(ah[r][c], al[r][c], md);
-                    ah[r][c] = 0;
-                }
-            terms = 0;
-        }
-    }
-    if (!colok) return;
-#pragma unroll
-    for (int r = 0; r < kRowsPerWave; r++) {
-        if (row0 + r >= M) break;
-        uint16_t *o = C + (uint64_t)(row0 + r) * ldc + c0;
-        uint32_t s[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) s[c] = fl::fold_pair(ah[r][c], al[r][c], md);
-        if (c0 + 4 <= N) {
-            uint64_t ov = *(const uint64_t *)o;
-            uint64_t nv = 0;
-#pragma unroll
-            for (int c = 0; c < 4; c++)
-                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu, s[c], md.p) << (16 * c);
-            *(uint64_t *)o = nv;
-        } else {
-            for (int c = 0; c < 4 && c0 + c < N; c++) o[c] = (uint16_t)fl::submod(o[c], s[c], md.p);
-        }
-    }
+    valu_gemm_tile(md, M, N, Kh, Kdev, A, lda, B, ldb, C, ldc, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace

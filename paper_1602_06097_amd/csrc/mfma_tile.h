@@ -1,0 +1,279 @@
+// mfma_tile.h -- the int8-limb MFMA tiles shared by the GEMM kernels.
+//
+// Every residue x in [0, p), p <= 65521, is centred into
+//     r = x            if x <= 32639
+//     r = x - p        otherwise            (r in [-32881, 32639])
+// and split into two signed 8-bit limbs r = 256 h + l with
+//     h = floor((r + 128) / 256) in [-128, 127],  l = r - 256 h in [-128, 127].
+// Then  sum_k A B = 65536 S_hh + 256 (S_hl + S_lh) + S_ll  with four int8 GEMMs
+// accumulated exactly in int32 (v_mfma_i32_16x16x64_i8): |h h'| <= 2^14, so a
+// K-chunk of at most kKChunk = 65472 terms keeps |S_hh|, |S_ll| < 2^30 and the
+// shared middle accumulator |S_hl + S_lh| < 2^31.  Each partial is biased to
+// a non-negative 32-bit value (a multiple of p added), Barrett-reduced, and
+// recombined with 2^16 mod p and 2^8.  No floating point anywhere.
+//
+// The tiles are device functions so that both the one-problem kernels and
+// the kernels that serve many problems in one launch (one problem per
+// workgroup, looked up in a table) run the same code.
+#pragma once
+
+#include "fl_internal.h"
+
+namespace fl_mfma {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr uint32_t kKChunk = 65472;  // multiple of BK, < 65536
+constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conflicts
+constexpr int kOutLd = BN + 4;       // u16 row stride of the epilogue tile (8-byte aligned rows)
+constexpr int kGemmLds = 4 * BM * kLdsRow;  // bytes of LDS of one GEMM tile
+constexpr int kRank64Ld = 128 + 4;          // u16 row stride of the rank-k residue tile
+
+__device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint32_t bias) {
+    return fl::reduce32((uint32_t)s + bias, md);
+}
+
+// bias: the smallest multiple of p that is >= 2^31, so s + bias >= 0 and
+// s + bias < 2^32 for |s| < 2^31 - 2^16.
+inline uint32_t gemm_bias(uint32_t p) { return (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p); }
+inline uint32_t gemm_c16(uint32_t p) { return (uint32_t)((1u << 16) % p); }
+
+// 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 outputs per wave as
+// 4 x 4 tiles of 16 x 16.  The next K-tile is loaded into registers while
+// the current one is multiplied, so global latency overlaps the MFMAs.
+__device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                               const GemmPlanes &g, uint32_t bx, uint32_t by,
+                                               int8_t *smem) {
+    static_assert(BM * kOutLd * 2 <= kGemmLds, "epilogue tile must fit the operand buffers");
+    int8_t *sAh = smem, *sAl = smem + BM * kLdsRow;
+    int8_t *sBh = smem + 2 * BM * kLdsRow, *sBl = smem + 3 * BM * kLdsRow;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wm = wave >> 1, wn = wave & 1;
+    const uint32_t m0 = by * BM, n0 = bx * BN;
+    uint32_t kbeg = g.kbeg, kend = g.kend;
+    if (g.krange) {
+        kbeg = g.krange[2 * by];
+        kend = g.krange[2 * by + 1];
+    }
+    if (g.krange_n) {  // per column block: intersect
+        const uint32_t b = g.krange_n[2 * bx], e = g.krange_n[2 * bx + 1];
+        kbeg = b > kbeg ? b : kbeg;
+        kend = e < kend ? e : kend;
+    }
+    if (g.klen_dev) {
+        const uint32_t kd = (*g.klen_dev + BK - 1) / BK * BK;
+        if (kend > kd) kend = kd;
+    }
+    v4i acc_hh[4][4], acc_mid[4][4], acc_ll[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            acc_hh[i][j] = v4i{0, 0, 0, 0};
+            acc_mid[i][j] = v4i{0, 0, 0, 0};
+            acc_ll[i][j] = v4i{0, 0, 0, 0};
+        }
+    // each plane tile is 128 rows x 64 bytes = 512 chunks of 16 B; thread t
+    // moves chunks t and t + 256 of each of the four planes
+    const uint32_t r_lo = tid >> 2, q = (tid & 3) * 16;
+    const uint64_t a_off0 = (uint64_t)(m0 + r_lo) * g.lda + g.a_k0 + q;
+    const uint64_t a_off1 = (uint64_t)(m0 + r_lo + 64) * g.lda + g.a_k0 + q;
+    const uint64_t b_off0 = (uint64_t)(n0 + r_lo) * g.ldb + g.b_k0 + q;
+    const uint64_t b_off1 = (uint64_t)(n0 + r_lo + 64) * g.ldb + g.b_k0 + q;
+    v4i pf[8];
+    auto gload = [&](uint32_t k0) {
+        pf[0] = *(const v4i *)(g.Ah + a_off0 + k0);
+        pf[1] = *(const v4i *)(g.Al + a_off0 + k0);
+        pf[2] = *(const v4i *)(g.Bh + b_off0 + k0);
+        pf[3] = *(const v4i *)(g.Bl + b_off0 + k0);
+        pf[4] = *(const v4i *)(g.Ah + a_off1 + k0);
+        pf[5] = *(const v4i *)(g.Al + a_off1 + k0);
+        pf[6] = *(const v4i *)(g.Bh + b_off1 + k0);
+        pf[7] = *(const v4i *)(g.Bl + b_off1 + k0);
+    };
+    if (kbeg < kend) gload(kbeg);
+    const uint32_t s0 = r_lo * kLdsRow + q, s1 = (r_lo + 64) * kLdsRow + q;
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
+        *(v4i *)(sAh + s0) = pf[0];
+        *(v4i *)(sAl + s0) = pf[1];
+        *(v4i *)(sBh + s0) = pf[2];
+        *(v4i *)(sBl + s0) = pf[3];
+        *(v4i *)(sAh + s1) = pf[4];
+        *(v4i *)(sAl + s1) = pf[5];
+        *(v4i *)(sBh + s1) = pf[6];
+        *(v4i *)(sBl + s1) = pf[7];
+        __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);
+        v4i ah[4], al[4], bh[4], bl[4];
+        const uint32_t kq = (lane >> 4) * 16;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
+            const uint32_t rb = wn * 64 + t * 16 + (lane & 15);
+            ah[t] = *(const v4i *)(sAh + ra * kLdsRow + kq);
+            al[t] = *(const v4i *)(sAl + ra * kLdsRow + kq);
+            bh[t] = *(const v4i *)(sBh + rb * kLdsRow + kq);
+            bl[t] = *(const v4i *)(sBl + rb * kLdsRow + kq);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
+                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
+                acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    if (kbeg >= kend) return;  // nothing to subtract
+    // epilogue: residues of the 128 x 128 tile go through LDS (the operand
+    // buffers are free now), then C is read, reduced and written back with
+    // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
+    // column lane%16) of each 16 x 16 tile is held by the wave.
+    uint16_t *sOut = (uint16_t *)smem;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t col = wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t row = wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                const uint32_t rhh = signed_to_res(acc_hh[i][j][e], md, bias);
+                const uint32_t rmid = signed_to_res(acc_mid[i][j][e], md, bias);
+                const uint32_t rll = signed_to_res(acc_ll[i][j][e], md, bias);
+                uint32_t v = fl::reduce32(rhh * c16 + rll, md);
+                v = fl::reduce32(v + rmid * 256u, md);
+                sOut[row * kOutLd + col] = (uint16_t)v;
+            }
+        }
+    __syncthreads();
+    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each, in
+    // batches of 4 whose C loads are issued before their stores
+#pragma unroll 1
+    for (int u0 = 0; u0 < 16; u0 += 4) {
+        uint64_t cvals[4];
+        uint32_t orows[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t ch = tid + (u0 + u) * 256;
+            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+            const uint32_t row = m0 + r, col = n0 + c4;
+            cvals[u] = 0;
+            orows[u] = 0xffffffffu;
+            if (row < g.M && col < g.N) {
+                orows[u] = g.row_map ? g.row_map[row] : row;
+                if (orows[u] != 0xffffffffu && col + 4 <= g.N)
+                    cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orows[u] * g.ldc + col);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t ch = tid + (u0 + u) * 256;
+            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+            const uint32_t col = n0 + c4;
+            if (orows[u] == 0xffffffffu) continue;
+            uint16_t *o = g.C + (uint64_t)orows[u] * g.ldc + col;
+            const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
+            if (col + 4 <= g.N) {
+                const uint64_t ov = cvals[u];
+                uint64_t nv = 0;
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
+                                               (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+                *(uint64_t *)o = nv;
+            } else {
+                for (uint32_t c = 0; col + c < g.N; c++)
+                    o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
+            }
+        }
+    }
+}
+
+// Rank-k update, k <= 64 (the Gauss-Jordan panel updates): one MFMA K-step,
+// so the kernel is bound by the read-modify-write of C and its epilogue.  A
+// block owns 64 rows x 128 columns; rows are taken through an optional row
+// list (row_map, count *Mdev: only rows with nonzero multipliers), the C tile
+// is loaded first with row-contiguous 8-byte accesses (latency overlapping
+// the operand loads and MFMAs), residues are staged through LDS and C is
+// written back with 8-byte accesses.  A planes are indexed by the C row.
+// With K <= 64, |S_hh|, |S_ll| <= 2^20 and |S_mid| <= 2^21, so
+// 256 S_mid + S_ll fits 32 bits and the recombination needs three Barrett
+// reductions instead of five.
+// One 64-row x 128-column tile (row block by, column block bx) of the
+// rank-k update; M rows in total.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in
+// LDS.  Callers looping over row blocks must synchronise between tiles.
+__device__ __forceinline__ void mfma_rank64_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                 const int8_t *__restrict__ Ah,
+                                                 const int8_t *__restrict__ Al,
+                                                 const int8_t *__restrict__ Bh,
+                                                 const int8_t *__restrict__ Bl,
+                                                 const uint32_t *__restrict__ row_map, uint32_t M,
+                                                 uint16_t *C, uint64_t ldc, uint32_t N, uint32_t bx,
+                                                 uint32_t by, uint16_t *sv, uint32_t *rows_s) {
+    constexpr int kLd = kRank64Ld;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t m0 = by * 64, n0 = bx * 128;
+    if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
+    __syncthreads();
+    // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread
+    uint64_t cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t row = rows_s[r], col = n0 + c4;
+        cv[u] = 0;
+        if (row != 0xffffffffu && col + 4 <= N) cv[u] = *(const uint64_t *)(C + (uint64_t)row * ldc + col);
+    }
+    const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
+    const uint32_t arow = rows_s[wave * 16 + cl];
+    v4i ah = {0, 0, 0, 0}, al = {0, 0, 0, 0};
+    if (arow != 0xffffffffu) {
+        ah = *(const v4i *)(Ah + (uint64_t)arow * 64 + kq);
+        al = *(const v4i *)(Al + (uint64_t)arow * 64 + kq);
+    }
+    const uint32_t bias2 = (uint32_t)(((1u << 30) + md.p - 1) / md.p * md.p);  // >= 2^30, multiple of p
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const uint64_t b = (uint64_t)(n0 + j * 16 + cl) * 64 + kq;
+        const v4i bh = *(const v4i *)(Bh + b);
+        const v4i bl = *(const v4i *)(Bl + b);
+        v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+        hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bh, hh, 0, 0, 0);
+        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bl, mid, 0, 0, 0);
+        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bh, mid, 0, 0, 0);
+        ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bl, ll, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t rhh = signed_to_res(hh[e], md, bias);
+            const uint32_t rlo = fl::reduce32((uint32_t)(mid[e] * 256 + ll[e]) + bias2, md);
+            const uint32_t v = fl::reduce32(rhh * c16 + rlo, md);
+            sv[(wave * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t row = rows_s[r], col = n0 + c4;
+        if (row == 0xffffffffu || col >= N) continue;
+        const uint64_t s4 = *(const uint64_t *)(sv + r * kLd + c4);
+        uint16_t *o = C + (uint64_t)row * ldc + col;
+        if (col + 4 <= N) {
+            uint64_t nv = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                nv |= (uint64_t)fl::submod((uint32_t)(cv[u] >> (16 * c)) & 0xffffu,
+                                           (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+            *(uint64_t *)o = nv;
+        } else {
+            for (uint32_t c = 0; col + c < N; c++)
+                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p);
+        }
+    }
+}
+
+}  // namespace fl_mfma

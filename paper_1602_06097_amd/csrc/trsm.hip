@@ -16,10 +16,11 @@
 // 24-bit multiply-adds into two 32-bit accumulators, folded mod p at most
 // every 256 terms (see fl_internal.h for the bound).
 #include "fl_internal.h"
+#include "mfma_tile.h"
 
 namespace {
 
-constexpr uint32_t kTrsmBlock = 128;  // rows per TRSM block (multiple of 8)
+constexpr uint32_t kTrsmBlock = kFlTrsmBlock;  // rows per TRSM block (multiple of 8)
 constexpr int kTile = 256;            // columns per wave in k_ml_spmm (4 per lane)
 
 // ---- CSR rows -> dense rows (out zeroed beforehand) ------------------------------
@@ -94,17 +95,17 @@ __device__ __forceinline__ uint64_t first_at_least(const uint32_t *__restrict__ 
 // for groups g in [g0, g0 + ngroups), rows < row_limit, columns < ncols.
 // One wave per (group, 256-column tile); blockIdx.y picks 4 consecutive groups.
 template <int W>
-__global__ __launch_bounds__(256) void k_ml_spmm(fl::Mod md, const uint64_t *__restrict__ gptr,
-                                                 const uint32_t *__restrict__ pos,
-                                                 const uint16_t *__restrict__ val, uint32_t g0,
-                                                 uint32_t ngroups, uint32_t row_limit,
-                                                 uint32_t pos_lo, const uint16_t *X, uint64_t ldx,
-                                                 uint16_t *out, uint64_t ldo, uint32_t ncols) {
+__device__ __forceinline__ void ml_spmm_tile(const fl::Mod &md, const uint64_t *__restrict__ gptr,
+                                             const uint32_t *__restrict__ pos,
+                                             const uint16_t *__restrict__ val, uint32_t g0,
+                                             uint32_t ngroups, uint32_t row_limit, uint32_t pos_lo,
+                                             const uint16_t *X, uint64_t ldx, uint16_t *out,
+                                             uint64_t ldo, uint32_t ncols, uint32_t bx, uint32_t by) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t gi = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const uint32_t gi = by * 4 + (threadIdx.x >> 6);
     if (gi >= ngroups) return;
     const uint32_t g = g0 + gi;
-    const uint32_t c0 = blockIdx.x * kTile + lane * 4;
+    const uint32_t c0 = bx * kTile + lane * 4;
     const bool colok = c0 < ncols;
     uint64_t kb = gptr[g], ke = gptr[g + 1];
     if (pos_lo) kb = first_at_least(pos, kb, ke, pos_lo);
@@ -197,6 +198,17 @@ __global__ __launch_bounds__(256) void k_ml_spmm(fl::Mod md, const uint64_t *__r
             for (int c = 0; c < 4 && c0 + c < ncols; c++) o[c] = (uint16_t)fl::submod(o[c], s[c], md.p);
         }
     }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_ml_spmm(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                 const uint32_t *__restrict__ pos,
+                                                 const uint16_t *__restrict__ val, uint32_t g0,
+                                                 uint32_t ngroups, uint32_t row_limit,
+                                                 uint32_t pos_lo, const uint16_t *X, uint64_t ldx,
+                                                 uint16_t *out, uint64_t ldo, uint32_t ncols) {
+    ml_spmm_tile<W>(md, gptr, pos, val, g0, ngroups, row_limit, pos_lo, X, ldx, out, ldo, ncols, blockIdx.x,
+                    blockIdx.y);
 }
 
 // For every multiline group g of A: nin[g] = number of its entries inside
@@ -322,14 +334,13 @@ __device__ void solve_groups(const fl::Mod &md, const Entries<W, STAGED> &E, uin
 // correction between its own rows.  Entries at positions >= r1 were applied
 // by the preceding update launch.
 template <int W>
-__global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *__restrict__ gptr,
-                                                   const uint32_t *__restrict__ pos,
-                                                   const uint16_t *__restrict__ val,
-                                                   const uint32_t *__restrict__ nin_a,
-                                                   const uint32_t *__restrict__ nnear_a, uint32_t r0,
-                                                   uint32_t r1, uint16_t *X, uint64_t ldx,
-                                                   uint32_t ncols, int8_t *Xth, int8_t *Xtl,
-                                                   uint64_t kp) {
+__device__ __forceinline__ void trsm_solve_tile(const fl::Mod &md, const uint64_t *__restrict__ gptr,
+                                                const uint32_t *__restrict__ pos,
+                                                const uint16_t *__restrict__ val,
+                                                const uint32_t *__restrict__ nin_a,
+                                                const uint32_t *__restrict__ nnear_a, uint32_t r0,
+                                                uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t ncols,
+                                                int8_t *Xth, int8_t *Xtl, uint64_t kp, uint32_t bx) {
     constexpr uint32_t kG = kTrsmBlock / W;
     __shared__ __attribute__((aligned(16))) uint16_t blk[kTrsmBlock][64];
     __shared__ uint32_t s_off[kG + 1];
@@ -338,7 +349,7 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
     __shared__ uint32_t s_pos[kNearCap];
     __shared__ uint16_t s_val[kNearCap * W];
     const uint32_t lane = threadIdx.x;
-    const uint32_t c0 = blockIdx.x * 64;
+    const uint32_t c0 = bx * 64;
     const uint32_t c = c0 + lane;
     const bool colok = c < ncols;
     const uint32_t gfirst = r0 / W, glast = (r1 + W - 1) / W, ng = glast - gfirst;
@@ -420,6 +431,79 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
             }
         }
     }
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                   const uint32_t *__restrict__ pos,
+                                                   const uint16_t *__restrict__ val,
+                                                   const uint32_t *__restrict__ nin_a,
+                                                   const uint32_t *__restrict__ nnear_a, uint32_t r0,
+                                                   uint32_t r1, uint16_t *X, uint64_t ldx,
+                                                   uint32_t ncols, int8_t *Xth, int8_t *Xtl,
+                                                   uint64_t kp) {
+    trsm_solve_tile<W>(md, gptr, pos, val, nin_a, nnear_a, r0, r1, X, ldx, ncols, Xth, Xtl, kp, blockIdx.x);
+}
+
+// ---- many TRSMs at once: step `step` solves block nblk - 1 - step of every
+// matrix in the task table (matrices with fewer blocks are finished) --------
+
+// Rows [r0, r1) of the task's block for this step; false if none.
+__device__ __forceinline__ bool step_block(const FlTrsmTask &t, uint32_t step, uint32_t &I, uint32_t &r0,
+                                           uint32_t &r1) {
+    if (step >= t.nblk) return false;
+    I = t.nblk - 1 - step;
+    r0 = I * kTrsmBlock;
+    r1 = r0 + kTrsmBlock < t.npiv ? r0 + kTrsmBlock : t.npiv;
+    return true;
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_trsm_solve_b(fl::Mod md, const FlTrsmTask *__restrict__ tasks,
+                                                     const uint32_t *__restrict__ ids,
+                                                     const uint32_t *__restrict__ prefix, uint32_t n,
+                                                     uint32_t step) {
+    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
+    const FlTrsmTask &t = tasks[ids[i]];
+    uint32_t I, r0, r1;
+    if (!step_block(t, step, I, r0, r1)) return;
+    trsm_solve_tile<W>(md, t.gptr, t.pos, t.val, t.nin, t.nnear, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp,
+                       blockIdx.x - prefix[i]);
+}
+
+// Far update of the step's block, VALU form: workgroup (bx, by) of the task as
+// in k_ml_spmm, flattened as by * ceil(nB / 256) + bx.
+template <int W>
+__global__ __launch_bounds__(256) void k_trsm_update_b(fl::Mod md, const FlTrsmTask *__restrict__ tasks,
+                                                       const uint32_t *__restrict__ ids,
+                                                       const uint32_t *__restrict__ prefix, uint32_t n,
+                                                       uint32_t step) {
+    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
+    const FlTrsmTask &t = tasks[ids[i]];
+    uint32_t I, r0, r1;
+    if (!step_block(t, step, I, r0, r1) || r1 >= t.npiv) return;
+    const uint32_t local = blockIdx.x - prefix[i], ct = (t.nB + kTile - 1) / kTile;
+    const uint32_t g0 = r0 / W, ng = (r1 + W - 1) / W - g0;
+    ml_spmm_tile<W>(md, t.gptr, t.pos, t.val, g0, ng, r1, r1, t.X, t.ldx, t.X, t.ldx, t.nB, local % ct,
+                    local / ct);
+}
+
+// Far update of the step's block, int8-MFMA form: one 128-column tile of the
+// band GEMM per workgroup.
+__global__ __launch_bounds__(256) void k_trsm_update_mfma_b(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                            const FlTrsmTask *__restrict__ tasks,
+                                                            const uint32_t *__restrict__ ids,
+                                                            const uint32_t *__restrict__ prefix,
+                                                            uint32_t n, uint32_t step) {
+    __shared__ __attribute__((aligned(16))) int8_t smem[fl_mfma::kGemmLds];
+    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
+    const FlTrsmTask &t = tasks[ids[i]];
+    uint32_t I, r0, r1;
+    if (!step_block(t, step, I, r0, r1) || r1 >= t.npiv) return;
+    const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1, r1,
+                          0, (uint32_t)(t.kp - r1), t.kext + I, nullptr, nullptr, nullptr,
+                          t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB};
+    fl_mfma::mfma_gemm_tile(md, bias, c16, g, blockIdx.x - prefix[i], 0, smem);
 }
 
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
@@ -597,14 +681,25 @@ extern "C" size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode) {
     return trsm_layout(info, mode, nullptr, nullptr);
 }
 
-extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X,
-                             uint64_t ldx, fl_mode mode, void *ws, size_t ws_bytes,
-                             hipStream_t stream) {
+fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
+                          fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream, FlTrsmTask *task) {
     fl_status st = check_split_info(info, s);
     if (st != FL_OK) return st;
     FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_trsm: bad mode");
     const uint32_t npiv = info->npiv, nB = info->nB, w = info->ml_width;
-    if (npiv == 0 || nB == 0) return FL_OK;
+    FlTrsmTask t = {};
+    t.npiv = npiv;
+    t.nB = nB;
+    t.X = X;
+    t.ldx = ldx;
+    t.mfma = mode == FL_MFMA_I8;
+    t.gptr = s->a_gptr;
+    t.pos = s->a_pos;
+    t.val = s->a_val;
+    if (npiv == 0 || nB == 0) {
+        *task = t;  // nblk = 0: nothing to do
+        return FL_OK;
+    }
     FL_ARG(X, "fl_trsm: NULL X");
     FL_ARG(ldx >= nB && ldx % 4 == 0, "fl_trsm: ldx must be >= nB and a multiple of 4");
     FL_ARG(((uintptr_t)X & 7) == 0, "fl_trsm: X must be 8-byte aligned");
@@ -614,18 +709,16 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         fl_set_error("fl_trsm: workspace too small");
         return FL_ERR_WORKSPACE;
     }
-    const fl::Mod md = fl::make_mod(info->p);
     hipError_t e0;
     FL_PROF("trsm.densify", stream, e0 = csr_to_dense(npiv, nB, s->b_ptr, s->b_col, s->b_val, X, ldx, stream));
     FL_HIP(e0);
     const uint32_t nblk = (npiv + kTrsmBlock - 1) / kTrsmBlock;
-    const bool mfma = mode == FL_MFMA_I8;
     const uint32_t ngroups = (npiv + w - 1) / w;
     FL_PROF("trsm.bounds", stream,
             hipLaunchKernelGGL(k_trsm_bounds, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, npiv, ngroups,
                                (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.nin, tw.nnear));
     FL_LAUNCH_CHECK("k_trsm_bounds");
-    if (mfma) {
+    if (t.mfma) {
         FL_PROF("trsm.tiles", stream, {
             hipLaunchKernelGGL(k_trsm_kext, dim3((nblk + 255) / 256), dim3(256), 0, stream, w, npiv,
                                nblk, (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.kext);
@@ -637,14 +730,63 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         });
         FL_LAUNCH_CHECK("trsm tiles");
     }
-    for (uint32_t I = nblk; I-- > 0;) {
+    t.nblk = nblk;
+    t.nin = tw.nin;
+    t.nnear = tw.nnear;
+    t.Ah = tw.Ah;
+    t.Al = tw.Al;
+    t.Xh = tw.Xh;
+    t.Xl = tw.Xl;
+    t.kext = tw.kext;
+    t.kp = tw.kp;
+    *task = t;
+    return FL_OK;
+}
+
+hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
+                                const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,
+                                uint32_t step, hipStream_t stream) {
+    if (n == 0 || grid == 0) return hipSuccess;
+    const fl::Mod md = fl::make_mod(p);
+    if (kind == 2) {
+        switch (w) {
+        case 1: hipLaunchKernelGGL(k_trsm_solve_b<1>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 2: hipLaunchKernelGGL(k_trsm_solve_b<2>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 4: hipLaunchKernelGGL(k_trsm_solve_b<4>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
+        default: hipLaunchKernelGGL(k_trsm_solve_b<8>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
+        }
+    } else if (step == 0) {
+        return hipSuccess;  // the bottom blocks have nothing below them
+    } else if (kind == 1) {
+        hipLaunchKernelGGL(k_trsm_update_mfma_b, dim3(grid), dim3(256), 0, stream, md, fl_mfma::gemm_bias(p),
+                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step);
+    } else {
+        switch (w) {
+        case 1: hipLaunchKernelGGL(k_trsm_update_b<1>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 2: hipLaunchKernelGGL(k_trsm_update_b<2>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 4: hipLaunchKernelGGL(k_trsm_update_b<4>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
+        default: hipLaunchKernelGGL(k_trsm_update_b<8>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X,
+                             uint64_t ldx, fl_mode mode, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+    FlTrsmTask t;
+    fl_status st = fl_trsm_prepare(info, s, X, ldx, mode, ws, ws_bytes, stream, &t);
+    if (st != FL_OK || t.nblk == 0) return st;
+    const fl::Mod md = fl::make_mod(info->p);
+    const uint32_t npiv = t.npiv, nB = t.nB, w = info->ml_width;
+    for (uint32_t I = t.nblk; I-- > 0;) {
         const uint32_t r0 = I * kTrsmBlock;
         const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
         if (r1 < npiv) {
             hipError_t e;
-            if (mfma) {
-                GemmPlanes gp = {tw.Ah + (uint64_t)r0 * tw.kp, tw.Al + (uint64_t)r0 * tw.kp, tw.Xh, tw.Xl,
-                                 tw.kp, tw.kp, r1, r1, 0, (uint32_t)(tw.kp - r1), tw.kext + I, nullptr,
+            if (t.mfma) {
+                GemmPlanes gp = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl,
+                                 t.kp, t.kp, r1, r1, 0, (uint32_t)(t.kp - r1), t.kext + I, nullptr,
                                  nullptr, nullptr, X + (uint64_t)r0 * ldx, ldx, r1 - r0, nB};
                 e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
             } else {
@@ -657,8 +799,8 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         }
         hipError_t e;
         FL_PROF("trsm.solve", stream,
-                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, r0, r1, X, ldx, nB,
-                               stream, mfma ? tw.Xh : nullptr, mfma ? tw.Xl : nullptr, tw.kp));
+                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, t.nin, t.nnear, r0, r1, X, ldx, nB,
+                               stream, t.mfma ? t.Xh : nullptr, t.mfma ? t.Xl : nullptr, t.kp));
         FL_HIP(e);
     }
     return FL_OK;
