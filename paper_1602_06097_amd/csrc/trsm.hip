@@ -40,6 +40,7 @@ template <int W> struct MlVals;
 template <> struct MlVals<1> {
     uint32_t v;
     __device__ void load(const uint16_t *val, uint64_t k) { v = val[k]; }
+    __device__ uint16_t raw(int q) const { (void)q; return (uint16_t)v; }
     __device__ uint32_t get(int j, int q) const {
         (void)q;
         return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
@@ -48,6 +49,7 @@ template <> struct MlVals<1> {
 template <> struct MlVals<2> {
     uint32_t v;
     __device__ void load(const uint16_t *val, uint64_t k) { v = *(const uint32_t *)(val + 2 * k); }
+    __device__ uint16_t raw(int q) const { return (uint16_t)(q ? v >> 16 : v); }
     __device__ uint32_t get(int j, int q) const {
         uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
         return q ? s >> 16 : s & 0xffffu;
@@ -58,6 +60,10 @@ template <> struct MlVals<4> {
     __device__ void load(const uint16_t *val, uint64_t k) {
         uint64_t x = *(const uint64_t *)(val + 4 * k);
         v0 = (uint32_t)x; v1 = (uint32_t)(x >> 32);
+    }
+    __device__ uint16_t raw(int q) const {
+        const uint32_t s = q < 2 ? v0 : v1;
+        return (uint16_t)((q & 1) ? s >> 16 : s);
     }
     __device__ uint32_t get(int j, int q) const {
         uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)(q < 2 ? v0 : v1), j);
@@ -70,6 +76,7 @@ template <> struct MlVals<8> {
         uint4 x = *(const uint4 *)(val + 8 * k);
         v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     }
+    __device__ uint16_t raw(int q) const { return (uint16_t)((q & 1) ? v[q >> 1] >> 16 : v[q >> 1]); }
     __device__ uint32_t get(int j, int q) const {
         uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)v[q >> 1], j);
         return (q & 1) ? s >> 16 : s & 0xffffu;
@@ -364,11 +371,23 @@ __device__ __forceinline__ void trsm_solve_tile(const fl::Mod &md, const uint64_
     // l/16, l/16 + 4, ... (16 lanes per row)
     const uint32_t tr = lane >> 4, tc = (lane & 15) * 4;
     const bool vec = c0 + tc + 4 <= ncols;
-    for (uint32_t r = tr; r < nrow; r += 4) {
-        const uint16_t *src = X + (uint64_t)(r0 + r) * ldx + c0 + tc;
-        if (vec) *(uint64_t *)&blk[r][tc] = *(const uint64_t *)src;
-        else
+    if (vec) {
+        // all 32 loads in flight before the first LDS store
+        constexpr int kR = kTrsmBlock / 4;
+        uint64_t tv[kR];
+#pragma unroll
+        for (int k = 0; k < kR; k++) {
+            const uint32_t r = tr + 4 * k;
+            tv[k] = r < nrow ? *(const uint64_t *)(X + (uint64_t)(r0 + r) * ldx + c0 + tc) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kR; k++)
+            if (tr + 4 * k < nrow) *(uint64_t *)&blk[tr + 4 * k][tc] = tv[k];
+    } else {
+        for (uint32_t r = tr; r < nrow; r += 4) {
+            const uint16_t *src = X + (uint64_t)(r0 + r) * ldx + c0 + tc;
             for (uint32_t k = 0; k < 4; k++) blk[r][tc + k] = c0 + tc + k < ncols ? src[k] : 0;
+        }
     }
     __syncthreads();
     if (lane == 0) {
@@ -378,17 +397,28 @@ __device__ __forceinline__ void trsm_solve_tile(const fl::Mod &md, const uint64_
     __syncthreads();
     const uint32_t total = s_off[ng];
     if (total <= kNearCap) {
-        for (uint32_t f = lane; f < total; f += 64) {
-            uint32_t lo = 0, hi = ng;  // group of staged entry f
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_off[mid] <= f) lo = mid;
-                else hi = mid;
-            }
-            const uint64_t k = s_kb[lo] + (f - s_off[lo]);
-            s_pos[f] = pos[k];
+        // one lane per group: its entries are contiguous in A; 8 loads per
+        // round in flight
+        for (uint32_t gi = lane; gi < ng; gi += 64) {
+            const uint32_t cnt = s_off[gi + 1] - s_off[gi], o = s_off[gi];
+            const uint64_t kb = s_kb[gi];
+            for (uint32_t j0 = 0; j0 < cnt; j0 += 8) {
+                uint32_t pv[8];
+                MlVals<W> vv[8];
 #pragma unroll
-            for (int q = 0; q < W; q++) s_val[f * W + q] = val[(uint64_t)W * k + q];
+                for (int u = 0; u < 8; u++)
+                    if (j0 + u < cnt) {
+                        pv[u] = pos[kb + j0 + u];
+                        vv[u].load(val, kb + j0 + u);
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (j0 + u < cnt) {
+                        s_pos[o + j0 + u] = pv[u];
+#pragma unroll
+                        for (int q = 0; q < W; q++) s_val[(o + j0 + u) * W + q] = vv[u].raw(q);
+                    }
+            }
         }
         __syncthreads();
         Entries<W, true> E{s_pos, s_val, s_off, s_kb, pos, val};
