@@ -27,7 +27,10 @@ constexpr int BM = 128, BN = 128, BK = 64;
 constexpr uint32_t kKChunk = 65472;  // multiple of BK, < 65536
 constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conflicts
 constexpr int kOutLd = BN + 4;       // u16 row stride of the epilogue tile (8-byte aligned rows)
-constexpr int kGemmLds = 4 * BM * kLdsRow;  // bytes of LDS of one GEMM tile
+constexpr uint32_t kStages = 4;                 // operand ring depth (K steps)
+constexpr uint32_t kPlaneBytes = BM * BK;       // one plane tile: 128 rows x 64 bytes
+constexpr uint32_t kStageBytes = 4 * kPlaneBytes;
+constexpr int kGemmLds = kStages * kStageBytes;  // bytes of LDS of one GEMM tile
 constexpr int kRank64Ld = 128 + 4;          // u16 row stride of the rank-k residue tile
 
 __device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint32_t bias) {
@@ -46,8 +49,6 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                                                const GemmPlanes &g, uint32_t bx, uint32_t by,
                                                int8_t *smem) {
     static_assert(BM * kOutLd * 2 <= kGemmLds, "epilogue tile must fit the operand buffers");
-    int8_t *sAh = smem, *sAl = smem + BM * kLdsRow;
-    int8_t *sBh = smem + 2 * BM * kLdsRow, *sBl = smem + 3 * BM * kLdsRow;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t wm = wave >> 1, wn = wave & 1;
     const uint32_t m0 = by * BM, n0 = bx * BN;
@@ -74,47 +75,66 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             acc_mid[i][j] = v4i{0, 0, 0, 0};
             acc_ll[i][j] = v4i{0, 0, 0, 0};
         }
-    // each plane tile is 128 rows x 64 bytes = 512 chunks of 16 B; thread t
-    // moves chunks t and t + 256 of each of the four planes
-    const uint32_t r_lo = tid >> 2, q = (tid & 3) * 16;
-    const uint64_t a_off0 = (uint64_t)(m0 + r_lo) * g.lda + g.a_k0 + q;
-    const uint64_t a_off1 = (uint64_t)(m0 + r_lo + 64) * g.lda + g.a_k0 + q;
-    const uint64_t b_off0 = (uint64_t)(n0 + r_lo) * g.ldb + g.b_k0 + q;
-    const uint64_t b_off1 = (uint64_t)(n0 + r_lo + 64) * g.ldb + g.b_k0 + q;
-    v4i pf[8];
-    auto gload = [&](uint32_t k0) {
-        pf[0] = *(const v4i *)(g.Ah + a_off0 + k0);
-        pf[1] = *(const v4i *)(g.Al + a_off0 + k0);
-        pf[2] = *(const v4i *)(g.Bh + b_off0 + k0);
-        pf[3] = *(const v4i *)(g.Bl + b_off0 + k0);
-        pf[4] = *(const v4i *)(g.Ah + a_off1 + k0);
-        pf[5] = *(const v4i *)(g.Al + a_off1 + k0);
-        pf[6] = *(const v4i *)(g.Bh + b_off1 + k0);
-        pf[7] = *(const v4i *)(g.Bl + b_off1 + k0);
+    // Operand pipeline: the four plane tiles of a K step (128 rows x 64 bytes
+    // each) are copied global -> LDS by the DMA path (global_load_lds, no
+    // registers involved) into a ring of kStages slots, issued kStages - 1
+    // steps ahead, so HBM latency is covered by several steps of MFMA work.
+    // A wave's DMA instruction fills a 1 KiB block (16 rows x 4 chunks of 16
+    // bytes, lane L -> row L / 4, slot L % 4); chunk c of row r sits in slot
+    // c ^ ((r >> 2) & 3) so that the 16-row reads below hit all LDS banks.
+    const uint32_t ring = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int8_t *)smem;
+    const uint32_t lrow = lane >> 2, lslot = lane & 3;
+    uint64_t goff[8];      // per DMA instruction of this wave: plane row offset + chunk
+    const int8_t *gbase[8];
+    uint32_t loff[8];      // LDS offset of the instruction's block within a slot
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint32_t plane = i >> 1, rb = wave * 2 + (i & 1);
+        const uint32_t r = rb * 16 + lrow;
+        const uint32_t c = lslot ^ ((r >> 2) & 3);
+        const bool isA = plane < 2;
+        gbase[i] = plane == 0 ? g.Ah : plane == 1 ? g.Al : plane == 2 ? g.Bh : g.Bl;
+        goff[i] = isA ? (uint64_t)(m0 + r) * g.lda + g.a_k0 + c * 16 : (uint64_t)(n0 + r) * g.ldb + g.b_k0 + c * 16;
+        loff[i] = plane * kPlaneBytes + rb * 1024;
+    }
+    // one K step into ring slot `slot` (steps past kend re-read the last valid
+    // step, so every step issues the same 8 instructions per wave)
+    auto issue = [&](uint32_t k0, uint32_t slot) {
+        const uint32_t kk = k0 < kend ? k0 : kend - BK;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int8_t *src = gbase[i] + goff[i] + kk;
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kStageBytes + loff[i]);
+            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory");
+        }
     };
-    if (kbeg < kend) gload(kbeg);
-    const uint32_t s0 = r_lo * kLdsRow + q, s1 = (r_lo + 64) * kLdsRow + q;
+    if (kbeg < kend) {
+#pragma unroll
+        for (uint32_t s = 0; s + 1 < kStages; s++) issue(kbeg + s * BK, s);
+    }
+    uint32_t slot = 0;
     for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
-        *(v4i *)(sAh + s0) = pf[0];
-        *(v4i *)(sAl + s0) = pf[1];
-        *(v4i *)(sBh + s0) = pf[2];
-        *(v4i *)(sBl + s0) = pf[3];
-        *(v4i *)(sAh + s1) = pf[4];
-        *(v4i *)(sAl + s1) = pf[5];
-        *(v4i *)(sBh + s1) = pf[6];
-        *(v4i *)(sBl + s1) = pf[7];
-        __syncthreads();
-        if (k0 + BK < kend) gload(k0 + BK);
+        // this step's slot is complete when at most the (kStages - 2) later
+        // steps' instructions are outstanding; the barrier extends that to
+        // every wave's instructions and retires the reads of the slot
+        // refilled next
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 2) * 8) : "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        issue(k0 + (kStages - 1) * BK, slot == 0 ? kStages - 1 : slot - 1);
+        const int8_t *st = smem + slot * kStageBytes;
         v4i ah[4], al[4], bh[4], bl[4];
-        const uint32_t kq = (lane >> 4) * 16;
+        const uint32_t kc = lane >> 4;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
             const uint32_t rb = wn * 64 + t * 16 + (lane & 15);
-            ah[t] = *(const v4i *)(sAh + ra * kLdsRow + kq);
-            al[t] = *(const v4i *)(sAl + ra * kLdsRow + kq);
-            bh[t] = *(const v4i *)(sBh + rb * kLdsRow + kq);
-            bl[t] = *(const v4i *)(sBl + rb * kLdsRow + kq);
+            const uint32_t oa = ra * 64 + ((kc ^ ((ra >> 2) & 3)) << 4);
+            const uint32_t ob = rb * 64 + ((kc ^ ((rb >> 2) & 3)) << 4);
+            ah[t] = *(const v4i *)(st + oa);
+            al[t] = *(const v4i *)(st + kPlaneBytes + oa);
+            bh[t] = *(const v4i *)(st + 2 * kPlaneBytes + ob);
+            bl[t] = *(const v4i *)(st + 3 * kPlaneBytes + ob);
         }
 #pragma unroll
         for (int i = 0; i < 4; i++)
@@ -125,8 +145,11 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                 acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
                 acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
             }
-        __syncthreads();
+        slot = slot + 1 == kStages ? 0 : slot + 1;
     }
+    // drain the DMA path before the ring is reused for the output tile
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
     if (kbeg >= kend) return;  // nothing to subtract
     // epilogue: residues of the 128 x 128 tile go through LDS (the operand
     // buffers are free now), then C is read, reduced and written back with
