@@ -209,6 +209,19 @@ fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_out *s, const
                          uint16_t *val, void *ws, size_t ws_bytes, hipStream_t stream);
 size_t fl_rref_csr_workspace(const fl_split_info *info);
 
+/* Sec. 4.3 (new order of operations): the same Dt = D - C A^{-1} B as
+ * fl_trsm + fl_reduce_cd, without forming X = A^{-1} B -- for callers that
+ * need only the echelon form of D and the rank of M.  C is reduced by A
+ * (its multipliers C' = C A^{-1} come from the blocked TRSM run on the
+ * transpose of A with the columns of C as right-hand sides, pivot order
+ * reversed) and Dt = D - C' B.  Dt: dense mD x nB (ld = ldd >= nB, ldd % 4
+ * == 0, 8-byte aligned), fully overwritten.  Bit-identical to fl_reduce_cd in
+ * both modes.  nnz(A) and nnz(C) must be below 2^31. */
+fl_status fl_reduce_neworder(const fl_split_info *info, const fl_split_out *s, uint16_t *Dt,
+                             uint64_t ldd, fl_mode mode, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+size_t fl_reduce_neworder_workspace(const fl_split_info *info, fl_mode mode);
+
 /* ---- dense contraction ------------------------------------------------------
  * fl_matmul_sub -- the dense form of the step-3 contraction:
  *     Dm = Dm - Cm * Xm mod p,  Cm: M x K (ld ldc), Xm: K x N (ld ldx),

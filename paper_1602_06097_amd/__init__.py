@@ -22,7 +22,7 @@ from dataclasses import dataclass
 
 import torch
 
-__all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd",
+__all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd", "reduce_neworder",
            "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp", "prof_report",
            "version", "Split", "Echelon", "Batch", "batch_plan", "batch_run", "batch_graph_build",
            "batch_graph_launch", "batch_results", "batch_autotune", "batch_config"]
@@ -86,6 +86,8 @@ def load():
         "fl_reduce_cd": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
                                     c_vp, c_sz, c_vp]),
         "fl_reduce_cd_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_reduce_neworder": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_reduce_neworder_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
         "fl_echelon_d": (ct.c_int, [c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_vp, ct.c_int, c_vp, c_sz,
                                     c_vp]),
         "fl_echelon_d_workspace": (c_sz, [c_u32, c_u32, ct.c_int]),
@@ -234,6 +236,18 @@ def reduce_cd(sp: Split, X: torch.Tensor, mode: int = FL_PLAIN) -> torch.Tensor:
     st = lib.fl_reduce_cd(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), X.shape[1], _ptr(Dt), ld,
                           mode, _ptr(ws), ws.numel(), _stream())
     _check(st, "fl_reduce_cd")
+    return Dt
+
+
+def reduce_neworder(sp: Split, mode: int = FL_PLAIN) -> torch.Tensor:
+    """Dt = D - C A^{-1} B without X (Sec. 4.3), dense (mD x ld) uint16."""
+    lib = load()
+    ld = _ld(sp.nB)
+    Dt = torch.empty((max(sp.mD, 1), ld), dtype=torch.int16, device=_dev())
+    ws = _ws(lib.fl_reduce_neworder_workspace(ct.byref(sp.info), mode))
+    st = lib.fl_reduce_neworder(ct.byref(sp.info), ct.byref(sp.out), _ptr(Dt), ld, mode, _ptr(ws), ws.numel(),
+                                _stream())
+    _check(st, "fl_reduce_neworder")
     return Dt
 
 

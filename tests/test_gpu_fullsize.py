@@ -163,6 +163,20 @@ def test_fullsize_reduce_equals_planted_schur_complement(full):
         assert np.array_equal(got, g["Dt"][r0:r1].toarray().astype(np.uint16)), f"rows {r0}..{r1}"
 
 
+def test_fullsize_neworder_equals_planted_schur_complement(full):
+    """Sec. 4.3 at full size: D - C A^{-1} B without X, in the MFMA form."""
+    g, s, res = full["g"], full["s"], full["res"]
+    mD, nB = s["mD"], s["nB"]
+    Dt = fl.reduce_neworder(res["split"], fl.FL_MFMA_I8)
+    torch.cuda.synchronize()
+    step = 2048
+    for r0 in range(0, mD, step):
+        r1 = min(mD, r0 + step)
+        assert np.array_equal(_u16(Dt[r0:r1, :nB]), g["Dt"][r0:r1].toarray().astype(np.uint16)), f"rows {r0}..{r1}"
+    del Dt
+    torch.cuda.empty_cache()
+
+
 def test_fullsize_rref_d_equals_planted_V(full):
     g, s, res = full["g"], full["s"], full["res"]
     mD, nB = s["mD"], s["nB"]

@@ -347,3 +347,32 @@ def test_echelon_flagged_rows_never_dropped(mode):
     assert np.array_equal(u32(ech.pivcol)[:rank], pc)
     assert np.array_equal(u16(T)[:rank], R[:rank])
     assert not u16(T)[rank:].any()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("w", [1, 2, 4])
+@pytest.mark.parametrize("mode", MODES)
+def test_reduce_neworder_parity(name, w, mode):
+    """Sec. 4.3: D - C A^{-1} B without X, equal to the oracle's reduction
+    (which itself equals the paper's row-by-row Algorithm of Sec. 4.3)."""
+    g, r = CASES[name], ref(name)
+    s = r["split"]
+    sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=w)
+    Dt = fl.reduce_neworder(sp, mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(u16(Dt)[:s["mD"], :s["nB"]], r["Dt"])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_reduce_neworder_many_blocks(mode):
+    """Several TRSM blocks in the transposed solve, a K range beyond one
+    128-column tile, and rank-only use: RREF of the new-order Dt."""
+    g = flgen.fl_matrix(m=1500, n=1800, npiv=1100, rank_d=250, density=0.04, p=65521, seed=41)
+    r = oracle.fl_rref(g)
+    sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=2)
+    Dt = fl.reduce_neworder(sp, mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(u16(Dt)[:sp.mD, :sp.nB], r["Dt"])
+    ech = fl.echelon_d(Dt, g["p"], sp.mD, sp.nB, mode)
+    torch.cuda.synchronize()
+    assert int(u32(ech.rank)[0]) == r["rank_d"]
