@@ -327,6 +327,44 @@ fl_status fl_batch_autotune(const fl_csr *Ms, uint32_t count, uint32_t p, void *
                             fl_batch_config *best, double *best_ms, hipStream_t stream);
 void fl_batch_free(fl_batch *plan);
 
+/* ---- matrix files (Sec. 3.2) ------------------------------------------------------
+ * Format 1: m, n, p (u32), nnz (u64), data (u16 x nnz), cols (u32 x nnz), rows
+ *   (u32 x m, row lengths) -- CSR with row lengths.
+ * Format 2: b (u32: element type of pdata, bit 0 signed, bits 1-2 log2 of the
+ *   byte width, higher bits a version), m, n (u32), p, nnz (u64), rows (u32 x m),
+ *   polmap (u32 x m), k (u64), colid (u64 x k: a run of s > 1 consecutive
+ *   columns from f is the pair f, s; a single column f is f | 2^31), pnb
+ *   (u32), pnnz (u64), prow (u32 x pnb, polynomial sizes), pdata (pnnz
+ *   elements); row i's coefficients are those of polynomial polmap[i].
+ * fl_file_layout_parse reads the header of a file image in HOST memory,
+ * checks that the file holds every section and that the sizes agree (row
+ * lengths add up to nnz; Format 2: polynomial sizes add up to pnnz, every row
+ * names a polynomial of its own length), and returns the byte offset of each
+ * section.  Errors: FL_ERR_ARG with a message.
+ * fl_file_decode builds the CSR of M on the device from the sections copied
+ * to device memory (d_sections: Format 1 {data, cols, rows}, Format 2 {rows,
+ * polmap, colid, prow, pdata}).  Format 1: writes row_ptr[m + 1] only (data
+ * and cols ARE val and col).  Format 2: writes row_ptr[m + 1], col[nnz],
+ * val[nnz] (coefficients reduced mod p).  *d_status (device) receives 0, or a
+ * bit mask: 1 a run without its length, 2 runs beyond nnz or n, 4 a row whose
+ * polynomial is missing or of another length.  Column order, range and zero
+ * values are checked later by fl_split's validation. */
+typedef struct {
+    uint32_t format;            /* 1 or 2 */
+    uint32_t m, n;
+    uint64_t p, nnz;
+    uint32_t b, elem_bytes, elem_signed, version;   /* Format 2 */
+    uint64_t k, pnb, pnnz;                          /* Format 2 */
+    uint64_t off_data, off_cols, off_rows;          /* byte offsets in the file */
+    uint64_t off_polmap, off_colid, off_prow, off_pdata;
+    uint64_t bytes;             /* size implied by the header */
+} fl_file_layout;
+fl_status fl_file_layout_parse(const void *file, uint64_t bytes, uint32_t format, fl_file_layout *out);
+size_t fl_file_decode_workspace(const fl_file_layout *layout);
+fl_status fl_file_decode(const fl_file_layout *layout, const void *const *d_sections, uint64_t *row_ptr,
+                         uint32_t *col, uint16_t *val, uint32_t *d_status, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* ---- helpers ----------------------------------------------------------------- */
 const char *fl_status_string(fl_status s);
 const char *fl_last_error(void);   /* thread-local; "" if none */

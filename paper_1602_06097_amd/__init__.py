@@ -68,6 +68,14 @@ class FlBatchMatrix(ct.Structure):
                 ("npiv", c_u32), ("mD", c_u32), ("nB", c_u32), ("mode", ct.c_int), ("status", ct.c_int)]
 
 
+class FlFileLayout(ct.Structure):
+    _fields_ = [("format", c_u32), ("m", c_u32), ("n", c_u32), ("p", c_u64), ("nnz", c_u64), ("b", c_u32),
+                ("elem_bytes", c_u32), ("elem_signed", c_u32), ("version", c_u32), ("k", c_u64), ("pnb", c_u64),
+                ("pnnz", c_u64), ("off_data", c_u64), ("off_cols", c_u64), ("off_rows", c_u64),
+                ("off_polmap", c_u64), ("off_colid", c_u64), ("off_prow", c_u64), ("off_pdata", c_u64),
+                ("bytes", c_u64)]
+
+
 def load():
     """Load libfl.so (raises if it has not been built)."""
     global _lib
@@ -118,6 +126,9 @@ def load():
         "fl_batch_autotune": (ct.c_int, [P(FlCsr), c_u32, c_u32, c_vp, c_sz, c_vp, c_sz, P(FlBatchConfig),
                                          P(ct.c_double), c_vp]),
         "fl_batch_free": (None, [c_vp]),
+        "fl_file_layout_parse": (ct.c_int, [c_vp, c_u64, c_u32, P(FlFileLayout)]),
+        "fl_file_decode_workspace": (c_sz, [P(FlFileLayout)]),
+        "fl_file_decode": (ct.c_int, [P(FlFileLayout), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
         "fl_prof_enable": (None, [ct.c_int]),
         "fl_prof_reset": (None, []),
         "fl_prof_report": (c_sz, [ct.c_char_p, c_sz]),
