@@ -41,7 +41,7 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 namespace {
 
 constexpr uint32_t kPanel = 64;
-constexpr uint32_t kProbe = 256;  // rows in the probe basis pass (at least)
+constexpr uint32_t kProbe = 64;  // rows in the probe basis pass (at least)
 constexpr uint32_t kListCap = 2048;  // LDS row list: room for two 1024-row windows
 constexpr int kGreedyThreads = 1024;
 
