@@ -383,9 +383,14 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     L.pre_p256 = pp;
     FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, pc, pm, pp, stream));
     uint32_t active = L.n_all;
+    auto active_at = [&](uint32_t P, uint32_t a) {
+        while (a && b->mats[ids[0][a - 1]].npanels <= P) a--;
+        return a;
+    };
     for (uint32_t P = 0; P < Pm; P++) {
-        while (active && b->mats[ids[0][active - 1]].npanels <= P) active--;
+        active = active_at(P, active);
         if (!active) break;
+        const uint32_t next = active_at(P + 1, active);
         uint32_t g256 = 0, g128 = 0, gp = 0, mrows = 0;
         for (uint32_t i : ids[0]) g256 += fl_ech_tiles(b->mats[i].info.nB, P, 256);
         for (uint32_t i : ids[1]) {
@@ -394,8 +399,8 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
             if (t) mrows = std::max(mrows, b->mats[i].info.mD);
         }
         for (uint32_t i : ids[2]) gp += fl_ech_tiles(b->mats[i].info.nB, P, 256);
-        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, active, pre_rows[active], g256, g128, gp, mrows,
-                                      stream));
+        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, active, pre_rows[active], g256, g128, gp, mrows, next,
+                                      next ? pre_rows[next] : 0, stream));
     }
     return FL_OK;
 }

@@ -271,16 +271,14 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
 // list is reduced against the probe basis in ps; rows left nonzero (outside
 // its span) go to the flagged list.  One wave per row, 8 rows per wave, 32
 // rows per workgroup.
-__global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                                   const uint32_t *__restrict__ ids,
-                                                   const uint32_t *__restrict__ pre_rows, uint32_t ntask,
-                                                   uint32_t P, int use_basis) {
-    __shared__ uint16_t Bv[64][64];
-    __shared__ uint32_t Cc[64];
-    const uint32_t ti = fl_task_of(pre_rows, ntask, blockIdx.x);
-    const FlEchTask &t = tasks[ids[ti]];
-    if (P >= t.npanels) return;
-    const uint32_t bx = blockIdx.x - pre_rows[ti];
+struct CheckLds {
+    uint16_t Bv[64][64];
+    uint32_t Cc[64];
+};
+
+// One workgroup (32 rows) of the check of panel P for table entry ti.
+__device__ void check_tile(const fl::Mod &md, const FlEchTask &t, uint32_t bx, uint32_t P, int use_basis,
+                           CheckLds &L) {
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     const PanelState *ps = (const PanelState *)t.ps;
     const uint32_t *in_list = use_basis ? t.nzlist : nullptr;
@@ -290,8 +288,8 @@ __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *
     const uint32_t kb = use_basis ? ps->kb : 0;
     const uint32_t n = in_list ? t.counts[3 * P] : t.rows;
     if (bx * 32 >= n) return;
-    for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) Bv[i >> 6][i & 63] = ps->Bv[i];
-    if (threadIdx.x < 64) Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
+    for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) L.Bv[i >> 6][i & 63] = ps->Bv[i];
+    if (threadIdx.x < 64) L.Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
     __syncthreads();
     for (uint32_t u = 0; u < 8; u++) {
         const uint32_t idx = (bx * 4 + wave) * 8 + u;
@@ -301,13 +299,24 @@ __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *
             i = in_list ? in_list[idx] : idx;
             if (!t.is_piv[i] && kb < pw) {
                 uint32_t v = lane < pw ? t.D[(uint64_t)i * t.ld + c0 + lane] : 0, g = 0;
-                if (kb) reduce_against(md, v, g, 0, kb, Bv, Bv, Cc, lane, false);
+                if (kb) reduce_against(md, v, g, 0, kb, L.Bv, L.Bv, L.Cc, lane, false);
                 flag = __ballot(v != 0) != 0;
             }
         }
         block_append(flag, i, out_list, out_count);
     }
     if (use_basis && threadIdx.x == 0) __threadfence();
+}
+
+__global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                   const uint32_t *__restrict__ ids,
+                                                   const uint32_t *__restrict__ pre_rows, uint32_t ntask,
+                                                   uint32_t P, int use_basis) {
+    __shared__ CheckLds L;
+    const uint32_t ti = fl_task_of(pre_rows, ntask, blockIdx.x);
+    const FlEchTask &t = tasks[ids[ti]];
+    if (P >= t.npanels) return;
+    check_tile(md, t, blockIdx.x - pre_rows[ti], P, use_basis, L);
 }
 
 // Panel step 3 (only when some row was flagged): continue the greedy basis
@@ -348,15 +357,17 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
 // limb planes, also U transposed as int8 limbs: Uh/Ul[(c - c0) * 64 + t]
 // (zero for t >= k), the B operand of the matrix-core rank-k update.
 // 256 columns per workgroup.
-__global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                               const uint32_t *__restrict__ ids,
-                                               const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P) {
-    __shared__ uint16_t Gs[64 * 64];
-    __shared__ uint16_t xs[64][256];
-    __shared__ uint32_t qs[64];
-    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
-    const FlEchTask &tk = tasks[ids[ti]];
-    if (P >= tk.npanels) return;
+struct ULds {
+    uint16_t Gs[64 * 64];
+    uint16_t xs[64][256];
+    uint32_t qs[64];
+};
+
+// One workgroup (256 columns from c0 + 256 bx) of U for panel P.
+__device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint32_t P, ULds &S) {
+    uint16_t *Gs = S.Gs;
+    uint16_t(*xs)[256] = S.xs;
+    uint32_t *qs = S.qs;
     const PanelState *ps = (const PanelState *)tk.ps;
     const uint32_t c0 = P * kPanel, cols = tk.cols;
     const uint16_t *D = tk.D;
@@ -368,7 +379,7 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const FlEchTask *__re
     for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) Gs[i] = ps->G[i];
     if (threadIdx.x < 64) qs[threadIdx.x] = ps->Qs[threadIdx.x];
     __syncthreads();
-    const uint32_t c = c0 + (blockIdx.x - pre[ti]) * 256 + threadIdx.x;
+    const uint32_t c = c0 + bx * 256 + threadIdx.x;
     const bool ok = c < cols;
 #pragma unroll 8
     for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)qs[s] * ld + c] : 0;
@@ -412,15 +423,8 @@ __global__ __launch_bounds__(256) void k_ech_U(fl::Mod md, const FlEchTask *__re
 // int8 limbs (64 bytes per row) and the list of rows with a nonzero
 // multiplier (rows whose update is zero are skipped by the rank-k update).
 // One wave per row, 8 rows per wave.
-__global__ __launch_bounds__(256) void k_ech_gather_L(uint32_t p, const FlEchTask *__restrict__ tasks,
-                                                      const uint32_t *__restrict__ ids,
-                                                      const uint32_t *__restrict__ pre_rows, uint32_t ntask,
-                                                      uint32_t P) {
-    __shared__ uint32_t ccol[64];
-    const uint32_t ti = fl_task_of(pre_rows, ntask, blockIdx.x);
-    const FlEchTask &tk = tasks[ids[ti]];
-    if (P >= tk.npanels) return;
-    const uint32_t bx = blockIdx.x - pre_rows[ti];
+// One workgroup (32 rows) of the multiplier gather of panel P.
+__device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P, uint32_t *ccol) {
     const PanelState *ps = (const PanelState *)tk.ps;
     const uint32_t rows = tk.rows;
     const uint16_t *D = tk.D;
@@ -447,6 +451,27 @@ __global__ __launch_bounds__(256) void k_ech_gather_L(uint32_t p, const FlEchTas
             }
         }
         if (Lh) block_append(nz, i, tk.upd_rows, tk.counts + 3 * P + 2);
+    }
+}
+
+// Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
+// (columns), the others gather L (rows).
+__global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
+                                                uint32_t n_all, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
+                                                uint32_t n_active, uint32_t P) {
+    __shared__ ULds S;
+    if (blockIdx.x < grid_u) {
+        const uint32_t ti = fl_task_of(pre_c, n_all, blockIdx.x);
+        const FlEchTask &t = tasks[ids[ti]];
+        if (P >= t.npanels) return;
+        U_tile(md, t, blockIdx.x - pre_c[ti], P, S);
+    } else {
+        const uint32_t b = blockIdx.x - grid_u;
+        const uint32_t ti = fl_task_of(pre_rows, n_active, b);
+        const FlEchTask &t = tasks[ids[ti]];
+        if (P >= t.npanels) return;
+        L_tile(md.p, t, b - pre_rows[ti], P, S.qs);
     }
 }
 
@@ -488,18 +513,46 @@ __global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEch
 
 // Rows of Q receive U (after the rank-k update touched them): 256 columns
 // per workgroup from the prefix, pivot t = blockIdx.y.
+__device__ void setq_tile(const FlEchTask &tk, uint32_t bx, uint32_t t, uint32_t P) {
+    const PanelState *ps = (const PanelState *)tk.ps;
+    if (t >= ps->k) return;
+    const uint32_t row = ps->Phys[t];
+    const uint32_t c = P * kPanel + bx * 256 + threadIdx.x;
+    if (c < tk.cols) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
+}
+
 __global__ __launch_bounds__(256) void k_ech_setq(const FlEchTask *__restrict__ tasks,
                                                   const uint32_t *__restrict__ ids,
                                                   const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P) {
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &tk = tasks[ids[ti]];
     if (P >= tk.npanels) return;
-    const PanelState *ps = (const PanelState *)tk.ps;
-    const uint32_t t = blockIdx.y;
-    if (t >= ps->k) return;
-    const uint32_t row = ps->Phys[t];
-    const uint32_t c = P * kPanel + (blockIdx.x - pre[ti]) * 256 + threadIdx.x;
-    if (c < tk.cols) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
+    setq_tile(tk, blockIdx.x - pre[ti], blockIdx.y, P);
+}
+
+// Step 7 of panel P and step 0 of panel P+1 in one launch (they touch
+// different rows: the pivot rows of P, and rows that are no pivot rows):
+// the first grid_c * 64 workgroups place U, the others list the rows
+// nonzero on panel P+1.
+__global__ __launch_bounds__(256) void k_ech_setq_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                        const uint32_t *__restrict__ ids,
+                                                        const uint32_t *__restrict__ pre_c, uint32_t n_all,
+                                                        uint32_t grid_c, const uint32_t *__restrict__ pre_rows,
+                                                        uint32_t n_next, uint32_t P) {
+    __shared__ CheckLds L;
+    if (blockIdx.x < grid_c * kPanel) {
+        const uint32_t bx = blockIdx.x % grid_c, t = blockIdx.x / grid_c;
+        const uint32_t ti = fl_task_of(pre_c, n_all, bx);
+        const FlEchTask &tk = tasks[ids[ti]];
+        if (P >= tk.npanels) return;
+        setq_tile(tk, bx - pre_c[ti], t, P);
+    } else {
+        const uint32_t b = blockIdx.x - grid_c * kPanel;
+        const uint32_t ti = fl_task_of(pre_rows, n_next, b);
+        const FlEchTask &tk = tasks[ids[ti]];
+        if (P + 1 >= tk.npanels) return;
+        check_tile(md, tk, b - pre_rows[ti], P + 1, 0, L);
+    }
 }
 
 // Per-panel workgroup prefixes of the column-tiled kernels (one thread per
@@ -655,15 +708,17 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
 hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t P,
                                   uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
                                   uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
-                                  hipStream_t stream) {
+                                  uint32_t n_next, uint32_t grid_rows_next, hipStream_t stream) {
     if (n_active == 0) return hipSuccess;
     const fl::Mod md = fl::make_mod(p);
     const uint32_t *c256 = L.pre_c256 + (uint64_t)P * (L.n_all + 1);
     hipError_t e;
-    FL_PROF("echelon.check", stream,
-            hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               L.pre_rows, n_active, P, 0));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (P == 0) {  // later panels are listed by the previous panel's last launch
+        FL_PROF("echelon.check", stream,
+                hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                                   L.pre_rows, n_active, P, 0));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     FL_PROF("echelon.probe", stream,
             hipLaunchKernelGGL(k_ech_probe, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
@@ -676,15 +731,9 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             hipLaunchKernelGGL(k_ech_merge, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (grid_c256) {
-        FL_PROF("echelon.U", stream,
-                hipLaunchKernelGGL(k_ech_U, dim3(grid_c256), dim3(256), 0, stream, md, tasks, L.ids_all, c256,
-                                   L.n_all, P));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    FL_PROF("echelon.L", stream,
-            hipLaunchKernelGGL(k_ech_gather_L, dim3(grid_rows), dim3(256), 0, stream, p, tasks, L.ids_all,
-                               L.pre_rows, n_active, P));
+    FL_PROF("echelon.UL", stream,
+            hipLaunchKernelGGL(k_ech_UL, dim3(grid_c256 + grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                               c256, L.n_all, grid_c256, L.pre_rows, n_active, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (grid_m128) {
         const uint32_t *m128 = L.pre_m128 + (uint64_t)P * (L.n_mfma + 1);
@@ -701,13 +750,16 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
                                    L.ids_plain, p256, L.n_plain, P));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (grid_c256) {
+    if (n_next) {
+        FL_PROF("echelon.setq_check", stream,
+                hipLaunchKernelGGL(k_ech_setq_check, dim3(grid_c256 * kPanel + grid_rows_next), dim3(256), 0, stream,
+                                   md, tasks, L.ids_all, c256, L.n_all, grid_c256, L.pre_rows, n_next, P));
+    } else if (grid_c256) {
         FL_PROF("echelon.setq", stream,
                 hipLaunchKernelGGL(k_ech_setq, dim3(grid_c256, kPanel), dim3(256), 0, stream, tasks, L.ids_all,
                                    c256, L.n_all, P));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
@@ -758,8 +810,9 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
     FL_HIP(fl_echelon_prefixes(e.task, L, np, e.pre, pre_m, pre_p, stream));
     for (uint32_t P = 0; P < np; P++) {
         const uint32_t g256 = fl_ech_tiles(cols, P, 256), g128 = fl_ech_tiles(cols, P, 128);
+        const uint32_t nn = P + 1 < np ? 1 : 0;
         FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, 1, pre_rows[1], g256, t.mfma ? g128 : 0,
-                                      t.mfma ? 0 : g256, rows, stream));
+                                      t.mfma ? 0 : g256, rows, nn, nn ? pre_rows[1] : 0, stream));
     }
     return fl_echelon_finish(t, stream);
 }

@@ -278,9 +278,11 @@ inline uint32_t fl_ech_tiles(uint32_t cols, uint32_t P, uint32_t tile) {
 // Panel P of every listed matrix: the seven panel kernels.  n_active: the
 // leading entries of ids_all with more than P panels; grid_*: the prefix
 // totals at P; mfma_rows: the largest row count among the MFMA-form matrices.
+// n_next, grid_rows_next: the same for panel P + 1 (its first step runs in
+// panel P's last launch).
 hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &lists,
                                    uint32_t P, uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
                                    uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
-                                   hipStream_t stream);
+                                   uint32_t n_next, uint32_t grid_rows_next, hipStream_t stream);
 // Moves the pivot rows of one matrix to the top in pivot order, clears the rest.
 fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream);
