@@ -32,11 +32,6 @@ namespace {
 
 constexpr uint32_t kMaxStreams = 16;
 
-#define FL_CHECK_ST(call)                      \
-    do {                                       \
-        fl_status st_ = (call);                \
-        if (st_ != FL_OK) return st_;          \
-    } while (0)
 constexpr uint64_t kDefaultMfmaMin = (uint64_t)1 << 22;
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -170,6 +165,9 @@ struct fl_batch {
     hipStream_t streams[kMaxStreams] = {};
     hipStream_t capture = nullptr;  // graph capture when the caller passes the null stream
     hipEvent_t fork = nullptr, join[kMaxStreams] = {};
+    // second stream of the panel loop (its far part) and its events
+    hipStream_t ech_far = nullptr;
+    hipEvent_t ech_near_ev = nullptr, ech_far_ev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -179,6 +177,9 @@ namespace {
 fl_status batch_init_streams(fl_batch *b) {
     FL_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     FL_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    FL_HIP(hipStreamCreateWithFlags(&b->ech_far, hipStreamNonBlocking));
+    FL_HIP(hipEventCreateWithFlags(&b->ech_near_ev, hipEventDisableTiming));
+    FL_HIP(hipEventCreateWithFlags(&b->ech_far_ev, hipEventDisableTiming));
     for (uint32_t k = 0; k < b->cfg.streams; k++) {
         FL_HIP(hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking));
         FL_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
@@ -231,7 +232,7 @@ void batch_layout(fl_batch *b) {
     b->off_etask = take(sizeof(FlEchTask) * n);
     b->off_eids = take(4 * 3 * n);
     b->off_epre_rows = take(4 * (n + 1));
-    b->off_epre = take(4 * 3 * (uint64_t)b->max_panels * (n + 1));
+    b->off_epre = take(4 * 6 * (uint64_t)b->max_panels * (n + 1));
     for (auto &mr : b->mats) {
         const fl_split_info &f = mr.info;
         mr.ldx = ld64(f.nB);
@@ -377,11 +378,10 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     L.n_mfma = (uint32_t)ids[1].size();
     L.n_plain = (uint32_t)ids[2].size();
     L.pre_rows = d_pre_rows;
-    uint32_t *pc = pre_base, *pm = pre_base + (size_t)Pm * (n + 1), *pp = pre_base + 2 * (size_t)Pm * (n + 1);
-    L.pre_c256 = pc;
-    L.pre_m128 = pm;
-    L.pre_p256 = pp;
-    FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, pc, pm, pp, stream));
+    uint32_t **tabs[6] = {&L.pre_n_all, &L.pre_n_mfma, &L.pre_n_plain, &L.pre_f_all, &L.pre_f_mfma, &L.pre_f_plain};
+    for (int k = 0; k < 6; k++) *tabs[k] = pre_base + (size_t)k * Pm * (n + 1);
+    FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, stream));
+    FlEchAux aux = {b->ech_far, b->ech_near_ev, b->ech_far_ev, false};
     uint32_t active = L.n_all;
     auto active_at = [&](uint32_t P, uint32_t a) {
         while (a && b->mats[ids[0][a - 1]].npanels <= P) a--;
@@ -390,18 +390,26 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     for (uint32_t P = 0; P < Pm; P++) {
         active = active_at(P, active);
         if (!active) break;
-        const uint32_t next = active_at(P + 1, active);
-        uint32_t g256 = 0, g128 = 0, gp = 0, mrows = 0;
-        for (uint32_t i : ids[0]) g256 += fl_ech_tiles(b->mats[i].info.nB, P, 256);
+        FlEchGrid g = {};
+        g.n_active = active;
+        g.grid_rows = pre_rows[active];
+        g.n_next = active_at(P + 1, active);
+        g.grid_rows_next = g.n_next ? pre_rows[g.n_next] : 0;
+        for (uint32_t i : ids[0]) g.f_all += fl_ech_tiles(b->mats[i].info.nB, P, 256, kFlEchNear);
         for (uint32_t i : ids[1]) {
-            const uint32_t t = fl_ech_tiles(b->mats[i].info.nB, P, 128);
-            g128 += t;
-            if (t) mrows = std::max(mrows, b->mats[i].info.mD);
+            if (!fl_ech_tiles(b->mats[i].info.nB, P, 1u << 31)) continue;
+            g.n_mfma++;
+            g.f_mfma += fl_ech_tiles(b->mats[i].info.nB, P, 128, kFlEchNear);
+            g.mfma_rows = std::max(g.mfma_rows, b->mats[i].info.mD);
         }
-        for (uint32_t i : ids[2]) gp += fl_ech_tiles(b->mats[i].info.nB, P, 256);
-        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, active, pre_rows[active], g256, g128, gp, mrows, next,
-                                      next ? pre_rows[next] : 0, stream));
+        for (uint32_t i : ids[2]) {
+            if (!fl_ech_tiles(b->mats[i].info.nB, P, 1u << 31)) continue;
+            g.n_plain++;
+            g.f_plain += fl_ech_tiles(b->mats[i].info.nB, P, 256, kFlEchNear);
+        }
+        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, g, stream, aux));
     }
+    FL_HIP(fl_echelon_join(stream, aux));
     return FL_OK;
 }
 
@@ -471,6 +479,9 @@ void batch_destroy(fl_batch *b) {
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->ech_far) (void)hipStreamDestroy(b->ech_far);
+    if (b->ech_near_ev) (void)hipEventDestroy(b->ech_near_ev);
+    if (b->ech_far_ev) (void)hipEventDestroy(b->ech_far_ev);
     delete b;
 }
 

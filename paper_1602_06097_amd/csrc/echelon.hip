@@ -4,7 +4,7 @@
 //
 // For a panel [c0, c0+64):
 //  0. k_ech_check   lists the remaining rows that are nonzero on the panel.
-//  1. k_ech_probe   one block: a greedy basis of (up to 256 of) those rows
+//  1. k_ech_probe   one block: a greedy basis of (up to 64 of) those rows
 //     restricted to the panel, in reduced form in LDS.  Every wave reduces one
 //     row against the basis (multipliers broadcast with v_readlane); rows
 //     that stay nonzero are inserted one wave at a time.  The coefficients G
@@ -17,14 +17,21 @@
 //  3. k_ech_merge   only if a row was listed: the greedy pass continues over
 //     those rows.  The result: pivot columns C (ascending) of the
 //     panel, rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
-//  4. k_ech_U              U = G * Dt[Q, c0:]   (unit vectors at C)
-//  5. k_ech_gather_L       L = Dt[:, C]          (multipliers, saved before
-//                                                 the update overwrites them)
+//  4. U = G * Dt[Q, c0:]   (unit vectors at C)
+//  5. L = Dt[:, C]          (multipliers, saved before the update
+//                            overwrites them; 4 and 5 are one launch)
 //  6. rank-k update        Dt[:, c0:] -= L U    (every row: Gauss-Jordan
 //     (VALU or int8 MFMA)                       clears C above and below)
-//  7. k_ech_setq           Dt[Q_t, c0:] = U_t
+//  7. Dt[Q_t, c0:] = U_t   (one launch with step 0 of the next panel)
+// Steps 4, 6 and 7 are split at column c0 + 128.  The near part (this panel
+// and the next) is all the next panel's search reads; the far part runs on a
+// second stream while that search runs, and the next panel's step 4 waits
+// for it (it reads and overwrites U, L and the columns the far part writes).
+// Panel states alternate between two slots for the same reason.
 // After the last panel the pivot rows are gathered to rows 0..r-1 in pivot
 // order and the other rows (now zero) are cleared.
+#include <vector>
+
 #include "fl_internal.h"
 #include "mfma_tile.h"
 #include "valu_tile.h"
@@ -84,25 +91,33 @@ struct EchWs {
     uint32_t *pre;       // 3 x [npanels][2]
 };
 
+// Panel states alternate between two slots, so that panel P + 1's search
+// can run while panel P's trailing update still reads its state.
+__device__ __forceinline__ PanelState *panel_state(const FlEchTask &t, uint32_t P) {
+    return (PanelState *)t.ps + (P & 1);
+}
+
 // Reduce the wave's vector (v: panel part, g: coefficient part, lane = column
 // or slot) against basis rows [t0, t1).  The basis is in reduced form, so all
-// multipliers can be read from the vector as it is on entry.
+// multipliers can be read from the vector as it is on entry.  The pivot
+// columns are read once into a register (lane t holds Cc[t]); a zero
+// multiplier adds nothing, so no term is skipped (no branch in the loop).
 __device__ inline void reduce_against(const fl::Mod &md, uint32_t &v, uint32_t &g, uint32_t t0,
                                       uint32_t t1, const uint16_t (*Bv)[64],
                                       const uint16_t (*Bg)[64], const uint32_t *Cc, uint32_t lane,
                                       bool track) {
     uint32_t vh = 0, vl = 0, gh = 0, gl = 0;
     const uint32_t vin = v;
+    const uint32_t cc = Cc[lane];
     for (uint32_t t = t0; t < t1; t++) {
-        int cidx = __builtin_amdgcn_readfirstlane((int)Cc[t]);
-        uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)vin, cidx);
-        if (lam == 0) continue;
-        uint32_t lh = lam >> 8, ll = lam & 0xffu;
-        uint32_t b = Bv[t][lane];
+        const int cidx = __builtin_amdgcn_readlane((int)cc, (int)t);
+        const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)vin, cidx);
+        const uint32_t lh = lam >> 8, ll = lam & 0xffu;
+        const uint32_t b = Bv[t][lane];
         vh = fl::mad24(lh, b, vh);
         vl = fl::mad24(ll, b, vl);
         if (track) {
-            uint32_t bg = Bg[t][lane];
+            const uint32_t bg = Bg[t][lane];
             gh = fl::mad24(lh, bg, gh);
             gl = fl::mad24(ll, bg, gl);
         }
@@ -110,6 +125,28 @@ __device__ inline void reduce_against(const fl::Mod &md, uint32_t &v, uint32_t &
     // at most 64 terms: no intermediate fold needed
     v = fl::submod(v, fl::fold_pair(vh, vl, md), md.p);
     if (track) g = fl::submod(g, fl::fold_pair(gh, gl, md), md.p);
+}
+
+// The same for the wave's 8 rows v[0..8) (no coefficient part), interleaved so
+// that the basis row and pivot column are read once per basis row.
+__device__ inline void reduce_rows8(const fl::Mod &md, uint32_t (&v)[8], uint32_t kb, const uint16_t (*Bv)[64],
+                                    const uint32_t *Cc, uint32_t lane) {
+    uint32_t vh[8], vl[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) vh[u] = vl[u] = 0;
+    const uint32_t cc = Cc[lane];
+    for (uint32_t t = 0; t < kb; t++) {
+        const int cidx = __builtin_amdgcn_readlane((int)cc, (int)t);
+        const uint32_t b = Bv[t][lane];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)v[u], cidx);
+            vh[u] = fl::mad24(lam >> 8, b, vh[u]);
+            vl[u] = fl::mad24(lam & 0xffu, b, vl[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = fl::submod(v[u], fl::fold_pair(vh[u], vl[u], md), md.p);
 }
 
 // Append the rows with flag set (one candidate row per wave) to a global
@@ -128,66 +165,113 @@ __device__ void block_append(bool flag, uint32_t row, uint32_t *list, uint32_t *
     if (flag && lane == 0) list[s_base + local] = row;
 }
 
+// Append up to 8 rows per wave to a global list with one global atomic per
+// block: bit u of the wave-uniform mask8 lists the row held by lane u.  All
+// threads of the (256-thread) block must call it.
+__device__ void block_append8(uint32_t mask8, uint32_t row, uint32_t *list, uint32_t *count) {
+    __shared__ uint32_t s_w[4], s_base;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_w[wave] = __popc(mask8);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        s_base = tot ? atomicAdd(count, tot) : 0;
+    }
+    __syncthreads();
+    uint32_t off = s_base;
+    for (uint32_t w = 0; w < wave; w++) off += s_w[w];
+    if (lane < 8 && ((mask8 >> lane) & 1u)) list[off + __popc(mask8 & ((1u << lane) - 1u))] = row;
+}
+
 // Greedy basis of the panel rows in LDS: reduced form over the panel
 // columns (Bv, pivots Cc), with the coefficients G of every basis row on the
 // selected input rows Qo (Bg), so that  Bv_j = sum_s Bg_j[s] Dt[Qo[s], panel].
-struct GreedyLds {
+struct __attribute__((aligned(16))) GreedyLds {
     uint16_t Bv[64][64];
     uint16_t Bg[64][64];
     uint32_t Cc[64];
     uint32_t Qo[64];
     uint32_t kb;
     uint32_t cnt;
+    uint32_t nzmask[2];  // waves holding a candidate row in the batch (batch parity)
+    uint32_t newc;    // pivot column of the row just inserted (64: none)
     uint32_t list[kListCap];
 };
 
 // Process rows S.list[0..S.cnt) in order: each wave reduces one row against
-// the basis; rows still nonzero are inserted one wave at a time (a new pivot
-// is the first nonzero column; it is cleared from the other basis rows).
-// This is the paper's parallel structured elimination (Sec. 5.1) in
-// miniature: reductions in parallel, insertion of a new pivot serialised.
+// the basis; rows still nonzero are inserted one at a time (a new pivot is
+// the first nonzero column).  The inserting wave normalises its row; the new
+// pivot column is then cleared from the older basis rows by all waves (rows
+// dealt round-robin), so that the basis stays in reduced form.  This is the
+// paper's parallel structured elimination (Sec. 5.1) in miniature:
+// reductions in parallel, insertion of a new pivot serialised.
 __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, uint64_t ld,
                             uint32_t c0, uint32_t pw, GreedyLds &S) {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t cnt = S.cnt;
+    const uint32_t col = c0 + (lane < pw ? lane : 0);
+    // the next batch's row is fetched while the current batch is processed
+    uint32_t row_n = wave < cnt ? S.list[wave] : S.list[0];
+    uint32_t v_n = D[(uint64_t)row_n * ld + col];
     for (uint32_t base = 0; base < cnt; base += nw) {
         if (S.kb >= pw) break;  // panel full: every further row reduces to 0
         const uint32_t item = base + wave;
         const bool have = item < cnt;
-        const uint32_t row = have ? S.list[item] : 0;
-        uint32_t v = (have && lane < pw) ? D[(uint64_t)row * ld + c0 + lane] : 0;
+        const uint32_t row = row_n;
+        uint32_t v = v_n;
+        if (!have || lane >= pw) v = 0;
+        {
+            const uint32_t nx = item + nw;
+            row_n = nx < cnt ? S.list[nx] : S.list[0];
+            v_n = D[(uint64_t)row_n * ld + col];
+        }
         uint32_t g = 0;
         const uint32_t ks = S.kb;
+        // the mask of this batch was last read two batches ago, before the
+        // barrier that ended the previous batch's reads
+        uint32_t *nzm = &S.nzmask[(base / nw) & 1];
+        if (threadIdx.x == 0) *nzm = 0;
+        __syncthreads();
         reduce_against(md, v, g, 0, ks, S.Bv, S.Bg, S.Cc, lane, true);
-        const bool nz = have && __ballot(v != 0) != 0;
-        const int any = __syncthreads_or(nz ? 1 : 0);
-        if (!any) continue;
-        for (uint32_t w = 0; w < nw; w++) {
-            if (w == wave && nz) {
+        const bool nz = __ballot(v != 0) != 0;
+        if (nz && lane == 0) atomicOr(nzm, 1u << wave);
+        __syncthreads();
+        uint32_t mask = *nzm;
+        while (mask) {
+            const uint32_t w = (uint32_t)__ffs((int)mask) - 1;
+            mask &= mask - 1;
+            if (wave == w) {
                 const uint32_t kb = S.kb;
                 reduce_against(md, v, g, ks, kb, S.Bv, S.Bg, S.Cc, lane, true);
-                const uint64_t mask = __ballot(v != 0);
-                if (mask != 0 && kb < pw) {
-                    const int c = __ffsll((long long)mask) - 1;
+                const uint64_t m = __ballot(v != 0);
+                uint32_t c = 64;
+                if (m != 0 && kb < pw) {
+                    c = (uint32_t)__ffsll((long long)m) - 1;
                     if (lane == kb) g = 1;
-                    const uint32_t piv = (uint32_t)__builtin_amdgcn_readlane((int)v, c);
+                    const uint32_t piv = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
                     const uint32_t inv = fl::invmod(piv, md);
-                    v = fl::mulmod(v, inv, md);
-                    g = fl::mulmod(g, inv, md);
-                    for (uint32_t t = 0; t < kb; t++) {
-                        const uint32_t f = S.Bv[t][c];
-                        if (f) {
-                            S.Bv[t][lane] = (uint16_t)fl::submod(S.Bv[t][lane], fl::mulmod(f, v, md), md.p);
-                            S.Bg[t][lane] = (uint16_t)fl::submod(S.Bg[t][lane], fl::mulmod(f, g, md), md.p);
-                        }
-                    }
-                    S.Bv[kb][lane] = (uint16_t)v;
-                    S.Bg[kb][lane] = (uint16_t)g;
-                    if (lane == 0) {
-                        S.Cc[kb] = (uint32_t)c;
+                    S.Bv[kb][lane] = (uint16_t)fl::mulmod(v, inv, md);
+                    S.Bg[kb][lane] = (uint16_t)fl::mulmod(g, inv, md);
+                }
+                if (lane == 0) {
+                    S.newc = c;
+                    if (c < 64) {
+                        S.Cc[kb] = c;
                         S.Qo[kb] = row;
                         S.kb = kb + 1;
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t c = S.newc, kn = S.kb;
+            if (c < 64) {
+                // clear column c from basis rows 0 .. kn - 2 with the new row kn - 1
+                for (uint32_t t = wave; t + 1 < kn; t += nw) {
+                    const uint32_t f = S.Bv[t][c];
+                    if (f) {
+                        S.Bv[t][lane] = (uint16_t)fl::submod(S.Bv[t][lane], fl::mulmod(f, S.Bv[kn - 1][lane], md), md.p);
+                        S.Bg[t][lane] = (uint16_t)fl::submod(S.Bg[t][lane], fl::mulmod(f, S.Bg[kn - 1][lane], md), md.p);
                     }
                 }
             }
@@ -248,7 +332,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
     const FlEchTask &t = tasks[ids[blockIdx.x]];
     if (P >= t.npanels) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
-    PanelState *ps = (PanelState *)t.ps;
+    PanelState *ps = panel_state(t, P);
     const uint32_t n = t.counts[3 * P];
     const uint32_t take = n < kProbe ? n : kProbe;
     if (threadIdx.x == 0) {
@@ -271,16 +355,18 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
 // list is reduced against the probe basis in ps; rows left nonzero (outside
 // its span) go to the flagged list.  One wave per row, 8 rows per wave, 32
 // rows per workgroup.
-struct CheckLds {
+struct __attribute__((aligned(16))) CheckLds {
     uint16_t Bv[64][64];
     uint32_t Cc[64];
 };
 
-// One workgroup (32 rows) of the check of panel P for table entry ti.
+// One workgroup (32 rows) of the check of panel P for table entry ti.  The
+// wave's 8 row ids, pivot flags and panel rows are fetched with independent
+// loads, reduced together, and listed with one append per workgroup.
 __device__ void check_tile(const fl::Mod &md, const FlEchTask &t, uint32_t bx, uint32_t P, int use_basis,
                            CheckLds &L) {
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
-    const PanelState *ps = (const PanelState *)t.ps;
+    const PanelState *ps = panel_state(t, P);
     const uint32_t *in_list = use_basis ? t.nzlist : nullptr;
     uint32_t *out_list = use_basis ? t.flist : t.nzlist;
     uint32_t *out_count = t.counts + 3 * P + (use_basis ? 1 : 0);
@@ -288,23 +374,45 @@ __device__ void check_tile(const fl::Mod &md, const FlEchTask &t, uint32_t bx, u
     const uint32_t kb = use_basis ? ps->kb : 0;
     const uint32_t n = in_list ? t.counts[3 * P] : t.rows;
     if (bx * 32 >= n) return;
-    for (uint32_t i = threadIdx.x; i < kb * 64; i += blockDim.x) L.Bv[i >> 6][i & 63] = ps->Bv[i];
-    if (threadIdx.x < 64) L.Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
-    __syncthreads();
-    for (uint32_t u = 0; u < 8; u++) {
-        const uint32_t idx = (bx * 4 + wave) * 8 + u;
-        bool flag = false;
-        uint32_t i = 0;
-        if (idx < n) {
-            i = in_list ? in_list[idx] : idx;
-            if (!t.is_piv[i] && kb < pw) {
-                uint32_t v = lane < pw ? t.D[(uint64_t)i * t.ld + c0 + lane] : 0, g = 0;
-                if (kb) reduce_against(md, v, g, 0, kb, L.Bv, L.Bv, L.Cc, lane, false);
-                flag = __ballot(v != 0) != 0;
-            }
-        }
-        block_append(flag, i, out_list, out_count);
+    // basis rows: kb * 64 halfwords = kb * 8 16-byte chunks (at most 512)
+    {
+        const uint4 *src = (const uint4 *)ps->Bv;
+        uint4 *dst = (uint4 *)&L.Bv[0][0];
+        const uint32_t nv = kb * 8, i0 = threadIdx.x, i1 = threadIdx.x + 256;
+        uint4 a = make_uint4(0, 0, 0, 0), b = a;
+        if (i0 < nv) a = src[i0];
+        if (i1 < nv) b = src[i1];
+        if (i0 < nv) dst[i0] = a;
+        if (i1 < nv) dst[i1] = b;
     }
+    if (threadIdx.x < 64) L.Cc[threadIdx.x] = use_basis ? ps->Cc[threadIdx.x] : 0;
+    // lane u < 8: row id and liveness of the wave's row u
+    const uint32_t idx0 = (bx * 4 + wave) * 8;
+    uint32_t my_row = 0, my_live = 0;
+    if (lane < 8 && idx0 + lane < n) {
+        my_row = in_list ? in_list[idx0 + lane] : idx0 + lane;
+        my_live = (kb < pw && !t.is_piv[my_row]) ? 1u : 0u;
+    }
+    const uint32_t col = c0 + (lane < pw ? lane : 0);
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)my_row, u);
+        v[u] = t.D[(uint64_t)row * t.ld + col];  // row 0 stands in for rows not live
+    }
+    uint32_t live = 0;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const bool lv = __builtin_amdgcn_readlane((int)my_live, u) != 0;
+        live |= lv ? 1u << u : 0u;
+        if (!lv || lane >= pw) v[u] = 0;
+    }
+    __syncthreads();
+    if (kb && live) reduce_rows8(md, v, kb, L.Bv, L.Cc, lane);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < 8; u++) mask |= (__ballot(v[u] != 0) != 0) ? 1u << u : 0u;
+    block_append8(mask & live, my_row, out_list, out_count);
     if (use_basis && threadIdx.x == 0) __threadfence();
 }
 
@@ -330,10 +438,13 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
     const uint32_t n = t.counts[3 * P + 1];
     if (n == 0) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
-    PanelState *ps = (PanelState *)t.ps;
-    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-        S.Bv[i >> 6][i & 63] = ps->Bv[i];
-        S.Bg[i >> 6][i & 63] = ps->Bg[i];
+    PanelState *ps = panel_state(t, P);
+    {  // the raw basis: 2 x 512 16-byte chunks, one of each per thread
+        static_assert(kGreedyThreads == 512 * 2, "one chunk of Bv and Bg per thread");
+        const uint32_t i = threadIdx.x & 511;
+        const uint4 *src = (const uint4 *)(threadIdx.x < 512 ? ps->Bv : ps->Bg);
+        uint4 *dst = (uint4 *)(threadIdx.x < 512 ? &S.Bv[0][0] : &S.Bg[0][0]);
+        dst[i] = src[i];
     }
     if (threadIdx.x < 64) {
         S.Cc[threadIdx.x] = ps->Cc[threadIdx.x];
@@ -356,48 +467,78 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
 // U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k; with
 // limb planes, also U transposed as int8 limbs: Uh/Ul[(c - c0) * 64 + t]
 // (zero for t >= k), the B operand of the matrix-core rank-k update.
-// 256 columns per workgroup.
-struct ULds {
+// 256 columns per workgroup, one per thread: the column's k entries of the
+// selected rows are held in registers (fetched with independent loads), G is
+// read from LDS 8 entries at a time.  G[t][s] = 0 for s >= k, so the sums run
+// over whole groups of 8.
+struct __attribute__((aligned(16))) ULds {
     uint16_t Gs[64 * 64];
-    uint16_t xs[64][256];
     uint32_t qs[64];
 };
 
-// One workgroup (256 columns from c0 + 256 bx) of U for panel P.
-__device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint32_t P, ULds &S) {
+// One workgroup (256 columns from c0 + lo + 256 bx, below c0 + hi) of U for
+// panel P.
+__device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint32_t P, ULds &S, uint32_t lo,
+                       uint32_t hi) {
     uint16_t *Gs = S.Gs;
-    uint16_t(*xs)[256] = S.xs;
     uint32_t *qs = S.qs;
-    const PanelState *ps = (const PanelState *)tk.ps;
-    const uint32_t c0 = P * kPanel, cols = tk.cols;
+    const PanelState *ps = panel_state(tk, P);
+    const uint32_t c0 = P * kPanel;
+    const uint32_t cols = hi < tk.cols - c0 ? c0 + hi : tk.cols;
     const uint16_t *D = tk.D;
     const uint64_t ld = tk.ld, ldu = tk.ldu;
     uint16_t *U = tk.U;
     int8_t *Uh = tk.Uh, *Ul = tk.Ul;
     const uint32_t k = ps->k;
     if (k == 0) return;
-    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) Gs[i] = ps->G[i];
+    {
+        const uint4 *g4 = (const uint4 *)ps->G;
+        uint4 *s4 = (uint4 *)Gs;
+        const uint4 a = g4[threadIdx.x], b = g4[threadIdx.x + 256];
+        s4[threadIdx.x] = a;
+        s4[threadIdx.x + 256] = b;
+    }
     if (threadIdx.x < 64) qs[threadIdx.x] = ps->Qs[threadIdx.x];
     __syncthreads();
-    const uint32_t c = c0 + bx * 256 + threadIdx.x;
+    const uint32_t c = c0 + lo + bx * 256 + threadIdx.x;
     const bool ok = c < cols;
-#pragma unroll 8
-    for (uint32_t s = 0; s < k; s++) xs[s][threadIdx.x] = ok ? D[(uint64_t)qs[s] * ld + c] : 0;
-    __syncthreads();
-    if (!ok) return;
+    if (__ballot(ok) == 0) return;  // whole wave past the end (no barrier follows)
+    const uint32_t cc = ok ? c : c0 + lo;  // a valid column for idle lanes
+    uint32_t x[64];
+#pragma unroll
+    for (int s16 = 0; s16 < 4; s16++) {
+        if ((uint32_t)s16 * 16 < k) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t s = s16 * 16 + j < k ? s16 * 16 + j : k - 1;
+                x[s16 * 16 + j] = D[(uint64_t)qs[s] * ld + cc];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; j++) x[s16 * 16 + j] = 0;
+        }
+    }
     uint32_t hw[16], lw[16];
 #pragma unroll
     for (int i = 0; i < 16; i++) hw[i] = lw[i] = 0;
     for (uint32_t t = 0; t < k; t++) {
         uint32_t h = 0, l = 0;
-        for (uint32_t s = 0; s < k; s++) {
-            uint32_t gts = Gs[t * 64 + s];
-            uint32_t x = xs[s][threadIdx.x];
-            h = fl::mad24(gts >> 8, x, h);
-            l = fl::mad24(gts & 0xffu, x, l);
+        const uint4 *gr = (const uint4 *)(Gs + t * 64);
+#pragma unroll
+        for (int s8 = 0; s8 < 8; s8++) {
+            if ((uint32_t)s8 * 8 < k) {
+                const uint4 gv = gr[s8];
+                const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const uint32_t gts = (gw[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                    h = fl::mad24(gts >> 8, x[s8 * 8 + j], h);
+                    l = fl::mad24(gts & 0xffu, x[s8 * 8 + j], l);
+                }
+            }
         }
         const uint32_t u = fl::fold_pair(h, l, md);
-        U[(uint64_t)t * ldu + c] = (uint16_t)u;
+        if (ok) U[(uint64_t)t * ldu + c] = (uint16_t)u;
         if (Uh) {
             int lh, ll;
             fl_split_limbs(u, md.p, lh, ll);
@@ -409,7 +550,7 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
                 }
         }
     }
-    if (Uh) {
+    if (Uh && ok) {
         uint4 *dh = (uint4 *)(Uh + (uint64_t)(c - c0) * 64), *dl = (uint4 *)(Ul + (uint64_t)(c - c0) * 64);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -422,10 +563,11 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
 // L[i][t] = Dt[i][Ccol[t]] (0 for t >= k); with limb planes, also L as
 // int8 limbs (64 bytes per row) and the list of rows with a nonzero
 // multiplier (rows whose update is zero are skipped by the rank-k update).
-// One wave per row, 8 rows per wave.
-// One workgroup (32 rows) of the multiplier gather of panel P.
+// One workgroup (32 rows) of the multiplier gather of panel P: one wave per
+// 8 rows, lane t = multiplier t, the 8 loads issued together, one list
+// append per workgroup.
 __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P, uint32_t *ccol) {
-    const PanelState *ps = (const PanelState *)tk.ps;
+    const PanelState *ps = panel_state(tk, P);
     const uint32_t rows = tk.rows;
     const uint16_t *D = tk.D;
     const uint64_t ld = tk.ld;
@@ -434,38 +576,49 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
     const uint32_t t = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (bx * 32 >= rows) return;
     const uint32_t k = ps->k;
+    if (k == 0) return;
     if (threadIdx.x < 64) ccol[threadIdx.x] = ps->Ccol[threadIdx.x];
     __syncthreads();
-    for (uint32_t u = 0; u < 8; u++) {
-        const uint32_t i = (bx * 4 + wave) * 8 + u;
-        bool nz = false;
+    const uint32_t col = t < k ? ccol[t] : P * kPanel;  // a valid column for t >= k
+    const uint32_t i0 = (bx * 4 + wave) * 8;
+    uint32_t x[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t i = i0 + u < rows ? i0 + u : rows - 1;
+        x[u] = D[(uint64_t)i * ld + col];
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t i = i0 + u;
+        if (t >= k) x[u] = 0;
         if (i < rows) {
-            const uint32_t x = t < k ? D[(uint64_t)i * ld + ccol[t]] : 0;
-            L[(uint64_t)i * 64 + t] = (uint16_t)x;
+            L[(uint64_t)i * 64 + t] = (uint16_t)x[u];
             if (Lh) {
                 int h = 0, l = 0;
-                fl_split_limbs(x, p, h, l);
+                fl_split_limbs(x[u], p, h, l);
                 Lh[(uint64_t)i * 64 + t] = (int8_t)h;
                 Ll[(uint64_t)i * 64 + t] = (int8_t)l;
-                nz = __ballot(x != 0) != 0;
+                mask |= (__ballot(x[u] != 0) != 0) ? 1u << u : 0u;
             }
         }
-        if (Lh) block_append(nz, i, tk.upd_rows, tk.counts + 3 * P + 2);
     }
+    if (Lh) block_append8(mask, i0 + t, tk.upd_rows, tk.counts + 3 * P + 2);
 }
 
 // Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
 // (columns), the others gather L (rows).
 __global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                 const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
-                                                uint32_t n_all, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
-                                                uint32_t n_active, uint32_t P) {
+                                                uint32_t n_c, uint32_t grid_u, uint32_t lo, uint32_t hi,
+                                                const uint32_t *__restrict__ pre_rows, uint32_t n_active,
+                                                uint32_t P) {
     __shared__ ULds S;
     if (blockIdx.x < grid_u) {
-        const uint32_t ti = fl_task_of(pre_c, n_all, blockIdx.x);
+        const uint32_t ti = fl_task_of(pre_c, n_c, blockIdx.x);
         const FlEchTask &t = tasks[ids[ti]];
         if (P >= t.npanels) return;
-        U_tile(md, t, blockIdx.x - pre_c[ti], P, S);
+        U_tile(md, t, blockIdx.x - pre_c[ti], P, S, lo, hi);
     } else {
         const uint32_t b = blockIdx.x - grid_u;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
@@ -482,17 +635,20 @@ __global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bi
                                                          const FlEchTask *__restrict__ tasks,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint32_t *__restrict__ pre, uint32_t ntask,
-                                                         uint32_t P) {
+                                                         uint32_t P, uint32_t lo, uint32_t hi) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &t = tasks[ids[ti]];
     if (P >= t.npanels) return;
     const uint32_t M = t.counts[3 * P + 2];
-    if (blockIdx.y * 64 >= M || ((const PanelState *)t.ps)->k == 0) return;
+    if (blockIdx.y * 64 >= M || panel_state(t, P)->k == 0) return;
     const uint32_t c0 = P * kPanel;
-    fl_mfma::mfma_rank64_tile(md, bias, c16, t.Lh, t.Ll, t.Uh, t.Ul, t.upd_rows, M, t.D + c0, t.ld, t.cols - c0,
-                              blockIdx.x - pre[ti], blockIdx.y, sv, rows_s);
+    const uint32_t w = hi < t.cols - c0 ? hi : t.cols - c0;
+    if (w <= lo) return;
+    fl_mfma::mfma_rank64_tile(md, bias, c16, t.Lh, t.Ll, t.Uh + (uint64_t)lo * 64, t.Ul + (uint64_t)lo * 64,
+                              t.upd_rows, M, t.D + c0 + lo, t.ld, w - lo, blockIdx.x - pre[ti], blockIdx.y, sv,
+                              rows_s);
 }
 
 // Rank-k update of every row, VALU form: column block (of 256) from the
@@ -500,34 +656,38 @@ __global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bi
 __global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint32_t *__restrict__ pre, uint32_t ntask,
-                                                         uint32_t P) {
+                                                         uint32_t P, uint32_t lo, uint32_t hi) {
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &t = tasks[ids[ti]];
     if (P >= t.npanels) return;
-    const PanelState *ps = (const PanelState *)t.ps;
+    const PanelState *ps = panel_state(t, P);
     const uint32_t c0 = P * kPanel, bx = blockIdx.x - pre[ti];
+    const uint32_t w = hi < t.cols - c0 ? hi : t.cols - c0;
+    if (w <= lo) return;
     for (uint32_t by = blockIdx.y; by * 32 < t.rows; by += gridDim.y)
-        fl_valu::valu_gemm_tile(md, t.rows, t.cols - c0, 0, &ps->k, t.L, 64, t.U + c0, t.ldu, t.D + c0, t.ld,
-                                bx, by);
+        fl_valu::valu_gemm_tile(md, t.rows, w - lo, 0, &ps->k, t.L, 64, t.U + c0 + lo, t.ldu, t.D + c0 + lo,
+                                t.ld, bx, by);
 }
 
 // Rows of Q receive U (after the rank-k update touched them): 256 columns
 // per workgroup from the prefix, pivot t = blockIdx.y.
-__device__ void setq_tile(const FlEchTask &tk, uint32_t bx, uint32_t t, uint32_t P) {
-    const PanelState *ps = (const PanelState *)tk.ps;
+__device__ void setq_tile(const FlEchTask &tk, uint32_t bx, uint32_t t, uint32_t P, uint32_t lo, uint32_t hi) {
+    const PanelState *ps = panel_state(tk, P);
     if (t >= ps->k) return;
-    const uint32_t row = ps->Phys[t];
-    const uint32_t c = P * kPanel + bx * 256 + threadIdx.x;
-    if (c < tk.cols) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
+    const uint32_t row = ps->Phys[t], c0 = P * kPanel;
+    const uint32_t end = hi < tk.cols - c0 ? c0 + hi : tk.cols;
+    const uint32_t c = c0 + lo + bx * 256 + threadIdx.x;
+    if (c < end) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
 }
 
 __global__ __launch_bounds__(256) void k_ech_setq(const FlEchTask *__restrict__ tasks,
                                                   const uint32_t *__restrict__ ids,
-                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P) {
+                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P,
+                                                  uint32_t lo, uint32_t hi) {
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &tk = tasks[ids[ti]];
     if (P >= tk.npanels) return;
-    setq_tile(tk, blockIdx.x - pre[ti], blockIdx.y, P);
+    setq_tile(tk, blockIdx.x - pre[ti], blockIdx.y, P, lo, hi);
 }
 
 // Step 7 of panel P and step 0 of panel P+1 in one launch (they touch
@@ -536,16 +696,17 @@ __global__ __launch_bounds__(256) void k_ech_setq(const FlEchTask *__restrict__ 
 // nonzero on panel P+1.
 __global__ __launch_bounds__(256) void k_ech_setq_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                         const uint32_t *__restrict__ ids,
-                                                        const uint32_t *__restrict__ pre_c, uint32_t n_all,
-                                                        uint32_t grid_c, const uint32_t *__restrict__ pre_rows,
-                                                        uint32_t n_next, uint32_t P) {
+                                                        const uint32_t *__restrict__ pre_c, uint32_t n_c,
+                                                        uint32_t grid_c, uint32_t lo, uint32_t hi,
+                                                        const uint32_t *__restrict__ pre_rows, uint32_t n_next,
+                                                        uint32_t P) {
     __shared__ CheckLds L;
     if (blockIdx.x < grid_c * kPanel) {
         const uint32_t bx = blockIdx.x % grid_c, t = blockIdx.x / grid_c;
-        const uint32_t ti = fl_task_of(pre_c, n_all, bx);
+        const uint32_t ti = fl_task_of(pre_c, n_c, bx);
         const FlEchTask &tk = tasks[ids[ti]];
         if (P >= tk.npanels) return;
-        setq_tile(tk, bx - pre_c[ti], t, P);
+        setq_tile(tk, bx - pre_c[ti], t, P, lo, hi);
     } else {
         const uint32_t b = blockIdx.x - grid_c * kPanel;
         const uint32_t ti = fl_task_of(pre_rows, n_next, b);
@@ -558,13 +719,13 @@ __global__ __launch_bounds__(256) void k_ech_setq_check(fl::Mod md, const FlEchT
 // Per-panel workgroup prefixes of the column-tiled kernels (one thread per
 // panel and table).
 __global__ void k_ech_prefixes(const FlEchTask *__restrict__ tasks, const uint32_t *__restrict__ ids,
-                               uint32_t n, uint32_t panels, uint32_t tile, uint32_t *out) {
+                               uint32_t n, uint32_t panels, uint32_t tile, uint32_t off, uint32_t *out) {
     for (uint32_t P = blockIdx.x * blockDim.x + threadIdx.x; P < panels; P += gridDim.x * blockDim.x) {
         uint32_t *o = out + (uint64_t)P * (n + 1);
         uint32_t acc = 0;
         o[0] = 0;
         for (uint32_t i = 0; i < n; i++) {
-            const uint32_t cols = tasks[ids[i]].cols, c0 = 64 * P;
+            const uint32_t cols = tasks[ids[i]].cols, c0 = 64 * P + off;
             acc += cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
             o[i + 1] = acc;
         }
@@ -607,7 +768,7 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     t.flist = c.take<uint32_t>(rows ? rows : 1);
     t.counts = c.take<uint32_t>(3 * (size_t)(npanels + 1));
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
-    t.ps = c.take<PanelState>(1);
+    t.ps = c.take<PanelState>(2);
     t.U = c.take<uint16_t>((size_t)64 * ldu);
     t.L = c.take<uint16_t>((size_t)(rows ? rows : 1) * 64);
     t.T = c.take<uint16_t>((size_t)(mn ? mn : 1) * ldu);
@@ -625,7 +786,7 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     t.task = c.take<FlEchTask>(1);
     t.ids = c.take<uint32_t>(1);
     t.pre_rows = c.take<uint32_t>(2);
-    t.pre = c.take<uint32_t>(3 * 2 * (size_t)(npanels ? npanels : 1));
+    t.pre = c.take<uint32_t>(4 * 2 * (size_t)(npanels ? npanels : 1));
     if (e) *e = t;
     return c.off;
 }
@@ -690,76 +851,123 @@ fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t 
 }
 
 hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint32_t panels,
-                               uint32_t *pre_c256, uint32_t *pre_m128, uint32_t *pre_p256,
                                hipStream_t stream) {
     if (panels == 0) return hipSuccess;
     const unsigned g = (panels + 255) / 256;
-    hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_all, L.n_all, panels, 256u,
-                       pre_c256);
-    if (L.n_mfma)
-        hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_mfma, L.n_mfma, panels,
-                           128u, pre_m128);
-    if (L.n_plain)
-        hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, L.ids_plain, L.n_plain, panels,
-                           256u, pre_p256);
+    const uint32_t one = 1u << 31;  // wider than any matrix: one tile per matrix
+    struct {
+        const uint32_t *ids;
+        uint32_t n, tile, off;
+        uint32_t *out;
+    } const tab[6] = {{L.ids_all, L.n_all, one, 0, L.pre_n_all},
+                      {L.ids_mfma, L.n_mfma, one, 0, L.pre_n_mfma},
+                      {L.ids_plain, L.n_plain, one, 0, L.pre_n_plain},
+                      {L.ids_all, L.n_all, 256, kFlEchNear, L.pre_f_all},
+                      {L.ids_mfma, L.n_mfma, 128, kFlEchNear, L.pre_f_mfma},
+                      {L.ids_plain, L.n_plain, 256, kFlEchNear, L.pre_f_plain}};
+    for (const auto &t : tab)
+        if (t.n) hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, t.ids, t.n, panels, t.tile,
+                                    t.off, t.out);
     return hipGetLastError();
 }
 
 hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t P,
-                                  uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
-                                  uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
-                                  uint32_t n_next, uint32_t grid_rows_next, hipStream_t stream) {
-    if (n_active == 0) return hipSuccess;
+                                  const FlEchGrid &g, hipStream_t stream, FlEchAux &aux) {
+    if (g.n_active == 0) return hipSuccess;
     const fl::Mod md = fl::make_mod(p);
-    const uint32_t *c256 = L.pre_c256 + (uint64_t)P * (L.n_all + 1);
+    const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
+    const uint32_t near = kFlEchNear, end = 0xffffffffu;
+    auto at = [P](const uint32_t *pre, uint32_t n) { return pre + (uint64_t)P * (n + 1); };
+    const uint32_t *na = at(L.pre_n_all, L.n_all), *fa = at(L.pre_f_all, L.n_all);
+    const uint32_t mfma_y = (g.mfma_rows + 63) / 64;
     hipError_t e;
-    if (P == 0) {  // later panels are listed by the previous panel's last launch
+    // pivot search: nonzero listing (panel 0 only: later panels are listed by
+    // the previous panel's last launch), probe basis, check, merge
+    if (P == 0) {
         FL_PROF("echelon.check", stream,
-                hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                                   L.pre_rows, n_active, P, 0));
+                hipLaunchKernelGGL(k_ech_check, dim3(g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                                   L.pre_rows, g.n_active, P, 0));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     FL_PROF("echelon.probe", stream,
-            hipLaunchKernelGGL(k_ech_probe, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
+            hipLaunchKernelGGL(k_ech_probe, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FL_PROF("echelon.check", stream,
-            hipLaunchKernelGGL(k_ech_check, dim3(grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               L.pre_rows, n_active, P, 1));
+            hipLaunchKernelGGL(k_ech_check, dim3(g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                               L.pre_rows, g.n_active, P, 1));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FL_PROF("echelon.merge", stream,
-            hipLaunchKernelGGL(k_ech_merge, dim3(n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
+            hipLaunchKernelGGL(k_ech_merge, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the previous panel's far part wrote the columns U and L read now
+    if (aux.far_pending) {
+        if ((e = hipStreamWaitEvent(stream, aux.ev_far, 0)) != hipSuccess) return e;
+        aux.far_pending = false;
+    }
     FL_PROF("echelon.UL", stream,
-            hipLaunchKernelGGL(k_ech_UL, dim3(grid_c256 + grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               c256, L.n_all, grid_c256, L.pre_rows, n_active, P));
+            hipLaunchKernelGGL(k_ech_UL, dim3(g.n_active + g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
+                               na, L.n_all, g.n_active, 0u, near, L.pre_rows, g.n_active, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (grid_m128) {
-        const uint32_t *m128 = L.pre_m128 + (uint64_t)P * (L.n_mfma + 1);
+    // far part on the second stream, once L and the panel state are there
+    if (g.f_all) {
+        if ((e = hipEventRecord(aux.ev_near, stream)) != hipSuccess) return e;
+        hipStream_t fs = aux.far;
+        if ((e = hipStreamWaitEvent(fs, aux.ev_near, 0)) != hipSuccess) return e;
+        FL_PROF("echelon.U_far", fs,
+                hipLaunchKernelGGL(k_ech_UL, dim3(g.f_all), dim3(256), 0, fs, md, tasks, L.ids_all, fa, L.n_all,
+                                   g.f_all, near, end, L.pre_rows, 0u, P));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (g.f_mfma) {
+            FL_PROF("echelon.mfma_far", fs,
+                    hipLaunchKernelGGL(k_ech_update_mfma, dim3(g.f_mfma, mfma_y), dim3(256), 0, fs, md, bias, c16,
+                                       tasks, L.ids_mfma, at(L.pre_f_mfma, L.n_mfma), L.n_mfma, P, near, end));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (g.f_plain) {
+            FL_PROF("echelon.plain_far", fs,
+                    hipLaunchKernelGGL(k_ech_update_valu, dim3(g.f_plain, 64), dim3(256), 0, fs, md, tasks,
+                                       L.ids_plain, at(L.pre_f_plain, L.n_plain), L.n_plain, P, near, end));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        FL_PROF("echelon.setq_far", fs,
+                hipLaunchKernelGGL(k_ech_setq, dim3(g.f_all, kPanel), dim3(256), 0, fs, tasks, L.ids_all, fa, L.n_all,
+                                   P, near, end));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipEventRecord(aux.ev_far, fs)) != hipSuccess) return e;
+        aux.far_pending = true;
+    }
+    // near part
+    if (g.n_mfma) {
         FL_PROF("echelon.mfma", stream,
-                hipLaunchKernelGGL(k_ech_update_mfma, dim3(grid_m128, (mfma_rows + 63) / 64), dim3(256), 0, stream, md,
-                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, m128,
-                                   L.n_mfma, P));
+                hipLaunchKernelGGL(k_ech_update_mfma, dim3(g.n_mfma, mfma_y), dim3(256), 0, stream, md, bias, c16,
+                                   tasks, L.ids_mfma, at(L.pre_n_mfma, L.n_mfma), L.n_mfma, P, 0u, near));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (grid_p256) {
-        const uint32_t *p256 = L.pre_p256 + (uint64_t)P * (L.n_plain + 1);
+    if (g.n_plain) {
         FL_PROF("echelon.plain", stream,
-                hipLaunchKernelGGL(k_ech_update_valu, dim3(grid_p256, 64), dim3(256), 0, stream, md, tasks,
-                                   L.ids_plain, p256, L.n_plain, P));
+                hipLaunchKernelGGL(k_ech_update_valu, dim3(g.n_plain, 64), dim3(256), 0, stream, md, tasks,
+                                   L.ids_plain, at(L.pre_n_plain, L.n_plain), L.n_plain, P, 0u, near));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (n_next) {
+    if (g.n_next) {
         FL_PROF("echelon.setq_check", stream,
-                hipLaunchKernelGGL(k_ech_setq_check, dim3(grid_c256 * kPanel + grid_rows_next), dim3(256), 0, stream,
-                                   md, tasks, L.ids_all, c256, L.n_all, grid_c256, L.pre_rows, n_next, P));
-    } else if (grid_c256) {
+                hipLaunchKernelGGL(k_ech_setq_check, dim3(g.n_active * kPanel + g.grid_rows_next), dim3(256), 0,
+                                   stream, md, tasks, L.ids_all, na, L.n_all, g.n_active, 0u, near, L.pre_rows,
+                                   g.n_next, P));
+    } else {
         FL_PROF("echelon.setq", stream,
-                hipLaunchKernelGGL(k_ech_setq, dim3(grid_c256, kPanel), dim3(256), 0, stream, tasks, L.ids_all,
-                                   c256, L.n_all, P));
+                hipLaunchKernelGGL(k_ech_setq, dim3(g.n_active, kPanel), dim3(256), 0, stream, tasks, L.ids_all, na,
+                                   L.n_all, P, 0u, near));
     }
     return hipGetLastError();
+}
+
+hipError_t fl_echelon_join(hipStream_t stream, FlEchAux &aux) {
+    if (!aux.far_pending) return hipSuccess;
+    aux.far_pending = false;
+    return hipStreamWaitEvent(stream, aux.ev_far, 0);
 }
 
 fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
@@ -778,12 +986,39 @@ fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
     return FL_OK;
 }
 
+// The second stream and events of fl_echelon_d, one set per host thread and
+// device (kept until the process ends), so that calls from several threads do
+// not share events.
+fl_status thread_aux(FlEchAux &aux) {
+    struct PerDevice {
+        hipStream_t s = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+    };
+    thread_local std::vector<PerDevice> cache;
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    if ((size_t)dev >= cache.size()) cache.resize(dev + 1);
+    PerDevice &d = cache[dev];
+    if (!d.s) {
+        FL_HIP(hipEventCreateWithFlags(&d.a, hipEventDisableTiming));
+        FL_HIP(hipEventCreateWithFlags(&d.b, hipEventDisableTiming));
+        FL_HIP(hipStreamCreateWithFlags(&d.s, hipStreamNonBlocking));
+    }
+    aux.far = d.s;
+    aux.ev_near = d.a;
+    aux.ev_far = d.b;
+    aux.far_pending = false;
+    return FL_OK;
+}
+
 extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt,
                                   uint64_t ldd, uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode,
                                   void *ws, size_t ws_bytes, hipStream_t stream) {
     FlEchTask t;
     fl_status st = fl_echelon_prepare(p, rows, cols, Dt, ldd, d_rank, d_pivcol, mode, ws, ws_bytes, stream, &t);
     if (st != FL_OK || t.npanels == 0) return st;
+    FlEchAux aux;
+    FL_CHECK_ST(thread_aux(aux));
     EchWs e;
     ech_layout(rows, cols, mode, ws, &e);
     // a one-entry task table
@@ -795,24 +1030,35 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
     FlEchLists L = {};
     L.ids_all = e.ids;
     L.pre_rows = e.pre_rows;
-    L.pre_c256 = e.pre;
     L.n_all = 1;
-    uint32_t *pre_m = e.pre + 2 * (size_t)np, *pre_p = e.pre + 4 * (size_t)np;
+    L.pre_n_all = e.pre;
+    L.pre_f_all = e.pre + 2 * (size_t)np;
     if (t.mfma) {
         L.ids_mfma = e.ids;
-        L.pre_m128 = pre_m;
         L.n_mfma = 1;
+        L.pre_n_mfma = e.pre + 4 * (size_t)np;
+        L.pre_f_mfma = e.pre + 6 * (size_t)np;
     } else {
         L.ids_plain = e.ids;
-        L.pre_p256 = pre_p;
         L.n_plain = 1;
+        L.pre_n_plain = e.pre + 4 * (size_t)np;
+        L.pre_f_plain = e.pre + 6 * (size_t)np;
     }
-    FL_HIP(fl_echelon_prefixes(e.task, L, np, e.pre, pre_m, pre_p, stream));
+    FL_HIP(fl_echelon_prefixes(e.task, L, np, stream));
     for (uint32_t P = 0; P < np; P++) {
-        const uint32_t g256 = fl_ech_tiles(cols, P, 256), g128 = fl_ech_tiles(cols, P, 128);
-        const uint32_t nn = P + 1 < np ? 1 : 0;
-        FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, 1, pre_rows[1], g256, t.mfma ? g128 : 0,
-                                      t.mfma ? 0 : g256, rows, nn, nn ? pre_rows[1] : 0, stream));
+        FlEchGrid g = {};
+        g.n_active = 1;
+        g.grid_rows = pre_rows[1];
+        g.n_mfma = t.mfma ? 1 : 0;
+        g.n_plain = t.mfma ? 0 : 1;
+        g.f_all = fl_ech_tiles(cols, P, 256, kFlEchNear);
+        g.f_mfma = t.mfma ? fl_ech_tiles(cols, P, 128, kFlEchNear) : 0;
+        g.f_plain = t.mfma ? 0 : g.f_all;
+        g.mfma_rows = rows;
+        g.n_next = P + 1 < np ? 1 : 0;
+        g.grid_rows_next = g.n_next ? pre_rows[1] : 0;
+        FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, g, stream, aux));
     }
+    FL_HIP(fl_echelon_join(stream, aux));
     return fl_echelon_finish(t, stream);
 }

@@ -132,6 +132,13 @@ void fl_prof_end(int tok, hipStream_t s);
 bool fl_prof_set(bool on);
 
 // Bracket one launch statement with profiler events (no-op when disabled).
+// Returns a non-OK fl_status from the enclosing function.
+#define FL_CHECK_ST(call)                      \
+    do {                                       \
+        fl_status st_ = (call);                \
+        if (st_ != FL_OK) return st_;          \
+    } while (0)
+
 #define FL_PROF(site, stream, ...)                                      \
     do {                                                                \
         int tok_ = fl_prof_begin(site, stream);                         \
@@ -251,38 +258,53 @@ struct FlEchTask {
 // Device tables for a panel loop over several matrices: ids sorted by panel
 // count (descending); per-panel workgroup prefixes for the column-tiled
 // kernels (n + 1 entries per panel, matrices already finished count 0).
+// Panel P's trailing work is split at column 64 P + 128: the near part (the
+// panel and the next one) is on the critical path of the next panel's pivot
+// search, the far part overlaps that search on a second stream.
 struct FlEchLists {
     const uint32_t *ids_all, *ids_mfma, *ids_plain;
-    const uint32_t *pre_rows;   // [n_all + 1]: ceil(rows / 32)
-    const uint32_t *pre_c256;   // [P][n_all + 1]: ceil((cols - 64 P) / 256)
-    const uint32_t *pre_m128;   // [P][n_mfma + 1]: ceil((cols - 64 P) / 128)
-    const uint32_t *pre_p256;   // [P][n_plain + 1]: ceil((cols - 64 P) / 256)
+    const uint32_t *pre_rows;  // [n_all + 1]: ceil(rows / 32)
+    // near part: one workgroup per matrix with more than P panels
+    uint32_t *pre_n_all, *pre_n_mfma, *pre_n_plain;
+    // far part: ceil((cols - 64 P - 128) / tile), tile 256 / 128 (MFMA) / 256
+    uint32_t *pre_f_all, *pre_f_mfma, *pre_f_plain;
     uint32_t n_all, n_mfma, n_plain;
 };
+constexpr uint32_t kFlEchNear = 128;  // columns of the near part
 // fl_echelon_d's set-up for one matrix (clears its bookkeeping on `stream`);
 // *task receives its table entry (npanels = 0 when there is nothing to do).
 fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt, uint64_t ldd,
                              uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws,
                              size_t ws_bytes, hipStream_t stream, FlEchTask *task);
-// Fills the three per-panel prefix tables of `lists` (device, P panels) from
-// the task table.
+// Fills the six per-panel prefix tables of `lists` (device, P panels) from the
+// task table.
 hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &lists, uint32_t panels,
-                               uint32_t *pre_c256, uint32_t *pre_m128, uint32_t *pre_p256,
                                hipStream_t stream);
 // Host mirror of the prefix tables' totals: workgroups of a column-tiled
-// kernel at panel P for a matrix with `cols` columns.
-inline uint32_t fl_ech_tiles(uint32_t cols, uint32_t P, uint32_t tile) {
-    const uint32_t c0 = 64 * P;
+// kernel over the columns from 64 P + off of a matrix with `cols` columns.
+inline uint32_t fl_ech_tiles(uint32_t cols, uint32_t P, uint32_t tile, uint32_t off = 0) {
+    const uint32_t c0 = 64 * P + off;
     return cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
 }
-// Panel P of every listed matrix: the seven panel kernels.  n_active: the
-// leading entries of ids_all with more than P panels; grid_*: the prefix
-// totals at P; mfma_rows: the largest row count among the MFMA-form matrices.
-// n_next, grid_rows_next: the same for panel P + 1 (its first step runs in
-// panel P's last launch).
-hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &lists,
-                                   uint32_t P, uint32_t n_active, uint32_t grid_rows, uint32_t grid_c256,
-                                   uint32_t grid_m128, uint32_t grid_p256, uint32_t mfma_rows,
-                                   uint32_t n_next, uint32_t grid_rows_next, hipStream_t stream);
+// Workgroup counts of panel P (host side).
+struct FlEchGrid {
+    uint32_t n_active, grid_rows;      // leading ids_all entries with more than P panels; their row blocks
+    uint32_t n_mfma, n_plain;          // MFMA / VALU-form matrices with more than P panels
+    uint32_t f_all, f_mfma, f_plain;   // far-part prefix totals
+    uint32_t mfma_rows;                // largest row count among the active MFMA-form matrices
+    uint32_t n_next, grid_rows_next;   // the same as n_active, grid_rows for panel P + 1
+};
+// The second stream of a panel loop and its two events; far_pending is set
+// while far-part work recorded on `far` has not yet been waited for.
+struct FlEchAux {
+    hipStream_t far;
+    hipEvent_t ev_near, ev_far;
+    bool far_pending;
+};
+// Panel P of every listed matrix on `stream`, its far part on aux.far.
+hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &lists, uint32_t P,
+                                   const FlEchGrid &g, hipStream_t stream, FlEchAux &aux);
+// Makes `stream` wait for the far part of the last panel.
+hipError_t fl_echelon_join(hipStream_t stream, FlEchAux &aux);
 // Moves the pivot rows of one matrix to the top in pivot order, clears the rest.
 fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream);
