@@ -232,7 +232,7 @@ void batch_layout(fl_batch *b) {
     b->off_etask = take(sizeof(FlEchTask) * n);
     b->off_eids = take(4 * 3 * n);
     b->off_epre_rows = take(4 * (n + 1));
-    b->off_epre = take(4 * 6 * (uint64_t)b->max_panels * (n + 1));
+    b->off_epre = take(4 * (3 * (uint64_t)b->max_panels + 6 * (uint64_t)((b->max_panels + 3) / 4)) * (n + 1));
     for (auto &mr : b->mats) {
         const fl_split_info &f = mr.info;
         mr.ldx = ld64(f.nB);
@@ -368,8 +368,13 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     }
     uint32_t *d_pre_rows = at<uint32_t>(arena, b->off_epre_rows);
     FL_CHECK_ST(upload_ids(d_pre_rows, pre_rows, stream));
-    const uint32_t Pm = b->max_panels;
-    uint32_t *pre_base = at<uint32_t>(arena, b->off_epre);
+    const uint32_t Pm = b->max_panels, Bm = (Pm + 3) / 4;
+    uint32_t *q = at<uint32_t>(arena, b->off_epre);
+    auto take_tab = [&q, n](uint32_t count) {
+        uint32_t *r = q;
+        q += (size_t)count * (n + 1);
+        return r;
+    };
     FlEchLists L = {};
     L.ids_all = d_ids[0];
     L.ids_mfma = d_ids[1];
@@ -378,9 +383,16 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     L.n_mfma = (uint32_t)ids[1].size();
     L.n_plain = (uint32_t)ids[2].size();
     L.pre_rows = d_pre_rows;
-    uint32_t **tabs[6] = {&L.pre_n_all, &L.pre_n_mfma, &L.pre_n_plain, &L.pre_f_all, &L.pre_f_mfma, &L.pre_f_plain};
-    for (int k = 0; k < 6; k++) *tabs[k] = pre_base + (size_t)k * Pm * (n + 1);
-    FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, stream));
+    L.pre_n_all = take_tab(Pm);
+    L.pre_n_mfma = take_tab(Pm);
+    L.pre_n_plain = take_tab(Pm);
+    L.pre_bn_all = take_tab(Bm);
+    L.pre_bn_mfma = take_tab(Bm);
+    L.pre_bn_plain = take_tab(Bm);
+    L.pre_bf_all = take_tab(Bm);
+    L.pre_bf_mfma = take_tab(Bm);
+    L.pre_bf_plain = take_tab(Bm);
+    FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, Bm, stream));
     FlEchAux aux = {b->ech_far, b->ech_near_ev, b->ech_far_ev, false};
     uint32_t active = L.n_all;
     auto active_at = [&](uint32_t P, uint32_t a) {
@@ -395,19 +407,33 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
         g.grid_rows = pre_rows[active];
         g.n_next = active_at(P + 1, active);
         g.grid_rows_next = g.n_next ? pre_rows[g.n_next] : 0;
-        for (uint32_t i : ids[0]) g.f_all += fl_ech_tiles(b->mats[i].info.nB, P, 256, kFlEchNear);
-        for (uint32_t i : ids[1]) {
-            if (!fl_ech_tiles(b->mats[i].info.nB, P, 1u << 31)) continue;
-            g.n_mfma++;
-            g.f_mfma += fl_ech_tiles(b->mats[i].info.nB, P, 128, kFlEchNear);
-            g.mfma_rows = std::max(g.mfma_rows, b->mats[i].info.mD);
+        for (uint32_t i : ids[1])
+            if (b->mats[i].npanels > P) {
+                g.n_mfma++;
+                g.mfma_rows = std::max(g.mfma_rows, b->mats[i].info.mD);
+            }
+        for (uint32_t i : ids[2])
+            if (b->mats[i].npanels > P) g.n_plain++;
+        FlEchBlockGrid bg = {};
+        const bool end = P % 4 == 3 || !g.n_next;
+        if (end) {
+            const uint64_t bend = (uint64_t)(P / 4 + 1) * kFlEchBlock;
+            for (uint32_t i : ids[0]) {
+                bg.bn_all += fl_ech_tiles(b->mats[i].info.nB, bend, kFlEchBlock, 64);
+                bg.bf_all += fl_ech_tiles(b->mats[i].info.nB, bend + kFlEchBlock, ~0ull, 64);
+            }
+            for (uint32_t i : ids[1]) {
+                const uint32_t cols = b->mats[i].info.nB;
+                bg.bn_mfma += fl_ech_tiles(cols, bend, kFlEchBlock, 128);
+                bg.bf_mfma += fl_ech_tiles(cols, bend + kFlEchBlock, ~0ull, 128);
+                if (cols > bend) bg.mfma_rows = std::max(bg.mfma_rows, b->mats[i].info.mD);
+            }
+            for (uint32_t i : ids[2]) {
+                bg.bn_plain += fl_ech_tiles(b->mats[i].info.nB, bend, kFlEchBlock, 256);
+                bg.bf_plain += fl_ech_tiles(b->mats[i].info.nB, bend + kFlEchBlock, ~0ull, 256);
+            }
         }
-        for (uint32_t i : ids[2]) {
-            if (!fl_ech_tiles(b->mats[i].info.nB, P, 1u << 31)) continue;
-            g.n_plain++;
-            g.f_plain += fl_ech_tiles(b->mats[i].info.nB, P, 256, kFlEchNear);
-        }
-        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, g, stream, aux));
+        FL_HIP(fl_echelon_batch_panel(b->p, d_tasks, L, P, g, end ? &bg : nullptr, stream, aux));
     }
     FL_HIP(fl_echelon_join(stream, aux));
     return FL_OK;

@@ -30,6 +30,7 @@
 // Panel states alternate between two slots for the same reason.
 // After the last panel the pivot rows are gathered to rows 0..r-1 in pivot
 // order and the other rows (now zero) are cleared.
+#include <algorithm>
 #include <vector>
 
 #include "fl_internal.h"
@@ -48,6 +49,9 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 namespace {
 
 constexpr uint32_t kPanel = 64;
+constexpr uint32_t kBlockPanels = 4;                  // panels per block of the delayed update
+constexpr uint32_t kBlock = kPanel * kBlockPanels;   // 256 columns, K of the block update
+constexpr uint32_t kSlots = 2 * kBlockPanels;        // panel states kept (two blocks)
 constexpr uint32_t kProbe = 64;  // rows in the probe basis pass (at least)
 constexpr uint32_t kListCap = 2048;  // LDS row list: room for two 1024-row windows
 constexpr int kGreedyThreads = 1024;
@@ -71,30 +75,33 @@ struct PanelState {
 struct EchWs {
     uint32_t *is_piv;   // [rows] 1 once the row is a pivot row
     uint32_t *piv_row;  // [min(rows, cols)]
-    PanelState *ps;
-    uint16_t *U;        // [64 x ldu]
-    uint16_t *L;        // [rows x 64]
+    PanelState *ps;     // [kSlots]
+    uint16_t *U;        // [64 x ldu] U of the current panel (its block's columns)
     uint16_t *T;        // [min(rows, cols) x ldu]
-    int8_t *Lh, *Ll;    // [rows x 64] limb planes of L (MFMA form)
-    int8_t *Uh, *Ul;    // [(cols + 128) x 64] limb planes of U transposed (MFMA form)
-    uint32_t *upd_rows; // [rows] rows with a nonzero multiplier
+    int8_t *Uh, *Ul;    // [(cols + 256) x 64] limb planes of U transposed (MFMA form)
+    uint16_t *Lb;       // [2][rows x 256] multipliers of a block's panels (block parity)
+    int8_t *Lbh, *Lbl;  // [2][rows x 256] their limb planes (MFMA form)
+    uint16_t *Ub;       // [2][256 x ldu] U of a block for the columns right of it (VALU form)
+    int8_t *Ubh, *Ubl;  // [2][(cols + 256) x 256] its limb planes, by column (MFMA form)
+    uint32_t *upd_rows; // [rows] rows with a nonzero multiplier in the current panel
+    uint32_t *blk_rows; // [2][rows] rows with a nonzero multiplier in a block
+    uint32_t *blk_cnt;  // [nblocks] their counts
+    uint32_t *mark;     // [rows] last block (+1) that listed the row
     uint32_t *nzlist;   // [rows] remaining rows nonzero on the panel
     uint32_t *flist;    // [rows] rows outside the probe basis' span
     uint32_t *counts;   // [3 * npanels] per panel: nonzero, flagged, update rows
-    void *gemm_ws;
-    size_t gemm_ws_bytes;
     uint64_t ldu;
     // one-entry task table for the single-matrix call
     FlEchTask *task;
     uint32_t *ids;       // [1] = 0
     uint32_t *pre_rows;  // [2]
-    uint32_t *pre;       // 3 x [npanels][2]
+    uint32_t *pre;       // prefix tables: 3 x [npanels][2], 6 x [nblocks][2]
 };
 
-// Panel states alternate between two slots, so that panel P + 1's search
-// can run while panel P's trailing update still reads its state.
+// The panel states of two blocks are kept, so that a block's panels can be
+// searched while the previous block's far update still reads its states.
 __device__ __forceinline__ PanelState *panel_state(const FlEchTask &t, uint32_t P) {
-    return (PanelState *)t.ps + (P & 1);
+    return (PanelState *)t.ps + (P % kSlots);
 }
 
 // Reduce the wave's vector (v: panel part, g: coefficient part, lane = column
@@ -198,13 +205,14 @@ struct __attribute__((aligned(16))) GreedyLds {
     uint32_t list[kListCap];
 };
 
-// Process rows S.list[0..S.cnt) in order: each wave reduces one row against
-// the basis; rows still nonzero are inserted one at a time (a new pivot is
-// the first nonzero column).  The inserting wave normalises its row; the new
-// pivot column is then cleared from the older basis rows by all waves (rows
-// dealt round-robin), so that the basis stays in reduced form.  This is the
-// paper's parallel structured elimination (Sec. 5.1) in miniature:
-// reductions in parallel, insertion of a new pivot serialised.
+// Process rows S.list[0..S.cnt), 16 at a time (one per wave): every row is
+// reduced against the basis in parallel; then, while some row of the batch
+// is still nonzero, the first such row is inserted (normalised at its first
+// nonzero column, the new pivot) and every wave clears the new pivot column,
+// from the older basis rows (dealt round-robin) and from its own row.  The
+// basis stays in reduced form, so each reduction reads the multipliers from
+// the vector as it is.  This is the paper's parallel structured elimination
+// (Sec. 5.1) in miniature: reductions in parallel, insertion serialised.
 __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, uint64_t ld,
                             uint32_t c0, uint32_t pw, GreedyLds &S) {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -214,6 +222,9 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
     // the next batch's row is fetched while the current batch is processed
     uint32_t row_n = wave < cnt ? S.list[wave] : S.list[0];
     uint32_t v_n = D[(uint64_t)row_n * ld + col];
+    // S.nzmask[r & 1]: waves with a nonzero row in round r; a slot is cleared
+    // one round before it is filled, after the barriers that end its last read
+    uint32_t r = 0;
     for (uint32_t base = 0; base < cnt; base += nw) {
         if (S.kb >= pw) break;  // panel full: every further row reduces to 0
         const uint32_t item = base + wave;
@@ -227,54 +238,48 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
             v_n = D[(uint64_t)row_n * ld + col];
         }
         uint32_t g = 0;
-        const uint32_t ks = S.kb;
-        // the mask of this batch was last read two batches ago, before the
-        // barrier that ended the previous batch's reads
-        uint32_t *nzm = &S.nzmask[(base / nw) & 1];
-        if (threadIdx.x == 0) *nzm = 0;
+        r++;
+        if (threadIdx.x == 0) S.nzmask[r & 1] = 0;
         __syncthreads();
-        reduce_against(md, v, g, 0, ks, S.Bv, S.Bg, S.Cc, lane, true);
-        const bool nz = __ballot(v != 0) != 0;
-        if (nz && lane == 0) atomicOr(nzm, 1u << wave);
+        reduce_against(md, v, g, 0, S.kb, S.Bv, S.Bg, S.Cc, lane, true);
+        if (__ballot(v != 0) != 0 && lane == 0) atomicOr(&S.nzmask[r & 1], 1u << wave);
         __syncthreads();
-        uint32_t mask = *nzm;
-        while (mask) {
-            const uint32_t w = (uint32_t)__ffs((int)mask) - 1;
-            mask &= mask - 1;
-            if (wave == w) {
+        for (;;) {
+            const uint32_t mask = S.nzmask[r & 1];
+            if (mask == 0 || S.kb >= pw) break;
+            if (threadIdx.x == 0) S.nzmask[(r + 1) & 1] = 0;
+            if (wave == (uint32_t)__ffs((int)mask) - 1) {
                 const uint32_t kb = S.kb;
-                reduce_against(md, v, g, ks, kb, S.Bv, S.Bg, S.Cc, lane, true);
-                const uint64_t m = __ballot(v != 0);
-                uint32_t c = 64;
-                if (m != 0 && kb < pw) {
-                    c = (uint32_t)__ffsll((long long)m) - 1;
-                    if (lane == kb) g = 1;
-                    const uint32_t piv = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
-                    const uint32_t inv = fl::invmod(piv, md);
-                    S.Bv[kb][lane] = (uint16_t)fl::mulmod(v, inv, md);
-                    S.Bg[kb][lane] = (uint16_t)fl::mulmod(g, inv, md);
-                }
+                const uint32_t c = (uint32_t)__ffsll((long long)__ballot(v != 0)) - 1;
+                if (lane == kb) g = 1;
+                const uint32_t inv = fl::invmod((uint32_t)__builtin_amdgcn_readlane((int)v, (int)c), md);
+                S.Bv[kb][lane] = (uint16_t)fl::mulmod(v, inv, md);
+                S.Bg[kb][lane] = (uint16_t)fl::mulmod(g, inv, md);
                 if (lane == 0) {
                     S.newc = c;
-                    if (c < 64) {
-                        S.Cc[kb] = c;
-                        S.Qo[kb] = row;
-                        S.kb = kb + 1;
-                    }
+                    S.Cc[kb] = c;
+                    S.Qo[kb] = row;
+                    S.kb = kb + 1;
                 }
+                v = 0;  // this row is now basis row kb
             }
             __syncthreads();
             const uint32_t c = S.newc, kn = S.kb;
-            if (c < 64) {
-                // clear column c from basis rows 0 .. kn - 2 with the new row kn - 1
-                for (uint32_t t = wave; t + 1 < kn; t += nw) {
-                    const uint32_t f = S.Bv[t][c];
-                    if (f) {
-                        S.Bv[t][lane] = (uint16_t)fl::submod(S.Bv[t][lane], fl::mulmod(f, S.Bv[kn - 1][lane], md), md.p);
-                        S.Bg[t][lane] = (uint16_t)fl::submod(S.Bg[t][lane], fl::mulmod(f, S.Bg[kn - 1][lane], md), md.p);
-                    }
+            const uint32_t nb = S.Bv[kn - 1][lane], ng = S.Bg[kn - 1][lane];
+            for (uint32_t t = wave; t + 1 < kn; t += nw) {
+                const uint32_t f = S.Bv[t][c];
+                if (f) {
+                    S.Bv[t][lane] = (uint16_t)fl::submod(S.Bv[t][lane], fl::mulmod(f, nb, md), md.p);
+                    S.Bg[t][lane] = (uint16_t)fl::submod(S.Bg[t][lane], fl::mulmod(f, ng, md), md.p);
                 }
             }
+            const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)c);
+            if (lam) {
+                v = fl::submod(v, fl::mulmod(lam, nb, md), md.p);
+                g = fl::submod(g, fl::mulmod(lam, ng, md), md.p);
+            }
+            r++;
+            if (__ballot(v != 0) != 0 && lane == 0) atomicOr(&S.nzmask[r & 1], 1u << wave);
             __syncthreads();
         }
     }
@@ -473,7 +478,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
 // over whole groups of 8.
 struct __attribute__((aligned(16))) ULds {
     uint16_t Gs[64 * 64];
-    uint32_t qs[64];
+    uint32_t qs[128];  // U: selected rows; L: pivot columns and rows
 };
 
 // One workgroup (256 columns from c0 + lo + 256 bx, below c0 + hi) of U for
@@ -560,26 +565,35 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
     }
 }
 
-// L[i][t] = Dt[i][Ccol[t]] (0 for t >= k); with limb planes, also L as
-// int8 limbs (64 bytes per row) and the list of rows with a nonzero
-// multiplier (rows whose update is zero are skipped by the rank-k update).
-// One workgroup (32 rows) of the multiplier gather of panel P: one wave per
-// 8 rows, lane t = multiplier t, the 8 loads issued together, one list
-// append per workgroup.
-__device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P, uint32_t *ccol) {
+// L'[i][t] = Dt[i][Ccol[t]] - [i = Phys[t]] (0 for t >= k): the multipliers
+// of panel P with the placement of U folded in (a pivot row t first loses
+// its whole panel combination, Dt[Q_t] - Dt[Q_t, C] U = 0, then gains U_t),
+// stored in slot P mod 4 of the block buffer Lb (256 per row) and, with limb
+// planes, as int8 limbs.  MFMA form: the rows with a nonzero multiplier are
+// listed for the panel's update, and the first time in the block also for
+// the block's update.  One workgroup (32 rows): one wave per 8 rows, lane t =
+// multiplier t, the 8 loads issued together, one list append per workgroup.
+__device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P, uint32_t *ccol,
+                       uint32_t *phys) {
     const PanelState *ps = panel_state(tk, P);
     const uint32_t rows = tk.rows;
     const uint16_t *D = tk.D;
     const uint64_t ld = tk.ld;
-    uint16_t *L = tk.L;
-    int8_t *Lh = tk.Lh, *Ll = tk.Ll;
+    const uint32_t b = P / kBlockPanels, slot = (P % kBlockPanels) * kPanel;
+    const uint64_t half = (uint64_t)(b & 1) * rows * kBlock;
+    uint16_t *Lb = tk.Lb + half;
+    int8_t *Lh = tk.Lbh ? tk.Lbh + half : nullptr, *Ll = tk.Lbl ? tk.Lbl + half : nullptr;
     const uint32_t t = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (bx * 32 >= rows) return;
     const uint32_t k = ps->k;
     if (k == 0) return;
-    if (threadIdx.x < 64) ccol[threadIdx.x] = ps->Ccol[threadIdx.x];
+    if (threadIdx.x < 64) {
+        ccol[threadIdx.x] = ps->Ccol[threadIdx.x];
+        phys[threadIdx.x] = ps->Phys[threadIdx.x];
+    }
     __syncthreads();
     const uint32_t col = t < k ? ccol[t] : P * kPanel;  // a valid column for t >= k
+    const uint32_t ph = t < k ? phys[t] : 0xffffffffu;
     const uint32_t i0 = (bx * 4 + wave) * 8;
     uint32_t x[8];
 #pragma unroll
@@ -592,148 +606,285 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
     for (int u = 0; u < 8; u++) {
         const uint32_t i = i0 + u;
         if (t >= k) x[u] = 0;
+        else if (ph == i) x[u] = fl::submod(x[u], 1, p);
         if (i < rows) {
-            L[(uint64_t)i * 64 + t] = (uint16_t)x[u];
+            Lb[(uint64_t)i * kBlock + slot + t] = (uint16_t)x[u];
             if (Lh) {
                 int h = 0, l = 0;
                 fl_split_limbs(x[u], p, h, l);
-                Lh[(uint64_t)i * 64 + t] = (int8_t)h;
-                Ll[(uint64_t)i * 64 + t] = (int8_t)l;
+                Lh[(uint64_t)i * kBlock + slot + t] = (int8_t)h;
+                Ll[(uint64_t)i * kBlock + slot + t] = (int8_t)l;
                 mask |= (__ballot(x[u] != 0) != 0) ? 1u << u : 0u;
             }
         }
     }
-    if (Lh) block_append8(mask, i0 + t, tk.upd_rows, tk.counts + 3 * P + 2);
+    if (!Lh) return;
+    block_append8(mask, i0 + t, tk.upd_rows, tk.counts + 3 * P + 2);
+    bool first = false;
+    if (t < 8 && ((mask >> t) & 1u)) first = atomicMax(&tk.mark[i0 + t], b + 1) < b + 1;
+    const uint32_t fmask = (uint32_t)__ballot(first) & 0xffu;
+    __syncthreads();  // block_append8's shared words are reused
+    block_append8(fmask, i0 + t, tk.blk_rows + (uint64_t)(b & 1) * rows, tk.blk_cnt + b);
 }
 
 // Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
-// (columns), the others gather L (rows).
+// over the rest of the panel's block (one workgroup per matrix), the others
+// gather L' (rows).
 __global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                 const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
-                                                uint32_t n_c, uint32_t grid_u, uint32_t lo, uint32_t hi,
-                                                const uint32_t *__restrict__ pre_rows, uint32_t n_active,
-                                                uint32_t P) {
+                                                uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
+                                                uint32_t n_active, uint32_t P) {
     __shared__ ULds S;
     if (blockIdx.x < grid_u) {
         const uint32_t ti = fl_task_of(pre_c, n_c, blockIdx.x);
         const FlEchTask &t = tasks[ids[ti]];
         if (P >= t.npanels) return;
-        U_tile(md, t, blockIdx.x - pre_c[ti], P, S, lo, hi);
+        const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
+        U_tile(md, t, blockIdx.x - pre_c[ti], P, S, 0, bend - c0);
     } else {
         const uint32_t b = blockIdx.x - grid_u;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
         const FlEchTask &t = tasks[ids[ti]];
         if (P >= t.npanels) return;
-        L_tile(md.p, t, b - pre_rows[ti], P, S.qs);
+        L_tile(md.p, t, b - pre_rows[ti], P, S.qs, S.qs + 64);
     }
 }
 
-// Rank-k update of the rows with a nonzero multiplier, int8 MFMA form: one
-// 64-row x 128-column tile per workgroup (column block from the prefix, row
-// block blockIdx.y of the row list; blocks beyond the list exit at once).
+// Panel P's update of the rest of its block, int8 MFMA form: rows with a
+// nonzero multiplier, one 64-row x 128-column tile per workgroup (two column
+// tiles per matrix: workgroup x = 2 slot + tile; row block blockIdx.y;
+// blocks beyond the list or the block exit at once).
 __global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                          const FlEchTask *__restrict__ tasks,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint32_t *__restrict__ pre, uint32_t ntask,
-                                                         uint32_t P, uint32_t lo, uint32_t hi) {
+                                                         uint32_t P) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
-    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x >> 1), bx = blockIdx.x & 1;
     const FlEchTask &t = tasks[ids[ti]];
     if (P >= t.npanels) return;
     const uint32_t M = t.counts[3 * P + 2];
     if (blockIdx.y * 64 >= M || panel_state(t, P)->k == 0) return;
-    const uint32_t c0 = P * kPanel;
-    const uint32_t w = hi < t.cols - c0 ? hi : t.cols - c0;
-    if (w <= lo) return;
-    fl_mfma::mfma_rank64_tile(md, bias, c16, t.Lh, t.Ll, t.Uh + (uint64_t)lo * 64, t.Ul + (uint64_t)lo * 64,
-                              t.upd_rows, M, t.D + c0 + lo, t.ld, w - lo, blockIdx.x - pre[ti], blockIdx.y, sv,
-                              rows_s);
+    const uint32_t c0 = P * kPanel, b = P / kBlockPanels, bend = (b + 1) * kBlock;
+    const uint32_t N = (bend < t.cols ? bend : t.cols) - c0;
+    if (bx * 128 >= N) return;
+    const uint64_t half = (uint64_t)(b & 1) * t.rows * kBlock, slot = (P % kBlockPanels) * kPanel;
+    fl_mfma::mfma_rankk_tile<1>(md, bias, c16, t.Lbh + half + slot, t.Lbl + half + slot, kBlock, t.Uh, t.Ul, 64,
+                                t.upd_rows, M, t.D + c0, t.ld, N, bx, blockIdx.y, sv, rows_s);
 }
 
-// Rank-k update of every row, VALU form: column block (of 256) from the
-// prefix, row blocks (of 32) blockIdx.y, blockIdx.y + gridDim.y, ...
+// The same, VALU form: every row, one 256-column tile per matrix, row blocks
+// (of 32) blockIdx.y, blockIdx.y + gridDim.y, ...
 __global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint32_t *__restrict__ pre, uint32_t ntask,
-                                                         uint32_t P, uint32_t lo, uint32_t hi) {
+                                                         uint32_t P) {
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &t = tasks[ids[ti]];
     if (P >= t.npanels) return;
     const PanelState *ps = panel_state(t, P);
-    const uint32_t c0 = P * kPanel, bx = blockIdx.x - pre[ti];
-    const uint32_t w = hi < t.cols - c0 ? hi : t.cols - c0;
-    if (w <= lo) return;
+    const uint32_t c0 = P * kPanel, b = P / kBlockPanels, bend = (b + 1) * kBlock;
+    const uint32_t N = (bend < t.cols ? bend : t.cols) - c0;
+    const uint16_t *A = t.Lb + (uint64_t)(b & 1) * t.rows * kBlock + (P % kBlockPanels) * kPanel;
     for (uint32_t by = blockIdx.y; by * 32 < t.rows; by += gridDim.y)
-        fl_valu::valu_gemm_tile(md, t.rows, w - lo, 0, &ps->k, t.L, 64, t.U + c0 + lo, t.ldu, t.D + c0 + lo,
-                                t.ld, bx, by);
+        fl_valu::valu_gemm_tile(md, t.rows, N, 0, &ps->k, A, kBlock, t.U + c0, t.ldu, t.D + c0, t.ld, 0, by);
 }
 
-// Rows of Q receive U (after the rank-k update touched them): 256 columns
-// per workgroup from the prefix, pivot t = blockIdx.y.
-__device__ void setq_tile(const FlEchTask &tk, uint32_t bx, uint32_t t, uint32_t P, uint32_t lo, uint32_t hi) {
-    const PanelState *ps = panel_state(tk, P);
-    if (t >= ps->k) return;
-    const uint32_t row = ps->Phys[t], c0 = P * kPanel;
-    const uint32_t end = hi < tk.cols - c0 ? c0 + hi : tk.cols;
-    const uint32_t c = c0 + lo + bx * 256 + threadIdx.x;
-    if (c < end) tk.D[(uint64_t)row * tk.ld + c] = tk.U[(uint64_t)t * tk.ldu + c];
-}
+// U of block b for the columns right of it.  With D0 = Dt at the start of
+// the block (the columns right of it are untouched by the block's panels)
+// and R_j = D0[Q_j] the selected rows of panel j of the block:
+//   U_j = G_j (R_j - sum_{j' < j} L'_j'[Q_j] U_j')
+// (the rows of panel j as the earlier panels of the block left them, then
+// panel j's combination).  One workgroup per 64 columns, lane = column:
+// wave w computes the entries s = w, w + 4, ... of the bracket, then the
+// rows t = w, w + 4, ... of U_j; the U rows of the block are kept in LDS.
+// Output: Ubh/Ubl (256 bytes per column, by absolute column) or Ub (rows
+// 64 j + t, u16).
+struct __attribute__((aligned(16))) UblkLds {
+    uint16_t Us[kBlock][64];
+    uint16_t Xs[64][64];
+};
 
-__global__ __launch_bounds__(256) void k_ech_setq(const FlEchTask *__restrict__ tasks,
+__global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                   const uint32_t *__restrict__ ids,
-                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t P,
-                                                  uint32_t lo, uint32_t hi) {
+                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t B,
+                                                  uint32_t lo, uint32_t span) {
+    __shared__ UblkLds S;
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
-    const FlEchTask &tk = tasks[ids[ti]];
-    if (P >= tk.npanels) return;
-    setq_tile(tk, blockIdx.x - pre[ti], blockIdx.y, P, lo, hi);
-}
-
-// Step 7 of panel P and step 0 of panel P+1 in one launch (they touch
-// different rows: the pivot rows of P, and rows that are no pivot rows):
-// the first grid_c * 64 workgroups place U, the others list the rows
-// nonzero on panel P+1.
-__global__ __launch_bounds__(256) void k_ech_setq_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                                        const uint32_t *__restrict__ ids,
-                                                        const uint32_t *__restrict__ pre_c, uint32_t n_c,
-                                                        uint32_t grid_c, uint32_t lo, uint32_t hi,
-                                                        const uint32_t *__restrict__ pre_rows, uint32_t n_next,
-                                                        uint32_t P) {
-    __shared__ CheckLds L;
-    if (blockIdx.x < grid_c * kPanel) {
-        const uint32_t bx = blockIdx.x % grid_c, t = blockIdx.x / grid_c;
-        const uint32_t ti = fl_task_of(pre_c, n_c, bx);
-        const FlEchTask &tk = tasks[ids[ti]];
-        if (P >= tk.npanels) return;
-        setq_tile(tk, bx - pre_c[ti], t, P, lo, hi);
+    const FlEchTask &t = tasks[ids[ti]];
+    const uint32_t P0 = B * kBlockPanels;
+    if (P0 >= t.npanels) return;
+    const uint32_t start = (B + 1) * kBlock + lo;
+    const uint32_t end = span < t.cols - start ? start + span : t.cols;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t c = start + (blockIdx.x - pre[ti]) * 64 + lane;
+    const bool ok = c < end;
+    const uint32_t cc = ok ? c : start;  // a valid column for idle lanes
+    const uint16_t *Lb = t.Lb + (uint64_t)(B & 1) * t.rows * kBlock;
+    {
+        uint4 *z = (uint4 *)&S.Us[0][0];
+        for (uint32_t i = threadIdx.x; i < kBlock * 64 * 2 / 16; i += 256) z[i] = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    const uint32_t nj = t.npanels - P0 < kBlockPanels ? t.npanels - P0 : kBlockPanels;
+    uint32_t kj[kBlockPanels];
+#pragma unroll
+    for (uint32_t j = 0; j < kBlockPanels; j++) kj[j] = j < nj ? panel_state(t, P0 + j)->k : 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kBlockPanels; j++) {
+        const PanelState *ps = panel_state(t, P0 + j);
+        const uint32_t k = kj[j];
+        if (k == 0) continue;
+        // bracket entries s = wave + 4 i: row q's entry and its multipliers
+        // on the earlier panels (lane tt holds L'_jj[q][tt]), fetched one
+        // entry ahead
+        uint32_t s = wave, q = s < k ? ps->Qs[s] : 0;
+        uint32_t x_n = t.D[(uint64_t)q * t.ld + cc], cf_n[kBlockPanels - 1];
+#pragma unroll
+        for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
+            cf_n[jj] = jj < j ? Lb[(uint64_t)q * kBlock + jj * kPanel + lane] : 0;
+        for (; s < k; s += 4) {
+            const uint32_t x = x_n;
+            uint32_t cf[kBlockPanels - 1];
+#pragma unroll
+            for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++) cf[jj] = cf_n[jj];
+            if (s + 4 < k) {
+                const uint32_t qn = ps->Qs[s + 4];
+                x_n = t.D[(uint64_t)qn * t.ld + cc];
+#pragma unroll
+                for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
+                    if (jj < j) cf_n[jj] = Lb[(uint64_t)qn * kBlock + jj * kPanel + lane];
+            }
+            uint32_t h = 0, l = 0;
+#pragma unroll
+            for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++) {
+                if (jj >= j) break;
+                for (uint32_t tt = 0; tt < kj[jj]; tt++) {
+                    const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)cf[jj], (int)tt);
+                    const uint32_t u = S.Us[jj * kPanel + tt][lane];
+                    h = fl::mad24(lam >> 8, u, h);
+                    l = fl::mad24(lam & 0xffu, u, l);
+                }
+            }
+            // at most 192 terms of 2^8 x 2^16: no intermediate fold needed
+            S.Xs[s][lane] = (uint16_t)fl::submod(x, fl::fold_pair(h, l, md), md.p);
+        }
+        __syncthreads();
+        // rows tt = wave + 4 i of U_j (lane s holds G_j[tt][s]), one row ahead
+        uint32_t g_n = wave < k ? ps->G[wave * 64 + lane] : 0;
+        for (uint32_t tt = wave; tt < k; tt += 4) {
+            const uint32_t gr = g_n;
+            if (tt + 4 < k) g_n = ps->G[(tt + 4) * 64 + lane];
+            uint32_t h = 0, l = 0;
+            for (uint32_t s2 = 0; s2 < k; s2++) {
+                const uint32_t gv = (uint32_t)__builtin_amdgcn_readlane((int)gr, (int)s2), xv = S.Xs[s2][lane];
+                h = fl::mad24(gv >> 8, xv, h);
+                l = fl::mad24(gv & 0xffu, xv, l);
+            }
+            S.Us[j * kPanel + tt][lane] = (uint16_t)fl::fold_pair(h, l, md);
+        }
+        __syncthreads();
+    }
+    if (!ok) return;
+    if (t.Ubh) {
+        // wave w: bytes [64 w, 64 w + 64) of the column's 256-byte rows
+        const uint64_t off = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)c * kBlock + wave * 64;
+        uint32_t hw[16], lw[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            hw[i] = lw[i] = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int lh, ll;
+                fl_split_limbs(S.Us[wave * 64 + 4 * i + e][lane], md.p, lh, ll);
+                hw[i] |= (uint32_t)(lh & 0xff) << (8 * e);
+                lw[i] |= (uint32_t)(ll & 0xff) << (8 * e);
+            }
+        }
+        uint4 *dh = (uint4 *)(t.Ubh + off), *dl = (uint4 *)(t.Ubl + off);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            dh[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
+            dl[i] = make_uint4(lw[4 * i], lw[4 * i + 1], lw[4 * i + 2], lw[4 * i + 3]);
+        }
     } else {
-        const uint32_t b = blockIdx.x - grid_c * kPanel;
-        const uint32_t ti = fl_task_of(pre_rows, n_next, b);
-        const FlEchTask &tk = tasks[ids[ti]];
-        if (P + 1 >= tk.npanels) return;
-        check_tile(md, tk, b - pre_rows[ti], P + 1, 0, L);
+        uint16_t *Ub = t.Ub + (uint64_t)(B & 1) * kBlock * t.ldu;
+        for (uint32_t r = wave; r < kBlock; r += 4) Ub[(uint64_t)r * t.ldu + c] = S.Us[r][lane];
     }
 }
 
-// Per-panel workgroup prefixes of the column-tiled kernels (one thread per
-// panel and table).
+// Block B's rank-256 update of columns [start, end) (start = 256 (B + 1) +
+// lo), int8 MFMA form: the rows listed for the block, one 64 x 128 tile per
+// workgroup.  Row blocks vary fastest (blockIdx.x), so that workgroups
+// dispatched together share their column tile of the block's U (64 KB of
+// limb planes) in L2 and stream the multiplier rows; column tiles (from the
+// prefix, `gcols` in all) are blockIdx.y, blockIdx.y + gridDim.y, ...
+__global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                             const FlEchTask *__restrict__ tasks,
+                                                             const uint32_t *__restrict__ ids,
+                                                             const uint32_t *__restrict__ pre, uint32_t ntask,
+                                                             uint32_t gcols, uint32_t B, uint32_t lo, uint32_t span) {
+    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
+    __shared__ uint32_t rows_s[64];
+    for (uint32_t cy = blockIdx.y; cy < gcols; cy += gridDim.y) {
+        const uint32_t ti = fl_task_of(pre, ntask, cy);
+        const FlEchTask &t = tasks[ids[ti]];
+        if (B * kBlockPanels >= t.npanels) continue;
+        const uint32_t M = t.blk_cnt[B];
+        if (blockIdx.x * 64 >= M) continue;
+        const uint32_t start = (B + 1) * kBlock + lo;
+        const uint32_t end = span < t.cols - start ? start + span : t.cols;
+        const uint64_t lhalf = (uint64_t)(B & 1) * t.rows * kBlock;
+        const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
+        fl_mfma::mfma_rankk_tile<kBlockPanels>(md, bias, c16, t.Lbh + lhalf, t.Lbl + lhalf, kBlock, t.Ubh + uoff,
+                                               t.Ubl + uoff, kBlock, t.blk_rows + (uint64_t)(B & 1) * t.rows, M,
+                                               t.D + start, t.ld, end - start, cy - pre[ti], blockIdx.x, sv,
+                                               rows_s);
+        __syncthreads();  // sv and rows_s are reused by the next tile
+    }
+}
+
+// The same, VALU form: every row, 256-column tiles from the prefix, row
+// blocks (of 32) blockIdx.y, blockIdx.y + gridDim.y, ...
+__global__ __launch_bounds__(256) void k_ech_update_blk_valu(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                             const uint32_t *__restrict__ ids,
+                                                             const uint32_t *__restrict__ pre, uint32_t ntask,
+                                                             uint32_t B, uint32_t lo, uint32_t span) {
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
+    const FlEchTask &t = tasks[ids[ti]];
+    if (B * kBlockPanels >= t.npanels) return;
+    const uint32_t start = (B + 1) * kBlock + lo;
+    const uint32_t end = span < t.cols - start ? start + span : t.cols;
+    const uint16_t *A = t.Lb + (uint64_t)(B & 1) * t.rows * kBlock;
+    const uint16_t *Ub = t.Ub + (uint64_t)(B & 1) * kBlock * t.ldu + start;
+    for (uint32_t by = blockIdx.y; by * 32 < t.rows; by += gridDim.y)
+        fl_valu::valu_gemm_tile(md, t.rows, end - start, kBlock, nullptr, A, kBlock, Ub, t.ldu, t.D + start,
+                                t.ld, blockIdx.x - pre[ti], by);
+}
+
+// Prefix tables: entry [i][x + 1] = workgroups of matrices ids[0..x] for panel
+// or block i, each counting ceil(min(cols - c, span) / tile) tiles over
+// [c, c + span), c = stride i + off (0 when cols <= c).
 __global__ void k_ech_prefixes(const FlEchTask *__restrict__ tasks, const uint32_t *__restrict__ ids,
-                               uint32_t n, uint32_t panels, uint32_t tile, uint32_t off, uint32_t *out) {
-    for (uint32_t P = blockIdx.x * blockDim.x + threadIdx.x; P < panels; P += gridDim.x * blockDim.x) {
-        uint32_t *o = out + (uint64_t)P * (n + 1);
+                               uint32_t n, uint32_t count, uint32_t stride, uint32_t off, uint32_t span,
+                               uint32_t tile, uint32_t *out) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        uint32_t *o = out + (uint64_t)i * (n + 1);
         uint32_t acc = 0;
         o[0] = 0;
-        for (uint32_t i = 0; i < n; i++) {
-            const uint32_t cols = tasks[ids[i]].cols, c0 = 64 * P + off;
-            acc += cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
-            o[i + 1] = acc;
+        for (uint32_t x = 0; x < n; x++) {
+            const uint64_t cols = tasks[ids[x]].cols, c = (uint64_t)stride * i + off;
+            if (cols > c) {
+                const uint64_t w = cols - c < span ? cols - c : span;
+                acc += (uint32_t)((w + tile - 1) / tile);
+            }
+            o[x + 1] = acc;
         }
     }
 }
 
-// Final placement: T[t] = Dt[piv_row[t]] for t < rank, then Dt[t] = T[t] and
-// the remaining rows are cleared.
 __global__ __launch_bounds__(256) void k_ech_gather_rows(const uint16_t *__restrict__ D, uint64_t ld,
                                                          uint32_t cols, const uint32_t *__restrict__ piv_row,
                                                          const uint32_t *__restrict__ d_rank,
@@ -762,31 +913,40 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     const uint32_t mn = rows < cols ? rows : cols;
     const uint64_t ldu = ((uint64_t)cols + 63) & ~(uint64_t)63;
     const uint32_t npanels = (cols + kPanel - 1) / kPanel;
+    const uint32_t nblocks = (npanels + kBlockPanels - 1) / kBlockPanels;
+    const size_t r1 = rows ? rows : 1;
     EchWs t;
-    t.is_piv = c.take<uint32_t>(rows ? rows : 1);
-    t.nzlist = c.take<uint32_t>(rows ? rows : 1);
-    t.flist = c.take<uint32_t>(rows ? rows : 1);
+    t.is_piv = c.take<uint32_t>(r1);
+    t.nzlist = c.take<uint32_t>(r1);
+    t.flist = c.take<uint32_t>(r1);
     t.counts = c.take<uint32_t>(3 * (size_t)(npanels + 1));
     t.piv_row = c.take<uint32_t>(mn ? mn : 1);
-    t.ps = c.take<PanelState>(2);
-    t.U = c.take<uint16_t>((size_t)64 * ldu);
-    t.L = c.take<uint16_t>((size_t)(rows ? rows : 1) * 64);
+    t.ps = c.take<PanelState>(kSlots);
+    // tiles read up to 4 columns past a row's last one: one spare row
+    t.U = c.take<uint16_t>((size_t)65 * ldu);
     t.T = c.take<uint16_t>((size_t)(mn ? mn : 1) * ldu);
+    t.Lb = c.take<uint16_t>(2 * r1 * kBlock);
     t.ldu = ldu;
-    t.gemm_ws_bytes = 0;
-    t.gemm_ws = nullptr;
-    t.Lh = t.Ll = t.Uh = t.Ul = nullptr;
+    t.Uh = t.Ul = t.Lbh = t.Lbl = t.Ubh = t.Ubl = nullptr;
+    t.Ub = nullptr;
     if (mode == FL_MFMA_I8) {
-        t.Lh = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
-        t.Ll = c.take<int8_t>((size_t)(rows ? rows : 1) * 64);
         t.Uh = c.take<int8_t>(((size_t)cols + 256) * 64);
         t.Ul = c.take<int8_t>(((size_t)cols + 256) * 64);
+        t.Lbh = c.take<int8_t>(2 * r1 * kBlock);
+        t.Lbl = c.take<int8_t>(2 * r1 * kBlock);
+        t.Ubh = c.take<int8_t>(2 * ((size_t)cols + kBlock) * kBlock);
+        t.Ubl = c.take<int8_t>(2 * ((size_t)cols + kBlock) * kBlock);
+    } else {
+        t.Ub = c.take<uint16_t>((2 * (size_t)kBlock + 1) * ldu);
     }
-    t.upd_rows = c.take<uint32_t>(rows ? rows : 1);
+    t.upd_rows = c.take<uint32_t>(r1);
+    t.blk_rows = c.take<uint32_t>(2 * r1);
+    t.blk_cnt = c.take<uint32_t>(nblocks ? nblocks : 1);
+    t.mark = c.take<uint32_t>(r1);
     t.task = c.take<FlEchTask>(1);
     t.ids = c.take<uint32_t>(1);
     t.pre_rows = c.take<uint32_t>(2);
-    t.pre = c.take<uint32_t>(4 * 2 * (size_t)(npanels ? npanels : 1));
+    t.pre = c.take<uint32_t>(2 * (3 * (size_t)(npanels ? npanels : 1) + 6 * (size_t)(nblocks ? nblocks : 1)));
     if (e) *e = t;
     return c.off;
 }
@@ -824,7 +984,10 @@ fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t 
         return FL_ERR_WORKSPACE;
     }
     const uint32_t npanels = (cols + kPanel - 1) / kPanel;
+    const uint32_t nblocks = (npanels + kBlockPanels - 1) / kBlockPanels;
     FL_HIP(fl_fill_u32(e.is_piv, 0, rows, stream));
+    FL_HIP(fl_fill_u32(e.mark, 0, rows, stream));
+    FL_HIP(fl_fill_u32(e.blk_cnt, 0, nblocks, stream));
     FL_HIP(fl_fill_u32(d_rank, 0, 1, stream));
     FL_HIP(fl_fill_u32(e.counts, 0, 3 * (size_t)npanels, stream));
     t.D = Dt;
@@ -835,14 +998,20 @@ fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t 
     t.piv_col = d_pivcol;
     t.ps = e.ps;
     t.U = e.U;
-    t.L = e.L;
     t.T = e.T;
     t.ldu = e.ldu;
-    t.Lh = e.Lh;
-    t.Ll = e.Ll;
     t.Uh = e.Uh;
     t.Ul = e.Ul;
+    t.Lb = e.Lb;
+    t.Ub = e.Ub;
+    t.Lbh = e.Lbh;
+    t.Lbl = e.Lbl;
+    t.Ubh = e.Ubh;
+    t.Ubl = e.Ubl;
     t.upd_rows = e.upd_rows;
+    t.blk_rows = e.blk_rows;
+    t.blk_cnt = e.blk_cnt;
+    t.mark = e.mark;
     t.nzlist = e.nzlist;
     t.flist = e.flist;
     t.counts = e.counts;
@@ -850,39 +1019,85 @@ fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t 
     return FL_OK;
 }
 
-hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint32_t panels,
+hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint32_t panels, uint32_t blocks,
                                hipStream_t stream) {
-    if (panels == 0) return hipSuccess;
-    const unsigned g = (panels + 255) / 256;
-    const uint32_t one = 1u << 31;  // wider than any matrix: one tile per matrix
-    struct {
+    const uint32_t one = 1u << 31, all = 0xffffffffu;  // a tile wider than any matrix; no cap
+    struct Tab {
         const uint32_t *ids;
-        uint32_t n, tile, off;
+        uint32_t n, count, stride, off, span, tile;
         uint32_t *out;
-    } const tab[6] = {{L.ids_all, L.n_all, one, 0, L.pre_n_all},
-                      {L.ids_mfma, L.n_mfma, one, 0, L.pre_n_mfma},
-                      {L.ids_plain, L.n_plain, one, 0, L.pre_n_plain},
-                      {L.ids_all, L.n_all, 256, kFlEchNear, L.pre_f_all},
-                      {L.ids_mfma, L.n_mfma, 128, kFlEchNear, L.pre_f_mfma},
-                      {L.ids_plain, L.n_plain, 256, kFlEchNear, L.pre_f_plain}};
-    for (const auto &t : tab)
-        if (t.n) hipLaunchKernelGGL(k_ech_prefixes, dim3(g), dim3(256), 0, stream, tasks, t.ids, t.n, panels, t.tile,
-                                    t.off, t.out);
+    } const tab[9] = {
+        {L.ids_all, L.n_all, panels, kPanel, 0, all, one, L.pre_n_all},
+        {L.ids_mfma, L.n_mfma, panels, kPanel, 0, all, one, L.pre_n_mfma},
+        {L.ids_plain, L.n_plain, panels, kPanel, 0, all, one, L.pre_n_plain},
+        {L.ids_all, L.n_all, blocks, kBlock, kBlock, kBlock, 64, L.pre_bn_all},
+        {L.ids_mfma, L.n_mfma, blocks, kBlock, kBlock, kBlock, 128, L.pre_bn_mfma},
+        {L.ids_plain, L.n_plain, blocks, kBlock, kBlock, kBlock, 256, L.pre_bn_plain},
+        {L.ids_all, L.n_all, blocks, kBlock, 2 * kBlock, all, 64, L.pre_bf_all},
+        {L.ids_mfma, L.n_mfma, blocks, kBlock, 2 * kBlock, all, 128, L.pre_bf_mfma},
+        {L.ids_plain, L.n_plain, blocks, kBlock, 2 * kBlock, all, 256, L.pre_bf_plain}};
+    for (const Tab &t : tab)
+        if (t.n && t.count)
+            hipLaunchKernelGGL(k_ech_prefixes, dim3((t.count + 255) / 256), dim3(256), 0, stream, tasks, t.ids, t.n,
+                               t.count, t.stride, t.off, t.span, t.tile, t.out);
     return hipGetLastError();
 }
 
+// Far-part kernels reserve this much LDS per workgroup (the rest of what
+// they use as dynamic shared memory), so that at most 3 of them share a
+// compute unit and every unit keeps room for one 1024-thread block of the
+// pivot search (its 25 KB of LDS and 4 waves per SIMD): otherwise the far
+// part, thousands of workgroups per launch, fills the chip and the search,
+// one workgroup on the critical path, waits for a free unit.
+constexpr uint32_t kFarLds = 44 * 1024;
+
+template <class K>
+uint32_t far_dyn_lds(K kernel) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void *)kernel) != hipSuccess || a.sharedSizeBytes >= kFarLds) return 0;
+    return kFarLds - (uint32_t)a.sharedSizeBytes;
+}
+
+// Block B's update of the columns [256 (B + 1) + lo, + span) on stream s:
+// U of the block for those columns, then the rank-256 update.
+hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t B,
+                        uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
+                        uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
+                        bool far, hipStream_t s) {
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk), dyn_m = far_dyn_lds(k_ech_update_blk_mfma),
+                          dyn_v = far_dyn_lds(k_ech_update_blk_valu);
+    hipError_t e;
+    if (!g_all) return hipSuccess;
+    FL_PROF(far ? "echelon.ublk_far" : "echelon.ublk", s,
+            hipLaunchKernelGGL(k_ech_ublk, dim3(g_all), dim3(256), far ? dyn_u : 0, s, md, tasks, L.ids_all, pa,
+                               L.n_all, B, lo, span));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (g_mfma) {
+        FL_PROF(far ? "echelon.blk_mfma_far" : "echelon.blk_mfma", s,
+                hipLaunchKernelGGL(k_ech_update_blk_mfma, dim3((mfma_rows + 63) / 64, std::min(g_mfma, 65535u)),
+                                   dim3(256), far ? dyn_m : 0, s, md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p),
+                                   tasks, L.ids_mfma, pm, L.n_mfma, g_mfma, B, lo, span));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (g_plain) {
+        FL_PROF(far ? "echelon.blk_plain_far" : "echelon.blk_plain", s,
+                hipLaunchKernelGGL(k_ech_update_blk_valu, dim3(g_plain, 64), dim3(256), far ? dyn_v : 0, s, md,
+                                   tasks, L.ids_plain, pp, L.n_plain, B, lo, span));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t P,
-                                  const FlEchGrid &g, hipStream_t stream, FlEchAux &aux) {
+                                  const FlEchGrid &g, const FlEchBlockGrid *blk, hipStream_t stream,
+                                  FlEchAux &aux) {
     if (g.n_active == 0) return hipSuccess;
     const fl::Mod md = fl::make_mod(p);
-    const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
-    const uint32_t near = kFlEchNear, end = 0xffffffffu;
-    auto at = [P](const uint32_t *pre, uint32_t n) { return pre + (uint64_t)P * (n + 1); };
-    const uint32_t *na = at(L.pre_n_all, L.n_all), *fa = at(L.pre_f_all, L.n_all);
+    auto at = [](const uint32_t *pre, uint32_t i, uint32_t n) { return pre + (uint64_t)i * (n + 1); };
     const uint32_t mfma_y = (g.mfma_rows + 63) / 64;
     hipError_t e;
-    // pivot search: nonzero listing (panel 0 only: later panels are listed by
-    // the previous panel's last launch), probe basis, check, merge
+    // pivot search: nonzero listing (panel 0 only: later panels are listed at
+    // the end of the previous one), probe basis, check, merge
     if (P == 0) {
         FL_PROF("echelon.check", stream,
                 hipLaunchKernelGGL(k_ech_check, dim3(g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
@@ -901,67 +1116,54 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             hipLaunchKernelGGL(k_ech_merge, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // the previous panel's far part wrote the columns U and L read now
-    if (aux.far_pending) {
-        if ((e = hipStreamWaitEvent(stream, aux.ev_far, 0)) != hipSuccess) return e;
-        aux.far_pending = false;
-    }
+    // U over the rest of the block and L'; the panel's update of its block
     FL_PROF("echelon.UL", stream,
             hipLaunchKernelGGL(k_ech_UL, dim3(g.n_active + g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               na, L.n_all, g.n_active, 0u, near, L.pre_rows, g.n_active, P));
+                               at(L.pre_n_all, P, L.n_all), L.n_all, g.n_active, L.pre_rows, g.n_active, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // far part on the second stream, once L and the panel state are there
-    if (g.f_all) {
-        if ((e = hipEventRecord(aux.ev_near, stream)) != hipSuccess) return e;
-        hipStream_t fs = aux.far;
-        if ((e = hipStreamWaitEvent(fs, aux.ev_near, 0)) != hipSuccess) return e;
-        FL_PROF("echelon.U_far", fs,
-                hipLaunchKernelGGL(k_ech_UL, dim3(g.f_all), dim3(256), 0, fs, md, tasks, L.ids_all, fa, L.n_all,
-                                   g.f_all, near, end, L.pre_rows, 0u, P));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (g.f_mfma) {
-            FL_PROF("echelon.mfma_far", fs,
-                    hipLaunchKernelGGL(k_ech_update_mfma, dim3(g.f_mfma, mfma_y), dim3(256), 0, fs, md, bias, c16,
-                                       tasks, L.ids_mfma, at(L.pre_f_mfma, L.n_mfma), L.n_mfma, P, near, end));
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (g.f_plain) {
-            FL_PROF("echelon.plain_far", fs,
-                    hipLaunchKernelGGL(k_ech_update_valu, dim3(g.f_plain, 64), dim3(256), 0, fs, md, tasks,
-                                       L.ids_plain, at(L.pre_f_plain, L.n_plain), L.n_plain, P, near, end));
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        FL_PROF("echelon.setq_far", fs,
-                hipLaunchKernelGGL(k_ech_setq, dim3(g.f_all, kPanel), dim3(256), 0, fs, tasks, L.ids_all, fa, L.n_all,
-                                   P, near, end));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = hipEventRecord(aux.ev_far, fs)) != hipSuccess) return e;
-        aux.far_pending = true;
-    }
-    // near part
     if (g.n_mfma) {
         FL_PROF("echelon.mfma", stream,
-                hipLaunchKernelGGL(k_ech_update_mfma, dim3(g.n_mfma, mfma_y), dim3(256), 0, stream, md, bias, c16,
-                                   tasks, L.ids_mfma, at(L.pre_n_mfma, L.n_mfma), L.n_mfma, P, 0u, near));
+                hipLaunchKernelGGL(k_ech_update_mfma, dim3(2 * g.n_mfma, mfma_y), dim3(256), 0, stream, md,
+                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma,
+                                   at(L.pre_n_mfma, P, L.n_mfma), L.n_mfma, P));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (g.n_plain) {
         FL_PROF("echelon.plain", stream,
                 hipLaunchKernelGGL(k_ech_update_valu, dim3(g.n_plain, 64), dim3(256), 0, stream, md, tasks,
-                                   L.ids_plain, at(L.pre_n_plain, L.n_plain), L.n_plain, P, 0u, near));
+                                   L.ids_plain, at(L.pre_n_plain, P, L.n_plain), L.n_plain, P));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (g.n_next) {
-        FL_PROF("echelon.setq_check", stream,
-                hipLaunchKernelGGL(k_ech_setq_check, dim3(g.n_active * kPanel + g.grid_rows_next), dim3(256), 0,
-                                   stream, md, tasks, L.ids_all, na, L.n_all, g.n_active, 0u, near, L.pre_rows,
-                                   g.n_next, P));
-    } else {
-        FL_PROF("echelon.setq", stream,
-                hipLaunchKernelGGL(k_ech_setq, dim3(g.n_active, kPanel), dim3(256), 0, stream, tasks, L.ids_all, na,
-                                   L.n_all, P, 0u, near));
+    if (blk) {
+        const uint32_t B = P / kBlockPanels;
+        // the previous block's far part wrote the columns read and updated now
+        if (aux.far_pending) {
+            if ((e = hipStreamWaitEvent(stream, aux.ev_far, 0)) != hipSuccess) return e;
+            aux.far_pending = false;
+        }
+        if ((e = block_update(md, p, tasks, L, B, 0, kBlock, blk->bn_all, blk->bn_mfma, blk->bn_plain,
+                              blk->mfma_rows, at(L.pre_bn_all, B, L.n_all), at(L.pre_bn_mfma, B, L.n_mfma),
+                              at(L.pre_bn_plain, B, L.n_plain), false, stream)) != hipSuccess)
+            return e;
+        if (blk->bf_all) {
+            if ((e = hipEventRecord(aux.ev_near, stream)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(aux.far, aux.ev_near, 0)) != hipSuccess) return e;
+            if ((e = block_update(md, p, tasks, L, B, kBlock, 0xffffffffu, blk->bf_all, blk->bf_mfma,
+                                  blk->bf_plain, blk->mfma_rows, at(L.pre_bf_all, B, L.n_all),
+                                  at(L.pre_bf_mfma, B, L.n_mfma), at(L.pre_bf_plain, B, L.n_plain), true,
+                                  aux.far)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(aux.ev_far, aux.far)) != hipSuccess) return e;
+            aux.far_pending = true;
+        }
     }
-    return hipGetLastError();
+    if (g.n_next) {
+        FL_PROF("echelon.check", stream,
+                hipLaunchKernelGGL(k_ech_check, dim3(g.grid_rows_next), dim3(256), 0, stream, md, tasks, L.ids_all,
+                                   L.pre_rows, g.n_next, P + 1, 0));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fl_echelon_join(hipStream_t stream, FlEchAux &aux) {
@@ -1026,38 +1228,57 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
     FL_HIP(fl_upload(e.task, &t, sizeof t, stream));
     FL_HIP(fl_upload(e.ids, &zero, 4, stream));
     FL_HIP(fl_upload(e.pre_rows, pre_rows, 8, stream));
-    const uint32_t np = t.npanels;
+    const uint32_t np = t.npanels, nb = (np + kBlockPanels - 1) / kBlockPanels;
     FlEchLists L = {};
     L.ids_all = e.ids;
     L.pre_rows = e.pre_rows;
     L.n_all = 1;
-    L.pre_n_all = e.pre;
-    L.pre_f_all = e.pre + 2 * (size_t)np;
+    uint32_t *q = e.pre;
+    auto take = [&q](uint32_t count) {
+        uint32_t *r = q;
+        q += 2 * (size_t)count;
+        return r;
+    };
+    L.pre_n_all = take(np);
+    L.pre_bn_all = take(nb);
+    L.pre_bf_all = take(nb);
+    uint32_t *pn = take(np), *pbn = take(nb), *pbf = take(nb);
     if (t.mfma) {
         L.ids_mfma = e.ids;
         L.n_mfma = 1;
-        L.pre_n_mfma = e.pre + 4 * (size_t)np;
-        L.pre_f_mfma = e.pre + 6 * (size_t)np;
+        L.pre_n_mfma = pn;
+        L.pre_bn_mfma = pbn;
+        L.pre_bf_mfma = pbf;
     } else {
         L.ids_plain = e.ids;
         L.n_plain = 1;
-        L.pre_n_plain = e.pre + 4 * (size_t)np;
-        L.pre_f_plain = e.pre + 6 * (size_t)np;
+        L.pre_n_plain = pn;
+        L.pre_bn_plain = pbn;
+        L.pre_bf_plain = pbf;
     }
-    FL_HIP(fl_echelon_prefixes(e.task, L, np, stream));
+    FL_HIP(fl_echelon_prefixes(e.task, L, np, nb, stream));
     for (uint32_t P = 0; P < np; P++) {
         FlEchGrid g = {};
         g.n_active = 1;
         g.grid_rows = pre_rows[1];
         g.n_mfma = t.mfma ? 1 : 0;
         g.n_plain = t.mfma ? 0 : 1;
-        g.f_all = fl_ech_tiles(cols, P, 256, kFlEchNear);
-        g.f_mfma = t.mfma ? fl_ech_tiles(cols, P, 128, kFlEchNear) : 0;
-        g.f_plain = t.mfma ? 0 : g.f_all;
         g.mfma_rows = rows;
         g.n_next = P + 1 < np ? 1 : 0;
         g.grid_rows_next = g.n_next ? pre_rows[1] : 0;
-        FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, g, stream, aux));
+        FlEchBlockGrid bg = {};
+        const bool end = P % kBlockPanels == kBlockPanels - 1 || P + 1 == np;
+        if (end) {
+            const uint64_t bend = (uint64_t)(P / kBlockPanels + 1) * kBlock;
+            bg.bn_all = fl_ech_tiles(cols, bend, kBlock, 64);
+            bg.bf_all = fl_ech_tiles(cols, bend + kBlock, ~0ull, 64);
+            const uint32_t bn = fl_ech_tiles(cols, bend, kBlock, t.mfma ? 128 : 256);
+            const uint32_t bf = fl_ech_tiles(cols, bend + kBlock, ~0ull, t.mfma ? 128 : 256);
+            (t.mfma ? bg.bn_mfma : bg.bn_plain) = bn;
+            (t.mfma ? bg.bf_mfma : bg.bf_plain) = bf;
+            bg.mfma_rows = rows;
+        }
+        FL_HIP(fl_echelon_batch_panel(p, e.task, L, P, g, end ? &bg : nullptr, stream, aux));
     }
     FL_HIP(fl_echelon_join(stream, aux));
     return fl_echelon_finish(t, stream);

@@ -249,50 +249,62 @@ struct FlEchTask {
     uint64_t ld;
     uint32_t rows, cols, npanels, mfma;
     uint32_t *is_piv, *piv_row, *piv_col, *d_rank;
-    void *ps;               // panel state
-    uint16_t *U, *L, *T;
+    void *ps;               // panel states
+    uint16_t *U, *T;
     uint64_t ldu;
-    int8_t *Lh, *Ll, *Uh, *Ul;  // int8-MFMA form only
-    uint32_t *upd_rows, *nzlist, *flist, *counts;
+    int8_t *Uh, *Ul;        // int8-MFMA form only
+    uint16_t *Lb, *Ub;      // block multipliers; block U (VALU form)
+    int8_t *Lbh, *Lbl, *Ubh, *Ubl;  // their limb planes (int8-MFMA form only)
+    uint32_t *upd_rows, *blk_rows, *blk_cnt, *mark, *nzlist, *flist, *counts;
 };
 // Device tables for a panel loop over several matrices: ids sorted by panel
-// count (descending); per-panel workgroup prefixes for the column-tiled
-// kernels (n + 1 entries per panel, matrices already finished count 0).
-// Panel P's trailing work is split at column 64 P + 128: the near part (the
-// panel and the next one) is on the critical path of the next panel's pivot
-// search, the far part overlaps that search on a second stream.
+// count (descending); workgroup prefixes for the column-tiled kernels (n + 1
+// entries per panel or block, matrices already finished count 0).
+// Panels are grouped in blocks of four (256 columns).  A panel updates only
+// the columns of its block; at the end of a block, the block's update of the
+// columns right of it is applied as one rank-256 update, the next block's
+// 256 columns first (they are on the critical path), the rest on a second
+// stream while the next block's panels are searched.
 struct FlEchLists {
     const uint32_t *ids_all, *ids_mfma, *ids_plain;
     const uint32_t *pre_rows;  // [n_all + 1]: ceil(rows / 32)
-    // near part: one workgroup per matrix with more than P panels
+    // per panel: one workgroup per matrix with more than P panels
     uint32_t *pre_n_all, *pre_n_mfma, *pre_n_plain;
-    // far part: ceil((cols - 64 P - 128) / tile), tile 256 / 128 (MFMA) / 256
-    uint32_t *pre_f_all, *pre_f_mfma, *pre_f_plain;
+    // per block b (bend = 256 (b + 1)): tiles of 64 / 128 / 256 columns over
+    // the next block [bend, bend + 256) and over the far part [bend + 256, cols)
+    uint32_t *pre_bn_all, *pre_bn_mfma, *pre_bn_plain;
+    uint32_t *pre_bf_all, *pre_bf_mfma, *pre_bf_plain;
     uint32_t n_all, n_mfma, n_plain;
 };
-constexpr uint32_t kFlEchNear = 128;  // columns of the near part
+constexpr uint32_t kFlEchBlock = 256;  // columns per block
 // fl_echelon_d's set-up for one matrix (clears its bookkeeping on `stream`);
 // *task receives its table entry (npanels = 0 when there is nothing to do).
 fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt, uint64_t ldd,
                              uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws,
                              size_t ws_bytes, hipStream_t stream, FlEchTask *task);
-// Fills the six per-panel prefix tables of `lists` (device, P panels) from the
-// task table.
+// Fills the prefix tables of `lists` (device; `panels` panels, `blocks`
+// blocks) from the task table.
 hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &lists, uint32_t panels,
-                               hipStream_t stream);
-// Host mirror of the prefix tables' totals: workgroups of a column-tiled
-// kernel over the columns from 64 P + off of a matrix with `cols` columns.
-inline uint32_t fl_ech_tiles(uint32_t cols, uint32_t P, uint32_t tile, uint32_t off = 0) {
-    const uint32_t c0 = 64 * P + off;
-    return cols > c0 ? (cols - c0 + tile - 1) / tile : 0;
+                               uint32_t blocks, hipStream_t stream);
+// Host mirror of the prefix tables' totals: tiles of `tile` columns over
+// [start, start + span) of a matrix with `cols` columns.
+inline uint32_t fl_ech_tiles(uint32_t cols, uint64_t start, uint64_t span, uint32_t tile) {
+    if (cols <= start) return 0;
+    const uint64_t w = cols - start < span ? cols - start : span;
+    return (uint32_t)((w + tile - 1) / tile);
 }
 // Workgroup counts of panel P (host side).
 struct FlEchGrid {
-    uint32_t n_active, grid_rows;      // leading ids_all entries with more than P panels; their row blocks
-    uint32_t n_mfma, n_plain;          // MFMA / VALU-form matrices with more than P panels
-    uint32_t f_all, f_mfma, f_plain;   // far-part prefix totals
-    uint32_t mfma_rows;                // largest row count among the active MFMA-form matrices
-    uint32_t n_next, grid_rows_next;   // the same as n_active, grid_rows for panel P + 1
+    uint32_t n_active, grid_rows;     // leading ids_all entries with more than P panels; their row blocks
+    uint32_t n_mfma, n_plain;         // MFMA / VALU-form matrices with more than P panels
+    uint32_t mfma_rows;               // largest row count among the active MFMA-form matrices
+    uint32_t n_next, grid_rows_next;  // the same as n_active, grid_rows for panel P + 1
+};
+// Workgroup counts of the update at the end of a block (host side): prefix
+// totals of the six block tables, and the largest row count among the
+// MFMA-form matrices with columns right of the block.
+struct FlEchBlockGrid {
+    uint32_t bn_all, bn_mfma, bn_plain, bf_all, bf_mfma, bf_plain, mfma_rows;
 };
 // The second stream of a panel loop and its two events; far_pending is set
 // while far-part work recorded on `far` has not yet been waited for.
@@ -301,10 +313,13 @@ struct FlEchAux {
     hipEvent_t ev_near, ev_far;
     bool far_pending;
 };
-// Panel P of every listed matrix on `stream`, its far part on aux.far.
+// Panel P of every listed matrix on `stream`; when P ends a block (blk
+// non-NULL), also the block's update of the columns right of it, its far
+// part on aux.far.
 hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEchLists &lists, uint32_t P,
-                                   const FlEchGrid &g, hipStream_t stream, FlEchAux &aux);
-// Makes `stream` wait for the far part of the last panel.
+                                   const FlEchGrid &g, const FlEchBlockGrid *blk, hipStream_t stream,
+                                   FlEchAux &aux);
+// Makes `stream` wait for the far part of the last block.
 hipError_t fl_echelon_join(hipStream_t stream, FlEchAux &aux);
 // Moves the pivot rows of one matrix to the top in pivot order, clears the rest.
 fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream);

@@ -216,64 +216,104 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     }
 }
 
-// Rank-k update, k <= 64 (the Gauss-Jordan panel updates): one MFMA K-step,
-// so the kernel is bound by the read-modify-write of C and its epilogue.  A
-// block owns 64 rows x 128 columns; rows are taken through an optional row
-// list (row_map, count *Mdev: only rows with nonzero multipliers), the C tile
-// is loaded first with row-contiguous 8-byte accesses (latency overlapping
-// the operand loads and MFMAs), residues are staged through LDS and C is
-// written back with 8-byte accesses.  A planes are indexed by the C row.
+// Rank-k update, k <= 64 KS (the Gauss-Jordan panel and block updates): KS
+// MFMA K-steps, so the kernel is bound by the read-modify-write of C and its
+// epilogue.  A block owns 64 rows x 128 columns; rows are taken through an
+// optional row list (row_map, M rows: only rows with nonzero multipliers),
+// the C tile is loaded first with row-contiguous 8-byte accesses (latency
+// overlapping the operand loads and MFMAs), residues are staged through LDS
+// and C is written back with 8-byte accesses.  A planes are indexed by the C
+// row (lda bytes per row), B planes by the C column (ldb bytes per column).
 // With K <= 64, |S_hh|, |S_ll| <= 2^20 and |S_mid| <= 2^21, so
 // 256 S_mid + S_ll fits 32 bits and the recombination needs three Barrett
-// reductions instead of five.
+// reductions; with K <= 256 the three sums are reduced separately.
 // One 64-row x 128-column tile (row block by, column block bx) of the
-// rank-k update; M rows in total.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in
-// LDS.  Callers looping over row blocks must synchronise between tiles.
-__device__ __forceinline__ void mfma_rank64_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
-                                                 const int8_t *__restrict__ Ah,
-                                                 const int8_t *__restrict__ Al,
-                                                 const int8_t *__restrict__ Bh,
-                                                 const int8_t *__restrict__ Bl,
-                                                 const uint32_t *__restrict__ row_map, uint32_t M,
-                                                 uint16_t *C, uint64_t ldc, uint32_t N, uint32_t bx,
-                                                 uint32_t by, uint16_t *sv, uint32_t *rows_s) {
+// update.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in LDS.  Callers looping
+// over row blocks must synchronise between tiles.
+template <int KS>
+__device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
+                                                uint32_t lda, const int8_t *__restrict__ Bh,
+                                                const int8_t *__restrict__ Bl, uint32_t ldb,
+                                                const uint32_t *__restrict__ row_map, uint32_t M, uint16_t *C,
+                                                uint64_t ldc, uint32_t N, uint32_t bx, uint32_t by, uint16_t *sv,
+                                                uint32_t *rows_s) {
+    static_assert(KS >= 1 && KS <= 4, "K up to 256");
+    // every operand lives in device memory: global (not flat) accesses, so
+    // that loads are counted apart from LDS traffic and can stay in flight
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
+    typedef __attribute__((address_space(1))) uint64_t gu64w;
+    typedef __attribute__((address_space(1))) const v4i gv4i;
     constexpr int kLd = kRank64Ld;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t m0 = by * 64, n0 = bx * 128;
     if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
     __syncthreads();
-    // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread
+    // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread;
+    // every load is issued (chunks outside the tile read C[0])
     uint64_t cv[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
         const uint32_t row = rows_s[r], col = n0 + c4;
-        cv[u] = 0;
-        if (row != 0xffffffffu && col + 4 <= N) cv[u] = *(const uint64_t *)(C + (uint64_t)row * ldc + col);
+        const bool ok = row != 0xffffffffu && col + 4 <= N;
+        cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
     }
     const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
     const uint32_t arow = rows_s[wave * 16 + cl];
-    v4i ah = {0, 0, 0, 0}, al = {0, 0, 0, 0};
-    if (arow != 0xffffffffu) {
-        ah = *(const v4i *)(Ah + (uint64_t)arow * 64 + kq);
-        al = *(const v4i *)(Al + (uint64_t)arow * 64 + kq);
+    const uint32_t ar = arow != 0xffffffffu ? arow : rows_s[0];  // row m0 exists
+    v4i ah[KS], al[KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+        ah[s] = *(gv4i *)(Ah + (uint64_t)ar * lda + s * 64 + kq);
+        al[s] = *(gv4i *)(Al + (uint64_t)ar * lda + s * 64 + kq);
+    }
+    // B fragments of column tile j + 1 are fetched while tile j is multiplied
+    v4i bh[2][KS], bl[2][KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+        const uint64_t b = (uint64_t)(n0 + cl) * ldb + s * 64 + kq;
+        bh[0][s] = *(gv4i *)(Bh + b);
+        bl[0][s] = *(gv4i *)(Bl + b);
+    }
+    if (arow == 0xffffffffu) {
+#pragma unroll
+        for (int s = 0; s < KS; s++) ah[s] = al[s] = v4i{0, 0, 0, 0};
     }
     const uint32_t bias2 = (uint32_t)(((1u << 30) + md.p - 1) / md.p * md.p);  // >= 2^30, multiple of p
 #pragma unroll
     for (int j = 0; j < 8; j++) {
-        const uint64_t b = (uint64_t)(n0 + j * 16 + cl) * 64 + kq;
-        const v4i bh = *(const v4i *)(Bh + b);
-        const v4i bl = *(const v4i *)(Bl + b);
+        const int cur = j & 1, nxt = cur ^ 1;
+        if (j + 1 < 8) {
+#pragma unroll
+            for (int s = 0; s < KS; s++) {
+                const uint64_t b = (uint64_t)(n0 + (j + 1) * 16 + cl) * ldb + s * 64 + kq;
+                bh[nxt][s] = *(gv4i *)(Bh + b);
+                bl[nxt][s] = *(gv4i *)(Bl + b);
+            }
+        }
         v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
-        hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bh, hh, 0, 0, 0);
-        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bl, mid, 0, 0, 0);
-        mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bh, mid, 0, 0, 0);
-        ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bl, ll, 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[s], bh[cur][s], hh, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[s], bl[cur][s], mid, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[s], bh[cur][s], mid, 0, 0, 0);
+            ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[s], bl[cur][s], ll, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const uint32_t rhh = signed_to_res(hh[e], md, bias);
-            const uint32_t rlo = fl::reduce32((uint32_t)(mid[e] * 256 + ll[e]) + bias2, md);
-            const uint32_t v = fl::reduce32(rhh * c16 + rlo, md);
+            uint32_t v;
+            if constexpr (KS == 1) {
+                const uint32_t rhh = signed_to_res(hh[e], md, bias);
+                const uint32_t rlo = fl::reduce32((uint32_t)(mid[e] * 256 + ll[e]) + bias2, md);
+                v = fl::reduce32(rhh * c16 + rlo, md);
+            } else {
+                const uint32_t rhh = signed_to_res(hh[e], md, bias);
+                const uint32_t rmid = signed_to_res(mid[e], md, bias);
+                const uint32_t rll = signed_to_res(ll[e], md, bias);
+                v = fl::reduce32(rhh * c16 + rll, md);
+                v = fl::reduce32(v + rmid * 256u, md);
+            }
             sv[(wave * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
         }
     }
@@ -291,12 +331,24 @@ __device__ __forceinline__ void mfma_rank64_tile(const fl::Mod &md, uint32_t bia
             for (int c = 0; c < 4; c++)
                 nv |= (uint64_t)fl::submod((uint32_t)(cv[u] >> (16 * c)) & 0xffffu,
                                            (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p) << (16 * c);
-            *(uint64_t *)o = nv;
+            *(gu64w *)o = nv;
         } else {
             for (uint32_t c = 0; col + c < N; c++)
                 o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p);
         }
     }
+}
+
+// K <= 64 with 64-byte A rows and B columns.
+__device__ __forceinline__ void mfma_rank64_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                 const int8_t *__restrict__ Ah,
+                                                 const int8_t *__restrict__ Al,
+                                                 const int8_t *__restrict__ Bh,
+                                                 const int8_t *__restrict__ Bl,
+                                                 const uint32_t *__restrict__ row_map, uint32_t M,
+                                                 uint16_t *C, uint64_t ldc, uint32_t N, uint32_t bx,
+                                                 uint32_t by, uint16_t *sv, uint32_t *rows_s) {
+    mfma_rankk_tile<1>(md, bias, c16, Ah, Al, 64, Bh, Bl, 64, row_map, M, C, ldc, N, bx, by, sv, rows_s);
 }
 
 }  // namespace fl_mfma
