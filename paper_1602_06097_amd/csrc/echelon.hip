@@ -706,10 +706,12 @@ struct __attribute__((aligned(16))) UblkLds {
     uint16_t Xs[64][64];
 };
 
-__global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                                  const uint32_t *__restrict__ ids,
-                                                  const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t B,
-                                                  uint32_t lo, uint32_t span) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                 const uint32_t *__restrict__ ids,
+                                                 const uint32_t *__restrict__ pre, uint32_t ntask, uint32_t B,
+                                                 uint32_t lo, uint32_t span) {
+    constexpr uint32_t NW = NT / 64;  // waves: entries s and rows t are dealt round-robin
     __shared__ UblkLds S;
     const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x);
     const FlEchTask &t = tasks[ids[ti]];
@@ -725,7 +727,7 @@ __global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *_
     const uint16_t *Lb = t.Lb + (uint64_t)(B & 1) * t.rows * kBlock;
     {
         uint4 *z = (uint4 *)&S.Us[0][0];
-        for (uint32_t i = threadIdx.x; i < kBlock * 64 * 2 / 16; i += 256) z[i] = make_uint4(0, 0, 0, 0);
+        for (uint32_t i = threadIdx.x; i < kBlock * 64 * 2 / 16; i += NT) z[i] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
     const uint32_t nj = t.npanels - P0 < kBlockPanels ? t.npanels - P0 : kBlockPanels;
@@ -745,13 +747,13 @@ __global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *_
 #pragma unroll
         for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
             cf_n[jj] = jj < j ? Lb[(uint64_t)q * kBlock + jj * kPanel + lane] : 0;
-        for (; s < k; s += 4) {
+        for (; s < k; s += NW) {
             const uint32_t x = x_n;
             uint32_t cf[kBlockPanels - 1];
 #pragma unroll
             for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++) cf[jj] = cf_n[jj];
-            if (s + 4 < k) {
-                const uint32_t qn = ps->Qs[s + 4];
+            if (s + NW < k) {
+                const uint32_t qn = ps->Qs[s + NW];
                 x_n = t.D[(uint64_t)qn * t.ld + cc];
 #pragma unroll
                 for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
@@ -774,9 +776,9 @@ __global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *_
         __syncthreads();
         // rows tt = wave + 4 i of U_j (lane s holds G_j[tt][s]), one row ahead
         uint32_t g_n = wave < k ? ps->G[wave * 64 + lane] : 0;
-        for (uint32_t tt = wave; tt < k; tt += 4) {
+        for (uint32_t tt = wave; tt < k; tt += NW) {
             const uint32_t gr = g_n;
-            if (tt + 4 < k) g_n = ps->G[(tt + 4) * 64 + lane];
+            if (tt + NW < k) g_n = ps->G[(tt + NW) * 64 + lane];
             uint32_t h = 0, l = 0;
             for (uint32_t s2 = 0; s2 < k; s2++) {
                 const uint32_t gv = (uint32_t)__builtin_amdgcn_readlane((int)gr, (int)s2), xv = S.Xs[s2][lane];
@@ -787,7 +789,7 @@ __global__ __launch_bounds__(256) void k_ech_ublk(fl::Mod md, const FlEchTask *_
         }
         __syncthreads();
     }
-    if (!ok) return;
+    if (!ok || wave >= 4) return;
     if (t.Ubh) {
         // wave w: bytes [64 w, 64 w + 64) of the column's 256-byte rows
         const uint64_t off = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)c * kBlock + wave * 64;
@@ -1044,12 +1046,13 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
 }
 
 // Far-part kernels reserve this much LDS per workgroup (the rest of what
-// they use as dynamic shared memory), so that at most 3 of them share a
+// they use as dynamic shared memory), so that at most 2 of them share a
 // compute unit and every unit keeps room for one 1024-thread block of the
-// pivot search (its 25 KB of LDS and 4 waves per SIMD): otherwise the far
-// part, thousands of workgroups per launch, fills the chip and the search,
-// one workgroup on the critical path, waits for a free unit.
-constexpr uint32_t kFarLds = 44 * 1024;
+// pivot search (its 25 KB of LDS, 4 waves per SIMD and their registers next
+// to two 160-register waves): otherwise the far part, thousands of
+// workgroups per launch, fills the chip and the search, one workgroup on the
+// critical path, waits for a free unit.
+constexpr uint32_t kFarLds = 64 * 1024;
 
 template <class K>
 uint32_t far_dyn_lds(K kernel) {
@@ -1064,13 +1067,20 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk), dyn_m = far_dyn_lds(k_ech_update_blk_mfma),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<256>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
-    FL_PROF(far ? "echelon.ublk_far" : "echelon.ublk", s,
-            hipLaunchKernelGGL(k_ech_ublk, dim3(g_all), dim3(256), far ? dyn_u : 0, s, md, tasks, L.ids_all, pa,
-                               L.n_all, B, lo, span));
+    // the next block's columns are on the critical path: 16 waves per 64
+    // columns there; the far part keeps 4 (and its LDS reservation)
+    if (far)
+        FL_PROF("echelon.ublk_far", s,
+                hipLaunchKernelGGL(k_ech_ublk<256>, dim3(g_all), dim3(256), dyn_u, s, md, tasks, L.ids_all, pa,
+                                   L.n_all, B, lo, span));
+    else
+        FL_PROF("echelon.ublk", s,
+                hipLaunchKernelGGL(k_ech_ublk<1024>, dim3(g_all), dim3(1024), 0, s, md, tasks, L.ids_all, pa,
+                                   L.n_all, B, lo, span));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g_mfma) {
         FL_PROF(far ? "echelon.blk_mfma_far" : "echelon.blk_mfma", s,
