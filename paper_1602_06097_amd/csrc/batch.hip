@@ -324,7 +324,7 @@ fl_status run_trsm(fl_batch *b, void *arena, hipStream_t stream) {
                                           sorted_ids(b, nblk, FL_PLAIN)};
     const std::vector<uint32_t> pre[3] = {
         prefix_of(b, ids[0], [](const MatrixRun &m) { return (m.info.nB + 63) / 64; }),
-        prefix_of(b, ids[1], [](const MatrixRun &m) { return (m.info.nB + 127) / 128; }),
+        prefix_of(b, ids[1], [](const MatrixRun &m) { return (m.info.nB + 127) / 128 * kFlTrsmSuper; }),
         prefix_of(b, ids[2], [&](const MatrixRun &m) { return (m.info.nB + 255) / 256 * (kFlTrsmBlock / w / 4); })};
     FlTrsmTask *d_tasks = at<FlTrsmTask>(arena, b->off_ttask);
     FL_HIP(fl_upload(d_tasks, tasks.data(), sizeof(FlTrsmTask) * n, stream));

@@ -225,10 +225,11 @@ struct FlTrsmTask {
     uint64_t ldx;
     uint32_t npiv, nB, nblk, mfma;
     int8_t *Ah, *Al, *Xh, *Xl;  // int8-MFMA form only
-    const uint32_t *kext;
+    const uint32_t *kext, *krange;
     uint64_t kp;
 };
 constexpr uint32_t kFlTrsmBlock = 128;
+constexpr uint32_t kFlTrsmSuper = 4;  // blocks per superblock of the MFMA-form update
 // fl_trsm's set-up (dense B into X, group bounds, MFMA band planes) for one
 // matrix, enqueued on `stream`; *task receives its table entry.
 fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
@@ -237,7 +238,7 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
 // (kind 0: VALU, 1: int8 MFMA; no-op at step 0) or the block solve (kind 2),
 // over tasks[ids[0..n)] with workgroup prefix `prefix` and `grid` workgroups.
 // Workgroups per matrix: solve ceil(nB / 64); VALU update
-// ceil(nB / 256) * (128 / w / 4); MFMA update ceil(nB / 128).
+// ceil(nB / 256) * (128 / w / 4); MFMA update ceil(nB / 128) * kFlTrsmSuper.
 hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
                                 const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,
                                 uint32_t step, hipStream_t stream);

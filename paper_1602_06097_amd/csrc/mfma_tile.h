@@ -216,7 +216,8 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     }
 }
 
-// Rank-k update, k <= 64 KS (the Gauss-Jordan panel and block updates): KS
+// Rank-k update, k <= 64 KS (Gauss-Jordan panel and block updates, TRSM near
+// updates): KS
 // MFMA K-steps, so the kernel is bound by the read-modify-write of C and its
 // epilogue.  A block owns 64 rows x 128 columns; rows are taken through an
 // optional row list (row_map, M rows: only rows with nonzero multipliers),
@@ -226,7 +227,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 // row (lda bytes per row), B planes by the C column (ldb bytes per column).
 // With K <= 64, |S_hh|, |S_ll| <= 2^20 and |S_mid| <= 2^21, so
 // 256 S_mid + S_ll fits 32 bits and the recombination needs three Barrett
-// reductions; with K <= 256 the three sums are reduced separately.
+// reductions; with K <= 384 the three sums are reduced separately.
 // One 64-row x 128-column tile (row block by, column block bx) of the
 // update.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in LDS.  Callers looping
 // over row blocks must synchronise between tiles.
@@ -238,7 +239,7 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
                                                 const uint32_t *__restrict__ row_map, uint32_t M, uint16_t *C,
                                                 uint64_t ldc, uint32_t N, uint32_t bx, uint32_t by, uint16_t *sv,
                                                 uint32_t *rows_s) {
-    static_assert(KS >= 1 && KS <= 4, "K up to 256");
+    static_assert(KS >= 1 && KS <= 6, "K up to 384");
     // every operand lives in device memory: global (not flat) accesses, so
     // that loads are counted apart from LDS traffic and can stay in flight
     typedef __attribute__((address_space(1))) const uint64_t gu64;

@@ -478,6 +478,19 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
 // ---- many TRSMs at once: step `step` solves block nblk - 1 - step of every
 // matrix in the task table (matrices with fewer blocks are finished) --------
 
+// Superblocks: kFlTrsmSuper consecutive blocks counted from the bottom
+// (block nblk - 1 starts the first).  The far update of a superblock takes
+// the A columns at and beyond its end R1 for all its rows in one GEMM; block
+// I's K range there, relative to R1, is [0, r1 + round_up(kext, 64) - R1)
+// (empty when negative); the columns between the block and R1 are the
+// block's near update, after the blocks below it in the superblock.
+__device__ __host__ inline uint32_t trsm_super_end(uint32_t I, uint32_t nblk, uint32_t npiv) {
+    const uint32_t s = nblk - 1 - I;                          // step of block I
+    const uint32_t bottom = nblk - 1 - s / kFlTrsmSuper * kFlTrsmSuper;  // the superblock's first block
+    const uint32_t e = (bottom + 1) * kTrsmBlock;
+    return e < npiv ? e : npiv;
+}
+
 // Rows [r0, r1) of the task's block for this step; false if none.
 __device__ __forceinline__ bool step_block(const FlTrsmTask &t, uint32_t step, uint32_t &I, uint32_t &r0,
                                            uint32_t &r1) {
@@ -518,8 +531,12 @@ __global__ __launch_bounds__(256) void k_trsm_update_b(fl::Mod md, const FlTrsmT
                     local / ct);
 }
 
-// Far update of the step's block, int8-MFMA form: one 128-column tile of the
-// band GEMM per workgroup.
+// Update of the step's block, int8-MFMA form, by superblocks: at the first
+// step of a superblock, its far update (all its rows, A columns from its end
+// R1 on: up to kFlTrsmSuper row tiles); at the other steps, the block's near
+// update (A columns [r1, R1): the blocks solved since).  Workgroups per
+// matrix: ceil(nB / 128) column tiles x kFlTrsmSuper row tiles, local index
+// = row tile * column tiles + column tile.
 __global__ __launch_bounds__(256) void k_trsm_update_mfma_b(fl::Mod md, uint32_t bias, uint32_t c16,
                                                             const FlTrsmTask *__restrict__ tasks,
                                                             const uint32_t *__restrict__ ids,
@@ -529,11 +546,66 @@ __global__ __launch_bounds__(256) void k_trsm_update_mfma_b(fl::Mod md, uint32_t
     const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
     const FlTrsmTask &t = tasks[ids[i]];
     uint32_t I, r0, r1;
-    if (!step_block(t, step, I, r0, r1) || r1 >= t.npiv) return;
-    const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1, r1,
-                          0, (uint32_t)(t.kp - r1), t.kext + I, nullptr, nullptr, nullptr,
-                          t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB};
-    fl_mfma::mfma_gemm_tile(md, bias, c16, g, blockIdx.x - prefix[i], 0, smem);
+    if (!step_block(t, step, I, r0, r1)) return;
+    const uint32_t ct = (t.nB + 127) / 128, local = blockIdx.x - prefix[i];
+    const uint32_t bx = local % ct, by = local / ct;
+    const uint32_t R1 = trsm_super_end(I, t.nblk, t.npiv);
+    if (step % kFlTrsmSuper == 0) {
+        const uint32_t top = I >= kFlTrsmSuper - 1 ? I - (kFlTrsmSuper - 1) : 0;
+        if (R1 >= t.npiv || top + by > I) return;
+        const uint32_t rt = top * kTrsmBlock;
+        const GemmPlanes g = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp, t.kp, R1,
+                              R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr, nullptr,
+                              t.X + (uint64_t)rt * t.ldx, t.ldx, R1 - rt, t.nB};
+        fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
+    } else {
+        if (by != 0) return;
+        // (R1 - r1 is a multiple of 128 unless R1 = npiv, where the band
+        // past R1 is zero)
+        const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1,
+                              r1, 0, (R1 - r1 + 63) / 64 * 64, t.kext + I, nullptr, nullptr, nullptr,
+                              t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB};
+        fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, 0, smem);
+    }
+}
+
+// Near update of block [r0, r1) (single matrix): X[r0:r1] -= A[r0:r1, r1:r1 + 64 KS]
+// X[r1:r1 + 64 KS] from the limb planes (the band is zero past the block's
+// entries), one 64-row x 128-column tile per workgroup, operands read
+// straight from global memory (K is at most 384: no LDS ring needed).
+template <int KS>
+__global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, uint32_t c16, const int8_t *Ah,
+                                                   const int8_t *Al, const int8_t *Xh, const int8_t *Xl,
+                                                   uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
+                                                   uint64_t ldx, uint32_t nB) {
+    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
+    __shared__ uint32_t rows_s[64];
+    fl_mfma::mfma_rankk_tile<KS>(md, bias, c16, Ah + (uint64_t)r0 * kp + r1, Al + (uint64_t)r0 * kp + r1,
+                                 (uint32_t)kp, Xh + r1, Xl + r1, (uint32_t)kp, nullptr, r1 - r0,
+                                 X + (uint64_t)r0 * ldx, ldx, nB, blockIdx.x, blockIdx.y, sv, rows_s);
+}
+
+hipError_t trsm_near(uint32_t ks, const fl::Mod &md, uint32_t p, const int8_t *Ah, const int8_t *Al,
+                     const int8_t *Xh, const int8_t *Xl, uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
+                     uint64_t ldx, uint32_t nB, hipStream_t s) {
+    const dim3 grid((nB + 127) / 128, (r1 - r0 + 63) / 64);
+    const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
+#define FL_NEAR(K)                                                                                         \
+    case K:                                                                                                \
+        hipLaunchKernelGGL(k_trsm_near<K>, grid, dim3(256), 0, s, md, bias, c16, Ah, Al, Xh, Xl, kp, r0, r1, X, \
+                           ldx, nB);                                                                       \
+        break;
+    switch (ks) {
+        FL_NEAR(1)
+        FL_NEAR(2)
+        FL_NEAR(3)
+        FL_NEAR(4)
+        FL_NEAR(5)
+        FL_NEAR(6)
+    default: return hipErrorInvalidValue;
+    }
+#undef FL_NEAR
+    return hipGetLastError();
 }
 
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
@@ -556,14 +628,27 @@ __global__ void k_trsm_kext(uint32_t w, uint32_t npiv, uint32_t nblk, const uint
     kext[I] = kend - r1;
 }
 
-// Zero the band [r1, r1 + round_up(kext, 64)) of the A limb planes for every
-// row of block blockIdx.x (row blockIdx.y within the block).
+__global__ void k_trsm_krange(uint32_t npiv, uint32_t nblk, const uint32_t *__restrict__ kext, uint32_t *krange) {
+    const uint32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nblk) return;
+    const uint32_t r1 = (I + 1) * kTrsmBlock < npiv ? (I + 1) * kTrsmBlock : npiv;
+    const uint32_t R1 = trsm_super_end(I, nblk, npiv);
+    const uint32_t end = r1 + (kext[I] + 63) / 64 * 64;
+    krange[2 * I] = 0;
+    krange[2 * I + 1] = end > R1 ? end - R1 : 0;
+}
+
+// Zero the band [r1, r1 + round_up(max(kext, R1 - r1), 64)) of the A limb
+// planes for every row of block blockIdx.x (row blockIdx.y within the block).
 __global__ __launch_bounds__(256) void k_trsm_zero_band(uint32_t npiv, const uint32_t *__restrict__ kext,
                                                         int8_t *Ah, int8_t *Al, uint64_t kp) {
     const uint32_t I = blockIdx.x, row = I * kTrsmBlock + blockIdx.y;
     if (row >= npiv) return;
     const uint32_t r1 = (I + 1) * kTrsmBlock < npiv ? (I + 1) * kTrsmBlock : npiv;
-    const uint32_t kb = (kext[I] + 63) / 64 * 64;
+    // the near update of the block reads up to round_up(R1 - r1, 64)
+    const uint32_t R1 = trsm_super_end(I, (npiv + kTrsmBlock - 1) / kTrsmBlock, npiv);
+    const uint32_t kf = (kext[I] + 63) / 64 * 64, kn = (R1 - r1 + 63) / 64 * 64;
+    const uint32_t kb = kf > kn ? kf : kn;
     int8_t *h = Ah + (uint64_t)row * kp + r1, *l = Al + (uint64_t)row * kp + r1;
     const uint4 z = make_uint4(0, 0, 0, 0);
     for (uint32_t k = threadIdx.x * 16; k < kb; k += blockDim.x * 16) {
@@ -638,7 +723,7 @@ hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const
 
 struct TrsmWs {
     int8_t *Ah, *Al, *Xh, *Xl;
-    uint32_t *kext;
+    uint32_t *kext, *krange;
     uint32_t *nin, *nnear;
     uint64_t kp;
 };
@@ -661,6 +746,7 @@ size_t trsm_layout(const fl_split_info *info, fl_mode mode, void *ws, TrsmWs *t)
         r.Xh = c.take<int8_t>(np * r.kp);
         r.Xl = c.take<int8_t>(np * r.kp);
         r.kext = c.take<uint32_t>((info->npiv + kTrsmBlock - 1) / kTrsmBlock);
+        r.krange = c.take<uint32_t>(2 * (size_t)((info->npiv + kTrsmBlock - 1) / kTrsmBlock));
     }
     if (t) *t = r;
     return c.off;
@@ -752,6 +838,8 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
         FL_PROF("trsm.tiles", stream, {
             hipLaunchKernelGGL(k_trsm_kext, dim3((nblk + 255) / 256), dim3(256), 0, stream, w, npiv,
                                nblk, (const uint64_t *)s->a_gptr, (const uint32_t *)s->a_pos, tw.kext);
+            hipLaunchKernelGGL(k_trsm_krange, dim3((nblk + 255) / 256), dim3(256), 0, stream, npiv, nblk,
+                               (const uint32_t *)tw.kext, tw.krange);
             hipLaunchKernelGGL(k_trsm_zero_band, dim3(nblk, kTrsmBlock), dim3(256), 0, stream, npiv,
                                (const uint32_t *)tw.kext, tw.Ah, tw.Al, tw.kp);
             hipLaunchKernelGGL(k_trsm_scatter_far, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w,
@@ -768,6 +856,7 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
     t.Xh = tw.Xh;
     t.Xl = tw.Xl;
     t.kext = tw.kext;
+    t.krange = tw.krange;
     t.kp = tw.kp;
     *task = t;
     return FL_OK;
@@ -815,10 +904,20 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         if (r1 < npiv) {
             hipError_t e;
             if (t.mfma) {
-                GemmPlanes gp = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl,
-                                 t.kp, t.kp, r1, r1, 0, (uint32_t)(t.kp - r1), t.kext + I, nullptr,
-                                 nullptr, nullptr, X + (uint64_t)r0 * ldx, ldx, r1 - r0, nB};
-                e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
+                const uint32_t step = t.nblk - 1 - I, R1 = trsm_super_end(I, t.nblk, npiv);
+                e = hipSuccess;
+                if (step % kFlTrsmSuper == 0) {  // far update of the superblock
+                    const uint32_t top = I >= kFlTrsmSuper - 1 ? I - (kFlTrsmSuper - 1) : 0;
+                    const uint32_t rt = top * kTrsmBlock;
+                    GemmPlanes gp = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp,
+                                     t.kp, R1, R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr,
+                                     nullptr, X + (uint64_t)rt * ldx, ldx, R1 - rt, nB};
+                    e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
+                } else {  // near update: the blocks of the superblock solved since
+                    FL_PROF("trsm.update.near", stream,
+                            e = trsm_near((R1 - r1 + 63) / 64, md, info->p, t.Ah, t.Al, t.Xh, t.Xl, t.kp, r0, r1,
+                                          X, ldx, nB, stream));
+                }
             } else {
                 const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
                 FL_PROF("trsm.update", stream,
