@@ -332,3 +332,29 @@ hipError_t fl_upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
     }
     return hipSuccess;
 }
+
+fl_status fl_aux_stream(uint32_t slot, hipStream_t *s, hipEvent_t *a, hipEvent_t *b) {
+    struct Aux {
+        hipStream_t s = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+    };
+    constexpr uint32_t kAuxSlots = 4;
+    thread_local std::vector<Aux> cache;
+    if (slot >= kAuxSlots) {
+        fl_set_error("fl_aux_stream: bad slot");
+        return FL_ERR_ARG;
+    }
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    if ((size_t)(dev + 1) * kAuxSlots > cache.size()) cache.resize((size_t)(dev + 1) * kAuxSlots);
+    Aux &x = cache[(size_t)dev * kAuxSlots + slot];
+    if (!x.s) {
+        FL_HIP(hipEventCreateWithFlags(&x.a, hipEventDisableTiming));
+        FL_HIP(hipEventCreateWithFlags(&x.b, hipEventDisableTiming));
+        FL_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    }
+    *s = x.s;
+    *a = x.a;
+    *b = x.b;
+    return FL_OK;
+}

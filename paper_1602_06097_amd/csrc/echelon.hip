@@ -1198,39 +1198,14 @@ fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
     return FL_OK;
 }
 
-// The second stream and events of fl_echelon_d, one set per host thread and
-// device (kept until the process ends), so that calls from several threads do
-// not share events.
-fl_status thread_aux(FlEchAux &aux) {
-    struct PerDevice {
-        hipStream_t s = nullptr;
-        hipEvent_t a = nullptr, b = nullptr;
-    };
-    thread_local std::vector<PerDevice> cache;
-    int dev = 0;
-    FL_HIP(hipGetDevice(&dev));
-    if ((size_t)dev >= cache.size()) cache.resize(dev + 1);
-    PerDevice &d = cache[dev];
-    if (!d.s) {
-        FL_HIP(hipEventCreateWithFlags(&d.a, hipEventDisableTiming));
-        FL_HIP(hipEventCreateWithFlags(&d.b, hipEventDisableTiming));
-        FL_HIP(hipStreamCreateWithFlags(&d.s, hipStreamNonBlocking));
-    }
-    aux.far = d.s;
-    aux.ev_near = d.a;
-    aux.ev_far = d.b;
-    aux.far_pending = false;
-    return FL_OK;
-}
-
 extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint16_t *Dt,
                                   uint64_t ldd, uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode,
                                   void *ws, size_t ws_bytes, hipStream_t stream) {
     FlEchTask t;
     fl_status st = fl_echelon_prepare(p, rows, cols, Dt, ldd, d_rank, d_pivcol, mode, ws, ws_bytes, stream, &t);
     if (st != FL_OK || t.npanels == 0) return st;
-    FlEchAux aux;
-    FL_CHECK_ST(thread_aux(aux));
+    FlEchAux aux = {};
+    FL_CHECK_ST(fl_aux_stream(0, &aux.far, &aux.ev_near, &aux.ev_far));
     EchWs e;
     ech_layout(rows, cols, mode, ws, &e);
     // a one-entry task table

@@ -168,6 +168,9 @@ struct GemmPlanes {
     uint32_t M, N;
 };
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
+// A second stream and two events for work that overlaps the caller's stream,
+// one set per host thread, device and slot (< 4), kept until the process ends.
+fl_status fl_aux_stream(uint32_t slot, hipStream_t *s, hipEvent_t *a, hipEvent_t *b);
 // Rank-k (k <= 64) update C[row_map[i], :N] -= A[row_map[i]] B^T for
 // i < *Mdev (<= Mmax); A planes: 64 bytes per C row; B planes: N_pad x 64.
 hipError_t fl_mfma_rank64_planes(uint32_t p, const int8_t *Ah, const int8_t *Al, const int8_t *Bh,
