@@ -228,6 +228,7 @@ struct FlTrsmTask {
     uint64_t ldx;
     uint32_t npiv, nB, nblk, mfma;
     int8_t *Ah, *Al, *Xh, *Xl;  // int8-MFMA form only
+    int8_t *Th, *Tl;            // limbs of I - (diagonal block)^-1, per block (int8-MFMA form)
     const uint32_t *kext, *krange;
     uint64_t kp;
 };

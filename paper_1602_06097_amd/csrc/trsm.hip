@@ -608,6 +608,187 @@ hipError_t trsm_near(uint32_t ks, const fl::Mod &md, uint32_t p, const int8_t *A
     return hipGetLastError();
 }
 
+// ---- int8-MFMA form: block solves as products with the block inverses ----
+// The diagonal block T = A[r0:r1, r0:r1] of every block is unit upper
+// triangular; its inverse is computed once for all blocks together (the
+// back substitution applied to the identity, every block in parallel).
+// The solve of a block at its step is then X[r0:r1] = T^-1 R (R: the block's
+// rows after the far and near updates), computed as R - (I - T^-1) R on the
+// matrix cores.
+
+// Y: identity in every 128 x 128 block (rows past npiv zero).
+__global__ __launch_bounds__(256) void k_trsm_eye(uint32_t npiv, uint32_t rows, uint16_t *Y) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)rows * kTrsmBlock) return;
+    const uint32_t r = (uint32_t)(i / kTrsmBlock), c = (uint32_t)(i % kTrsmBlock);
+    Y[i] = (r < npiv && c == r % kTrsmBlock) ? 1 : 0;
+}
+
+// Back substitution of every block on its identity: block blockIdx.x / 2,
+// 64-column half blockIdx.x % 2.
+template <int W>
+__global__ __launch_bounds__(64) void k_trsm_inv(fl::Mod md, const uint64_t *__restrict__ gptr,
+                                                 const uint32_t *__restrict__ pos, const uint16_t *__restrict__ val,
+                                                 const uint32_t *__restrict__ nin_a,
+                                                 const uint32_t *__restrict__ nnear_a, uint32_t npiv, uint16_t *Y) {
+    const uint32_t I = blockIdx.x / 2, r0 = I * kTrsmBlock;
+    const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
+    trsm_solve_tile<W>(md, gptr, pos, val, nin_a, nnear_a, r0, r1, Y, kTrsmBlock, kTrsmBlock, nullptr, nullptr, 0,
+                       blockIdx.x % 2);
+}
+
+// Th/Tl = limbs of (I - Y) (zero rows past npiv).
+__global__ __launch_bounds__(256) void k_trsm_inv_planes(uint32_t p, uint32_t npiv, uint32_t rows,
+                                                         const uint16_t *__restrict__ Y, int8_t *Th, int8_t *Tl) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)rows * kTrsmBlock) return;
+    const uint32_t r = (uint32_t)(i / kTrsmBlock), c = (uint32_t)(i % kTrsmBlock);
+    int h = 0, l = 0;
+    if (r < npiv) {
+        const uint32_t y = Y[i], e = c == r % kTrsmBlock ? 1u : 0u;
+        fl_split_limbs(e >= y ? e - y : e + p - y, p, h, l);
+    }
+    Th[i] = (int8_t)h;
+    Tl[i] = (int8_t)l;
+}
+
+// Solve of block [r0, r1) for 64 columns per workgroup: R (the block's X
+// rows) is staged in LDS and transposed to int8 limbs there (the B operand,
+// 128 bytes of K per column); wave w computes rows [32 w, 32 w + 32) of
+// (I - T^-1) R with K = 128; X = R - that, written back with the transposed
+// limb planes of the finished rows (for the updates of the blocks above).
+struct __attribute__((aligned(16))) ApplyLds {
+    uint16_t R[kTrsmBlock][64];
+    int8_t Bh[64][kTrsmBlock];
+    int8_t Bl[64][kTrsmBlock];
+};
+
+__global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                    const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
+                                                    uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
+                                                    int8_t *Xh, int8_t *Xl, uint64_t kp) {
+    using fl_mfma::v4i;
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
+    typedef __attribute__((address_space(1))) const v4i gv4i;
+    __shared__ ApplyLds S;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nrow = r1 - r0, c0 = blockIdx.x * 64;
+    // R: 128 rows x 16 chunks of 4 columns, 8 chunks per thread (rows past the
+    // block or columns past nB read as zero)
+    uint64_t rv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 4, c4 = (ch & 15) * 4;
+        const bool ok = r < nrow && c0 + c4 + 4 <= nB;
+        rv[u] = *(gu64 *)(ok ? X + (uint64_t)(r0 + r) * ldx + c0 + c4 : X);
+        if (!ok) {
+            rv[u] = 0;
+            if (r < nrow)
+                for (uint32_t k = 0; k < 4 && c0 + c4 + k < nB; k++)
+                    rv[u] |= (uint64_t)X[(uint64_t)(r0 + r) * ldx + c0 + c4 + k] << (16 * k);
+        }
+    }
+    // A fragments: rows 32 w + 16 rt + (lane & 15), K bytes 64 s + 16 (lane >> 4)
+    const uint32_t cl = lane & 15, kq = (lane >> 4) * 16, rq = (lane >> 4) * 4;
+    v4i ah[2][2], al[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const uint64_t o = (uint64_t)(r0 + wave * 32 + rt * 16 + cl) * kTrsmBlock + s * 64 + kq;
+            ah[rt][s] = *(gv4i *)(Th + o);
+            al[rt][s] = *(gv4i *)(Tl + o);
+        }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 4, c4 = (ch & 15) * 4;
+        *(uint64_t *)&S.R[r][c4] = rv[u];
+    }
+    __syncthreads();
+    // transpose to limbs: thread -> (column, 16-row group), two per thread
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const uint32_t task = tid + u * 256, c = task & 63, g = task >> 6;
+        uint32_t hw[4] = {0, 0, 0, 0}, lw[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            int h, l;
+            fl_split_limbs(S.R[g * 16 + k][c], md.p, h, l);
+            hw[k >> 2] |= (uint32_t)(h & 0xff) << (8 * (k & 3));
+            lw[k >> 2] |= (uint32_t)(l & 0xff) << (8 * (k & 3));
+        }
+        *(uint4 *)&S.Bh[c][g * 16] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        *(uint4 *)&S.Bl[c][g * 16] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+    __syncthreads();
+    // per 16-column group j: K = 128 in two steps, then X = R - (I - T^-1) R
+    // in place in LDS (each output is read and written by its own lane only)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        v4i acc_hh[2], acc_mid[2], acc_ll[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++) acc_hh[rt] = acc_mid[rt] = acc_ll[rt] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const v4i bh = *(const v4i *)&S.Bh[j * 16 + cl][s * 64 + kq];
+            const v4i bl = *(const v4i *)&S.Bl[j * 16 + cl][s * 64 + kq];
+#pragma unroll
+            for (int rt = 0; rt < 2; rt++) {
+                acc_hh[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[rt][s], bh, acc_hh[rt], 0, 0, 0);
+                acc_mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[rt][s], bl, acc_mid[rt], 0, 0, 0);
+                acc_mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[rt][s], bh, acc_mid[rt], 0, 0, 0);
+                acc_ll[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[rt][s], bl, acc_ll[rt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t rhh = fl_mfma::signed_to_res(acc_hh[rt][e], md, bias);
+                const uint32_t rmid = fl_mfma::signed_to_res(acc_mid[rt][e], md, bias);
+                const uint32_t rll = fl_mfma::signed_to_res(acc_ll[rt][e], md, bias);
+                uint32_t v = fl::reduce32(rhh * c16 + rll, md);
+                v = fl::reduce32(v + rmid * 256u, md);
+                uint16_t &o = S.R[wave * 32 + rt * 16 + rq + e][j * 16 + cl];
+                o = (uint16_t)fl::submod(o, v, md.p);
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t ch = tid + u * 256, r = ch >> 4, c4 = (ch & 15) * 4;
+        if (r >= nrow || c0 + c4 >= nB) continue;
+        uint16_t *o = X + (uint64_t)(r0 + r) * ldx + c0 + c4;
+        if (c0 + c4 + 4 <= nB) *(uint64_t *)o = *(const uint64_t *)&S.R[r][c4];
+        else
+            for (uint32_t k = 0; c0 + c4 + k < nB; k++) o[k] = S.R[r][c4 + k];
+    }
+    // transposed limb planes of the finished rows: column c, rows r0 + 16 g ..
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const uint32_t task = tid + u * 256, c = task & 63, g = task >> 6;
+        if (c0 + c >= nB || g * 16 >= nrow) continue;
+        uint32_t hw[4] = {0, 0, 0, 0}, lw[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            int h = 0, l = 0;
+            if (g * 16 + k < nrow) fl_split_limbs(S.R[g * 16 + k][c], md.p, h, l);
+            hw[k >> 2] |= (uint32_t)(h & 0xff) << (8 * (k & 3));
+            lw[k >> 2] |= (uint32_t)(l & 0xff) << (8 * (k & 3));
+        }
+        int8_t *dh = Xh + (uint64_t)(c0 + c) * kp + r0 + g * 16, *dl = Xl + (uint64_t)(c0 + c) * kp + r0 + g * 16;
+        if (g * 16 + 16 <= nrow) {
+            *(uint4 *)dh = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            *(uint4 *)dl = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        } else {
+            for (uint32_t k = 0; g * 16 + k < nrow; k++) {
+                dh[k] = (int8_t)((hw[k >> 2] >> (8 * (k & 3))) & 0xff);
+                dl[k] = (int8_t)((lw[k >> 2] >> (8 * (k & 3))) & 0xff);
+            }
+        }
+    }
+}
+
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
 
 // kext[I] = (last A column used by block I's rows) + 1 - r1, or 0.
@@ -723,6 +904,8 @@ hipError_t trsm_solve(uint32_t w, const fl::Mod &md, const uint64_t *gptr, const
 
 struct TrsmWs {
     int8_t *Ah, *Al, *Xh, *Xl;
+    uint16_t *Y;        // [nblk * 128 x 128] inverses of the diagonal blocks
+    int8_t *Th, *Tl;    // [nblk * 128 x 128] limb planes of I - (block inverse)
     uint32_t *kext, *krange;
     uint32_t *nin, *nnear;
     uint64_t kp;
@@ -747,6 +930,9 @@ size_t trsm_layout(const fl_split_info *info, fl_mode mode, void *ws, TrsmWs *t)
         r.Xl = c.take<int8_t>(np * r.kp);
         r.kext = c.take<uint32_t>((info->npiv + kTrsmBlock - 1) / kTrsmBlock);
         r.krange = c.take<uint32_t>(2 * (size_t)((info->npiv + kTrsmBlock - 1) / kTrsmBlock));
+        r.Y = c.take<uint16_t>(mp * kTrsmBlock);
+        r.Th = c.take<int8_t>(mp * kTrsmBlock);
+        r.Tl = c.take<int8_t>(mp * kTrsmBlock);
     }
     if (t) *t = r;
     return c.off;
@@ -847,6 +1033,21 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
                                (const uint32_t *)s->a_pos, (const uint16_t *)s->a_val, tw.Ah, tw.Al, tw.kp);
         });
         FL_LAUNCH_CHECK("trsm tiles");
+        const uint32_t rows = nblk * kTrsmBlock;
+        const unsigned ge = (unsigned)(((uint64_t)rows * kTrsmBlock + 255) / 256);
+        const fl::Mod md = fl::make_mod(info->p);
+        FL_PROF("trsm.inverse", stream, {
+            hipLaunchKernelGGL(k_trsm_eye, dim3(ge), dim3(256), 0, stream, npiv, rows, tw.Y);
+            switch (w) {
+            case 1: hipLaunchKernelGGL(k_trsm_inv<1>, dim3(2 * nblk), dim3(64), 0, stream, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, npiv, tw.Y); break;
+            case 2: hipLaunchKernelGGL(k_trsm_inv<2>, dim3(2 * nblk), dim3(64), 0, stream, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, npiv, tw.Y); break;
+            case 4: hipLaunchKernelGGL(k_trsm_inv<4>, dim3(2 * nblk), dim3(64), 0, stream, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, npiv, tw.Y); break;
+            default: hipLaunchKernelGGL(k_trsm_inv<8>, dim3(2 * nblk), dim3(64), 0, stream, md, s->a_gptr, s->a_pos, s->a_val, tw.nin, tw.nnear, npiv, tw.Y); break;
+            }
+            hipLaunchKernelGGL(k_trsm_inv_planes, dim3(ge), dim3(256), 0, stream, info->p, npiv, rows,
+                               (const uint16_t *)tw.Y, tw.Th, tw.Tl);
+        });
+        FL_LAUNCH_CHECK("trsm inverse");
     }
     t.nblk = nblk;
     t.nin = tw.nin;
@@ -857,6 +1058,8 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
     t.Xl = tw.Xl;
     t.kext = tw.kext;
     t.krange = tw.krange;
+    t.Th = tw.Th;
+    t.Tl = tw.Tl;
     t.kp = tw.kp;
     *task = t;
     return FL_OK;
@@ -927,9 +1130,18 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
             FL_HIP(e);
         }
         hipError_t e;
-        FL_PROF("trsm.solve", stream,
-                e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, t.nin, t.nnear, r0, r1, X, ldx, nB,
-                               stream, t.mfma ? t.Xh : nullptr, t.mfma ? t.Xl : nullptr, t.kp));
+        if (t.mfma) {
+            FL_PROF("trsm.apply", stream,
+                    hipLaunchKernelGGL(k_trsm_apply, dim3((nB + 63) / 64), dim3(256), 0, stream, md,
+                                       fl_mfma::gemm_bias(info->p), fl_mfma::gemm_c16(info->p),
+                                       (const int8_t *)t.Th, (const int8_t *)t.Tl, r0, r1, X, ldx, nB, t.Xh, t.Xl,
+                                       t.kp));
+            e = hipGetLastError();
+        } else {
+            FL_PROF("trsm.solve", stream,
+                    e = trsm_solve(w, md, s->a_gptr, s->a_pos, s->a_val, t.nin, t.nnear, r0, r1, X, ldx, nB, stream,
+                                   nullptr, nullptr, t.kp));
+        }
         FL_HIP(e);
     }
     return FL_OK;
