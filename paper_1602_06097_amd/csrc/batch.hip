@@ -159,7 +159,7 @@ struct fl_batch {
     std::vector<MatrixRun> mats;
     uint64_t summary_off = 0, run_bytes = 0;
     // device tables of the stepped loops (TRSM blocks, echelon panels)
-    uint64_t off_ttask = 0, off_tids = 0, off_tpre = 0;  // 3 lists each: all, mfma, plain
+    uint64_t off_ttask = 0, off_tids = 0, off_tpre = 0;  // 4 lists each (solves and updates by form)
     uint64_t off_etask = 0, off_eids = 0, off_epre_rows = 0, off_epre = 0;
     uint32_t max_blk = 0, max_panels = 0;
     hipStream_t streams[kMaxStreams] = {};
@@ -227,8 +227,8 @@ void batch_layout(fl_batch *b) {
     const uint64_t n = b->count;
     b->summary_off = take(32 * n);
     b->off_ttask = take(sizeof(FlTrsmTask) * n);
-    b->off_tids = take(4 * 3 * n);
-    b->off_tpre = take(4 * 3 * (n + 1));
+    b->off_tids = take(4 * 4 * n);
+    b->off_tpre = take(4 * 4 * (n + 1));
     b->off_etask = take(sizeof(FlEchTask) * n);
     b->off_eids = take(4 * 3 * n);
     b->off_epre_rows = take(4 * (n + 1));
@@ -320,26 +320,29 @@ fl_status run_trsm(fl_batch *b, void *arena, hipStream_t stream) {
     FL_CHECK_ST(join(b, stream));
     if (b->max_blk == 0) return FL_OK;
     auto nblk = [](const MatrixRun &m) { return m.nblk; };
-    const std::vector<uint32_t> ids[3] = {sorted_ids(b, nblk, -1), sorted_ids(b, nblk, FL_MFMA_I8),
-                                          sorted_ids(b, nblk, FL_PLAIN)};
-    const std::vector<uint32_t> pre[3] = {
+    // lists: 0 = MFMA-form solve (product with the block inverse), 1 = MFMA
+    // update, 2 = VALU update, 3 = VALU-form solve (back substitution)
+    const std::vector<uint32_t> ids[4] = {sorted_ids(b, nblk, FL_MFMA_I8), sorted_ids(b, nblk, FL_MFMA_I8),
+                                          sorted_ids(b, nblk, FL_PLAIN), sorted_ids(b, nblk, FL_PLAIN)};
+    const std::vector<uint32_t> pre[4] = {
         prefix_of(b, ids[0], [](const MatrixRun &m) { return (m.info.nB + 63) / 64; }),
         prefix_of(b, ids[1], [](const MatrixRun &m) { return (m.info.nB + 127) / 128 * kFlTrsmSuper; }),
-        prefix_of(b, ids[2], [&](const MatrixRun &m) { return (m.info.nB + 255) / 256 * (kFlTrsmBlock / w / 4); })};
+        prefix_of(b, ids[2], [&](const MatrixRun &m) { return (m.info.nB + 255) / 256 * (kFlTrsmBlock / w / 4); }),
+        prefix_of(b, ids[3], [](const MatrixRun &m) { return (m.info.nB + 63) / 64; })};
     FlTrsmTask *d_tasks = at<FlTrsmTask>(arena, b->off_ttask);
     FL_HIP(fl_upload(d_tasks, tasks.data(), sizeof(FlTrsmTask) * n, stream));
-    uint32_t *d_ids[3], *d_pre[3];
-    for (int k = 0; k < 3; k++) {
+    uint32_t *d_ids[4], *d_pre[4];
+    for (int k = 0; k < 4; k++) {
         d_ids[k] = at<uint32_t>(arena, b->off_tids) + (size_t)k * n;
         d_pre[k] = at<uint32_t>(arena, b->off_tpre) + (size_t)k * (n + 1);
         FL_CHECK_ST(upload_ids(d_ids[k], ids[k], stream));
         FL_CHECK_ST(upload_ids(d_pre[k], pre[k], stream));
     }
-    const int kind_of[3] = {2, 1, 0};  // solve over all, MFMA update, VALU update
-    std::vector<uint32_t> active(3);
-    for (int k = 0; k < 3; k++) active[k] = (uint32_t)ids[k].size();
+    const int kind_of[4] = {3, 1, 0, 2};
+    std::vector<uint32_t> active(4);
+    for (int k = 0; k < 4; k++) active[k] = (uint32_t)ids[k].size();
     for (uint32_t step = 0; step < b->max_blk; step++) {
-        for (int k : {1, 2, 0}) {  // updates of the step, then its solves
+        for (int k : {1, 2, 0, 3}) {  // updates of the step, then its solves
             while (active[k] && b->mats[ids[k][active[k] - 1]].nblk <= step) active[k]--;
             if (!active[k]) continue;
             FL_HIP(fl_trsm_batch_launch(kind_of[k], b->p, w, d_tasks, d_ids[k], d_pre[k], active[k],

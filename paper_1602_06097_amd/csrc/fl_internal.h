@@ -239,9 +239,11 @@ constexpr uint32_t kFlTrsmSuper = 4;  // blocks per superblock of the MFMA-form 
 fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
                           fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream, FlTrsmTask *task);
 // Step `step` (block nblk - 1 - step of each listed matrix): the far update
-// (kind 0: VALU, 1: int8 MFMA; no-op at step 0) or the block solve (kind 2),
+// (kind 0: VALU, 1: int8 MFMA; no-op at step 0), the block solve (kind 2: by
+// back substitution) or the MFMA-form block solve (kind 3: product with the
+// block inverse),
 // over tasks[ids[0..n)] with workgroup prefix `prefix` and `grid` workgroups.
-// Workgroups per matrix: solve ceil(nB / 64); VALU update
+// Workgroups per matrix: solve and MFMA-form solve ceil(nB / 64); VALU update
 // ceil(nB / 256) * (128 / w / 4); MFMA update ceil(nB / 128) * kFlTrsmSuper.
 hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
                                 const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,

@@ -663,16 +663,15 @@ struct __attribute__((aligned(16))) ApplyLds {
     int8_t Bl[64][kTrsmBlock];
 };
 
-__global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, uint32_t c16,
-                                                    const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
-                                                    uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
-                                                    int8_t *Xh, int8_t *Xl, uint64_t kp) {
+__device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
+                                                uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
+                                                int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t bx, ApplyLds &S) {
     using fl_mfma::v4i;
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) const v4i gv4i;
-    __shared__ ApplyLds S;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t nrow = r1 - r0, c0 = blockIdx.x * 64;
+    const uint32_t nrow = r1 - r0, c0 = bx * 64;
     // R: 128 rows x 16 chunks of 4 columns, 8 chunks per thread (rows past the
     // block or columns past nB read as zero)
     uint64_t rv[8];
@@ -787,6 +786,28 @@ __global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, u
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                    const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
+                                                    uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
+                                                    int8_t *Xh, int8_t *Xl, uint64_t kp) {
+    __shared__ ApplyLds S;
+    trsm_apply_tile(md, bias, c16, Th, Tl, r0, r1, X, ldx, nB, Xh, Xl, kp, blockIdx.x, S);
+}
+
+// The same for many matrices: the step's block of every MFMA-form matrix,
+// 64-column tiles from the prefix.
+__global__ __launch_bounds__(256) void k_trsm_apply_b(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                      const FlTrsmTask *__restrict__ tasks,
+                                                      const uint32_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ prefix, uint32_t n, uint32_t step) {
+    __shared__ ApplyLds S;
+    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
+    const FlTrsmTask &t = tasks[ids[i]];
+    uint32_t I, r0, r1;
+    if (!step_block(t, step, I, r0, r1)) return;
+    trsm_apply_tile(md, bias, c16, t.Th, t.Tl, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp, blockIdx.x - prefix[i], S);
 }
 
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
@@ -1070,7 +1091,10 @@ hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTa
                                 uint32_t step, hipStream_t stream) {
     if (n == 0 || grid == 0) return hipSuccess;
     const fl::Mod md = fl::make_mod(p);
-    if (kind == 2) {
+    if (kind == 3) {
+        hipLaunchKernelGGL(k_trsm_apply_b, dim3(grid), dim3(256), 0, stream, md, fl_mfma::gemm_bias(p),
+                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step);
+    } else if (kind == 2) {
         switch (w) {
         case 1: hipLaunchKernelGGL(k_trsm_solve_b<1>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
         case 2: hipLaunchKernelGGL(k_trsm_solve_b<2>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
