@@ -472,16 +472,18 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
 // U[t][c] = sum_s G[t][s] Dt[Qs[s]][c] for c in [c0, cols), t < k; with
 // limb planes, also U transposed as int8 limbs: Uh/Ul[(c - c0) * 64 + t]
 // (zero for t >= k), the B operand of the matrix-core rank-k update.
-// 256 columns per workgroup, one per thread: the column's k entries of the
-// selected rows are held in registers (fetched with independent loads), G is
-// read from LDS 8 entries at a time.  G[t][s] = 0 for s >= k, so the sums run
-// over whole groups of 8.
+// 64 columns per workgroup, lane = column: every wave holds the column's k
+// entries of the selected rows in registers (independent loads) and computes
+// the rows t = wave, wave + 4, ... (G read from LDS 8 entries at a time;
+// G[t][s] = 0 for s >= k, so the sums run over whole groups of 8); the limb
+// planes are assembled in LDS.
 struct __attribute__((aligned(16))) ULds {
     uint16_t Gs[64 * 64];
+    uint16_t Us[64][64];
     uint32_t qs[128];  // U: selected rows; L: pivot columns and rows
 };
 
-// One workgroup (256 columns from c0 + lo + 256 bx, below c0 + hi) of U for
+// One workgroup (64 columns from c0 + lo + 64 bx, below c0 + hi) of U for
 // panel P.
 __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint32_t P, ULds &S, uint32_t lo,
                        uint32_t hi) {
@@ -490,12 +492,16 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
     const PanelState *ps = panel_state(tk, P);
     const uint32_t c0 = P * kPanel;
     const uint32_t cols = hi < tk.cols - c0 ? c0 + hi : tk.cols;
+    const uint32_t cbase = c0 + lo + bx * 64;
+    if (cbase >= cols) return;
     const uint16_t *D = tk.D;
     const uint64_t ld = tk.ld, ldu = tk.ldu;
     uint16_t *U = tk.U;
     int8_t *Uh = tk.Uh, *Ul = tk.Ul;
     const uint32_t k = ps->k;
     if (k == 0) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     {
         const uint4 *g4 = (const uint4 *)ps->G;
         uint4 *s4 = (uint4 *)Gs;
@@ -505,10 +511,9 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
     }
     if (threadIdx.x < 64) qs[threadIdx.x] = ps->Qs[threadIdx.x];
     __syncthreads();
-    const uint32_t c = c0 + lo + bx * 256 + threadIdx.x;
+    const uint32_t c = cbase + lane;
     const bool ok = c < cols;
-    if (__ballot(ok) == 0) return;  // whole wave past the end (no barrier follows)
-    const uint32_t cc = ok ? c : c0 + lo;  // a valid column for idle lanes
+    const uint32_t cc = ok ? c : cbase;  // a valid column for idle lanes
     uint32_t x[64];
 #pragma unroll
     for (int s16 = 0; s16 < 4; s16++) {
@@ -523,46 +528,43 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
             for (int j = 0; j < 16; j++) x[s16 * 16 + j] = 0;
         }
     }
-    uint32_t hw[16], lw[16];
+    for (uint32_t t = wave; t < 64; t += 4) {
+        uint32_t u = 0;
+        if (t < k) {
+            uint32_t h = 0, l = 0;
+            const uint4 *gr = (const uint4 *)(Gs + t * 64);
 #pragma unroll
-    for (int i = 0; i < 16; i++) hw[i] = lw[i] = 0;
-    for (uint32_t t = 0; t < k; t++) {
-        uint32_t h = 0, l = 0;
-        const uint4 *gr = (const uint4 *)(Gs + t * 64);
+            for (int s8 = 0; s8 < 8; s8++) {
+                if ((uint32_t)s8 * 8 < k) {
+                    const uint4 gv = gr[s8];
+                    const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
 #pragma unroll
-        for (int s8 = 0; s8 < 8; s8++) {
-            if ((uint32_t)s8 * 8 < k) {
-                const uint4 gv = gr[s8];
-                const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const uint32_t gts = (gw[j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                    h = fl::mad24(gts >> 8, x[s8 * 8 + j], h);
-                    l = fl::mad24(gts & 0xffu, x[s8 * 8 + j], l);
+                    for (int j = 0; j < 8; j++) {
+                        const uint32_t gts = (gw[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                        h = fl::mad24(gts >> 8, x[s8 * 8 + j], h);
+                        l = fl::mad24(gts & 0xffu, x[s8 * 8 + j], l);
+                    }
                 }
             }
+            u = fl::fold_pair(h, l, md);
+            if (ok) U[(uint64_t)t * ldu + c] = (uint16_t)u;
         }
-        const uint32_t u = fl::fold_pair(h, l, md);
-        if (ok) U[(uint64_t)t * ldu + c] = (uint16_t)u;
-        if (Uh) {
-            int lh, ll;
-            fl_split_limbs(u, md.p, lh, ll);
-#pragma unroll
-            for (int i = 0; i < 16; i++)
-                if ((uint32_t)i == (t >> 2)) {
-                    hw[i] |= (uint32_t)(lh & 0xff) << (8 * (t & 3));
-                    lw[i] |= (uint32_t)(ll & 0xff) << (8 * (t & 3));
-                }
-        }
+        S.Us[t][lane] = (uint16_t)u;
     }
-    if (Uh && ok) {
-        uint4 *dh = (uint4 *)(Uh + (uint64_t)(c - c0) * 64), *dl = (uint4 *)(Ul + (uint64_t)(c - c0) * 64);
+    if (!Uh) return;
+    __syncthreads();
+    if (!ok) return;
+    // wave w: bytes [16 w, 16 w + 16) of the column's 64
+    uint32_t hw[4] = {0, 0, 0, 0}, lw[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            dh[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
-            dl[i] = make_uint4(lw[4 * i], lw[4 * i + 1], lw[4 * i + 2], lw[4 * i + 3]);
-        }
+    for (int i = 0; i < 16; i++) {
+        int lh, ll;
+        fl_split_limbs(S.Us[wave * 16 + i][lane], md.p, lh, ll);
+        hw[i >> 2] |= (uint32_t)(lh & 0xff) << (8 * (i & 3));
+        lw[i >> 2] |= (uint32_t)(ll & 0xff) << (8 * (i & 3));
     }
+    *(uint4 *)(Uh + (uint64_t)(c - c0) * 64 + wave * 16) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *(uint4 *)(Ul + (uint64_t)(c - c0) * 64 + wave * 16) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
 }
 
 // L'[i][t] = Dt[i][Ccol[t]] - [i = Phys[t]] (0 for t >= k): the multipliers
@@ -628,19 +630,19 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
 }
 
 // Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
-// over the rest of the panel's block (one workgroup per matrix), the others
-// gather L' (rows).
+// over the rest of the panel's block (four workgroups of 64 columns per
+// matrix), the others gather L' (rows).
 __global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                 const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
                                                 uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
                                                 uint32_t n_active, uint32_t P) {
     __shared__ ULds S;
     if (blockIdx.x < grid_u) {
-        const uint32_t ti = fl_task_of(pre_c, n_c, blockIdx.x);
+        const uint32_t ti = fl_task_of(pre_c, n_c, blockIdx.x / kBlockPanels);
         const FlEchTask &t = tasks[ids[ti]];
         if (P >= t.npanels) return;
         const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
-        U_tile(md, t, blockIdx.x - pre_c[ti], P, S, 0, bend - c0);
+        U_tile(md, t, blockIdx.x % kBlockPanels, P, S, 0, bend - c0);
     } else {
         const uint32_t b = blockIdx.x - grid_u;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
@@ -1128,8 +1130,9 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // U over the rest of the block and L'; the panel's update of its block
     FL_PROF("echelon.UL", stream,
-            hipLaunchKernelGGL(k_ech_UL, dim3(g.n_active + g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               at(L.pre_n_all, P, L.n_all), L.n_all, g.n_active, L.pre_rows, g.n_active, P));
+            hipLaunchKernelGGL(k_ech_UL, dim3(kBlockPanels * g.n_active + g.grid_rows), dim3(256), 0, stream, md,
+                               tasks, L.ids_all, at(L.pre_n_all, P, L.n_all), L.n_all, kBlockPanels * g.n_active,
+                               L.pre_rows, g.n_active, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g.n_mfma) {
         FL_PROF("echelon.mfma", stream,
