@@ -3,31 +3,33 @@
 // blocked Gauss-Jordan elimination over 64-column panels.
 //
 // For a panel [c0, c0+64):
-//  0. k_ech_check   lists the remaining rows that are nonzero on the panel.
-//  1. k_ech_probe   one block: a greedy basis of (up to 64 of) those rows
-//     restricted to the panel, in reduced form in LDS.  Every wave reduces one
-//     row against the basis (multipliers broadcast with v_readlane); rows
-//     that stay nonzero are inserted one wave at a time.  The coefficients G
-//     with  G * Dt[Q, panel] = basis  are tracked (Q = selected rows).
-//     This is the paper's parallel structured Gaussian elimination (Sec. 5.1:
-//     rows reduced in parallel against the known pivots, a new pivot added by
-//     one worker at a time) applied to a panel.
+//  0. k_ech_check   lists the remaining rows that are nonzero on the panel,
+//     with the first nonzero column of each.
+//  1. k_ech_probe   one block: a greedy basis of one listed row per panel
+//     column that is some row's first nonzero (independent rows),
+//     in reduced form in LDS.  Rows are reduced against the basis in
+//     parallel (multipliers broadcast with v_readlane); a row that stays
+//     nonzero is inserted (normalised), and all waves clear its pivot column
+//     from the older basis rows.  The coefficients G with
+//     G * Dt[Q, panel] = basis are tracked (Q = selected rows).  This is the
+//     paper's parallel structured Gaussian elimination (Sec. 5.1: rows reduced
+//     in parallel against the known pivots, a new pivot added by one worker
+//     at a time) applied to a panel.
 //  2. k_ech_check   every listed row is reduced against that basis in
 //     parallel; rows outside its span are listed again.
 //  3. k_ech_merge   only if a row was listed: the greedy pass continues over
-//     those rows.  The result: pivot columns C (ascending) of the
-//     panel, rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
-//  4. U = G * Dt[Q, c0:]   (unit vectors at C)
-//  5. L = Dt[:, C]          (multipliers, saved before the update
-//                            overwrites them; 4 and 5 are one launch)
-//  6. rank-k update        Dt[:, c0:] -= L U    (every row: Gauss-Jordan
-//     (VALU or int8 MFMA)                       clears C above and below)
-//  7. Dt[Q_t, c0:] = U_t   (one launch with step 0 of the next panel)
-// Steps 4, 6 and 7 are split at column c0 + 128.  The near part (this panel
-// and the next) is all the next panel's search reads; the far part runs on a
-// second stream while that search runs, and the next panel's step 4 waits
-// for it (it reads and overwrites U, L and the columns the far part writes).
-// Panel states alternate between two slots for the same reason.
+//     those rows.  The result: pivot columns C (ascending) of the panel,
+//     rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
+//  4. U = G * Dt[Q, c0:bend)     over the rest of the panel's 256-column block
+//  5. L' = Dt[:, C] - [row = Q_t] (multipliers with the placement of U folded
+//                                  in; 4 and 5 are one launch)
+//  6. Dt[:, c0:bend) -= L' U      (every row with a nonzero multiplier:
+//     (VALU or int8 MFMA)          Gauss-Jordan clears C above and below, and
+//                                  pivot row Q_t becomes U_t)
+// The columns right of the block are updated once per block of four panels
+// (K = 256): U of the block for them by a recurrence over its panels, then
+// the next block's columns (critical path) and the far part (second stream,
+// overlapping the next block's panels).
 // After the last panel the pivot rows are gathered to rows 0..r-1 in pivot
 // order and the other rows (now zero) are cleared.
 #include <algorithm>
@@ -52,7 +54,6 @@ constexpr uint32_t kPanel = 64;
 constexpr uint32_t kBlockPanels = 4;                  // panels per block of the delayed update
 constexpr uint32_t kBlock = kPanel * kBlockPanels;   // 256 columns, K of the block update
 constexpr uint32_t kSlots = 2 * kBlockPanels;        // panel states kept (two blocks)
-constexpr uint32_t kProbe = 64;  // rows in the probe basis pass (at least)
 constexpr uint32_t kListCap = 2048;  // LDS row list: room for two 1024-row windows
 constexpr int kGreedyThreads = 1024;
 
@@ -87,6 +88,7 @@ struct EchWs {
     uint32_t *blk_rows; // [2][rows] rows with a nonzero multiplier in a block
     uint32_t *blk_cnt;  // [nblocks] their counts
     uint32_t *mark;     // [rows] last block (+1) that listed the row
+    uint32_t *nzlead;   // [rows] first nonzero column (on the panel) of each listed row
     uint32_t *nzlist;   // [rows] remaining rows nonzero on the panel
     uint32_t *flist;    // [rows] rows outside the probe basis' span
     uint32_t *counts;   // [3 * npanels] per panel: nonzero, flagged, update rows
@@ -173,9 +175,11 @@ __device__ void block_append(bool flag, uint32_t row, uint32_t *list, uint32_t *
 }
 
 // Append up to 8 rows per wave to a global list with one global atomic per
-// block: bit u of the wave-uniform mask8 lists the row held by lane u.  All
-// threads of the (256-thread) block must call it.
-__device__ void block_append8(uint32_t mask8, uint32_t row, uint32_t *list, uint32_t *count) {
+// block: bit u of the wave-uniform mask8 lists the row held by lane u (and,
+// with list2, lane u's val2 at the same position).  All threads of the
+// (256-thread) block must call it.
+__device__ void block_append8(uint32_t mask8, uint32_t row, uint32_t *list, uint32_t *count,
+                              uint32_t *list2 = nullptr, uint32_t val2 = 0) {
     __shared__ uint32_t s_w[4], s_base;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) s_w[wave] = __popc(mask8);
@@ -187,7 +191,11 @@ __device__ void block_append8(uint32_t mask8, uint32_t row, uint32_t *list, uint
     __syncthreads();
     uint32_t off = s_base;
     for (uint32_t w = 0; w < wave; w++) off += s_w[w];
-    if (lane < 8 && ((mask8 >> lane) & 1u)) list[off + __popc(mask8 & ((1u << lane) - 1u))] = row;
+    if (lane < 8 && ((mask8 >> lane) & 1u)) {
+        const uint32_t at = off + __popc(mask8 & ((1u << lane) - 1u));
+        list[at] = row;
+        if (list2) list2[at] = val2;
+    }
 }
 
 // Greedy basis of the panel rows in LDS: reduced form over the panel
@@ -218,6 +226,10 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t cnt = S.cnt;
+    if (cnt == 0) {  // nothing listed (S.list holds no row to prefetch)
+        __syncthreads();
+        return;
+    }
     const uint32_t col = c0 + (lane < pw ? lane : 0);
     // the next batch's row is fetched while the current batch is processed
     uint32_t row_n = wave < cnt ? S.list[wave] : S.list[0];
@@ -328,8 +340,8 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
     }
 }
 
-// Panel step 1: greedy basis of (at most kProbe of) the rows nonzero on the
-// panel, taken from the list built by step 0.  One workgroup per matrix.
+// Panel step 1: greedy basis of representatives of the rows nonzero on the
+// panel (listed by step 0).  One workgroup per matrix.
 __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                               const uint32_t *__restrict__ ids, uint32_t P) {
     __shared__ GreedyLds S;
@@ -339,15 +351,27 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
     const uint32_t n = t.counts[3 * P];
-    const uint32_t take = n < kProbe ? n : kProbe;
+    // the basis starts from one listed row per panel column that is some
+    // row's first nonzero (the first such row in the list): these rows are
+    // independent (their first nonzeros differ), and in the matrices of the
+    // method they span most of the panel; check and merge add what is missing
+    __shared__ uint32_t s_rep[kPanel];
+    if (threadIdx.x < kPanel) s_rep[threadIdx.x] = 0xffffffffu;
     if (threadIdx.x == 0) {
         S.kb = 0;
-        S.cnt = take;
         rank0_s = *t.d_rank;
         ps->nflag = 0;
         ps->rank0 = rank0_s;
     }
-    if (threadIdx.x < take) S.list[threadIdx.x] = t.nzlist[threadIdx.x];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicMin(&s_rep[t.nzlead[i]], i);
+    __syncthreads();
+    if (threadIdx.x < kPanel) {
+        const uint32_t at = s_rep[threadIdx.x];
+        const uint64_t have = __ballot(at != 0xffffffffu);
+        if (at != 0xffffffffu) S.list[__popcll(have & ((1ull << threadIdx.x) - 1))] = t.nzlist[at];
+        if (threadIdx.x == 0) S.cnt = (uint32_t)__popcll(have);
+    }
     __syncthreads();
     const uint32_t rank0 = rank0_s;
     greedy_rows(md, t.D, t.ld, c0, pw, S);
@@ -414,10 +438,15 @@ __device__ void check_tile(const fl::Mod &md, const FlEchTask &t, uint32_t bx, u
     }
     __syncthreads();
     if (kb && live) reduce_rows8(md, v, kb, L.Bv, L.Cc, lane);
-    uint32_t mask = 0;
+    uint32_t mask = 0, my_lead = 0;
 #pragma unroll
-    for (int u = 0; u < 8; u++) mask |= (__ballot(v[u] != 0) != 0) ? 1u << u : 0u;
-    block_append8(mask & live, my_row, out_list, out_count);
+    for (int u = 0; u < 8; u++) {
+        const uint64_t nz = __ballot(v[u] != 0);
+        mask |= nz != 0 ? 1u << u : 0u;
+        if (lane == (uint32_t)u) my_lead = nz ? (uint32_t)__ffsll((long long)nz) - 1 : 0;
+    }
+    // step 0 also records each listed row's first nonzero column
+    block_append8(mask & live, my_row, out_list, out_count, use_basis ? nullptr : t.nzlead, my_lead);
     if (use_basis && threadIdx.x == 0) __threadfence();
 }
 
@@ -820,11 +849,12 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 }
 
 // Block B's rank-256 update of columns [start, end) (start = 256 (B + 1) +
-// lo), int8 MFMA form: the rows listed for the block, one 64 x 128 tile per
-// workgroup.  Row blocks vary fastest (blockIdx.x), so that workgroups
-// dispatched together share their column tile of the block's U (64 KB of
-// limb planes) in L2 and stream the multiplier rows; column tiles (from the
-// prefix, `gcols` in all) are blockIdx.y, blockIdx.y + gridDim.y, ...
+// lo), int8 MFMA form: the rows listed for the block, 64 x 128 tiles.  A
+// workgroup owns one row block (blockIdx.x) and walks the column tiles
+// blockIdx.y, blockIdx.y + gridDim.y, ... (`gcols` in all, from the prefix),
+// keeping the row block's multiplier fragments in registers; the workgroups
+// of one blockIdx.y walk the same column tiles together, so each tile of the
+// block's U is fetched into L2 once for all row blocks.
 __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                              const FlEchTask *__restrict__ tasks,
                                                              const uint32_t *__restrict__ ids,
@@ -832,6 +862,8 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
                                                              uint32_t gcols, uint32_t B, uint32_t lo, uint32_t span) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
+    fl_mfma::RankkRows<kBlockPanels> R;
+    uint32_t cur = 0xffffffffu;  // task whose row block is loaded
     for (uint32_t cy = blockIdx.y; cy < gcols; cy += gridDim.y) {
         const uint32_t ti = fl_task_of(pre, ntask, cy);
         const FlEchTask &t = tasks[ids[ti]];
@@ -840,13 +872,17 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
         if (blockIdx.x * 64 >= M) continue;
         const uint32_t start = (B + 1) * kBlock + lo;
         const uint32_t end = span < t.cols - start ? start + span : t.cols;
-        const uint64_t lhalf = (uint64_t)(B & 1) * t.rows * kBlock;
+        if (ti != cur) {
+            const uint64_t lhalf = (uint64_t)(B & 1) * t.rows * kBlock;
+            __syncthreads();  // rows_s of the previous task is still read
+            fl_mfma::rankk_rows<kBlockPanels>(t.Lbh + lhalf, t.Lbl + lhalf, kBlock,
+                                              t.blk_rows + (uint64_t)(B & 1) * t.rows, M, blockIdx.x, rows_s, R);
+            cur = ti;
+        }
         const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
-        fl_mfma::mfma_rankk_tile<kBlockPanels>(md, bias, c16, t.Lbh + lhalf, t.Lbl + lhalf, kBlock, t.Ubh + uoff,
-                                               t.Ubl + uoff, kBlock, t.blk_rows + (uint64_t)(B & 1) * t.rows, M,
-                                               t.D + start, t.ld, end - start, cy - pre[ti], blockIdx.x, sv,
-                                               rows_s);
-        __syncthreads();  // sv and rows_s are reused by the next tile
+        fl_mfma::rankk_cols<kBlockPanels>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start, t.ld,
+                                          end - start, cy - pre[ti], sv, rows_s);
+        __syncthreads();  // sv is reused by the next tile
     }
 }
 
@@ -947,6 +983,7 @@ size_t ech_layout(uint32_t rows, uint32_t cols, fl_mode mode, void *ws, EchWs *e
     t.blk_rows = c.take<uint32_t>(2 * r1);
     t.blk_cnt = c.take<uint32_t>(nblocks ? nblocks : 1);
     t.mark = c.take<uint32_t>(r1);
+    t.nzlead = c.take<uint32_t>(r1);
     t.task = c.take<FlEchTask>(1);
     t.ids = c.take<uint32_t>(1);
     t.pre_rows = c.take<uint32_t>(2);
@@ -1016,6 +1053,7 @@ fl_status fl_echelon_prepare(uint32_t p, uint32_t rows, uint32_t cols, uint16_t 
     t.blk_rows = e.blk_rows;
     t.blk_cnt = e.blk_cnt;
     t.mark = e.mark;
+    t.nzlead = e.nzlead;
     t.nzlist = e.nzlist;
     t.flist = e.flist;
     t.counts = e.counts;
@@ -1055,6 +1093,9 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
 // workgroups per launch, fills the chip and the search, one workgroup on the
 // critical path, waits for a free unit.
 constexpr uint32_t kFarLds = 64 * 1024;
+// column tiles walked by one workgroup of the block update: at most this
+// many workgroups per row block
+constexpr uint32_t kBlkColGroups = 16;
 
 template <class K>
 uint32_t far_dyn_lds(K kernel) {
@@ -1086,7 +1127,7 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g_mfma) {
         FL_PROF(far ? "echelon.blk_mfma_far" : "echelon.blk_mfma", s,
-                hipLaunchKernelGGL(k_ech_update_blk_mfma, dim3((mfma_rows + 63) / 64, std::min(g_mfma, 65535u)),
+                hipLaunchKernelGGL(k_ech_update_blk_mfma, dim3((mfma_rows + 63) / 64, std::min(g_mfma, kBlkColGroups)),
                                    dim3(256), far ? dyn_m : 0, s, md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p),
                                    tasks, L.ids_mfma, pm, L.n_mfma, g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -262,7 +262,7 @@ struct FlEchTask {
     int8_t *Uh, *Ul;        // int8-MFMA form only
     uint16_t *Lb, *Ub;      // block multipliers; block U (VALU form)
     int8_t *Lbh, *Lbl, *Ubh, *Ubl;  // their limb planes (int8-MFMA form only)
-    uint32_t *upd_rows, *blk_rows, *blk_cnt, *mark, *nzlist, *flist, *counts;
+    uint32_t *upd_rows, *blk_rows, *blk_cnt, *mark, *nzlist, *flist, *counts, *nzlead;
 };
 // Device tables for a panel loop over several matrices: ids sorted by panel
 // count (descending); workgroup prefixes for the column-tiled kernels (n + 1

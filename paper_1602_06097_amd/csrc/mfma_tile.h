@@ -231,15 +231,43 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 // One 64-row x 128-column tile (row block by, column block bx) of the
 // update.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in LDS.  Callers looping
 // over row blocks must synchronise between tiles.
+// The row block's part of a rank-k tile: its row list entries (rows_s, LDS)
+// and its A fragments, kept in registers for any number of column tiles.
+template <int KS> struct RankkRows {
+    v4i ah[KS], al[KS];
+};
+
 template <int KS>
-__device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
-                                                const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
-                                                uint32_t lda, const int8_t *__restrict__ Bh,
-                                                const int8_t *__restrict__ Bl, uint32_t ldb,
-                                                const uint32_t *__restrict__ row_map, uint32_t M, uint16_t *C,
-                                                uint64_t ldc, uint32_t N, uint32_t bx, uint32_t by, uint16_t *sv,
-                                                uint32_t *rows_s) {
+__device__ __forceinline__ void rankk_rows(const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
+                                           uint32_t lda, const uint32_t *__restrict__ row_map, uint32_t M,
+                                           uint32_t by, uint32_t *rows_s, RankkRows<KS> &R) {
     static_assert(KS >= 1 && KS <= 6, "K up to 384");
+    typedef __attribute__((address_space(1))) const v4i gv4i;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t m0 = by * 64;
+    if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
+    __syncthreads();
+    const uint32_t cl = lane & 15, kq = (lane >> 4) * 16;
+    const uint32_t arow = rows_s[wave * 16 + cl];
+    const uint32_t ar = arow != 0xffffffffu ? arow : rows_s[0];  // row m0 exists
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+        R.ah[s] = *(gv4i *)(Ah + (uint64_t)ar * lda + s * 64 + kq);
+        R.al[s] = *(gv4i *)(Al + (uint64_t)ar * lda + s * 64 + kq);
+    }
+    if (arow == 0xffffffffu) {
+#pragma unroll
+        for (int s = 0; s < KS; s++) R.ah[s] = R.al[s] = v4i{0, 0, 0, 0};
+    }
+}
+
+// One 128-column tile bx of the row block set up by rankk_rows.  Callers
+// looping over column tiles must synchronise between tiles (sv is reused).
+template <int KS>
+__device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16, const RankkRows<KS> &R,
+                                           const int8_t *__restrict__ Bh, const int8_t *__restrict__ Bl,
+                                           uint32_t ldb, uint16_t *C, uint64_t ldc, uint32_t N, uint32_t bx,
+                                           uint16_t *sv, const uint32_t *rows_s) {
     // every operand lives in device memory: global (not flat) accesses, so
     // that loads are counted apart from LDS traffic and can stay in flight
     typedef __attribute__((address_space(1))) const uint64_t gu64;
@@ -247,9 +275,7 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
     typedef __attribute__((address_space(1))) const v4i gv4i;
     constexpr int kLd = kRank64Ld;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t m0 = by * 64, n0 = bx * 128;
-    if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
-    __syncthreads();
+    const uint32_t n0 = bx * 128;
     // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread;
     // every load is issued (chunks outside the tile read C[0])
     uint64_t cv[8];
@@ -261,14 +287,6 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
         cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
     }
     const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
-    const uint32_t arow = rows_s[wave * 16 + cl];
-    const uint32_t ar = arow != 0xffffffffu ? arow : rows_s[0];  // row m0 exists
-    v4i ah[KS], al[KS];
-#pragma unroll
-    for (int s = 0; s < KS; s++) {
-        ah[s] = *(gv4i *)(Ah + (uint64_t)ar * lda + s * 64 + kq);
-        al[s] = *(gv4i *)(Al + (uint64_t)ar * lda + s * 64 + kq);
-    }
     // B fragments of column tile j + 1 are fetched while tile j is multiplied
     v4i bh[2][KS], bl[2][KS];
 #pragma unroll
@@ -276,10 +294,6 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
         const uint64_t b = (uint64_t)(n0 + cl) * ldb + s * 64 + kq;
         bh[0][s] = *(gv4i *)(Bh + b);
         bl[0][s] = *(gv4i *)(Bl + b);
-    }
-    if (arow == 0xffffffffu) {
-#pragma unroll
-        for (int s = 0; s < KS; s++) ah[s] = al[s] = v4i{0, 0, 0, 0};
     }
     const uint32_t bias2 = (uint32_t)(((1u << 30) + md.p - 1) / md.p * md.p);  // >= 2^30, multiple of p
 #pragma unroll
@@ -296,10 +310,10 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
         v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; s++) {
-            hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[s], bh[cur][s], hh, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[s], bl[cur][s], mid, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[s], bh[cur][s], mid, 0, 0, 0);
-            ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[s], bl[cur][s], ll, 0, 0, 0);
+            hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[s], bh[cur][s], hh, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[s], bl[cur][s], mid, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[s], bh[cur][s], mid, 0, 0, 0);
+            ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[s], bl[cur][s], ll, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -338,6 +352,20 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
                 o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(s4 >> (16 * c)) & 0xffffu, md.p);
         }
     }
+}
+
+
+template <int KS>
+__device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
+                                                uint32_t lda, const int8_t *__restrict__ Bh,
+                                                const int8_t *__restrict__ Bl, uint32_t ldb,
+                                                const uint32_t *__restrict__ row_map, uint32_t M, uint16_t *C,
+                                                uint64_t ldc, uint32_t N, uint32_t bx, uint32_t by, uint16_t *sv,
+                                                uint32_t *rows_s) {
+    RankkRows<KS> R;
+    rankk_rows<KS>(Ah, Al, lda, row_map, M, by, rows_s, R);
+    rankk_cols<KS>(md, bias, c16, R, Bh, Bl, ldb, C, ldc, N, bx, sv, rows_s);
 }
 
 // K <= 64 with 64-byte A rows and B columns.
