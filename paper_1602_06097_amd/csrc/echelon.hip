@@ -340,41 +340,105 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
     }
 }
 
-// Panel step 1: greedy basis of representatives of the rows nonzero on the
-// panel (listed by step 0).  One workgroup per matrix.
+// Panel step 1: the probe basis, from one representative row per leading
+// column of the rows nonzero on the panel (listed, with their first nonzero
+// column, by step 0).  One workgroup per matrix.
+//
+// Rows with different first nonzero columns are independent, so the
+// representatives need no elimination search: sorted by first nonzero column
+// (descending), their panel parts form a matrix whose restriction T to the
+// leading columns is lower triangular, and the reduced basis is T^-1 times
+// the rows (coefficients: T^-1 itself).  It is computed by back
+// substitution in groups of kProbeGroup slots: one wave finishes a group's
+// rows in order (each row reduced against the group's earlier, finished
+// rows), then all waves reduce the later slots against the finished group.
+// Reduction against finished rows never changes a later slot's leading
+// entry (finished rows are zero left of their own, larger, leading column),
+// so every pivot's inverse is known from the start.  In the matrices of
+// the method the representatives span most of the panel; check and merge
+// add what is missing.
+constexpr uint32_t kProbeGroup = 8;
+constexpr uint32_t kLeadLoads = 16;  // lead entries in flight per thread
+
 __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                               const uint32_t *__restrict__ ids, uint32_t P) {
+    typedef __attribute__((address_space(1))) const uint32_t gu32;
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
+    __shared__ uint32_t s_rep[kPanel];
     const FlEchTask &t = tasks[ids[blockIdx.x]];
     if (P >= t.npanels) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
     const uint32_t n = t.counts[3 * P];
-    // the basis starts from one listed row per panel column that is some
-    // row's first nonzero (the first such row in the list): these rows are
-    // independent (their first nonzeros differ), and in the matrices of the
-    // method they span most of the panel; check and merge add what is missing
-    __shared__ uint32_t s_rep[kPanel];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (threadIdx.x < kPanel) s_rep[threadIdx.x] = 0xffffffffu;
-    if (threadIdx.x == 0) {
-        S.kb = 0;
-        rank0_s = *t.d_rank;
-        ps->nflag = 0;
-        ps->rank0 = rank0_s;
+    __syncthreads();
+    // the first listed row of every leading column: a chunk of lead entries
+    // is loaded before any is used (the loads overlap)
+    const gu32 *lead = (const gu32 *)t.nzlead;
+    for (uint32_t base = 0; base < n; base += kLeadLoads * blockDim.x) {
+        uint32_t l[kLeadLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kLeadLoads; u++) {
+            const uint32_t i = base + u * blockDim.x + threadIdx.x;
+            l[u] = lead[i < n ? i : 0];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kLeadLoads; u++) {
+            const uint32_t i = base + u * blockDim.x + threadIdx.x;
+            if (i < n) atomicMin(&s_rep[l[u]], i);
+        }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicMin(&s_rep[t.nzlead[i]], i);
-    __syncthreads();
-    if (threadIdx.x < kPanel) {
-        const uint32_t at = s_rep[threadIdx.x];
+    // slots by leading column, descending (lane 0 takes column 63)
+    if (wave == 0) {
+        const uint32_t c = kPanel - 1 - lane;
+        const uint32_t at = s_rep[c];
         const uint64_t have = __ballot(at != 0xffffffffu);
-        if (at != 0xffffffffu) S.list[__popcll(have & ((1ull << threadIdx.x) - 1))] = t.nzlist[at];
-        if (threadIdx.x == 0) S.cnt = (uint32_t)__popcll(have);
+        if (at != 0xffffffffu) {
+            const uint32_t s = (uint32_t)__popcll(have & ((1ull << lane) - 1));
+            S.Cc[s] = c;
+            S.Qo[s] = t.nzlist[at];
+        }
+        if (lane == 0) {
+            S.kb = (uint32_t)__popcll(have);
+            rank0_s = *t.d_rank;
+            ps->nflag = 0;
+            ps->rank0 = rank0_s;
+        }
     }
     __syncthreads();
+    const uint32_t kr = S.kb;
+    // the representatives' panel parts (one wave per row) and unit coefficients
+    for (uint32_t s = wave; s < kr; s += nw) {
+        S.Bv[s][lane] = lane < pw ? t.D[(uint64_t)S.Qo[s] * t.ld + c0 + lane] : 0;
+        S.Bg[s][lane] = lane == s ? 1 : 0;
+    }
+    __syncthreads();
+    // lane s of wave 0: inverse of slot s's leading entry
+    const uint32_t inv = wave == 0 && lane < kr ? fl::invmod(S.Bv[lane][S.Cc[lane]], md) : 0;
+    for (uint32_t g0 = 0; g0 < kr; g0 += kProbeGroup) {
+        const uint32_t g1 = g0 + kProbeGroup < kr ? g0 + kProbeGroup : kr;
+        if (wave == 0) {
+            for (uint32_t s = g0; s < g1; s++) {
+                uint32_t v = S.Bv[s][lane], g = S.Bg[s][lane];
+                reduce_against(md, v, g, g0, s, S.Bv, S.Bg, S.Cc, lane, true);
+                const uint32_t is = (uint32_t)__builtin_amdgcn_readlane((int)inv, (int)s);
+                S.Bv[s][lane] = (uint16_t)fl::mulmod(v, is, md);
+                S.Bg[s][lane] = (uint16_t)fl::mulmod(g, is, md);
+            }
+        }
+        __syncthreads();
+        for (uint32_t s = g1 + wave; s < kr; s += nw) {
+            uint32_t v = S.Bv[s][lane], g = S.Bg[s][lane];
+            reduce_against(md, v, g, g0, g1, S.Bv, S.Bg, S.Cc, lane, true);
+            S.Bv[s][lane] = (uint16_t)v;
+            S.Bg[s][lane] = (uint16_t)g;
+        }
+        __syncthreads();
+    }
     const uint32_t rank0 = rank0_s;
-    greedy_rows(md, t.D, t.ld, c0, pw, S);
     save_raw(S, ps);
     finalize(S, ps, c0, rank0, t.is_piv, t.piv_row, t.piv_col, t.d_rank);
 }
