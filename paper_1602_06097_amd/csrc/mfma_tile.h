@@ -37,6 +37,21 @@ __device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint
     return fl::reduce32((uint32_t)s + bias, md);
 }
 
+// The residue of 65536 S_hh + 256 S_mid + S_ll for short sums (K <= 448
+// terms per accumulator, i.e. at most 7 MFMA K-steps of 64): then
+// |S_hh| <= 2^14 K, |S_mid| <= 2^15 K and T = S_mid + 256 S_hh satisfies
+// |T| <= K (2^22 + 2^15) < 2^31 - 2^16, so T + bias is a non-negative 32-bit
+// value; the result is 256 (T mod p) + S_ll (mod p), where 256 (T mod p) <
+// 2^24 and S_ll + bias2 lies in [2^30 - 2^23, 2^30 + 2^23 + p).  Two Barrett
+// reductions instead of five.  bias2: a multiple of p >= 2^30.
+__device__ __forceinline__ uint32_t combine_short(int hh, int mid, int ll, const fl::Mod &md, uint32_t bias,
+                                                  uint32_t bias2) {
+    const uint32_t t = (uint32_t)mid + ((uint32_t)hh << 8) + bias;
+    const uint32_t rt = fl::reduce32(t, md);
+    return fl::reduce32((rt << 8) + (uint32_t)ll + bias2, md);
+}
+__device__ __forceinline__ uint32_t bias_2_30(uint32_t p) { return ((1u << 30) + p - 1) / p * p; }
+
 // bias: the smallest multiple of p that is >= 2^31, so s + bias >= 0 and
 // s + bias < 2^32 for |s| < 2^31 - 2^16.
 inline uint32_t gemm_bias(uint32_t p) { return (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p); }
@@ -295,7 +310,8 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
         bh[0][s] = *(gv4i *)(Bh + b);
         bl[0][s] = *(gv4i *)(Bl + b);
     }
-    const uint32_t bias2 = (uint32_t)(((1u << 30) + md.p - 1) / md.p * md.p);  // >= 2^30, multiple of p
+    static_assert(KS <= 7, "short-sum combination: K <= 448");
+    const uint32_t bias2 = bias_2_30(md.p);
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const int cur = j & 1, nxt = cur ^ 1;
@@ -317,18 +333,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            uint32_t v;
-            if constexpr (KS == 1) {
-                const uint32_t rhh = signed_to_res(hh[e], md, bias);
-                const uint32_t rlo = fl::reduce32((uint32_t)(mid[e] * 256 + ll[e]) + bias2, md);
-                v = fl::reduce32(rhh * c16 + rlo, md);
-            } else {
-                const uint32_t rhh = signed_to_res(hh[e], md, bias);
-                const uint32_t rmid = signed_to_res(mid[e], md, bias);
-                const uint32_t rll = signed_to_res(ll[e], md, bias);
-                v = fl::reduce32(rhh * c16 + rll, md);
-                v = fl::reduce32(v + rmid * 256u, md);
-            }
+            const uint32_t v = combine_short(hh[e], mid[e], ll[e], md, bias, bias2);
             sv[(wave * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
         }
     }

@@ -672,6 +672,8 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
     typedef __attribute__((address_space(1))) const v4i gv4i;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nrow = r1 - r0, c0 = bx * 64;
+    const uint32_t bias2 = fl_mfma::bias_2_30(md.p);
+    (void)c16;
     // R: 128 rows x 16 chunks of 4 columns, 8 chunks per thread (rows past the
     // block or columns past nB read as zero)
     uint64_t rv[8];
@@ -743,11 +745,8 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
         for (int rt = 0; rt < 2; rt++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const uint32_t rhh = fl_mfma::signed_to_res(acc_hh[rt][e], md, bias);
-                const uint32_t rmid = fl_mfma::signed_to_res(acc_mid[rt][e], md, bias);
-                const uint32_t rll = fl_mfma::signed_to_res(acc_ll[rt][e], md, bias);
-                uint32_t v = fl::reduce32(rhh * c16 + rll, md);
-                v = fl::reduce32(v + rmid * 256u, md);
+                const uint32_t v = fl_mfma::combine_short(acc_hh[rt][e], acc_mid[rt][e], acc_ll[rt][e], md, bias,
+                                                          bias2);  // K = 128
                 uint16_t &o = S.R[wave * 32 + rt * 16 + rq + e][j * 16 + cl];
                 o = (uint16_t)fl::submod(o, v, md.p);
             }
