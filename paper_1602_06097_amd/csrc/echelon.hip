@@ -919,33 +919,35 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 // keeping the row block's multiplier fragments in registers; the workgroups
 // of one blockIdx.y walk the same column tiles together, so each tile of the
 // block's U is fetched into L2 once for all row blocks.
+template <int RT>
 __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                              const FlEchTask *__restrict__ tasks,
                                                              const uint32_t *__restrict__ ids,
                                                              const uint32_t *__restrict__ pre, uint32_t ntask,
                                                              uint32_t gcols, uint32_t B, uint32_t lo, uint32_t span) {
-    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
-    __shared__ uint32_t rows_s[64];
-    fl_mfma::RankkRows<kBlockPanels> R;
+    constexpr uint32_t kRows = 64 * RT;  // rows of a workgroup's block
+    __shared__ __attribute__((aligned(16))) uint16_t sv[kRows * fl_mfma::kRank64Ld];
+    __shared__ uint32_t rows_s[kRows];
+    fl_mfma::RankkRows<kBlockPanels, RT> R;
     uint32_t cur = 0xffffffffu;  // task whose row block is loaded
     for (uint32_t cy = blockIdx.y; cy < gcols; cy += gridDim.y) {
         const uint32_t ti = fl_task_of(pre, ntask, cy);
         const FlEchTask &t = tasks[ids[ti]];
         if (B * kBlockPanels >= t.npanels) continue;
         const uint32_t M = t.blk_cnt[B];
-        if (blockIdx.x * 64 >= M) continue;
+        if (blockIdx.x * kRows >= M) continue;
         const uint32_t start = (B + 1) * kBlock + lo;
         const uint32_t end = span < t.cols - start ? start + span : t.cols;
         if (ti != cur) {
             const uint64_t lhalf = (uint64_t)(B & 1) * t.rows * kBlock;
             __syncthreads();  // rows_s of the previous task is still read
-            fl_mfma::rankk_rows<kBlockPanels>(t.Lbh + lhalf, t.Lbl + lhalf, kBlock,
-                                              t.blk_rows + (uint64_t)(B & 1) * t.rows, M, blockIdx.x, rows_s, R);
+            fl_mfma::rankk_rows<kBlockPanels, RT>(t.Lbh + lhalf, t.Lbl + lhalf, kBlock,
+                                                  t.blk_rows + (uint64_t)(B & 1) * t.rows, M, blockIdx.x, rows_s, R);
             cur = ti;
         }
         const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
-        fl_mfma::rankk_cols<kBlockPanels>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start, t.ld,
-                                          end - start, cy - pre[ti], sv, rows_s);
+        fl_mfma::rankk_cols<kBlockPanels, RT>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start,
+                                              t.ld, end - start, cy - pre[ti], sv, rows_s);
         __syncthreads();  // sv is reused by the next tile
     }
 }
@@ -1174,7 +1176,7 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<256>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<256>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
@@ -1189,11 +1191,23 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                 hipLaunchKernelGGL(k_ech_ublk<1024>, dim3(g_all), dim3(1024), 0, s, md, tasks, L.ids_all, pa,
                                    L.n_all, B, lo, span));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (g_mfma) {
-        FL_PROF(far ? "echelon.blk_mfma_far" : "echelon.blk_mfma", s,
-                hipLaunchKernelGGL(k_ech_update_blk_mfma, dim3((mfma_rows + 63) / 64, std::min(g_mfma, kBlkColGroups)),
-                                   dim3(256), far ? dyn_m : 0, s, md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p),
-                                   tasks, L.ids_mfma, pm, L.n_mfma, g_mfma, B, lo, span));
+    // the far part (long row loops over many column tiles) takes 32 rows per
+    // wave, so each B fragment feeds two row tiles; the next block's update
+    // (two column tiles, latency bound) keeps 16 rows per wave and twice the
+    // workgroups
+    if (g_mfma && far) {
+        FL_PROF("echelon.blk_mfma_far", s,
+                hipLaunchKernelGGL(k_ech_update_blk_mfma<2>,
+                                   dim3((mfma_rows + 127) / 128, std::min(g_mfma, kBlkColGroups)), dim3(256), dyn_m, s,
+                                   md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
+                                   g_mfma, B, lo, span));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (g_mfma) {
+        FL_PROF("echelon.blk_mfma", s,
+                hipLaunchKernelGGL(k_ech_update_blk_mfma<1>,
+                                   dim3((mfma_rows + 63) / 64, std::min(g_mfma, kBlkColGroups)), dim3(256), 0, s, md,
+                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
+                                   g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (g_plain) {

@@ -248,54 +248,64 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 // over row blocks must synchronise between tiles.
 // The row block's part of a rank-k tile: its row list entries (rows_s, LDS)
 // and its A fragments, kept in registers for any number of column tiles.
-template <int KS> struct RankkRows {
-    v4i ah[KS], al[KS];
+// A row block of RT x 64 rows: wave w holds the A fragments (both limb
+// planes, K = 64 KS) of its RT row tiles of 16, rows (w RT + rt) 16 + [0, 16).
+template <int KS, int RT = 1> struct RankkRows {
+    v4i ah[RT][KS], al[RT][KS];
 };
 
-template <int KS>
+template <int KS, int RT = 1>
 __device__ __forceinline__ void rankk_rows(const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
                                            uint32_t lda, const uint32_t *__restrict__ row_map, uint32_t M,
-                                           uint32_t by, uint32_t *rows_s, RankkRows<KS> &R) {
+                                           uint32_t by, uint32_t *rows_s, RankkRows<KS, RT> &R) {
     static_assert(KS >= 1 && KS <= 6, "K up to 384");
+    static_assert(RT == 1 || RT == 2, "16 or 32 rows per wave");
     typedef __attribute__((address_space(1))) const v4i gv4i;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t m0 = by * 64;
-    if (tid < 64) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
+    const uint32_t m0 = by * 64 * RT;
+    if (tid < 64 * RT) rows_s[tid] = (m0 + tid < M) ? (row_map ? row_map[m0 + tid] : m0 + tid) : 0xffffffffu;
     __syncthreads();
     const uint32_t cl = lane & 15, kq = (lane >> 4) * 16;
-    const uint32_t arow = rows_s[wave * 16 + cl];
-    const uint32_t ar = arow != 0xffffffffu ? arow : rows_s[0];  // row m0 exists
 #pragma unroll
-    for (int s = 0; s < KS; s++) {
-        R.ah[s] = *(gv4i *)(Ah + (uint64_t)ar * lda + s * 64 + kq);
-        R.al[s] = *(gv4i *)(Al + (uint64_t)ar * lda + s * 64 + kq);
-    }
-    if (arow == 0xffffffffu) {
+    for (int rt = 0; rt < RT; rt++) {
+        const uint32_t arow = rows_s[(wave * RT + rt) * 16 + cl];
+        const uint32_t ar = arow != 0xffffffffu ? arow : rows_s[0];  // row m0 exists
 #pragma unroll
-        for (int s = 0; s < KS; s++) R.ah[s] = R.al[s] = v4i{0, 0, 0, 0};
+        for (int s = 0; s < KS; s++) {
+            R.ah[rt][s] = *(gv4i *)(Ah + (uint64_t)ar * lda + s * 64 + kq);
+            R.al[rt][s] = *(gv4i *)(Al + (uint64_t)ar * lda + s * 64 + kq);
+        }
+        if (arow == 0xffffffffu) {
+#pragma unroll
+            for (int s = 0; s < KS; s++) R.ah[rt][s] = R.al[rt][s] = v4i{0, 0, 0, 0};
+        }
     }
 }
 
-// One 128-column tile bx of the row block set up by rankk_rows.  Callers
-// looping over column tiles must synchronise between tiles (sv is reused).
-template <int KS>
-__device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16, const RankkRows<KS> &R,
-                                           const int8_t *__restrict__ Bh, const int8_t *__restrict__ Bl,
-                                           uint32_t ldb, uint16_t *C, uint64_t ldc, uint32_t N, uint32_t bx,
-                                           uint16_t *sv, const uint32_t *rows_s) {
+// One 128-column tile bx of the row block set up by rankk_rows (sv: 64 RT
+// rows of kRank64Ld residues).  Callers looping over column tiles must
+// synchronise between tiles (sv is reused).  Each B fragment feeds the RT
+// row tiles of the wave.
+template <int KS, int RT = 1>
+__device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                           const RankkRows<KS, RT> &R, const int8_t *__restrict__ Bh,
+                                           const int8_t *__restrict__ Bl, uint32_t ldb, uint16_t *C, uint64_t ldc,
+                                           uint32_t N, uint32_t bx, uint16_t *sv, const uint32_t *rows_s) {
     // every operand lives in device memory: global (not flat) accesses, so
     // that loads are counted apart from LDS traffic and can stay in flight
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) uint64_t gu64w;
     typedef __attribute__((address_space(1))) const v4i gv4i;
     constexpr int kLd = kRank64Ld;
+    constexpr int kChunks = 8 * RT;  // C chunks of 4 columns per thread
+    (void)c16;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n0 = bx * 128;
-    // C tile: 64 rows x 32 chunks of 4 columns = 2048 chunks, 8 per thread;
-    // every load is issued (chunks outside the tile read C[0])
-    uint64_t cv[8];
+    // C tile: 64 RT rows x 32 chunks of 4 columns; every load is issued
+    // (chunks outside the tile read C[0])
+    uint64_t cv[kChunks];
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
+    for (int u = 0; u < kChunks; u++) {
         const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
         const uint32_t row = rows_s[r], col = n0 + c4;
         const bool ok = row != 0xffffffffu && col + 4 <= N;
@@ -323,23 +333,29 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
                 bl[nxt][s] = *(gv4i *)(Bl + b);
             }
         }
-        v4i hh = {0, 0, 0, 0}, mid = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+        v4i hh[RT], mid[RT], ll[RT];
 #pragma unroll
-        for (int s = 0; s < KS; s++) {
-            hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[s], bh[cur][s], hh, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[s], bl[cur][s], mid, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[s], bh[cur][s], mid, 0, 0, 0);
-            ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[s], bl[cur][s], ll, 0, 0, 0);
-        }
+        for (int rt = 0; rt < RT; rt++) hh[rt] = mid[rt] = ll[rt] = v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const uint32_t v = combine_short(hh[e], mid[e], ll[e], md, bias, bias2);
-            sv[(wave * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
-        }
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++) {
+                hh[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[rt][s], bh[cur][s], hh[rt], 0, 0, 0);
+                mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.ah[rt][s], bl[cur][s], mid[rt], 0, 0, 0);
+                mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[rt][s], bh[cur][s], mid[rt], 0, 0, 0);
+                ll[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(R.al[rt][s], bl[cur][s], ll[rt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t v = combine_short(hh[rt][e], mid[rt][e], ll[rt][e], md, bias, bias2);
+                sv[((wave * RT + rt) * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
+            }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
+    for (int u = 0; u < kChunks; u++) {
         const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
         const uint32_t row = rows_s[r], col = n0 + c4;
         if (row == 0xffffffffu || col >= N) continue;
