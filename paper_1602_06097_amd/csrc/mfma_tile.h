@@ -67,6 +67,13 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t wm = wave >> 1, wn = wave & 1;
     const uint32_t m0 = by * BM, n0 = bx * BN;
+    // C row of each tile row (0xffffffff: past M or unmapped), read by the
+    // epilogue after its barrier
+    __shared__ uint32_t rows_s[BM];
+    if (tid < BM) {
+        const uint32_t row = m0 + tid;
+        rows_s[tid] = row < g.M ? (g.row_map ? g.row_map[row] : row) : 0xffffffffu;
+    }
     uint32_t kbeg = g.kbeg, kend = g.kend;
     if (g.krange) {
         kbeg = g.krange[2 * by];
@@ -166,6 +173,19 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (kbeg >= kend) return;  // nothing to subtract
+    // the C tile (128 rows x 32 chunks of 4 columns, 16 chunks per thread) is
+    // loaded before the residues are formed, so its latency overlaps that
+    // work; every load is issued (chunks outside the tile read C[0])
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
+    typedef __attribute__((address_space(1))) uint64_t gu64w;
+    uint64_t cvals[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const uint32_t ch = tid + u * 256, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+        const uint32_t orow = rows_s[r], col = n0 + c4;
+        const bool ok = orow != 0xffffffffu && col + 4 <= g.N;
+        cvals[u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
+    }
     // epilogue: residues of the 128 x 128 tile go through LDS (the operand
     // buffers are free now), then C is read, reduced and written back with
     // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
@@ -188,45 +208,24 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             }
         }
     __syncthreads();
-    // 128 rows x 32 chunks of 4 columns; 256 threads -> 16 chunks each, in
-    // batches of 4 whose C loads are issued before their stores
-#pragma unroll 1
-    for (int u0 = 0; u0 < 16; u0 += 4) {
-        uint64_t cvals[4];
-        uint32_t orows[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const uint32_t ch = tid + (u0 + u) * 256;
-            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-            const uint32_t row = m0 + r, col = n0 + c4;
-            cvals[u] = 0;
-            orows[u] = 0xffffffffu;
-            if (row < g.M && col < g.N) {
-                orows[u] = g.row_map ? g.row_map[row] : row;
-                if (orows[u] != 0xffffffffu && col + 4 <= g.N)
-                    cvals[u] = *(const uint64_t *)(g.C + (uint64_t)orows[u] * g.ldc + col);
-            }
-        }
+    for (int u = 0; u < 16; u++) {
+        const uint32_t ch = tid + u * 256, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+        const uint32_t orow = rows_s[r], col = n0 + c4;
+        if (orow == 0xffffffffu || col >= g.N) continue;
+        uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
+        const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
+        if (col + 4 <= g.N) {
+            const uint64_t ov = cvals[u];
+            uint64_t nv = 0;
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const uint32_t ch = tid + (u0 + u) * 256;
-            const uint32_t r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-            const uint32_t col = n0 + c4;
-            if (orows[u] == 0xffffffffu) continue;
-            uint16_t *o = g.C + (uint64_t)orows[u] * g.ldc + col;
-            const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
-            if (col + 4 <= g.N) {
-                const uint64_t ov = cvals[u];
-                uint64_t nv = 0;
-#pragma unroll
-                for (int c = 0; c < 4; c++)
-                    nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
-                                               (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
-                *(uint64_t *)o = nv;
-            } else {
-                for (uint32_t c = 0; col + c < g.N; c++)
-                    o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
-            }
+            for (int c = 0; c < 4; c++)
+                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
+                                           (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+            *(gu64w *)o = nv;
+        } else {
+            for (uint32_t c = 0; col + c < g.N; c++)
+                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
         }
     }
 }
