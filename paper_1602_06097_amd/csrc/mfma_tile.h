@@ -8,9 +8,11 @@
 // Then  sum_k A B = 65536 S_hh + 256 (S_hl + S_lh) + S_ll  with four int8 GEMMs
 // accumulated exactly in int32 (v_mfma_i32_16x16x64_i8): |h h'| <= 2^14, so a
 // K-chunk of at most kKChunk = 65472 terms keeps |S_hh|, |S_ll| < 2^30 and the
-// shared middle accumulator |S_hl + S_lh| < 2^31.  Each partial is biased to
-// a non-negative 32-bit value (a multiple of p added), Barrett-reduced, and
-// recombined with 2^16 mod p and 2^8.  No floating point anywhere.
+// shared middle accumulator |S_hl + S_lh| < 2^31.  The three partials are
+// combined into S = 65536 S_hh + 256 S_mid + S_ll and reduced mod p in
+// double precision (combine_limbs): every intermediate is an integer below
+// 2^53 in magnitude, so all of it is exact except the quotient estimate,
+// which only selects a candidate remainder that two comparisons correct.
 //
 // The tiles are device functions so that both the one-problem kernels and
 // the kernels that serve many problems in one launch (one problem per
@@ -33,24 +35,35 @@ constexpr uint32_t kStageBytes = 4 * kPlaneBytes;
 constexpr int kGemmLds = kStages * kStageBytes;  // bytes of LDS of one GEMM tile
 constexpr int kRank64Ld = 128 + 4;          // u16 row stride of the rank-k residue tile
 
-__device__ __forceinline__ uint32_t signed_to_res(int s, const fl::Mod &md, uint32_t bias) {
-    return fl::reduce32((uint32_t)s + bias, md);
+// The residue of S = 65536 S_hh + 256 S_mid + S_ll mod p from the three int32
+// limb sums, in double precision (full-rate FP64 on the vector units,
+// against four quarter-rate 32-bit multiplies per Barrett reduction):
+//   t = 256 S_hh + S_mid and S = 256 t + S_ll are exact fused multiply-adds
+//   (|S| < 2^47 for sums of at most kKChunk terms);
+//   q = floor(S * (1/p)) is within 1 of floor(S / p), because the relative
+//   error of the product is below 2^-50 and |S / p| < 2^46;
+//   r = S - q p is exact (an integer below 2^53), lies in [-p, 2p), and two
+//   conditional corrections bring it into [0, p).
+struct LimbCombine {
+    double pd, inv;
+    int p;
+};
+__device__ __forceinline__ LimbCombine limb_combine(const fl::Mod &md) {
+    LimbCombine c;
+    c.p = (int)md.p;
+    c.pd = (double)md.p;
+    c.inv = 1.0 / c.pd;
+    return c;
 }
-
-// The residue of 65536 S_hh + 256 S_mid + S_ll for short sums (K <= 448
-// terms per accumulator, i.e. at most 7 MFMA K-steps of 64): then
-// |S_hh| <= 2^14 K, |S_mid| <= 2^15 K and T = S_mid + 256 S_hh satisfies
-// |T| <= K (2^22 + 2^15) < 2^31 - 2^16, so T + bias is a non-negative 32-bit
-// value; the result is 256 (T mod p) + S_ll (mod p), where 256 (T mod p) <
-// 2^24 and S_ll + bias2 lies in [2^30 - 2^23, 2^30 + 2^23 + p).  Two Barrett
-// reductions instead of five.  bias2: a multiple of p >= 2^30.
-__device__ __forceinline__ uint32_t combine_short(int hh, int mid, int ll, const fl::Mod &md, uint32_t bias,
-                                                  uint32_t bias2) {
-    const uint32_t t = (uint32_t)mid + ((uint32_t)hh << 8) + bias;
-    const uint32_t rt = fl::reduce32(t, md);
-    return fl::reduce32((rt << 8) + (uint32_t)ll + bias2, md);
+__device__ __forceinline__ uint32_t combine_limbs(const LimbCombine &c, int hh, int mid, int ll) {
+    const double t = __builtin_fma((double)hh, 256.0, (double)mid);
+    const double S = __builtin_fma(t, 256.0, (double)ll);
+    const double q = __builtin_floor(S * c.inv);
+    int r = (int)__builtin_fma(-q, c.pd, S);
+    r += r < 0 ? c.p : 0;
+    r -= r >= c.p ? c.p : 0;
+    return (uint32_t)r;
 }
-__device__ __forceinline__ uint32_t bias_2_30(uint32_t p) { return ((1u << 30) + p - 1) / p * p; }
 
 // bias: the smallest multiple of p that is >= 2^31, so s + bias >= 0 and
 // s + bias < 2^32 for |s| < 2^31 - 2^16.
@@ -191,6 +204,9 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
     // column lane%16) of each 16 x 16 tile is held by the wave.
     uint16_t *sOut = (uint16_t *)smem;
+    const LimbCombine lc = limb_combine(md);
+    (void)bias;
+    (void)c16;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -199,12 +215,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const uint32_t row = wm * 64 + i * 16 + (lane >> 4) * 4 + e;
-                const uint32_t rhh = signed_to_res(acc_hh[i][j][e], md, bias);
-                const uint32_t rmid = signed_to_res(acc_mid[i][j][e], md, bias);
-                const uint32_t rll = signed_to_res(acc_ll[i][j][e], md, bias);
-                uint32_t v = fl::reduce32(rhh * c16 + rll, md);
-                v = fl::reduce32(v + rmid * 256u, md);
-                sOut[row * kOutLd + col] = (uint16_t)v;
+                sOut[row * kOutLd + col] = (uint16_t)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
             }
         }
     __syncthreads();
@@ -319,8 +330,8 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
         bh[0][s] = *(gv4i *)(Bh + b);
         bl[0][s] = *(gv4i *)(Bl + b);
     }
-    static_assert(KS <= 7, "short-sum combination: K <= 448");
-    const uint32_t bias2 = bias_2_30(md.p);
+    const LimbCombine lc = limb_combine(md);
+    (void)bias;
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const int cur = j & 1, nxt = cur ^ 1;
@@ -348,7 +359,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
         for (int rt = 0; rt < RT; rt++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const uint32_t v = combine_short(hh[rt][e], mid[rt][e], ll[rt][e], md, bias, bias2);
+                const uint32_t v = combine_limbs(lc, hh[rt][e], mid[rt][e], ll[rt][e]);
                 sv[((wave * RT + rt) * 16 + rq + e) * kLd + j * 16 + cl] = (uint16_t)v;
             }
     }

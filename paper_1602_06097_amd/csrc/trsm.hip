@@ -672,7 +672,8 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
     typedef __attribute__((address_space(1))) const v4i gv4i;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nrow = r1 - r0, c0 = bx * 64;
-    const uint32_t bias2 = fl_mfma::bias_2_30(md.p);
+    const fl_mfma::LimbCombine lc = fl_mfma::limb_combine(md);
+    (void)bias;
     (void)c16;
     // R: 128 rows x 16 chunks of 4 columns, 8 chunks per thread (rows past the
     // block or columns past nB read as zero)
@@ -745,8 +746,7 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
         for (int rt = 0; rt < 2; rt++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const uint32_t v = fl_mfma::combine_short(acc_hh[rt][e], acc_mid[rt][e], acc_ll[rt][e], md, bias,
-                                                          bias2);  // K = 128
+                const uint32_t v = fl_mfma::combine_limbs(lc, acc_hh[rt][e], acc_mid[rt][e], acc_ll[rt][e]);
                 uint16_t &o = S.R[wave * 32 + rt * 16 + rq + e][j * 16 + cl];
                 o = (uint16_t)fl::submod(o, v, md.p);
             }
