@@ -148,13 +148,26 @@ size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint32_t ml_widt
  * a multiline).  X: dense npiv x nB (ld = ldx).  B is read from s->b_*.
  * FL_PLAIN: the part of each block's rows that refers to finished rows below
  * the block is applied by the multiline sparse-times-dense kernel on the
- * vector ALUs.  FL_MFMA_I8: that part is an int8-limb GEMM on the matrix
- * cores (A's band expanded into dense limb planes in the workspace).  The
- * in-block back substitution is on the vector ALUs in both forms; results are
- * bit-identical. */
+ * vector ALUs, and each block is solved by a back substitution on the vector
+ * ALUs.  FL_MFMA_I8: A's band is expanded into dense int8 limb planes in the
+ * workspace; the part beyond each superblock of four blocks is one limb GEMM
+ * on the matrix cores, the part inside it a rank-k product per block, and
+ * each block is solved as a product with its (precomputed) inverse.  Both
+ * forms give the same, unique X. */
 fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
                   fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
 size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode);
+
+/* fl_trsm_planes -- where an FL_MFMA_I8 fl_trsm leaves the int8 limb planes
+ * of X in its workspace ws (ws_bytes >= fl_trsm_workspace(info, FL_MFMA_I8)):
+ * the centred residue of X[k][c] (X[k][c], or X[k][c] - p above 32639) is
+ * 256 Xh[c * ldp + k] + Xl[c * ldp + k] (the limb form of the matrix-core
+ * products), for k < npiv, c < nB; the planes hold round_up(nB, 128) columns.  Pointers into ws, no copy; their
+ * contents are those of the last fl_trsm that used ws in the FL_MFMA_I8 form
+ * and stay valid until ws is reused.  Errors: FL_ERR_ARG for NULL arguments,
+ * npiv or nB of 0, or a workspace that is too small. */
+fl_status fl_trsm_planes(const fl_split_info *info, const void *ws, size_t ws_bytes, const int8_t **Xh,
+                         const int8_t **Xl, uint64_t *ldp);
 
 /* ---- step 3 --------------------------------------------------------------
  * fl_reduce_cd -- Sec. 4.1 step 3: Dt = D - C X mod p (C reduced to zero by
@@ -165,6 +178,18 @@ fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out *s, const u
                        uint64_t ldx, uint16_t *Dt, uint64_t ldd, fl_mode mode, void *ws,
                        size_t ws_bytes, hipStream_t stream);
 size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode);
+
+/* fl_reduce_cd_planes -- fl_reduce_cd in the FL_MFMA_I8 form with X given by
+ * its int8 limb planes (as fl_trsm_planes returns them: column c of X at
+ * Xh/Xl + c * ldp, round_up(nB, 128) columns, ldp >= round_up(npiv, 64),
+ * ldp a multiple of 16, both planes 16-byte aligned), so that X is not
+ * converted again; the planes are only read.  Same Dt as fl_reduce_cd, bit
+ * for bit.  Workspace: fl_reduce_cd_planes_workspace(info) bytes (smaller
+ * than fl_reduce_cd's: no planes of X).  Errors as fl_reduce_cd. */
+fl_status fl_reduce_cd_planes(const fl_split_info *info, const fl_split_out *s, const int8_t *Xh,
+                              const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+size_t fl_reduce_cd_planes_workspace(const fl_split_info *info);
 
 /* ---- step 4 --------------------------------------------------------------
  * fl_echelon_d -- Sec. 4.1 step 4 / Sec. 4.4, read as the REDUCED row

@@ -22,7 +22,8 @@ from dataclasses import dataclass
 
 import torch
 
-__all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd", "reduce_neworder",
+__all__ = ["FL_PLAIN", "FL_MFMA_I8", "FlError", "lib_path", "load", "split", "trsm", "reduce_cd", "reduce_cd_planes", "Planes",
+           "reduce_neworder",
            "echelon_d", "rref", "rref_to_csr", "matmul_sub", "fl_reduce", "check_modp", "prof_report",
            "version", "Split", "Echelon", "Batch", "batch_plan", "batch_run", "batch_graph_build",
            "batch_graph_launch", "batch_results", "batch_autotune", "batch_config"]
@@ -94,6 +95,10 @@ def load():
         "fl_reduce_cd": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
                                     c_vp, c_sz, c_vp]),
         "fl_reduce_cd_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_trsm_planes": (ct.c_int, [P(FlSplitInfo), c_vp, c_sz, P(c_vp), P(c_vp), P(c_u64)]),
+        "fl_reduce_cd_planes": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_vp, c_u64, c_vp, c_u64,
+                                           c_vp, c_sz, c_vp]),
+        "fl_reduce_cd_planes_workspace": (c_sz, [P(FlSplitInfo)]),
         "fl_reduce_neworder": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, ct.c_int, c_vp, c_sz, c_vp]),
         "fl_reduce_neworder_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
         "fl_echelon_d": (ct.c_int, [c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_vp, ct.c_int, c_vp, c_sz,
@@ -227,8 +232,18 @@ def split(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, m: int, n
     return Split(info=info, out=out, bufs=bufs)
 
 
-def trsm(sp: Split, mode: int = FL_PLAIN) -> torch.Tensor:
-    """X = A^{-1} B as a dense (npiv x ld) uint16 tensor (int16 storage)."""
+class Planes:
+    """The int8 limb planes of X left in an MFMA-form TRSM workspace (which
+    this object keeps alive): Xh/Xl device addresses and their row stride."""
+
+    def __init__(self, ws, xh: int, xl: int, ldp: int):
+        self.ws, self.xh, self.xl, self.ldp = ws, xh, xl, ldp
+
+
+def trsm(sp: Split, mode: int = FL_PLAIN, keep_planes: bool = False):
+    """X = A^{-1} B as a dense (npiv x ld) uint16 tensor (int16 storage).
+    With keep_planes (FL_MFMA_I8 only) returns (X, Planes): the limb planes of
+    X in the TRSM workspace, for reduce_cd_planes."""
     lib = load()
     ld = _ld(sp.nB)
     X = torch.empty((max(sp.npiv, 1), ld), dtype=torch.int16, device=_dev())
@@ -236,7 +251,26 @@ def trsm(sp: Split, mode: int = FL_PLAIN) -> torch.Tensor:
     st = lib.fl_trsm(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), ld, mode, _ptr(ws), ws.numel(),
                      _stream())
     _check(st, "fl_trsm")
-    return X
+    if not keep_planes:
+        return X
+    if mode != FL_MFMA_I8:
+        raise ValueError("trsm: keep_planes needs the FL_MFMA_I8 form")
+    xh, xl, ldp = ct.c_void_p(), ct.c_void_p(), c_u64()
+    st = lib.fl_trsm_planes(ct.byref(sp.info), _ptr(ws), ws.numel(), ct.byref(xh), ct.byref(xl), ct.byref(ldp))
+    _check(st, "fl_trsm_planes")
+    return X, Planes(ws, xh.value, xl.value, ldp.value)
+
+
+def reduce_cd_planes(sp: Split, planes: Planes) -> torch.Tensor:
+    """reduce_cd (FL_MFMA_I8) from the limb planes of X that trsm kept."""
+    lib = load()
+    ld = _ld(sp.nB)
+    Dt = torch.empty((max(sp.mD, 1), ld), dtype=torch.int16, device=_dev())
+    ws = _ws(lib.fl_reduce_cd_planes_workspace(ct.byref(sp.info)))
+    st = lib.fl_reduce_cd_planes(ct.byref(sp.info), ct.byref(sp.out), planes.xh, planes.xl, planes.ldp,
+                                 _ptr(Dt), ld, _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_reduce_cd_planes")
+    return Dt
 
 
 def reduce_cd(sp: Split, X: torch.Tensor, mode: int = FL_PLAIN) -> torch.Tensor:

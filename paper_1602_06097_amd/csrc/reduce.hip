@@ -154,7 +154,9 @@ struct ReduceWs {
     uint32_t ntiles, nbuckets;
 };
 
-size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs *r) {
+// x_planes: the workspace holds the limb planes of X (false when the caller
+// passes them in).
+size_t reduce_layout(const fl_split_info *info, fl_mode mode, bool x_planes, void *ws, ReduceWs *r) {
     WsCarve c(ws);
     ReduceWs t = {};
     if (mode == FL_MFMA_I8 && info->mD && info->nB && info->npiv) {
@@ -165,8 +167,10 @@ size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs
         const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
         t.Ah = c.take<int8_t>(mp * t.kp);
         t.Al = c.take<int8_t>(mp * t.kp);
-        t.Xh = c.take<int8_t>(np * t.kp);
-        t.Xl = c.take<int8_t>(np * t.kp);
+        if (x_planes) {
+            t.Xh = c.take<int8_t>(np * t.kp);
+            t.Xl = c.take<int8_t>(np * t.kp);
+        }
         t.first = c.take<uint32_t>(info->mD);
         t.last = c.take<uint32_t>(info->mD);
         t.bucket = c.take<uint32_t>(info->mD);
@@ -186,38 +190,15 @@ size_t reduce_layout(const fl_split_info *info, fl_mode mode, void *ws, ReduceWs
 
 fl_limbs_cols_fn fl_limbs_cols_kernel();
 
-extern "C" size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode) {
-    if (!info) return 0;
-    return reduce_layout(info, mode, nullptr, nullptr);
-}
-
-extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out *s,
-                                  const uint16_t *X, uint64_t ldx, uint16_t *Dt, uint64_t ldd,
-                                  fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream) {
-    fl_status st = fl_check_split(info, s);
-    if (st != FL_OK) return st;
-    FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_reduce_cd: bad mode");
+namespace {
+// The int8-MFMA form of the reduce: C's rows sorted by first column into
+// 128-row tiles with their K ranges, C as limb planes, X's limb planes (Xh,
+// Xl, row stride ldp) converted from X when X is given, then Dt -= C X.
+fl_status reduce_mfma(const fl_split_info *info, const fl_split_out *s, const uint16_t *X, uint64_t ldx,
+                      const int8_t *Xh, const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd,
+                      const ReduceWs &r, hipStream_t stream) {
     const uint32_t mD = info->mD, nB = info->nB, npiv = info->npiv, w = info->ml_width;
-    if (mD == 0 || nB == 0) return FL_OK;
-    FL_ARG(Dt, "fl_reduce_cd: NULL Dt");
-    FL_ARG(ldd >= nB && ldd % 4 == 0, "fl_reduce_cd: ldd must be >= nB and a multiple of 4");
-    FL_ARG(((uintptr_t)Dt & 7) == 0, "fl_reduce_cd: Dt must be 8-byte aligned");
-    FL_ARG(npiv == 0 || (X && ldx >= nB && ldx % 4 == 0 && ((uintptr_t)X & 7) == 0),
-           "fl_reduce_cd: bad X (NULL, ldx < nB, ldx % 4, or misaligned)");
-    ReduceWs r;
-    size_t need = reduce_layout(info, mode, ws, &r);
-    if (need && (!ws || ws_bytes < need)) {
-        fl_set_error("fl_reduce_cd: workspace too small");
-        return FL_ERR_WORKSPACE;
-    }
-    FL_HIP(fl_csr_to_dense(mD, nB, s->d_ptr, s->d_col, s->d_val, Dt, ldd, stream));
-    if (npiv == 0) return FL_OK;
     const uint32_t ngroups = (mD + w - 1) / w;
-    if (mode == FL_PLAIN) {
-        FL_HIP(fl_ml_spmm(w, info->p, s->c_gptr, s->c_pos, s->c_val, 0, ngroups, mD, 0, X, ldx, Dt,
-                          ldd, nB, stream, "reduce.spmm"));
-        return FL_OK;
-    }
     FL_HIP(fl_fill_u64(r.hist, 0, r.nbuckets, stream));
     FL_HIP(fl_fill_u32(r.fill, 0, r.nbuckets, stream));
     FL_PROF("reduce.sort", stream, {
@@ -238,15 +219,83 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
         hipLaunchKernelGGL(k_tile_scatter, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, info->p, ngroups,
                            mD, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
                            (const uint16_t *)s->c_val, (const uint32_t *)r.rank_of, r.Ah, r.Al, r.kp);
-        const uint32_t np = (nB + 127) / 128 * 128;
-        hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(np / 64, (unsigned)(r.kp / 64)), dim3(256), 0, stream,
-                           info->p, X, ldx, nB, npiv, (const uint32_t *)nullptr, r.Xh, r.Xl, (uint32_t)r.kp);
+        if (X) {  // X's limb planes into the workspace
+            const uint32_t np = (nB + 127) / 128 * 128;
+            hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(np / 64, (unsigned)(r.kp / 64)), dim3(256), 0,
+                               stream, info->p, X, ldx, nB, npiv, (const uint32_t *)nullptr, r.Xh, r.Xl,
+                               (uint32_t)r.kp);
+        }
     });
     FL_LAUNCH_CHECK("reduce limbs");
-    GemmPlanes gp = {r.Ah, r.Al, r.Xh, r.Xl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
+    GemmPlanes gp = {r.Ah, r.Al, Xh, Xl, r.kp, ldp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
                      nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "reduce.mfma"));
     return FL_OK;
+}
+}  // namespace
+
+extern "C" size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode) {
+    if (!info) return 0;
+    return reduce_layout(info, mode, true, nullptr, nullptr);
+}
+
+extern "C" size_t fl_reduce_cd_planes_workspace(const fl_split_info *info) {
+    if (!info) return 0;
+    return reduce_layout(info, FL_MFMA_I8, false, nullptr, nullptr);
+}
+
+extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out *s,
+                                  const uint16_t *X, uint64_t ldx, uint16_t *Dt, uint64_t ldd,
+                                  fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream) {
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    FL_ARG(mode == FL_PLAIN || mode == FL_MFMA_I8, "fl_reduce_cd: bad mode");
+    const uint32_t mD = info->mD, nB = info->nB, npiv = info->npiv, w = info->ml_width;
+    if (mD == 0 || nB == 0) return FL_OK;
+    FL_ARG(Dt, "fl_reduce_cd: NULL Dt");
+    FL_ARG(ldd >= nB && ldd % 4 == 0, "fl_reduce_cd: ldd must be >= nB and a multiple of 4");
+    FL_ARG(((uintptr_t)Dt & 7) == 0, "fl_reduce_cd: Dt must be 8-byte aligned");
+    FL_ARG(npiv == 0 || (X && ldx >= nB && ldx % 4 == 0 && ((uintptr_t)X & 7) == 0),
+           "fl_reduce_cd: bad X (NULL, ldx < nB, ldx % 4, or misaligned)");
+    ReduceWs r;
+    size_t need = reduce_layout(info, mode, true, ws, &r);
+    if (need && (!ws || ws_bytes < need)) {
+        fl_set_error("fl_reduce_cd: workspace too small");
+        return FL_ERR_WORKSPACE;
+    }
+    FL_HIP(fl_csr_to_dense(mD, nB, s->d_ptr, s->d_col, s->d_val, Dt, ldd, stream));
+    if (npiv == 0) return FL_OK;
+    const uint32_t ngroups = (mD + w - 1) / w;
+    if (mode == FL_PLAIN) {
+        FL_HIP(fl_ml_spmm(w, info->p, s->c_gptr, s->c_pos, s->c_val, 0, ngroups, mD, 0, X, ldx, Dt,
+                          ldd, nB, stream, "reduce.spmm"));
+        return FL_OK;
+    }
+    return reduce_mfma(info, s, X, ldx, r.Xh, r.Xl, r.kp, Dt, ldd, r, stream);
+}
+
+extern "C" fl_status fl_reduce_cd_planes(const fl_split_info *info, const fl_split_out *s, const int8_t *Xh,
+                                         const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd, void *ws,
+                                         size_t ws_bytes, hipStream_t stream) {
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    const uint32_t mD = info->mD, nB = info->nB, npiv = info->npiv;
+    if (mD == 0 || nB == 0) return FL_OK;
+    FL_ARG(Dt, "fl_reduce_cd_planes: NULL Dt");
+    FL_ARG(ldd >= nB && ldd % 4 == 0, "fl_reduce_cd_planes: ldd must be >= nB and a multiple of 4");
+    FL_ARG(((uintptr_t)Dt & 7) == 0, "fl_reduce_cd_planes: Dt must be 8-byte aligned");
+    FL_ARG(npiv == 0 || (Xh && Xl && ldp >= ((uint64_t)npiv + 63) / 64 * 64 && ldp % 16 == 0 &&
+                         ((uintptr_t)Xh & 15) == 0 && ((uintptr_t)Xl & 15) == 0),
+           "fl_reduce_cd_planes: bad planes (NULL, ldp < npiv rounded up to 64, ldp % 16, or misaligned)");
+    ReduceWs r;
+    size_t need = reduce_layout(info, FL_MFMA_I8, false, ws, &r);
+    if (need && (!ws || ws_bytes < need)) {
+        fl_set_error("fl_reduce_cd_planes: workspace too small");
+        return FL_ERR_WORKSPACE;
+    }
+    FL_HIP(fl_csr_to_dense(mD, nB, s->d_ptr, s->d_col, s->d_val, Dt, ldd, stream));
+    if (npiv == 0) return FL_OK;
+    return reduce_mfma(info, s, nullptr, 0, Xh, Xl, ldp, Dt, ldd, r, stream);
 }
 
 extern "C" size_t fl_matmul_sub_workspace(uint32_t M, uint32_t N, uint32_t K, fl_mode mode) {

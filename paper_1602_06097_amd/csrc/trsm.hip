@@ -1003,6 +1003,21 @@ extern "C" size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode) {
     return trsm_layout(info, mode, nullptr, nullptr);
 }
 
+// The limb planes of X that an MFMA-form fl_trsm leaves in its workspace
+// (written by the block solves, read by the far and near updates).
+extern "C" fl_status fl_trsm_planes(const fl_split_info *info, const void *ws, size_t ws_bytes,
+                                    const int8_t **Xh, const int8_t **Xl, uint64_t *ldp) {
+    FL_ARG(info && Xh && Xl && ldp, "fl_trsm_planes: NULL argument");
+    FL_ARG(info->npiv && info->nB, "fl_trsm_planes: empty X (npiv or nB is 0)");
+    TrsmWs tw;
+    const size_t need = trsm_layout(info, FL_MFMA_I8, const_cast<void *>(ws), &tw);
+    FL_ARG(ws && ws_bytes >= need, "fl_trsm_planes: workspace smaller than fl_trsm_workspace(info, FL_MFMA_I8)");
+    *Xh = tw.Xh;
+    *Xl = tw.Xl;
+    *ldp = tw.kp;
+    return FL_OK;
+}
+
 fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
                           fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream, FlTrsmTask *task) {
     fl_status st = check_split_info(info, s);

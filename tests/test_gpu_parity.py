@@ -363,6 +363,41 @@ def test_reduce_neworder_parity(name, w, mode):
     assert np.array_equal(u16(Dt)[:s["mD"], :s["nB"]], r["Dt"])
 
 
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("w", [1, 2])
+def test_reduce_from_trsm_planes(name, w):
+    """Dt from the limb planes of X that the MFMA-form TRSM leaves in its
+    workspace (fl_trsm_planes + fl_reduce_cd_planes) equals the oracle's,
+    and X itself is unchanged by keeping the planes."""
+    g, r = CASES[name], ref(name)
+    s = r["split"]
+    sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=w)
+    if not (s["npiv"] and s["nB"]):  # no X: no planes
+        with pytest.raises(fl.FlError):
+            fl.trsm(sp, fl.FL_MFMA_I8, keep_planes=True)
+        return
+    X, planes = fl.trsm(sp, fl.FL_MFMA_I8, keep_planes=True)
+    Dt = fl.reduce_cd_planes(sp, planes)
+    torch.cuda.synchronize()
+    assert np.array_equal(u16(X)[:s["npiv"], :s["nB"]], r["X"])
+    if s["mD"]:
+        assert np.array_equal(u16(Dt)[:s["mD"], :s["nB"]], r["Dt"])
+
+
+def test_reduce_from_trsm_planes_many_blocks():
+    """Planes of a TRSM with several superblocks, ragged nB and npiv, and a
+    reduce whose 128-row tiles span several K ranges."""
+    g = flgen.fl_matrix(m=1500, n=1800, npiv=1100, rank_d=250, density=0.04, p=65521, seed=43)
+    r = oracle.fl_rref(g)
+    sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=2)
+    X, planes = fl.trsm(sp, fl.FL_MFMA_I8, keep_planes=True)
+    Dt = fl.reduce_cd_planes(sp, planes)
+    Dt2 = fl.reduce_cd(sp, X, fl.FL_MFMA_I8)
+    torch.cuda.synchronize()
+    assert np.array_equal(u16(Dt)[:sp.mD, :sp.nB], r["Dt"])
+    assert np.array_equal(u16(Dt2)[:sp.mD, :sp.nB], r["Dt"])
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_reduce_neworder_many_blocks(mode):
     """Several TRSM blocks in the transposed solve, a K range beyond one
