@@ -222,7 +222,9 @@ size_t fl_rref_workspace(const fl_split_info *info, fl_mode mode);
  * fl_rref_csr_size writes row_ptr[rank + 1] (device, capacity
  * npiv + min(mD, nB) + 1), synchronises `stream` and returns the rank and
  * the nonzero count through h_rank / h_nnz.
- * fl_rref_to_csr then fills col[nnz] and val[nnz] (device) given row_ptr. */
+ * fl_rref_to_csr then fills col[nnz] and val[nnz] (device) given row_ptr.
+ * Xp and RD as fl_rref leaves them: ldx, ldd multiples of 4 and both
+ * 8-byte aligned (FL_ERR_ARG otherwise). */
 fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
                            uint64_t ldx, const uint16_t *RD, uint64_t ldd,
                            const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,

@@ -137,6 +137,14 @@ __device__ __forceinline__ OutRow out_row(uint32_t j, uint32_t npiv, uint32_t r,
     return o;
 }
 
+// Nonzero u16 entries among the four of v.
+__device__ __forceinline__ uint32_t nz4(uint64_t v) {
+    return ((v & 0xffffull) != 0) + ((v & 0xffff0000ull) != 0) + ((v & 0xffff00000000ull) != 0) +
+           ((v >> 48) != 0);
+}
+
+// Rows are read as 8-byte chunks of four entries (rows start 8-byte aligned:
+// ld is a multiple of 4); the nB % 4 entries past the last chunk one by one.
 __global__ __launch_bounds__(256) void k_csr_count(uint32_t npiv, uint32_t nB,
                                                    const uint32_t *__restrict__ col_perm,
                                                    const uint16_t *__restrict__ Xp, uint64_t ldx,
@@ -144,18 +152,25 @@ __global__ __launch_bounds__(256) void k_csr_count(uint32_t npiv, uint32_t nB,
                                                    const uint32_t *__restrict__ d_rank,
                                                    const uint32_t *__restrict__ pivcol,
                                                    uint64_t *cnt) {
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
     const uint32_t r = *d_rank;
     if (j >= npiv + r) return;
     OutRow o = out_row(j, npiv, r, col_perm, pivcol);
     const uint16_t *row = o.top ? Xp + (uint64_t)o.src * ldx : RD + (uint64_t)o.src * ldd;
+    const gu64 *row8 = (const gu64 *)row;
+    const uint32_t nq = nB / 4;
     uint32_t c = 0;
-    for (uint32_t k = lane; k < nB; k += 64) c += row[k] != 0 ? 1 : 0;
+#pragma unroll 4
+    for (uint32_t q = lane; q < nq; q += 64) c += nz4(row8[q]);
+    for (uint32_t k = nq * 4 + lane; k < nB; k += 64) c += row[k] != 0 ? 1 : 0;
     for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
     if (lane == 0) cnt[o.pos] = c + (o.top ? 1 : 0);
 }
 
+// One wave per output row: each lane takes a chunk of four entries, and the
+// wave's exclusive prefix sum of the chunks' nonzero counts places them.
 __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
                                                   const uint32_t *__restrict__ col_perm,
                                                   const uint16_t *__restrict__ Xp, uint64_t ldx,
@@ -164,28 +179,54 @@ __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
                                                   const uint32_t *__restrict__ pivcol,
                                                   const uint64_t *__restrict__ row_ptr,
                                                   uint32_t *ocol, uint16_t *oval) {
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
     const uint32_t r = *d_rank;
     if (j >= npiv + r) return;
     OutRow o = out_row(j, npiv, r, col_perm, pivcol);
     const uint16_t *row = o.top ? Xp + (uint64_t)o.src * ldx : RD + (uint64_t)o.src * ldd;
+    const gu64 *row8 = (const gu64 *)row;
+    const uint32_t *perm = col_perm + npiv;
     uint64_t out = row_ptr[o.pos];
     if (o.top) {
         if (lane == 0) { ocol[out] = o.pivot; oval[out] = 1; }
         out++;
     }
-    for (uint32_t k0 = 0; k0 < nB; k0 += 64) {
-        const uint32_t k = k0 + lane;
+    const uint32_t nq = nB / 4;
+    for (uint32_t q0 = 0; q0 < nq; q0 += 64) {
+        const uint32_t q = q0 + lane;
+        const uint64_t v = q < nq ? row8[q] : 0;
+        const uint32_t n = nz4(v);
+        uint32_t incl = n;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(incl, d, 64);
+            if (lane >= (uint32_t)d) incl += t;
+        }
+        uint64_t at = out + incl - n;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t x = (uint32_t)(v >> (16 * e)) & 0xffffu;
+            if (x) {
+                ocol[at] = perm[4 * q + e];
+                oval[at] = (uint16_t)x;
+                at++;
+            }
+        }
+        out += __shfl(incl, 63, 64);
+    }
+    // the nB % 4 entries past the last chunk
+    {
+        const uint32_t k = nq * 4 + lane;
         const uint32_t x = k < nB ? row[k] : 0;
         const uint64_t mask = __ballot(x != 0);
         const uint64_t below = lane == 0 ? 0 : (mask & (~(uint64_t)0 >> (64 - lane)));
         if (x) {
             const uint64_t at = out + __popcll(below);
-            ocol[at] = col_perm[npiv + k];
+            ocol[at] = perm[k];
             oval[at] = (uint16_t)x;
         }
-        out += __popcll(mask);
     }
 }
 
@@ -319,8 +360,10 @@ static fl_status csr_count_scan(const fl_split_info *info, const fl_split_out *s
     FL_ARG(row_ptr && d_rank, "fl_rref_csr_size: NULL argument");
     const uint32_t npiv = info->npiv, nB = info->nB;
     const uint32_t maxr = info->mD < nB ? info->mD : nB;
-    FL_ARG(npiv == 0 || nB == 0 || (Xp && ldx >= nB), "fl_rref_csr_size: bad X'");
-    FL_ARG(maxr == 0 || (RD && d_pivcol && ldd >= nB), "fl_rref_csr_size: bad R_D");
+    FL_ARG(npiv == 0 || nB == 0 || (Xp && ldx >= nB && ldx % 4 == 0 && ((uintptr_t)Xp & 7) == 0),
+           "fl_rref_csr_size: bad X' (NULL, ldx < nB, ldx % 4, or not 8-byte aligned)");
+    FL_ARG(maxr == 0 || (RD && d_pivcol && ldd >= nB && ldd % 4 == 0 && ((uintptr_t)RD & 7) == 0),
+           "fl_rref_csr_size: bad R_D (NULL, ldd < nB, ldd % 4, or not 8-byte aligned)");
     CsrWs c;
     size_t need = csr_layout(npiv, maxr, ws, &c);
     if (!ws || ws_bytes < need) {
@@ -393,6 +436,10 @@ extern "C" fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_ou
     const size_t nrows_max = (size_t)npiv + maxr;
     if (nrows_max == 0) return FL_OK;
     FL_ARG(col && val, "fl_rref_to_csr: NULL col/val");
+    FL_ARG(npiv == 0 || nB == 0 || (Xp && ldx >= nB && ldx % 4 == 0 && ((uintptr_t)Xp & 7) == 0),
+           "fl_rref_to_csr: bad X' (NULL, ldx < nB, ldx % 4, or not 8-byte aligned)");
+    FL_ARG(maxr == 0 || (RD && d_pivcol && ldd >= nB && ldd % 4 == 0 && ((uintptr_t)RD & 7) == 0),
+           "fl_rref_to_csr: bad R_D (NULL, ldd < nB, ldd % 4, or not 8-byte aligned)");
     hipLaunchKernelGGL(k_csr_emit, dim3((unsigned)((nrows_max + 3) / 4)), dim3(256), 0, stream, npiv,
                        nB, (const uint32_t *)s->col_perm, Xp, ldx, RD, ldd, d_rank, d_pivcol,
                        row_ptr, col, val);
