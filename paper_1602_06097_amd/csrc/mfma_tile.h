@@ -292,11 +292,11 @@ __device__ __forceinline__ void rankk_rows(const int8_t *__restrict__ Ah, const 
     }
 }
 
-// One 128-column tile bx of the row block set up by rankk_rows (sv: 64 RT
-// rows of kRank64Ld residues).  Callers looping over column tiles must
+// One column tile bx (16 NJ columns, NJ = 8 or 4) of the row block set up by
+// rankk_rows (sv: 64 RT rows of kRank64Ld residues).  Callers looping over column tiles must
 // synchronise between tiles (sv is reused).  Each B fragment feeds the RT
 // row tiles of the wave.
-template <int KS, int RT = 1>
+template <int KS, int RT = 1, int NJ = 8>
 __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                            const RankkRows<KS, RT> &R, const int8_t *__restrict__ Bh,
                                            const int8_t *__restrict__ Bl, uint32_t ldb, uint16_t *C, uint64_t ldc,
@@ -307,16 +307,18 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     typedef __attribute__((address_space(1))) uint64_t gu64w;
     typedef __attribute__((address_space(1))) const v4i gv4i;
     constexpr int kLd = kRank64Ld;
-    constexpr int kChunks = 8 * RT;  // C chunks of 4 columns per thread
+    static_assert(NJ == 8 || NJ == 4, "128 or 64 columns per tile");
+    constexpr int kCpr = 4 * NJ;        // C chunks of 4 columns per row
+    constexpr int kChunks = NJ * RT;    // C chunks per thread
     (void)c16;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t n0 = bx * 128;
-    // C tile: 64 RT rows x 32 chunks of 4 columns; every load is issued
+    const uint32_t n0 = bx * 16 * NJ;
+    // C tile: 64 RT rows x kCpr chunks of 4 columns; every load is issued
     // (chunks outside the tile read C[0])
     uint64_t cv[kChunks];
 #pragma unroll
     for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t ch = tid + u * 256, r = ch / kCpr, c4 = (ch % kCpr) * 4;
         const uint32_t row = rows_s[r], col = n0 + c4;
         const bool ok = row != 0xffffffffu && col + 4 <= N;
         cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
@@ -333,9 +335,9 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     const LimbCombine lc = limb_combine(md);
     (void)bias;
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < NJ; j++) {
         const int cur = j & 1, nxt = cur ^ 1;
-        if (j + 1 < 8) {
+        if (j + 1 < NJ) {
 #pragma unroll
             for (int s = 0; s < KS; s++) {
                 const uint64_t b = (uint64_t)(n0 + (j + 1) * 16 + cl) * ldb + s * 64 + kq;
@@ -366,7 +368,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * 256, r = ch >> 5, c4 = (ch & 31) * 4;
+        const uint32_t ch = tid + u * 256, r = ch / kCpr, c4 = (ch % kCpr) * 4;
         const uint32_t row = rows_s[r], col = n0 + c4;
         if (row == 0xffffffffu || col >= N) continue;
         const uint64_t s4 = *(const uint64_t *)(sv + r * kLd + c4);
@@ -386,7 +388,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
 }
 
 
-template <int KS>
+template <int KS, int NJ = 8>
 __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                 const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
                                                 uint32_t lda, const int8_t *__restrict__ Bh,
@@ -396,7 +398,7 @@ __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias
                                                 uint32_t *rows_s) {
     RankkRows<KS> R;
     rankk_rows<KS>(Ah, Al, lda, row_map, M, by, rows_s, R);
-    rankk_cols<KS>(md, bias, c16, R, Bh, Bl, ldb, C, ldc, N, bx, sv, rows_s);
+    rankk_cols<KS, 1, NJ>(md, bias, c16, R, Bh, Bl, ldb, C, ldc, N, bx, sv, rows_s);
 }
 
 // K <= 64 with 64-byte A rows and B columns.

@@ -571,8 +571,10 @@ __global__ __launch_bounds__(256) void k_trsm_update_mfma_b(fl::Mod md, uint32_t
 
 // Near update of block [r0, r1) (single matrix): X[r0:r1] -= A[r0:r1, r1:r1 + 64 KS]
 // X[r1:r1 + 64 KS] from the limb planes (the band is zero past the block's
-// entries), one 64-row x 128-column tile per workgroup, operands read
-// straight from global memory (K is at most 384: no LDS ring needed).
+// entries), one 64-row x 64-column tile per workgroup, operands read
+// straight from global memory (K is at most 384: no LDS ring needed).  The
+// narrow tiles give four workgroups per unit: the kernel is bound by the
+// latency of its operand loads, which more workgroups in flight overlap.
 template <int KS>
 __global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, uint32_t c16, const int8_t *Ah,
                                                    const int8_t *Al, const int8_t *Xh, const int8_t *Xl,
@@ -580,15 +582,15 @@ __global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, ui
                                                    uint64_t ldx, uint32_t nB) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
-    fl_mfma::mfma_rankk_tile<KS>(md, bias, c16, Ah + (uint64_t)r0 * kp + r1, Al + (uint64_t)r0 * kp + r1,
-                                 (uint32_t)kp, Xh + r1, Xl + r1, (uint32_t)kp, nullptr, r1 - r0,
-                                 X + (uint64_t)r0 * ldx, ldx, nB, blockIdx.x, blockIdx.y, sv, rows_s);
+    fl_mfma::mfma_rankk_tile<KS, 4>(md, bias, c16, Ah + (uint64_t)r0 * kp + r1, Al + (uint64_t)r0 * kp + r1,
+                                    (uint32_t)kp, Xh + r1, Xl + r1, (uint32_t)kp, nullptr, r1 - r0,
+                                    X + (uint64_t)r0 * ldx, ldx, nB, blockIdx.x, blockIdx.y, sv, rows_s);
 }
 
 hipError_t trsm_near(uint32_t ks, const fl::Mod &md, uint32_t p, const int8_t *Ah, const int8_t *Al,
                      const int8_t *Xh, const int8_t *Xl, uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
                      uint64_t ldx, uint32_t nB, hipStream_t s) {
-    const dim3 grid((nB + 127) / 128, (r1 - r0 + 63) / 64);
+    const dim3 grid((nB + 63) / 64, (r1 - r0 + 63) / 64);
     const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
 #define FL_NEAR(K)                                                                                         \
     case K:                                                                                                \
