@@ -756,17 +756,20 @@ __global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bi
                                                          uint32_t P) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
-    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x >> 1), bx = blockIdx.x & 1;
+    // four 64-column tiles per matrix (the panel's block has at most 256
+    // columns from the panel on): more workgroups in flight on this
+    // latency-bound step
+    const uint32_t ti = fl_task_of(pre, ntask, blockIdx.x >> 2), bx = blockIdx.x & 3;
     const FlEchTask &t = tasks[ids[ti]];
     if (P >= t.npanels) return;
     const uint32_t M = t.counts[3 * P + 2];
     if (blockIdx.y * 64 >= M || panel_state(t, P)->k == 0) return;
     const uint32_t c0 = P * kPanel, b = P / kBlockPanels, bend = (b + 1) * kBlock;
     const uint32_t N = (bend < t.cols ? bend : t.cols) - c0;
-    if (bx * 128 >= N) return;
+    if (bx * 64 >= N) return;
     const uint64_t half = (uint64_t)(b & 1) * t.rows * kBlock, slot = (P % kBlockPanels) * kPanel;
-    fl_mfma::mfma_rankk_tile<1>(md, bias, c16, t.Lbh + half + slot, t.Lbl + half + slot, kBlock, t.Uh, t.Ul, 64,
-                                t.upd_rows, M, t.D + c0, t.ld, N, bx, blockIdx.y, sv, rows_s);
+    fl_mfma::mfma_rankk_tile<1, 4>(md, bias, c16, t.Lbh + half + slot, t.Lbl + half + slot, kBlock, t.Uh, t.Ul,
+                                   64, t.upd_rows, M, t.D + c0, t.ld, N, bx, blockIdx.y, sv, rows_s);
 }
 
 // The same, VALU form: every row, one 256-column tile per matrix, row blocks
@@ -1255,7 +1258,7 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g.n_mfma) {
         FL_PROF("echelon.mfma", stream,
-                hipLaunchKernelGGL(k_ech_update_mfma, dim3(2 * g.n_mfma, mfma_y), dim3(256), 0, stream, md,
+                hipLaunchKernelGGL(k_ech_update_mfma, dim3(4 * g.n_mfma, mfma_y), dim3(256), 0, stream, md,
                                    fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma,
                                    at(L.pre_n_mfma, P, L.n_mfma), L.n_mfma, P));
         if ((e = hipGetLastError()) != hipSuccess) return e;
