@@ -1156,11 +1156,10 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
 
 // Far-part kernels reserve this much LDS per workgroup (the rest of what
 // they use as dynamic shared memory), so that at most 2 of them share a
-// compute unit and every unit keeps room for one 1024-thread block of the
-// pivot search (its 25 KB of LDS, 4 waves per SIMD and their registers next
-// to two 160-register waves): otherwise the far part, thousands of
-// workgroups per launch, fills the chip and the search, one workgroup on the
-// critical path, waits for a free unit.
+// compute unit: the main stream's kernels (the pivot search is a single
+// 1024-thread workgroup on the critical path) then get a unit as soon as a
+// far workgroup on it finishes, instead of queueing behind a chip filled
+// with thousands of far workgroups.
 constexpr uint32_t kFarLds = 64 * 1024;
 // column tiles walked by one workgroup of the block update: at most this
 // many workgroups per row block
@@ -1179,15 +1178,15 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<256>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<1024>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
-    // the next block's columns are on the critical path: 16 waves per 64
-    // columns there; the far part keeps 4 (and its LDS reservation)
+    // 16 waves per 64 columns (the entries of the bracket and the rows of U
+    // dealt to the waves); the far part also takes the LDS reservation
     if (far)
         FL_PROF("echelon.ublk_far", s,
-                hipLaunchKernelGGL(k_ech_ublk<256>, dim3(g_all), dim3(256), dyn_u, s, md, tasks, L.ids_all, pa,
+                hipLaunchKernelGGL(k_ech_ublk<1024>, dim3(g_all), dim3(1024), dyn_u, s, md, tasks, L.ids_all, pa,
                                    L.n_all, B, lo, span));
     else
         FL_PROF("echelon.ublk", s,
