@@ -154,6 +154,9 @@ bool fl_prof_set(bool on);
 //   block ranges krange_n[2*nb..2*nb+1] (intersected; all-zero blocks of the
 //   operands are skipped), and output row map (~0u = no output row).
 // A must have round_up(M, 128) readable rows, B round_up(N, 128).
+// group_m: 0 = tiles in grid order; g > 0 = each XCD takes a contiguous
+// range of tiles, walked column by column in groups of g row tiles (the
+// row tiles that share a B column tile run together on one XCD's L2).
 struct GemmPlanes {
     const int8_t *Ah, *Al, *Bh, *Bl;
     uint64_t lda, ldb;
@@ -166,6 +169,7 @@ struct GemmPlanes {
     uint16_t *C;
     uint64_t ldc;
     uint32_t M, N;
+    uint32_t group_m;
 };
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
 // A second stream and two events for work that overlaps the caller's stream,

@@ -67,10 +67,32 @@ __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *
     }
 }
 
+// The tile of this workgroup under GemmPlanes::group_m.  Workgroups are
+// dispatched x fastest and dealt round-robin to the 8 XCDs; the linear
+// dispatch index is renumbered so that every XCD receives a contiguous
+// range, which is walked column tile by column tile in groups of gm row
+// tiles.  Both steps are bijections of the grid.
+__device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t &bx, uint32_t &by) {
+    const uint32_t nx = gridDim.x, ny = gridDim.y;
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    if (gm == 0) return;
+    const uint32_t total = nx * ny, pid = by * nx + bx;
+    const uint32_t q = total / 8, r = total % 8, x = pid % 8, i = pid / 8;
+    const uint32_t id = x * q + (x < r ? x : r) + i;
+    const uint32_t per = gm * nx, group = id / per, first = group * gm;
+    const uint32_t rows = ny - first < gm ? ny - first : gm;
+    const uint32_t within = id - group * per;
+    by = first + within % rows;
+    bx = within / rows;
+}
+
 __global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
                                                    GemmPlanes g) {
     __shared__ __attribute__((aligned(16))) int8_t smem[kGemmLds];
-    mfma_gemm_tile(md, bias, c16, g, blockIdx.x, blockIdx.y, smem);
+    uint32_t bx, by;
+    gemm_tile_of(g.group_m, bx, by);
+    mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
 }
 
 // Rank-k update, k <= 64: one 64-row x 128-column tile per workgroup; row

@@ -1155,6 +1155,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                     GemmPlanes gp = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp,
                                      t.kp, R1, R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr,
                                      nullptr, X + (uint64_t)rt * ldx, ldx, R1 - rt, nB};
+                    gp.group_m = kFlTrsmSuper;  // the superblock's row tiles share each B column tile
                     e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
                 } else {  // near update: the blocks of the superblock solved since
                     FL_PROF("trsm.update.near", stream,
