@@ -87,7 +87,7 @@ __device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t &bx, uint32_t
     bx = within / rows;
 }
 
-__global__ __launch_bounds__(256) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
+__global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
                                                    GemmPlanes g) {
     __shared__ __attribute__((aligned(16))) int8_t smem[kGemmLds];
     uint32_t bx, by;
@@ -159,7 +159,7 @@ hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, 
     const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
     const uint32_t c16 = (uint32_t)((1u << 16) % p);
     dim3 grid((gp.N + BN - 1) / BN, (gp.M + BM - 1) / BM);
-    FL_PROF(site, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, gp));
+    FL_PROF(site, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp));
     return hipGetLastError();
 }
 
@@ -218,7 +218,7 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
         GemmPlanes gp = {w.Ah, w.Al, w.Bh, w.Bl, w.Kp, w.Kp, 0, 0, kb, ke, Kdev, nullptr, nullptr,
                          nullptr, C, ldc, M, N};
-        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(256), 0, s, md, bias, c16, gp));
+        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -70,15 +70,19 @@ __device__ __forceinline__ uint32_t combine_limbs(const LimbCombine &c, int hh, 
 inline uint32_t gemm_bias(uint32_t p) { return (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p); }
 inline uint32_t gemm_c16(uint32_t p) { return (uint32_t)((1u << 16) % p); }
 
-// 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 outputs per wave as
-// 4 x 4 tiles of 16 x 16.  The next K-tile is loaded into registers while
-// the current one is multiplied, so global latency overlaps the MFMAs.
+// One 128 x 128 output tile per workgroup of kGemmThreads = 512 threads: 8
+// waves in a 2 x 4 arrangement, 64 x 32 outputs per wave as 4 x 2 tiles of
+// 16 x 16 (three int32 accumulators each: 96 registers), so two waves share
+// each SIMD and one wave's MFMAs cover the other's waits.
+constexpr int kGemmThreads = 512;
+
 __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                const GemmPlanes &g, uint32_t bx, uint32_t by,
                                                int8_t *smem) {
     static_assert(BM * kOutLd * 2 <= kGemmLds, "epilogue tile must fit the operand buffers");
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t wm = wave >> 1, wn = wave & 1;
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
+    const uint32_t wm = wave >> 2, wn = wave & 3;
     const uint32_t m0 = by * BM, n0 = bx * BN;
     // C row of each tile row (0xffffffff: past M or unmapped), read by the
     // epilogue after its barrier
@@ -101,106 +105,140 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         const uint32_t kd = (*g.klen_dev + BK - 1) / BK * BK;
         if (kend > kd) kend = kd;
     }
-    v4i acc_hh[4][4], acc_mid[4][4], acc_ll[4][4];
+    v4i acc_hh[4][2], acc_mid[4][2], acc_ll[4][2];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < 2; j++) {
             acc_hh[i][j] = v4i{0, 0, 0, 0};
             acc_mid[i][j] = v4i{0, 0, 0, 0};
             acc_ll[i][j] = v4i{0, 0, 0, 0};
         }
     // Operand pipeline: the four plane tiles of a K step (128 rows x 64 bytes
-    // each) are copied global -> LDS by the DMA path (global_load_lds, no
-    // registers involved) into a ring of kStages slots, issued kStages - 1
-    // steps ahead, so HBM latency is covered by several steps of MFMA work.
-    // A wave's DMA instruction fills a 1 KiB block (16 rows x 4 chunks of 16
-    // bytes, lane L -> row L / 4, slot L % 4); chunk c of row r sits in slot
-    // c ^ ((r >> 2) & 3) so that the 16-row reads below hit all LDS banks.
+    // each, 32 blocks of 16 rows) are copied global -> LDS by the DMA path
+    // (global_load_lds, no registers involved) into a ring of kStages slots,
+    // issued kStages - 1 steps ahead.  Wave w fills blocks 4 (w & 1) .. + 3
+    // of plane w / 2, one 1 KiB block per instruction (lane L -> row L / 4,
+    // slot L % 4); chunk c of row r sits in slot c ^ ((r >> 2) & 3) so that
+    // the 16-row reads below hit all LDS banks.
     const uint32_t ring = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int8_t *)smem;
     const uint32_t lrow = lane >> 2, lslot = lane & 3;
-    uint64_t goff[8];      // per DMA instruction of this wave: plane row offset + chunk
-    const int8_t *gbase[8];
-    uint32_t loff[8];      // LDS offset of the instruction's block within a slot
+    const uint32_t plane = wave >> 1;
+    // (selected with masks: a select among the kernel argument's fields by a
+    // runtime index would be compiled into a private-memory table)
+    const uint64_t m_a = plane < 2 ? ~0ull : 0ull;
+    const uint64_t pld = (g.lda & m_a) | (g.ldb & ~m_a);
+    const uint64_t poff = (uint64_t)(((uint64_t)m0 & m_a) | ((uint64_t)n0 & ~m_a)) * pld +
+                          (((uint64_t)g.a_k0 & m_a) | ((uint64_t)g.b_k0 & ~m_a));
+    const uint64_t m_lo = (plane & 1) ? 0ull : ~0ull;
+    const uint64_t p_a = ((uint64_t)(uintptr_t)g.Ah & m_lo) | ((uint64_t)(uintptr_t)g.Al & ~m_lo);
+    const uint64_t p_b = ((uint64_t)(uintptr_t)g.Bh & m_lo) | ((uint64_t)(uintptr_t)g.Bl & ~m_lo);
+    const int8_t *const pbase = (const int8_t *)(uintptr_t)(((p_a & m_a) | (p_b & ~m_a)) + poff);
+    uint64_t goff[4];  // the lane's offset in the plane tile, per instruction
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const uint32_t plane = i >> 1, rb = wave * 2 + (i & 1);
-        const uint32_t r = rb * 16 + lrow;
-        const uint32_t c = lslot ^ ((r >> 2) & 3);
-        const bool isA = plane < 2;
-        gbase[i] = plane == 0 ? g.Ah : plane == 1 ? g.Al : plane == 2 ? g.Bh : g.Bl;
-        goff[i] = isA ? (uint64_t)(m0 + r) * g.lda + g.a_k0 + c * 16 : (uint64_t)(n0 + r) * g.ldb + g.b_k0 + c * 16;
-        loff[i] = plane * kPlaneBytes + rb * 1024;
+    for (int i = 0; i < 4; i++) {
+        const uint32_t r = ((wave & 1) * 4 + i) * 16 + lrow;
+        goff[i] = (uint64_t)r * pld + (uint32_t)((lslot ^ ((r >> 2) & 3)) * 16);
     }
     // one K step into ring slot `slot` (steps past kend re-read the last valid
-    // step, so every step issues the same 8 instructions per wave)
+    // step, so every step issues the same 4 instructions per wave)
     auto issue = [&](uint32_t k0, uint32_t slot) {
         const uint32_t kk = k0 < kend ? k0 : kend - BK;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int8_t *src = gbase[i] + goff[i] + kk;
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kStageBytes + loff[i]);
+        for (int i = 0; i < 4; i++) {
+            const int8_t *src = pbase + goff[i] + kk;
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kStageBytes + plane * kPlaneBytes +
+                                                                ((wave & 1) * 4 + i) * 1024);
             asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory");
         }
     };
-    if (kbeg < kend) {
-#pragma unroll
-        for (uint32_t s = 0; s + 1 < kStages; s++) issue(kbeg + s * BK, s);
-    }
-    uint32_t slot = 0;
-    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
-        // this step's slot is complete when at most the (kStages - 2) later
-        // steps' instructions are outstanding; the barrier extends that to
-        // every wave's instructions and retires the reads of the slot
-        // refilled next
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 2) * 8) : "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        issue(k0 + (kStages - 1) * BK, slot == 0 ? kStages - 1 : slot - 1);
+    // The wave's fragments of a step: A row tiles (4 of 16 rows) and B column
+    // tiles (2 of 16 columns), both limb planes, 16 bytes of K per lane.
+    const uint32_t kc = lane >> 4;
+    auto read_ops = [&](uint32_t slot, v4i (&ah)[4], v4i (&al)[4], v4i (&bh)[2], v4i (&bl)[2]) {
         const int8_t *st = smem + slot * kStageBytes;
-        v4i ah[4], al[4], bh[4], bl[4];
-        const uint32_t kc = lane >> 4;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
-            const uint32_t rb = wn * 64 + t * 16 + (lane & 15);
             const uint32_t oa = ra * 64 + ((kc ^ ((ra >> 2) & 3)) << 4);
-            const uint32_t ob = rb * 64 + ((kc ^ ((rb >> 2) & 3)) << 4);
             ah[t] = *(const v4i *)(st + oa);
             al[t] = *(const v4i *)(st + kPlaneBytes + oa);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const uint32_t rb = wn * 32 + t * 16 + (lane & 15);
+            const uint32_t ob = rb * 64 + ((kc ^ ((rb >> 2) & 3)) << 4);
             bh[t] = *(const v4i *)(st + 2 * kPlaneBytes + ob);
             bl[t] = *(const v4i *)(st + 3 * kPlaneBytes + ob);
         }
+    };
+    auto next = [](uint32_t slot) { return slot + 1 == kStages ? 0u : slot + 1; };
+    auto prev = [](uint32_t slot) { return slot == 0 ? kStages - 1 : slot - 1; };
+    // The fragments of step j + 1 are read during step j (into the second
+    // register set, copied over after the MFMAs), so the LDS reads overlap
+    // the MFMAs.  Step j's iteration waits for step j + 1's slot (at most the
+    // kStages - 3 later steps' instructions outstanding); the barrier also
+    // retires every wave's reads of step j - 1's slot, which is refilled next.
+    v4i ah[4], al[4], bh[2], bl[2], nah[4], nal[4], nbh[2], nbl[2];
+    uint32_t slot = 0;  // ring slot of step k0
+    if (kbeg < kend) {
+#pragma unroll
+        for (uint32_t s = 0; s + 1 < kStages; s++) issue(kbeg + s * BK, s);
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 2) * 4) : "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        read_ops(0, ah, al, bh, bl);
+    }
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 3) * 4) : "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        issue(k0 + (kStages - 1) * BK, prev(slot));
+        const bool more = k0 + BK < kend;
+        if (more) read_ops(next(slot), nah, nal, nbh, nbl);
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < 2; j++) {
                 acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
                 acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
                 acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
                 acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
             }
-        slot = slot + 1 == kStages ? 0 : slot + 1;
+        if (more) {
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                ah[t] = nah[t];
+                al[t] = nal[t];
+            }
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                bh[t] = nbh[t];
+                bl[t] = nbl[t];
+            }
+        }
+        slot = next(slot);
     }
     // drain the DMA path before the ring is reused for the output tile
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (kbeg >= kend) return;  // nothing to subtract
-    // the C tile (128 rows x 32 chunks of 4 columns, 16 chunks per thread) is
+    // the C tile (128 rows x 32 chunks of 4 columns, 8 chunks per thread) is
     // loaded before the residues are formed, so its latency overlaps that
     // work; every load is issued (chunks outside the tile read C[0])
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) uint64_t gu64w;
-    uint64_t cvals[16];
+    constexpr int kChunks = BM * (BN / 4) / kGemmThreads;
+    uint64_t cvals[kChunks];
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        const uint32_t ch = tid + u * 256, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+    for (int u = 0; u < kChunks; u++) {
+        const uint32_t ch = tid + u * kGemmThreads, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
         const uint32_t orow = rows_s[r], col = n0 + c4;
         const bool ok = orow != 0xffffffffu && col + 4 <= g.N;
         cvals[u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
     }
     // epilogue: residues of the 128 x 128 tile go through LDS (the operand
-    // buffers are free now), then C is read, reduced and written back with
+    // buffers are free now), then C is reduced and written back with
     // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
     // column lane%16) of each 16 x 16 tile is held by the wave.
     uint16_t *sOut = (uint16_t *)smem;
@@ -210,18 +248,19 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint32_t col = wn * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < 2; j++) {
+            const uint32_t col = wn * 32 + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const uint32_t row = wm * 64 + i * 16 + (lane >> 4) * 4 + e;
-                sOut[row * kOutLd + col] = (uint16_t)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
+                sOut[row * kOutLd + col] =
+                    (uint16_t)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
             }
         }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-        const uint32_t ch = tid + u * 256, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+    for (int u = 0; u < kChunks; u++) {
+        const uint32_t ch = tid + u * kGemmThreads, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
         const uint32_t orow = rows_s[r], col = n0 + c4;
         if (orow == 0xffffffffu || col >= g.N) continue;
         uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
@@ -250,9 +289,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 // overlapping the operand loads and MFMAs), residues are staged through LDS
 // and C is written back with 8-byte accesses.  A planes are indexed by the C
 // row (lda bytes per row), B planes by the C column (ldb bytes per column).
-// With K <= 64, |S_hh|, |S_ll| <= 2^20 and |S_mid| <= 2^21, so
-// 256 S_mid + S_ll fits 32 bits and the recombination needs three Barrett
-// reductions; with K <= 384 the three sums are reduced separately.
+// The three limb sums are combined by combine_limbs.
 // One 64-row x 128-column tile (row block by, column block bx) of the
 // update.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in LDS.  Callers looping
 // over row blocks must synchronise between tiles.

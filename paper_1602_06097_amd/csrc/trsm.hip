@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_trsm_update_b(fl::Mod md, const FlTrsmT
 // update (A columns [r1, R1): the blocks solved since).  Workgroups per
 // matrix: ceil(nB / 128) column tiles x kFlTrsmSuper row tiles, local index
 // = row tile * column tiles + column tile.
-__global__ __launch_bounds__(256) void k_trsm_update_mfma_b(fl::Mod md, uint32_t bias, uint32_t c16,
+__global__ __launch_bounds__(fl_mfma::kGemmThreads) void k_trsm_update_mfma_b(fl::Mod md, uint32_t bias, uint32_t c16,
                                                             const FlTrsmTask *__restrict__ tasks,
                                                             const uint32_t *__restrict__ ids,
                                                             const uint32_t *__restrict__ prefix,
@@ -1120,7 +1120,7 @@ hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTa
     } else if (step == 0) {
         return hipSuccess;  // the bottom blocks have nothing below them
     } else if (kind == 1) {
-        hipLaunchKernelGGL(k_trsm_update_mfma_b, dim3(grid), dim3(256), 0, stream, md, fl_mfma::gemm_bias(p),
+        hipLaunchKernelGGL(k_trsm_update_mfma_b, dim3(grid), dim3(fl_mfma::kGemmThreads), 0, stream, md, fl_mfma::gemm_bias(p),
                            fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step);
     } else {
         switch (w) {
