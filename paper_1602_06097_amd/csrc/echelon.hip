@@ -1161,9 +1161,12 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
 // far workgroup on it finishes, instead of queueing behind a chip filled
 // with thousands of far workgroups.
 constexpr uint32_t kFarLds = 64 * 1024;
-// column tiles walked by one workgroup of the block update: at most this
-// many workgroups per row block
-constexpr uint32_t kBlkColGroups = 16;
+// Column tiles walked by one workgroup of the block update: at most this
+// many workgroups per row block.  Many short workgroups rather than few long
+// ones: the main stream's kernels get a compute unit whenever a far
+// workgroup finishes, so short far workgroups keep the critical path moving
+// (and balance the far kernel's own tail).
+constexpr uint32_t kBlkColGroups = 128;
 
 template <class K>
 uint32_t far_dyn_lds(K kernel) {
