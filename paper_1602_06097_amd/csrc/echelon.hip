@@ -1181,15 +1181,17 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<1024>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
-    // 16 waves per 64 columns (the entries of the bracket and the rows of U
-    // dealt to the waves); the far part also takes the LDS reservation
+    // 16 waves per 64 columns on the critical path (the entries of the
+    // bracket and the rows of U dealt to the waves); the far part takes 8
+    // (and the LDS reservation), which leaves every unit room for the main
+    // stream's waves
     if (far)
         FL_PROF("echelon.ublk_far", s,
-                hipLaunchKernelGGL(k_ech_ublk<1024>, dim3(g_all), dim3(1024), dyn_u, s, md, tasks, L.ids_all, pa,
+                hipLaunchKernelGGL(k_ech_ublk<512>, dim3(g_all), dim3(512), dyn_u, s, md, tasks, L.ids_all, pa,
                                    L.n_all, B, lo, span));
     else
         FL_PROF("echelon.ublk", s,
