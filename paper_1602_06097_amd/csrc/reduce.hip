@@ -229,6 +229,11 @@ fl_status reduce_mfma(const fl_split_info *info, const fl_split_out *s, const ui
     FL_LAUNCH_CHECK("reduce limbs");
     GemmPlanes gp = {r.Ah, r.Al, Xh, Xl, r.kp, ldp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
                      nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
+    // column tiles outer, all row tiles inner (each XCD a range of column
+    // tiles): C's limb planes (every row tile's K range) stay resident in the
+    // last-level cache while X's planes stream through once, instead of X
+    // being re-read by every row tile
+    gp.group_m = 0xffffu;
     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "reduce.mfma"));
     return FL_OK;
 }
