@@ -398,10 +398,13 @@ const char *fl_last_error(void);   /* thread-local; "" if none */
 /* Version string of the device library ("fl-gfx950 <semver>"). */
 const char *fl_version(void);
 
-/* Device self-check of the modular reduction used by every kernel: for each
- * prime in p_list, compares the kernels' reduction of every x in [0, 2^32)
- * against the remainder x % p and returns the number of mismatches through
- * d_mismatch (device, one uint64 per prime).  Diagnostic only. */
+/* Device self-check of the modular reductions used by the kernels: for each
+ * prime in p_list and every x in [0, 2^32), compares the 32-bit reduction of
+ * x with x % p, the fold of an accumulator pair (256 x + y, y = x times an
+ * odd constant mod 2^32) with 64-bit division, and the product of the
+ * residues (x mod 2^16) mod p and (x >> 16) mod p; returns the number of
+ * mismatches through d_mismatch (device, one uint64 per prime).
+ * Diagnostic only. */
 fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count, uint64_t *d_mismatch,
                         hipStream_t stream);
 

@@ -185,7 +185,11 @@ hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t co
     return hipGetLastError();
 }
 
-// ---- self-check of the 32-bit reduction ------------------------------------------
+// ---- self-check of the modular reductions ---------------------------------------
+// Every 32-bit x through reduce32; with it, fold_pair(x, y) against 64-bit
+// division for y = x times an odd constant (a spread of low words over the
+// whole 2^41 range of 256 x + y), and mulmod over the residue pairs (x mod
+// 2^16 mod p, x >> 16 mod p).
 namespace {
 __global__ void k_check_modp(fl::Mod m, uint64_t *mismatch) {
     const uint64_t total = (uint64_t)1 << 32;
@@ -194,6 +198,10 @@ __global__ void k_check_modp(fl::Mod m, uint64_t *mismatch) {
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += nthreads) {
         uint32_t v = (uint32_t)x;
         if (fl::reduce32(v, m) != v % m.p) bad++;
+        const uint32_t y = v * 2654435761u;
+        if (fl::fold_pair(v, y, m) != (uint32_t)((((uint64_t)v << 8) + y) % m.p)) bad++;
+        const uint32_t a = (v & 0xffffu) % m.p, b = (v >> 16) % m.p;
+        if (fl::mulmod(a, b, m) != a * b % m.p) bad++;
     }
     if (bad) atomicAdd((unsigned long long *)mismatch, (unsigned long long)bad);
 }
