@@ -350,8 +350,9 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
 // leading columns is lower triangular, and the reduced basis is T^-1 times
 // the rows (coefficients: T^-1 itself).  It is computed by back
 // substitution in groups of kProbeGroup slots: one wave finishes a group's
-// rows in order (each row reduced against the group's earlier, finished
-// rows), then all waves reduce the later slots against the finished group.
+// rows in order, in registers (each row reduced against the group's
+// earlier, finished rows), then all waves reduce the later slots against
+// the finished group.
 // Reduction against finished rows never changes a later slot's leading
 // entry (finished rows are zero left of their own, larger, leading column),
 // so every pivot's inverse is known from the start.  In the matrices of
@@ -418,15 +419,41 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
     __syncthreads();
     // lane s of wave 0: inverse of slot s's leading entry
     const uint32_t inv = wave == 0 && lane < kr ? fl::invmod(S.Bv[lane][S.Cc[lane]], md) : 0;
+    const uint32_t ccv = S.Cc[lane];  // lane t: Cc[t]
     for (uint32_t g0 = 0; g0 < kr; g0 += kProbeGroup) {
         const uint32_t g1 = g0 + kProbeGroup < kr ? g0 + kProbeGroup : kr;
         if (wave == 0) {
-            for (uint32_t s = g0; s < g1; s++) {
-                uint32_t v = S.Bv[s][lane], g = S.Bg[s][lane];
-                reduce_against(md, v, g, g0, s, S.Bv, S.Bg, S.Cc, lane, true);
-                const uint32_t is = (uint32_t)__builtin_amdgcn_readlane((int)inv, (int)s);
-                S.Bv[s][lane] = (uint16_t)fl::mulmod(v, is, md);
-                S.Bg[s][lane] = (uint16_t)fl::mulmod(g, is, md);
+            // the group's rows in registers (row j = slot g0 + j), finished in
+            // order: row j's multipliers are read from it as it is on entry
+            uint32_t v[kProbeGroup], g[kProbeGroup];
+#pragma unroll
+            for (uint32_t j = 0; j < kProbeGroup; j++) {
+                v[j] = g0 + j < g1 ? S.Bv[g0 + j][lane] : 0;
+                g[j] = g0 + j < g1 ? S.Bg[g0 + j][lane] : 0;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kProbeGroup; j++) {
+                if (g0 + j >= g1) break;
+                uint32_t hv = 0, lv = 0, hg = 0, lg = 0;
+#pragma unroll
+                for (uint32_t t = 0; t < j; t++) {
+                    const int cidx = __builtin_amdgcn_readlane((int)ccv, (int)(g0 + t));
+                    const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)v[j], cidx);
+                    hv = fl::mad24(lam >> 8, v[t], hv);
+                    lv = fl::mad24(lam & 0xffu, v[t], lv);
+                    hg = fl::mad24(lam >> 8, g[t], hg);
+                    lg = fl::mad24(lam & 0xffu, g[t], lg);
+                }
+                const uint32_t is = (uint32_t)__builtin_amdgcn_readlane((int)inv, (int)(g0 + j));
+                v[j] = fl::mulmod(fl::submod(v[j], fl::fold_pair(hv, lv, md), md.p), is, md);
+                g[j] = fl::mulmod(fl::submod(g[j], fl::fold_pair(hg, lg, md), md.p), is, md);
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kProbeGroup; j++) {
+                if (g0 + j < g1) {
+                    S.Bv[g0 + j][lane] = (uint16_t)v[j];
+                    S.Bg[g0 + j][lane] = (uint16_t)g[j];
+                }
             }
         }
         __syncthreads();
