@@ -57,7 +57,7 @@ constexpr uint32_t kSlots = 2 * kBlockPanels;        // panel states kept (two b
 constexpr uint32_t kListCap = 2048;  // LDS row list: room for two 1024-row windows
 constexpr int kGreedyThreads = 1024;
 
-struct PanelState {
+struct __attribute__((aligned(16))) PanelState {
     uint32_t k;            // pivots found in this panel (final)
     uint32_t rank0;        // rank before this panel
     uint32_t nflag;        // rows outside the probe basis' span
@@ -72,6 +72,10 @@ struct PanelState {
     uint16_t Bv[64 * 64];  // raw basis rows (panel part), insertion order
     uint16_t Bg[64 * 64];  // raw basis rows (coefficient part)
 };
+
+static_assert(offsetof(PanelState, Bv) % 16 == 0 && offsetof(PanelState, Bg) % 16 == 0 &&
+                  offsetof(PanelState, G) % 16 == 0,
+              "16-byte copies of the basis planes");
 
 struct EchWs {
     uint32_t *is_piv;   // [rows] 1 once the row is a pivot row
@@ -298,10 +302,16 @@ __device__ void greedy_rows(const fl::Mod &md, const uint16_t *__restrict__ D, u
     __syncthreads();
 }
 
+// The raw basis for check and merge: the kb rows in use of both planes
+// (16-byte chunks; rows past kb are never read), their pivot columns and
+// their rows.
 __device__ void save_raw(const GreedyLds &S, PanelState *ps) {
-    for (uint32_t i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-        ps->Bv[i] = S.Bv[i >> 6][i & 63];
-        ps->Bg[i] = S.Bg[i >> 6][i & 63];
+    const uint32_t nch = S.kb * 8;  // 16-byte chunks per plane
+    for (uint32_t i = threadIdx.x; i < 2 * nch; i += blockDim.x) {
+        const bool gpl = i >= nch;
+        const uint32_t c = gpl ? i - nch : i;
+        const uint4 v = ((const uint4 *)(gpl ? &S.Bg[0][0] : &S.Bv[0][0]))[c];
+        ((uint4 *)(gpl ? ps->Bg : ps->Bv))[c] = v;
     }
     if (threadIdx.x < 64) {
         ps->Cc[threadIdx.x] = S.Cc[threadIdx.x];
@@ -366,41 +376,43 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
     typedef __attribute__((address_space(1))) const uint32_t gu32;
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
-    __shared__ uint32_t s_rep[kPanel];
+    __shared__ unsigned long long s_rep[kPanel];  // (list position << 32) | row
     const FlEchTask &t = tasks[ids[blockIdx.x]];
     if (P >= t.npanels) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
     const uint32_t n = t.counts[3 * P];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (threadIdx.x < kPanel) s_rep[threadIdx.x] = 0xffffffffu;
+    if (threadIdx.x < kPanel) s_rep[threadIdx.x] = ~0ull;
     __syncthreads();
     // the first listed row of every leading column: a chunk of lead entries
-    // is loaded before any is used (the loads overlap)
-    const gu32 *lead = (const gu32 *)t.nzlead;
+    // and list rows is loaded before any is used (the loads overlap), and the
+    // minimum of (position, row) keeps the row with it
+    const gu32 *lead = (const gu32 *)t.nzlead, *list = (const gu32 *)t.nzlist;
     for (uint32_t base = 0; base < n; base += kLeadLoads * blockDim.x) {
-        uint32_t l[kLeadLoads];
+        uint32_t l[kLeadLoads], r[kLeadLoads];
 #pragma unroll
         for (uint32_t u = 0; u < kLeadLoads; u++) {
             const uint32_t i = base + u * blockDim.x + threadIdx.x;
             l[u] = lead[i < n ? i : 0];
+            r[u] = list[i < n ? i : 0];
         }
 #pragma unroll
         for (uint32_t u = 0; u < kLeadLoads; u++) {
             const uint32_t i = base + u * blockDim.x + threadIdx.x;
-            if (i < n) atomicMin(&s_rep[l[u]], i);
+            if (i < n) atomicMin(&s_rep[l[u]], ((unsigned long long)i << 32) | r[u]);
         }
     }
     __syncthreads();
     // slots by leading column, descending (lane 0 takes column 63)
     if (wave == 0) {
         const uint32_t c = kPanel - 1 - lane;
-        const uint32_t at = s_rep[c];
-        const uint64_t have = __ballot(at != 0xffffffffu);
-        if (at != 0xffffffffu) {
+        const unsigned long long at = s_rep[c];
+        const uint64_t have = __ballot(at != ~0ull);
+        if (at != ~0ull) {
             const uint32_t s = (uint32_t)__popcll(have & ((1ull << lane) - 1));
             S.Cc[s] = c;
-            S.Qo[s] = t.nzlist[at];
+            S.Qo[s] = (uint32_t)at;
         }
         if (lane == 0) {
             S.kb = (uint32_t)__popcll(have);
