@@ -427,7 +427,7 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
             }
             for (uint32_t i : ids[1]) {
                 const uint32_t cols = b->mats[i].info.nB;
-                bg.bn_mfma += fl_ech_tiles(cols, bend, kFlEchBlock, 128);
+                bg.bn_mfma += fl_ech_tiles(cols, bend, kFlEchBlock, 64);
                 bg.bf_mfma += fl_ech_tiles(cols, bend + kFlEchBlock, ~0ull, 128);
                 if (cols > bend) bg.mfma_rows = std::max(bg.mfma_rows, b->mats[i].info.mD);
             }

@@ -961,7 +961,7 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 // keeping the row block's multiplier fragments in registers; the workgroups
 // of one blockIdx.y walk the same column tiles together, so each tile of the
 // block's U is fetched into L2 once for all row blocks.
-template <int RT>
+template <int RT, int NJ>
 __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                              const FlEchTask *__restrict__ tasks,
                                                              const uint32_t *__restrict__ ids,
@@ -988,8 +988,8 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
             cur = ti;
         }
         const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
-        fl_mfma::rankk_cols<kBlockPanels, RT>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start,
-                                              t.ld, end - start, cy - pre[ti], sv, rows_s);
+        fl_mfma::rankk_cols<kBlockPanels, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock,
+                                                  t.D + start, t.ld, end - start, cy - pre[ti], sv, rows_s);
         __syncthreads();  // sv is reused by the next tile
     }
 }
@@ -1181,7 +1181,7 @@ hipError_t fl_echelon_prefixes(const FlEchTask *tasks, const FlEchLists &L, uint
         {L.ids_mfma, L.n_mfma, panels, kPanel, 0, all, one, L.pre_n_mfma},
         {L.ids_plain, L.n_plain, panels, kPanel, 0, all, one, L.pre_n_plain},
         {L.ids_all, L.n_all, blocks, kBlock, kBlock, kBlock, 64, L.pre_bn_all},
-        {L.ids_mfma, L.n_mfma, blocks, kBlock, kBlock, kBlock, 128, L.pre_bn_mfma},
+        {L.ids_mfma, L.n_mfma, blocks, kBlock, kBlock, kBlock, 64, L.pre_bn_mfma},
         {L.ids_plain, L.n_plain, blocks, kBlock, kBlock, kBlock, 256, L.pre_bn_plain},
         {L.ids_all, L.n_all, blocks, kBlock, 2 * kBlock, all, 64, L.pre_bf_all},
         {L.ids_mfma, L.n_mfma, blocks, kBlock, 2 * kBlock, all, 128, L.pre_bf_mfma},
@@ -1220,7 +1220,7 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds(k_ech_update_blk_mfma<2>),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8>)),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
@@ -1237,20 +1237,19 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                 hipLaunchKernelGGL(k_ech_ublk<1024>, dim3(g_all), dim3(1024), 0, s, md, tasks, L.ids_all, pa,
                                    L.n_all, B, lo, span));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // the far part (long row loops over many column tiles) takes 32 rows per
-    // wave, so each B fragment feeds two row tiles; the next block's update
-    // (two column tiles, latency bound) keeps 16 rows per wave and twice the
-    // workgroups
+    // the far part takes 32 rows per wave, so each B fragment feeds two row
+    // tiles; the next block's update (256 columns, latency bound) takes 16
+    // rows per wave and 64-column tiles, four times the workgroups
     if (g_mfma && far) {
         FL_PROF("echelon.blk_mfma_far", s,
-                hipLaunchKernelGGL(k_ech_update_blk_mfma<2>,
+                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8>),
                                    dim3((mfma_rows + 127) / 128, std::min(g_mfma, kBlkColGroups)), dim3(256), dyn_m, s,
                                    md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
                                    g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (g_mfma) {
         FL_PROF("echelon.blk_mfma", s,
-                hipLaunchKernelGGL(k_ech_update_blk_mfma<1>,
+                hipLaunchKernelGGL((k_ech_update_blk_mfma<1, 4>),
                                    dim3((mfma_rows + 63) / 64, std::min(g_mfma, kBlkColGroups)), dim3(256), 0, s, md,
                                    fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
                                    g_mfma, B, lo, span));
@@ -1425,7 +1424,7 @@ extern "C" fl_status fl_echelon_d(uint32_t p, uint32_t rows, uint32_t cols, uint
             const uint64_t bend = (uint64_t)(P / kBlockPanels + 1) * kBlock;
             bg.bn_all = fl_ech_tiles(cols, bend, kBlock, 64);
             bg.bf_all = fl_ech_tiles(cols, bend + kBlock, ~0ull, 64);
-            const uint32_t bn = fl_ech_tiles(cols, bend, kBlock, t.mfma ? 128 : 256);
+            const uint32_t bn = fl_ech_tiles(cols, bend, kBlock, t.mfma ? 64 : 256);
             const uint32_t bf = fl_ech_tiles(cols, bend + kBlock, ~0ull, t.mfma ? 128 : 256);
             (t.mfma ? bg.bn_mfma : bg.bn_plain) = bn;
             (t.mfma ? bg.bf_mfma : bg.bf_plain) = bf;
