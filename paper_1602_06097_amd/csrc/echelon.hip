@@ -841,6 +841,7 @@ __global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEch
 struct __attribute__((aligned(16))) UblkLds {
     uint16_t Us[kBlock][64];
     uint16_t Xs[64][64];
+    uint32_t qs[kBlockPanels][64];  // the panels' selected rows (16-wave form)
 };
 
 template <int NT>
@@ -871,6 +872,79 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
     uint32_t kj[kBlockPanels];
 #pragma unroll
     for (uint32_t j = 0; j < kBlockPanels; j++) kj[j] = j < nj ? panel_state(t, P0 + j)->k : 0;
+    if constexpr (NW == 16) {
+        // Every load of the four stages depends only on the panel states, so
+        // all are issued up front, in two rounds: the panels' selected rows
+        // (into LDS) with the rows of G (registers), then each entry's value
+        // and multipliers; the stages then run on registers and LDS only.
+        // Entry s of stage j and row tt of U_j: s, tt = wave + 16 i, i < 4.
+        constexpr uint32_t kE = 64 / NW;
+        for (uint32_t i = threadIdx.x; i < kBlockPanels * 64; i += NT) {
+            const uint32_t j = i >> 6, s = i & 63;
+            S.qs[j][s] = s < kj[j] ? panel_state(t, P0 + j)->Qs[s] : 0;
+        }
+        uint32_t gq[kBlockPanels][kE];
+#pragma unroll
+        for (uint32_t j = 0; j < kBlockPanels; j++)
+#pragma unroll
+            for (uint32_t i = 0; i < kE; i++) {
+                const uint32_t tt = wave + NW * i;
+                gq[j][i] = tt < kj[j] ? panel_state(t, P0 + j)->G[tt * 64 + lane] : 0;
+            }
+        __syncthreads();
+        // stage j's multipliers on the j earlier panels: cf[j (j - 1) / 2 * kE + i j + jj]
+        uint32_t xq[kBlockPanels][kE], cf[kE * kBlockPanels * (kBlockPanels - 1) / 2];
+#pragma unroll
+        for (uint32_t j = 0; j < kBlockPanels; j++)
+#pragma unroll
+            for (uint32_t i = 0; i < kE; i++) {
+                const uint32_t s = wave + NW * i;
+                const uint32_t q = S.qs[j][s < kj[j] ? s : 0];  // row 0 stands in for absent entries
+                xq[j][i] = t.D[(uint64_t)q * t.ld + cc];
+#pragma unroll
+                for (uint32_t jj = 0; jj < j; jj++)
+                    cf[j * (j - 1) / 2 * kE + i * j + jj] = Lb[(uint64_t)q * kBlock + jj * kPanel + lane];
+            }
+#pragma unroll
+        for (uint32_t j = 0; j < kBlockPanels; j++) {
+            const uint32_t k = kj[j];
+            if (k == 0) continue;
+#pragma unroll
+            for (uint32_t i = 0; i < kE; i++) {
+                const uint32_t s = wave + NW * i;
+                if (s >= k) break;
+                uint32_t h = 0, l = 0;
+#pragma unroll
+                for (uint32_t jj = 0; jj < j; jj++) {
+                    const uint32_t cfv = cf[j * (j - 1) / 2 * kE + i * j + jj];
+#pragma unroll 8
+                    for (uint32_t tt = 0; tt < kj[jj]; tt++) {
+                        const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)cfv, (int)tt);
+                        const uint32_t u = S.Us[jj * kPanel + tt][lane];
+                        h = fl::mad24(lam >> 8, u, h);
+                        l = fl::mad24(lam & 0xffu, u, l);
+                    }
+                }
+                S.Xs[s][lane] = (uint16_t)fl::submod(xq[j][i], fl::fold_pair(h, l, md), md.p);
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t i = 0; i < kE; i++) {
+                const uint32_t tt = wave + NW * i;
+                if (tt >= k) break;
+                uint32_t h = 0, l = 0;
+#pragma unroll 8
+                for (uint32_t s2 = 0; s2 < k; s2++) {
+                    const uint32_t gv = (uint32_t)__builtin_amdgcn_readlane((int)gq[j][i], (int)s2);
+                    const uint32_t xv = S.Xs[s2][lane];
+                    h = fl::mad24(gv >> 8, xv, h);
+                    l = fl::mad24(gv & 0xffu, xv, l);
+                }
+                S.Us[j * kPanel + tt][lane] = (uint16_t)fl::fold_pair(h, l, md);
+            }
+            __syncthreads();
+        }
+    } else {
 #pragma unroll
     for (uint32_t j = 0; j < kBlockPanels; j++) {
         const PanelState *ps = panel_state(t, P0 + j);
@@ -925,6 +999,7 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
             S.Us[j * kPanel + tt][lane] = (uint16_t)fl::fold_pair(h, l, md);
         }
         __syncthreads();
+    }
     }
     if (!ok || wave >= 4) return;
     if (t.Ubh) {
