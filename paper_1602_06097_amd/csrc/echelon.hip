@@ -5,21 +5,20 @@
 // For a panel [c0, c0+64):
 //  0. k_ech_check   lists the remaining rows that are nonzero on the panel,
 //     with the first nonzero column of each.
-//  1. k_ech_probe   one block: a greedy basis of one listed row per panel
-//     column that is some row's first nonzero (independent rows),
-//     in reduced form in LDS.  Rows are reduced against the basis in
-//     parallel (multipliers broadcast with v_readlane); a row that stays
-//     nonzero is inserted (normalised), and all waves clear its pivot column
-//     from the older basis rows.  The coefficients G with
-//     G * Dt[Q, panel] = basis are tracked (Q = selected rows).  This is the
-//     paper's parallel structured Gaussian elimination (Sec. 5.1: rows reduced
-//     in parallel against the known pivots, a new pivot added by one worker
-//     at a time) applied to a panel.
+//  1. k_ech_probe   one block: the basis of one listed row per panel
+//     column that is some row's first nonzero (independent rows: their
+//     leading entries form a triangular matrix), in reduced form in LDS by
+//     back substitution.  The coefficients G with G * Dt[Q, panel] = basis
+//     are tracked (Q = selected rows).
 //  2. k_ech_check   every listed row is reduced against that basis in
-//     parallel; rows outside its span are listed again.
-//  3. k_ech_merge   only if a row was listed: the greedy pass continues over
-//     those rows.  The result: pivot columns C (ascending) of the panel,
-//     rows Q, and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
+//     parallel (multipliers broadcast with v_readlane); rows outside its
+//     span are listed again.
+//  3. k_ech_merge   only if a row was listed: a greedy pass over those rows,
+//     the paper's parallel structured Gaussian elimination (Sec. 5.1: rows
+//     reduced in parallel against the known pivots, a new pivot added by one
+//     worker at a time, all waves clearing its column from the older basis
+//     rows).  The result: pivot columns C (ascending) of the panel, rows Q,
+//     and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
 //  4. U = G * Dt[Q, c0:bend)     over the rest of the panel's 256-column block
 //  5. L' = Dt[:, C] - [row = Q_t] (multipliers with the placement of U folded
 //                                  in; 4 and 5 are one launch)
@@ -1030,12 +1029,10 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 }
 
 // Block B's rank-256 update of columns [start, end) (start = 256 (B + 1) +
-// lo), int8 MFMA form: the rows listed for the block, 64 x 128 tiles.  A
-// workgroup owns one row block (blockIdx.x) and walks the column tiles
-// blockIdx.y, blockIdx.y + gridDim.y, ... (`gcols` in all, from the prefix),
-// keeping the row block's multiplier fragments in registers; the workgroups
-// of one blockIdx.y walk the same column tiles together, so each tile of the
-// block's U is fetched into L2 once for all row blocks.
+// lo), int8 MFMA form: the rows listed for the block, tiles of 64 RT rows x
+// 16 NJ columns.  A workgroup owns one row block (blockIdx.x) and walks the
+// column tiles blockIdx.y, blockIdx.y + gridDim.y, ... (`gcols` in all, from
+// the prefix), keeping the row block's multiplier fragments in registers.
 template <int RT, int NJ>
 __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                              const FlEchTask *__restrict__ tasks,

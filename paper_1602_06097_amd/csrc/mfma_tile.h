@@ -281,22 +281,21 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 }
 
 // Rank-k update, k <= 64 KS (Gauss-Jordan panel and block updates, TRSM near
-// updates): KS
-// MFMA K-steps, so the kernel is bound by the read-modify-write of C and its
-// epilogue.  A block owns 64 rows x 128 columns; rows are taken through an
-// optional row list (row_map, M rows: only rows with nonzero multipliers),
-// the C tile is loaded first with row-contiguous 8-byte accesses (latency
-// overlapping the operand loads and MFMAs), residues are staged through LDS
-// and C is written back with 8-byte accesses.  A planes are indexed by the C
-// row (lda bytes per row), B planes by the C column (ldb bytes per column).
-// The three limb sums are combined by combine_limbs.
-// One 64-row x 128-column tile (row block by, column block bx) of the
-// update.  sv: kRank64Ld * 64 u16, rows_s: 64 u32 in LDS.  Callers looping
-// over row blocks must synchronise between tiles.
-// The row block's part of a rank-k tile: its row list entries (rows_s, LDS)
-// and its A fragments, kept in registers for any number of column tiles.
-// A row block of RT x 64 rows: wave w holds the A fragments (both limb
-// planes, K = 64 KS) of its RT row tiles of 16, rows (w RT + rt) 16 + [0, 16).
+// updates): only KS MFMA K-steps, so the kernel is bound by the
+// read-modify-write of C, its epilogue and the latency of its operand loads.
+// A tile is 64 RT rows x 16 NJ columns (RT = 1 or 2, NJ = 8 or 4); rows are
+// taken through an optional row list (row_map, M rows: only rows with
+// nonzero multipliers), the C tile is loaded first with row-contiguous
+// 8-byte accesses (latency overlapping the operand loads and MFMAs),
+// residues are staged through LDS and C is written back with 8-byte
+// accesses.  A planes are indexed by the C row (lda bytes per row), B planes
+// by the C column (ldb bytes per column).  The three limb sums are combined
+// by combine_limbs.  sv: kRank64Ld * 64 RT u16, rows_s: 64 RT u32 in LDS;
+// callers looping over tiles must synchronise between them.
+// rankk_rows sets up the row block (its row list entries and its A
+// fragments, kept in registers for any number of column tiles): wave w holds
+// the A fragments (both limb planes, K = 64 KS) of its RT row tiles of 16,
+// rows (w RT + rt) 16 + [0, 16).
 template <int KS, int RT = 1> struct RankkRows {
     v4i ah[RT][KS], al[RT][KS];
 };
