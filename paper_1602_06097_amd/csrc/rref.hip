@@ -330,6 +330,10 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
         FL_LAUNCH_CHECK("rref ranges");
         GemmPlanes gp = {r.Lh, r.Ll, r.Rh, r.Rl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, d_rank, nullptr,
                          r.krange, nullptr, X, ldx, npiv, nB};
+        // groups of 4 row tiles per column tile on each XCD: the group shares
+        // the column tile's R_D planes in L2 (measured: 4 beats grid order,
+        // 16, and all row tiles per column)
+        gp.group_m = 4;
         FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "rref.mfma"));
     } else {
         dim3 g((maxr + 255) / 256, npiv < 1024 ? npiv : 1024);
