@@ -1105,15 +1105,21 @@ __global__ void k_ech_prefixes(const FlEchTask *__restrict__ tasks, const uint32
     }
 }
 
+// Rows are moved as 8-byte chunks of four entries (D and T rows start
+// 8-byte aligned: ld and ldt are multiples of 4), the cols % 4 entries past
+// the last chunk one by one.
 __global__ __launch_bounds__(256) void k_ech_gather_rows(const uint16_t *__restrict__ D, uint64_t ld,
                                                          uint32_t cols, const uint32_t *__restrict__ piv_row,
                                                          const uint32_t *__restrict__ d_rank,
                                                          uint16_t *T, uint64_t ldt) {
-    const uint32_t r = *d_rank;
+    const uint32_t r = *d_rank, nq = cols / 4;
     for (uint32_t t = blockIdx.y; t < r; t += gridDim.y) {
         const uint32_t src = piv_row[t];
-        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += gridDim.x * blockDim.x)
-            T[(uint64_t)t * ldt + c] = D[(uint64_t)src * ld + c];
+        const uint64_t *s8 = (const uint64_t *)(D + (uint64_t)src * ld);
+        uint64_t *d8 = (uint64_t *)(T + (uint64_t)t * ldt);
+        for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) d8[q] = s8[q];
+        if (blockIdx.x == 0 && threadIdx.x < cols - nq * 4)
+            T[(uint64_t)t * ldt + nq * 4 + threadIdx.x] = D[(uint64_t)src * ld + nq * 4 + threadIdx.x];
     }
 }
 
@@ -1121,10 +1127,14 @@ __global__ __launch_bounds__(256) void k_ech_place_rows(uint16_t *D, uint64_t ld
                                                         uint32_t cols,
                                                         const uint32_t *__restrict__ d_rank,
                                                         const uint16_t *__restrict__ T, uint64_t ldt) {
-    const uint32_t r = *d_rank;
+    const uint32_t r = *d_rank, nq = cols / 4;
     for (uint32_t i = blockIdx.y; i < rows; i += gridDim.y) {
-        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += gridDim.x * blockDim.x)
-            D[(uint64_t)i * ld + c] = i < r ? T[(uint64_t)i * ldt + c] : 0;
+        uint64_t *d8 = (uint64_t *)(D + (uint64_t)i * ld);
+        const uint64_t *s8 = (const uint64_t *)(T + (uint64_t)i * ldt);
+        for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x)
+            d8[q] = i < r ? s8[q] : 0;
+        if (blockIdx.x == 0 && threadIdx.x < cols - nq * 4)
+            D[(uint64_t)i * ld + nq * 4 + threadIdx.x] = i < r ? T[(uint64_t)i * ldt + nq * 4 + threadIdx.x] : 0;
     }
 }
 
@@ -1425,7 +1435,9 @@ fl_status fl_echelon_finish(const FlEchTask &t, hipStream_t stream) {
     if (t.npanels == 0) return FL_OK;
     const uint32_t rows = t.rows, cols = t.cols;
     const uint32_t mn = rows < cols ? rows : cols;
-    const unsigned gx = (cols + 255) / 256 < 64 ? (cols + 255) / 256 : 64;
+    // 8-byte chunks of four columns, at most 16 workgroups of 256 per row
+    // (at least one: it also moves the cols % 4 last entries)
+    const unsigned gq = (cols / 4 + 255) / 256, gx = gq < 1 ? 1 : gq < 16 ? gq : 16;
     hipLaunchKernelGGL(k_ech_gather_rows, dim3(gx, mn < 65535 ? mn : 65535), dim3(256), 0, stream,
                        (const uint16_t *)t.D, t.ld, cols, (const uint32_t *)t.piv_row, (const uint32_t *)t.d_rank,
                        t.T, t.ldu);
