@@ -45,20 +45,33 @@ __global__ __launch_bounds__(256) void k_gather_pivcols(const uint16_t *__restri
 
 // MFMA form: L = X[:, P_D] directly as int8 limb planes (Kp bytes per row,
 // zero for t >= r).
+// Four K entries per thread (kp is a multiple of 64): the limbs of each row
+// are written four bytes at a time.
 __global__ __launch_bounds__(256) void k_gather_pivcols_limbs(uint32_t p, const uint16_t *__restrict__ X,
                                                               uint64_t ldx, uint32_t npiv,
                                                               const uint32_t *__restrict__ d_rank,
                                                               const uint32_t *__restrict__ pivcol,
                                                               int8_t *Lh, int8_t *Ll, uint64_t kp) {
     const uint32_t r = *d_rank;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kp) return;
-    const uint32_t c = t < r ? pivcol[t] : 0;
+    const uint32_t t0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (t0 >= kp) return;
+    uint32_t c[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) c[e] = t0 + e < r ? pivcol[t0 + e] : 0;
     for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) {
-        int h = 0, l = 0;
-        if (t < r) fl_split_limbs(X[(uint64_t)i * ldx + c], p, h, l);
-        Lh[(uint64_t)i * kp + t] = (int8_t)h;
-        Ll[(uint64_t)i * kp + t] = (int8_t)l;
+        uint32_t x[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) x[e] = X[(uint64_t)i * ldx + c[e]];
+        uint32_t hw = 0, lw = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            int h = 0, l = 0;
+            if (t0 + e < r) fl_split_limbs(x[e], p, h, l);
+            hw |= (uint32_t)(h & 0xff) << (8 * e);
+            lw |= (uint32_t)(l & 0xff) << (8 * e);
+        }
+        *(uint32_t *)(Lh + (uint64_t)i * kp + t0) = hw;
+        *(uint32_t *)(Ll + (uint64_t)i * kp + t0) = lw;
     }
 }
 
@@ -311,7 +324,7 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
     if (mode == FL_MFMA_I8) {
         // L = X[:, P_D] and R_D as limb planes; per 128-column tile of X the
         // range of R_D rows that are nonzero there
-        dim3 g((unsigned)((r.kp + 255) / 256), npiv < 1024 ? npiv : 1024);
+        dim3 g((unsigned)((r.kp / 4 + 255) / 256), npiv < 1024 ? npiv : 1024);
         FL_PROF("rref.limbs", stream, {
             hipLaunchKernelGGL(k_gather_pivcols_limbs, g, dim3(256), 0, stream, info->p, (const uint16_t *)X,
                                ldx, npiv, d_rank, d_pivcol, r.Lh, r.Ll, r.kp);
