@@ -146,7 +146,17 @@ __global__ __launch_bounds__(256) void k_count_bd(uint32_t m, const uint64_t *__
     uint32_t npiv = (uint32_t)d.tot[0];
     uint64_t s = rp[i], e = rp[i + 1];
     uint32_t cnt = 0;
-    for (uint64_t k = s + lane; k < e; k += 64) cnt += d.colmap[ci[k]] >= npiv ? 1 : 0;
+    // four entries per lane in flight: the column loads, then the map lookups
+    for (uint64_t k0 = s + lane; k0 < e; k0 += 256) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = k0 + 64 * u < e ? ci[k0 + 64 * u] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t nc = d.colmap[c[u]];
+            cnt += k0 + 64 * u < e && nc >= npiv ? 1 : 0;
+        }
+    }
     for (int dd = 32; dd >= 1; dd >>= 1) cnt += __shfl_xor(cnt, dd, 64);
     if (lane == 0) {
         uint32_t pos = d.rowpos[i];
@@ -262,11 +272,17 @@ __device__ void group_span(const GroupInfo &gi, uint32_t npiv, const uint32_t *r
     for (uint32_t r = gi.r0; r < gi.r1; r++) {
         uint32_t orig = row_perm[r];
         uint64_t s = rp[orig], e = rp[orig + 1];
-        for (uint64_t k = s + threadIdx.x; k < e; k += blockDim.x) {
-            uint32_t nc = d.colmap[ci[k]];
-            if (ml_entry(nc, npiv, gi.is_a, r)) {
-                mn = nc < mn ? nc : mn;
-                mx = nc > mx ? nc : mx;
+        for (uint64_t k0 = s + threadIdx.x; k0 < e; k0 += 4 * (uint64_t)blockDim.x) {
+            uint32_t c[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t nc = d.colmap[c[u]];
+                if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r)) {
+                    mn = nc < mn ? nc : mn;
+                    mx = nc > mx ? nc : mx;
+                }
             }
         }
     }
@@ -295,10 +311,17 @@ __global__ __launch_bounds__(256) void k_ml_count(uint32_t m, uint32_t w,
             for (uint32_t r = gi.r0; r < gi.r1; r++) {
                 uint32_t orig = row_perm[r];
                 uint64_t s = rp[orig], e = rp[orig + 1];
-                for (uint64_t k = s + threadIdx.x; k < e; k += blockDim.x) {
-                    uint32_t nc = d.colmap[ci[k]];
-                    if (ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 && nc - w0 < kWinBits)
-                        atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
+                for (uint64_t k0 = s + threadIdx.x; k0 < e; k0 += 4 * (uint64_t)blockDim.x) {
+                    uint32_t c[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint32_t nc = d.colmap[c[u]];
+                        if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
+                            nc - w0 < kWinBits)
+                            atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
+                    }
                 }
             }
             __syncthreads();
@@ -359,10 +382,17 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, uint32_
         for (uint32_t r = gi.r0; r < gi.r1; r++) {
             uint32_t orig = row_perm[r];
             uint64_t s = rp[orig], e = rp[orig + 1];
-            for (uint64_t k = s + threadIdx.x; k < e; k += blockDim.x) {
-                uint32_t nc = d.colmap[ci[k]];
-                if (ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 && nc - w0 < kWinBits)
-                    atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
+            for (uint64_t k0 = s + threadIdx.x; k0 < e; k0 += 4 * (uint64_t)blockDim.x) {
+                uint32_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t nc = d.colmap[c[u]];
+                    if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
+                        nc - w0 < kWinBits)
+                        atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
+                }
             }
         }
         __syncthreads();
@@ -410,14 +440,25 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, uint32_
             uint32_t orig = row_perm[r];
             uint32_t sc = scale_s[r - gi.r0];
             uint64_t s = rp[orig], e = rp[orig + 1];
-            for (uint64_t k = s + threadIdx.x; k < e; k += blockDim.x) {
-                uint32_t nc = d.colmap[ci[k]];
-                if (ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 && nc - w0 < kWinBits) {
-                    uint32_t off = nc - w0;
-                    uint32_t word = off >> 5, bit = off & 31;
-                    uint32_t idx = pre[word] + __popc(bits[word] & ((1u << bit) - 1));
-                    uint32_t x = gi.is_a ? fl::mulmod(v[k], sc, md) : v[k];
-                    val[(out + idx) * w + (r - gi.r0)] = (uint16_t)x;
+            for (uint64_t k0 = s + threadIdx.x; k0 < e; k0 += 4 * (uint64_t)blockDim.x) {
+                uint32_t c[4], xv[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint64_t k = k0 + u * blockDim.x;
+                    c[u] = k < e ? ci[k] : 0;
+                    xv[u] = k < e ? v[k] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t nc = d.colmap[c[u]];
+                    if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
+                        nc - w0 < kWinBits) {
+                        uint32_t off = nc - w0;
+                        uint32_t word = off >> 5, bit = off & 31;
+                        uint32_t idx = pre[word] + __popc(bits[word] & ((1u << bit) - 1));
+                        uint32_t x = gi.is_a ? fl::mulmod(xv[u], sc, md) : xv[u];
+                        val[(out + idx) * w + (r - gi.r0)] = (uint16_t)x;
+                    }
                 }
             }
         }
