@@ -204,17 +204,28 @@ __global__ __launch_bounds__(256) void k_scatter_bd(uint32_t m, uint32_t p,
     uint64_t out = d.cnt[pos] - bstart;
     uint32_t *oc = top ? b_col : d_col;
     uint16_t *ov = top ? b_val : d_val;
-    for (uint64_t k0 = s; k0 < e; k0 += 64) {
-        uint64_t k = k0 + lane;
-        bool in = k < e;
-        uint32_t nc = in ? d.colmap[ci[k]] : 0;
-        bool take = in && nc >= npiv;
-        uint32_t before = lane_prefix_count(take, lane);
-        if (take) {
-            oc[out + before] = nc - npiv;
-            ov[out + before] = (uint16_t)(top ? fl::mulmod(v[k], scale, md) : v[k]);
+    // four chunks of 64 entries at a time: their loads and map lookups are
+    // issued before the chunks are compacted in order
+    for (uint64_t k0 = s; k0 < e; k0 += 256) {
+        uint32_t c[4], x[4], nc[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint64_t k = k0 + 64 * u + lane;
+            c[u] = k < e ? ci[k] : 0;
+            x[u] = k < e ? v[k] : 0;
         }
-        out += __popcll(__ballot(take));
+#pragma unroll
+        for (int u = 0; u < 4; u++) nc[u] = d.colmap[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const bool take = k0 + 64 * u + lane < e && nc[u] >= npiv;
+            const uint32_t before = lane_prefix_count(take, lane);
+            if (take) {
+                oc[out + before] = nc[u] - npiv;
+                ov[out + before] = (uint16_t)(top ? fl::mulmod(x[u], scale, md) : x[u]);
+            }
+            out += __popcll(__ballot(take));
+        }
     }
 }
 
