@@ -10,7 +10,8 @@
 //   k_csr_count        nonzeros of every output row, stored at the row's
 //                      position in pivot-column order; exclusive scan
 //   k_csr_emit         one wave per output row: pivot 1, then the nonzeros of
-//                      the X' or R_D row (both ascending in original order).
+//                      the X' or R_D row (both ascending in original order),
+//                      staged in LDS up to 256 entries at a time for coalesced stores.
 #include <string>
 
 #include "fl_internal.h"
@@ -182,8 +183,17 @@ __global__ __launch_bounds__(256) void k_csr_count(uint32_t npiv, uint32_t nB,
     if (lane == 0) cnt[o.pos] = c + (o.top ? 1 : 0);
 }
 
+// Orders one wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wave per output row: each lane takes a chunk of four entries, and the
-// wave's exclusive prefix sum of the chunks' nonzero counts places them.
+// wave's exclusive prefix sum of the chunks' nonzero counts places them in an
+// LDS staging run of up to 256 entries, which the wave then stores to the CSR
+// arrays as contiguous, coalesced runs.
 __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
                                                   const uint32_t *__restrict__ col_perm,
                                                   const uint16_t *__restrict__ Xp, uint64_t ldx,
@@ -193,14 +203,18 @@ __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
                                                   const uint64_t *__restrict__ row_ptr,
                                                   uint32_t *ocol, uint16_t *oval) {
     typedef __attribute__((address_space(1))) const uint64_t gu64;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ uint32_t s_col[4][256];
+    __shared__ uint16_t s_val[4][256];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t j = blockIdx.x * 4 + wv;
     const uint32_t r = *d_rank;
     if (j >= npiv + r) return;
     OutRow o = out_row(j, npiv, r, col_perm, pivcol);
     const uint16_t *row = o.top ? Xp + (uint64_t)o.src * ldx : RD + (uint64_t)o.src * ldd;
     const gu64 *row8 = (const gu64 *)row;
     const uint32_t *perm = col_perm + npiv;
+    uint32_t *const sc = s_col[wv];
+    uint16_t *const sv = s_val[wv];
     uint64_t out = row_ptr[o.pos];
     if (o.top) {
         if (lane == 0) { ocol[out] = o.pivot; oval[out] = 1; }
@@ -217,17 +231,24 @@ __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
             const uint32_t t = __shfl_up(incl, d, 64);
             if (lane >= (uint32_t)d) incl += t;
         }
-        uint64_t at = out + incl - n;
+        uint32_t at = incl - n;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const uint32_t x = (uint32_t)(v >> (16 * e)) & 0xffffu;
             if (x) {
-                ocol[at] = perm[4 * q + e];
-                oval[at] = (uint16_t)x;
+                sc[at] = perm[4 * q + e];
+                sv[at] = (uint16_t)x;
                 at++;
             }
         }
-        out += __shfl(incl, 63, 64);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        wave_lds_sync();
+        for (uint32_t i = lane; i < tot; i += 64) {
+            ocol[out + i] = sc[i];
+            oval[out + i] = sv[i];
+        }
+        wave_lds_sync();
+        out += tot;
     }
     // the nB % 4 entries past the last chunk
     {
