@@ -92,9 +92,10 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         rows_s[tid] = row < g.M ? (g.row_map ? g.row_map[row] : row) : 0xffffffffu;
     }
     uint32_t kbeg = g.kbeg, kend = g.kend;
-    if (g.krange) {
-        kbeg = g.krange[2 * by];
-        kend = g.krange[2 * by + 1];
+    if (g.krange) {  // per row block: intersect
+        const uint32_t b = g.krange[2 * by], e = g.krange[2 * by + 1];
+        kbeg = b > kbeg ? b : kbeg;
+        kend = e < kend ? e : kend;
     }
     if (g.krange_n) {  // per column block: intersect
         const uint32_t b = g.krange_n[2 * bx], e = g.krange_n[2 * bx + 1];

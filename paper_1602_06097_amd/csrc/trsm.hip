@@ -483,7 +483,10 @@ __global__ __launch_bounds__(64) void k_trsm_solve(fl::Mod md, const uint64_t *_
 // the A columns at and beyond its end R1 for all its rows in one GEMM; block
 // I's K range there, relative to R1, is [0, r1 + round_up(kext, 64) - R1)
 // (empty when negative); the columns between the block and R1 are the
-// block's near update, after the blocks below it in the superblock.
+// block's near update, after the blocks below it in the superblock.  The
+// single-matrix call splits the far GEMM by K: the columns of the superblock
+// just below (critical path), and the columns past it, which are solved one
+// superblock earlier and are issued then on a second stream.
 __device__ __host__ inline uint32_t trsm_super_end(uint32_t I, uint32_t nblk, uint32_t npiv) {
     const uint32_t s = nblk - 1 - I;                          // step of block I
     const uint32_t bottom = nblk - 1 - s / kFlTrsmSuper * kFlTrsmSuper;  // the superblock's first block
@@ -1141,6 +1144,14 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
     if (st != FL_OK || t.nblk == 0) return st;
     const fl::Mod md = fl::make_mod(info->p);
     const uint32_t npiv = t.npiv, nB = t.nB, w = info->ml_width;
+    // MFMA form: the far update of a superblock is split by K.  The terms
+    // from the superblock just below it are the critical path (main stream);
+    // the terms from the rows below that are ready one superblock earlier and
+    // run on a second stream, overlapping the superblock below's solve.
+    hipStream_t far_s = nullptr;
+    hipEvent_t ev_ready = nullptr, ev_far = nullptr;
+    if (t.mfma) FL_CHECK_ST(fl_aux_stream(1, &far_s, &ev_ready, &ev_far));
+    bool far_pending = false;
     for (uint32_t I = t.nblk; I-- > 0;) {
         const uint32_t r0 = I * kTrsmBlock;
         const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
@@ -1149,14 +1160,38 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
             if (t.mfma) {
                 const uint32_t step = t.nblk - 1 - I, R1 = trsm_super_end(I, t.nblk, npiv);
                 e = hipSuccess;
-                if (step % kFlTrsmSuper == 0) {  // far update of the superblock
+                if (step % kFlTrsmSuper == 0) {
+                    // superblock [rt, R1) (not the bottom one: it has 512 rows
+                    // unless it is the top one); every row at or past R1 is solved
                     const uint32_t top = I >= kFlTrsmSuper - 1 ? I - (kFlTrsmSuper - 1) : 0;
                     const uint32_t rt = top * kTrsmBlock;
+                    const uint32_t R2 = R1 + kFlTrsmSuper * kTrsmBlock < npiv ? R1 + kFlTrsmSuper * kTrsmBlock : npiv;
+                    // wait for its terms from rows at or past R2 (second stream)
+                    if (far_pending) {
+                        FL_HIP(hipStreamWaitEvent(stream, ev_far, 0));
+                        far_pending = false;
+                    }
+                    // its terms from the superblock [R1, R2) below it
                     GemmPlanes gp = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp,
-                                     t.kp, R1, R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr,
+                                     t.kp, R1, R1, 0, (R2 - R1 + 63) / 64 * 64, nullptr, t.krange + 2 * top, nullptr,
                                      nullptr, X + (uint64_t)rt * ldx, ldx, R1 - rt, nB};
                     gp.group_m = kFlTrsmSuper;  // the superblock's row tiles share each B column tile
-                    e = fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma");
+                    FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma"));
+                    // the superblock above [ru, rt): its terms from rows at or past R1,
+                    // issued after the critical-path GEMM, which then does not queue behind it
+                    if (top > 0) {
+                        const uint32_t topu = top >= kFlTrsmSuper ? top - kFlTrsmSuper : 0;
+                        const uint32_t ru = topu * kTrsmBlock;
+                        FL_HIP(hipEventRecord(ev_ready, stream));
+                        FL_HIP(hipStreamWaitEvent(far_s, ev_ready, 0));
+                        GemmPlanes gf = {t.Ah + (uint64_t)ru * t.kp, t.Al + (uint64_t)ru * t.kp, t.Xh, t.Xl, t.kp,
+                                         t.kp, rt, rt, R1 - rt, (uint32_t)(t.kp - rt), nullptr, t.krange + 2 * topu,
+                                         nullptr, nullptr, X + (uint64_t)ru * ldx, ldx, rt - ru, nB};
+                        gf.group_m = kFlTrsmSuper;
+                        FL_HIP(fl_mfma_gemm_planes(info->p, gf, far_s, "trsm.update.far"));
+                        FL_HIP(hipEventRecord(ev_far, far_s));
+                        far_pending = true;
+                    }
                 } else {  // near update: the blocks of the superblock solved since
                     FL_PROF("trsm.update.near", stream,
                             e = trsm_near((R1 - r1 + 63) / 64, md, info->p, t.Ah, t.Al, t.Xh, t.Xl, t.kp, r0, r1,
@@ -1185,5 +1220,6 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         }
         FL_HIP(e);
     }
+    if (far_pending) FL_HIP(hipStreamWaitEvent(stream, ev_far, 0));
     return FL_OK;
 }

@@ -283,6 +283,25 @@ def test_trsm_many_blocks_both_forms():
             assert np.array_equal(u16(X)[:sp.npiv, :sp.nB], r["X"]), (mode, w)
 
 
+def test_trsm_lookahead_far_update():
+    """A band reaching past the superblock below (wide row supports): the
+    MFMA form's far update is split by K between the main stream and a
+    second stream; both parts and their ordering against the block solves
+    are checked, twice in a row (no race between the streams)."""
+    g = flgen.fl_matrix(m=2600, n=3400, npiv=2200, rank_d=200, density=0.06, p=65521, seed=61,
+                        rho_loc=0.05)
+    s = oracle.split(g)
+    Xr = oracle.trsm(s)
+    for mode in MODES:
+        for w in (1, 2):
+            sp = fl.split(*up(g), g["m"], g["n"], g["p"], ml_width=w)
+            X1 = fl.trsm(sp, mode)
+            X2 = fl.trsm(sp, mode)
+            torch.cuda.synchronize()
+            assert np.array_equal(u16(X1)[:sp.npiv, :sp.nB], Xr), (mode, w)
+            assert np.array_equal(u16(X2)[:sp.npiv, :sp.nB], Xr), (mode, w)
+
+
 def test_repeat_runs_identical():
     """Two runs of the whole path give identical bytes (no data races)."""
     g = CASES["planted_ragged"]
