@@ -44,27 +44,46 @@ __global__ __launch_bounds__(256) void k_limbs_rows(uint32_t p, const uint16_t *
 }
 
 // B (K x cols, row-major u16, ldb) -> Bh, Bl transposed (Cp x Kp int8).
+// One workgroup per 64 (K) x 64 (column) tile: rows are read as 8-byte
+// chunks of four columns (entry by entry past cols or where B or ldb is not
+// 8-byte aligned), the limbs are transposed through LDS, and each column's
+// 64 K bytes are written as four 16-byte stores per plane.  Rows k >= K
+// (K read from Kdev when non-NULL) and columns >= cols are zero.
 __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *__restrict__ B,
                                                     uint64_t ldb, uint32_t cols, uint32_t Kh,
                                                     const uint32_t *__restrict__ Kdev,
                                                     int8_t *Bh, int8_t *Bl, uint32_t Kp) {
-    __shared__ int8_t th[64][65], tl[64][65];
+    constexpr uint32_t kLd = 80;  // LDS bytes per column (16-byte aligned rows)
+    __shared__ __attribute__((aligned(16))) int8_t th[64 * kLd], tl[64 * kLd];
     const uint32_t K = Kdev ? *Kdev : Kh;
     const uint32_t k0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-    for (uint32_t kk = ty; kk < 64; kk += 4) {
-        const uint32_t k = k0 + kk, c = c0 + tx;
-        int h = 0, l = 0;
-        if (k < K && c < cols) split_limbs(B[(uint64_t)k * ldb + c], p, h, l);
-        th[kk][tx] = (int8_t)h;
-        tl[kk][tx] = (int8_t)l;
+    const uint32_t tid = threadIdx.x, cq = tid & 15, kr = tid >> 4;  // 16 chunks x 16 rows
+    const bool vec = ((((uintptr_t)B) | (uintptr_t)(ldb * 2)) & 7) == 0;
+    const uint32_t c = c0 + cq * 4;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t kk = kr + 16 * i, k = k0 + kk;
+        uint64_t v = 0;
+        if (k < K) {
+            const uint16_t *row = B + (uint64_t)k * ldb;
+            if (vec && c + 4 <= cols) v = *(const uint64_t *)(row + c);
+            else
+                for (uint32_t e = 0; e < 4 && c + e < cols; e++) v |= (uint64_t)row[c + e] << (16 * e);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            int h, l;
+            split_limbs((uint32_t)(v >> (16 * e)) & 0xffffu, p, h, l);
+            th[(cq * 4 + e) * kLd + kk] = (int8_t)h;
+            tl[(cq * 4 + e) * kLd + kk] = (int8_t)l;
+        }
     }
     __syncthreads();
-    for (uint32_t cc = ty; cc < 64; cc += 4) {
-        const uint32_t c = c0 + cc;
-        Bh[(uint64_t)c * Kp + k0 + tx] = th[tx][cc];
-        Bl[(uint64_t)c * Kp + k0 + tx] = tl[tx][cc];
-    }
+    const uint32_t cc = tid >> 2, seg = (tid & 3) * 16;
+    const uint4 hv = *(const uint4 *)&th[cc * kLd + seg];
+    const uint4 lv = *(const uint4 *)&tl[cc * kLd + seg];
+    *(uint4 *)(Bh + (uint64_t)(c0 + cc) * Kp + k0 + seg) = hv;
+    *(uint4 *)(Bl + (uint64_t)(c0 + cc) * Kp + k0 + seg) = lv;
 }
 
 // The tile of this workgroup under GemmPlanes::group_m.  Workgroups are
