@@ -191,9 +191,13 @@ hipError_t fl_mfma_rank64_planes(uint32_t p, const int8_t *Ah, const int8_t *Al,
                                  const int8_t *Bl, const uint32_t *Kdev, const uint32_t *row_map,
                                  const uint32_t *Mdev, uint32_t Mmax, uint16_t *C, uint64_t ldc,
                                  uint32_t N, hipStream_t s, const char *site);
-// Residue x -> signed int8 limbs (h, l) with centred r = 256 h + l.
+// Residue x -> signed int8 limbs (h, l) with centred r = 256 h + l = x mod p:
+// r = x if x <= t, else x - p, with t = 32639, or t = (p - 1) / 2 for
+// p < 256 (then r is the symmetric residue in [-127, 127]: a single limb,
+// h = 0).  The threshold is a select on p, so no branch enters loops.
 __device__ __forceinline__ void fl_split_limbs(uint32_t x, uint32_t p, int &h, int &l) {
-    const int r = x <= 32639u ? (int)x : (int)x - (int)p;
+    const uint32_t t = p < 256 ? (p - 1) >> 1 : 32639u;
+    const int r = x <= t ? (int)x : (int)x - (int)p;
     h = (r + 128) >> 8;  // arithmetic shift: floor
     l = r - (h << 8);
 }

@@ -106,12 +106,23 @@ __device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t &bx, uint32_t
     bx = within / rows;
 }
 
+// ONE: single-limb operands (p < 256).
+template <bool ONE>
 __global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
                                                    GemmPlanes g) {
     __shared__ __attribute__((aligned(16))) int8_t smem[kGemmLds];
     uint32_t bx, by;
     gemm_tile_of(g.group_m, bx, by);
-    mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
+    mfma_gemm_tile<ONE>(md, bias, c16, g, bx, by, smem);
+}
+
+hipError_t launch_gemm(uint32_t p, dim3 grid, const fl::Mod &md, uint32_t bias, uint32_t c16, const GemmPlanes &gp,
+                       hipStream_t s) {
+    if (p < 256)
+        hipLaunchKernelGGL(k_mfma_gemm<true>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp);
+    else
+        hipLaunchKernelGGL(k_mfma_gemm<false>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp);
+    return hipGetLastError();
 }
 
 // Rank-k update, k <= 64: one 64-row x 128-column tile per workgroup; row
@@ -178,8 +189,9 @@ hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, 
     const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
     const uint32_t c16 = (uint32_t)((1u << 16) % p);
     dim3 grid((gp.N + BN - 1) / BN, (gp.M + BM - 1) / BM);
-    FL_PROF(site, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp));
-    return hipGetLastError();
+    hipError_t e;
+    FL_PROF(site, s, e = launch_gemm(p, grid, md, bias, c16, gp, s));
+    return e;
 }
 
 // The transposing limb conversion, for other translation units: B (K x cols,
@@ -237,8 +249,8 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
         GemmPlanes gp = {w.Ah, w.Al, w.Bh, w.Bl, w.Kp, w.Kp, 0, 0, kb, ke, Kdev, nullptr, nullptr,
                          nullptr, C, ldc, M, N};
-        FL_PROF(site_mfma, s, hipLaunchKernelGGL(k_mfma_gemm, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp));
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        FL_PROF(site_mfma, s, e = launch_gemm(p, grid, md, bias, c16, gp, s));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

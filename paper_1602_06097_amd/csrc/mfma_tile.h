@@ -5,6 +5,8 @@
 //     r = x - p        otherwise            (r in [-32881, 32639])
 // and split into two signed 8-bit limbs r = 256 h + l with
 //     h = floor((r + 128) / 256) in [-128, 127],  l = r - 256 h in [-128, 127].
+// (For p < 256 the symmetric residue in [-127, 127] is the single limb l and
+// h = 0: the GEMM tile then runs only the S_ll product, one int8 GEMM.)
 // Then  sum_k A B = 65536 S_hh + 256 (S_hl + S_lh) + S_ll  with four int8 GEMMs
 // accumulated exactly in int32 (v_mfma_i32_16x16x64_i8): |h h'| <= 2^14, so a
 // K-chunk of at most kKChunk = 65472 terms keeps |S_hh|, |S_ll| < 2^30 and the
@@ -76,6 +78,9 @@ inline uint32_t gemm_c16(uint32_t p) { return (uint32_t)((1u << 16) % p); }
 // each SIMD and one wave's MFMAs cover the other's waits.
 constexpr int kGemmThreads = 512;
 
+// ONE: single-limb operands (p < 256, zero h planes): the h planes are
+// neither copied nor multiplied.
+template <bool ONE = false>
 __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                const GemmPlanes &g, uint32_t bx, uint32_t by,
                                                int8_t *smem) {
@@ -144,6 +149,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     // one K step into ring slot `slot` (steps past kend re-read the last valid
     // step, so every step issues the same 4 instructions per wave)
     auto issue = [&](uint32_t k0, uint32_t slot) {
+        if (ONE && !(plane & 1)) return;  // an h plane: all zero
         const uint32_t kk = k0 < kend ? k0 : kend - BK;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -162,14 +168,14 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         for (int t = 0; t < 4; t++) {
             const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
             const uint32_t oa = ra * 64 + ((kc ^ ((ra >> 2) & 3)) << 4);
-            ah[t] = *(const v4i *)(st + oa);
+            if (!ONE) ah[t] = *(const v4i *)(st + oa);
             al[t] = *(const v4i *)(st + kPlaneBytes + oa);
         }
 #pragma unroll
         for (int t = 0; t < 2; t++) {
             const uint32_t rb = wn * 32 + t * 16 + (lane & 15);
             const uint32_t ob = rb * 64 + ((kc ^ ((rb >> 2) & 3)) << 4);
-            bh[t] = *(const v4i *)(st + 2 * kPlaneBytes + ob);
+            if (!ONE) bh[t] = *(const v4i *)(st + 2 * kPlaneBytes + ob);
             bl[t] = *(const v4i *)(st + 3 * kPlaneBytes + ob);
         }
     };
@@ -201,20 +207,22 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int j = 0; j < 2; j++) {
-                acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
-                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
-                acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
+                if (!ONE) {
+                    acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+                    acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
+                    acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
+                }
                 acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
             }
         if (more) {
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                ah[t] = nah[t];
+                if (!ONE) ah[t] = nah[t];
                 al[t] = nal[t];
             }
 #pragma unroll
             for (int t = 0; t < 2; t++) {
-                bh[t] = nbh[t];
+                if (!ONE) bh[t] = nbh[t];
                 bl[t] = nbl[t];
             }
         }

@@ -244,6 +244,25 @@ def test_matmul_sub_limb_extremes(value):
         assert np.array_equal(u16(td).astype(np.int64), want), mode
 
 
+@pytest.mark.parametrize("p,value", [(251, 125), (251, 126), (251, 250), (241, 121), (3, 2), (2, 1)])
+def test_matmul_sub_single_limb_extremes(p, value):
+    """p < 256: each residue is one symmetric int8 limb ((p - 1) / 2 stays,
+    (p + 1) / 2 becomes -(p - 1) / 2) and the MFMA GEMM runs the single
+    product; K beyond one int32 chunk."""
+    M, N, K = 32, 40, 70000
+    C = np.full((M, K), value, np.int64)
+    X = np.full((K, N), value, np.int64)
+    X[::3] = (p + 1) // 2 % p
+    want = (-(C @ X)) % p
+    for mode in MODES:
+        tc = torch.from_numpy(C.astype(np.uint16).view(np.int16)).cuda()
+        tx = torch.from_numpy(X.astype(np.uint16).view(np.int16)).cuda()
+        td = torch.zeros((M, N), dtype=torch.int16, device="cuda")
+        fl.matmul_sub(p, tc, tx, td, M, N, K, mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(u16(td).astype(np.int64), want), mode
+
+
 def test_modular_reduction_exhaustive_on_device():
     """The kernels' Barrett reduction equals x % p for every x < 2^32."""
     assert fl.check_modp([2, 3, 251, 32749, 65521]) == [0, 0, 0, 0, 0]
