@@ -63,9 +63,9 @@ typedef enum {
 
 /* Arithmetic form of the dense contractions.  Both give bit-identical
  * results.  FL_PLAIN: 32-bit VALU multiply-adds with delayed reduction.
- * FL_MFMA_I8: centred residues split into two signed 8-bit limbs, products
- * on the int8 matrix cores with exact int32 accumulation, recombined and
- * reduced mod p. */
+ * FL_MFMA_I8: centred residues split into two signed 8-bit limbs (one limb,
+ * the symmetric residue, for p < 256), products on the int8 matrix cores
+ * with exact int32 accumulation, recombined and reduced mod p. */
 typedef enum { FL_PLAIN = 0, FL_MFMA_I8 = 1 } fl_mode;
 
 /* Sparse input (Sec. 3.2, Format 1 is this CSR layout).  Device pointers. */
@@ -150,17 +150,21 @@ size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint32_t ml_widt
  * the block is applied by the multiline sparse-times-dense kernel on the
  * vector ALUs, and each block is solved by a back substitution on the vector
  * ALUs.  FL_MFMA_I8: A's band is expanded into dense int8 limb planes in the
- * workspace; the part beyond each superblock of four blocks is one limb GEMM
- * on the matrix cores, the part inside it a rank-k product per block, and
- * each block is solved as a product with its (precomputed) inverse.  Both
- * forms give the same, unique X. */
+ * workspace; the part beyond each superblock of four blocks is applied by
+ * limb GEMMs on the matrix cores (the columns of the superblock below it on
+ * `stream`, the columns past those one superblock earlier on a second stream
+ * of the library's that `stream` then waits for), the part inside it by a
+ * rank-k product per block, and each block is solved as a product with its
+ * (precomputed) inverse.  Both forms give the same, unique X; all work is
+ * ordered before later work on `stream`. */
 fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, uint16_t *X, uint64_t ldx,
                   fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
 size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode);
 
 /* fl_trsm_planes -- where an FL_MFMA_I8 fl_trsm leaves the int8 limb planes
  * of X in its workspace ws (ws_bytes >= fl_trsm_workspace(info, FL_MFMA_I8)):
- * the centred residue of X[k][c] (X[k][c], or X[k][c] - p above 32639) is
+ * the centred residue of X[k][c] (X[k][c], or X[k][c] - p above 32639;
+ * for p < 256 above (p - 1) / 2, with Xh zero) is
  * 256 Xh[c * ldp + k] + Xl[c * ldp + k] (the limb form of the matrix-core
  * products), for k < npiv, c < nB; the planes hold round_up(nB, 128) columns.  Pointers into ws, no copy; their
  * contents are those of the last fl_trsm that used ws in the FL_MFMA_I8 form
