@@ -302,12 +302,14 @@ def test_trsm_many_blocks_both_forms():
             assert np.array_equal(u16(X)[:sp.npiv, :sp.nB], r["X"]), (mode, w)
 
 
-def test_trsm_lookahead_far_update():
+@pytest.mark.parametrize("p", [65521, 251])
+def test_trsm_lookahead_far_update(p):
     """A band reaching past the superblock below (wide row supports): the
     MFMA form's far update is split by K between the main stream and a
     second stream; both parts and their ordering against the block solves
-    are checked, twice in a row (no race between the streams)."""
-    g = flgen.fl_matrix(m=2600, n=3400, npiv=2200, rank_d=200, density=0.06, p=65521, seed=61,
+    are checked, twice in a row (no race between the streams).  p = 251
+    runs the single-limb GEMM."""
+    g = flgen.fl_matrix(m=2600, n=3400, npiv=2200, rank_d=200, density=0.06, p=p, seed=61,
                         rho_loc=0.05)
     s = oracle.split(g)
     Xr = oracle.trsm(s)
@@ -319,6 +321,28 @@ def test_trsm_lookahead_far_update():
             torch.cuda.synchronize()
             assert np.array_equal(u16(X1)[:sp.npiv, :sp.nB], Xr), (mode, w)
             assert np.array_equal(u16(X2)[:sp.npiv, :sp.nB], Xr), (mode, w)
+
+
+@pytest.mark.parametrize("p", [251, 241])
+def test_single_limb_pipeline_many_blocks(p):
+    """The whole MFMA-form path for p < 256 (single-limb GEMM in the TRSM
+    band, the reduce and the second pass; single limbs through the rank-k
+    tiles) on a matrix with several TRSM superblocks and echelon blocks,
+    against the oracle and the plain form."""
+    g = flgen.fl_matrix(m=2600, n=3400, npiv=2000, rank_d=420, density=0.05, p=p, seed=71 + p,
+                        rho_loc=0.08)
+    r = oracle.fl_rref(g)
+    outs = {}
+    for mode in MODES:
+        res = fl.fl_reduce(*up(g), g["m"], g["n"], g["p"], mode=mode, keep=True)
+        torch.cuda.synchronize()
+        sp = res["split"]
+        assert np.array_equal(u16(res["X"])[:sp.npiv, :sp.nB], r["X"]), mode
+        assert np.array_equal(u16(res["Dt"])[:sp.mD, :sp.nB], r["Dt"]), mode
+        assert np.array_equal(u16(res["Xp"])[:sp.npiv, :sp.nB], r["Xp"]), mode
+        outs[mode] = [t.cpu() for t in res["rref"][:3]]
+    for a, b in zip(outs[fl.FL_PLAIN], outs[fl.FL_MFMA_I8]):
+        assert torch.equal(a, b)
 
 
 def test_repeat_runs_identical():
