@@ -405,9 +405,12 @@ const char *fl_version(void);
 /* Device self-check of the modular reductions used by the kernels: for each
  * prime in p_list and every x in [0, 2^32), compares the 32-bit reduction of
  * x with x % p, the fold of an accumulator pair (256 x + y, y = x times an
- * odd constant mod 2^32) with 64-bit division, and the product of the
- * residues (x mod 2^16) mod p and (x >> 16) mod p; returns the number of
- * mismatches through d_mismatch (device, one uint64 per prime).
+ * odd constant mod 2^32) with 64-bit division, the product of the
+ * residues (x mod 2^16) mod p and (x >> 16) mod p, and the recombination of
+ * the three int32 limb sums of the int8 MFMA contractions (65536 S_hh +
+ * 256 S_mid + S_ll mod p) on a 2^32-point grid over the whole range those
+ * sums can take, its corners included; returns the number of mismatches
+ * through d_mismatch (device, one uint64 per prime).
  * Diagnostic only. */
 fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count, uint64_t *d_mismatch,
                         hipStream_t stream);

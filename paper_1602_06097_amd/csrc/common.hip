@@ -1,5 +1,6 @@
 // common.hip -- error plumbing, device scan and fill kernels, self-checks.
 #include "fl_internal.h"
+#include "mfma_tile.h"
 
 #include <cstdio>
 #include <cstring>
@@ -188,12 +189,29 @@ hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t co
 // ---- self-check of the modular reductions ---------------------------------------
 // Every 32-bit x through reduce32; with it, fold_pair(x, y) against 64-bit
 // division for y = x times an odd constant (a spread of low words over the
-// whole 2^41 range of 256 x + y), and mulmod over the residue pairs (x mod
-// 2^16 mod p, x >> 16 mod p).
+// whole 2^41 range of 256 x + y), mulmod over the residue pairs (x mod 2^16
+// mod p, x >> 16 mod p), and combine_limbs over a grid of (S_hh, S_mid, S_ll)
+// spanning the whole range its callers can produce (sums of up to kKChunk
+// limb products, S_ll plus a folded residue), corners included.
 namespace {
-__global__ void k_check_modp(fl::Mod m, uint64_t *mismatch) {
+// Value i (of 2^bits) of a grid over [lo, hi]: the four values at each end,
+// the four around zero, and a jittered linear spread in between.
+__device__ int64_t grid_value(uint32_t i, uint32_t bits, int64_t lo, int64_t hi) {
+    const uint32_t n = 1u << bits;
+    if (i < 4) return lo + i;
+    if (i >= n - 4) return hi - (int64_t)(n - 1 - i);
+    if (i >= n / 2 - 2 && i < n / 2 + 2) return (int64_t)i - (int64_t)(n / 2);
+    const uint64_t span = (uint64_t)(hi - lo);
+    return lo + (int64_t)(span / n * i + (i * 2654435761u) % (span / n));
+}
+
+__global__ void k_check_modp(fl::Mod m, uint32_t bias, uint32_t c16, uint64_t *mismatch) {
     const uint64_t total = (uint64_t)1 << 32;
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    const fl_mfma::LimbCombine lc = fl_mfma::limb_combine(m, bias, c16);
+    const int64_t kMaxHH = (int64_t)fl_mfma::kKChunk * 16384;
+    const int64_t kMaxMid = (int64_t)fl_mfma::kKChunk * 32512;
+    const int64_t kMaxLL = kMaxHH + m.p - 1;
     uint64_t bad = 0;
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += nthreads) {
         uint32_t v = (uint32_t)x;
@@ -202,6 +220,12 @@ __global__ void k_check_modp(fl::Mod m, uint64_t *mismatch) {
         if (fl::fold_pair(v, y, m) != (uint32_t)((((uint64_t)v << 8) + y) % m.p)) bad++;
         const uint32_t a = (v & 0xffffu) % m.p, b = (v >> 16) % m.p;
         if (fl::mulmod(a, b, m) != a * b % m.p) bad++;
+        const int64_t hh = grid_value(v >> 21, 11, -kMaxHH, kMaxHH);
+        const int64_t mid = grid_value((v >> 10) & 2047u, 11, -kMaxMid, kMaxMid);
+        const int64_t ll = grid_value(v & 1023u, 10, -kMaxHH, kMaxLL);
+        const int64_t S = hh * 65536 + mid * 256 + ll;
+        const int64_t want = ((S % (int64_t)m.p) + m.p) % m.p;
+        if (fl_mfma::combine_limbs(lc, (int)hh, (int)mid, (int)ll) != (uint32_t)want) bad++;
     }
     if (bad) atomicAdd((unsigned long long *)mismatch, (unsigned long long)bad);
 }
@@ -214,8 +238,8 @@ extern "C" fl_status fl_check_modp(const uint32_t *h_p_list, uint32_t count,
     if (e != hipSuccess) return fl_hip_fail(e, "fl_check_modp fill");
     for (uint32_t i = 0; i < count; i++) {
         FL_ARG(h_p_list[i] >= 2 && h_p_list[i] <= 65521, "fl_check_modp: p out of range");
-        hipLaunchKernelGGL(k_check_modp, dim3(4096), dim3(256), 0, stream,
-                           fl::make_mod(h_p_list[i]), d_mismatch + i);
+        hipLaunchKernelGGL(k_check_modp, dim3(4096), dim3(256), 0, stream, fl::make_mod(h_p_list[i]),
+                           fl_mfma::gemm_bias(h_p_list[i]), fl_mfma::gemm_c16(h_p_list[i]), d_mismatch + i);
         FL_LAUNCH_CHECK("k_check_modp");
     }
     return FL_OK;

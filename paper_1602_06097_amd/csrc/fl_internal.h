@@ -23,14 +23,12 @@ namespace fl {
 struct Mod {
     uint32_t p;
     uint32_t mu;  // floor(2^32 / p)
-    double inv;   // 1 / p, rounded
 };
 
 __host__ __device__ inline Mod make_mod(uint32_t p) {
     Mod m;
     m.p = p;
     m.mu = (uint32_t)(((uint64_t)1 << 32) / p);
-    m.inv = 1.0 / (double)p;
     return m;
 }
 
@@ -61,18 +59,13 @@ __device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
     return __umul24(a, b) + c;
 }
 
-// Fold a split accumulator pair (hi counts 256x) into one residue, in double
-// precision: v = 256 hi + lo < 2^41 is exact; q = floor(v * inv) is within 1
-// of floor(v / p) (the product's relative error is below 2^-51 and
-// v / p < 2^40), so r = v - q p, exact, lies in [-p, 2p) and two comparisons
-// finish.  Full-rate FP64 instead of six quarter-rate 32-bit multiplies.
+// Fold a split accumulator pair (hi counts 256x) into one residue:
+// 256 hi + lo = 256 (hi mod p) + (lo mod p) (mod p), and
+// 256 (hi mod p) + (lo mod p) < 2^24 + 2^16, so a third reduction finishes.
+// The first two reductions are independent.
 __device__ __forceinline__ uint32_t fold_pair(uint32_t hi, uint32_t lo, const Mod &m) {
-    const double v = __builtin_fma((double)hi, 256.0, (double)lo);
-    const double q = __builtin_floor(v * m.inv);
-    int r = (int)__builtin_fma(-q, (double)m.p, v);
-    r += r < 0 ? (int)m.p : 0;
-    r -= r >= (int)m.p ? (int)m.p : 0;
-    return (uint32_t)r;
+    const uint32_t rh = reduce32(hi, m), rl = reduce32(lo, m);
+    return reduce32((rh << 8) + rl, m);
 }
 
 // Modular inverse by Fermat's little theorem (x != 0, p prime).

@@ -8,13 +8,15 @@
 // (For p < 256 the symmetric residue in [-127, 127] is the single limb l and
 // h = 0: the GEMM tile then runs only the S_ll product, one int8 GEMM.)
 // Then  sum_k A B = 65536 S_hh + 256 (S_hl + S_lh) + S_ll  with four int8 GEMMs
-// accumulated exactly in int32 (v_mfma_i32_16x16x64_i8): |h h'| <= 2^14, so a
+// accumulated exactly in int32 (v_mfma_i32_16x16x64_i8).  Per K term
+// |h h'|, |l l'| <= 2^14 and |h l' + l h'| <= 32512 (the largest pair sum of
+// two limb pairs of the window above, at r = -32641 = 256 (-128) + 127), so a
 // K-chunk of at most kKChunk = 65472 terms keeps |S_hh|, |S_ll| < 2^30 and the
-// shared middle accumulator |S_hl + S_lh| < 2^31.  The three partials are
-// combined into S = 65536 S_hh + 256 S_mid + S_ll and reduced mod p in
-// double precision (combine_limbs): every intermediate is an integer below
-// 2^53 in magnitude, so all of it is exact except the quotient estimate,
-// which only selects a candidate remainder that two comparisons correct.
+// shared middle accumulator |S_mid| <= 65472 * 32512 < 2^31.  A tile whose K
+// range is longer folds its accumulators every kKChunk terms: the residue of
+// the chunk's sum goes into S_ll (it has 2^20 of headroom) and S_hh, S_mid
+// restart at zero.  The three partials are combined and reduced mod p with
+// 32-bit integer operations only (combine_limbs).
 //
 // The tiles are device functions so that both the one-problem kernels and
 // the kernels that serve many problems in one launch (one problem per
@@ -38,37 +40,38 @@ constexpr int kGemmLds = kStages * kStageBytes;  // bytes of LDS of one GEMM til
 constexpr int kRank64Ld = 128 + 4;          // u16 row stride of the rank-k residue tile
 
 // The residue of S = 65536 S_hh + 256 S_mid + S_ll mod p from the three int32
-// limb sums, in double precision (full-rate FP64 on the vector units,
-// against four quarter-rate 32-bit multiplies per Barrett reduction):
-//   t = 256 S_hh + S_mid and S = 256 t + S_ll are exact fused multiply-adds
-//   (|S| < 2^47 for sums of at most kKChunk terms);
-//   q = floor(S * (1/p)) is within 1 of floor(S / p), because the relative
-//   error of the product is below 2^-50 and |S / p| < 2^46;
-//   r = S - q p is exact (an integer below 2^53), lies in [-p, 2p), and two
-//   conditional corrections bring it into [0, p).
+// limb sums (|S_hh| < 2^30, |S_mid| < 2^31, |S_ll| < 2^30 + 2^16), in 32-bit
+// integer arithmetic:
+//   carry the low byte of S_ll into S_mid and the low byte of that into S_hh,
+//     m1 = S_mid + (S_ll >> 8),  h1 = S_hh + (m1 >> 8)      (arithmetic shifts:
+//     |m1| < 2^31 - 2^23, |h1| < 2^30 + 2^23),
+//   so that S = 65536 h1 + L with L = 256 (m1 & 255) + (S_ll & 255) in [0, 2^16);
+//   r1 = (h1 + bias) mod p, bias the smallest multiple of p >= 2^31 (so
+//   h1 + bias lies in [0, 2^32));
+//   S = r1 c16 + L (mod p) with c16 = 2^16 mod p, and r1 c16 + L <=
+//   (p - 1)^2 + 2^16 - 1 < 2^32, so one more reduction gives the residue.
+// Both reductions are fl::reduce32 (Barrett, exact for every 32-bit value).
 struct LimbCombine {
-    double pd, inv;
-    int p;
+    fl::Mod md;
+    uint32_t bias, c16;
 };
-__device__ __forceinline__ LimbCombine limb_combine(const fl::Mod &md) {
+__device__ __forceinline__ LimbCombine limb_combine(const fl::Mod &md, uint32_t bias, uint32_t c16) {
     LimbCombine c;
-    c.p = (int)md.p;
-    c.pd = (double)md.p;
-    c.inv = 1.0 / c.pd;
+    c.md = md;
+    c.bias = bias;
+    c.c16 = c16;
     return c;
 }
 __device__ __forceinline__ uint32_t combine_limbs(const LimbCombine &c, int hh, int mid, int ll) {
-    const double t = __builtin_fma((double)hh, 256.0, (double)mid);
-    const double S = __builtin_fma(t, 256.0, (double)ll);
-    const double q = __builtin_floor(S * c.inv);
-    int r = (int)__builtin_fma(-q, c.pd, S);
-    r += r < 0 ? c.p : 0;
-    r -= r >= c.p ? c.p : 0;
-    return (uint32_t)r;
+    const int m1 = mid + (ll >> 8);
+    const int h1 = hh + (m1 >> 8);
+    const uint32_t L = (((uint32_t)m1 & 255u) << 8) | ((uint32_t)ll & 255u);
+    const uint32_t r1 = fl::reduce32((uint32_t)h1 + c.bias, c.md);
+    return fl::reduce32(r1 * c.c16 + L, c.md);
 }
 
-// bias: the smallest multiple of p that is >= 2^31, so s + bias >= 0 and
-// s + bias < 2^32 for |s| < 2^31 - 2^16.
+// bias: the smallest multiple of p that is >= 2^31 (combine_limbs);
+// c16 = 2^16 mod p.
 inline uint32_t gemm_bias(uint32_t p) { return (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p); }
 inline uint32_t gemm_c16(uint32_t p) { return (uint32_t)((1u << 16) % p); }
 
@@ -187,7 +190,9 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     // kStages - 3 later steps' instructions outstanding); the barrier also
     // retires every wave's reads of step j - 1's slot, which is refilled next.
     v4i ah[4], al[4], bh[2], bl[2], nah[4], nal[4], nbh[2], nbl[2];
+    const LimbCombine lc = limb_combine(md, bias, c16);
     uint32_t slot = 0;  // ring slot of step k0
+    uint32_t left = kKChunk / BK;  // K steps before the accumulators are folded
     if (kbeg < kend) {
 #pragma unroll
         for (uint32_t s = 0; s + 1 < kStages; s++) issue(kbeg + s * BK, s);
@@ -214,6 +219,19 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                 }
                 acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
             }
+        if (--left == 0 && more) {  // a K range longer than kKChunk: fold
+            left = kKChunk / BK;
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        acc_ll[i][j][e] = (int)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
+                        acc_hh[i][j][e] = 0;
+                        acc_mid[i][j][e] = 0;
+                    }
+        }
         if (more) {
 #pragma unroll
             for (int t = 0; t < 4; t++) {
@@ -251,9 +269,6 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
     // column lane%16) of each 16 x 16 tile is held by the wave.
     uint16_t *sOut = (uint16_t *)smem;
-    const LimbCombine lc = limb_combine(md);
-    (void)bias;
-    (void)c16;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -299,7 +314,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 // residues are staged through LDS and C is written back with 8-byte
 // accesses.  A planes are indexed by the C row (lda bytes per row), B planes
 // by the C column (ldb bytes per column).  The three limb sums are combined
-// by combine_limbs.  sv: kRank64Ld * 64 RT u16, rows_s: 64 RT u32 in LDS;
+// by combine_limbs (K <= 384, far inside its bounds).  sv: kRank64Ld * 64 RT u16, rows_s: 64 RT u32 in LDS;
 // callers looping over tiles must synchronise between them.
 // rankk_rows sets up the row block (its row list entries and its A
 // fragments, kept in registers for any number of column tiles): wave w holds
@@ -355,7 +370,6 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     static_assert(NJ == 8 || NJ == 4, "128 or 64 columns per tile");
     constexpr int kCpr = 4 * NJ;        // C chunks of 4 columns per row
     constexpr int kChunks = NJ * RT;    // C chunks per thread
-    (void)c16;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n0 = bx * 16 * NJ;
     // C tile: 64 RT rows x kCpr chunks of 4 columns; every load is issued
@@ -377,8 +391,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
         bh[0][s] = *(gv4i *)(Bh + b);
         bl[0][s] = *(gv4i *)(Bl + b);
     }
-    const LimbCombine lc = limb_combine(md);
-    (void)bias;
+    const LimbCombine lc = limb_combine(md, bias, c16);
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
         const int cur = j & 1, nxt = cur ^ 1;

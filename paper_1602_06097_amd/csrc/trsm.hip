@@ -677,9 +677,7 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
     typedef __attribute__((address_space(1))) const v4i gv4i;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nrow = r1 - r0, c0 = bx * 64;
-    const fl_mfma::LimbCombine lc = fl_mfma::limb_combine(md);
-    (void)bias;
-    (void)c16;
+    const fl_mfma::LimbCombine lc = fl_mfma::limb_combine(md, bias, c16);
     // R: 128 rows x 16 chunks of 4 columns, 8 chunks per thread (rows past the
     // block or columns past nB read as zero)
     uint64_t rv[8];
