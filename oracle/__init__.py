@@ -145,14 +145,59 @@ def multiline(csr, rows: int, cols: int, w: int):
     return gptr, pos[:L].copy(), val[:L * w].copy()
 
 
-def trsm(s: dict) -> np.ndarray:
+def column_stripe(csr, rows: int, c0: int, c1: int):
+    """Columns [c0, c1) of a CSR triple, relabelled to [0, c1 - c0)."""
+    rp, ci, v = csr
+    keep = (ci >= c0) & (ci < c1)
+    cs = np.zeros(len(ci) + 1, np.int64)
+    np.cumsum(keep, out=cs[1:])
+    nrp = cs[rp.astype(np.int64)].astype(np.uint64)
+    return nrp, (ci[keep] - c0).astype(np.uint32), v[keep].copy()
+
+
+def column_subset(csr, rows: int, cols: np.ndarray):
+    """The columns `cols` (ascending) of a CSR triple, column cols[k]
+    relabelled to k."""
+    rp, ci, v = csr
+    cols = np.asarray(cols, np.int64)
+    lut = np.full(int(max(cols.max() + 1 if len(cols) else 0, ci.max() + 1 if len(ci) else 0)), -1, np.int64)
+    lut[cols] = np.arange(len(cols))
+    new = lut[ci.astype(np.int64)] if len(ci) else np.zeros(0, np.int64)
+    keep = new >= 0
+    cs = np.zeros(len(ci) + 1, np.int64)
+    np.cumsum(keep, out=cs[1:])
+    nrp = cs[rp.astype(np.int64)].astype(np.uint64)
+    return nrp, new[keep].astype(np.uint32), v[keep].copy()
+
+
+def trsm(s: dict, threads: int = 1) -> np.ndarray:
+    """X = A^{-1} B.  With threads > 1 the columns of B are cut into that
+    many stripes, each solved by its own call of the same back substitution
+    in a thread of its own (the columns of X are independent, Sec. 4.2)."""
     lib = _load()
-    X = np.zeros((s["npiv"], s["nB"]), np.uint16)
-    if s["npiv"] == 0:
+    npiv, nB = s["npiv"], s["nB"]
+    X = np.zeros((npiv, nB), np.uint16)
+    if npiv == 0:
         return X
-    rc = lib.or_trsm(s["npiv"], s["nB"], *_csr_args(*s["A"]), *_csr_args(*s["B"]), s["p"],
-                     _p(X, P_U16), max(s["nB"], 1))
-    assert rc == 0, "A is not unit upper triangular"
+    if threads <= 1 or nB < 2 * threads:
+        rc = lib.or_trsm(npiv, nB, *_csr_args(*s["A"]), *_csr_args(*s["B"]), s["p"],
+                         _p(X, P_U16), max(nB, 1))
+        assert rc == 0, "A is not unit upper triangular"
+        return X
+    import concurrent.futures as cf
+    edges = np.linspace(0, nB, threads + 1).astype(np.int64)
+
+    def solve(k):
+        c0, c1 = int(edges[k]), int(edges[k + 1])
+        Bs = column_stripe(s["B"], npiv, c0, c1)
+        Xs = np.zeros((npiv, c1 - c0), np.uint16)
+        rc = lib.or_trsm(npiv, c1 - c0, *_csr_args(*s["A"]), *_csr_args(*Bs), s["p"], _p(Xs, P_U16),
+                         max(c1 - c0, 1))
+        assert rc == 0, "A is not unit upper triangular"
+        X[:, c0:c1] = Xs
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(solve, range(threads)))
     return X
 
 
@@ -228,12 +273,13 @@ def assemble(n: int, npiv: int, col_perm, Xp, rank: int, R, pivcols):
     return rp, ci[:nnz].copy(), v[:nnz].copy()
 
 
-def fl_rref(mat: dict, keep: bool = True) -> dict:
+def fl_rref(mat: dict, keep: bool = True, threads: int = 1) -> dict:
     """The whole oracle pipeline: split, TRSM, reduce, RREF of the Schur
-    complement, second pass, read-off.  Returns every intermediate."""
+    complement, second pass, read-off.  Returns every intermediate.
+    threads: column stripes of the TRSM solved concurrently (see trsm)."""
     s = split(mat)
     p = mat["p"]
-    X = trsm(s)
+    X = trsm(s, threads)
     Dt = reduce(s, X)
     R, r, pc = rref_dense(Dt, p)
     Xp = second_pass(X, R, r, pc, p)

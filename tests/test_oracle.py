@@ -247,3 +247,30 @@ def test_dense_planted_rank_generator_pin():
     assert r == 29 and np.array_equal(pc, d["pivcols"])
     assert np.array_equal(R[:r], d["V"])
     assert not R[r:].any()
+
+
+@pytest.mark.parametrize("threads", [2, 5, 16])
+def test_striped_trsm_equals_single_call(c1_case, threads):
+    """The oracle's TRSM over column stripes in several threads is the same
+    back substitution on independent column sets (Sec. 4.2): it must return
+    the single call's X exactly, also with stripes narrower than a row run
+    and with more stripes than the workload has cores."""
+    g, r = c1_case
+    s = r["split"]
+    assert np.array_equal(oracle.trsm(s, threads), r["X"])
+
+
+def test_column_subset_and_stripe():
+    """The column selections the benchmark's CPU sample uses: relabelled
+    columns, row pointers of the kept entries, values carried along."""
+    import scipy.sparse as sps
+    g = flgen.random_sparse(40, 90, 0.2, 65521, seed=9, zero_rows=0.1)
+    M = sps.csr_matrix((g["val"].astype(np.int64), g["col"].astype(np.int64), g["row_ptr"].astype(np.int64)),
+                       shape=(40, 90)).toarray()
+    cols = np.array([0, 3, 4, 17, 50, 89])
+    rp, ci, v = oracle.column_subset((g["row_ptr"], g["col"], g["val"]), 40, cols)
+    S = sps.csr_matrix((v.astype(np.int64), ci.astype(np.int64), rp.astype(np.int64)), shape=(40, len(cols)))
+    assert np.array_equal(S.toarray(), M[:, cols])
+    rp, ci, v = oracle.column_stripe((g["row_ptr"], g["col"], g["val"]), 40, 10, 33)
+    S = sps.csr_matrix((v.astype(np.int64), ci.astype(np.int64), rp.astype(np.int64)), shape=(40, 23))
+    assert np.array_equal(S.toarray(), M[:, 10:33])
