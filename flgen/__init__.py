@@ -358,26 +358,35 @@ def csr_to_dense(mat: dict) -> np.ndarray:
     return out
 
 
-def batch_matrices(count: int, m_lo: int, m_hi: int, p: int, seed: int) -> list:
+def _batch_member(args) -> dict:
+    i, m_lo, m_hi, p, seed = args
+    s = seed ^ (i << 32)
+    rng = np.random.default_rng(s)
+    m = int(round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi)))))
+    n = int(round(rng.uniform(1.3, 1.6) * m))
+    npiv = int(round(rng.uniform(0.70, 0.85) * m))
+    density = float(rng.uniform(0.02, 0.15))
+    mD, nB = m - npiv, n - npiv
+    r = int(np.floor(rng.uniform(0.5, 0.95) * min(mD, nB)))
+    return fl_matrix(m=m, n=n, npiv=npiv, rank_d=r, density=density, p=p, seed=s + 1)
+
+
+def batch_matrices(count: int, m_lo: int, m_hi: int, p: int, seed: int, workers: int = 1) -> list:
     """``count`` planted FL matrices with the batch size distribution (see
-    ``BATCH_CONFIGS``); matrix i is drawn from seed ``seed ^ (i << 32)``."""
-    out = []
-    for i in range(count):
-        s = seed ^ (i << 32)
-        rng = np.random.default_rng(s)
-        m = int(round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi)))))
-        n = int(round(rng.uniform(1.3, 1.6) * m))
-        npiv = int(round(rng.uniform(0.70, 0.85) * m))
-        density = float(rng.uniform(0.02, 0.15))
-        mD, nB = m - npiv, n - npiv
-        r = int(np.floor(rng.uniform(0.5, 0.95) * min(mD, nB)))
-        out.append(fl_matrix(m=m, n=n, npiv=npiv, rank_d=r, density=density, p=p, seed=s + 1))
-    return out
+    ``BATCH_CONFIGS``); matrix i is drawn from seed ``seed ^ (i << 32)``, so
+    the list does not depend on ``workers`` (processes building matrices
+    concurrently)."""
+    jobs = [(i, m_lo, m_hi, p, seed) for i in range(count)]
+    if workers <= 1:
+        return [_batch_member(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_member, jobs, chunksize=1)
 
 
-def config_batch(name: str, p: int = 65521, seed: int | None = None) -> list:
+def config_batch(name: str, p: int = 65521, seed: int | None = None, workers: int = 1) -> list:
     """The named batch workload (``c4``) with its default seed."""
     cfg = BATCH_CONFIGS[name]
     if seed is None:
         seed = BASE_SEED + int(name[1:])
-    return batch_matrices(p=p, seed=seed, **cfg)
+    return batch_matrices(p=p, seed=seed, workers=workers, **cfg)
