@@ -29,7 +29,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["CONFIGS", "BATCH_CONFIGS", "fl_matrix", "random_sparse", "dense_planted_rank",
-           "csr_to_dense", "config_matrix", "batch_matrices", "config_batch"]
+           "csr_to_dense", "config_matrix", "batch_matrices", "config_batch", "config_batch_member"]
 
 # Sizes of the workloads (rows x cols, pivot rows, planted rank of D, density).
 CONFIGS = {
@@ -390,3 +390,12 @@ def config_batch(name: str, p: int = 65521, seed: int | None = None, workers: in
     if seed is None:
         seed = BASE_SEED + int(name[1:])
     return batch_matrices(p=p, seed=seed, workers=workers, **cfg)
+
+
+def config_batch_member(name: str, i: int, p: int = 65521, seed: int | None = None) -> dict:
+    """Matrix ``i`` of the named batch workload alone (equal to
+    ``config_batch(name)[i]``)."""
+    cfg = BATCH_CONFIGS[name]
+    if seed is None:
+        seed = BASE_SEED + int(name[1:])
+    return _batch_member((i, cfg["m_lo"], cfg["m_hi"], p, seed))
