@@ -240,6 +240,23 @@ fl_status fl_rref_to_csr(const fl_split_info *info, const fl_split_out *s, const
                          uint16_t *val, void *ws, size_t ws_bytes, hipStream_t stream);
 size_t fl_rref_csr_workspace(const fl_split_info *info);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fl_rref_csr_size
+ * with its count/scan scratch in a static device array of
+ * fl_rref_csr_noalloc_scratch_bytes() = 16 MiB per GPU, held until the
+ * process ends, instead of a caller workspace.  Same arguments and results
+ * as fl_rref_csr_size otherwise.  Allocates nothing (no hipMalloc/hipFree, no
+ * allocating library call); the first call on a device looks up the array's
+ * device address.  FL_ERR_ARG when npiv + min(mD, nB) + 1 rows need more
+ * scratch than that (about 2.09 million rows).  Every call on one GPU uses the
+ * same array: calls that overlap on one GPU (different streams or threads)
+ * race, and must be ordered by the caller. */
+fl_status fl_rref_csr_size_noalloc(const fl_split_info *info, const fl_split_out *s, const uint16_t *Xp,
+                                   uint64_t ldx, const uint16_t *RD, uint64_t ldd,
+                                   const uint32_t *d_rank, const uint32_t *d_pivcol, uint64_t *row_ptr,
+                                   uint32_t *h_rank, uint64_t *h_nnz, hipStream_t stream);
+size_t fl_rref_csr_noalloc_scratch_bytes(void);
+
 /* Sec. 4.3 (new order of operations): the same Dt = D - C A^{-1} B as
  * fl_trsm + fl_reduce_cd, without forming X = A^{-1} B -- for callers that
  * need only the echelon form of D and the rank of M.  C is reduced by A

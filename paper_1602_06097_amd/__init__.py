@@ -112,6 +112,9 @@ def load():
         "fl_rref_to_csr": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
                                       c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
         "fl_rref_csr_workspace": (c_sz, [P(FlSplitInfo)]),
+        "fl_rref_csr_size_noalloc": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
+                                                c_vp, c_vp, P(c_u32), P(c_u64), c_vp]),
+        "fl_rref_csr_noalloc_scratch_bytes": (c_sz, []),
         "fl_matmul_sub": (ct.c_int, [c_u32, c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_u64, c_vp, c_u64,
                                      ct.c_int, c_vp, c_sz, c_vp]),
         "fl_matmul_sub_workspace": (c_sz, [c_u32, c_u32, c_u32, ct.c_int]),
@@ -335,6 +338,26 @@ def rref_to_csr(sp: Split, Xp: torch.Tensor, Dt: torch.Tensor, ech: Echelon):
     _check(st, "fl_rref_to_csr")
     rank = int(h_rank.value)
     return row_ptr[:rank + 1], col[:nnz], val[:nnz], rank
+
+
+def rref_to_csr_noalloc(sp: Split, Xp: torch.Tensor, Dt: torch.Tensor, ech: Echelon, row_ptr: torch.Tensor,
+                        col: torch.Tensor, val: torch.Tensor):
+    """rref_to_csr into caller-provided outputs, with no device allocation by
+    the library: the size query runs on the library's static scratch
+    (fl_rref_csr_size_noalloc).  row_ptr must hold npiv + min(mD, nB) + 1
+    entries and col/val the nonzeros.  Returns (nnz, rank)."""
+    lib = load()
+    h_rank, h_nnz = c_u32(0), c_u64(0)
+    args = (ct.byref(sp.info), ct.byref(sp.out), _ptr(Xp), Xp.shape[1], _ptr(Dt), Dt.shape[1],
+            _ptr(ech.rank), _ptr(ech.pivcol))
+    st = lib.fl_rref_csr_size_noalloc(*args, _ptr(row_ptr), ct.byref(h_rank), ct.byref(h_nnz), _stream())
+    _check(st, "fl_rref_csr_size_noalloc")
+    nnz = int(h_nnz.value)
+    if nnz > min(col.numel(), val.numel()):
+        raise ValueError(f"col/val hold {min(col.numel(), val.numel())} entries, RREF(M) has {nnz}")
+    st = lib.fl_rref_to_csr(*args, _ptr(row_ptr), _ptr(col), _ptr(val), None, 0, _stream())
+    _check(st, "fl_rref_to_csr")
+    return nnz, int(h_rank.value)
 
 
 def matmul_sub(p: int, C: torch.Tensor, X: torch.Tensor, D: torch.Tensor, M: int, N: int, K: int,

@@ -12,6 +12,7 @@
 //   k_csr_emit         one wave per output row: pivot 1, then the nonzeros of
 //                      the X' or R_D row (both ascending in original order),
 //                      staged in LDS up to 256 entries at a time for coalesced stores.
+#include <mutex>
 #include <string>
 
 #include "fl_internal.h"
@@ -443,6 +444,56 @@ extern "C" fl_status fl_rref_csr_size(const fl_split_info *info, const fl_split_
     *h_rank = info->npiv + r;
     *h_nnz = tot;
     return FL_OK;
+}
+
+// ---- the read-off's size query without any allocation -------------------------
+// The count/scan scratch lives in a file-scope device array (one copy per GPU,
+// held until the process ends).  Host code never passes the array's name to a
+// kernel: its device address is looked up once per device with
+// hipGetSymbolAddress and kept here.
+namespace {
+constexpr size_t kCsrScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kCsrScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+fl_status csr_scratch(void **out) {
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    FL_ARG(dev >= 0 && dev < kMaxDevices, "fl_rref_csr_size_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        FL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FL_ARG(ptr != nullptr, "fl_rref_csr_size_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FL_OK;
+}
+}  // namespace
+
+extern "C" size_t fl_rref_csr_noalloc_scratch_bytes(void) { return kCsrScratchBytes; }
+
+extern "C" fl_status fl_rref_csr_size_noalloc(const fl_split_info *info, const fl_split_out *s,
+                                              const uint16_t *Xp, uint64_t ldx, const uint16_t *RD,
+                                              uint64_t ldd, const uint32_t *d_rank,
+                                              const uint32_t *d_pivcol, uint64_t *row_ptr,
+                                              uint32_t *h_rank, uint64_t *h_nnz, hipStream_t stream) {
+    fl_status st = fl_check_split(info, s);
+    if (st != FL_OK) return st;
+    const size_t need = fl_rref_csr_workspace(info);
+    if (need > kCsrScratchBytes) {
+        fl_set_error("fl_rref_csr_size_noalloc: npiv + min(mD, nB) rows need more than the 16 MiB "
+                     "static scratch; use fl_rref_csr_size with a workspace");
+        return FL_ERR_ARG;
+    }
+    void *ws = nullptr;
+    st = csr_scratch(&ws);
+    if (st != FL_OK) return st;
+    return fl_rref_csr_size(info, s, Xp, ldx, RD, ldd, d_rank, d_pivcol, row_ptr, h_rank, h_nnz, ws,
+                            kCsrScratchBytes, stream);
 }
 
 // Count, scan and emit without a host sync: col/val must hold the upper bound
