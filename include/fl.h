@@ -168,10 +168,13 @@ size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode);
  * 256 Xh[c * ldp + k] + Xl[c * ldp + k] (the limb form of the matrix-core
  * products), for k < npiv, c < nB; the planes hold round_up(nB, 128) columns.  Pointers into ws, no copy; their
  * contents are those of the last fl_trsm that used ws in the FL_MFMA_I8 form
- * and stay valid until ws is reused.  Errors: FL_ERR_ARG for NULL arguments,
- * npiv or nB of 0, or a workspace that is too small. */
+ * and stay valid until ws is reused.  *row_end (may be NULL) receives, per
+ * 128-column tile j of X, 1 + the last row of X with a nonzero in columns
+ * [128 j, 128 j + 128) (0: none), device u32[round_up(nB, 128) / 128].
+ * Errors: FL_ERR_ARG for NULL arguments, npiv or nB of 0, or a workspace
+ * that is too small. */
 fl_status fl_trsm_planes(const fl_split_info *info, const void *ws, size_t ws_bytes, const int8_t **Xh,
-                         const int8_t **Xl, uint64_t *ldp);
+                         const int8_t **Xl, uint64_t *ldp, const uint32_t **row_end);
 
 /* ---- step 3 --------------------------------------------------------------
  * fl_reduce_cd -- Sec. 4.1 step 3: Dt = D - C X mod p (C reduced to zero by
@@ -189,10 +192,13 @@ size_t fl_reduce_cd_workspace(const fl_split_info *info, fl_mode mode);
  * ldp a multiple of 16, both planes 16-byte aligned), so that X is not
  * converted again; the planes are only read.  Same Dt as fl_reduce_cd, bit
  * for bit.  Workspace: fl_reduce_cd_planes_workspace(info) bytes (smaller
- * than fl_reduce_cd's: no planes of X).  Errors as fl_reduce_cd. */
+ * than fl_reduce_cd's: no planes of X).  row_end (device, may be NULL): per
+ * 128-column tile of X an upper bound on 1 + its last row with a nonzero
+ * there, as fl_trsm_planes returns it; the product skips the rows past it.
+ * Errors as fl_reduce_cd. */
 fl_status fl_reduce_cd_planes(const fl_split_info *info, const fl_split_out *s, const int8_t *Xh,
-                              const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd, void *ws,
-                              size_t ws_bytes, hipStream_t stream);
+                              const int8_t *Xl, uint64_t ldp, const uint32_t *row_end, uint16_t *Dt,
+                              uint64_t ldd, void *ws, size_t ws_bytes, hipStream_t stream);
 size_t fl_reduce_cd_planes_workspace(const fl_split_info *info);
 
 /* ---- step 4 --------------------------------------------------------------

@@ -95,9 +95,9 @@ def load():
         "fl_reduce_cd": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
                                     c_vp, c_sz, c_vp]),
         "fl_reduce_cd_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
-        "fl_trsm_planes": (ct.c_int, [P(FlSplitInfo), c_vp, c_sz, P(c_vp), P(c_vp), P(c_u64)]),
-        "fl_reduce_cd_planes": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_vp, c_u64, c_vp, c_u64,
-                                           c_vp, c_sz, c_vp]),
+        "fl_trsm_planes": (ct.c_int, [P(FlSplitInfo), c_vp, c_sz, P(c_vp), P(c_vp), P(c_u64), P(c_vp)]),
+        "fl_reduce_cd_planes": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_vp, c_u64, c_vp, c_vp,
+                                           c_u64, c_vp, c_sz, c_vp]),
         "fl_reduce_cd_planes_workspace": (c_sz, [P(FlSplitInfo)]),
         "fl_reduce_neworder": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, ct.c_int, c_vp, c_sz, c_vp]),
         "fl_reduce_neworder_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
@@ -239,8 +239,8 @@ class Planes:
     """The int8 limb planes of X left in an MFMA-form TRSM workspace (which
     this object keeps alive): Xh/Xl device addresses and their row stride."""
 
-    def __init__(self, ws, xh: int, xl: int, ldp: int):
-        self.ws, self.xh, self.xl, self.ldp = ws, xh, xl, ldp
+    def __init__(self, ws, xh: int, xl: int, ldp: int, row_end: int | None = None):
+        self.ws, self.xh, self.xl, self.ldp, self.row_end = ws, xh, xl, ldp, row_end
 
 
 def trsm(sp: Split, mode: int = FL_PLAIN, keep_planes: bool = False):
@@ -258,10 +258,11 @@ def trsm(sp: Split, mode: int = FL_PLAIN, keep_planes: bool = False):
         return X
     if mode != FL_MFMA_I8:
         raise ValueError("trsm: keep_planes needs the FL_MFMA_I8 form")
-    xh, xl, ldp = ct.c_void_p(), ct.c_void_p(), c_u64()
-    st = lib.fl_trsm_planes(ct.byref(sp.info), _ptr(ws), ws.numel(), ct.byref(xh), ct.byref(xl), ct.byref(ldp))
+    xh, xl, ldp, rend = ct.c_void_p(), ct.c_void_p(), c_u64(), ct.c_void_p()
+    st = lib.fl_trsm_planes(ct.byref(sp.info), _ptr(ws), ws.numel(), ct.byref(xh), ct.byref(xl), ct.byref(ldp),
+                            ct.byref(rend))
     _check(st, "fl_trsm_planes")
-    return X, Planes(ws, xh.value, xl.value, ldp.value)
+    return X, Planes(ws, xh.value, xl.value, ldp.value, rend.value)
 
 
 def reduce_cd_planes(sp: Split, planes: Planes) -> torch.Tensor:
@@ -271,7 +272,7 @@ def reduce_cd_planes(sp: Split, planes: Planes) -> torch.Tensor:
     Dt = torch.empty((max(sp.mD, 1), ld), dtype=torch.int16, device=_dev())
     ws = _ws(lib.fl_reduce_cd_planes_workspace(ct.byref(sp.info)))
     st = lib.fl_reduce_cd_planes(ct.byref(sp.info), ct.byref(sp.out), planes.xh, planes.xl, planes.ldp,
-                                 _ptr(Dt), ld, _ptr(ws), ws.numel(), _stream())
+                                 planes.row_end, _ptr(Dt), ld, _ptr(ws), ws.numel(), _stream())
     _check(st, "fl_reduce_cd_planes")
     return Dt
 

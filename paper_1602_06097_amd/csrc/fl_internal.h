@@ -173,6 +173,10 @@ struct GemmPlanes {
     uint64_t ldc;
     uint32_t M, N;
     uint32_t group_m;
+    // optional, per 128-column tile: an exclusive upper bound on the rows of
+    // B (absolute K index, before b_k0 is subtracted) that hold a nonzero in
+    // that tile's columns; K blocks past it are skipped
+    const uint32_t *kcap_n;
 };
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
 // A second stream and two events for work that overlaps the caller's stream,
@@ -184,6 +188,16 @@ hipError_t fl_mfma_rank64_planes(uint32_t p, const int8_t *Ah, const int8_t *Al,
                                  const int8_t *Bl, const uint32_t *Kdev, const uint32_t *row_map,
                                  const uint32_t *Mdev, uint32_t Mmax, uint16_t *C, uint64_t ldc,
                                  uint32_t N, hipStream_t s, const char *site);
+// Maximum of v over the 64 lanes of the wave (every lane receives it).
+__device__ __forceinline__ uint32_t fl_wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
 // Residue x -> signed int8 limbs (h, l) with centred r = 256 h + l = x mod p:
 // r = x if x <= t, else x - p, with t = 32639, or t = (p - 1) / 2 for
 // p < 256 (then r is the symmetric residue in [-127, 127]: a single limb,
@@ -242,6 +256,9 @@ struct FlTrsmTask {
     int8_t *Th, *Tl;            // limbs of I - (diagonal block)^-1, per block (int8-MFMA form)
     const uint32_t *kext, *krange;
     uint64_t kp;
+    // per 128-column tile of X: 1 + the last solved row with a nonzero there
+    // (0: none yet), raised by every block solve (int8-MFMA form)
+    uint32_t *xkend;
 };
 constexpr uint32_t kFlTrsmBlock = 128;
 constexpr uint32_t kFlTrsmSuper = 4;  // blocks per superblock of the MFMA-form update

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_limbs_rows(uint32_t p, const uint16_t *
 __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *__restrict__ B,
                                                     uint64_t ldb, uint32_t cols, uint32_t Kh,
                                                     const uint32_t *__restrict__ Kdev,
-                                                    int8_t *Bh, int8_t *Bl, uint32_t Kp) {
+                                                    int8_t *Bh, int8_t *Bl, uint32_t Kp, uint32_t *row_end) {
     constexpr uint32_t kLd = 80;  // LDS bytes per column (16-byte aligned rows)
     __shared__ __attribute__((aligned(16))) int8_t th[64 * kLd], tl[64 * kLd];
     const uint32_t K = Kdev ? *Kdev : Kh;
@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *
     const uint32_t tid = threadIdx.x, cq = tid & 15, kr = tid >> 4;  // 16 chunks x 16 rows
     const bool vec = ((((uintptr_t)B) | (uintptr_t)(ldb * 2)) & 7) == 0;
     const uint32_t c = c0 + cq * 4;
+    uint32_t last = 0;  // 1 + the last row k with a nonzero in these columns
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         const uint32_t kk = kr + 16 * i, k = k0 + kk;
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *
             else
                 for (uint32_t e = 0; e < 4 && c + e < cols; e++) v |= (uint64_t)row[c + e] << (16 * e);
         }
+        if (v) last = k + 1;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             int h, l;
@@ -77,6 +79,10 @@ __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *
             th[(cq * 4 + e) * kLd + kk] = (int8_t)h;
             tl[(cq * 4 + e) * kLd + kk] = (int8_t)l;
         }
+    }
+    if (row_end) {  // per 128-column tile (one per two workgroups along x)
+        last = fl_wave_max(last);
+        if ((tid & 63) == 0 && last) atomicMax(&row_end[c0 / 128], last);
     }
     __syncthreads();
     const uint32_t cc = tid >> 2, seg = (tid & 3) * 16;
@@ -198,7 +204,7 @@ hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, 
 // ld ldb) -> Bh, Bl (cols_pad x Kp); launch with grid (cols_pad/64, Kp/64),
 // 256 threads.
 typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
-                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t, uint32_t *);
 fl_limbs_cols_fn fl_limbs_cols_kernel() { return k_limbs_cols; }
 
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax) {
@@ -233,7 +239,7 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
     {
         dim3 g(w.Np / 64, w.Kp / 64);
         FL_PROF(site_limbs, s, hipLaunchKernelGGL(k_limbs_cols, g, dim3(256), 0, s, p, B, ldb, N, Kmax, Kdev,
-                                                  w.Bh, w.Bl, w.Kp));
+                                                  w.Bh, w.Bl, w.Kp, (uint32_t *)nullptr));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

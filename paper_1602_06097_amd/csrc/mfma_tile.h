@@ -114,6 +114,12 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         const uint32_t kd = (*g.klen_dev + BK - 1) / BK * BK;
         if (kend > kd) kend = kd;
     }
+    if (g.kcap_n) {  // rows of B past the column tile's last nonzero row: zero
+        const uint32_t cap = g.kcap_n[bx];
+        const uint32_t rel = cap > g.b_k0 ? (cap - g.b_k0 + BK - 1) / BK * BK : 0u;
+        // (a cap that would leave less than one K step keeps the range)
+        if (rel < kend && (rel <= kbeg || rel - kbeg >= BK)) kend = rel;
+    }
     v4i acc_hh[4][2], acc_mid[4][2], acc_ll[4][2];
 #pragma unroll
     for (int i = 0; i < 4; i++)

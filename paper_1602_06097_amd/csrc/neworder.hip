@@ -26,7 +26,7 @@ hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, co
                              uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
-                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t, uint32_t *);
 fl_limbs_cols_fn fl_limbs_cols_kernel();
 
 namespace {
@@ -299,7 +299,7 @@ extern "C" fl_status fl_reduce_neworder(const fl_split_info *info, const fl_spli
         FL_PROF("neworder.limbs", stream,
                 hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3((unsigned)(mp / 64), (unsigned)(t.kp / 64)), dim3(256),
                                    0, stream, p, (const uint16_t *)t.Xc, t.ldxc, mD, npiv, (const uint32_t *)nullptr,
-                                   t.Ch, t.Cl, (uint32_t)t.kp));
+                                   t.Ch, t.Cl, (uint32_t)t.kp, (uint32_t *)nullptr));
         FL_LAUNCH_CHECK("neworder limbs");
         const uint64_t np = (uint64_t)t.ntiles * 128;
         FL_HIP(fl_fill_u32((uint32_t *)t.Bh, 0, np * t.kp / 4, stream));

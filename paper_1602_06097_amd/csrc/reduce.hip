@@ -28,7 +28,7 @@ size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 namespace {
 
 typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
-                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t, uint32_t *);
 
 // ---- MFMA form: C's multiline groups sorted by first column, so that each
 // 128-row tile of the dense C operand is nonzero only on a short K range ----
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(uint32_t w, uint32_t p, ui
 struct ReduceWs {
     int8_t *Ah, *Al, *Xh, *Xl;
     uint32_t *first, *last, *bucket, *fill, *order, *rank_of, *krange, *row_map;
+    uint32_t *xend;  // per 128-column tile of X: 1 + its last nonzero row (X given as u16 only)
     uint64_t *hist, *scantmp;
     uint64_t kp;
     uint32_t ntiles, nbuckets;
@@ -178,6 +179,7 @@ size_t reduce_layout(const fl_split_info *info, fl_mode mode, bool x_planes, voi
         t.order = c.take<uint32_t>(info->mD);
         t.rank_of = c.take<uint32_t>(info->mD);
         t.krange = c.take<uint32_t>(2 * (size_t)t.ntiles);
+        if (x_planes) t.xend = c.take<uint32_t>(np / 128);
         t.row_map = c.take<uint32_t>(mp);
         t.hist = c.take<uint64_t>(t.nbuckets);
         t.scantmp = c.take<uint64_t>(fl_scan_tmp_elems(t.nbuckets));
@@ -195,8 +197,8 @@ namespace {
 // 128-row tiles with their K ranges, C as limb planes, X's limb planes (Xh,
 // Xl, row stride ldp) converted from X when X is given, then Dt -= C X.
 fl_status reduce_mfma(const fl_split_info *info, const fl_split_out *s, const uint16_t *X, uint64_t ldx,
-                      const int8_t *Xh, const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd,
-                      const ReduceWs &r, hipStream_t stream) {
+                      const int8_t *Xh, const int8_t *Xl, uint64_t ldp, const uint32_t *row_end, uint16_t *Dt,
+                      uint64_t ldd, const ReduceWs &r, hipStream_t stream) {
     const uint32_t mD = info->mD, nB = info->nB, npiv = info->npiv, w = info->ml_width;
     const uint32_t ngroups = (mD + w - 1) / w;
     FL_HIP(fl_fill_u64(r.hist, 0, r.nbuckets, stream));
@@ -219,16 +221,19 @@ fl_status reduce_mfma(const fl_split_info *info, const fl_split_out *s, const ui
         hipLaunchKernelGGL(k_tile_scatter, dim3((ngroups + 3) / 4), dim3(256), 0, stream, w, info->p, ngroups,
                            mD, (const uint64_t *)s->c_gptr, (const uint32_t *)s->c_pos,
                            (const uint16_t *)s->c_val, (const uint32_t *)r.rank_of, r.Ah, r.Al, r.kp);
-        if (X) {  // X's limb planes into the workspace
+        if (X) {  // X's limb planes into the workspace, with the last nonzero row per column tile
             const uint32_t np = (nB + 127) / 128 * 128;
+            (void)fl_fill_u32(r.xend, 0, np / 128, stream);
             hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(np / 64, (unsigned)(r.kp / 64)), dim3(256), 0,
                                stream, info->p, X, ldx, nB, npiv, (const uint32_t *)nullptr, r.Xh, r.Xl,
-                               (uint32_t)r.kp);
+                               (uint32_t)r.kp, r.xend);
         }
     });
     FL_LAUNCH_CHECK("reduce limbs");
     GemmPlanes gp = {r.Ah, r.Al, Xh, Xl, r.kp, ldp, 0, 0, 0, (uint32_t)r.kp, nullptr, r.krange,
                      nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
+    // column tiles of X past whose last nonzero row C's K range starts: skipped
+    gp.kcap_n = X ? r.xend : row_end;
     // column tiles outer, all row tiles inner (each XCD a range of column
     // tiles): C's limb planes (every row tile's K range) stay resident in the
     // last-level cache while X's planes stream through once, instead of X
@@ -276,12 +281,12 @@ extern "C" fl_status fl_reduce_cd(const fl_split_info *info, const fl_split_out 
                           ldd, nB, stream, "reduce.spmm"));
         return FL_OK;
     }
-    return reduce_mfma(info, s, X, ldx, r.Xh, r.Xl, r.kp, Dt, ldd, r, stream);
+    return reduce_mfma(info, s, X, ldx, r.Xh, r.Xl, r.kp, nullptr, Dt, ldd, r, stream);
 }
 
 extern "C" fl_status fl_reduce_cd_planes(const fl_split_info *info, const fl_split_out *s, const int8_t *Xh,
-                                         const int8_t *Xl, uint64_t ldp, uint16_t *Dt, uint64_t ldd, void *ws,
-                                         size_t ws_bytes, hipStream_t stream) {
+                                         const int8_t *Xl, uint64_t ldp, const uint32_t *row_end, uint16_t *Dt,
+                                         uint64_t ldd, void *ws, size_t ws_bytes, hipStream_t stream) {
     fl_status st = fl_check_split(info, s);
     if (st != FL_OK) return st;
     const uint32_t mD = info->mD, nB = info->nB, npiv = info->npiv;
@@ -300,7 +305,7 @@ extern "C" fl_status fl_reduce_cd_planes(const fl_split_info *info, const fl_spl
     }
     FL_HIP(fl_csr_to_dense(mD, nB, s->d_ptr, s->d_col, s->d_val, Dt, ldd, stream));
     if (npiv == 0) return FL_OK;
-    return reduce_mfma(info, s, nullptr, 0, Xh, Xl, ldp, Dt, ldd, r, stream);
+    return reduce_mfma(info, s, nullptr, 0, Xh, Xl, ldp, row_end, Dt, ldd, r, stream);
 }
 
 extern "C" size_t fl_matmul_sub_workspace(uint32_t M, uint32_t N, uint32_t K, fl_mode mode) {

@@ -26,7 +26,7 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
                             const char *site);
 size_t fl_gemm_sub_mfma_ws(uint32_t M, uint32_t N, uint32_t Kmax);
 typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
-                                 const uint32_t *, int8_t *, int8_t *, uint32_t);
+                                 const uint32_t *, int8_t *, int8_t *, uint32_t, uint32_t *);
 fl_limbs_cols_fn fl_limbs_cols_kernel();
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 
@@ -53,28 +53,50 @@ __global__ __launch_bounds__(256) void k_gather_pivcols_limbs(uint32_t p, const 
                                                               uint64_t ldx, uint32_t npiv,
                                                               const uint32_t *__restrict__ d_rank,
                                                               const uint32_t *__restrict__ pivcol,
-                                                              int8_t *Lh, int8_t *Ll, uint64_t kp) {
+                                                              int8_t *Lh, int8_t *Ll, uint64_t kp,
+                                                              uint32_t *tfirst) {
     const uint32_t r = *d_rank;
     const uint32_t t0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (t0 >= kp) return;
+    const bool act = t0 < kp;  // (every lane takes part in the wave minimum below)
     uint32_t c[4];
 #pragma unroll
-    for (int e = 0; e < 4; e++) c[e] = t0 + e < r ? pivcol[t0 + e] : 0;
+    for (int e = 0; e < 4; e++) c[e] = act && t0 + e < r ? pivcol[t0 + e] : 0;
     for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) {
         uint32_t x[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) x[e] = X[(uint64_t)i * ldx + c[e]];
-        uint32_t hw = 0, lw = 0;
+        for (int e = 0; e < 4; e++) x[e] = act ? X[(uint64_t)i * ldx + c[e]] : 0;
+        uint32_t hw = 0, lw = 0, first = 0xffffffffu;
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 3; e >= 0; e--) {
             int h = 0, l = 0;
-            if (t0 + e < r) fl_split_limbs(x[e], p, h, l);
+            if (t0 + e < r) {
+                fl_split_limbs(x[e], p, h, l);
+                if (x[e]) first = t0 + e;
+            }
             hw |= (uint32_t)(h & 0xff) << (8 * e);
             lw |= (uint32_t)(l & 0xff) << (8 * e);
         }
-        *(uint32_t *)(Lh + (uint64_t)i * kp + t0) = hw;
-        *(uint32_t *)(Ll + (uint64_t)i * kp + t0) = lw;
+        if (act) {
+            *(uint32_t *)(Lh + (uint64_t)i * kp + t0) = hw;
+            *(uint32_t *)(Ll + (uint64_t)i * kp + t0) = lw;
+        }
+        if (tfirst) {  // first pivot index t with X[i][q_t] != 0
+            first = ~fl_wave_max(~first);
+            if ((threadIdx.x & 63) == 0 && first != 0xffffffffu) atomicMin(&tfirst[i], first);
+        }
     }
+}
+
+// Per 128-row tile of L = X[:, P_D]: K range [first nonzero t of its rows,
+// rounded down to 64; kp) (empty when all its rows are zero there).
+__global__ void k_tile_kbeg(uint32_t npiv, uint32_t mtiles, const uint32_t *__restrict__ tfirst, uint32_t kp,
+                            uint32_t *krange) {
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= mtiles) return;
+    uint32_t b = 0xffffffffu;
+    for (uint32_t i = m * 128; i < m * 128 + 128 && i < npiv; i++) b = tfirst[i] < b ? tfirst[i] : b;
+    krange[2 * m] = b == 0xffffffffu ? kp : b / 64 * 64;
+    krange[2 * m + 1] = kp;
 }
 
 // For every row t < r of R_D: the 128-column output tiles its nonzeros span
@@ -287,6 +309,7 @@ struct RrefWs {
     uint64_t ldl;
     int8_t *Lh, *Ll, *Rh, *Rl;
     uint32_t *tmin, *tmax, *krange;
+    uint32_t *tfirst, *krange_m;  // per row of L / per 128-row tile of L
     uint64_t kp;
     uint32_t ntiles;
 };
@@ -308,6 +331,8 @@ size_t rref_layout(const fl_split_info *info, fl_mode mode, void *ws, RrefWs *r)
         t.tmin = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
         t.tmax = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
         t.krange = w.take<uint32_t>(2 * (size_t)(t.ntiles ? t.ntiles : 1));
+        t.tfirst = w.take<uint32_t>(mp ? mp : 1);
+        t.krange_m = w.take<uint32_t>(2 * (mp / 128 ? mp / 128 : 1));
     } else {
         t.ldl = ((uint64_t)maxr + 7) & ~(uint64_t)7;
         t.L = w.take<uint16_t>((size_t)(info->npiv ? info->npiv : 1) * (t.ldl ? t.ldl : 1));
@@ -347,11 +372,16 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
         // L = X[:, P_D] and R_D as limb planes; per 128-column tile of X the
         // range of R_D rows that are nonzero there
         dim3 g((unsigned)((r.kp / 4 + 255) / 256), npiv < 1024 ? npiv : 1024);
+        const uint32_t mtiles = (npiv + 127) / 128;
+        FL_HIP(fl_fill_u32(r.tfirst, 0xffffffffu, npiv, stream));
         FL_PROF("rref.limbs", stream, {
             hipLaunchKernelGGL(k_gather_pivcols_limbs, g, dim3(256), 0, stream, info->p, (const uint16_t *)X,
-                               ldx, npiv, d_rank, d_pivcol, r.Lh, r.Ll, r.kp);
+                               ldx, npiv, d_rank, d_pivcol, r.Lh, r.Ll, r.kp, r.tfirst);
+            hipLaunchKernelGGL(k_tile_kbeg, dim3((mtiles + 255) / 256), dim3(256), 0, stream, npiv, mtiles,
+                               (const uint32_t *)r.tfirst, (uint32_t)r.kp, r.krange_m);
             hipLaunchKernelGGL(fl_limbs_cols_kernel(), dim3(r.ntiles * 2, (unsigned)(r.kp / 64)), dim3(256), 0,
-                               stream, info->p, RD, ldd, nB, maxr, d_rank, r.Rh, r.Rl, (uint32_t)r.kp);
+                               stream, info->p, RD, ldd, nB, maxr, d_rank, r.Rh, r.Rl, (uint32_t)r.kp,
+                               (uint32_t *)nullptr);
         });
         FL_LAUNCH_CHECK("rref limbs");
         FL_HIP(fl_fill_u32(r.tmin, 0xffffffffu, r.ntiles, stream));
@@ -363,7 +393,7 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
                                (const uint32_t *)r.tmin, (const uint32_t *)r.tmax, (uint32_t)r.kp, r.krange);
         });
         FL_LAUNCH_CHECK("rref ranges");
-        GemmPlanes gp = {r.Lh, r.Ll, r.Rh, r.Rl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, d_rank, nullptr,
+        GemmPlanes gp = {r.Lh, r.Ll, r.Rh, r.Rl, r.kp, r.kp, 0, 0, 0, (uint32_t)r.kp, d_rank, r.krange_m,
                          r.krange, nullptr, X, ldx, npiv, nB};
         // groups of 4 row tiles per column tile on each XCD: the group shares
         // the column tile's R_D planes in L2 (measured: 4 beats grid order,

@@ -559,7 +559,7 @@ __global__ __launch_bounds__(fl_mfma::kGemmThreads) void k_trsm_update_mfma_b(fl
         const uint32_t rt = top * kTrsmBlock;
         const GemmPlanes g = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp, t.kp, R1,
                               R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr, nullptr,
-                              t.X + (uint64_t)rt * t.ldx, t.ldx, R1 - rt, t.nB};
+                              t.X + (uint64_t)rt * t.ldx, t.ldx, R1 - rt, t.nB, 0, t.xkend};
         fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
     } else {
         if (by != 0) return;
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(fl_mfma::kGemmThreads) void k_trsm_update_mfma_b(fl
         // past R1 is zero)
         const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1,
                               r1, 0, (R1 - r1 + 63) / 64 * 64, t.kext + I, nullptr, nullptr, nullptr,
-                              t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB};
+                              t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB, 0, t.xkend};
         fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, 0, smem);
     }
 }
@@ -582,9 +582,11 @@ template <int KS>
 __global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, uint32_t c16, const int8_t *Ah,
                                                    const int8_t *Al, const int8_t *Xh, const int8_t *Xl,
                                                    uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
-                                                   uint64_t ldx, uint32_t nB) {
+                                                   uint64_t ldx, uint32_t nB, const uint32_t *__restrict__ xkend) {
     __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[64];
+    // rows r1.. of X are zero in these columns: nothing to subtract
+    if (xkend && xkend[blockIdx.x / 2] <= r1) return;
     fl_mfma::mfma_rankk_tile<KS, 4>(md, bias, c16, Ah + (uint64_t)r0 * kp + r1, Al + (uint64_t)r0 * kp + r1,
                                     (uint32_t)kp, Xh + r1, Xl + r1, (uint32_t)kp, nullptr, r1 - r0,
                                     X + (uint64_t)r0 * ldx, ldx, nB, blockIdx.x, blockIdx.y, sv, rows_s);
@@ -592,13 +594,13 @@ __global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, ui
 
 hipError_t trsm_near(uint32_t ks, const fl::Mod &md, uint32_t p, const int8_t *Ah, const int8_t *Al,
                      const int8_t *Xh, const int8_t *Xl, uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
-                     uint64_t ldx, uint32_t nB, hipStream_t s) {
+                     uint64_t ldx, uint32_t nB, const uint32_t *xkend, hipStream_t s) {
     const dim3 grid((nB + 63) / 64, (r1 - r0 + 63) / 64);
     const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
 #define FL_NEAR(K)                                                                                         \
     case K:                                                                                                \
         hipLaunchKernelGGL(k_trsm_near<K>, grid, dim3(256), 0, s, md, bias, c16, Ah, Al, Xh, Xl, kp, r0, r1, X, \
-                           ldx, nB);                                                                       \
+                           ldx, nB, xkend);                                                                \
         break;
     switch (ks) {
         FL_NEAR(1)
@@ -671,7 +673,8 @@ struct __attribute__((aligned(16))) ApplyLds {
 __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                 const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
                                                 uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
-                                                int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t bx, ApplyLds &S) {
+                                                int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t *xkend, uint32_t bx,
+                                                ApplyLds &S) {
     using fl_mfma::v4i;
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) const v4i gv4i;
@@ -755,14 +758,21 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
             }
     }
     __syncthreads();
+    uint32_t last = 0;  // 1 + the last row of the block with a nonzero in these columns
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const uint32_t ch = tid + u * 256, r = ch >> 4, c4 = (ch & 15) * 4;
         if (r >= nrow || c0 + c4 >= nB) continue;
         uint16_t *o = X + (uint64_t)(r0 + r) * ldx + c0 + c4;
-        if (c0 + c4 + 4 <= nB) *(uint64_t *)o = *(const uint64_t *)&S.R[r][c4];
+        const uint64_t v = *(const uint64_t *)&S.R[r][c4];  // zero past nB
+        if (v) last = r0 + r + 1;
+        if (c0 + c4 + 4 <= nB) *(uint64_t *)o = v;
         else
             for (uint32_t k = 0; c0 + c4 + k < nB; k++) o[k] = S.R[r][c4 + k];
+    }
+    if (xkend) {
+        last = fl_wave_max(last);
+        if (lane == 0 && last) atomicMax(&xkend[c0 / 128], last);
     }
     // transposed limb planes of the finished rows: column c, rows r0 + 16 g ..
 #pragma unroll
@@ -793,9 +803,9 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
 __global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, uint32_t c16,
                                                     const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
                                                     uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
-                                                    int8_t *Xh, int8_t *Xl, uint64_t kp) {
+                                                    int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t *xkend) {
     __shared__ ApplyLds S;
-    trsm_apply_tile(md, bias, c16, Th, Tl, r0, r1, X, ldx, nB, Xh, Xl, kp, blockIdx.x, S);
+    trsm_apply_tile(md, bias, c16, Th, Tl, r0, r1, X, ldx, nB, Xh, Xl, kp, xkend, blockIdx.x, S);
 }
 
 // The same for many matrices: the step's block of every MFMA-form matrix,
@@ -809,7 +819,8 @@ __global__ __launch_bounds__(256) void k_trsm_apply_b(fl::Mod md, uint32_t bias,
     const FlTrsmTask &t = tasks[ids[i]];
     uint32_t I, r0, r1;
     if (!step_block(t, step, I, r0, r1)) return;
-    trsm_apply_tile(md, bias, c16, t.Th, t.Tl, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp, blockIdx.x - prefix[i], S);
+    trsm_apply_tile(md, bias, c16, t.Th, t.Tl, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp, t.xkend,
+                    blockIdx.x - prefix[i], S);
 }
 
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
@@ -931,6 +942,7 @@ struct TrsmWs {
     int8_t *Th, *Tl;    // [nblk * 128 x 128] limb planes of I - (block inverse)
     uint32_t *kext, *krange;
     uint32_t *nin, *nnear;
+    uint32_t *xkend;    // [ceil(nB / 128)] see FlTrsmTask::xkend
     uint64_t kp;
 };
 
@@ -956,6 +968,7 @@ size_t trsm_layout(const fl_split_info *info, fl_mode mode, void *ws, TrsmWs *t)
         r.Y = c.take<uint16_t>(mp * kTrsmBlock);
         r.Th = c.take<int8_t>(mp * kTrsmBlock);
         r.Tl = c.take<int8_t>(mp * kTrsmBlock);
+        r.xkend = c.take<uint32_t>(np / 128);
     }
     if (t) *t = r;
     return c.off;
@@ -1009,7 +1022,8 @@ extern "C" size_t fl_trsm_workspace(const fl_split_info *info, fl_mode mode) {
 // The limb planes of X that an MFMA-form fl_trsm leaves in its workspace
 // (written by the block solves, read by the far and near updates).
 extern "C" fl_status fl_trsm_planes(const fl_split_info *info, const void *ws, size_t ws_bytes,
-                                    const int8_t **Xh, const int8_t **Xl, uint64_t *ldp) {
+                                    const int8_t **Xh, const int8_t **Xl, uint64_t *ldp,
+                                    const uint32_t **row_end) {
     FL_ARG(info && Xh && Xl && ldp, "fl_trsm_planes: NULL argument");
     FL_ARG(info->npiv && info->nB, "fl_trsm_planes: empty X (npiv or nB is 0)");
     TrsmWs tw;
@@ -1018,6 +1032,7 @@ extern "C" fl_status fl_trsm_planes(const fl_split_info *info, const void *ws, s
     *Xh = tw.Xh;
     *Xl = tw.Xl;
     *ldp = tw.kp;
+    if (row_end) *row_end = tw.xkend;
     return FL_OK;
 }
 
@@ -1071,6 +1086,7 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
                                (const uint32_t *)s->a_pos, (const uint16_t *)s->a_val, tw.Ah, tw.Al, tw.kp);
         });
         FL_LAUNCH_CHECK("trsm tiles");
+        FL_HIP(fl_fill_u32(tw.xkend, 0, (nB + 127) / 128, stream));
         const uint32_t rows = nblk * kTrsmBlock;
         const unsigned ge = (unsigned)(((uint64_t)rows * kTrsmBlock + 255) / 256);
         const fl::Mod md = fl::make_mod(info->p);
@@ -1099,6 +1115,7 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
     t.Th = tw.Th;
     t.Tl = tw.Tl;
     t.kp = tw.kp;
+    t.xkend = tw.xkend;
     *task = t;
     return FL_OK;
 }
@@ -1174,6 +1191,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                                      t.kp, R1, R1, 0, (R2 - R1 + 63) / 64 * 64, nullptr, t.krange + 2 * top, nullptr,
                                      nullptr, X + (uint64_t)rt * ldx, ldx, R1 - rt, nB};
                     gp.group_m = kFlTrsmSuper;  // the superblock's row tiles share each B column tile
+                    gp.kcap_n = t.xkend;        // column tiles where those rows of X are zero: skipped
                     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma"));
                     // the superblock above [ru, rt): its terms from rows at or past R1,
                     // issued after the critical-path GEMM, which then does not queue behind it
@@ -1186,6 +1204,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                                          t.kp, rt, rt, R1 - rt, (uint32_t)(t.kp - rt), nullptr, t.krange + 2 * topu,
                                          nullptr, nullptr, X + (uint64_t)ru * ldx, ldx, rt - ru, nB};
                         gf.group_m = kFlTrsmSuper;
+                        gf.kcap_n = t.xkend;
                         FL_HIP(fl_mfma_gemm_planes(info->p, gf, far_s, "trsm.update.far"));
                         FL_HIP(hipEventRecord(ev_far, far_s));
                         far_pending = true;
@@ -1193,7 +1212,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                 } else {  // near update: the blocks of the superblock solved since
                     FL_PROF("trsm.update.near", stream,
                             e = trsm_near((R1 - r1 + 63) / 64, md, info->p, t.Ah, t.Al, t.Xh, t.Xl, t.kp, r0, r1,
-                                          X, ldx, nB, stream));
+                                          X, ldx, nB, t.xkend, stream));
                 }
             } else {
                 const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
@@ -1209,7 +1228,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                     hipLaunchKernelGGL(k_trsm_apply, dim3((nB + 63) / 64), dim3(256), 0, stream, md,
                                        fl_mfma::gemm_bias(info->p), fl_mfma::gemm_c16(info->p),
                                        (const int8_t *)t.Th, (const int8_t *)t.Tl, r0, r1, X, ldx, nB, t.Xh, t.Xl,
-                                       t.kp));
+                                       t.kp, t.xkend));
             e = hipGetLastError();
         } else {
             FL_PROF("trsm.solve", stream,
