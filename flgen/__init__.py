@@ -106,13 +106,37 @@ def _modp(a: sp.csr_matrix, p: int) -> sp.csr_matrix:
     return a
 
 
-def _pack(a: sp.csr_matrix) -> dict:
+def _spmm_mod(a: sp.csr_matrix, b: sp.csr_matrix, p: int) -> sp.csr_matrix:
+    """a @ b mod p with int64 sums that cannot overflow: for p >= 2^16 the
+    entries of b are split into 16-bit halves (each term then stays below
+    2^48, and the factors here have few terms per output entry)."""
+    if p < (1 << 16):
+        return _modp(a @ b, p)
+    b = b.tocsr()
+    lo = sp.csr_matrix((b.data & 0xFFFF, b.indices, b.indptr), shape=b.shape)
+    hi = sp.csr_matrix((b.data >> 16, b.indices, b.indptr), shape=b.shape)
+    h = _modp(a @ hi, p)
+    h.data = (h.data << 16) % p
+    return _modp(h + _modp(a @ lo, p), p)
+
+
+def _vtype(p: int):
+    """Storage type of residues: uint16 below 2^16, else uint32."""
+    return np.uint16 if p <= (1 << 16) else np.uint32
+
+
+def _pack(a: sp.csr_matrix, p: int = 2) -> dict:
     a = a.tocsr()
     a.sort_indices()
     return dict(m=a.shape[0], n=a.shape[1],
                 row_ptr=a.indptr.astype(np.uint64),
                 col=a.indices.astype(np.uint32),
-                val=a.data.astype(np.uint16))
+                val=a.data.astype(_vtype(p)))
+
+
+def _axpy_mod(d: np.ndarray, x: int, v: np.ndarray, p: int) -> np.ndarray:
+    """(d + x v) mod p elementwise for residues (uint64: no overflow for p < 2^32)."""
+    return (d.astype(np.uint64) + (np.uint64(x) * v.astype(np.uint64)) % np.uint64(p)) % np.uint64(p)
 
 
 def fl_matrix(m: int, n: int, npiv: int, rank_d: int, density: float, p: int,
@@ -180,7 +204,7 @@ def fl_matrix(m: int, n: int, npiv: int, rank_d: int, density: float, p: int,
         vals_t.append(rng.integers(1, p, size=len(ri)))
     T = sp.csr_matrix((np.concatenate(vals_t), (np.concatenate(rows_t), np.concatenate(cols_t))),
                       shape=(mD, r))
-    P = _modp(T @ V, p) if r > 0 else sp.csr_matrix((mD, nB), dtype=np.int64)
+    P = _spmm_mod(T, V, p) if r > 0 else sp.csr_matrix((mD, nB), dtype=np.int64)
     P = _modp(P[rng.permutation(mD)], p)
 
     # Pivot rows, in runs sharing one clustered support right of the run's
@@ -208,7 +232,7 @@ def fl_matrix(m: int, n: int, npiv: int, rank_d: int, density: float, p: int,
     si = _segment_arange(sl)
     piv_col[np.repeat(piv_ptr[:-1] + lead_cnt, sl) + si] = s_cols[np.repeat(s_off[run_of], sl) + si]
     del si, s_cols
-    piv_val = rng.integers(1, p, size=len(piv_col), dtype=np.int32)
+    piv_val = rng.integers(1, p, size=len(piv_col), dtype=np.int32 if p < (1 << 31) else np.int64)
     piv_val[piv_ptr[:-1]] = 1  # monic
     PIV = sp.csr_matrix((piv_val, piv_col, piv_ptr), shape=(npiv, n))
     del piv_col, piv_val
@@ -243,7 +267,7 @@ def fl_matrix(m: int, n: int, npiv: int, rank_d: int, density: float, p: int,
     S = sp.csr_matrix((sval[keep], (srow[keep], scol[keep])), shape=(mD, npiv))
     Pexp = sp.csr_matrix((P.data, nonpiv[P.indices] if nB else P.indices, P.indptr), shape=(mD, n))
     PIV64 = sp.csr_matrix((PIV.data.astype(np.int64), PIV.indices, PIV.indptr), shape=PIV.shape)
-    CD = _modp(S @ PIV64 + Pexp, p)
+    CD = _modp(_spmm_mod(S, PIV64, p) + Pexp, p)
     del PIV64, Pexp
 
     # Selection rule check: min (nnz, index) among rows sharing a lead must be
@@ -269,7 +293,7 @@ def fl_matrix(m: int, n: int, npiv: int, rank_d: int, density: float, p: int,
     row_ptr = np.zeros(m + 1, dtype=np.uint64)
     np.cumsum(row_len_out, out=row_ptr[1:])
     col = np.empty(int(row_ptr[-1]), dtype=np.uint32)
-    val = np.empty(int(row_ptr[-1]), dtype=np.uint16)
+    val = np.empty(int(row_ptr[-1]), dtype=_vtype(p))
     dst = 0
     cd_order = []
     for b in order:
@@ -315,7 +339,7 @@ def random_sparse(m: int, n: int, density: float, p: int, seed: int,
             if len(nz):
                 vals[i, nz[0]] = 1
     a = sp.csr_matrix(vals.astype(np.int64))
-    out = _pack(_modp(a, p))
+    out = _pack(_modp(a, p), p)
     out.update(p=p)
     return out
 
@@ -338,20 +362,20 @@ def dense_planted_rank(rows: int, cols: int, rank: int, p: int, seed: int) -> di
     for k in range(1, rank):
         js = rng.integers(0, k, size=min(k, 3))
         for j in js:
-            D[k] = (D[k] + int(rng.integers(1, p)) * D[j]) % p
+            D[k] = _axpy_mod(D[k], int(rng.integers(1, p)), D[j], p)
     for i in range(rank, rows):
         js = rng.integers(0, max(rank, 1), size=4) if rank else []
         for j in js:
-            D[i] = (D[i] + int(rng.integers(1, p)) * V[j]) % p
+            D[i] = _axpy_mod(D[i], int(rng.integers(1, p)), V[j], p)
     D = D[rng.permutation(rows)]
-    return dict(D=D.astype(np.uint16), V=V.astype(np.uint16), pivcols=q.astype(np.uint32),
+    return dict(D=D.astype(_vtype(p)), V=V.astype(_vtype(p)), pivcols=q.astype(np.uint32),
                 rank=rank, p=p)
 
 
 def csr_to_dense(mat: dict) -> np.ndarray:
-    """Dense uint16 copy of a CSR dict (tiny inputs only)."""
+    """Dense copy (the value type of the CSR dict) of a CSR dict (tiny inputs only)."""
     m, n = mat["m"], mat["n"]
-    out = np.zeros((m, n), dtype=np.uint16)
+    out = np.zeros((m, n), dtype=mat["val"].dtype)
     rp = mat["row_ptr"].astype(np.int64)
     for i in range(m):
         out[i, mat["col"][rp[i]:rp[i + 1]]] = mat["val"][rp[i]:rp[i + 1]]

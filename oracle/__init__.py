@@ -4,7 +4,8 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 import this package.  The device library never loads, links or calls it, and
 the two share no code.
 
-``fl_oracle.c`` holds the plain FL steps (Sec. 4.1 of the paper, plus the new
+``fl_oracle_wide.c`` holds the same steps for uint32 residues (32-bit
+primes; every product reduced at once).  ``fl_oracle.c`` holds the plain FL steps (Sec. 4.1 of the paper, plus the new
 order of operations of Sec. 4.3 as an independent route to the Schur
 complement); ``bruteforce.c`` is direct Gauss-Jordan on the whole matrix;
 ``bruteforce.py`` is pure-Python Gauss-Jordan for tiny inputs.  This module
@@ -20,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["fl_oracle.c", "bruteforce.c"]
+_SOURCES = ["fl_oracle.c", "fl_oracle_wide.c", "bruteforce.c"]
 _lib = None
 
 P_U64 = ct.POINTER(ct.c_uint64)
@@ -75,6 +76,27 @@ def _load():
     lib.or_assemble.restype = ct.c_uint64
     lib.or_assemble.argtypes = [ct.c_uint32, ct.c_uint32, ct.c_uint32, P_U32, P_U16, ct.c_uint64,
                                 ct.c_uint32, P_U16, ct.c_uint64, P_U32, P_U64, P_U32, P_U16]
+    lib.ow_inv.restype = ct.c_uint32
+    lib.ow_inv.argtypes = [ct.c_uint32, ct.c_uint32]
+    lib.ow_validate.restype = ct.c_int
+    lib.ow_validate.argtypes = [ct.c_uint32, ct.c_uint32, P_U64, P_U32, P_U32, ct.c_uint32]
+    lib.ow_split.restype = ct.c_uint32
+    lib.ow_split.argtypes = [ct.c_uint32, ct.c_uint32, P_U64, P_U32, P_U32, ct.c_uint32,
+                             P_U32, P_U32] + [P_U64, P_U32, P_U32] * 4
+    lib.ow_trsm.restype = ct.c_int
+    lib.ow_trsm.argtypes = [ct.c_uint32, ct.c_uint32, P_U64, P_U32, P_U32, P_U64, P_U32, P_U32,
+                            ct.c_uint32, P_U32, ct.c_uint64]
+    lib.ow_reduce.restype = None
+    lib.ow_reduce.argtypes = [ct.c_uint32, ct.c_uint32, P_U64, P_U32, P_U32, P_U64, P_U32, P_U32,
+                              P_U32, ct.c_uint64, ct.c_uint32, P_U32, ct.c_uint64]
+    lib.ow_rref_dense.restype = ct.c_uint32
+    lib.ow_rref_dense.argtypes = [ct.c_uint32, ct.c_uint32, P_U32, ct.c_uint64, ct.c_uint32, P_U32]
+    lib.ow_second_pass.restype = None
+    lib.ow_second_pass.argtypes = [ct.c_uint32, ct.c_uint32, P_U32, ct.c_uint64, ct.c_uint32,
+                                   P_U32, ct.c_uint64, P_U32, ct.c_uint32]
+    lib.ow_assemble.restype = ct.c_uint64
+    lib.ow_assemble.argtypes = [ct.c_uint32, ct.c_uint32, ct.c_uint32, P_U32, P_U32, ct.c_uint64,
+                                ct.c_uint32, P_U32, ct.c_uint64, P_U32, P_U64, P_U32, P_U32]
     lib.bf_rref_csr.restype = ct.c_uint64
     lib.bf_rref_csr.argtypes = [ct.c_uint32, ct.c_uint32, P_U64, P_U32, P_U16, ct.c_uint32, P_U32,
                                 P_U64, P_U32, P_U16]
@@ -302,3 +324,124 @@ def bruteforce_rref(mat: dict):
     v = np.zeros(max(nnz, 1), np.uint16)
     lib.bf_rref_csr(*args, _p(rp, P_U64), _p(ci, P_U32), _p(v, P_U16))
     return (rp, ci[:nnz].copy(), v[:nnz].copy()), rank.value
+
+
+# ---- 32-bit field characteristic (uint32 residues) ---------------------------
+
+def _csr_args32(rp, ci, v):
+    return [_p(rp, P_U64), _p(ci, P_U32), _p(v, P_U32)]
+
+
+def validate_wide(mat: dict) -> int:
+    lib = _load()
+    return int(lib.ow_validate(mat["m"], mat["n"], *_csr_args32(mat["row_ptr"], mat["col"],
+                                                                 np.ascontiguousarray(mat["val"], np.uint32)),
+                               mat["p"]))
+
+
+def split_wide(mat: dict) -> dict:
+    """FL step 1 over uint32 residues (same readings as split)."""
+    lib = _load()
+    m, n, p = mat["m"], mat["n"], mat["p"]
+    nnz = int(mat["row_ptr"][-1])
+    col_perm = np.zeros(n, np.uint32)
+    row_perm = np.zeros(m, np.uint32)
+    bufs = [(np.zeros(m + 1, np.uint64), np.zeros(max(nnz, 1), np.uint32), np.zeros(max(nnz, 1), np.uint32))
+            for _ in range(4)]
+    args = []
+    for b in bufs:
+        args += _csr_args32(*b)
+    val = np.ascontiguousarray(mat["val"], np.uint32)
+    npiv = int(lib.ow_split(m, n, *_csr_args32(mat["row_ptr"], mat["col"], val), p,
+                            _p(col_perm, P_U32), _p(row_perm, P_U32), *args))
+    mD, nB = m - npiv, n - npiv
+    out = dict(npiv=npiv, mD=mD, nB=nB, m=m, n=n, p=p, col_perm=col_perm, row_perm=row_perm)
+    for name, b, r in zip("ABCD", bufs, [npiv, npiv, mD, mD]):
+        rp = b[0][:r + 1].copy()
+        k = int(rp[-1])
+        out[name] = (rp, b[1][:k].copy(), b[2][:k].copy())
+    return out
+
+
+def trsm_wide(s: dict) -> np.ndarray:
+    lib = _load()
+    npiv, nB = s["npiv"], s["nB"]
+    X = np.zeros((npiv, nB), np.uint32)
+    if npiv == 0:
+        return X
+    rc = lib.ow_trsm(npiv, nB, *_csr_args32(*s["A"]), *_csr_args32(*s["B"]), s["p"], _p(X, P_U32), max(nB, 1))
+    assert rc == 0, "A is not unit upper triangular"
+    return X
+
+
+def reduce_wide(s: dict, X: np.ndarray) -> np.ndarray:
+    lib = _load()
+    Dt = np.zeros((s["mD"], s["nB"]), np.uint32)
+    if s["mD"] == 0:
+        return Dt
+    X = np.ascontiguousarray(X, np.uint32)
+    lib.ow_reduce(s["mD"], s["nB"], *_csr_args32(*s["C"]), *_csr_args32(*s["D"]), _p(X, P_U32),
+                  max(X.shape[1], 1), s["p"], _p(Dt, P_U32), max(s["nB"], 1))
+    return Dt
+
+
+def rref_dense_wide(D: np.ndarray, p: int):
+    """(R, rank, pivcols): R is a copy of D with rows 0..rank-1 = RREF."""
+    lib = _load()
+    R = np.ascontiguousarray(D, dtype=np.uint32).copy()
+    rows, cols = R.shape
+    piv = np.zeros(max(min(rows, cols), 1), np.uint32)
+    if rows == 0 or cols == 0:
+        return R, 0, piv[:0]
+    rank = int(lib.ow_rref_dense(rows, cols, _p(R, P_U32), cols, p, _p(piv, P_U32)))
+    return R, rank, piv[:rank].copy()
+
+
+def second_pass_wide(X: np.ndarray, R: np.ndarray, rank: int, pivcols: np.ndarray, p: int) -> np.ndarray:
+    lib = _load()
+    Xp = np.ascontiguousarray(X, dtype=np.uint32).copy()
+    npiv, nB = Xp.shape
+    if npiv == 0 or rank == 0:
+        return Xp
+    R = np.ascontiguousarray(R, dtype=np.uint32)
+    pc = np.ascontiguousarray(pivcols, dtype=np.uint32)
+    lib.ow_second_pass(npiv, nB, _p(Xp, P_U32), max(nB, 1), rank, _p(R, P_U32), max(R.shape[1], 1),
+                       _p(pc, P_U32), p)
+    return Xp
+
+
+def assemble_wide(n: int, npiv: int, col_perm, Xp, rank: int, R, pivcols):
+    lib = _load()
+    nB = n - npiv
+    Xp = np.ascontiguousarray(Xp, dtype=np.uint32).reshape(npiv, nB) if npiv else np.zeros((0, nB), np.uint32)
+    R = np.ascontiguousarray(R, dtype=np.uint32)
+    if R.size == 0:
+        R = np.zeros((1, max(nB, 1)), np.uint32)
+    pc = np.ascontiguousarray(pivcols, dtype=np.uint32)
+    if pc.size == 0:
+        pc = np.zeros(1, np.uint32)
+    cp = np.ascontiguousarray(col_perm, dtype=np.uint32)
+    Xarg = Xp if Xp.size else np.zeros(1, np.uint32)
+    args = [n, npiv, nB, _p(cp, P_U32), _p(Xarg, P_U32), max(nB, 1), rank, _p(R, P_U32),
+            max(R.shape[1], 1), _p(pc, P_U32)]
+    nnz = int(lib.ow_assemble(*args, _p(None, P_U64), None, None))
+    rp = np.zeros(npiv + rank + 1, np.uint64)
+    ci = np.zeros(max(nnz, 1), np.uint32)
+    v = np.zeros(max(nnz, 1), np.uint32)
+    lib.ow_assemble(*args, _p(rp, P_U64), _p(ci, P_U32), _p(v, P_U32))
+    return rp, ci[:nnz].copy(), v[:nnz].copy()
+
+
+def fl_rref_wide(mat: dict, keep: bool = True) -> dict:
+    """The whole oracle pipeline over uint32 residues (p < 2^32)."""
+    s = split_wide(mat)
+    p = mat["p"]
+    X = trsm_wide(s)
+    Dt = reduce_wide(s, X)
+    R, r, pc = rref_dense_wide(Dt, p)
+    Xp = second_pass_wide(X, R, r, pc, p)
+    out_csr = assemble_wide(mat["n"], s["npiv"], s["col_perm"], Xp, r, R[:r], pc)
+    res = dict(split=s, rank_d=r, pivcols=pc, rank=s["npiv"] + r, rref=out_csr)
+    if keep:
+        res.update(X=X, Dt=Dt, RD=R[:r].copy(), Xp=Xp)
+    return res
