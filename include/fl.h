@@ -419,6 +419,93 @@ fl_status fl_file_decode(const fl_file_layout *layout, const void *const *d_sect
                          uint32_t *col, uint16_t *val, uint32_t *d_status, void *ws, size_t ws_bytes,
                          hipStream_t stream);
 
+/* ==== 32-bit field characteristic ==========================================
+ * Sec. 2 lists, beside the uint16 coefficients for p < 2^16, a version for
+ * 32-bit field characteristic with uint32 coefficients.  The calls below
+ * run the same five steps with the same readings over uint32 residues,
+ * p prime, 2 <= p < 2^32 (p's primality is not checked).  Arithmetic:
+ * 64-bit products reduced by Barrett (mu = floor((2^64 - 1) / p)), sums of
+ * raw products in 64 bits with 2^64 mod p folded back on wrap-around.
+ * FL_PLAIN runs every step on the vector ALUs.  FL_MFMA_I8 runs the dense
+ * contractions (the reduce with C as a dense operand, the echelon step's
+ * rank-k updates, the second pass) on the int8 matrix cores: a residue is
+ * centred to r = x (x <= 2139062143) or x - p and written as four balanced
+ * signed bytes; the 16 limb products per multiply-add are summed into seven
+ * int32 diagonals over K chunks of at most 32,704 terms (4 * 2^14 * K <
+ * 2^31), then combined mod p.  The TRSM is the sparse back substitution of
+ * Sec. 4.1 step 2 on the vector ALUs in both forms.  Results are
+ * bit-identical across forms.  Conventions (device pointers owned by the
+ * caller, workspaces, errors, single syncs) are those of the uint16 calls;
+ * dense matrices are row-major uint32 with leading dimension >= their
+ * column count. */
+typedef struct {
+    uint32_t rows, cols;
+    uint64_t nnz;
+    const uint64_t *row_ptr; /* [rows + 1]                                    */
+    const uint32_t *col;     /* [nnz], strictly increasing within each row    */
+    const uint32_t *val;     /* [nnz], in [1, p-1]                            */
+} fl_csr32;
+
+/* fl_split_out with uint32 values (same capacities). */
+typedef struct {
+    uint32_t *row_perm, *col_perm;
+    uint64_t *a_gptr;
+    uint32_t *a_pos;
+    uint32_t *a_val;     /* [w * nnz] */
+    uint64_t *b_ptr;
+    uint32_t *b_col;
+    uint32_t *b_val;     /* [nnz]     */
+    uint64_t *c_gptr;
+    uint32_t *c_pos;
+    uint32_t *c_val;     /* [w * nnz] */
+    uint64_t *d_ptr;
+    uint32_t *d_col;
+    uint32_t *d_val;     /* [nnz]     */
+} fl_split_out32;
+
+/* Step 1 (Sec. 3.1, Sec. 4.1 step 1) over uint32 residues; the layout,
+ * rules, workspace (fl_split_workspace) and the single sync are those of
+ * fl_split.  FL_ERR_ARG for p < 2. */
+fl_status fl_split32(const fl_csr32 *M, uint32_t p, uint32_t ml_width, const fl_split_out32 *out,
+                     fl_split_info *h_info, void *ws, size_t ws_bytes, hipStream_t stream);
+/* Step 2 (Sec. 4.1): X = A^{-1} B, dense npiv x nB (ldx >= nB), by back
+ * substitution over 64-row blocks: the entries of A past a block are
+ * applied as one sparse update of the block's rows, then the block is
+ * solved row by row. */
+fl_status fl_trsm32(const fl_split_info *info, const fl_split_out32 *s, uint32_t *X, uint64_t ldx,
+                    fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_trsm32_workspace(const fl_split_info *info, fl_mode mode);
+/* Step 3 (Sec. 4.1): Dt = D - C X, dense mD x nB (ldd >= nB). */
+fl_status fl_reduce_cd32(const fl_split_info *info, const fl_split_out32 *s, const uint32_t *X, uint64_t ldx,
+                         uint32_t *Dt, uint64_t ldd, fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_reduce_cd32_workspace(const fl_split_info *info, fl_mode mode);
+/* Step 4 (Sec. 4.1 step 4, Sec. 4.4), read as the reduced row echelon form
+ * of the dense rows x cols matrix Dt, in place (rows 0..r-1 = RREF, pivots
+ * ascending in d_pivcol, the other rows zero, *d_rank = r): blocked
+ * Gauss-Jordan over 64-column panels (pivot search in one workgroup, then
+ * a rank-k update of every row, k <= 64). */
+fl_status fl_echelon_d32(uint32_t p, uint32_t rows, uint32_t cols, uint32_t *Dt, uint64_t ldd,
+                         uint32_t *d_rank, uint32_t *d_pivcol, fl_mode mode, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+size_t fl_echelon_d32_workspace(uint32_t rows, uint32_t cols, fl_mode mode);
+/* Second pass (end of Sec. 4.1): X <- X - X[:, P_D] R_D in place. */
+fl_status fl_rref32(const fl_split_info *info, const fl_split_out32 *s, uint32_t *X, uint64_t ldx,
+                    const uint32_t *RD, uint64_t ldd, const uint32_t *d_rank, const uint32_t *d_pivcol,
+                    fl_mode mode, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_rref32_workspace(const fl_split_info *info, fl_mode mode);
+/* Step 5 (Sec. 4.1): the canonical CSR of RREF(M) in the original column
+ * order with uint32 values, in two calls as fl_rref_csr_size /
+ * fl_rref_to_csr (the first synchronises and returns rank and nonzeros). */
+fl_status fl_rref32_csr_size(const fl_split_info *info, const fl_split_out32 *s, const uint32_t *Xp,
+                             uint64_t ldx, const uint32_t *RD, uint64_t ldd, const uint32_t *d_rank,
+                             const uint32_t *d_pivcol, uint64_t *row_ptr, uint32_t *h_rank, uint64_t *h_nnz,
+                             void *ws, size_t ws_bytes, hipStream_t stream);
+fl_status fl_rref32_to_csr(const fl_split_info *info, const fl_split_out32 *s, const uint32_t *Xp,
+                           uint64_t ldx, const uint32_t *RD, uint64_t ldd, const uint32_t *d_rank,
+                           const uint32_t *d_pivcol, const uint64_t *row_ptr, uint32_t *col, uint32_t *val,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+size_t fl_rref32_csr_workspace(const fl_split_info *info);
+
 /* ---- helpers ----------------------------------------------------------------- */
 const char *fl_status_string(fl_status s);
 const char *fl_last_error(void);   /* thread-local; "" if none */

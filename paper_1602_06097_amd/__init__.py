@@ -115,6 +115,23 @@ def load():
         "fl_rref_csr_size_noalloc": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
                                                 c_vp, c_vp, P(c_u32), P(c_u64), c_vp]),
         "fl_rref_csr_noalloc_scratch_bytes": (c_sz, []),
+        "fl_split32": (ct.c_int, [P(FlCsr), c_u32, c_u32, P(FlSplitOut), P(FlSplitInfo), c_vp, c_sz, c_vp]),
+        "fl_trsm32": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_trsm32_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_reduce_cd32": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, ct.c_int,
+                                      c_vp, c_sz, c_vp]),
+        "fl_reduce_cd32_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_echelon_d32": (ct.c_int, [c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_vp, ct.c_int, c_vp, c_sz,
+                                      c_vp]),
+        "fl_echelon_d32_workspace": (c_sz, [c_u32, c_u32, ct.c_int]),
+        "fl_rref32": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp, c_vp,
+                                 ct.c_int, c_vp, c_sz, c_vp]),
+        "fl_rref32_workspace": (c_sz, [P(FlSplitInfo), ct.c_int]),
+        "fl_rref32_csr_size": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
+                                          c_vp, c_vp, P(c_u32), P(c_u64), c_vp, c_sz, c_vp]),
+        "fl_rref32_to_csr": (ct.c_int, [P(FlSplitInfo), P(FlSplitOut), c_vp, c_u64, c_vp, c_u64, c_vp,
+                                        c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+        "fl_rref32_csr_workspace": (c_sz, [P(FlSplitInfo)]),
         "fl_matmul_sub": (ct.c_int, [c_u32, c_u32, c_u32, c_u32, c_vp, c_u64, c_vp, c_u64, c_vp, c_u64,
                                      ct.c_int, c_vp, c_sz, c_vp]),
         "fl_matmul_sub_workspace": (c_sz, [c_u32, c_u32, c_u32, ct.c_int]),
@@ -531,3 +548,107 @@ def check_modp(primes) -> list:
     _check(st, "fl_check_modp")
     torch.cuda.synchronize()
     return [int(x) for x in out.cpu()]
+
+
+# ---- 32-bit field characteristic (uint32 residues, p < 2^32) --------------------
+# fl_csr32 / fl_split_out32 have the layouts of fl_csr / fl_split_out (every
+# array is a pointer), so the same ctypes structures marshal them.
+
+def split32(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, m: int, n: int, p: int,
+            ml_width: int = 2) -> Split:
+    """split over uint32 residues (val: int32 storage of uint32 values)."""
+    lib = load()
+    nnz = int(col.numel())
+    w = int(ml_width)
+    G = (m + w - 1) // w + 1
+    d = _dev()
+
+    def e(n_, dt):
+        return torch.empty(max(n_, 1), dtype=dt, device=d)
+
+    bufs = dict(row_perm=e(m, torch.int32), col_perm=e(n, torch.int32),
+                a_gptr=e(G, torch.int64), a_pos=e(nnz, torch.int32), a_val=e(w * nnz, torch.int32),
+                b_ptr=e(m + 1, torch.int64), b_col=e(nnz, torch.int32), b_val=e(nnz, torch.int32),
+                c_gptr=e(G, torch.int64), c_pos=e(nnz, torch.int32), c_val=e(w * nnz, torch.int32),
+                d_ptr=e(m + 1, torch.int64), d_col=e(nnz, torch.int32), d_val=e(nnz, torch.int32))
+    out = FlSplitOut(**{k: c_vp(v.data_ptr()) for k, v in bufs.items()})
+    M = FlCsr(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val))
+    info = FlSplitInfo()
+    ws = _ws(lib.fl_split_workspace(m, n, nnz, w))
+    st = lib.fl_split32(ct.byref(M), p, w, ct.byref(out), ct.byref(info), _ptr(ws), ws.numel(), _stream())
+    _check(st, "fl_split32")
+    bufs["_input"] = (row_ptr, col, val)
+    return Split(info=info, out=out, bufs=bufs)
+
+
+def trsm32(sp: Split, mode: int = FL_PLAIN) -> torch.Tensor:
+    lib = load()
+    ld = _ld(sp.nB)
+    X = torch.empty((max(sp.npiv, 1), ld), dtype=torch.int32, device=_dev())
+    ws = _ws(lib.fl_trsm32_workspace(ct.byref(sp.info), mode))
+    _check(lib.fl_trsm32(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), ld, mode, _ptr(ws), ws.numel(), _stream()),
+           "fl_trsm32")
+    return X
+
+
+def reduce_cd32(sp: Split, X: torch.Tensor, mode: int = FL_PLAIN) -> torch.Tensor:
+    lib = load()
+    ld = _ld(sp.nB)
+    Dt = torch.empty((max(sp.mD, 1), ld), dtype=torch.int32, device=_dev())
+    ws = _ws(lib.fl_reduce_cd32_workspace(ct.byref(sp.info), mode))
+    _check(lib.fl_reduce_cd32(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), X.shape[1], _ptr(Dt), ld, mode,
+                              _ptr(ws), ws.numel(), _stream()), "fl_reduce_cd32")
+    return Dt
+
+
+def echelon_d32(Dt: torch.Tensor, p: int, rows: int, cols: int, mode: int = FL_PLAIN) -> Echelon:
+    lib = load()
+    d = _dev()
+    rank = torch.zeros(1, dtype=torch.int32, device=d)
+    piv = torch.zeros(max(min(rows, cols), 1), dtype=torch.int32, device=d)
+    ws = _ws(lib.fl_echelon_d32_workspace(rows, cols, mode))
+    _check(lib.fl_echelon_d32(p, rows, cols, _ptr(Dt), Dt.shape[1], _ptr(rank), _ptr(piv), mode, _ptr(ws),
+                              ws.numel(), _stream()), "fl_echelon_d32")
+    return Echelon(rank=rank, pivcol=piv, rows=rows, cols=cols)
+
+
+def rref32(sp: Split, X: torch.Tensor, Dt: torch.Tensor, ech: Echelon, mode: int = FL_PLAIN) -> None:
+    lib = load()
+    ws = _ws(lib.fl_rref32_workspace(ct.byref(sp.info), mode))
+    _check(lib.fl_rref32(ct.byref(sp.info), ct.byref(sp.out), _ptr(X), X.shape[1], _ptr(Dt), Dt.shape[1],
+                         _ptr(ech.rank), _ptr(ech.pivcol), mode, _ptr(ws), ws.numel(), _stream()), "fl_rref32")
+
+
+def rref32_to_csr(sp: Split, Xp: torch.Tensor, Dt: torch.Tensor, ech: Echelon):
+    """RREF(M) in original column order: (row_ptr int64, col int32, val int32 (uint32 values), rank)."""
+    lib = load()
+    maxr = min(sp.mD, sp.nB)
+    row_ptr = torch.empty(sp.npiv + maxr + 1, dtype=torch.int64, device=_dev())
+    ws = _ws(lib.fl_rref32_csr_workspace(ct.byref(sp.info)))
+    h_rank, h_nnz = c_u32(0), c_u64(0)
+    args = (ct.byref(sp.info), ct.byref(sp.out), _ptr(Xp), Xp.shape[1], _ptr(Dt), Dt.shape[1],
+            _ptr(ech.rank), _ptr(ech.pivcol))
+    _check(lib.fl_rref32_csr_size(*args, _ptr(row_ptr), ct.byref(h_rank), ct.byref(h_nnz), _ptr(ws), ws.numel(),
+                                  _stream()), "fl_rref32_csr_size")
+    nnz = int(h_nnz.value)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=_dev())
+    val = torch.empty(max(nnz, 1), dtype=torch.int32, device=_dev())
+    _check(lib.fl_rref32_to_csr(*args, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(ws), ws.numel(), _stream()),
+           "fl_rref32_to_csr")
+    rank = int(h_rank.value)
+    return row_ptr[:rank + 1], col[:nnz], val[:nnz], rank
+
+
+def fl_reduce32(row_ptr, col, val, m: int, n: int, p: int, mode: int = FL_PLAIN, ml_width: int = 2,
+                keep: bool = False) -> dict:
+    """The whole hot path over uint32 residues on one device-resident matrix."""
+    sp = split32(row_ptr, col, val, m, n, p, ml_width)
+    X = trsm32(sp, mode)
+    Dt = reduce_cd32(sp, X, mode)
+    res = dict(split=sp)
+    if keep:
+        res["X"], res["Dt"] = X.clone(), Dt.clone()
+    ech = echelon_d32(Dt, p, sp.mD, sp.nB, mode)
+    rref32(sp, X, Dt, ech, mode)
+    res.update(echelon=ech, Xp=X, RD=Dt, rref=rref32_to_csr(sp, X, Dt, ech))
+    return res

@@ -21,6 +21,27 @@
 //   k_ml_fill      one block per group: pos list and interleaved values
 //   k_info         sizes for the host
 #include "fl_internal.h"
+#include "wide.h"
+
+namespace {
+// The field arithmetic the split needs (scaling pivot rows by the inverse of
+// their lead): uint16 residues with 32-bit Barrett, or uint32 residues with
+// 64-bit Barrett (the 32-bit field path).
+struct FieldU16 {
+    using V = uint16_t;
+    fl::Mod md;
+    uint32_t p() const { return md.p; }
+    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return fl::mulmod(a, b, md); }
+    __device__ uint32_t inv(uint32_t a) const { return fl::invmod(a, md); }
+};
+struct FieldU32 {
+    using V = uint32_t;
+    flw::Mod64 md;
+    uint32_t p() const { return md.p; }
+    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return flw::mulw(a, b, md); }
+    __device__ uint32_t inv(uint32_t a) const { return flw::invw(a, md); }
+};
+}  // namespace
 
 namespace {
 
@@ -58,10 +79,11 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     return v;
 }
 
+template <class V>
 __global__ __launch_bounds__(256) void k_rows(uint32_t m, uint32_t n, uint64_t nnz,
                                               const uint64_t *__restrict__ rp,
                                               const uint32_t *__restrict__ ci,
-                                              const uint16_t *__restrict__ v, uint32_t p,
+                                              const V *__restrict__ v, uint32_t p,
                                               SplitDev d) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -184,26 +206,27 @@ __device__ __forceinline__ uint32_t lane_prefix_count(bool pred, uint32_t lane) 
     return __popcll(below);
 }
 
-__global__ __launch_bounds__(256) void k_scatter_bd(uint32_t m, uint32_t p,
+template <class F>
+__global__ __launch_bounds__(256) void k_scatter_bd(uint32_t m, F f,
                                                     const uint64_t *__restrict__ rp,
                                                     const uint32_t *__restrict__ ci,
-                                                    const uint16_t *__restrict__ v, SplitDev d,
-                                                    uint32_t *b_col, uint16_t *b_val,
-                                                    uint32_t *d_col, uint16_t *d_val) {
+                                                    const typename F::V *__restrict__ v, SplitDev d,
+                                                    uint32_t *b_col, typename F::V *b_val,
+                                                    uint32_t *d_col, typename F::V *d_val) {
+    using V = typename F::V;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= m || failed(d.errkey)) return;
-    const fl::Mod md = fl::make_mod(p);
     uint32_t npiv = (uint32_t)d.tot[0];
     uint32_t pos = d.rowpos[i];
     bool top = pos < npiv;
     uint64_t s = rp[i], e = rp[i + 1];
     uint32_t scale = 1;
-    if (top) scale = fl::invmod(v[s], md);
+    if (top) scale = f.inv(v[s]);
     uint64_t bstart = top ? 0 : (npiv < m ? d.cnt[npiv] : d.tot[2]);
     uint64_t out = d.cnt[pos] - bstart;
     uint32_t *oc = top ? b_col : d_col;
-    uint16_t *ov = top ? b_val : d_val;
+    V *ov = top ? b_val : d_val;
     // four chunks of 64 entries at a time: their loads and map lookups are
     // issued before the chunks are compacted in order
     for (uint64_t k0 = s; k0 < e; k0 += 256) {
@@ -222,7 +245,7 @@ __global__ __launch_bounds__(256) void k_scatter_bd(uint32_t m, uint32_t p,
             const uint32_t before = lane_prefix_count(take, lane);
             if (take) {
                 oc[out + before] = nc[u] - npiv;
-                ov[out + before] = (uint16_t)(top ? fl::mulmod(x[u], scale, md) : x[u]);
+                ov[out + before] = (V)(top ? f.mul(x[u], scale) : x[u]);
             }
             out += __popcll(__ballot(take));
         }
@@ -359,29 +382,30 @@ __global__ void k_ml_ptr(uint32_t m, uint32_t w, SplitDev d, uint64_t *a_gptr, u
     }
 }
 
-__global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, uint32_t p,
+template <class F>
+__global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
                                                  const uint64_t *__restrict__ rp,
                                                  const uint32_t *__restrict__ ci,
-                                                 const uint16_t *__restrict__ v,
+                                                 const typename F::V *__restrict__ v,
                                                  const uint32_t *__restrict__ row_perm,
-                                                 SplitDev d, uint32_t *a_pos, uint16_t *a_val,
-                                                 uint32_t *c_pos, uint16_t *c_val) {
+                                                 SplitDev d, uint32_t *a_pos, typename F::V *a_val,
+                                                 uint32_t *c_pos, typename F::V *c_val) {
+    using V = typename F::V;
     __shared__ uint32_t bits[kWinWords];
     __shared__ uint32_t pre[kWinWords];
     __shared__ uint32_t red[8];
     __shared__ uint32_t scale_s[8];
     if (failed(d.errkey)) return;
-    const fl::Mod md = fl::make_mod(p);
     uint32_t npiv = (uint32_t)d.tot[0];
     GroupInfo gi;
     if (!group_of(blockIdx.x, w, npiv, m, gi)) return;
     uint32_t ga = (npiv + w - 1) / w;
     uint64_t base = d.glen[blockIdx.x] - (gi.is_a ? 0 : (ga < gridDim.x ? d.glen[ga] : 0));
     uint32_t *pos = gi.is_a ? a_pos : c_pos;
-    uint16_t *val = gi.is_a ? a_val : c_val;
+    V *val = gi.is_a ? a_val : c_val;
     if (threadIdx.x < gi.r1 - gi.r0) {
         uint32_t orig = row_perm[gi.r0 + threadIdx.x];
-        scale_s[threadIdx.x] = gi.is_a ? fl::invmod(v[rp[orig]], md) : 1u;
+        scale_s[threadIdx.x] = gi.is_a ? f.inv(v[rp[orig]]) : 1u;
     }
     uint32_t lo, hi;
     group_span(gi, npiv, row_perm, rp, ci, d, red, lo, hi);  // (syncs)
@@ -467,8 +491,8 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, uint32_
                         uint32_t off = nc - w0;
                         uint32_t word = off >> 5, bit = off & 31;
                         uint32_t idx = pre[word] + __popc(bits[word] & ((1u << bit) - 1));
-                        uint32_t x = gi.is_a ? fl::mulmod(xv[u], sc, md) : xv[u];
-                        val[(out + idx) * w + (r - gi.r0)] = (uint16_t)x;
+                        uint32_t x = gi.is_a ? f.mul(xv[u], sc) : xv[u];
+                        val[(out + idx) * w + (r - gi.r0)] = (V)x;
                     }
                 }
             }
@@ -538,25 +562,45 @@ extern "C" size_t fl_split_workspace(uint32_t m, uint32_t n, uint64_t nnz, uint3
     return split_ws_layout(m, n, ml_width, nullptr, nullptr, nullptr);
 }
 
-// Everything of fl_split but the final sync: validation, permutations, A, B,
+// Output pointers of the split for value type V (fl_split_out for uint16,
+// fl_split_out32 for uint32).
+template <class V> struct SplitOutT {
+    uint32_t *row_perm, *col_perm;
+    uint64_t *a_gptr;
+    uint32_t *a_pos;
+    V *a_val;
+    uint64_t *b_ptr;
+    uint32_t *b_col;
+    V *b_val;
+    uint64_t *c_gptr;
+    uint32_t *c_pos;
+    V *c_val;
+    uint64_t *d_ptr;
+    uint32_t *d_col;
+    V *d_val;
+};
+template <class O, class V> SplitOutT<V> out_view(const O *o) {
+    return SplitOutT<V>{o->row_perm, o->col_perm, o->a_gptr, o->a_pos, o->a_val, o->b_ptr, o->b_col, o->b_val,
+                        o->c_gptr, o->c_pos, o->c_val, o->d_ptr, o->d_col, o->d_val};
+}
+
+// Everything of the split but the final sync: validation, permutations, A, B,
 // C, D.  The eight size words (see k_info) go to dinfo_out when it is
 // non-NULL, else to the workspace.  With m == 0 nothing but col_perm is
 // written and the size words are left alone.
-fl_status fl_split_enqueue(const fl_csr *M, uint32_t p, uint32_t ml_width, const fl_split_out *o,
-                           void *ws, size_t ws_bytes, uint64_t *dinfo_out, hipStream_t stream) {
-    FL_ARG(M && o, "fl_split: NULL argument");
-    FL_ARG(p >= 2 && p <= 65521, "fl_split: p must be in [2, 65521]");
+template <class F>
+fl_status split_enqueue(uint32_t m, uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *ci,
+                        const typename F::V *v, F f, uint32_t ml_width, const SplitOutT<typename F::V> &o,
+                        void *ws, size_t ws_bytes, uint64_t *dinfo_out, hipStream_t stream) {
+    const uint32_t p = f.p();
     FL_ARG(ml_width == 1 || ml_width == 2 || ml_width == 4 || ml_width == 8,
            "fl_split: ml_width must be 1, 2, 4 or 8");
-    FL_ARG(M->rows < (1u << 31) && M->cols < (1u << 31), "fl_split: dimensions must be < 2^31");
-    const uint32_t m = M->rows, n = M->cols, w = ml_width;
-    FL_ARG(m == 0 || (M->row_ptr && (M->nnz == 0 || (M->col && M->val))),
-           "fl_split: NULL CSR array");
-    FL_ARG(m == 0 || (o->row_perm && o->a_gptr && o->b_ptr && o->c_gptr && o->d_ptr),
-           "fl_split: NULL output array");
-    FL_ARG(n == 0 || o->col_perm, "fl_split: NULL col_perm");
-    FL_ARG(M->nnz == 0 || (o->a_pos && o->a_val && o->b_col && o->b_val && o->c_pos &&
-                           o->c_val && o->d_col && o->d_val),
+    FL_ARG(m < (1u << 31) && n < (1u << 31), "fl_split: dimensions must be < 2^31");
+    const uint32_t w = ml_width;
+    FL_ARG(m == 0 || (rp && (nnz == 0 || (ci && v))), "fl_split: NULL CSR array");
+    FL_ARG(m == 0 || (o.row_perm && o.a_gptr && o.b_ptr && o.c_gptr && o.d_ptr), "fl_split: NULL output array");
+    FL_ARG(n == 0 || o.col_perm, "fl_split: NULL col_perm");
+    FL_ARG(nnz == 0 || (o.a_pos && o.a_val && o.b_col && o.b_val && o.c_pos && o.c_val && o.d_col && o.d_val),
            "fl_split: NULL output array");
     SplitDev d;
     uint64_t *dinfo;
@@ -568,60 +612,61 @@ fl_status fl_split_enqueue(const fl_csr *M, uint32_t p, uint32_t ml_width, const
     if (dinfo_out) dinfo = dinfo_out;
     if (m == 0) {  // no rows: no pivots, every column is a non-pivot column
         if (n) {
-            hipLaunchKernelGGL(k_iota, dim3(blocks(n, 256)), dim3(256), 0, stream, n, o->col_perm);
+            hipLaunchKernelGGL(k_iota, dim3(blocks(n, 256)), dim3(256), 0, stream, n, o.col_perm);
             FL_LAUNCH_CHECK("k_iota");
         }
         return FL_OK;
     }
-    const uint64_t *rp = M->row_ptr;
-    const uint32_t *ci = M->col;
-    const uint16_t *v = M->val;
     const size_t groups = (size_t)(m + w - 1) / w + 1;
 
     FL_HIP(fl_fill_u64(d.errkey, ~(uint64_t)0, 1, stream));
     FL_HIP(fl_fill_u64(d.pivkey, ~(uint64_t)0, n, stream));
     FL_HIP(fl_fill_u64(d.tot, 0, 8, stream));
-    hipLaunchKernelGGL(k_rows, dim3(blocks(m, 4)), dim3(256), 0, stream, m, n, M->nnz, rp, ci, v,
+    hipLaunchKernelGGL(k_rows<typename F::V>, dim3(blocks(m, 4)), dim3(256), 0, stream, m, n, nnz, rp, ci, v,
                        p, d);
     FL_LAUNCH_CHECK("k_rows");
     if (n) {
         hipLaunchKernelGGL(k_colflag, dim3(blocks(n, 256)), dim3(256), 0, stream, n, d);
         FL_LAUNCH_CHECK("k_colflag");
         FL_HIP(fl_exclusive_scan_u64(d.colscan, d.colscan, n, d.scantmp, d.tot + 0, stream));
-        hipLaunchKernelGGL(k_colmap, dim3(blocks(n, 256)), dim3(256), 0, stream, n, d,
-                           o->col_perm);
+        hipLaunchKernelGGL(k_colmap, dim3(blocks(n, 256)), dim3(256), 0, stream, n, d, o.col_perm);
         FL_LAUNCH_CHECK("k_colmap");
     }
     hipLaunchKernelGGL(k_rowflag, dim3(blocks(m, 256)), dim3(256), 0, stream, m, d);
     FL_LAUNCH_CHECK("k_rowflag");
     FL_HIP(fl_exclusive_scan_u64(d.rowscan, d.rowscan, m, d.scantmp, d.tot + 1, stream));
-    hipLaunchKernelGGL(k_rowmap, dim3(blocks(m, 256)), dim3(256), 0, stream, m, d, o->row_perm);
+    hipLaunchKernelGGL(k_rowmap, dim3(blocks(m, 256)), dim3(256), 0, stream, m, d, o.row_perm);
     FL_LAUNCH_CHECK("k_rowmap");
     hipLaunchKernelGGL(k_count_bd, dim3(blocks(m, 4)), dim3(256), 0, stream, m, rp, ci, d);
     FL_LAUNCH_CHECK("k_count_bd");
     FL_HIP(fl_exclusive_scan_u64(d.cnt, d.cnt, m, d.scantmp, d.tot + 2, stream));
-    hipLaunchKernelGGL(k_bd_ptr, dim3(blocks(m + 1, 256)), dim3(256), 0, stream, m, d, o->b_ptr,
-                       o->d_ptr);
+    hipLaunchKernelGGL(k_bd_ptr, dim3(blocks(m + 1, 256)), dim3(256), 0, stream, m, d, o.b_ptr, o.d_ptr);
     FL_LAUNCH_CHECK("k_bd_ptr");
-    hipLaunchKernelGGL(k_scatter_bd, dim3(blocks(m, 4)), dim3(256), 0, stream, m, p, rp, ci, v, d,
-                       o->b_col, o->b_val, o->d_col, o->d_val);
+    hipLaunchKernelGGL(k_scatter_bd<F>, dim3(blocks(m, 4)), dim3(256), 0, stream, m, f, rp, ci, v, d, o.b_col,
+                       o.b_val, o.d_col, o.d_val);
     FL_LAUNCH_CHECK("k_scatter_bd");
     // multiline groups: A groups then C groups, at most ceil(m/w) + 1 of them
     FL_HIP(fl_fill_u64(d.glen, 0, groups, stream));
-    hipLaunchKernelGGL(k_ml_count, dim3((unsigned)groups), dim3(256), 0, stream, m, w, rp, ci,
-                       o->row_perm, d);
+    hipLaunchKernelGGL(k_ml_count, dim3((unsigned)groups), dim3(256), 0, stream, m, w, rp, ci, o.row_perm, d);
     FL_LAUNCH_CHECK("k_ml_count");
     FL_HIP(fl_exclusive_scan_u64(d.glen, d.glen, groups, d.scantmp, d.tot + 3, stream));
-    hipLaunchKernelGGL(k_ml_ptr, dim3(blocks(groups + 1, 256)), dim3(256), 0, stream, m, w, d,
-                       o->a_gptr, o->c_gptr);
+    hipLaunchKernelGGL(k_ml_ptr, dim3(blocks(groups + 1, 256)), dim3(256), 0, stream, m, w, d, o.a_gptr,
+                       o.c_gptr);
     FL_LAUNCH_CHECK("k_ml_ptr");
-    hipLaunchKernelGGL(k_ml_fill, dim3((unsigned)groups), dim3(256), 0, stream, m, w, p, rp, ci,
-                       v, o->row_perm, d, o->a_pos, o->a_val, o->c_pos, o->c_val);
+    hipLaunchKernelGGL(k_ml_fill<F>, dim3((unsigned)groups), dim3(256), 0, stream, m, w, f, rp, ci, v, o.row_perm,
+                       d, o.a_pos, o.a_val, o.c_pos, o.c_val);
     FL_LAUNCH_CHECK("k_ml_fill");
     hipLaunchKernelGGL(k_info, dim3(1), dim3(1), 0, stream, m, n, w, d, dinfo);
     FL_LAUNCH_CHECK("k_info");
-
     return FL_OK;
+}
+
+fl_status fl_split_enqueue(const fl_csr *M, uint32_t p, uint32_t ml_width, const fl_split_out *o,
+                           void *ws, size_t ws_bytes, uint64_t *dinfo_out, hipStream_t stream) {
+    FL_ARG(M && o, "fl_split: NULL argument");
+    FL_ARG(p >= 2 && p <= 65521, "fl_split: p must be in [2, 65521]");
+    return split_enqueue(M->rows, M->cols, M->nnz, M->row_ptr, M->col, M->val, FieldU16{fl::make_mod(p)},
+                         ml_width, out_view<fl_split_out, uint16_t>(o), ws, ws_bytes, dinfo_out, stream);
 }
 
 // Host side of fl_split after the sync: the size words -> h_info.
@@ -671,4 +716,24 @@ extern "C" fl_status fl_split(const fl_csr *M, uint32_t p, uint32_t ml_width,
         FL_HIP(hipStreamSynchronize(stream));
     }
     return fl_split_finish(M, p, ml_width, hinf, h_info);
+}
+
+// The 32-bit field path's split: the same steps over uint32 residues.
+extern "C" fl_status fl_split32(const fl_csr32 *M, uint32_t p, uint32_t ml_width, const fl_split_out32 *o,
+                                fl_split_info *h_info, void *ws, size_t ws_bytes, hipStream_t stream) {
+    FL_ARG(M && o && h_info, "fl_split32: NULL argument");
+    FL_ARG(p >= 2, "fl_split32: p must be >= 2");
+    fl_status st = split_enqueue(M->rows, M->cols, M->nnz, M->row_ptr, M->col, M->val, FieldU32{flw::make_mod64(p)},
+                                 ml_width, out_view<fl_split_out32, uint32_t>(o), ws, ws_bytes, nullptr, stream);
+    if (st != FL_OK) return st;
+    uint64_t hinf[8] = {~(uint64_t)0, 0, 0, 0, 0, 0, 0, 0};
+    if (M->rows) {
+        SplitDev d;
+        uint64_t *dinfo;
+        split_ws_layout(M->rows, M->cols, ml_width, ws, &d, &dinfo);
+        FL_HIP(hipMemcpyAsync(hinf, dinfo, sizeof(hinf), hipMemcpyDeviceToHost, stream));
+        FL_HIP(hipStreamSynchronize(stream));
+    }
+    fl_csr shape = {M->rows, M->cols, M->nnz, M->row_ptr, M->col, nullptr};
+    return fl_split_finish(&shape, p, ml_width, hinf, h_info);
 }
