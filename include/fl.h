@@ -306,8 +306,9 @@ size_t fl_matmul_sub_workspace(uint32_t M, uint32_t N, uint32_t K, fl_mode mode)
  *                   (each replay recomputes every result from the split);
  *   fl_batch_autotune
  *                   times candidate configurations (multiline width, branch
- *                   count, MFMA size threshold) on the given batch and
- *                   remembers the best one for batches of the same shape.
+ *                   count, MFMA size threshold, work-queue width, far-update
+ *                   column groups) on the given batch and remembers the best
+ *                   one for batches of the same shape.
  *
  * Memory: the caller allocates two device arenas: the split arena
  * (fl_batch_split_workspace, known from the CSR shapes alone; it holds every
@@ -332,7 +333,18 @@ typedef struct {
                                   C X, echelon updates, second pass) on int8 MFMA
                                   when (npiv + mD) * nB >= this; 0 = default (2^22);
                                   UINT64_MAX = always the VALU form */
+    uint32_t queue_per_cu;     /* the stepped launches of the TRSM (one per block
+                                  step for all matrices) run as persistent
+                                  work-queue launches with this many workgroups
+                                  per compute unit, which take the step's tiles
+                                  of every matrix from an atomic counter;
+                                  0 = default (2), FL_BATCH_DIRECT = one
+                                  workgroup per tile instead */
+    uint32_t far_groups;       /* workgroups along the columns of the echelon
+                                  step's far block updates (each walks that
+                                  many-th column tile); 0 = default (128) */
 } fl_batch_config;
+#define FL_BATCH_DIRECT 0xFFFFu
 
 typedef struct fl_batch fl_batch;   /* opaque host object */
 

@@ -60,8 +60,12 @@ class FlSplitInfo(ct.Structure):
                 ("lenC", c_u64)]
 
 
+FL_BATCH_DIRECT = 0xFFFF
+
+
 class FlBatchConfig(ct.Structure):
-    _fields_ = [("ml_width", c_u32), ("streams", c_u32), ("mfma_min_entries", c_u64)]
+    _fields_ = [("ml_width", c_u32), ("streams", c_u32), ("mfma_min_entries", c_u64), ("queue_per_cu", c_u32),
+                ("far_groups", c_u32)]
 
 
 class FlBatchMatrix(ct.Structure):
@@ -430,7 +434,8 @@ def _config(cfg):
     if cfg is None:
         return None
     return FlBatchConfig(int(cfg.get("ml_width", 0)), int(cfg.get("streams", 0)),
-                         int(cfg.get("mfma_min_entries", 0)))
+                         int(cfg.get("mfma_min_entries", 0)), int(cfg.get("queue_per_cu", 0)),
+                         int(cfg.get("far_groups", 0)))
 
 
 def batch_plan(mats, p: int, config: dict | None = None) -> Batch:
@@ -471,7 +476,8 @@ def batch_config(b: Batch) -> dict:
     lib = load()
     c = FlBatchConfig()
     lib.fl_batch_get_config(b.handle, ct.byref(c))
-    return dict(ml_width=c.ml_width, streams=c.streams, mfma_min_entries=c.mfma_min_entries)
+    return dict(ml_width=c.ml_width, streams=c.streams, mfma_min_entries=c.mfma_min_entries,
+                queue_per_cu=c.queue_per_cu, far_groups=c.far_groups)
 
 
 def batch_results(b: Batch) -> list:
@@ -523,7 +529,8 @@ def batch_autotune(mats, p: int, run_bytes: int | None = None):
     st = lib.fl_batch_autotune(arr, len(mats), p, _ptr(split_arena), split_arena.numel(), _ptr(run_arena),
                                run_arena.numel(), ct.byref(best), ct.byref(ms), _stream())
     _check(st, "fl_batch_autotune")
-    return dict(ml_width=best.ml_width, streams=best.streams, mfma_min_entries=best.mfma_min_entries), ms.value
+    return dict(ml_width=best.ml_width, streams=best.streams, mfma_min_entries=best.mfma_min_entries,
+                queue_per_cu=best.queue_per_cu, far_groups=best.far_groups), ms.value
 
 
 def prof_report() -> dict:

@@ -33,6 +33,8 @@ namespace {
 constexpr uint32_t kMaxStreams = 16;
 
 constexpr uint64_t kDefaultMfmaMin = (uint64_t)1 << 22;
+constexpr uint32_t kDefaultQueuePerCu = 2;
+constexpr uint32_t kDefaultFarGroups = 128;
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline uint64_t ld64(uint32_t cols) { return cols ? ((uint64_t)cols + 63) / 64 * 64 : 64; }
@@ -137,7 +139,7 @@ std::string shape_key(const fl_csr *Ms, uint32_t count, uint32_t p) {
 }
 
 fl_batch_config resolve(const fl_batch_config *cfg, const fl_csr *Ms, uint32_t count, uint32_t p) {
-    fl_batch_config c = {0, 0, 0};
+    fl_batch_config c = {};
     if (cfg) {
         c = *cfg;
     } else {
@@ -148,6 +150,8 @@ fl_batch_config resolve(const fl_batch_config *cfg, const fl_csr *Ms, uint32_t c
     if (c.ml_width == 0) c.ml_width = 2;
     if (c.streams == 0) c.streams = 8;
     if (c.mfma_min_entries == 0) c.mfma_min_entries = kDefaultMfmaMin;
+    if (c.queue_per_cu == 0) c.queue_per_cu = kDefaultQueuePerCu;
+    if (c.far_groups == 0) c.far_groups = kDefaultFarGroups;
     return c;
 }
 
@@ -161,6 +165,8 @@ struct fl_batch {
     // device tables of the stepped loops (TRSM blocks, echelon panels)
     uint64_t off_ttask = 0, off_tids = 0, off_tpre = 0;  // 4 lists each (solves and updates by form)
     uint64_t off_etask = 0, off_eids = 0, off_epre_rows = 0, off_epre = 0;
+    uint64_t off_queue = 0;  // work-queue counters of the stepped launches (4 per TRSM step)
+    uint32_t n_queue = 0;
     uint32_t max_blk = 0, max_panels = 0;
     hipStream_t streams[kMaxStreams] = {};
     hipStream_t capture = nullptr;  // graph capture when the caller passes the null stream
@@ -233,6 +239,8 @@ void batch_layout(fl_batch *b) {
     b->off_eids = take(4 * 3 * n);
     b->off_epre_rows = take(4 * (n + 1));
     b->off_epre = take(4 * (3 * (uint64_t)b->max_panels + 6 * (uint64_t)((b->max_panels + 3) / 4)) * (n + 1));
+    b->n_queue = 4 * b->max_blk;
+    b->off_queue = take(4 * (uint64_t)(b->n_queue ? b->n_queue : 1));
     for (auto &mr : b->mats) {
         const fl_split_info &f = mr.info;
         mr.ldx = ld64(f.nB);
@@ -341,12 +349,17 @@ fl_status run_trsm(fl_batch *b, void *arena, hipStream_t stream) {
     const int kind_of[4] = {3, 1, 0, 2};
     std::vector<uint32_t> active(4);
     for (int k = 0; k < 4; k++) active[k] = (uint32_t)ids[k].size();
+    // one counter per (step, kind), all cleared by one fill kernel (captured
+    // with the run, so every graph replay starts from zero)
+    uint32_t *queue = at<uint32_t>(arena, b->off_queue);
+    const uint32_t per_cu = b->cfg.queue_per_cu == FL_BATCH_DIRECT ? 0 : b->cfg.queue_per_cu;
+    FL_HIP(fl_fill_u32(queue, 0, b->n_queue, stream));
     for (uint32_t step = 0; step < b->max_blk; step++) {
         for (int k : {1, 2, 0, 3}) {  // updates of the step, then its solves
             while (active[k] && b->mats[ids[k][active[k] - 1]].nblk <= step) active[k]--;
             if (!active[k]) continue;
             FL_HIP(fl_trsm_batch_launch(kind_of[k], b->p, w, d_tasks, d_ids[k], d_pre[k], active[k],
-                                        pre[k][active[k]], step, stream));
+                                        pre[k][active[k]], step, queue + 4 * step + k, per_cu, stream));
         }
     }
     return FL_OK;
@@ -396,7 +409,7 @@ fl_status run_echelon(fl_batch *b, void *arena, std::vector<FlEchTask> &tasks, h
     L.pre_bf_mfma = take_tab(Bm);
     L.pre_bf_plain = take_tab(Bm);
     FL_HIP(fl_echelon_prefixes(d_tasks, L, Pm, Bm, stream));
-    FlEchAux aux = {b->ech_far, b->ech_near_ev, b->ech_far_ev, false};
+    FlEchAux aux = {b->ech_far, b->ech_near_ev, b->ech_far_ev, false, b->cfg.far_groups};
     uint32_t active = L.n_all;
     auto active_at = [&](uint32_t P, uint32_t a) {
         while (a && b->mats[ids[0][a - 1]].npanels <= P) a--;
@@ -703,9 +716,16 @@ extern "C" fl_status fl_batch_autotune(const fl_csr *Ms, uint32_t count, uint32_
                                        size_t run_bytes, fl_batch_config *best, double *best_ms,
                                        hipStream_t stream) {
     FL_ARG(Ms && count && split_arena && run_arena && best, "fl_batch_autotune: NULL argument");
-    hipEvent_t e0, e1;
-    FL_HIP(hipEventCreate(&e0));
-    FL_HIP(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    FL_HIP(hipEventCreate(&ev.a));
+    FL_HIP(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     // one full timed pass (plan + run) per candidate, after one warm-up
     auto measure = [&](const fl_batch_config &c, double *ms) -> fl_status {
         *ms = INFINITY;
@@ -738,7 +758,7 @@ extern "C" fl_status fl_batch_autotune(const fl_csr *Ms, uint32_t count, uint32_
         *ms = best_t;
         return FL_OK;
     };
-    fl_batch_config cur = {2, 8, kDefaultMfmaMin};
+    fl_batch_config cur = {2, 8, kDefaultMfmaMin, kDefaultQueuePerCu, kDefaultFarGroups};
     double cur_ms;
     fl_status st = measure(cur, &cur_ms);
     // coordinate descent: multiline width, then MFMA threshold, then branches
@@ -769,8 +789,26 @@ extern "C" fl_status fl_batch_autotune(const fl_csr *Ms, uint32_t count, uint32_
         st = measure(c, &ms);
         if (ms < cur_ms) cur = c, cur_ms = ms;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // launch geometry: work-queue width of the stepped TRSM launches (or
+    // one workgroup per tile), column groups of the far echelon updates
+    const uint32_t queues[] = {FL_BATCH_DIRECT, 1, 4};
+    const uint32_t groups[] = {32, 512};
+    for (uint32_t qw : queues) {
+        if (st != FL_OK) break;
+        fl_batch_config c = cur;
+        c.queue_per_cu = qw;
+        double ms;
+        st = measure(c, &ms);
+        if (ms < cur_ms) cur = c, cur_ms = ms;
+    }
+    for (uint32_t gsz : groups) {
+        if (st != FL_OK) break;
+        fl_batch_config c = cur;
+        c.far_groups = gsz;
+        double ms;
+        st = measure(c, &ms);
+        if (ms < cur_ms) cur = c, cur_ms = ms;
+    }
     if (st != FL_OK) return st;
     if (!isfinite(cur_ms)) {
         fl_set_error("fl_batch_autotune: no candidate fits the arenas");

@@ -164,6 +164,18 @@ hipError_t fl_exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, ui
     return hipGetLastError();
 }
 
+uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu) {
+    static int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        return n;
+    }();
+    const uint64_t cap = (uint64_t)per_cu * (uint64_t)cus;
+    return (uint32_t)(cap < total ? cap : total);
+}
+
 hipError_t fl_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);

@@ -1301,7 +1301,7 @@ uint32_t far_dyn_lds(K kernel) {
 hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, const FlEchLists &L, uint32_t B,
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
-                        bool far, hipStream_t s) {
+                        bool far, uint32_t far_groups, hipStream_t s) {
     static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8>)),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
@@ -1325,7 +1325,7 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
     if (g_mfma && far) {
         FL_PROF("echelon.blk_mfma_far", s,
                 hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8>),
-                                   dim3((mfma_rows + 127) / 128, std::min(g_mfma, kBlkColGroups)), dim3(256), dyn_m, s,
+                                   dim3((mfma_rows + 127) / 128, std::min(g_mfma, far_groups)), dim3(256), dyn_m, s,
                                    md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
                                    g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1402,7 +1402,7 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
         }
         if ((e = block_update(md, p, tasks, L, B, 0, kBlock, blk->bn_all, blk->bn_mfma, blk->bn_plain,
                               blk->mfma_rows, at(L.pre_bn_all, B, L.n_all), at(L.pre_bn_mfma, B, L.n_mfma),
-                              at(L.pre_bn_plain, B, L.n_plain), false, stream)) != hipSuccess)
+                              at(L.pre_bn_plain, B, L.n_plain), false, kBlkColGroups, stream)) != hipSuccess)
             return e;
         if (blk->bf_all) {
             if ((e = hipEventRecord(aux.ev_near, stream)) != hipSuccess) return e;
@@ -1410,7 +1410,7 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             if ((e = block_update(md, p, tasks, L, B, kBlock, 0xffffffffu, blk->bf_all, blk->bf_mfma,
                                   blk->bf_plain, blk->mfma_rows, at(L.pre_bf_all, B, L.n_all),
                                   at(L.pre_bf_mfma, B, L.n_mfma), at(L.pre_bf_plain, B, L.n_plain), true,
-                                  aux.far)) != hipSuccess)
+                                  aux.far_groups ? aux.far_groups : kBlkColGroups, aux.far)) != hipSuccess)
                 return e;
             if ((e = hipEventRecord(aux.ev_far, aux.far)) != hipSuccess) return e;
             aux.far_pending = true;

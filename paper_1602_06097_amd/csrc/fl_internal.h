@@ -238,6 +238,37 @@ __device__ __forceinline__ uint32_t fl_task_of(const uint32_t *__restrict__ pref
     return lo;
 }
 
+// The tasks of one workgroup.  With counter == NULL a launch maps workgroup
+// x to task x (one task each).  Otherwise the launch is persistent: a fixed
+// number of workgroups (about as many as stay resident) take task indices
+// from the atomic *counter until it passes `total`, so tiles of all problems
+// are dealt dynamically to whichever workgroup is free.  The counter of each
+// launch starts at zero (cleared by a fill kernel, so graph replays work);
+// no workgroup ever waits for another.  Used as
+//     uint32_t task;
+//     for (bool ok = fl_queue_take(q, task, true); ok; ok = fl_queue_take(q, task, false)) { ... }
+// where the body ends a task with `continue` (never a bare return: every
+// thread must come back for the next take).
+struct FlQueue {
+    uint32_t *counter;
+    uint32_t total;
+};
+__device__ __forceinline__ bool fl_queue_take(const FlQueue &q, uint32_t &task, bool first) {
+    if (!q.counter) {  // (uniform) one task per workgroup
+        task = blockIdx.x;
+        return first;
+    }
+    __shared__ uint32_t s_task;
+    __syncthreads();  // the previous task is done with LDS and with s_task
+    if (threadIdx.x == 0) s_task = atomicAdd(q.counter, 1u);
+    __syncthreads();
+    task = s_task;
+    return task < q.total;
+}
+// Workgroups of a persistent launch: `per_cu` per compute unit, at most
+// `total`; counter NULL (one workgroup per task) when per_cu is 0.
+uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu);
+
 // Copies `bytes` from host memory into device memory through kernel
 // arguments (1 KiB per launch), so that the copy can be captured in a graph
 // without referring to host memory at replay time.
@@ -275,7 +306,7 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
 // ceil(nB / 256) * (128 / w / 4); MFMA update ceil(nB / 128) * kFlTrsmSuper.
 hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
                                 const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,
-                                uint32_t step, hipStream_t stream);
+                                uint32_t step, uint32_t *counter, uint32_t per_cu, hipStream_t stream);
 
 // One matrix's Gauss-Jordan elimination of the Schur complement as the panel
 // kernels see it (device-side table entry).
@@ -347,6 +378,7 @@ struct FlEchAux {
     hipStream_t far;
     hipEvent_t ev_near, ev_far;
     bool far_pending;
+    uint32_t far_groups;  // workgroups along the columns of a far block update (0: 128)
 };
 // Panel P of every listed matrix on `stream`; when P ends a block (blk
 // non-NULL), also the block's update of the columns right of it, its far

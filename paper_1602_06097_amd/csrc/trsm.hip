@@ -508,13 +508,16 @@ template <int W>
 __global__ __launch_bounds__(64) void k_trsm_solve_b(fl::Mod md, const FlTrsmTask *__restrict__ tasks,
                                                      const uint32_t *__restrict__ ids,
                                                      const uint32_t *__restrict__ prefix, uint32_t n,
-                                                     uint32_t step) {
-    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
-    const FlTrsmTask &t = tasks[ids[i]];
-    uint32_t I, r0, r1;
-    if (!step_block(t, step, I, r0, r1)) return;
-    trsm_solve_tile<W>(md, t.gptr, t.pos, t.val, t.nin, t.nnear, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp,
-                       blockIdx.x - prefix[i]);
+                                                     uint32_t step, FlQueue q) {
+    uint32_t task;
+    for (bool ok = fl_queue_take(q, task, true); ok; ok = fl_queue_take(q, task, false)) {
+        const uint32_t i = fl_task_of(prefix, n, task);
+        const FlTrsmTask &t = tasks[ids[i]];
+        uint32_t I, r0, r1;
+        if (!step_block(t, step, I, r0, r1)) continue;
+        trsm_solve_tile<W>(md, t.gptr, t.pos, t.val, t.nin, t.nnear, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp,
+                           task - prefix[i]);
+    }
 }
 
 // Far update of the step's block, VALU form: workgroup (bx, by) of the task as
@@ -523,15 +526,19 @@ template <int W>
 __global__ __launch_bounds__(256) void k_trsm_update_b(fl::Mod md, const FlTrsmTask *__restrict__ tasks,
                                                        const uint32_t *__restrict__ ids,
                                                        const uint32_t *__restrict__ prefix, uint32_t n,
-                                                       uint32_t step) {
-    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
-    const FlTrsmTask &t = tasks[ids[i]];
-    uint32_t I, r0, r1;
-    if (!step_block(t, step, I, r0, r1) || r1 >= t.npiv) return;
-    const uint32_t local = blockIdx.x - prefix[i], ct = (t.nB + kTile - 1) / kTile;
-    const uint32_t g0 = r0 / W, ng = (r1 + W - 1) / W - g0;
-    ml_spmm_tile<W>(md, t.gptr, t.pos, t.val, g0, ng, r1, r1, t.X, t.ldx, t.X, t.ldx, t.nB, local % ct,
-                    local / ct);
+                                                       uint32_t step, FlQueue q) {
+    uint32_t task;
+    for (bool ok = fl_queue_take(q, task, true); ok; ok = fl_queue_take(q, task, false)) {
+        const uint32_t i = fl_task_of(prefix, n, task);
+        const FlTrsmTask &t = tasks[ids[i]];
+        uint32_t I, r0, r1;
+        if (!step_block(t, step, I, r0, r1) || r1 >= t.npiv) continue;
+        const uint32_t local = task - prefix[i], ct = (t.nB + kTile - 1) / kTile;
+        const uint32_t g0 = r0 / W, ng = (r1 + W - 1) / W - g0;
+        // (per-wave early exits inside the tile: it has no barrier)
+        ml_spmm_tile<W>(md, t.gptr, t.pos, t.val, g0, ng, r1, r1, t.X, t.ldx, t.X, t.ldx, t.nB, local % ct,
+                        local / ct);
+    }
 }
 
 // Update of the step's block, int8-MFMA form, by superblocks: at the first
@@ -544,31 +551,34 @@ __global__ __launch_bounds__(fl_mfma::kGemmThreads) void k_trsm_update_mfma_b(fl
                                                             const FlTrsmTask *__restrict__ tasks,
                                                             const uint32_t *__restrict__ ids,
                                                             const uint32_t *__restrict__ prefix,
-                                                            uint32_t n, uint32_t step) {
+                                                            uint32_t n, uint32_t step, FlQueue q) {
     __shared__ __attribute__((aligned(16))) int8_t smem[fl_mfma::kGemmLds];
-    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
-    const FlTrsmTask &t = tasks[ids[i]];
-    uint32_t I, r0, r1;
-    if (!step_block(t, step, I, r0, r1)) return;
-    const uint32_t ct = (t.nB + 127) / 128, local = blockIdx.x - prefix[i];
-    const uint32_t bx = local % ct, by = local / ct;
-    const uint32_t R1 = trsm_super_end(I, t.nblk, t.npiv);
-    if (step % kFlTrsmSuper == 0) {
-        const uint32_t top = I >= kFlTrsmSuper - 1 ? I - (kFlTrsmSuper - 1) : 0;
-        if (R1 >= t.npiv || top + by > I) return;
-        const uint32_t rt = top * kTrsmBlock;
-        const GemmPlanes g = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp, t.kp, R1,
-                              R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr, nullptr,
-                              t.X + (uint64_t)rt * t.ldx, t.ldx, R1 - rt, t.nB, 0, t.xkend};
-        fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
-    } else {
-        if (by != 0) return;
-        // (R1 - r1 is a multiple of 128 unless R1 = npiv, where the band
-        // past R1 is zero)
-        const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1,
-                              r1, 0, (R1 - r1 + 63) / 64 * 64, t.kext + I, nullptr, nullptr, nullptr,
-                              t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB, 0, t.xkend};
-        fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, 0, smem);
+    uint32_t task;
+    for (bool ok = fl_queue_take(q, task, true); ok; ok = fl_queue_take(q, task, false)) {
+        const uint32_t i = fl_task_of(prefix, n, task);
+        const FlTrsmTask &t = tasks[ids[i]];
+        uint32_t I, r0, r1;
+        if (!step_block(t, step, I, r0, r1)) continue;
+        const uint32_t ct = (t.nB + 127) / 128, local = task - prefix[i];
+        const uint32_t bx = local % ct, by = local / ct;
+        const uint32_t R1 = trsm_super_end(I, t.nblk, t.npiv);
+        if (step % kFlTrsmSuper == 0) {
+            const uint32_t top = I >= kFlTrsmSuper - 1 ? I - (kFlTrsmSuper - 1) : 0;
+            if (R1 >= t.npiv || top + by > I) continue;
+            const uint32_t rt = top * kTrsmBlock;
+            const GemmPlanes g = {t.Ah + (uint64_t)rt * t.kp, t.Al + (uint64_t)rt * t.kp, t.Xh, t.Xl, t.kp, t.kp, R1,
+                                  R1, 0, (uint32_t)(t.kp - R1), nullptr, t.krange + 2 * top, nullptr, nullptr,
+                                  t.X + (uint64_t)rt * t.ldx, t.ldx, R1 - rt, t.nB, 0, t.xkend};
+            fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, by, smem);
+        } else {
+            if (by != 0) continue;
+            // (R1 - r1 is a multiple of 128 unless R1 = npiv, where the band
+            // past R1 is zero)
+            const GemmPlanes g = {t.Ah + (uint64_t)r0 * t.kp, t.Al + (uint64_t)r0 * t.kp, t.Xh, t.Xl, t.kp, t.kp, r1,
+                                  r1, 0, (R1 - r1 + 63) / 64 * 64, t.kext + I, nullptr, nullptr, nullptr,
+                                  t.X + (uint64_t)r0 * t.ldx, t.ldx, r1 - r0, t.nB, 0, t.xkend};
+            fl_mfma::mfma_gemm_tile(md, bias, c16, g, bx, 0, smem);
+        }
     }
 }
 
@@ -813,14 +823,18 @@ __global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, u
 __global__ __launch_bounds__(256) void k_trsm_apply_b(fl::Mod md, uint32_t bias, uint32_t c16,
                                                       const FlTrsmTask *__restrict__ tasks,
                                                       const uint32_t *__restrict__ ids,
-                                                      const uint32_t *__restrict__ prefix, uint32_t n, uint32_t step) {
+                                                      const uint32_t *__restrict__ prefix, uint32_t n, uint32_t step,
+                                                      FlQueue q) {
     __shared__ ApplyLds S;
-    const uint32_t i = fl_task_of(prefix, n, blockIdx.x);
-    const FlTrsmTask &t = tasks[ids[i]];
-    uint32_t I, r0, r1;
-    if (!step_block(t, step, I, r0, r1)) return;
-    trsm_apply_tile(md, bias, c16, t.Th, t.Tl, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp, t.xkend,
-                    blockIdx.x - prefix[i], S);
+    uint32_t task;
+    for (bool ok = fl_queue_take(q, task, true); ok; ok = fl_queue_take(q, task, false)) {
+        const uint32_t i = fl_task_of(prefix, n, task);
+        const FlTrsmTask &t = tasks[ids[i]];
+        uint32_t I, r0, r1;
+        if (!step_block(t, step, I, r0, r1)) continue;
+        trsm_apply_tile(md, bias, c16, t.Th, t.Tl, r0, r1, t.X, t.ldx, t.nB, t.Xh, t.Xl, t.kp, t.xkend,
+                        task - prefix[i], S);
+    }
 }
 
 // ---- int8-MFMA form of the TRSM: far part of every block as a limb GEMM ----
@@ -1121,31 +1135,35 @@ fl_status fl_trsm_prepare(const fl_split_info *info, const fl_split_out *s, uint
 }
 
 hipError_t fl_trsm_batch_launch(int kind, uint32_t p, uint32_t w, const FlTrsmTask *tasks,
-                                const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t grid,
-                                uint32_t step, hipStream_t stream) {
-    if (n == 0 || grid == 0) return hipSuccess;
+                                const uint32_t *ids, const uint32_t *prefix, uint32_t n, uint32_t total,
+                                uint32_t step, uint32_t *counter, uint32_t per_cu, hipStream_t stream) {
+    if (n == 0 || total == 0) return hipSuccess;
     const fl::Mod md = fl::make_mod(p);
+    // persistent launch over the step's tiles of every matrix, or one
+    // workgroup per tile
+    const FlQueue q = {per_cu && counter ? counter : nullptr, total};
+    const uint32_t grid = q.counter ? fl_queue_grid(total, per_cu) : total;
     if (kind == 3) {
         hipLaunchKernelGGL(k_trsm_apply_b, dim3(grid), dim3(256), 0, stream, md, fl_mfma::gemm_bias(p),
-                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step);
+                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step, q);
     } else if (kind == 2) {
         switch (w) {
-        case 1: hipLaunchKernelGGL(k_trsm_solve_b<1>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
-        case 2: hipLaunchKernelGGL(k_trsm_solve_b<2>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
-        case 4: hipLaunchKernelGGL(k_trsm_solve_b<4>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
-        default: hipLaunchKernelGGL(k_trsm_solve_b<8>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 1: hipLaunchKernelGGL(k_trsm_solve_b<1>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        case 2: hipLaunchKernelGGL(k_trsm_solve_b<2>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        case 4: hipLaunchKernelGGL(k_trsm_solve_b<4>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        default: hipLaunchKernelGGL(k_trsm_solve_b<8>, dim3(grid), dim3(64), 0, stream, md, tasks, ids, prefix, n, step, q); break;
         }
     } else if (step == 0) {
         return hipSuccess;  // the bottom blocks have nothing below them
     } else if (kind == 1) {
         hipLaunchKernelGGL(k_trsm_update_mfma_b, dim3(grid), dim3(fl_mfma::kGemmThreads), 0, stream, md, fl_mfma::gemm_bias(p),
-                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step);
+                           fl_mfma::gemm_c16(p), tasks, ids, prefix, n, step, q);
     } else {
         switch (w) {
-        case 1: hipLaunchKernelGGL(k_trsm_update_b<1>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
-        case 2: hipLaunchKernelGGL(k_trsm_update_b<2>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
-        case 4: hipLaunchKernelGGL(k_trsm_update_b<4>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
-        default: hipLaunchKernelGGL(k_trsm_update_b<8>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step); break;
+        case 1: hipLaunchKernelGGL(k_trsm_update_b<1>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        case 2: hipLaunchKernelGGL(k_trsm_update_b<2>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        case 4: hipLaunchKernelGGL(k_trsm_update_b<4>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step, q); break;
+        default: hipLaunchKernelGGL(k_trsm_update_b<8>, dim3(grid), dim3(256), 0, stream, md, tasks, ids, prefix, n, step, q); break;
         }
     }
     return hipGetLastError();

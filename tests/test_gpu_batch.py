@@ -77,11 +77,18 @@ CONFIGS = [
     dict(ml_width=1, streams=1, mfma_min_entries=1),               # everything MFMA, one branch
     dict(ml_width=4, streams=3, mfma_min_entries=(1 << 64) - 1),   # everything VALU
     dict(ml_width=8, streams=16, mfma_min_entries=1 << 16),
+    # work-queue launches: one workgroup per unit (most tasks per workgroup),
+    # four, and one workgroup per tile; far-update column groups
+    dict(ml_width=2, streams=4, mfma_min_entries=1 << 16, queue_per_cu=1, far_groups=7),
+    dict(ml_width=2, streams=4, mfma_min_entries=1, queue_per_cu=4, far_groups=512),
+    dict(ml_width=2, streams=4, mfma_min_entries=(1 << 64) - 1, queue_per_cu=1),
+    dict(ml_width=2, streams=4, mfma_min_entries=1 << 16, queue_per_cu=fl.FL_BATCH_DIRECT),
 ]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=["tuned-or-default", "default", "w1-s1-mfma", "w4-s3-plain",
-                                              "w8-s16-mixed"])
+                                              "w8-s16-mixed", "queue1-g7", "queue4-g512-mfma",
+                                              "queue1-plain", "direct"])
 def test_batch_equals_oracle(cfg):
     b = fl.batch_plan(_up(MATS), P, cfg)
     fl.batch_run(b)
@@ -132,6 +139,7 @@ def test_batch_autotune_choice_is_used_and_exact():
     mats = _up(MATS)
     cfg, ms = fl.batch_autotune(mats, P)
     assert cfg["ml_width"] in (1, 2, 4) and 1 <= cfg["streams"] <= 16 and ms > 0
+    assert cfg["queue_per_cu"] in (fl.FL_BATCH_DIRECT, 1, 2, 4) and cfg["far_groups"] in (32, 128, 512)
     b = fl.batch_plan(mats, P, None)
     assert fl.batch_config(b) == cfg
     fl.batch_run(b)
