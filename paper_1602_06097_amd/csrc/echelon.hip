@@ -38,9 +38,6 @@
 #include "mfma_tile.h"
 #include "valu_tile.h"
 
-hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
-                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
                             uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,

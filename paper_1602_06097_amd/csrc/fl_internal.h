@@ -179,6 +179,13 @@ struct GemmPlanes {
     const uint32_t *kcap_n;
 };
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
+// C[M x N] -= A[M x K] B[K x N] (mod p) on the vector ALUs (gemm_plain.hip),
+// K = *Kdev when Kdev is given; krange_n / kfirst: optional zero-skipping
+// ranges of B's column tiles and A's rows (valu_tile.h).
+hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
+                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
+                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site,
+                             const uint32_t *krange_n = nullptr, const uint32_t *kfirst = nullptr);
 // A second stream and two events for work that overlaps the caller's stream,
 // one set per host thread, device and slot (< 4), kept until the process ends.
 fl_status fl_aux_stream(uint32_t slot, hipStream_t *s, hipEvent_t *a, hipEvent_t *b);

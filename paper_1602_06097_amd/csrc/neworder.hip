@@ -21,9 +21,6 @@
 
 hipError_t fl_csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
                            const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s);
-hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
-                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
 typedef void (*fl_limbs_cols_fn)(uint32_t, const uint16_t *, uint64_t, uint32_t, uint32_t,
                                  const uint32_t *, int8_t *, int8_t *, uint32_t, uint32_t *);

@@ -16,9 +16,6 @@ hipError_t fl_ml_spmm(uint32_t w, uint32_t p, const uint64_t *gptr, const uint32
 hipError_t fl_csr_to_dense(uint32_t rows, uint32_t cols, const uint64_t *rp, const uint32_t *ci,
                            const uint16_t *v, uint16_t *out, uint64_t ld, hipStream_t s);
 fl_status fl_check_split(const fl_split_info *info, const fl_split_out *s);
-hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
-                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
                             uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,

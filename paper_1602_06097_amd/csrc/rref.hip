@@ -17,9 +17,6 @@
 
 #include "fl_internal.h"
 
-hipError_t fl_gemm_sub_plain(uint32_t p, uint32_t M, uint32_t N, uint32_t Kh, const uint32_t *Kdev,
-                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
-                             uint16_t *C, uint64_t ldc, hipStream_t s, const char *site);
 hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, const uint32_t *Kdev,
                             const uint16_t *A, uint64_t lda, const uint16_t *B, uint64_t ldb,
                             uint16_t *C, uint64_t ldc, void *ws, size_t ws_bytes, hipStream_t s,
@@ -37,12 +34,19 @@ __global__ __launch_bounds__(256) void k_gather_pivcols(const uint16_t *__restri
                                                         uint32_t npiv,
                                                         const uint32_t *__restrict__ d_rank,
                                                         const uint32_t *__restrict__ pivcol,
-                                                        uint16_t *L, uint64_t ldl) {
+                                                        uint16_t *L, uint64_t ldl, uint32_t *tfirst) {
     const uint32_t r = *d_rank;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= r) return;
-    const uint32_t c = pivcol[t];
-    for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) L[(uint64_t)i * ldl + t] = X[(uint64_t)i * ldx + c];
+    const bool act = t < r;  // (every lane takes part in the wave minimum)
+    const uint32_t c = act ? pivcol[t] : 0;
+    for (uint32_t i = blockIdx.y; i < npiv; i += gridDim.y) {
+        const uint32_t x = act ? X[(uint64_t)i * ldx + c] : 0;
+        if (act) L[(uint64_t)i * ldl + t] = (uint16_t)x;
+        if (tfirst) {  // first pivot index t with X[i][q_t] != 0
+            const uint32_t first = ~fl_wave_max(x ? ~t : 0u);
+            if ((threadIdx.x & 63) == 0 && first != 0xffffffffu) atomicMin(&tfirst[i], first);
+        }
+    }
 }
 
 // MFMA form: L = X[:, P_D] directly as int8 limb planes (Kp bytes per row,
@@ -336,6 +340,12 @@ size_t rref_layout(const fl_split_info *info, fl_mode mode, void *ws, RrefWs *r)
     } else {
         t.ldl = ((uint64_t)maxr + 7) & ~(uint64_t)7;
         t.L = w.take<uint16_t>((size_t)(info->npiv ? info->npiv : 1) * (t.ldl ? t.ldl : 1));
+        const uint64_t np = ((uint64_t)info->nB + 127) / 128 * 128;
+        t.ntiles = (uint32_t)(np / 128);
+        t.tmin = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
+        t.tmax = w.take<uint32_t>(t.ntiles ? t.ntiles : 1);
+        t.krange = w.take<uint32_t>(2 * (size_t)(t.ntiles ? t.ntiles : 1));
+        t.tfirst = w.take<uint32_t>(info->npiv ? info->npiv : 1);
     }
     if (r) *r = t;
     return w.off;
@@ -401,12 +411,21 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
         gp.group_m = 4;
         FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "rref.mfma"));
     } else {
+        // the same zero-skipping as the MFMA form: per 128-column tile the R_D
+        // rows nonzero there, per row of X its first nonzero pivot column
+        FL_HIP(fl_fill_u32(r.tmin, 0xffffffffu, r.ntiles, stream));
+        FL_HIP(fl_fill_u32(r.tmax, 0, r.ntiles, stream));
+        FL_HIP(fl_fill_u32(r.tfirst, 0xffffffffu, npiv, stream));
+        hipLaunchKernelGGL(k_rd_tile_ranges, dim3((maxr + 3) / 4), dim3(256), 0, stream, RD, ldd, nB, d_rank,
+                           d_pivcol, r.tmin, r.tmax);
+        hipLaunchKernelGGL(k_krange_from_t, dim3((r.ntiles + 255) / 256), dim3(256), 0, stream, r.ntiles,
+                           (const uint32_t *)r.tmin, (const uint32_t *)r.tmax, (uint32_t)r.ldl, r.krange);
         dim3 g((maxr + 255) / 256, npiv < 1024 ? npiv : 1024);
         hipLaunchKernelGGL(k_gather_pivcols, g, dim3(256), 0, stream, (const uint16_t *)X, ldx, npiv,
-                           d_rank, d_pivcol, r.L, r.ldl);
+                           d_rank, d_pivcol, r.L, r.ldl, r.tfirst);
         FL_LAUNCH_CHECK("k_gather_pivcols");
         FL_HIP(fl_gemm_sub_plain(info->p, npiv, nB, 0, d_rank, r.L, r.ldl, RD, ldd, X, ldx, stream,
-                                 "rref.plain"));
+                                 "rref.plain", r.krange, r.tfirst));
     }
     return FL_OK;
 }

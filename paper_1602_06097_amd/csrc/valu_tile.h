@@ -18,16 +18,42 @@ constexpr int kRowsPerWave = 8;
 constexpr int kColsPerWave = 256;
 
 // Workgroup (bx, by): rows [(4 by + wave) * 8, +8) x columns [256 bx, +256).
+// Optional zero-skipping (both NULL: the whole K range):
+//   krange_n  per 128-column tile of B a range [b, e) of K holding every row
+//             of B with a nonzero in those columns (b >= e: none);
+//   kfirst    per row of A the first k with A[row][k] != 0 (0xffffffff: none).
 __device__ __forceinline__ void valu_gemm_tile(const fl::Mod &md, uint32_t M, uint32_t N, uint32_t Kh,
                                                const uint32_t *__restrict__ Kdev,
                                                const uint16_t *__restrict__ A, uint64_t lda,
                                                const uint16_t *__restrict__ B, uint64_t ldb,
-                                               uint16_t *C, uint64_t ldc, uint32_t bx, uint32_t by) {
+                                               uint16_t *C, uint64_t ldc, uint32_t bx, uint32_t by,
+                                               const uint32_t *__restrict__ krange_n = nullptr,
+                                               const uint32_t *__restrict__ kfirst = nullptr) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t row0 = (by * 4 + (threadIdx.x >> 6)) * kRowsPerWave;
     if (row0 >= M) return;
     const uint32_t K = Kdev ? *Kdev : Kh;
     if (K == 0) return;
+    uint32_t kbeg = 0, kend = K;
+    if (krange_n) {  // the (one or two) 128-column tiles of this 256-column tile
+        const uint32_t t0 = 2 * bx, nt = (N + 127) / 128;
+        uint32_t b = 0xffffffffu, e = 0;
+        for (uint32_t t = t0; t < t0 + 2 && t < nt; t++) {
+            const uint32_t tb = krange_n[2 * t], te = krange_n[2 * t + 1];
+            if (tb < te) {
+                b = tb < b ? tb : b;
+                e = te > e ? te : e;
+            }
+        }
+        kbeg = b > kbeg ? b : kbeg;
+        kend = e < kend ? e : kend;
+    }
+    if (kfirst) {  // the wave's rows are zero in A before their first nonzero
+        uint32_t f = 0xffffffffu;
+        for (uint32_t r = 0; r < kRowsPerWave && row0 + r < M; r++) f = kfirst[row0 + r] < f ? kfirst[row0 + r] : f;
+        kbeg = f > kbeg ? f : kbeg;
+    }
+    if (kbeg >= kend) return;  // (wave-uniform) nothing to subtract
     const uint32_t c0 = bx * kColsPerWave + lane * 4;
     const bool colok = c0 < N;
     uint32_t ah[kRowsPerWave][4], al[kRowsPerWave][4];
@@ -36,8 +62,8 @@ __device__ __forceinline__ void valu_gemm_tile(const fl::Mod &md, uint32_t M, ui
 #pragma unroll
         for (int c = 0; c < 4; c++) ah[r][c] = al[r][c] = 0;
     uint32_t terms = 0;
-    for (uint32_t k0 = 0; k0 < K; k0 += 64) {
-        const uint32_t chunk = K - k0 < 64 ? K - k0 : 64;
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += 64) {
+        const uint32_t chunk = kend - k0 < 64 ? kend - k0 : 64;
         uint32_t a[kRowsPerWave];
 #pragma unroll
         for (int r = 0; r < kRowsPerWave; r++)
