@@ -118,6 +118,7 @@ __device__ inline void reduce_against(const fl::Mod &md, uint32_t &v, uint32_t &
     uint32_t vh = 0, vl = 0, gh = 0, gl = 0;
     const uint32_t vin = v;
     const uint32_t cc = Cc[lane];
+#pragma unroll 4
     for (uint32_t t = t0; t < t1; t++) {
         const int cidx = __builtin_amdgcn_readlane((int)cc, (int)t);
         const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)vin, cidx);
@@ -144,6 +145,7 @@ __device__ inline void reduce_rows8(const fl::Mod &md, uint32_t (&v)[8], uint32_
 #pragma unroll
     for (int u = 0; u < 8; u++) vh[u] = vl[u] = 0;
     const uint32_t cc = Cc[lane];
+#pragma unroll 4
     for (uint32_t t = 0; t < kb; t++) {
         const int cidx = __builtin_amdgcn_readlane((int)cc, (int)t);
         const uint32_t b = Bv[t][lane];
@@ -318,20 +320,21 @@ __device__ void save_raw(const GreedyLds &S, PanelState *ps) {
 
 // Publish the panel result: basis rows ordered by pivot column, G, and the
 // global pivot bookkeeping (rank0 = rank before this panel).
+// All threads of the block call it (the rows of G are dealt to the waves).
 __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32_t rank0,
                          uint32_t *is_piv, uint32_t *piv_row, uint32_t *piv_col, uint32_t *d_rank) {
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (wave != 0) return;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t kb = S.kb;
-    uint32_t my_t = 0;
+    uint32_t my_t = 0;  // lane j < kb: the position of basis row j by pivot column
     if (lane < kb) {
         const uint32_t cj = S.Cc[lane];
         for (uint32_t j = 0; j < kb; j++) my_t += S.Cc[j] < cj ? 1 : 0;
     }
-    for (uint32_t j = 0; j < kb; j++) {
+    for (uint32_t j = wave; j < kb; j += nw) {
         const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)my_t, (int)j);
         ps->G[t * 64 + lane] = lane < kb ? S.Bg[j][lane] : 0;
     }
+    if (wave != 0) return;
     if (lane < kb) {
         const uint32_t t = my_t;
         ps->Phys[t] = S.Qo[lane];
@@ -354,16 +357,23 @@ __device__ void finalize(const GreedyLds &S, PanelState *ps, uint32_t c0, uint32
 // representatives need no elimination search: sorted by first nonzero column
 // (descending), their panel parts form a matrix whose restriction T to the
 // leading columns is lower triangular, and the reduced basis is T^-1 times
-// the rows (coefficients: T^-1 itself).  It is computed by back
-// substitution in groups of kProbeGroup slots: one wave finishes a group's
-// rows in order, in registers (each row reduced against the group's
-// earlier, finished rows), then all waves reduce the later slots against
-// the finished group.
-// Reduction against finished rows never changes a later slot's leading
-// entry (finished rows are zero left of their own, larger, leading column),
-// so every pivot's inverse is known from the start.  In the matrices of
-// the method the representatives span most of the panel; check and merge
-// add what is missing.
+// the rows (coefficients: T^-1 itself).  Any listed row may represent its
+// leading column (the panel's final basis, after check and merge, spans all
+// of its rows whichever are picked), so the pick is a plain LDS store.
+//
+// The back substitution runs over groups of kProbeGroup slots.  A row's
+// entries at the leading columns of the groups after its own are never
+// changed by reduction against the earlier groups' finished rows (those are
+// zero left of their own, larger, leading columns), so the solve of each
+// group among itself commutes with the reductions against the earlier
+// groups: first every group is solved among itself (one wave per group, all
+// groups at once, in registers: a row's multipliers are read from it as it
+// is on entry, the group's finished rows being in reduced form), then the
+// groups are finished in order, each reducing every later slot (all waves,
+// one barrier per group).  Every pivot's inverse is known from the start,
+// since the leading entries never change.  In the matrices of the method the
+// representatives span most of the panel; check and merge add what is
+// missing.
 constexpr uint32_t kProbeGroup = 8;
 constexpr uint32_t kLeadLoads = 16;  // lead entries in flight per thread
 
@@ -372,18 +382,18 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
     typedef __attribute__((address_space(1))) const uint32_t gu32;
     __shared__ GreedyLds S;
     __shared__ uint32_t rank0_s;
-    __shared__ unsigned long long s_rep[kPanel];  // (list position << 32) | row
+    __shared__ uint32_t s_rep[kPanel];  // a listed row per leading column
     const FlEchTask &t = tasks[ids[blockIdx.x]];
     if (P >= t.npanels) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
     const uint32_t n = t.counts[3 * P];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (threadIdx.x < kPanel) s_rep[threadIdx.x] = ~0ull;
+    if (threadIdx.x < kPanel) s_rep[threadIdx.x] = ~0u;
     __syncthreads();
-    // the first listed row of every leading column: a chunk of lead entries
-    // and list rows is loaded before any is used (the loads overlap), and the
-    // minimum of (position, row) keeps the row with it
+    // a listed row of every leading column: a chunk of lead entries and list
+    // rows is loaded before any is used (the loads overlap); the first store
+    // seen wins (a store after it overwrites with another valid row)
     const gu32 *lead = (const gu32 *)t.nzlead, *list = (const gu32 *)t.nzlist;
     for (uint32_t base = 0; base < n; base += kLeadLoads * blockDim.x) {
         uint32_t l[kLeadLoads], r[kLeadLoads];
@@ -396,19 +406,19 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
 #pragma unroll
         for (uint32_t u = 0; u < kLeadLoads; u++) {
             const uint32_t i = base + u * blockDim.x + threadIdx.x;
-            if (i < n) atomicMin(&s_rep[l[u]], ((unsigned long long)i << 32) | r[u]);
+            if (i < n && s_rep[l[u]] == ~0u) s_rep[l[u]] = r[u];
         }
     }
     __syncthreads();
     // slots by leading column, descending (lane 0 takes column 63)
     if (wave == 0) {
         const uint32_t c = kPanel - 1 - lane;
-        const unsigned long long at = s_rep[c];
-        const uint64_t have = __ballot(at != ~0ull);
-        if (at != ~0ull) {
+        const uint32_t at = s_rep[c];
+        const uint64_t have = __ballot(at != ~0u);
+        if (at != ~0u) {
             const uint32_t s = (uint32_t)__popcll(have & ((1ull << lane) - 1));
             S.Cc[s] = c;
-            S.Qo[s] = (uint32_t)at;
+            S.Qo[s] = at;
         }
         if (lane == 0) {
             S.kb = (uint32_t)__popcll(have);
@@ -425,46 +435,50 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_probe(fl::Mod md, const 
         S.Bg[s][lane] = lane == s ? 1 : 0;
     }
     __syncthreads();
-    // lane s of wave 0: inverse of slot s's leading entry
-    const uint32_t inv = wave == 0 && lane < kr ? fl::invmod(S.Bv[lane][S.Cc[lane]], md) : 0;
-    const uint32_t ccv = S.Cc[lane];  // lane t: Cc[t]
-    for (uint32_t g0 = 0; g0 < kr; g0 += kProbeGroup) {
-        const uint32_t g1 = g0 + kProbeGroup < kr ? g0 + kProbeGroup : kr;
-        if (wave == 0) {
-            // the group's rows in registers (row j = slot g0 + j), finished in
-            // order: row j's multipliers are read from it as it is on entry
-            uint32_t v[kProbeGroup], g[kProbeGroup];
+    const uint32_t ng = (kr + kProbeGroup - 1) / kProbeGroup;
+    static_assert(kGreedyThreads / 64 >= kPanel / kProbeGroup, "one wave per group");
+    if (wave < ng) {
+        // group `wave` among itself: rows j = slot g0 + j in registers,
+        // finished in order
+        const uint32_t g0 = wave * kProbeGroup, g1 = g0 + kProbeGroup < kr ? g0 + kProbeGroup : kr;
+        const uint32_t ccv = S.Cc[lane];  // lane t: Cc[t]
+        // lane s of the group: inverse of slot s's leading entry
+        const uint32_t inv = lane >= g0 && lane < g1 ? fl::invmod(S.Bv[lane][ccv], md) : 0;
+        uint32_t v[kProbeGroup], g[kProbeGroup];
 #pragma unroll
-            for (uint32_t j = 0; j < kProbeGroup; j++) {
-                v[j] = g0 + j < g1 ? S.Bv[g0 + j][lane] : 0;
-                g[j] = g0 + j < g1 ? S.Bg[g0 + j][lane] : 0;
+        for (uint32_t j = 0; j < kProbeGroup; j++) {
+            v[j] = g0 + j < g1 ? S.Bv[g0 + j][lane] : 0;
+            g[j] = g0 + j < g1 ? S.Bg[g0 + j][lane] : 0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kProbeGroup; j++) {
+            if (g0 + j >= g1) break;
+            uint32_t hv = 0, lv = 0, hg = 0, lg = 0;
+#pragma unroll
+            for (uint32_t u = 0; u < j; u++) {
+                const int cidx = __builtin_amdgcn_readlane((int)ccv, (int)(g0 + u));
+                const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)v[j], cidx);
+                hv = fl::mad24(lam >> 8, v[u], hv);
+                lv = fl::mad24(lam & 0xffu, v[u], lv);
+                hg = fl::mad24(lam >> 8, g[u], hg);
+                lg = fl::mad24(lam & 0xffu, g[u], lg);
             }
+            const uint32_t is = (uint32_t)__builtin_amdgcn_readlane((int)inv, (int)(g0 + j));
+            v[j] = fl::mulmod(fl::submod(v[j], fl::fold_pair(hv, lv, md), md.p), is, md);
+            g[j] = fl::mulmod(fl::submod(g[j], fl::fold_pair(hg, lg, md), md.p), is, md);
+        }
 #pragma unroll
-            for (uint32_t j = 0; j < kProbeGroup; j++) {
-                if (g0 + j >= g1) break;
-                uint32_t hv = 0, lv = 0, hg = 0, lg = 0;
-#pragma unroll
-                for (uint32_t t = 0; t < j; t++) {
-                    const int cidx = __builtin_amdgcn_readlane((int)ccv, (int)(g0 + t));
-                    const uint32_t lam = (uint32_t)__builtin_amdgcn_readlane((int)v[j], cidx);
-                    hv = fl::mad24(lam >> 8, v[t], hv);
-                    lv = fl::mad24(lam & 0xffu, v[t], lv);
-                    hg = fl::mad24(lam >> 8, g[t], hg);
-                    lg = fl::mad24(lam & 0xffu, g[t], lg);
-                }
-                const uint32_t is = (uint32_t)__builtin_amdgcn_readlane((int)inv, (int)(g0 + j));
-                v[j] = fl::mulmod(fl::submod(v[j], fl::fold_pair(hv, lv, md), md.p), is, md);
-                g[j] = fl::mulmod(fl::submod(g[j], fl::fold_pair(hg, lg, md), md.p), is, md);
-            }
-#pragma unroll
-            for (uint32_t j = 0; j < kProbeGroup; j++) {
-                if (g0 + j < g1) {
-                    S.Bv[g0 + j][lane] = (uint16_t)v[j];
-                    S.Bg[g0 + j][lane] = (uint16_t)g[j];
-                }
+        for (uint32_t j = 0; j < kProbeGroup; j++) {
+            if (g0 + j < g1) {
+                S.Bv[g0 + j][lane] = (uint16_t)v[j];
+                S.Bg[g0 + j][lane] = (uint16_t)g[j];
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // group h is finished: every later slot is reduced against it
+    for (uint32_t h = 0; h + 1 < ng; h++) {
+        const uint32_t g0 = h * kProbeGroup, g1 = g0 + kProbeGroup;
         for (uint32_t s = g1 + wave; s < kr; s += nw) {
             uint32_t v = S.Bv[s][lane], g = S.Bg[s][lane];
             reduce_against(md, v, g, g0, g1, S.Bv, S.Bg, S.Cc, lane, true);

@@ -132,7 +132,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     // Operand pipeline: the four plane tiles of a K step (128 rows x 64 bytes
     // each, 32 blocks of 16 rows) are copied global -> LDS by the DMA path
     // (global_load_lds, no registers involved) into a ring of kStages slots,
-    // issued kStages - 1 steps ahead.  Wave w fills blocks 4 (w & 1) .. + 3
+    // issued kStages steps ahead.  Wave w fills blocks 4 (w & 1) .. + 3
     // of plane w / 2, one 1 KiB block per instruction (lane L -> row L / 4,
     // slot L % 4); chunk c of row r sits in slot c ^ ((r >> 2) & 3) so that
     // the 16-row reads below hit all LDS banks.
@@ -189,29 +189,30 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         }
     };
     auto next = [](uint32_t slot) { return slot + 1 == kStages ? 0u : slot + 1; };
-    auto prev = [](uint32_t slot) { return slot == 0 ? kStages - 1 : slot - 1; };
     // The fragments of step j + 1 are read during step j (into the second
     // register set, copied over after the MFMAs), so the LDS reads overlap
     // the MFMAs.  Step j's iteration waits for step j + 1's slot (at most the
-    // kStages - 3 later steps' instructions outstanding); the barrier also
-    // retires every wave's reads of step j - 1's slot, which is refilled next.
+    // kStages - 2 later steps' instructions outstanding) and for its own LDS
+    // reads of step j's slot, issued in the previous iteration; after the
+    // barrier no wave reads step j's slot any more, and it is refilled with
+    // step j + kStages: kStages - 1 steps are in flight while one is read.
     v4i ah[4], al[4], bh[2], bl[2], nah[4], nal[4], nbh[2], nbl[2];
     const LimbCombine lc = limb_combine(md, bias, c16);
     uint32_t slot = 0;  // ring slot of step k0
     uint32_t left = kKChunk / BK;  // K steps before the accumulators are folded
     if (kbeg < kend) {
 #pragma unroll
-        for (uint32_t s = 0; s + 1 < kStages; s++) issue(kbeg + s * BK, s);
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 2) * 4) : "memory");
+        for (uint32_t s = 0; s < kStages; s++) issue(kbeg + s * BK, s);
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 1) * 4) : "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         read_ops(0, ah, al, bh, bl);
     }
     for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 3) * 4) : "memory");
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"((kStages - 2) * 4) : "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        issue(k0 + (kStages - 1) * BK, prev(slot));
+        issue(k0 + kStages * BK, slot);
         const bool more = k0 + BK < kend;
         if (more) read_ops(next(slot), nah, nal, nbh, nbl);
 #pragma unroll
