@@ -582,48 +582,6 @@ __global__ __launch_bounds__(fl_mfma::kGemmThreads) void k_trsm_update_mfma_b(fl
     }
 }
 
-// Near update of block [r0, r1) (single matrix): X[r0:r1] -= A[r0:r1, r1:r1 + 64 KS]
-// X[r1:r1 + 64 KS] from the limb planes (the band is zero past the block's
-// entries), one 64-row x 64-column tile per workgroup, operands read
-// straight from global memory (K is at most 384: no LDS ring needed).  The
-// narrow tiles give four workgroups per unit: the kernel is bound by the
-// latency of its operand loads, which more workgroups in flight overlap.
-template <int KS>
-__global__ __launch_bounds__(256) void k_trsm_near(fl::Mod md, uint32_t bias, uint32_t c16, const int8_t *Ah,
-                                                   const int8_t *Al, const int8_t *Xh, const int8_t *Xl,
-                                                   uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
-                                                   uint64_t ldx, uint32_t nB, const uint32_t *__restrict__ xkend) {
-    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * fl_mfma::kRank64Ld];
-    __shared__ uint32_t rows_s[64];
-    // rows r1.. of X are zero in these columns: nothing to subtract
-    if (xkend && xkend[blockIdx.x / 2] <= r1) return;
-    fl_mfma::mfma_rankk_tile<KS, 4>(md, bias, c16, Ah + (uint64_t)r0 * kp + r1, Al + (uint64_t)r0 * kp + r1,
-                                    (uint32_t)kp, Xh + r1, Xl + r1, (uint32_t)kp, nullptr, r1 - r0,
-                                    X + (uint64_t)r0 * ldx, ldx, nB, blockIdx.x, blockIdx.y, sv, rows_s);
-}
-
-hipError_t trsm_near(uint32_t ks, const fl::Mod &md, uint32_t p, const int8_t *Ah, const int8_t *Al,
-                     const int8_t *Xh, const int8_t *Xl, uint64_t kp, uint32_t r0, uint32_t r1, uint16_t *X,
-                     uint64_t ldx, uint32_t nB, const uint32_t *xkend, hipStream_t s) {
-    const dim3 grid((nB + 63) / 64, (r1 - r0 + 63) / 64);
-    const uint32_t bias = fl_mfma::gemm_bias(p), c16 = fl_mfma::gemm_c16(p);
-#define FL_NEAR(K)                                                                                         \
-    case K:                                                                                                \
-        hipLaunchKernelGGL(k_trsm_near<K>, grid, dim3(256), 0, s, md, bias, c16, Ah, Al, Xh, Xl, kp, r0, r1, X, \
-                           ldx, nB, xkend);                                                                \
-        break;
-    switch (ks) {
-        FL_NEAR(1)
-        FL_NEAR(2)
-        FL_NEAR(3)
-        FL_NEAR(4)
-        FL_NEAR(5)
-        FL_NEAR(6)
-    default: return hipErrorInvalidValue;
-    }
-#undef FL_NEAR
-    return hipGetLastError();
-}
 
 // ---- int8-MFMA form: block solves as products with the block inverses ----
 // The diagonal block T = A[r0:r1, r0:r1] of every block is unit upper
@@ -680,11 +638,85 @@ struct __attribute__((aligned(16))) ApplyLds {
     int8_t Bl[64][kTrsmBlock];
 };
 
+// The block's near update inside its solve: R[0:nrow) -= A[r0:r1, r1:r1 + 64 KS]
+// X[r1:r1 + 64 KS] for the workgroup's 64 columns, from the limb planes
+// (A row-major, X transposed, kp bytes per row / column), on R in LDS.  Wave
+// w computes rows [32 w, 32 w + 32) as two 16-row tiles, column tile j (16
+// columns) at a time with the next tile's X fragments in flight; every
+// output is owned by one lane.  K <= 384 terms: the limb sums stay far
+// inside combine_limbs' bounds.
+template <int KS>
+__device__ __forceinline__ void trsm_near_lds(const fl::Mod &md, const fl_mfma::LimbCombine &lc,
+                                              const int8_t *__restrict__ Ah, const int8_t *__restrict__ Al,
+                                              const int8_t *__restrict__ Xh, const int8_t *__restrict__ Xl,
+                                              uint64_t kp, uint32_t r0, uint32_t r1, uint32_t c0, uint32_t nB,
+                                              uint16_t (*R)[64]) {
+    using fl_mfma::v4i;
+    typedef __attribute__((address_space(1))) const v4i gv4i;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nrow = r1 - r0;
+    const uint32_t cl = lane & 15, kq = (lane >> 4) * 16, rq = (lane >> 4) * 4;
+    v4i ah[2][KS], al[2][KS];
+#pragma unroll
+    for (int rt = 0; rt < 2; rt++) {
+        const uint32_t row = wave * 32 + rt * 16 + cl;
+        const uint64_t o = (uint64_t)(r0 + (row < nrow ? row : 0)) * kp + r1 + kq;
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            ah[rt][s] = row < nrow ? *(gv4i *)(Ah + o + s * 64) : v4i{0, 0, 0, 0};
+            al[rt][s] = row < nrow ? *(gv4i *)(Al + o + s * 64) : v4i{0, 0, 0, 0};
+        }
+    }
+    v4i bh[2][KS], bl[2][KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+        const uint64_t o = (uint64_t)(c0 + cl) * kp + r1 + s * 64 + kq;
+        bh[0][s] = *(gv4i *)(Xh + o);
+        bl[0][s] = *(gv4i *)(Xl + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int cur = j & 1, nxt = cur ^ 1;
+        if (j + 1 < 4) {
+#pragma unroll
+            for (int s = 0; s < KS; s++) {
+                const uint64_t o = (uint64_t)(c0 + (j + 1) * 16 + cl) * kp + r1 + s * 64 + kq;
+                bh[nxt][s] = *(gv4i *)(Xh + o);
+                bl[nxt][s] = *(gv4i *)(Xl + o);
+            }
+        }
+        v4i hh[2], mid[2], ll[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++) hh[rt] = mid[rt] = ll[rt] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int rt = 0; rt < 2; rt++) {
+                hh[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[rt][s], bh[cur][s], hh[rt], 0, 0, 0);
+                mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[rt][s], bl[cur][s], mid[rt], 0, 0, 0);
+                mid[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[rt][s], bh[cur][s], mid[rt], 0, 0, 0);
+                ll[rt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[rt][s], bl[cur][s], ll[rt], 0, 0, 0);
+            }
+        const uint32_t col = j * 16 + cl;
+#pragma unroll
+        for (int rt = 0; rt < 2; rt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t row = wave * 32 + rt * 16 + rq + e;
+                const uint32_t v = fl_mfma::combine_limbs(lc, hh[rt][e], mid[rt][e], ll[rt][e]);
+                if (row < nrow && c0 + col < nB) R[row][col] = (uint16_t)fl::submod(R[row][col], v, md.p);
+            }
+    }
+}
+
+// KS > 0: the near update of the block (A columns [r1, r1 + 64 KS)) is
+// applied to R in LDS first (see trsm_near_lds); column tiles whose X rows
+// past r1 are all zero skip it.
+template <int KS = 0>
 __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                 const int8_t *__restrict__ Th, const int8_t *__restrict__ Tl,
                                                 uint32_t r0, uint32_t r1, uint16_t *X, uint64_t ldx, uint32_t nB,
                                                 int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t *xkend, uint32_t bx,
-                                                ApplyLds &S) {
+                                                ApplyLds &S, const int8_t *Ah = nullptr, const int8_t *Al = nullptr) {
     using fl_mfma::v4i;
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) const v4i gv4i;
@@ -707,22 +739,34 @@ __device__ __forceinline__ void trsm_apply_tile(const fl::Mod &md, uint32_t bias
         }
     }
     // A fragments: rows 32 w + 16 rt + (lane & 15), K bytes 64 s + 16 (lane >> 4)
+    // (after the near update when there is one: fewer registers live there)
     const uint32_t cl = lane & 15, kq = (lane >> 4) * 16, rq = (lane >> 4) * 4;
     v4i ah[2][2], al[2][2];
+    auto load_t = [&]() {
 #pragma unroll
-    for (int rt = 0; rt < 2; rt++)
+        for (int rt = 0; rt < 2; rt++)
 #pragma unroll
-        for (int s = 0; s < 2; s++) {
-            const uint64_t o = (uint64_t)(r0 + wave * 32 + rt * 16 + cl) * kTrsmBlock + s * 64 + kq;
-            ah[rt][s] = *(gv4i *)(Th + o);
-            al[rt][s] = *(gv4i *)(Tl + o);
-        }
+            for (int s = 0; s < 2; s++) {
+                const uint64_t o = (uint64_t)(r0 + wave * 32 + rt * 16 + cl) * kTrsmBlock + s * 64 + kq;
+                ah[rt][s] = *(gv4i *)(Th + o);
+                al[rt][s] = *(gv4i *)(Tl + o);
+            }
+    };
+    if (KS == 0) load_t();
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const uint32_t ch = tid + u * 256, r = ch >> 4, c4 = (ch & 15) * 4;
         *(uint64_t *)&S.R[r][c4] = rv[u];
     }
     __syncthreads();
+    if constexpr (KS > 0) {
+        // (uniform per workgroup) rows past r1 of X are zero in these columns
+        if (!(xkend && xkend[c0 / 128] <= r1)) {
+            trsm_near_lds<KS>(md, lc, Ah, Al, Xh, Xl, kp, r0, r1, c0, nB, S.R);
+            __syncthreads();
+        }
+        load_t();
+    }
     // transpose to limbs: thread -> (column, 16-row group), two per thread
 #pragma unroll
     for (int u = 0; u < 2; u++) {
@@ -816,6 +860,20 @@ __global__ __launch_bounds__(256) void k_trsm_apply(fl::Mod md, uint32_t bias, u
                                                     int8_t *Xh, int8_t *Xl, uint64_t kp, uint32_t *xkend) {
     __shared__ ApplyLds S;
     trsm_apply_tile(md, bias, c16, Th, Tl, r0, r1, X, ldx, nB, Xh, Xl, kp, xkend, blockIdx.x, S);
+}
+
+// The near update of block [r0, r1) (A columns [r1, r1 + 64 KS), the blocks
+// of its superblock solved since its far update) and its solve in one
+// launch: both are local to the workgroup's 64 columns.
+template <int KS>
+__global__ __launch_bounds__(256) void k_trsm_near_apply(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                         const int8_t *__restrict__ Th,
+                                                         const int8_t *__restrict__ Tl, const int8_t *Ah,
+                                                         const int8_t *Al, uint32_t r0, uint32_t r1, uint16_t *X,
+                                                         uint64_t ldx, uint32_t nB, int8_t *Xh, int8_t *Xl,
+                                                         uint64_t kp, uint32_t *xkend) {
+    __shared__ ApplyLds S;
+    trsm_apply_tile<KS>(md, bias, c16, Th, Tl, r0, r1, X, ldx, nB, Xh, Xl, kp, xkend, blockIdx.x, S, Ah, Al);
 }
 
 // The same for many matrices: the step's block of every MFMA-form matrix,
@@ -1188,6 +1246,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
     for (uint32_t I = t.nblk; I-- > 0;) {
         const uint32_t r0 = I * kTrsmBlock;
         const uint32_t r1 = r0 + kTrsmBlock < npiv ? r0 + kTrsmBlock : npiv;
+        uint32_t near_ks = 0;  // MFMA form: K steps of the near update, done in the solve's launch
         if (r1 < npiv) {
             hipError_t e;
             if (t.mfma) {
@@ -1228,9 +1287,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                         far_pending = true;
                     }
                 } else {  // near update: the blocks of the superblock solved since
-                    FL_PROF("trsm.update.near", stream,
-                            e = trsm_near((R1 - r1 + 63) / 64, md, info->p, t.Ah, t.Al, t.Xh, t.Xl, t.kp, r0, r1,
-                                          X, ldx, nB, t.xkend, stream));
+                    near_ks = (R1 - r1 + 63) / 64;
                 }
             } else {
                 const uint32_t g0 = r0 / w, g1 = (r1 + w - 1) / w;
@@ -1242,11 +1299,32 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
         }
         hipError_t e;
         if (t.mfma) {
-            FL_PROF("trsm.apply", stream,
-                    hipLaunchKernelGGL(k_trsm_apply, dim3((nB + 63) / 64), dim3(256), 0, stream, md,
-                                       fl_mfma::gemm_bias(info->p), fl_mfma::gemm_c16(info->p),
-                                       (const int8_t *)t.Th, (const int8_t *)t.Tl, r0, r1, X, ldx, nB, t.Xh, t.Xl,
-                                       t.kp, t.xkend));
+            const uint32_t bias = fl_mfma::gemm_bias(info->p), c16 = fl_mfma::gemm_c16(info->p);
+            const dim3 grid((nB + 63) / 64);
+            const int8_t *Th = t.Th, *Tl = t.Tl;
+            if (near_ks == 0) {
+                FL_PROF("trsm.apply", stream,
+                        hipLaunchKernelGGL(k_trsm_apply, grid, dim3(256), 0, stream, md, bias, c16, Th, Tl, r0, r1,
+                                           X, ldx, nB, t.Xh, t.Xl, t.kp, t.xkend));
+            } else {
+#define FL_NEAR_APPLY(K)                                                                                        \
+    case K:                                                                                                     \
+        FL_PROF("trsm.near_apply", stream,                                                                      \
+                hipLaunchKernelGGL(k_trsm_near_apply<K>, grid, dim3(256), 0, stream, md, bias, c16, Th, Tl,     \
+                                   (const int8_t *)t.Ah, (const int8_t *)t.Al, r0, r1, X, ldx, nB, t.Xh, t.Xl, \
+                                   t.kp, t.xkend));                                                             \
+        break;
+                switch (near_ks) {
+                    FL_NEAR_APPLY(1)
+                    FL_NEAR_APPLY(2)
+                    FL_NEAR_APPLY(3)
+                    FL_NEAR_APPLY(4)
+                    FL_NEAR_APPLY(5)
+                    FL_NEAR_APPLY(6)
+                default: FL_HIP(hipErrorInvalidValue);
+                }
+#undef FL_NEAR_APPLY
+            }
             e = hipGetLastError();
         } else {
             FL_PROF("trsm.solve", stream,
