@@ -31,12 +31,11 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128, BN = 128, BK = 64;
 constexpr uint32_t kKChunk = 65472;  // multiple of BK, < 65536
-constexpr int kLdsRow = BK + 16;     // padded LDS row (bytes) against bank conflicts
 constexpr int kOutLd = BN + 4;       // u16 row stride of the epilogue tile (8-byte aligned rows)
-constexpr uint32_t kStages = 4;                 // operand ring depth (K steps)
-constexpr uint32_t kPlaneBytes = BM * BK;       // one plane tile: 128 rows x 64 bytes
-constexpr uint32_t kStageBytes = 4 * kPlaneBytes;
-constexpr int kGemmLds = kStages * kStageBytes;  // bytes of LDS of one GEMM tile
+constexpr uint32_t kPairRow = 2 * BK;                // bytes of a plane row in a ring slot (two K steps)
+constexpr uint32_t kPairPlane = BM * kPairRow;       // one plane tile of a slot: 128 rows x 128 bytes
+constexpr uint32_t kPairBytes = 4 * kPairPlane;      // one ring slot: the four plane tiles
+constexpr int kGemmLds = 2 * kPairBytes;             // bytes of LDS of one GEMM tile (two slots)
 constexpr int kRank64Ld = 128 + 4;          // u16 row stride of the rank-k residue tile
 
 // The residue of S = 65536 S_hh + 256 S_mid + S_ll mod p from the three int32
@@ -129,15 +128,18 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             acc_mid[i][j] = v4i{0, 0, 0, 0};
             acc_ll[i][j] = v4i{0, 0, 0, 0};
         }
-    // Operand pipeline: the four plane tiles of a K step (128 rows x 64 bytes
-    // each, 32 blocks of 16 rows) are copied global -> LDS by the DMA path
-    // (global_load_lds, no registers involved) into a ring of kStages slots,
-    // issued kStages steps ahead.  Wave w fills blocks 4 (w & 1) .. + 3
-    // of plane w / 2, one 1 KiB block per instruction (lane L -> row L / 4,
-    // slot L % 4); chunk c of row r sits in slot c ^ ((r >> 2) & 3) so that
-    // the 16-row reads below hit all LDS banks.
+    // Operand pipeline: K steps are fetched in pairs, so that every row of a
+    // plane tile is read as one whole 128-byte line (two 64-byte steps).  A
+    // ring of two slots holds pairs of the four plane tiles (128 rows x 128
+    // bytes each), copied global -> LDS by the DMA path (global_load_lds, no
+    // registers involved).  Wave w fills rows 64 (w & 1) .. + 63 of plane
+    // w / 2, 8 rows per instruction (lane L -> row L / 8, slot L % 8); global
+    // chunk c (16 bytes) of row r sits in slot c ^ swz(r), swz(r) =
+    // ((r >> 1) & 7) ^ (4 (r & 1)), so that the 16-row fragment reads below
+    // hit distinct banks for both 128- and 256-byte LDS cycles.  A pair whose
+    // second step lies past kend fetches its first step twice (chunks 4..7
+    // repeat 0..3), so no fetch leaves [kbeg, kend).
     const uint32_t ring = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int8_t *)smem;
-    const uint32_t lrow = lane >> 2, lslot = lane & 3;
     const uint32_t plane = wave >> 1;
     // (selected with masks: a select among the kernel argument's fields by a
     // runtime index would be compiled into a private-memory table)
@@ -149,94 +151,106 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     const uint64_t p_a = ((uint64_t)(uintptr_t)g.Ah & m_lo) | ((uint64_t)(uintptr_t)g.Al & ~m_lo);
     const uint64_t p_b = ((uint64_t)(uintptr_t)g.Bh & m_lo) | ((uint64_t)(uintptr_t)g.Bl & ~m_lo);
     const int8_t *const pbase = (const int8_t *)(uintptr_t)(((p_a & m_a) | (p_b & ~m_a)) + poff);
-    uint64_t goff[4];  // the lane's offset in the plane tile, per instruction
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const uint32_t r = ((wave & 1) * 4 + i) * 16 + lrow;
-        goff[i] = (uint64_t)r * pld + (uint32_t)((lslot ^ ((r >> 2) & 3)) * 16);
-    }
-    // one K step into ring slot `slot` (steps past kend re-read the last valid
-    // step, so every step issues the same 4 instructions per wave)
-    auto issue = [&](uint32_t k0, uint32_t slot) {
+    auto swz = [](uint32_t r) { return ((r >> 1) & 7u) ^ ((r & 1u) << 2); };
+    // the lane's row of instruction 0 and its chunk there; instruction i is 8 i
+    // rows further down, where swz differs by 4 (i odd)
+    const uint32_t lrow = (wave & 1) * 64 + (lane >> 3), lpos = lane & 7;
+    const uint32_t lchunk = lpos ^ swz(lrow);
+    const uint64_t lbase = (uint64_t)lrow * pld;
+    const uint32_t last_pair = kbeg + (kend > kbeg ? (kend - kbeg - 1) / (2 * BK) * (2 * BK) : 0);
+    // pair starting at K offset ks (past the range: the last pair, fetched
+    // again, so every pair issues the same 8 instructions per wave) into
+    // slot `slot`
+    auto issue = [&](uint32_t ks, uint32_t slot) {
         if (ONE && !(plane & 1)) return;  // an h plane: all zero
-        const uint32_t kk = k0 < kend ? k0 : kend - BK;
+        const uint32_t kk = ks < kend ? ks : last_pair;
+        const uint32_t cmask = kk + 2 * BK <= kend ? 7u : 3u;
+        const int8_t *src_e = pbase + lbase + kk + ((lchunk & cmask) << 4);        // even i
+        const int8_t *src_o = pbase + lbase + kk + (((lchunk ^ 4u) & cmask) << 4);  // odd i
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int8_t *src = pbase + goff[i] + kk;
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kStageBytes + plane * kPlaneBytes +
-                                                                ((wave & 1) * 4 + i) * 1024);
+        for (int i = 0; i < 8; i++) {
+            const int8_t *src = ((i & 1) ? src_o : src_e) + (uint64_t)(i * 8) * pld;
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kPairBytes + plane * kPairPlane +
+                                                                ((wave & 1) * 64 + i * 8) * kPairRow);
             asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory");
         }
     };
-    // The wave's fragments of a step: A row tiles (4 of 16 rows) and B column
-    // tiles (2 of 16 columns), both limb planes, 16 bytes of K per lane.
+    // The wave's fragments of a step (half h of the pair in slot `slot`): A
+    // row tiles (4 of 16 rows) and B column tiles (2 of 16 columns), both limb
+    // planes, 16 bytes of K per lane.
     const uint32_t kc = lane >> 4;
-    auto read_ops = [&](uint32_t slot, v4i (&ah)[4], v4i (&al)[4], v4i (&bh)[2], v4i (&bl)[2]) {
-        const int8_t *st = smem + slot * kStageBytes;
+    auto read_ops = [&](uint32_t slot, uint32_t h, v4i (&ah)[4], v4i (&al)[4], v4i (&bh)[2], v4i (&bl)[2]) {
+        const int8_t *st = smem + slot * kPairBytes;
+        const uint32_t gc = h * 4 + kc;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
-            const uint32_t oa = ra * 64 + ((kc ^ ((ra >> 2) & 3)) << 4);
+            const uint32_t oa = ra * kPairRow + ((gc ^ swz(ra)) << 4);
             if (!ONE) ah[t] = *(const v4i *)(st + oa);
-            al[t] = *(const v4i *)(st + kPlaneBytes + oa);
+            al[t] = *(const v4i *)(st + kPairPlane + oa);
         }
 #pragma unroll
         for (int t = 0; t < 2; t++) {
             const uint32_t rb = wn * 32 + t * 16 + (lane & 15);
-            const uint32_t ob = rb * 64 + ((kc ^ ((rb >> 2) & 3)) << 4);
-            if (!ONE) bh[t] = *(const v4i *)(st + 2 * kPlaneBytes + ob);
-            bl[t] = *(const v4i *)(st + 3 * kPlaneBytes + ob);
+            const uint32_t ob = rb * kPairRow + ((gc ^ swz(rb)) << 4);
+            if (!ONE) bh[t] = *(const v4i *)(st + 2 * kPairPlane + ob);
+            bl[t] = *(const v4i *)(st + 3 * kPairPlane + ob);
         }
     };
-    auto next = [](uint32_t slot) { return slot + 1 == kStages ? 0u : slot + 1; };
-    // The fragments of step j + 1 are read during step j (into the second
-    // register set, copied over after the MFMAs), so the LDS reads overlap
-    // the MFMAs.  Step j's iteration waits for step j + 1's slot (at most the
-    // kStages - 2 later steps' instructions outstanding) and for its own LDS
-    // reads of step j's slot, issued in the previous iteration; after the
-    // barrier no wave reads step j's slot any more, and it is refilled with
-    // step j + kStages: kStages - 1 steps are in flight while one is read.
+    // Step j is half j & 1 of pair j / 2 (slot (j / 2) & 1).  Its fragments
+    // are read during step j - 1 (into the second register set, copied over
+    // after the MFMAs), so the LDS reads overlap the MFMAs.  At an odd step
+    // the next step opens a new pair: the wave waits for that pair's fetch
+    // (issued two steps earlier) and for its own LDS reads; after the
+    // barrier nobody reads the pair just finished, and its slot is refilled
+    // with the pair after the next.  Even steps need no barrier.
     v4i ah[4], al[4], bh[2], bl[2], nah[4], nal[4], nbh[2], nbl[2];
     const LimbCombine lc = limb_combine(md, bias, c16);
-    uint32_t slot = 0;  // ring slot of step k0
     uint32_t left = kKChunk / BK;  // K steps before the accumulators are folded
     if (kbeg < kend) {
-#pragma unroll
-        for (uint32_t s = 0; s < kStages; s++) issue(kbeg + s * BK, s);
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStages - 1) * 4) : "memory");
+        issue(kbeg, 0);
+        issue(kbeg + 2 * BK, 1);
+        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        read_ops(0, ah, al, bh, bl);
+        read_ops(0, 0, ah, al, bh, bl);
     }
-    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
-        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"((kStages - 2) * 4) : "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        issue(k0 + kStages * BK, slot);
+    uint32_t j = 0;
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK, j++) {
         const bool more = k0 + BK < kend;
-        if (more) read_ops(next(slot), nah, nal, nbh, nbl);
+        if (j & 1) {
+            const uint32_t q = (j + 1) >> 1;  // the pair of step j + 1
+            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            issue(kbeg + (q + 1) * 2 * BK, (q + 1) & 1);
+            if (more) read_ops(q & 1, 0, nah, nal, nbh, nbl);
+        } else if (more) {
+            read_ops((j >> 1) & 1, 1, nah, nal, nbh, nbl);
+        }
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
+            for (int jj = 0; jj < 2; jj++) {
                 if (!ONE) {
-                    acc_hh[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
-                    acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[j], acc_mid[i][j], 0, 0, 0);
-                    acc_mid[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[j], acc_mid[i][j], 0, 0, 0);
+                    acc_hh[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[jj], acc_hh[i][jj], 0, 0, 0);
+                    acc_mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[jj], acc_mid[i][jj], 0, 0, 0);
+                    acc_mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[jj], acc_mid[i][jj], 0, 0, 0);
                 }
-                acc_ll[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[j], acc_ll[i][j], 0, 0, 0);
+                acc_ll[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[jj], acc_ll[i][jj], 0, 0, 0);
             }
         if (--left == 0 && more) {  // a K range longer than kKChunk: fold
             left = kKChunk / BK;
 #pragma unroll
             for (int i = 0; i < 4; i++)
 #pragma unroll
-                for (int j = 0; j < 2; j++)
+                for (int jj = 0; jj < 2; jj++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        acc_ll[i][j][e] = (int)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
-                        acc_hh[i][j][e] = 0;
-                        acc_mid[i][j][e] = 0;
+                        acc_ll[i][jj][e] =
+                            (int)combine_limbs(lc, acc_hh[i][jj][e], acc_mid[i][jj][e], acc_ll[i][jj][e]);
+                        acc_hh[i][jj][e] = 0;
+                        acc_mid[i][jj][e] = 0;
                     }
         }
         if (more) {
@@ -251,7 +265,6 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                 bl[t] = nbl[t];
             }
         }
-        slot = next(slot);
     }
     // drain the DMA path before the ring is reused for the output tile
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
