@@ -214,6 +214,9 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         read_ops(0, 0, ah, al, bh, bl);
+        // (a wait the compiler sees: the loop's MFMAs then never wait for the
+        // next step's LDS reads, issued just before them)
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     }
     uint32_t j = 0;
     for (uint32_t k0 = kbeg; k0 < kend; k0 += BK, j++) {
@@ -224,10 +227,11 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
             issue(kbeg + (q + 1) * 2 * BK, (q + 1) & 1);
-            if (more) read_ops(q & 1, 0, nah, nal, nbh, nbl);
-        } else if (more) {
+            read_ops(q & 1, 0, nah, nal, nbh, nbl);  // (past the range: stale, unused)
+        } else {
             read_ops((j >> 1) & 1, 1, nah, nal, nbh, nbl);
         }
+        __builtin_amdgcn_sched_barrier(0);  // the reads go out before the MFMAs
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -253,17 +257,15 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                         acc_mid[i][jj][e] = 0;
                     }
         }
-        if (more) {
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                if (!ONE) ah[t] = nah[t];
-                al[t] = nal[t];
-            }
+        for (int t = 0; t < 4; t++) {
+            if (!ONE) ah[t] = nah[t];
+            al[t] = nal[t];
+        }
 #pragma unroll
-            for (int t = 0; t < 2; t++) {
-                if (!ONE) bh[t] = nbh[t];
-                bl[t] = nbl[t];
-            }
+        for (int t = 0; t < 2; t++) {
+            if (!ONE) bh[t] = nbh[t];
+            bl[t] = nbl[t];
         }
     }
     // drain the DMA path before the ring is reused for the output tile
