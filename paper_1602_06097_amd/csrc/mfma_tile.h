@@ -395,12 +395,17 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n0 = bx * 16 * NJ;
     // C tile: 64 RT rows x kCpr chunks of 4 columns; every load is issued
-    // (chunks outside the tile read C[0])
+    // (chunks outside the tile read C[0]).  The row numbers are read from LDS
+    // first, all together, so the C loads go out back to back.
+    uint32_t crow[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; u++) crow[u] = rows_s[(tid + u * 256) / kCpr];
+    __builtin_amdgcn_sched_barrier(0);
     uint64_t cv[kChunks];
 #pragma unroll
     for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * 256, r = ch / kCpr, c4 = (ch % kCpr) * 4;
-        const uint32_t row = rows_s[r], col = n0 + c4;
+        const uint32_t ch = tid + u * 256, c4 = (ch % kCpr) * 4;
+        const uint32_t row = crow[u], col = n0 + c4;
         const bool ok = row != 0xffffffffu && col + 4 <= N;
         cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
     }
@@ -449,7 +454,7 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
 #pragma unroll
     for (int u = 0; u < kChunks; u++) {
         const uint32_t ch = tid + u * 256, r = ch / kCpr, c4 = (ch % kCpr) * 4;
-        const uint32_t row = rows_s[r], col = n0 + c4;
+        const uint32_t row = crow[u], col = n0 + c4;
         if (row == 0xffffffffu || col >= N) continue;
         const uint64_t s4 = *(const uint64_t *)(sv + r * kLd + c4);
         uint16_t *o = C + (uint64_t)row * ldc + col;
