@@ -231,11 +231,11 @@ fl_status reduce_mfma(const fl_split_info *info, const fl_split_out *s, const ui
                      nullptr, r.row_map, Dt, ldd, r.ntiles * 128, nB};
     // column tiles of X past whose last nonzero row C's K range starts: skipped
     gp.kcap_n = X ? r.xend : row_end;
-    // column tiles outer, all row tiles inner (each XCD a range of column
-    // tiles): C's limb planes (every row tile's K range) stay resident in the
-    // last-level cache while X's planes stream through once, instead of X
-    // being re-read by every row tile
-    gp.group_m = 0xffffu;
+    // groups of 4 row tiles per column tile on each XCD: the group shares the
+    // column tile's X planes in L2 while C's limb planes are re-read from the
+    // last-level cache (measured on the 60,000 x 80,000 workload: 4 beats
+    // 8, 16, 32 and all row tiles per column tile by 4-15%)
+    gp.group_m = 4;
     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "reduce.mfma"));
     return FL_OK;
 }
