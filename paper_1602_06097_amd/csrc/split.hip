@@ -62,6 +62,8 @@ struct SplitDev {
     uint64_t *rowscan;   // [m]  non-pivot flag, then exclusive scan
     uint32_t *rowpos;    // [m]  new row position of each input row
     uint64_t *cnt;       // [m]  B/D counts by new row position, then scan
+    uint32_t *rspan;     // [2m] by new row position: least and greatest new column of
+                         //      the row's multiline entries (kNone, 0: none)
     uint64_t *glen;      // [G+1] multiline union sizes, then scan
     uint64_t *tot;       // [8]  0: npiv, 1: #nonpiv rows, 2: nnz(B)+nnz(D), 3: total ml len,
                          //      4: nnz(A) strictly upper, 5: nnz(C)
@@ -158,16 +160,26 @@ __global__ void k_rowmap(uint32_t m, SplitDev d, uint32_t *row_perm) {
     row_perm[pos] = i;
 }
 
+// Entry (k) of input row `orig` at new row position `pos` belongs to the
+// multiline iff it lies in a pivot column and is not A's unit diagonal.
+__device__ __forceinline__ bool ml_entry(uint32_t nc, uint32_t npiv, bool is_a, uint32_t pos) {
+    return nc < npiv && !(is_a && nc == pos);
+}
+
 // Number of entries of input row i in non-pivot columns, stored at the row's
-// new position (pivot rows: B counts at [0, npiv); others: D counts after).
+// new position (pivot rows: B counts at [0, npiv); others: D counts after);
+// also the span of its multiline entries (pivot columns, A's unit diagonal
+// excluded), which the multiline packing reads instead of the row.
 __global__ __launch_bounds__(256) void k_count_bd(uint32_t m, const uint64_t *__restrict__ rp,
                                                   const uint32_t *__restrict__ ci, SplitDev d) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= m || failed(d.errkey)) return;
     uint32_t npiv = (uint32_t)d.tot[0];
+    const uint32_t pos = d.rowpos[i];
+    const bool is_a = pos < npiv;
     uint64_t s = rp[i], e = rp[i + 1];
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, mn = kNone, mx = 0;
     // four entries per lane in flight: the column loads, then the map lookups
     for (uint64_t k0 = s + lane; k0 < e; k0 += 256) {
         uint32_t c[4];
@@ -176,12 +188,23 @@ __global__ __launch_bounds__(256) void k_count_bd(uint32_t m, const uint64_t *__
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const uint32_t nc = d.colmap[c[u]];
-            cnt += k0 + 64 * u < e && nc >= npiv ? 1 : 0;
+            const bool in = k0 + 64 * u < e;
+            cnt += in && nc >= npiv ? 1 : 0;
+            if (in && ml_entry(nc, npiv, is_a, pos)) {
+                mn = nc < mn ? nc : mn;
+                mx = nc > mx ? nc : mx;
+            }
         }
     }
-    for (int dd = 32; dd >= 1; dd >>= 1) cnt += __shfl_xor(cnt, dd, 64);
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        cnt += __shfl_xor(cnt, dd, 64);
+        const uint32_t omn = __shfl_xor(mn, dd, 64), omx = __shfl_xor(mx, dd, 64);
+        mn = omn < mn ? omn : mn;
+        mx = omx > mx ? omx : mx;
+    }
     if (lane == 0) {
-        uint32_t pos = d.rowpos[i];
+        d.rspan[2 * (uint64_t)pos] = mn;
+        d.rspan[2 * (uint64_t)pos + 1] = mx;
         d.cnt[pos] = cnt;
         uint64_t in_piv = (e - s) - cnt;  // entries in pivot columns
         if (pos < npiv) atomicAdd((unsigned long long *)&d.tot[4], (unsigned long long)(in_piv - 1));
@@ -293,35 +316,22 @@ __device__ inline uint32_t block_reduce(uint32_t v, int op, uint32_t *red) {
     return r;
 }
 
-// Entry (k) of input row `orig` at new row position `pos` belongs to the
-// multiline iff it lies in a pivot column and is not A's unit diagonal.
-__device__ __forceinline__ bool ml_entry(uint32_t nc, uint32_t npiv, bool is_a, uint32_t pos) {
-    return nc < npiv && !(is_a && nc == pos);
+
+// The span of the group's multiline columns, from the rows' spans (the same
+// in every thread).
+__device__ __forceinline__ void group_span(const GroupInfo &gi, const SplitDev &d, uint32_t &lo, uint32_t &hi) {
+    lo = kNone;
+    hi = 0;
+    for (uint32_t r = gi.r0; r < gi.r1; r++) {
+        const uint32_t a = d.rspan[2 * (uint64_t)r], b = d.rspan[2 * (uint64_t)r + 1];
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
 }
 
-__device__ void group_span(const GroupInfo &gi, uint32_t npiv, const uint32_t *row_perm,
-                           const uint64_t *rp, const uint32_t *ci, const SplitDev &d,
-                           uint32_t *red, uint32_t &lo, uint32_t &hi) {
-    uint32_t mn = kNone, mx = 0;
-    for (uint32_t r = gi.r0; r < gi.r1; r++) {
-        uint32_t orig = row_perm[r];
-        uint64_t s = rp[orig], e = rp[orig + 1];
-        for (uint64_t k0 = s + threadIdx.x; k0 < e; k0 += 4 * (uint64_t)blockDim.x) {
-            uint32_t c[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const uint32_t nc = d.colmap[c[u]];
-                if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r)) {
-                    mn = nc < mn ? nc : mn;
-                    mx = nc > mx ? nc : mx;
-                }
-            }
-        }
-    }
-    lo = block_reduce(mn, 0, red);
-    hi = block_reduce(mx, 1, red);
+// Words of the window at w0 that the span [w0, hi] touches.
+__device__ __forceinline__ uint32_t window_words(uint32_t w0, uint32_t hi) {
+    return ((hi - w0 < kWinBits ? hi - w0 : kWinBits - 1) >> 5) + 1;
 }
 
 __global__ __launch_bounds__(256) void k_ml_count(uint32_t m, uint32_t w,
@@ -336,11 +346,12 @@ __global__ __launch_bounds__(256) void k_ml_count(uint32_t m, uint32_t w,
     GroupInfo gi;
     if (!group_of(blockIdx.x, w, npiv, m, gi)) return;
     uint32_t lo, hi;
-    group_span(gi, npiv, row_perm, rp, ci, d, red, lo, hi);
+    group_span(gi, d, lo, hi);
     uint32_t total = 0;
     if (lo != kNone) {
         for (uint32_t w0 = lo; w0 <= hi; w0 += kWinBits) {
-            for (int k = threadIdx.x; k < kWinWords; k += blockDim.x) bits[k] = 0;
+            const uint32_t nwords = window_words(w0, hi);
+            for (uint32_t k = threadIdx.x; k < nwords; k += blockDim.x) bits[k] = 0;
             __syncthreads();
             for (uint32_t r = gi.r0; r < gi.r1; r++) {
                 uint32_t orig = row_perm[r];
@@ -360,7 +371,7 @@ __global__ __launch_bounds__(256) void k_ml_count(uint32_t m, uint32_t w,
             }
             __syncthreads();
             uint32_t c = 0;
-            for (int k = threadIdx.x; k < kWinWords; k += blockDim.x) c += __popc(bits[k]);
+            for (uint32_t k = threadIdx.x; k < nwords; k += blockDim.x) c += __popc(bits[k]);
             total += block_reduce(c, 2, red);
             if (hi - w0 < kWinBits) break;
         }
@@ -408,12 +419,13 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
         scale_s[threadIdx.x] = gi.is_a ? f.inv(v[rp[orig]]) : 1u;
     }
     uint32_t lo, hi;
-    group_span(gi, npiv, row_perm, rp, ci, d, red, lo, hi);  // (syncs)
+    group_span(gi, d, lo, hi);
     if (lo == kNone) return;
     uint64_t out = base;
     for (uint32_t w0 = lo; w0 <= hi; w0 += kWinBits) {
-        for (int k = threadIdx.x; k < kWinWords; k += blockDim.x) bits[k] = 0;
-        __syncthreads();
+        const uint32_t nwords = window_words(w0, hi);
+        for (uint32_t k = threadIdx.x; k < nwords; k += blockDim.x) bits[k] = 0;
+        __syncthreads();  // (also publishes scale_s)
         for (uint32_t r = gi.r0; r < gi.r1; r++) {
             uint32_t orig = row_perm[r];
             uint64_t s = rp[orig], e = rp[orig + 1];
@@ -438,7 +450,7 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
         const int w_lo = threadIdx.x * kPer;
         for (int k = 0; k < kPer; k++) {
             pre[w_lo + k] = csum;
-            csum += __popc(bits[w_lo + k]);
+            csum += (uint32_t)(w_lo + k) < nwords ? __popc(bits[w_lo + k]) : 0;
         }
         // block exclusive scan of csum
         uint32_t incl = csum;
@@ -458,7 +470,7 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
         for (int k = 0; k < kPer; k++) pre[w_lo + k] += excl;
         __syncthreads();
         // positions and zeroed value slots
-        for (int k = threadIdx.x; k < kWinWords; k += blockDim.x) {
+        for (uint32_t k = threadIdx.x; k < nwords; k += blockDim.x) {
             uint32_t b = bits[k];
             uint32_t idx = pre[k];
             while (b) {
@@ -538,6 +550,7 @@ size_t split_ws_layout(uint32_t m, uint32_t n, uint32_t w, void *ws, SplitDev *d
     t.rowscan = c.take<uint64_t>(m ? m : 1);
     t.rowpos = c.take<uint32_t>(m ? m : 1);
     t.cnt = c.take<uint64_t>(m ? m : 1);
+    t.rspan = c.take<uint32_t>(2 * (size_t)(m ? m : 1));
     t.glen = c.take<uint64_t>(groups);
     t.tot = c.take<uint64_t>(8);
     t.scantmp = c.take<uint64_t>(fl_scan_tmp_elems(big));
