@@ -248,9 +248,22 @@ __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
         out++;
     }
     const uint32_t nq = nB / 4;
+    // software pipeline over chunks of 64 x 4 entries: the row chunk two
+    // ahead and the original columns of the next chunk's nonzeros are in
+    // flight while a chunk is compacted and stored
+    uint64_t v1 = lane < nq ? row8[lane] : 0;
+    uint64_t v2 = 64 + lane < nq ? row8[64 + lane] : 0;
+    uint32_t pc[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) pc[e] = (v1 >> (16 * e)) & 0xffffu ? perm[4 * lane + e] : 0;
     for (uint32_t q0 = 0; q0 < nq; q0 += 64) {
         const uint32_t q = q0 + lane;
-        const uint64_t v = q < nq ? row8[q] : 0;
+        const uint64_t v = v1;
+        const uint32_t c4[4] = {pc[0], pc[1], pc[2], pc[3]};
+        v1 = v2;  // (zero past the row: no column is fetched for it)
+#pragma unroll
+        for (int e = 0; e < 4; e++) pc[e] = (v1 >> (16 * e)) & 0xffffu ? perm[4 * (q + 64) + e] : 0;
+        v2 = q + 128 < nq ? row8[q + 128] : 0;
         const uint32_t n = nz4(v);
         uint32_t incl = n;
 #pragma unroll
@@ -263,7 +276,7 @@ __global__ __launch_bounds__(256) void k_csr_emit(uint32_t npiv, uint32_t nB,
         for (int e = 0; e < 4; e++) {
             const uint32_t x = (uint32_t)(v >> (16 * e)) & 0xffffu;
             if (x) {
-                sc[at] = perm[4 * q + e];
+                sc[at] = c4[e];
                 sv[at] = (uint16_t)x;
                 at++;
             }
