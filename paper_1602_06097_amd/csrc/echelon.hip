@@ -21,7 +21,9 @@
 //     and G = Dt[Q, C]^{-1} (rows ordered by pivot column).
 //  4. U = G * Dt[Q, c0:bend)     over the rest of the panel's 256-column block
 //  5. L' = Dt[:, C] - [row = Q_t] (multipliers with the placement of U folded
-//                                  in; 4 and 5 are one launch)
+//                                  in; 4 and 5 are computed from the probe
+//                                  basis in step 2's launch, and again after a
+//                                  merge, only for the matrices it changed)
 //  6. Dt[:, c0:bend) -= L' U      (every row with a nonzero multiplier:
 //     (VALU or int8 MFMA)          Gauss-Jordan clears C above and below, and
 //                                  pivot row Q_t becomes U_t)
@@ -586,6 +588,8 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
     if (n == 0) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
+    // U and L' are computed again (k_ech_UL redo): its row list restarts
+    if (threadIdx.x == 0) t.counts[3 * P + 2] = 0;
     {  // the raw basis: 2 x 512 16-byte chunks, one of each per thread
         static_assert(kGreedyThreads == 512 * 2, "one chunk of Bv and Bg per thread");
         const uint32_t i = threadIdx.x & 511;
@@ -774,23 +778,59 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
 // Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
 // over the rest of the panel's block (four workgroups of 64 columns per
 // matrix), the others gather L' (rows).
+// One workgroup of steps 4 + 5: the first grid_u workgroups of a launch
+// compute U, the next (pre_rows) L'.  redo: only for matrices whose check
+// flagged rows (the merge changed the basis after the first U and L').
+__device__ __forceinline__ void UL_tile(const fl::Mod &md, const FlEchTask *__restrict__ tasks,
+                                        const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
+                                        uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
+                                        uint32_t n_active, uint32_t P, uint32_t bid, bool redo, ULds &S) {
+    if (bid < grid_u) {
+        const uint32_t ti = fl_task_of(pre_c, n_c, bid / kBlockPanels);
+        const FlEchTask &t = tasks[ids[ti]];
+        if (P >= t.npanels || (redo && t.counts[3 * P + 1] == 0)) return;
+        const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
+        U_tile(md, t, bid % kBlockPanels, P, S, 0, bend - c0);
+    } else {
+        const uint32_t b = bid - grid_u;
+        const uint32_t ti = fl_task_of(pre_rows, n_active, b);
+        const FlEchTask &t = tasks[ids[ti]];
+        if (P >= t.npanels || (redo && t.counts[3 * P + 1] == 0)) return;
+        L_tile(md.p, t, b - pre_rows[ti], P, S.qs, S.qs + 64);
+    }
+}
+
+// Steps 4 + 5 again after a merge (matrices without flagged rows exit).
 __global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                 const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
                                                 uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
                                                 uint32_t n_active, uint32_t P) {
     __shared__ ULds S;
-    if (blockIdx.x < grid_u) {
-        const uint32_t ti = fl_task_of(pre_c, n_c, blockIdx.x / kBlockPanels);
-        const FlEchTask &t = tasks[ids[ti]];
-        if (P >= t.npanels) return;
-        const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
-        U_tile(md, t, blockIdx.x % kBlockPanels, P, S, 0, bend - c0);
+    UL_tile(md, tasks, ids, pre_c, n_c, grid_u, pre_rows, n_active, P, blockIdx.x, true, S);
+}
+
+// Step 2 (the check against the probe basis: workgroups from grid_ul on) and
+// steps 4 + 5 with the probe basis (before them) in one launch.  Almost
+// always no row is flagged and the probe basis is final; otherwise the merge
+// and k_ech_UL redo U and L' for the matrices concerned.
+__global__ __launch_bounds__(256) void k_ech_check_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                      const uint32_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ pre_c, uint32_t n_c,
+                                                      uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
+                                                      uint32_t n_active, uint32_t grid_rows, uint32_t P) {
+    __shared__ union {
+        ULds u;
+        CheckLds c;
+    } S;
+    const uint32_t grid_ul = grid_u + grid_rows;
+    if (blockIdx.x < grid_ul) {
+        UL_tile(md, tasks, ids, pre_c, n_c, grid_u, pre_rows, n_active, P, blockIdx.x, false, S.u);
     } else {
-        const uint32_t b = blockIdx.x - grid_u;
+        const uint32_t b = blockIdx.x - grid_ul;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
         const FlEchTask &t = tasks[ids[ti]];
         if (P >= t.npanels) return;
-        L_tile(md.p, t, b - pre_rows[ti], P, S.qs, S.qs + 64);
+        check_tile(md, t, b - pre_rows[ti], P, 1, S.c);
     }
 }
 
@@ -1377,15 +1417,17 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             hipLaunchKernelGGL(k_ech_probe, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    FL_PROF("echelon.check", stream,
-            hipLaunchKernelGGL(k_ech_check, dim3(g.grid_rows), dim3(256), 0, stream, md, tasks, L.ids_all,
-                               L.pre_rows, g.n_active, P, 1));
+    // the check, with U over the rest of the block and L' from the probe
+    // basis; when a row was flagged: the merge, then U and L' again
+    FL_PROF("echelon.check_UL", stream,
+            hipLaunchKernelGGL(k_ech_check_UL, dim3(kBlockPanels * g.n_active + 2 * g.grid_rows), dim3(256), 0,
+                               stream, md, tasks, L.ids_all, at(L.pre_n_all, P, L.n_all), L.n_all,
+                               kBlockPanels * g.n_active, L.pre_rows, g.n_active, g.grid_rows, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FL_PROF("echelon.merge", stream,
             hipLaunchKernelGGL(k_ech_merge, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
                                P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // U over the rest of the block and L'; the panel's update of its block
     FL_PROF("echelon.UL", stream,
             hipLaunchKernelGGL(k_ech_UL, dim3(kBlockPanels * g.n_active + g.grid_rows), dim3(256), 0, stream, md,
                                tasks, L.ids_all, at(L.pre_n_all, P, L.n_all), L.n_all, kBlockPanels * g.n_active,
