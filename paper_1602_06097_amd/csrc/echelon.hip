@@ -108,6 +108,26 @@ __device__ __forceinline__ PanelState *panel_state(const FlEchTask &t, uint32_t 
     return (PanelState *)t.ps + (P % kSlots);
 }
 
+// The K dimension of a block's delayed update holds its panels' pivots
+// packed: panel j of the block takes slots [kbase_j, kbase_j + k_j), kbase_j
+// the sum of round_up(k_i, 16) over the block's earlier panels (16-slot
+// granularity keeps the limb planes' 16-byte fragments aligned); the slots
+// up to the next multiple of 16 are padding (zero in U).  With about 22
+// pivots per panel the block needs K = 128 instead of 4 x 64.
+__device__ __forceinline__ uint32_t round16(uint32_t k) { return (k + 15) & ~15u; }
+__device__ __forceinline__ uint32_t panel_kbase(const FlEchTask &t, uint32_t P) {
+    uint32_t base = 0;
+    for (uint32_t P1 = P / kBlockPanels * kBlockPanels; P1 < P; P1++) base += round16(panel_state(t, P1)->k);
+    return base;
+}
+// K of block B's update: the packed slots of all of its panels.
+__device__ __forceinline__ uint32_t block_k(const FlEchTask &t, uint32_t B) {
+    const uint32_t P0 = B * kBlockPanels, P1 = P0 + kBlockPanels < t.npanels ? P0 + kBlockPanels : t.npanels;
+    uint32_t k = 0;
+    for (uint32_t P = P0; P < P1; P++) k += round16(panel_state(t, P)->k);
+    return k;
+}
+
 // Reduce the wave's vector (v: panel part, g: coefficient part, lane = column
 // or slot) against basis rows [t0, t1).  The basis is in reduced form, so all
 // multipliers can be read from the vector as it is on entry.  The pivot
@@ -716,7 +736,9 @@ __device__ void U_tile(const fl::Mod &md, const FlEchTask &tk, uint32_t bx, uint
 // L'[i][t] = Dt[i][Ccol[t]] - [i = Phys[t]] (0 for t >= k): the multipliers
 // of panel P with the placement of U folded in (a pivot row t first loses
 // its whole panel combination, Dt[Q_t] - Dt[Q_t, C] U = 0, then gains U_t),
-// stored in slot P mod 4 of the block buffer Lb (256 per row) and, with limb
+// stored at the panel's packed slots of the block buffer Lb (256 per row;
+// slots kbase .. kbase + 63 are written, the next panel's overwrite the
+// tail) and, with limb
 // planes, as int8 limbs.  MFMA form: the rows with a nonzero multiplier are
 // listed for the panel's update, and the first time in the block also for
 // the block's update.  One workgroup (32 rows): one wave per 8 rows, lane t =
@@ -727,7 +749,7 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
     const uint32_t rows = tk.rows;
     const uint16_t *D = tk.D;
     const uint64_t ld = tk.ld;
-    const uint32_t b = P / kBlockPanels, slot = (P % kBlockPanels) * kPanel;
+    const uint32_t b = P / kBlockPanels, slot = panel_kbase(tk, P);
     const uint64_t half = (uint64_t)(b & 1) * rows * kBlock;
     uint16_t *Lb = tk.Lb + half;
     int8_t *Lh = tk.Lbh ? tk.Lbh + half : nullptr, *Ll = tk.Lbl ? tk.Lbl + half : nullptr;
@@ -856,7 +878,7 @@ __global__ __launch_bounds__(256) void k_ech_update_mfma(fl::Mod md, uint32_t bi
     const uint32_t c0 = P * kPanel, b = P / kBlockPanels, bend = (b + 1) * kBlock;
     const uint32_t N = (bend < t.cols ? bend : t.cols) - c0;
     if (bx * 64 >= N) return;
-    const uint64_t half = (uint64_t)(b & 1) * t.rows * kBlock, slot = (P % kBlockPanels) * kPanel;
+    const uint64_t half = (uint64_t)(b & 1) * t.rows * kBlock, slot = panel_kbase(t, P);
     fl_mfma::mfma_rankk_tile<1, 4>(md, bias, c16, t.Lbh + half + slot, t.Lbl + half + slot, kBlock, t.Uh, t.Ul,
                                    64, t.upd_rows, M, t.D + c0, t.ld, N, bx, blockIdx.y, sv, rows_s);
 }
@@ -873,7 +895,7 @@ __global__ __launch_bounds__(256) void k_ech_update_valu(fl::Mod md, const FlEch
     const PanelState *ps = panel_state(t, P);
     const uint32_t c0 = P * kPanel, b = P / kBlockPanels, bend = (b + 1) * kBlock;
     const uint32_t N = (bend < t.cols ? bend : t.cols) - c0;
-    const uint16_t *A = t.Lb + (uint64_t)(b & 1) * t.rows * kBlock + (P % kBlockPanels) * kPanel;
+    const uint16_t *A = t.Lb + (uint64_t)(b & 1) * t.rows * kBlock + panel_kbase(t, P);
     for (uint32_t by = blockIdx.y; by * 32 < t.rows; by += gridDim.y)
         fl_valu::valu_gemm_tile(md, t.rows, N, 0, &ps->k, A, kBlock, t.U + c0, t.ldu, t.D + c0, t.ld, 0, by);
 }
@@ -919,9 +941,12 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
     }
     __syncthreads();
     const uint32_t nj = t.npanels - P0 < kBlockPanels ? t.npanels - P0 : kBlockPanels;
-    uint32_t kj[kBlockPanels];
+    uint32_t kj[kBlockPanels], kb[kBlockPanels];  // pivots and packed K base of each panel
 #pragma unroll
     for (uint32_t j = 0; j < kBlockPanels; j++) kj[j] = j < nj ? panel_state(t, P0 + j)->k : 0;
+    kb[0] = 0;
+#pragma unroll
+    for (uint32_t j = 1; j < kBlockPanels; j++) kb[j] = kb[j - 1] + ((kj[j - 1] + 15) & ~15u);
     if constexpr (NW == 16) {
         // Every load of the four stages depends only on the panel states, so
         // all are issued up front, in two rounds: the panels' selected rows
@@ -953,7 +978,7 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
                 xq[j][i] = t.D[(uint64_t)q * t.ld + cc];
 #pragma unroll
                 for (uint32_t jj = 0; jj < j; jj++)
-                    cf[j * (j - 1) / 2 * kE + i * j + jj] = Lb[(uint64_t)q * kBlock + jj * kPanel + lane];
+                    cf[j * (j - 1) / 2 * kE + i * j + jj] = Lb[(uint64_t)q * kBlock + kb[jj] + lane];
             }
 #pragma unroll
         for (uint32_t j = 0; j < kBlockPanels; j++) {
@@ -1007,7 +1032,7 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
         uint32_t x_n = t.D[(uint64_t)q * t.ld + cc], cf_n[kBlockPanels - 1];
 #pragma unroll
         for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
-            cf_n[jj] = jj < j ? Lb[(uint64_t)q * kBlock + jj * kPanel + lane] : 0;
+            cf_n[jj] = jj < j ? Lb[(uint64_t)q * kBlock + kb[jj] + lane] : 0;
         for (; s < k; s += NW) {
             const uint32_t x = x_n;
             uint32_t cf[kBlockPanels - 1];
@@ -1018,7 +1043,7 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
                 x_n = t.D[(uint64_t)qn * t.ld + cc];
 #pragma unroll
                 for (uint32_t jj = 0; jj < kBlockPanels - 1; jj++)
-                    if (jj < j) cf_n[jj] = Lb[(uint64_t)qn * kBlock + jj * kPanel + lane];
+                    if (jj < j) cf_n[jj] = Lb[(uint64_t)qn * kBlock + kb[jj] + lane];
             }
             uint32_t h = 0, l = 0;
 #pragma unroll
@@ -1052,6 +1077,15 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
     }
     }
     if (!ok || wave >= 4) return;
+    // packed K position x -> the row of S.Us holding it (kBlock: padding,
+    // zero): panel j's pivot x - kb[j] when kb[j] <= x < kb[j] + kj[j]
+    auto urow = [&](uint32_t x) {
+        uint32_t r = kBlock;
+#pragma unroll
+        for (uint32_t j = 0; j < kBlockPanels; j++)
+            if (x >= kb[j] && x < kb[j] + kj[j]) r = j * kPanel + (x - kb[j]);
+        return r;
+    };
     if (t.Ubh) {
         // wave w: bytes [64 w, 64 w + 64) of the column's 256-byte rows
         const uint64_t off = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)c * kBlock + wave * 64;
@@ -1062,7 +1096,8 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 int lh, ll;
-                fl_split_limbs(S.Us[wave * 64 + 4 * i + e][lane], md.p, lh, ll);
+                const uint32_t r = urow(wave * 64 + 4 * i + e);
+                fl_split_limbs(r < kBlock ? S.Us[r][lane] : 0u, md.p, lh, ll);
                 hw[i] |= (uint32_t)(lh & 0xff) << (8 * e);
                 lw[i] |= (uint32_t)(ll & 0xff) << (8 * e);
             }
@@ -1075,7 +1110,10 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
         }
     } else {
         uint16_t *Ub = t.Ub + (uint64_t)(B & 1) * kBlock * t.ldu;
-        for (uint32_t r = wave; r < kBlock; r += 4) Ub[(uint64_t)r * t.ldu + c] = S.Us[r][lane];
+        for (uint32_t x = wave; x < kBlock; x += 4) {
+            const uint32_t r = urow(x);
+            Ub[(uint64_t)x * t.ldu + c] = r < kBlock ? S.Us[r][lane] : 0;
+        }
     }
 }
 
@@ -1084,7 +1122,10 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 // 16 NJ columns.  A workgroup owns one row block (blockIdx.x) and walks the
 // column tiles blockIdx.y, blockIdx.y + gridDim.y, ... (`gcols` in all, from
 // the prefix), keeping the row block's multiplier fragments in registers.
-template <int RT, int NJ>
+// KS: K steps of 64 (the block's packed K rounded up); a matrix whose block
+// needs more than KS steps, or at most KS_MIN (the launch for fewer steps
+// covers it), is skipped.
+template <int RT, int NJ, int KS = kBlockPanels, int KS_MIN = 0>
 __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
                                                              const FlEchTask *__restrict__ tasks,
                                                              const uint32_t *__restrict__ ids,
@@ -1093,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
     constexpr uint32_t kRows = 64 * RT;  // rows of a workgroup's block
     __shared__ __attribute__((aligned(16))) uint16_t sv[kRows * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[kRows];
-    fl_mfma::RankkRows<kBlockPanels, RT> R;
+    fl_mfma::RankkRows<KS, RT> R;
     uint32_t cur = 0xffffffffu;  // task whose row block is loaded
     for (uint32_t cy = blockIdx.y; cy < gcols; cy += gridDim.y) {
         const uint32_t ti = fl_task_of(pre, ntask, cy);
@@ -1101,17 +1142,21 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
         if (B * kBlockPanels >= t.npanels) continue;
         const uint32_t M = t.blk_cnt[B];
         if (blockIdx.x * kRows >= M) continue;
+        if (KS < kBlockPanels || KS_MIN > 0) {
+            const uint32_t steps = (block_k(t, B) + 63) / 64;
+            if (steps > KS || steps <= KS_MIN) continue;
+        }
         const uint32_t start = (B + 1) * kBlock + lo;
         const uint32_t end = span < t.cols - start ? start + span : t.cols;
         if (ti != cur) {
             const uint64_t lhalf = (uint64_t)(B & 1) * t.rows * kBlock;
             __syncthreads();  // rows_s of the previous task is still read
-            fl_mfma::rankk_rows<kBlockPanels, RT>(t.Lbh + lhalf, t.Lbl + lhalf, kBlock,
+            fl_mfma::rankk_rows<KS, RT>(t.Lbh + lhalf, t.Lbl + lhalf, kBlock,
                                                   t.blk_rows + (uint64_t)(B & 1) * t.rows, M, blockIdx.x, rows_s, R);
             cur = ti;
         }
         const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
-        fl_mfma::rankk_cols<kBlockPanels, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock,
+        fl_mfma::rankk_cols<KS, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock,
                                                   t.D + start, t.ld, end - start, cy - pre[ti], sv, rows_s);
         __syncthreads();  // sv is reused by the next tile
     }
@@ -1353,7 +1398,9 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, uint32_t far_groups, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8>)),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>),
+                          dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8, kBlockPanels, 2>)),
+                          dyn_m2 = far_dyn_lds((k_ech_update_blk_mfma<2, 8, 2>)),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
@@ -1374,10 +1421,17 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
     // tiles; the next block's update (256 columns, latency bound) takes 16
     // rows per wave and 64-column tiles, four times the workgroups
     if (g_mfma && far) {
+        // two launches: blocks whose packed K fits two steps, and the others
+        // (each matrix's block runs in exactly one of them)
+        const dim3 grid((mfma_rows + 127) / 128, std::min(g_mfma, far_groups));
         FL_PROF("echelon.blk_mfma_far", s,
-                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8>),
-                                   dim3((mfma_rows + 127) / 128, std::min(g_mfma, far_groups)), dim3(256), dyn_m, s,
-                                   md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
+                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8, 2>), grid, dim3(256), dyn_m2, s, md,
+                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
+                                   g_mfma, B, lo, span));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        FL_PROF("echelon.blk_mfma_far", s,
+                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8, kBlockPanels, 2>), grid, dim3(256), dyn_m, s, md,
+                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
                                    g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (g_mfma) {
