@@ -1135,6 +1135,8 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
     __shared__ __attribute__((aligned(16))) uint16_t sv[kRows * fl_mfma::kRank64Ld];
     __shared__ uint32_t rows_s[kRows];
     fl_mfma::RankkRows<KS, RT> R;
+    fl_mfma::RankkC<RT, NJ> T;   // (KS <= 2) the C tile of column tile pf, loaded ahead
+    uint32_t pf = 0xffffffffu;
     uint32_t cur = 0xffffffffu;  // task whose row block is loaded
     for (uint32_t cy = blockIdx.y; cy < gcols; cy += gridDim.y) {
         const uint32_t ti = fl_task_of(pre, ntask, cy);
@@ -1156,8 +1158,24 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
             cur = ti;
         }
         const uint64_t uoff = (uint64_t)(B & 1) * (t.cols + kBlock) * kBlock + (uint64_t)start * kBlock;
-        fl_mfma::rankk_cols<KS, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock,
-                                                  t.D + start, t.ld, end - start, cy - pre[ti], sv, rows_s);
+        if constexpr (KS <= 2) {
+            // the C tile of this workgroup's next column tile of the same
+            // matrix (same rows) is loaded while this one is computed
+            if (pf != cy) fl_mfma::rankk_cload<RT, NJ>(T, t.D + start, t.ld, end - start, cy - pre[ti], rows_s);
+            const uint32_t nx = cy + gridDim.y;
+            const bool more = nx < gcols && fl_task_of(pre, ntask, nx) == ti;
+            fl_mfma::RankkC<RT, NJ> Tn;
+            if (more) fl_mfma::rankk_cload<RT, NJ>(Tn, t.D + start, t.ld, end - start, nx - pre[ti], rows_s);
+            fl_mfma::rankk_cols_loaded<KS, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start,
+                                                   t.ld, end - start, cy - pre[ti], sv, T);
+            if (more) {
+                T = Tn;
+                pf = nx;
+            }
+        } else {
+            fl_mfma::rankk_cols<KS, RT, NJ>(md, bias, c16, R, t.Ubh + uoff, t.Ubl + uoff, kBlock, t.D + start, t.ld,
+                                            end - start, cy - pre[ti], sv, rows_s);
+        }
         __syncthreads();  // sv is reused by the next tile
     }
 }
@@ -1383,7 +1401,7 @@ constexpr uint32_t kFarLds = 64 * 1024;
 // ones: the main stream's kernels get a compute unit whenever a far
 // workgroup finishes, so short far workgroups keep the critical path moving
 // (and balance the far kernel's own tail).
-constexpr uint32_t kBlkColGroups = 128;
+constexpr uint32_t kBlkColGroups = 64;
 
 template <class K>
 uint32_t far_dyn_lds(K kernel) {

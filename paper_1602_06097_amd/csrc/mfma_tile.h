@@ -374,18 +374,48 @@ __device__ __forceinline__ void rankk_rows(const int8_t *__restrict__ Ah, const 
     }
 }
 
-// One column tile bx (16 NJ columns, NJ = 8 or 4) of the row block set up by
-// rankk_rows (sv: 64 RT rows of kRank64Ld residues).  Callers looping over column tiles must
+// The C tile of column tile bx of a rank-k row block (64 RT rows x 16 NJ
+// columns, kChunks 8-byte chunks per thread): its row numbers (from rows_s)
+// and its values, loaded ahead of the tile's products (possibly while the
+// previous tile is computed).
+template <int RT, int NJ> struct RankkC {
+    static constexpr int kChunks = NJ * RT;
+    uint32_t crow[kChunks];
+    uint64_t cv[kChunks];
+};
+
+template <int RT, int NJ>
+__device__ __forceinline__ void rankk_cload(RankkC<RT, NJ> &T, const uint16_t *C, uint64_t ldc, uint32_t N,
+                                            uint32_t bx, const uint32_t *rows_s) {
+    typedef __attribute__((address_space(1))) const uint64_t gu64;
+    constexpr int kCpr = 4 * NJ;
+    const uint32_t tid = threadIdx.x, n0 = bx * 16 * NJ;
+    // every load is issued (chunks outside the tile read C[0]); the row
+    // numbers are read from LDS first, all together, so the loads go out
+    // back to back
+#pragma unroll
+    for (int u = 0; u < T.kChunks; u++) T.crow[u] = rows_s[(tid + u * 256) / kCpr];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < T.kChunks; u++) {
+        const uint32_t ch = tid + u * 256, c4 = (ch % kCpr) * 4;
+        const uint32_t row = T.crow[u], col = n0 + c4;
+        const bool ok = row != 0xffffffffu && col + 4 <= N;
+        T.cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
+    }
+}
+
+// The products and the write-back of column tile bx (16 NJ columns, NJ = 8
+// or 4) of the row block set up by rankk_rows, its C tile loaded (sv: 64 RT
+// rows of kRank64Ld residues).  Callers looping over column tiles must
 // synchronise between tiles (sv is reused).  Each B fragment feeds the RT
 // row tiles of the wave.
-template <int KS, int RT = 1, int NJ = 8>
-__device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16,
-                                           const RankkRows<KS, RT> &R, const int8_t *__restrict__ Bh,
-                                           const int8_t *__restrict__ Bl, uint32_t ldb, uint16_t *C, uint64_t ldc,
-                                           uint32_t N, uint32_t bx, uint16_t *sv, const uint32_t *rows_s) {
-    // every operand lives in device memory: global (not flat) accesses, so
-    // that loads are counted apart from LDS traffic and can stay in flight
-    typedef __attribute__((address_space(1))) const uint64_t gu64;
+template <int KS, int RT, int NJ>
+__device__ __forceinline__ void rankk_cols_loaded(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                  const RankkRows<KS, RT> &R, const int8_t *__restrict__ Bh,
+                                                  const int8_t *__restrict__ Bl, uint32_t ldb, uint16_t *C,
+                                                  uint64_t ldc, uint32_t N, uint32_t bx, uint16_t *sv,
+                                                  const RankkC<RT, NJ> &T) {
     typedef __attribute__((address_space(1))) uint64_t gu64w;
     typedef __attribute__((address_space(1))) const v4i gv4i;
     constexpr int kLd = kRank64Ld;
@@ -394,21 +424,8 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     constexpr int kChunks = NJ * RT;    // C chunks per thread
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n0 = bx * 16 * NJ;
-    // C tile: 64 RT rows x kCpr chunks of 4 columns; every load is issued
-    // (chunks outside the tile read C[0]).  The row numbers are read from LDS
-    // first, all together, so the C loads go out back to back.
-    uint32_t crow[kChunks];
-#pragma unroll
-    for (int u = 0; u < kChunks; u++) crow[u] = rows_s[(tid + u * 256) / kCpr];
-    __builtin_amdgcn_sched_barrier(0);
-    uint64_t cv[kChunks];
-#pragma unroll
-    for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * 256, c4 = (ch % kCpr) * 4;
-        const uint32_t row = crow[u], col = n0 + c4;
-        const bool ok = row != 0xffffffffu && col + 4 <= N;
-        cv[u] = *(gu64 *)(ok ? C + (uint64_t)row * ldc + col : C);
-    }
+    const uint32_t *crow = T.crow;
+    const uint64_t *cv = T.cv;
     const uint32_t rq = (lane >> 4) * 4, cl = lane & 15, kq = (lane >> 4) * 16;
     // B fragments of column tile j + 1 are fetched while tile j is multiplied
     v4i bh[2][KS], bl[2][KS];
@@ -472,6 +489,18 @@ __device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uin
     }
 }
 
+
+// One column tile bx (16 NJ columns, NJ = 8 or 4) of the row block set up by
+// rankk_rows: C tile loaded, products, write-back.
+template <int KS, int RT = 1, int NJ = 8>
+__device__ __forceinline__ void rankk_cols(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                           const RankkRows<KS, RT> &R, const int8_t *__restrict__ Bh,
+                                           const int8_t *__restrict__ Bl, uint32_t ldb, uint16_t *C, uint64_t ldc,
+                                           uint32_t N, uint32_t bx, uint16_t *sv, const uint32_t *rows_s) {
+    RankkC<RT, NJ> T;
+    rankk_cload<RT, NJ>(T, C, ldc, N, bx, rows_s);
+    rankk_cols_loaded<KS, RT, NJ>(md, bias, c16, R, Bh, Bl, ldb, C, ldc, N, bx, sv, T);
+}
 
 template <int KS, int NJ = 8>
 __device__ __forceinline__ void mfma_rankk_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
