@@ -1122,18 +1122,17 @@ __global__ __launch_bounds__(NT) void k_ech_ublk(fl::Mod md, const FlEchTask *__
 // 16 NJ columns.  A workgroup owns one row block (blockIdx.x) and walks the
 // column tiles blockIdx.y, blockIdx.y + gridDim.y, ... (`gcols` in all, from
 // the prefix), keeping the row block's multiplier fragments in registers.
-// KS: K steps of 64 (the block's packed K rounded up); a matrix whose block
-// needs more than KS steps, or at most KS_MIN (the launch for fewer steps
-// covers it), is skipped.
-template <int RT, int NJ, int KS = kBlockPanels, int KS_MIN = 0>
-__global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
-                                                             const FlEchTask *__restrict__ tasks,
-                                                             const uint32_t *__restrict__ ids,
-                                                             const uint32_t *__restrict__ pre, uint32_t ntask,
-                                                             uint32_t gcols, uint32_t B, uint32_t lo, uint32_t span) {
+// One pass of the block update over the matrices whose block needs K
+// steps of 64 in (KS_MIN, KS] (the block's packed K rounded up); the others
+// are skipped (the kernel runs a pass for at most two steps, then one for
+// more, so that both kinds cost one launch and the registers of one pass).
+template <int RT, int NJ, int KS, int KS_MIN>
+__device__ __forceinline__ void blk_update_pass(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                                const FlEchTask *__restrict__ tasks,
+                                                const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre,
+                                                uint32_t ntask, uint32_t gcols, uint32_t B, uint32_t lo,
+                                                uint32_t span, uint16_t *sv, uint32_t *rows_s) {
     constexpr uint32_t kRows = 64 * RT;  // rows of a workgroup's block
-    __shared__ __attribute__((aligned(16))) uint16_t sv[kRows * fl_mfma::kRank64Ld];
-    __shared__ uint32_t rows_s[kRows];
     fl_mfma::RankkRows<KS, RT> R;
     fl_mfma::RankkC<RT, NJ> T;   // (KS <= 2) the C tile of column tile pf, loaded ahead
     uint32_t pf = 0xffffffffu;
@@ -1144,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
         if (B * kBlockPanels >= t.npanels) continue;
         const uint32_t M = t.blk_cnt[B];
         if (blockIdx.x * kRows >= M) continue;
-        if (KS < kBlockPanels || KS_MIN > 0) {
+        {
             const uint32_t steps = (block_k(t, B) + 63) / 64;
             if (steps > KS || steps <= KS_MIN) continue;
         }
@@ -1178,6 +1177,20 @@ __global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_
         }
         __syncthreads();  // sv is reused by the next tile
     }
+}
+
+template <int RT, int NJ>
+__global__ __launch_bounds__(256) void k_ech_update_blk_mfma(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                             const FlEchTask *__restrict__ tasks,
+                                                             const uint32_t *__restrict__ ids,
+                                                             const uint32_t *__restrict__ pre, uint32_t ntask,
+                                                             uint32_t gcols, uint32_t B, uint32_t lo, uint32_t span) {
+    __shared__ __attribute__((aligned(16))) uint16_t sv[64 * RT * fl_mfma::kRank64Ld];
+    __shared__ uint32_t rows_s[64 * RT];
+    blk_update_pass<RT, NJ, 2, 0>(md, bias, c16, tasks, ids, pre, ntask, gcols, B, lo, span, sv, rows_s);
+    __syncthreads();  // rows_s and sv are reused
+    blk_update_pass<RT, NJ, kBlockPanels, 2>(md, bias, c16, tasks, ids, pre, ntask, gcols, B, lo, span, sv,
+                                             rows_s);
 }
 
 // The same, VALU form: every row, 256-column tiles from the prefix, row
@@ -1416,9 +1429,7 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
                         uint32_t lo, uint32_t span, uint32_t g_all, uint32_t g_mfma, uint32_t g_plain,
                         uint32_t mfma_rows, const uint32_t *pa, const uint32_t *pm, const uint32_t *pp,
                         bool far, uint32_t far_groups, hipStream_t s) {
-    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>),
-                          dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8, kBlockPanels, 2>)),
-                          dyn_m2 = far_dyn_lds((k_ech_update_blk_mfma<2, 8, 2>)),
+    static const uint32_t dyn_u = far_dyn_lds(k_ech_ublk<512>), dyn_m = far_dyn_lds((k_ech_update_blk_mfma<2, 8>)),
                           dyn_v = far_dyn_lds(k_ech_update_blk_valu);
     hipError_t e;
     if (!g_all) return hipSuccess;
@@ -1439,17 +1450,10 @@ hipError_t block_update(const fl::Mod &md, uint32_t p, const FlEchTask *tasks, c
     // tiles; the next block's update (256 columns, latency bound) takes 16
     // rows per wave and 64-column tiles, four times the workgroups
     if (g_mfma && far) {
-        // two launches: blocks whose packed K fits two steps, and the others
-        // (each matrix's block runs in exactly one of them)
-        const dim3 grid((mfma_rows + 127) / 128, std::min(g_mfma, far_groups));
         FL_PROF("echelon.blk_mfma_far", s,
-                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8, 2>), grid, dim3(256), dyn_m2, s, md,
-                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
-                                   g_mfma, B, lo, span));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        FL_PROF("echelon.blk_mfma_far", s,
-                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8, kBlockPanels, 2>), grid, dim3(256), dyn_m, s, md,
-                                   fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
+                hipLaunchKernelGGL((k_ech_update_blk_mfma<2, 8>),
+                                   dim3((mfma_rows + 127) / 128, std::min(g_mfma, far_groups)), dim3(256), dyn_m, s,
+                                   md, fl_mfma::gemm_bias(p), fl_mfma::gemm_c16(p), tasks, L.ids_mfma, pm, L.n_mfma,
                                    g_mfma, B, lo, span));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (g_mfma) {
