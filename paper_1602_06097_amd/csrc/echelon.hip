@@ -597,25 +597,17 @@ __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *
 }
 
 // Panel step 3 (only when some row was flagged): continue the greedy basis
-// with the flagged rows and publish the final result.  One workgroup per
-// matrix.
-__global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                                              const uint32_t *__restrict__ ids, uint32_t P) {
-    __shared__ GreedyLds S;
-    const FlEchTask &t = tasks[ids[blockIdx.x]];
-    if (P >= t.npanels) return;
+// with the flagged rows and publish the final result.  Run by one whole
+// workgroup (any number of waves).
+__device__ void merge_panel(const fl::Mod &md, const FlEchTask &t, uint32_t P, GreedyLds &S) {
     const uint32_t n = t.counts[3 * P + 1];
-    if (n == 0) return;
     const uint32_t c0 = P * kPanel, pw = t.cols - c0 < kPanel ? t.cols - c0 : kPanel;
     PanelState *ps = panel_state(t, P);
-    // U and L' are computed again (k_ech_UL redo): its row list restarts
-    if (threadIdx.x == 0) t.counts[3 * P + 2] = 0;
-    {  // the raw basis: 2 x 512 16-byte chunks, one of each per thread
-        static_assert(kGreedyThreads == 512 * 2, "one chunk of Bv and Bg per thread");
-        const uint32_t i = threadIdx.x & 511;
-        const uint4 *src = (const uint4 *)(threadIdx.x < 512 ? ps->Bv : ps->Bg);
-        uint4 *dst = (uint4 *)(threadIdx.x < 512 ? &S.Bv[0][0] : &S.Bg[0][0]);
-        dst[i] = src[i];
+    // the raw basis: 2 x 512 16-byte chunks
+    for (uint32_t i = threadIdx.x; i < 1024; i += blockDim.x) {
+        const uint4 *src = (const uint4 *)(i < 512 ? ps->Bv : ps->Bg);
+        uint4 *dst = (uint4 *)(i < 512 ? &S.Bv[0][0] : &S.Bg[0][0]);
+        dst[i & 511] = src[i & 511];
     }
     if (threadIdx.x < 64) {
         S.Cc[threadIdx.x] = ps->Cc[threadIdx.x];
@@ -624,8 +616,8 @@ __global__ __launch_bounds__(kGreedyThreads) void k_ech_merge(fl::Mod md, const 
     if (threadIdx.x == 0) S.kb = ps->kb;
     __syncthreads();
     const uint32_t rank0 = ps->rank0;
-    for (uint32_t base = 0; base < n && S.kb < pw; base += kGreedyThreads) {
-        const uint32_t cnt = n - base < kGreedyThreads ? n - base : kGreedyThreads;
+    for (uint32_t base = 0; base < n && S.kb < pw; base += blockDim.x) {
+        const uint32_t cnt = n - base < blockDim.x ? n - base : blockDim.x;
         if (threadIdx.x < cnt) S.list[threadIdx.x] = t.flist[base + threadIdx.x];
         if (threadIdx.x == 0) S.cnt = cnt;
         __syncthreads();
@@ -800,41 +792,57 @@ __device__ void L_tile(uint32_t p, const FlEchTask &tk, uint32_t bx, uint32_t P,
 // Panel steps 4 and 5 in one launch: the first grid_u workgroups compute U
 // over the rest of the panel's block (four workgroups of 64 columns per
 // matrix), the others gather L' (rows).
-// One workgroup of steps 4 + 5: the first grid_u workgroups of a launch
-// compute U, the next (pre_rows) L'.  redo: only for matrices whose check
-// flagged rows (the merge changed the basis after the first U and L').
+// One workgroup of steps 4 + 5 from the probe basis: the first grid_u
+// workgroups of the launch compute U, the next (pre_rows) L'.
 __device__ __forceinline__ void UL_tile(const fl::Mod &md, const FlEchTask *__restrict__ tasks,
                                         const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
                                         uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
-                                        uint32_t n_active, uint32_t P, uint32_t bid, bool redo, ULds &S) {
+                                        uint32_t n_active, uint32_t P, uint32_t bid, ULds &S) {
     if (bid < grid_u) {
         const uint32_t ti = fl_task_of(pre_c, n_c, bid / kBlockPanels);
         const FlEchTask &t = tasks[ids[ti]];
-        if (P >= t.npanels || (redo && t.counts[3 * P + 1] == 0)) return;
+        if (P >= t.npanels) return;
         const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
         U_tile(md, t, bid % kBlockPanels, P, S, 0, bend - c0);
     } else {
         const uint32_t b = bid - grid_u;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
         const FlEchTask &t = tasks[ids[ti]];
-        if (P >= t.npanels || (redo && t.counts[3 * P + 1] == 0)) return;
+        if (P >= t.npanels) return;
         L_tile(md.p, t, b - pre_rows[ti], P, S.qs, S.qs + 64);
     }
 }
 
-// Steps 4 + 5 again after a merge (matrices without flagged rows exit).
-__global__ __launch_bounds__(256) void k_ech_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
-                                                const uint32_t *__restrict__ ids, const uint32_t *__restrict__ pre_c,
-                                                uint32_t n_c, uint32_t grid_u, const uint32_t *__restrict__ pre_rows,
-                                                uint32_t n_active, uint32_t P) {
-    __shared__ ULds S;
-    UL_tile(md, tasks, ids, pre_c, n_c, grid_u, pre_rows, n_active, P, blockIdx.x, true, S);
+// Step 3, only for the matrices whose check flagged rows (almost never): one
+// workgroup per matrix merges the flagged rows into the basis, then computes
+// U and L' again from the final basis, tile after tile (its row list
+// restarts), so that no further launch waits on the critical path.
+__global__ __launch_bounds__(256) void k_ech_merge(fl::Mod md, const FlEchTask *__restrict__ tasks,
+                                                   const uint32_t *__restrict__ ids, uint32_t P) {
+    __shared__ union {
+        GreedyLds g;
+        ULds u;
+    } S;
+    const FlEchTask &t = tasks[ids[blockIdx.x]];
+    if (P >= t.npanels || t.counts[3 * P + 1] == 0) return;
+    merge_panel(md, t, P, S.g);
+    if (threadIdx.x == 0) t.counts[3 * P + 2] = 0;
+    __syncthreads();  // (also: S.g is reused)
+    const uint32_t c0 = P * kPanel, bend = (P / kBlockPanels + 1) * kBlock;
+    for (uint32_t bx = 0; bx < kBlockPanels; bx++) {
+        U_tile(md, t, bx, P, S.u, 0, bend - c0);
+        __syncthreads();
+    }
+    for (uint32_t bx = 0; bx * 32 < t.rows; bx++) {
+        L_tile(md.p, t, bx, P, S.u.qs, S.u.qs + 64);
+        __syncthreads();
+    }
 }
 
 // Step 2 (the check against the probe basis: workgroups from grid_ul on) and
 // steps 4 + 5 with the probe basis (before them) in one launch.  Almost
 // always no row is flagged and the probe basis is final; otherwise the merge
-// and k_ech_UL redo U and L' for the matrices concerned.
+// kernel redoes U and L' for the matrices concerned.
 __global__ __launch_bounds__(256) void k_ech_check_UL(fl::Mod md, const FlEchTask *__restrict__ tasks,
                                                       const uint32_t *__restrict__ ids,
                                                       const uint32_t *__restrict__ pre_c, uint32_t n_c,
@@ -846,7 +854,7 @@ __global__ __launch_bounds__(256) void k_ech_check_UL(fl::Mod md, const FlEchTas
     } S;
     const uint32_t grid_ul = grid_u + grid_rows;
     if (blockIdx.x < grid_ul) {
-        UL_tile(md, tasks, ids, pre_c, n_c, grid_u, pre_rows, n_active, P, blockIdx.x, false, S.u);
+        UL_tile(md, tasks, ids, pre_c, n_c, grid_u, pre_rows, n_active, P, blockIdx.x, S.u);
     } else {
         const uint32_t b = blockIdx.x - grid_ul;
         const uint32_t ti = fl_task_of(pre_rows, n_active, b);
@@ -1501,13 +1509,7 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
                                kBlockPanels * g.n_active, L.pre_rows, g.n_active, g.grid_rows, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FL_PROF("echelon.merge", stream,
-            hipLaunchKernelGGL(k_ech_merge, dim3(g.n_active), dim3(kGreedyThreads), 0, stream, md, tasks, L.ids_all,
-                               P));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    FL_PROF("echelon.UL", stream,
-            hipLaunchKernelGGL(k_ech_UL, dim3(kBlockPanels * g.n_active + g.grid_rows), dim3(256), 0, stream, md,
-                               tasks, L.ids_all, at(L.pre_n_all, P, L.n_all), L.n_all, kBlockPanels * g.n_active,
-                               L.pre_rows, g.n_active, P));
+            hipLaunchKernelGGL(k_ech_merge, dim3(g.n_active), dim3(256), 0, stream, md, tasks, L.ids_all, P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g.n_mfma) {
         FL_PROF("echelon.mfma", stream,
