@@ -164,7 +164,7 @@ hipError_t fl_exclusive_scan_u64(const uint64_t *in, uint64_t *out, size_t n, ui
     return hipGetLastError();
 }
 
-uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu) {
+uint32_t fl_cu_count() {
     static int cus = [] {
         int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -172,7 +172,11 @@ uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu) {
             n = 256;
         return n;
     }();
-    const uint64_t cap = (uint64_t)per_cu * (uint64_t)cus;
+    return (uint32_t)cus;
+}
+
+uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu) {
+    const uint64_t cap = (uint64_t)per_cu * (uint64_t)fl_cu_count();
     return (uint32_t)(cap < total ? cap : total);
 }
 

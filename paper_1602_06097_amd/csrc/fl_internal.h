@@ -177,7 +177,12 @@ struct GemmPlanes {
     // B (absolute K index, before b_k0 is subtracted) that hold a nonzero in
     // that tile's columns; K blocks past it are skipped
     const uint32_t *kcap_n;
+    // workgroups of the launch: 0 = one per tile; kGemmPerCu = one per
+    // compute unit, each taking several tiles in turn; otherwise at most
+    // this many
+    uint32_t max_wg;
 };
+constexpr uint32_t kGemmPerCu = 0xffffffffu;
 hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &g, hipStream_t s, const char *site);
 // C[M x N] -= A[M x K] B[K x N] (mod p) on the vector ALUs (gemm_plain.hip),
 // K = *Kdev when Kdev is given; krange_n / kfirst: optional zero-skipping
@@ -275,6 +280,8 @@ __device__ __forceinline__ bool fl_queue_take(const FlQueue &q, uint32_t &task, 
 // Workgroups of a persistent launch: `per_cu` per compute unit, at most
 // `total`; counter NULL (one workgroup per task) when per_cu is 0.
 uint32_t fl_queue_grid(uint32_t total, uint32_t per_cu);
+// Compute units of the current device.
+uint32_t fl_cu_count();
 
 // Copies `bytes` from host memory into device memory through kernel
 // arguments (1 KiB per launch), so that the copy can be captured in a graph

@@ -92,18 +92,30 @@ __global__ __launch_bounds__(256) void k_limbs_cols(uint32_t p, const uint16_t *
     *(uint4 *)(Bl + (uint64_t)(c0 + cc) * Kp + k0 + seg) = lv;
 }
 
-// The tile of this workgroup under GemmPlanes::group_m.  Workgroups are
-// dispatched x fastest and dealt round-robin to the 8 XCDs; the linear
-// dispatch index is renumbered so that every XCD receives a contiguous
-// range, which is walked column tile by column tile in groups of gm row
-// tiles.  Both steps are bijections of the grid.
-__device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t &bx, uint32_t &by) {
-    const uint32_t nx = gridDim.x, ny = gridDim.y;
-    bx = blockIdx.x;
-    by = blockIdx.y;
-    if (gm == 0) return;
-    const uint32_t total = nx * ny, pid = by * nx + bx;
-    const uint32_t q = total / 8, r = total % 8, x = pid % 8, i = pid / 8;
+// Tile `pid` of an nx x ny tile grid under GemmPlanes::group_m, in a launch
+// of G workgroups (workgroup b takes the tiles pid = b + j G).  Tile
+// numbers are dealt round-robin to the 8 XCDs (pid % 8: the XCD of the
+// workgroup that takes it); they are renumbered so that every XCD receives a
+// contiguous range, which is walked column tile by column tile in groups of
+// gm row tiles.  Within an XCD, the W = G / 8 tiles of one round (j) are
+// rotated by j, so that a workgroup's tiles in successive rounds lie in
+// different rows of a group (row tiles can differ much in their K ranges).
+// Every step is a bijection.
+__device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t nx, uint32_t ny, uint32_t G, uint32_t pid,
+                                             uint32_t &bx, uint32_t &by) {
+    if (gm == 0) {
+        bx = pid % nx;
+        by = pid / nx;
+        return;
+    }
+    const uint32_t total = nx * ny;
+    const uint32_t q = total / 8, r = total % 8, x = pid % 8;
+    uint32_t i = pid / 8;
+    const uint32_t W = G / 8;
+    if (W > 1) {
+        const uint32_t c = i / W, qx = q + (x < r ? 1u : 0u);
+        if ((c + 1) * W <= qx) i = c * W + (i % W + c) % W;
+    }
     const uint32_t id = x * q + (x < r ? x : r) + i;
     const uint32_t per = gm * nx, group = id / per, first = group * gm;
     const uint32_t rows = ny - first < gm ? ny - first : gm;
@@ -112,22 +124,120 @@ __device__ __forceinline__ void gemm_tile_of(uint32_t gm, uint32_t &bx, uint32_t
     bx = within / rows;
 }
 
-// ONE: single-limb operands (p < 256).
-template <bool ONE>
-__global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
-                                                   GemmPlanes g) {
-    __shared__ __attribute__((aligned(16))) int8_t smem[kGemmLds];
-    uint32_t bx, by;
-    gemm_tile_of(g.group_m, bx, by);
-    mfma_gemm_tile<ONE>(md, bias, c16, g, bx, by, smem);
+// A tile of the grid and its K range.
+struct GemmTile {
+    uint32_t t, bx, by, kbeg, kend;
+};
+
+// The first tile t + i G (i >= 0) whose K range is not empty (t = nx ny if
+// none).  The tile t itself is probed alone (the usual case); past an empty
+// one the lanes of the wave probe 64 tiles at once.  The result is uniform.
+__device__ __forceinline__ GemmTile gemm_next_tile(const GemmPlanes &g, uint32_t nx, uint32_t ny, uint32_t t,
+                                                   uint32_t G, uint32_t lane) {
+    const uint32_t total = nx * ny;
+    GemmTile r = {total, 0, 0, 0, 0};
+    if (t >= total) return r;
+    gemm_tile_of(g.group_m, nx, ny, G, t, r.bx, r.by);
+    gemm_tile_krange(g, r.bx, r.by, r.kbeg, r.kend);
+    if (r.kbeg < r.kend) {
+        r.t = t;
+        return r;
+    }
+    for (uint64_t t0 = (uint64_t)t + G; t0 < total; t0 += 64ull * G) {
+        const uint64_t c = t0 + (uint64_t)lane * G;
+        bool ne = false;
+        uint32_t bx, by, kb, ke;
+        if (c < total) {
+            gemm_tile_of(g.group_m, nx, ny, G, (uint32_t)c, bx, by);
+            gemm_tile_krange(g, bx, by, kb, ke);
+            ne = kb < ke;
+        }
+        const uint64_t m = __ballot(ne);
+        if (m) {
+            const int src = __builtin_ctzll(m);
+            r.t = (uint32_t)(t0 + (uint64_t)src * G);
+            r.bx = (uint32_t)__builtin_amdgcn_readlane((int)bx, src);
+            r.by = (uint32_t)__builtin_amdgcn_readlane((int)by, src);
+            r.kbeg = (uint32_t)__builtin_amdgcn_readlane((int)kb, src);
+            r.kend = (uint32_t)__builtin_amdgcn_readlane((int)ke, src);
+            return r;
+        }
+    }
+    return r;
 }
 
-hipError_t launch_gemm(uint32_t p, dim3 grid, const fl::Mod &md, uint32_t bias, uint32_t c16, const GemmPlanes &gp,
-                       hipStream_t s) {
+// Persistent GEMM: gridDim.x workgroups (at most one per compute unit: the
+// LDS of kGemmLdsP bytes) take the tiles blockIdx.x + i gridDim.x of the nx x
+// ny grid that have a K range, in order.  As soon as a tile's products are
+// done, the first two operand pairs of the workgroup's next tile are fetched
+// into the ring, so the fetch overlaps the write-back of the tile (staged
+// beside the ring).  The next tile is looked up while the current tile's
+// first operands are in flight.  ONE: single-limb operands (p < 256).
+template <bool ONE>
+__global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
+                                                            GemmPlanes g, uint32_t nx, uint32_t ny) {
+    __shared__ __attribute__((aligned(16))) int8_t smem[kGemmLdsP];
+    __shared__ uint32_t rows_s[2][BM];  // C rows of the current tile and of the next one
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
+    const uint32_t G = gridDim.x, total = nx * ny;
+    const LimbCombine lc = limb_combine(md, bias, c16);
+    GemmTile cur = gemm_next_tile(g, nx, ny, blockIdx.x, G, lane);
+    if (cur.t >= total) return;
+    // (a tile's row numbers are read before its first fetch is issued: the
+    // wait for them would otherwise wait for the fetch too)
+    if (tid < BM) rows_s[0][tid] = gemm_tile_row(g, cur.by * BM, tid);
+    GemmFeed<ONE> f;
+    f.init(g, cur.by * BM, cur.bx * BN, cur.kbeg, cur.kend, smem, wave, lane);
+    f.issue(cur.kbeg, 0);
+    f.issue(cur.kbeg + 2 * BK, 1);
+    GemmAcc a;
+    for (uint32_t it = 0;; it++) {
+        // A wait for every memory access in flight (the write-back of the
+        // tile before; this tile's operands, issued before that write-back's
+        // loads, have landed, except on the first tile) that the compiler
+        // sees: with it, the compiler's model of the queue is empty, and it
+        // places no wait inside the main loop (such a wait would also wait
+        // for the operand fetch, issued by inline asm the compiler does not
+        // count).
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        const GemmTile nxt = gemm_next_tile(g, nx, ny, cur.t + G, G, lane);
+        const bool more = nxt.t < total;
+        gemm_mainloop<ONE>(f, cur.kbeg, cur.kend, smem, lc, wave, lane, a);
+        if (more) {
+            // (rows_s[(it + 1) & 1] was last read by the epilogue of the tile
+            // before, ahead of the main loop's barriers)
+            if (tid < BM) rows_s[(it + 1) & 1][tid] = gemm_tile_row(g, nxt.by * BM, tid);
+            f.init(g, nxt.by * BM, nxt.bx * BN, nxt.kbeg, nxt.kend, smem, wave, lane);
+            f.issue(nxt.kbeg, 0);
+            f.issue(nxt.kbeg + 2 * BK, 1);
+        }
+        gemm_epilogue(md, lc, g, cur.bx * BN, rows_s[it & 1], (uint16_t *)(smem + kGemmLds), wave, lane, a);
+        if (!more) return;
+        cur = nxt;
+    }
+}
+
+// Workgroups of a GEMM launch over `tiles` tiles (GemmPlanes::max_wg): one
+// per tile by default (the dispatcher then balances tiles of uneven K
+// ranges); with kGemmPerCu one per compute unit (the LDS allows no more),
+// each taking every G-th tile, which hides the operand fetch of a tile
+// behind the write-back of the one before (short, even K ranges); any other
+// value caps the count (a multiple of 8, the XCD count, when it caps).
+uint32_t gemm_workgroups(uint32_t tiles, uint32_t max_wg) {
+    if (max_wg == 0) return tiles;
+    uint32_t G = fl_queue_grid(tiles, 1);
+    if (max_wg != kGemmPerCu && G > max_wg) G = max_wg >= 8 ? max_wg / 8 * 8 : max_wg;
+    return G ? G : 1;
+}
+
+hipError_t launch_gemm(uint32_t p, uint32_t nx, uint32_t ny, const fl::Mod &md, uint32_t bias, uint32_t c16,
+                       const GemmPlanes &gp, hipStream_t s) {
+    const dim3 grid(gemm_workgroups(nx * ny, gp.max_wg));
     if (p < 256)
-        hipLaunchKernelGGL(k_mfma_gemm<true>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp);
+        hipLaunchKernelGGL(k_mfma_gemm<true>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp, nx, ny);
     else
-        hipLaunchKernelGGL(k_mfma_gemm<false>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp);
+        hipLaunchKernelGGL(k_mfma_gemm<false>, grid, dim3(kGemmThreads), 0, s, md, bias, c16, gp, nx, ny);
     return hipGetLastError();
 }
 
@@ -194,9 +304,8 @@ hipError_t fl_mfma_gemm_planes(uint32_t p, const GemmPlanes &gp, hipStream_t s, 
     const fl::Mod md = fl::make_mod(p);
     const uint32_t bias = (uint32_t)((((uint64_t)1 << 31) + p - 1) / p * p);
     const uint32_t c16 = (uint32_t)((1u << 16) % p);
-    dim3 grid((gp.N + BN - 1) / BN, (gp.M + BM - 1) / BM);
     hipError_t e;
-    FL_PROF(site, s, e = launch_gemm(p, grid, md, bias, c16, gp, s));
+    FL_PROF(site, s, e = launch_gemm(p, (gp.N + BN - 1) / BN, (gp.M + BM - 1) / BM, md, bias, c16, gp, s));
     return e;
 }
 
@@ -250,13 +359,12 @@ hipError_t fl_gemm_sub_mfma(uint32_t p, uint32_t M, uint32_t N, uint32_t Kmax, c
                                                  (const uint32_t *)nullptr, C, ldc, M, N));
         return hipGetLastError();
     }
-    dim3 grid(w.Np / BN, w.Mp / BM);
     for (uint32_t kb = 0; kb < w.Kp; kb += kKChunk) {
         const uint32_t ke = kb + kKChunk < w.Kp ? kb + kKChunk : w.Kp;
         GemmPlanes gp = {w.Ah, w.Al, w.Bh, w.Bl, w.Kp, w.Kp, 0, 0, kb, ke, Kdev, nullptr, nullptr,
                          nullptr, C, ldc, M, N};
         hipError_t e;
-        FL_PROF(site_mfma, s, e = launch_gemm(p, grid, md, bias, c16, gp, s));
+        FL_PROF(site_mfma, s, e = launch_gemm(p, w.Np / BN, w.Mp / BM, md, bias, c16, gp, s));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -79,26 +79,18 @@ inline uint32_t gemm_c16(uint32_t p) { return (uint32_t)((1u << 16) % p); }
 // 16 x 16 (three int32 accumulators each: 96 registers), so two waves share
 // each SIMD and one wave's MFMAs cover the other's waits.
 constexpr int kGemmThreads = 512;
+// The epilogue stages the residues of half a tile (64 rows) at a time.
+constexpr int kGemmOutBytes = (BM / 2) * kOutLd * 2;
+// LDS of the persistent GEMM kernel: the operand ring and, beside it, the
+// epilogue's staging area, so that the next tile's operands can be fetched
+// while the current tile is written back.
+constexpr int kGemmLdsP = kGemmLds + kGemmOutBytes;
 
-// ONE: single-limb operands (p < 256, zero h planes): the h planes are
-// neither copied nor multiplied.
-template <bool ONE = false>
-__device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
-                                               const GemmPlanes &g, uint32_t bx, uint32_t by,
-                                               int8_t *smem) {
-    static_assert(BM * kOutLd * 2 <= kGemmLds, "epilogue tile must fit the operand buffers");
-    const uint32_t tid = threadIdx.x, lane = tid & 63;
-    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
-    const uint32_t wm = wave >> 2, wn = wave & 3;
-    const uint32_t m0 = by * BM, n0 = bx * BN;
-    // C row of each tile row (0xffffffff: past M or unmapped), read by the
-    // epilogue after its barrier
-    __shared__ uint32_t rows_s[BM];
-    if (tid < BM) {
-        const uint32_t row = m0 + tid;
-        rows_s[tid] = row < g.M ? (g.row_map ? g.row_map[row] : row) : 0xffffffffu;
-    }
-    uint32_t kbeg = g.kbeg, kend = g.kend;
+// The K range [kbeg, kend) of tile (bx, by) of g (empty when kbeg >= kend).
+__device__ __forceinline__ void gemm_tile_krange(const GemmPlanes &g, uint32_t bx, uint32_t by, uint32_t &kbeg,
+                                                 uint32_t &kend) {
+    kbeg = g.kbeg;
+    kend = g.kend;
     if (g.krange) {  // per row block: intersect
         const uint32_t b = g.krange[2 * by], e = g.krange[2 * by + 1];
         kbeg = b > kbeg ? b : kbeg;
@@ -119,65 +111,110 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
         // (a cap that would leave less than one K step keeps the range)
         if (rel < kend && (rel <= kbeg || rel - kbeg >= BK)) kend = rel;
     }
-    v4i acc_hh[4][2], acc_mid[4][2], acc_ll[4][2];
+}
+
+// C row of row r of the row tile starting at m0 (0xffffffff: past M).
+__device__ __forceinline__ uint32_t gemm_tile_row(const GemmPlanes &g, uint32_t m0, uint32_t r) {
+    const uint32_t row = m0 + r;
+    return row < g.M ? (g.row_map ? g.row_map[row] : row) : 0xffffffffu;
+}
+
+// Operand pipeline: K steps are fetched in pairs, so that every row of a
+// plane tile is read as one whole 128-byte line (two 64-byte steps).  A
+// ring of two slots holds pairs of the four plane tiles (128 rows x 128
+// bytes each), copied global -> LDS by the DMA path (global_load_lds, no
+// registers involved).  Wave w fills rows 64 (w & 1) .. + 63 of plane
+// w / 2, 8 rows per instruction (lane L -> row L / 8, slot L % 8); global
+// chunk c (16 bytes) of row r sits in slot c ^ swz(r), swz(r) =
+// ((r >> 1) & 7) ^ (4 (r & 1)), so that the 16-row fragment reads below
+// hit distinct banks for both 128- and 256-byte LDS cycles.  A pair whose
+// second step lies past kend fetches its first step twice (chunks 4..7
+// repeat 0..3), so no fetch leaves [kbeg, kend).
+__device__ __forceinline__ uint32_t gemm_swz(uint32_t r) { return ((r >> 1) & 7u) ^ ((r & 1u) << 2); }
+
+template <bool ONE> struct GemmFeed {
+    const int8_t *src;   // the lane's first source byte of a pair at K offset 0
+    uint64_t pld;        // bytes per plane row
+    uint32_t ring;       // LDS address of the ring
+    uint32_t plane;      // plane filled by this wave: Ah, Al, Bh, Bl
+    uint32_t wrow;       // first tile row of this wave
+    uint32_t lchunk;     // the lane's chunk slot (even instructions)
+    uint32_t kend, last_pair;
+
+    // (fields selected with masks: a select among the kernel argument's
+    // fields by a runtime index would be compiled into a private-memory table)
+    __device__ __forceinline__ void init(const GemmPlanes &g, uint32_t m0, uint32_t n0, uint32_t kbeg,
+                                         uint32_t kend_, const int8_t *smem, uint32_t wave, uint32_t lane) {
+        ring = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const int8_t *)smem;
+        plane = wave >> 1;
+        wrow = (wave & 1) * 64;
+        const uint64_t m_a = plane < 2 ? ~0ull : 0ull;
+        pld = (g.lda & m_a) | (g.ldb & ~m_a);
+        const uint64_t poff = (uint64_t)(((uint64_t)m0 & m_a) | ((uint64_t)n0 & ~m_a)) * pld +
+                              (((uint64_t)g.a_k0 & m_a) | ((uint64_t)g.b_k0 & ~m_a));
+        const uint64_t m_lo = (plane & 1) ? 0ull : ~0ull;
+        const uint64_t p_a = ((uint64_t)(uintptr_t)g.Ah & m_lo) | ((uint64_t)(uintptr_t)g.Al & ~m_lo);
+        const uint64_t p_b = ((uint64_t)(uintptr_t)g.Bh & m_lo) | ((uint64_t)(uintptr_t)g.Bl & ~m_lo);
+        // the lane's row of instruction 0 and its chunk there; instruction i
+        // is 8 i rows further down, where swz differs by 4 (i odd)
+        const uint32_t lrow = wrow + (lane >> 3);
+        lchunk = (lane & 7) ^ gemm_swz(lrow);
+        src = (const int8_t *)(uintptr_t)(((p_a & m_a) | (p_b & ~m_a)) + poff) + (uint64_t)lrow * pld;
+        kend = kend_;
+        last_pair = kbeg + (kend_ > kbeg ? (kend_ - kbeg - 1) / (2 * BK) * (2 * BK) : 0);
+    }
+    // pair starting at K offset ks (past the range: the last pair, fetched
+    // again, so every pair issues the same 8 instructions per wave) into
+    // slot `slot`
+    __device__ __forceinline__ void issue(uint32_t ks, uint32_t slot) const {
+        if (ONE && !(plane & 1)) return;  // an h plane: all zero
+        const uint32_t kk = ks < kend ? ks : last_pair;
+        const uint32_t cmask = kk + 2 * BK <= kend ? 7u : 3u;
+        const int8_t *src_e = src + kk + ((lchunk & cmask) << 4);        // even i
+        const int8_t *src_o = src + kk + (((lchunk ^ 4u) & cmask) << 4);  // odd i
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int8_t *s = ((i & 1) ? src_o : src_e) + (uint64_t)(i * 8) * pld;
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kPairBytes + plane * kPairPlane +
+                                                                (wrow + i * 8) * kPairRow);
+            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(s) : "memory");
+        }
+    }
+};
+
+struct GemmAcc {
+    v4i hh[4][2], mid[4][2], ll[4][2];
+};
+
+// The products of one tile over [kbeg, kend) (kbeg < kend) into a (zeroed
+// here).  On entry the tile's first two pairs have been issued by f into
+// slots 0 and 1 (other memory operations may follow them); on return every
+// fetch of the ring has landed and the workgroup has passed a barrier, so
+// the ring may be refilled.
+//
+// Step j is half j & 1 of pair j / 2 (slot (j / 2) & 1).  Its fragments
+// are read during step j - 1 (into the second register set, copied over
+// after the MFMAs), so the LDS reads overlap the MFMAs.  At an odd step
+// the next step opens a new pair: the wave waits for that pair's fetch
+// (issued two steps earlier) and for its own LDS reads; after the barrier
+// nobody reads the pair just finished, and its slot is refilled with the
+// pair after the next.  Even steps need no barrier.
+template <bool ONE>
+__device__ __forceinline__ void gemm_mainloop(const GemmFeed<ONE> &f, uint32_t kbeg, uint32_t kend,
+                                              const int8_t *smem, const LimbCombine &lc, uint32_t wave,
+                                              uint32_t lane, GemmAcc &a) {
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) {
-            acc_hh[i][j] = v4i{0, 0, 0, 0};
-            acc_mid[i][j] = v4i{0, 0, 0, 0};
-            acc_ll[i][j] = v4i{0, 0, 0, 0};
+            a.hh[i][j] = v4i{0, 0, 0, 0};
+            a.mid[i][j] = v4i{0, 0, 0, 0};
+            a.ll[i][j] = v4i{0, 0, 0, 0};
         }
-    // Operand pipeline: K steps are fetched in pairs, so that every row of a
-    // plane tile is read as one whole 128-byte line (two 64-byte steps).  A
-    // ring of two slots holds pairs of the four plane tiles (128 rows x 128
-    // bytes each), copied global -> LDS by the DMA path (global_load_lds, no
-    // registers involved).  Wave w fills rows 64 (w & 1) .. + 63 of plane
-    // w / 2, 8 rows per instruction (lane L -> row L / 8, slot L % 8); global
-    // chunk c (16 bytes) of row r sits in slot c ^ swz(r), swz(r) =
-    // ((r >> 1) & 7) ^ (4 (r & 1)), so that the 16-row fragment reads below
-    // hit distinct banks for both 128- and 256-byte LDS cycles.  A pair whose
-    // second step lies past kend fetches its first step twice (chunks 4..7
-    // repeat 0..3), so no fetch leaves [kbeg, kend).
-    const uint32_t ring = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int8_t *)smem;
-    const uint32_t plane = wave >> 1;
-    // (selected with masks: a select among the kernel argument's fields by a
-    // runtime index would be compiled into a private-memory table)
-    const uint64_t m_a = plane < 2 ? ~0ull : 0ull;
-    const uint64_t pld = (g.lda & m_a) | (g.ldb & ~m_a);
-    const uint64_t poff = (uint64_t)(((uint64_t)m0 & m_a) | ((uint64_t)n0 & ~m_a)) * pld +
-                          (((uint64_t)g.a_k0 & m_a) | ((uint64_t)g.b_k0 & ~m_a));
-    const uint64_t m_lo = (plane & 1) ? 0ull : ~0ull;
-    const uint64_t p_a = ((uint64_t)(uintptr_t)g.Ah & m_lo) | ((uint64_t)(uintptr_t)g.Al & ~m_lo);
-    const uint64_t p_b = ((uint64_t)(uintptr_t)g.Bh & m_lo) | ((uint64_t)(uintptr_t)g.Bl & ~m_lo);
-    const int8_t *const pbase = (const int8_t *)(uintptr_t)(((p_a & m_a) | (p_b & ~m_a)) + poff);
-    auto swz = [](uint32_t r) { return ((r >> 1) & 7u) ^ ((r & 1u) << 2); };
-    // the lane's row of instruction 0 and its chunk there; instruction i is 8 i
-    // rows further down, where swz differs by 4 (i odd)
-    const uint32_t lrow = (wave & 1) * 64 + (lane >> 3), lpos = lane & 7;
-    const uint32_t lchunk = lpos ^ swz(lrow);
-    const uint64_t lbase = (uint64_t)lrow * pld;
-    const uint32_t last_pair = kbeg + (kend > kbeg ? (kend - kbeg - 1) / (2 * BK) * (2 * BK) : 0);
-    // pair starting at K offset ks (past the range: the last pair, fetched
-    // again, so every pair issues the same 8 instructions per wave) into
-    // slot `slot`
-    auto issue = [&](uint32_t ks, uint32_t slot) {
-        if (ONE && !(plane & 1)) return;  // an h plane: all zero
-        const uint32_t kk = ks < kend ? ks : last_pair;
-        const uint32_t cmask = kk + 2 * BK <= kend ? 7u : 3u;
-        const int8_t *src_e = pbase + lbase + kk + ((lchunk & cmask) << 4);        // even i
-        const int8_t *src_o = pbase + lbase + kk + (((lchunk ^ 4u) & cmask) << 4);  // odd i
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int8_t *src = ((i & 1) ? src_o : src_e) + (uint64_t)(i * 8) * pld;
-            const uint32_t dst = __builtin_amdgcn_readfirstlane(ring + slot * kPairBytes + plane * kPairPlane +
-                                                                ((wave & 1) * 64 + i * 8) * kPairRow);
-            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory");
-        }
-    };
+    const uint32_t wm = wave >> 2, wn = wave & 3;
     // The wave's fragments of a step (half h of the pair in slot `slot`): A
-    // row tiles (4 of 16 rows) and B column tiles (2 of 16 columns), both limb
-    // planes, 16 bytes of K per lane.
+    // row tiles (4 of 16 rows) and B column tiles (2 of 16 columns), both
+    // limb planes, 16 bytes of K per lane.
     const uint32_t kc = lane >> 4;
     auto read_ops = [&](uint32_t slot, uint32_t h, v4i (&ah)[4], v4i (&al)[4], v4i (&bh)[2], v4i (&bl)[2]) {
         const int8_t *st = smem + slot * kPairBytes;
@@ -185,39 +222,27 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const uint32_t ra = wm * 64 + t * 16 + (lane & 15);
-            const uint32_t oa = ra * kPairRow + ((gc ^ swz(ra)) << 4);
+            const uint32_t oa = ra * kPairRow + ((gc ^ gemm_swz(ra)) << 4);
             if (!ONE) ah[t] = *(const v4i *)(st + oa);
             al[t] = *(const v4i *)(st + kPairPlane + oa);
         }
 #pragma unroll
         for (int t = 0; t < 2; t++) {
             const uint32_t rb = wn * 32 + t * 16 + (lane & 15);
-            const uint32_t ob = rb * kPairRow + ((gc ^ swz(rb)) << 4);
+            const uint32_t ob = rb * kPairRow + ((gc ^ gemm_swz(rb)) << 4);
             if (!ONE) bh[t] = *(const v4i *)(st + 2 * kPairPlane + ob);
             bl[t] = *(const v4i *)(st + 3 * kPairPlane + ob);
         }
     };
-    // Step j is half j & 1 of pair j / 2 (slot (j / 2) & 1).  Its fragments
-    // are read during step j - 1 (into the second register set, copied over
-    // after the MFMAs), so the LDS reads overlap the MFMAs.  At an odd step
-    // the next step opens a new pair: the wave waits for that pair's fetch
-    // (issued two steps earlier) and for its own LDS reads; after the
-    // barrier nobody reads the pair just finished, and its slot is refilled
-    // with the pair after the next.  Even steps need no barrier.
     v4i ah[4], al[4], bh[2], bl[2], nah[4], nal[4], nbh[2], nbl[2];
-    const LimbCombine lc = limb_combine(md, bias, c16);
     uint32_t left = kKChunk / BK;  // K steps before the accumulators are folded
-    if (kbeg < kend) {
-        issue(kbeg, 0);
-        issue(kbeg + 2 * BK, 1);
-        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        read_ops(0, 0, ah, al, bh, bl);
-        // (a wait the compiler sees: the loop's MFMAs then never wait for the
-        // next step's LDS reads, issued just before them)
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    }
+    asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    read_ops(0, 0, ah, al, bh, bl);
+    // (a wait the compiler sees: the loop's MFMAs then never wait for the
+    // next step's LDS reads, issued just before them)
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     uint32_t j = 0;
     for (uint32_t k0 = kbeg; k0 < kend; k0 += BK, j++) {
         const bool more = k0 + BK < kend;
@@ -226,7 +251,7 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
-            issue(kbeg + (q + 1) * 2 * BK, (q + 1) & 1);
+            f.issue(kbeg + (q + 1) * 2 * BK, (q + 1) & 1);
             read_ops(q & 1, 0, nah, nal, nbh, nbl);  // (past the range: stale, unused)
         } else {
             read_ops((j >> 1) & 1, 1, nah, nal, nbh, nbl);
@@ -237,11 +262,11 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
 #pragma unroll
             for (int jj = 0; jj < 2; jj++) {
                 if (!ONE) {
-                    acc_hh[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[jj], acc_hh[i][jj], 0, 0, 0);
-                    acc_mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[jj], acc_mid[i][jj], 0, 0, 0);
-                    acc_mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[jj], acc_mid[i][jj], 0, 0, 0);
+                    a.hh[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bh[jj], a.hh[i][jj], 0, 0, 0);
+                    a.mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah[i], bl[jj], a.mid[i][jj], 0, 0, 0);
+                    a.mid[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bh[jj], a.mid[i][jj], 0, 0, 0);
                 }
-                acc_ll[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[jj], acc_ll[i][jj], 0, 0, 0);
+                a.ll[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(al[i], bl[jj], a.ll[i][jj], 0, 0, 0);
             }
         if (--left == 0 && more) {  // a K range longer than kKChunk: fold
             left = kKChunk / BK;
@@ -251,10 +276,9 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
                 for (int jj = 0; jj < 2; jj++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        acc_ll[i][jj][e] =
-                            (int)combine_limbs(lc, acc_hh[i][jj][e], acc_mid[i][jj][e], acc_ll[i][jj][e]);
-                        acc_hh[i][jj][e] = 0;
-                        acc_mid[i][jj][e] = 0;
+                        a.ll[i][jj][e] = (int)combine_limbs(lc, a.hh[i][jj][e], a.mid[i][jj][e], a.ll[i][jj][e]);
+                        a.hh[i][jj][e] = 0;
+                        a.mid[i][jj][e] = 0;
                     }
         }
 #pragma unroll
@@ -268,62 +292,124 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
             bl[t] = nbl[t];
         }
     }
-    // drain the DMA path before the ring is reused for the output tile
+    // drain the DMA path before the ring is reused
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (kbeg >= kend) return;  // nothing to subtract
-    // the C tile (128 rows x 32 chunks of 4 columns, 8 chunks per thread) is
-    // loaded before the residues are formed, so its latency overlaps that
-    // work; every load is issued (chunks outside the tile read C[0])
+}
+
+// Epilogue of a tile whose products are in a: C[rows_s[r], n0 + c] -= the
+// residue of the limb sums.  The C tile (128 rows x 32 chunks of 4 columns,
+// 8 chunks per thread) is loaded first, so its latency overlaps the
+// reduction of the sums; the residues then go through LDS (sOut: 64 rows of
+// kOutLd u16, one half tile at a time) and C is reduced and written back
+// with coalesced 8-byte accesses.  Output element (row 4 (lane / 16) + e,
+// column lane % 16) of each 16 x 16 tile is held by the wave; the waves of
+// row half h (wave / 4 = h) stage half h.  rows_s (the tile's C rows, see
+// gemm_tile_row) must be visible to all threads on entry; callers reusing
+// sOut or rows_s afterwards must synchronise first.
+__device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombine &lc, const GemmPlanes &g,
+                                              uint32_t n0, const uint32_t *rows_s, uint16_t *sOut, uint32_t wave,
+                                              uint32_t lane, GemmAcc &a) {
     typedef __attribute__((address_space(1))) const uint64_t gu64;
     typedef __attribute__((address_space(1))) uint64_t gu64w;
-    constexpr int kChunks = BM * (BN / 4) / kGemmThreads;
-    uint64_t cvals[kChunks];
+    const uint32_t tid = threadIdx.x, wm = wave >> 2, wn = wave & 3;
+    constexpr int kHalf = (BM / 2) * (BN / 4) / kGemmThreads;  // chunks per thread and half tile
+    // (every load is issued: chunks outside the tile read C[0])
+    uint64_t cvals[2][kHalf];
 #pragma unroll
-    for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * kGemmThreads, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-        const uint32_t orow = rows_s[r], col = n0 + c4;
-        const bool ok = orow != 0xffffffffu && col + 4 <= g.N;
-        cvals[u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
-    }
-    // epilogue: residues of the 128 x 128 tile go through LDS (the operand
-    // buffers are free now), then C is reduced and written back with
-    // coalesced 8-byte accesses.  Output element (row 4*(lane/16) + e,
-    // column lane%16) of each 16 x 16 tile is held by the wave.
-    uint16_t *sOut = (uint16_t *)smem;
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int u = 0; u < kHalf; u++) {
+            const uint32_t ch = tid + u * kGemmThreads, r = h * (BM / 2) + ch / (BN / 4);
+            const uint32_t orow = rows_s[r], col = n0 + (ch % (BN / 4)) * 4;
+            const bool ok = orow != 0xffffffffu && col + 4 <= g.N;
+            cvals[h][u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
+        }
+    // the residues, in place of the ll sums
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const uint32_t col = wn * 32 + j * 16 + (lane & 15);
+        for (int j = 0; j < 2; j++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const uint32_t row = wm * 64 + i * 16 + (lane >> 4) * 4 + e;
-                sOut[row * kOutLd + col] =
-                    (uint16_t)combine_limbs(lc, acc_hh[i][j][e], acc_mid[i][j][e], acc_ll[i][j][e]);
+            for (int e = 0; e < 4; e++)
+                a.ll[i][j][e] = (int)combine_limbs(lc, a.hh[i][j][e], a.mid[i][j][e], a.ll[i][j][e]);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        if (wm == (uint32_t)h) {
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const uint32_t col = wn * 32 + j * 16 + (lane & 15);
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        sOut[(i * 16 + (lane >> 4) * 4 + e) * kOutLd + col] = (uint16_t)a.ll[i][j][e];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kHalf; u++) {
+            const uint32_t ch = tid + u * kGemmThreads, rl = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
+            const uint32_t orow = rows_s[h * (BM / 2) + rl], col = n0 + c4;
+            // (every C value is taken on every path, also where it is not
+            // needed: a load left outstanding would make the compiler wait
+            // for it inside the next tile's main loop, which reuses its
+            // registers)
+            const uint64_t ov = cvals[h][u];
+            if (orow == 0xffffffffu || col >= g.N) {
+                asm volatile("" ::"v"(ov));
+                continue;
+            }
+            uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
+            const uint64_t sv = *(const uint64_t *)(sOut + rl * kOutLd + c4);
+            if (col + 4 <= g.N) {
+                uint64_t nv = 0;
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
+                                               (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
+                *(gu64w *)o = nv;
+            } else {
+                asm volatile("" ::"v"(ov));
+                for (uint32_t c = 0; col + c < g.N; c++)
+                    o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
             }
         }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kChunks; u++) {
-        const uint32_t ch = tid + u * kGemmThreads, r = ch / (BN / 4), c4 = (ch % (BN / 4)) * 4;
-        const uint32_t orow = rows_s[r], col = n0 + c4;
-        if (orow == 0xffffffffu || col >= g.N) continue;
-        uint16_t *o = g.C + (uint64_t)orow * g.ldc + col;
-        const uint64_t sv = *(const uint64_t *)(sOut + r * kOutLd + c4);
-        if (col + 4 <= g.N) {
-            const uint64_t ov = cvals[u];
-            uint64_t nv = 0;
-#pragma unroll
-            for (int c = 0; c < 4; c++)
-                nv |= (uint64_t)fl::submod((uint32_t)(ov >> (16 * c)) & 0xffffu,
-                                           (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p) << (16 * c);
-            *(gu64w *)o = nv;
-        } else {
-            for (uint32_t c = 0; col + c < g.N; c++)
-                o[c] = (uint16_t)fl::submod(o[c], (uint32_t)(sv >> (16 * c)) & 0xffffu, md.p);
-        }
+        if (h == 0) __syncthreads();  // half 1 is staged in the same buffer
     }
+}
+
+// One tile (bx, by) by one workgroup, for kernels that take their tiles one
+// at a time (smem: kGemmLds bytes; callers looping over tiles must
+// synchronise between them).
+template <bool ONE = false>
+__device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
+                                               const GemmPlanes &g, uint32_t bx, uint32_t by,
+                                               int8_t *smem) {
+    static_assert(kGemmOutBytes <= kGemmLds, "epilogue tile must fit the operand buffers");
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
+    // C row of each tile row, read by the epilogue after the main loop's barriers
+    __shared__ uint32_t rows_s[BM];
+    if (tid < BM) rows_s[tid] = gemm_tile_row(g, by * BM, tid);
+    uint32_t kbeg, kend;
+    gemm_tile_krange(g, bx, by, kbeg, kend);
+    if (kbeg >= kend) {  // nothing to subtract
+        __syncthreads();
+        return;
+    }
+    const LimbCombine lc = limb_combine(md, bias, c16);
+    // (a wait the compiler sees for the accesses still in flight, such as a
+    // previous tile's write-back: the compiler then places no wait inside the
+    // main loop, where it would also wait for the operand fetch)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    GemmFeed<ONE> f;
+    f.init(g, by * BM, bx * BN, kbeg, kend, smem, wave, lane);
+    f.issue(kbeg, 0);
+    f.issue(kbeg + 2 * BK, 1);
+    GemmAcc a;
+    gemm_mainloop<ONE>(f, kbeg, kend, smem, lc, wave, lane, a);
+    gemm_epilogue(md, lc, g, bx * BN, rows_s, (uint16_t *)smem, wave, lane, a);
 }
 
 // Rank-k update, k <= 64 KS (Gauss-Jordan panel and block updates, TRSM near

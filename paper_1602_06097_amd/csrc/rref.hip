@@ -422,6 +422,7 @@ extern "C" fl_status fl_rref(const fl_split_info *info, const fl_split_out *s, u
         // the column tile's R_D planes in L2 (measured: 4 beats grid order,
         // 16, and all row tiles per column)
         gp.group_m = 4;
+        gp.max_wg = kGemmPerCu;  // (measured: a little faster than one workgroup per tile)
         FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "rref.mfma"));
     } else {
         // the same zero-skipping as the MFMA form: per 128-column tile the R_D

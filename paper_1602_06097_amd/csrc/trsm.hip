@@ -1269,6 +1269,7 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                                      nullptr, X + (uint64_t)rt * ldx, ldx, R1 - rt, nB};
                     gp.group_m = kFlTrsmSuper;  // the superblock's row tiles share each B column tile
                     gp.kcap_n = t.xkend;        // column tiles where those rows of X are zero: skipped
+                    gp.max_wg = kGemmPerCu;     // short K ranges: fetch overlapping write-back
                     FL_HIP(fl_mfma_gemm_planes(info->p, gp, stream, "trsm.update.mfma"));
                     // the superblock above [ru, rt): its terms from rows at or past R1,
                     // issued after the critical-path GEMM, which then does not queue behind it
@@ -1282,6 +1283,10 @@ extern "C" fl_status fl_trsm(const fl_split_info *info, const fl_split_out *s, u
                                          nullptr, nullptr, X + (uint64_t)ru * ldx, ldx, rt - ru, nB};
                         gf.group_m = kFlTrsmSuper;
                         gf.kcap_n = t.xkend;
+                        // 32 compute units stay free for the solves of the
+                        // superblock below, which run meanwhile (measured on
+                        // 256: 1 ms faster than all units, equal to 64 free)
+                        gf.max_wg = fl_cu_count() > 96 ? fl_cu_count() - 32 : kGemmPerCu;
                         FL_HIP(fl_mfma_gemm_planes(info->p, gf, far_s, "trsm.update.far"));
                         FL_HIP(hipEventRecord(ev_far, far_s));
                         far_pending = true;
