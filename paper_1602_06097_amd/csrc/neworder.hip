@@ -314,6 +314,7 @@ extern "C" fl_status fl_reduce_neworder(const fl_split_info *info, const fl_spli
             const uint64_t ke = kb + kKChunk < t.kp ? kb + kKChunk : t.kp;
             GemmPlanes gp = {t.Ch, t.Cl, t.Bh, t.Bl, t.kp, t.kp, 0, 0, (uint32_t)kb, (uint32_t)ke, nullptr,
                              nullptr, t.krange_n, nullptr, Dt, ldd, mD, nB};
+            gp.group_m = 4;  // groups of 4 row tiles per column tile on each XCD
             FL_HIP(fl_mfma_gemm_planes(p, gp, stream, "neworder.mfma"));
         }
     } else {
