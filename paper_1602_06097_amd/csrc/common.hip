@@ -206,9 +206,11 @@ hipError_t fl_zero_rows_u16(uint16_t *p, uint64_t ld, uint32_t rows, uint32_t co
 // Every 32-bit x through reduce32; with it, fold_pair(x, y) against 64-bit
 // division for y = x times an odd constant (a spread of low words over the
 // whole 2^41 range of 256 x + y), mulmod over the residue pairs (x mod 2^16
-// mod p, x >> 16 mod p), and combine_limbs over a grid of (S_hh, S_mid, S_ll)
-// spanning the whole range its callers can produce (sums of up to kKChunk
-// limb products, S_ll plus a folded residue), corners included.
+// mod p, x >> 16 mod p), and combine_limbs (with its p >= 256 form
+// combine_limbs_2) over a grid of (S_hh, S_mid, S_ll) spanning the whole
+// range its callers can produce (sums of up to kKChunk limb products, S_ll
+// plus a folded residue), corners included; for p < 256 the single-limb
+// combine_limbs_1 over the range of its sums instead.
 namespace {
 // Value i (of 2^bits) of a grid over [lo, hi]: the four values at each end,
 // the four around zero, and a jittered linear spread in between.
@@ -242,6 +244,14 @@ __global__ void k_check_modp(fl::Mod m, uint32_t bias, uint32_t c16, uint64_t *m
         const int64_t S = hh * 65536 + mid * 256 + ll;
         const int64_t want = ((S % (int64_t)m.p) + m.p) % m.p;
         if (fl_mfma::combine_limbs(lc, (int)hh, (int)mid, (int)ll) != (uint32_t)want) bad++;
+        if (m.p >= 256) {  // the two-limb GEMM's combine (p >= 256 only)
+            if (fl_mfma::combine_limbs_2(lc, (int)hh, (int)mid, (int)ll) != (uint32_t)want) bad++;
+        } else {  // the single-limb GEMM's combine: S_ll of up to kKChunk products in [-127^2, 127^2]
+            const int64_t kMaxOne = (int64_t)fl_mfma::kKChunk * 16129;
+            const int64_t l1 = grid_value(v & 0x3fffffu, 22, -kMaxOne, kMaxOne + m.p - 1);
+            const int64_t w1 = ((l1 % (int64_t)m.p) + m.p) % m.p;
+            if (fl_mfma::combine_limbs_1(lc, (int)l1) != (uint32_t)w1) bad++;
+        }
     }
     if (bad) atomicAdd((unsigned long long *)mismatch, (unsigned long long)bad);
 }

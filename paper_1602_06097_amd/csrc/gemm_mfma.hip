@@ -172,7 +172,9 @@ __device__ __forceinline__ GemmTile gemm_next_tile(const GemmPlanes &g, uint32_t
 // done, the first two operand pairs of the workgroup's next tile are fetched
 // into the ring, so the fetch overlaps the write-back of the tile (staged
 // beside the ring).  The next tile is looked up while the current tile's
-// first operands are in flight.  ONE: single-limb operands (p < 256).
+// first operands are in flight.  ONE: single-limb operands (p < 256); the
+// launch takes ONE exactly when p < 256, so the two-limb form combines the
+// limb sums with p >= 256.
 template <bool ONE>
 __global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t bias, uint32_t c16,
                                                             GemmPlanes g, uint32_t nx, uint32_t ny) {
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         const GemmTile nxt = gemm_next_tile(g, nx, ny, cur.t + G, G, lane);
         const bool more = nxt.t < total;
-        gemm_mainloop<ONE>(f, cur.kbeg, cur.kend, smem, lc, wave, lane, a);
+        gemm_mainloop<ONE, !ONE>(f, cur.kbeg, cur.kend, smem, lc, wave, lane, a);
         if (more) {
             // (rows_s[(it + 1) & 1] was last read by the epilogue of the tile
             // before, ahead of the main loop's barriers)
@@ -212,7 +214,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_mfma_gemm(fl::Mod md, uint32_t
             f.issue(nxt.kbeg, 0);
             f.issue(nxt.kbeg + 2 * BK, 1);
         }
-        gemm_epilogue(md, lc, g, cur.bx * BN, rows_s[it & 1], (uint16_t *)(smem + kGemmLds), wave, lane, a);
+        gemm_epilogue<ONE, !ONE>(md, lc, g, cur.bx * BN, rows_s[it & 1], (uint16_t *)(smem + kGemmLds), wave, lane,
+                                    a);
         if (!more) return;
         cur = nxt;
     }

@@ -68,6 +68,42 @@ __device__ __forceinline__ uint32_t combine_limbs(const LimbCombine &c, int hh, 
     const uint32_t r1 = fl::reduce32((uint32_t)h1 + c.bias, c.md);
     return fl::reduce32(r1 * c.c16 + L, c.md);
 }
+// reduce32 for p >= 256: the quotient estimate floor(x mu / 2^32) <= x / p
+// is below 2^24, so q p is the full-rate 24-bit product.
+__device__ __forceinline__ uint32_t reduce32_q24(uint32_t x, const fl::Mod &m) {
+    const uint32_t q = __umulhi(x, m.mu);
+    const uint32_t r = x - __umul24(q, m.p);
+    return r >= m.p ? r - m.p : r;
+}
+// combine_limbs for p >= 256 (two limbs), with full-rate 24-bit products
+// only: r1 < p and c16 < p are below 2^16.
+__device__ __forceinline__ uint32_t combine_limbs_2(const LimbCombine &c, int hh, int mid, int ll) {
+    const int m1 = mid + (ll >> 8);
+    const int h1 = hh + (m1 >> 8);
+    const uint32_t L = (((uint32_t)m1 & 255u) << 8) | ((uint32_t)ll & 255u);
+    const uint32_t r1 = reduce32_q24((uint32_t)h1 + c.bias, c.md);
+    return reduce32_q24(__umul24(r1, c.c16) + L, c.md);
+}
+// The residue of a single-limb sum S_ll (p < 256, |S_ll| < 2^30: at most
+// kKChunk products of two limbs in [-127, 127], plus a folded residue):
+// S_ll + bias lies in [0, 2^32).
+__device__ __forceinline__ uint32_t combine_limbs_1(const LimbCombine &c, int ll) {
+    return fl::reduce32((uint32_t)ll + c.bias, c.md);
+}
+// The GEMM tile's combine: ONE = single-limb operands (p < 256); BIG =
+// p >= 256 is known; otherwise any p.
+template <bool ONE, bool BIG>
+__device__ __forceinline__ uint32_t combine_limbs_t(const LimbCombine &c, int hh, int mid, int ll) {
+    if constexpr (ONE) {
+        (void)hh;
+        (void)mid;
+        return combine_limbs_1(c, ll);
+    } else if constexpr (BIG) {
+        return combine_limbs_2(c, hh, mid, ll);
+    } else {
+        return combine_limbs(c, hh, mid, ll);
+    }
+}
 
 // bias: the smallest multiple of p that is >= 2^31 (combine_limbs);
 // c16 = 2^16 mod p.
@@ -199,7 +235,7 @@ struct GemmAcc {
 // (issued two steps earlier) and for its own LDS reads; after the barrier
 // nobody reads the pair just finished, and its slot is refilled with the
 // pair after the next.  Even steps need no barrier.
-template <bool ONE>
+template <bool ONE, bool BIG>
 __device__ __forceinline__ void gemm_mainloop(const GemmFeed<ONE> &f, uint32_t kbeg, uint32_t kend,
                                               const int8_t *smem, const LimbCombine &lc, uint32_t wave,
                                               uint32_t lane, GemmAcc &a) {
@@ -276,7 +312,8 @@ __device__ __forceinline__ void gemm_mainloop(const GemmFeed<ONE> &f, uint32_t k
                 for (int jj = 0; jj < 2; jj++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        a.ll[i][jj][e] = (int)combine_limbs(lc, a.hh[i][jj][e], a.mid[i][jj][e], a.ll[i][jj][e]);
+                        a.ll[i][jj][e] =
+                            (int)combine_limbs_t<ONE, BIG>(lc, a.hh[i][jj][e], a.mid[i][jj][e], a.ll[i][jj][e]);
                         a.hh[i][jj][e] = 0;
                         a.mid[i][jj][e] = 0;
                     }
@@ -307,6 +344,7 @@ __device__ __forceinline__ void gemm_mainloop(const GemmFeed<ONE> &f, uint32_t k
 // row half h (wave / 4 = h) stage half h.  rows_s (the tile's C rows, see
 // gemm_tile_row) must be visible to all threads on entry; callers reusing
 // sOut or rows_s afterwards must synchronise first.
+template <bool ONE, bool BIG>
 __device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombine &lc, const GemmPlanes &g,
                                               uint32_t n0, const uint32_t *rows_s, uint16_t *sOut, uint32_t wave,
                                               uint32_t lane, GemmAcc &a) {
@@ -332,7 +370,7 @@ __device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombi
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int e = 0; e < 4; e++)
-                a.ll[i][j][e] = (int)combine_limbs(lc, a.hh[i][j][e], a.mid[i][j][e], a.ll[i][j][e]);
+                a.ll[i][j][e] = (int)combine_limbs_t<ONE, BIG>(lc, a.hh[i][j][e], a.mid[i][j][e], a.ll[i][j][e]);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         if (wm == (uint32_t)h) {
@@ -381,7 +419,7 @@ __device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombi
 
 // One tile (bx, by) by one workgroup, for kernels that take their tiles one
 // at a time (smem: kGemmLds bytes; callers looping over tiles must
-// synchronise between them).
+// synchronise between them).  Any p (two-limb operands unless ONE).
 template <bool ONE = false>
 __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias, uint32_t c16,
                                                const GemmPlanes &g, uint32_t bx, uint32_t by,
@@ -408,8 +446,8 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     f.issue(kbeg, 0);
     f.issue(kbeg + 2 * BK, 1);
     GemmAcc a;
-    gemm_mainloop<ONE>(f, kbeg, kend, smem, lc, wave, lane, a);
-    gemm_epilogue(md, lc, g, bx * BN, rows_s, (uint16_t *)smem, wave, lane, a);
+    gemm_mainloop<ONE, false>(f, kbeg, kend, smem, lc, wave, lane, a);
+    gemm_epilogue<ONE, false>(md, lc, g, bx * BN, rows_s, (uint16_t *)smem, wave, lane, a);
 }
 
 // Rank-k update, k <= 64 KS (Gauss-Jordan panel and block updates, TRSM near

@@ -264,8 +264,12 @@ def test_matmul_sub_single_limb_extremes(p, value):
 
 
 def test_modular_reduction_exhaustive_on_device():
-    """The kernels' Barrett reduction equals x % p for every x < 2^32."""
-    assert fl.check_modp([2, 3, 251, 32749, 65521]) == [0, 0, 0, 0, 0]
+    """The kernels' Barrett reduction equals x % p for every x < 2^32, and
+    the limb combines (the general one, the p >= 256 one with 24-bit
+    products, the single-limb one for p < 256) equal S mod p over their
+    input ranges; 257 is the smallest prime of the 24-bit form."""
+    primes = [2, 3, 251, 257, 32749, 65521]
+    assert fl.check_modp(primes) == [0] * len(primes)
 
 
 @pytest.mark.parametrize("field,value,code", [("col", 10**6, 4), ("val", 0, 6), ("val", 65521, 6)])
