@@ -582,7 +582,7 @@ __device__ void check_tile(const fl::Mod &md, const FlEchTask &t, uint32_t bx, u
     }
     // step 0 also records each listed row's first nonzero column
     block_append8(mask & live, my_row, out_list, out_count, use_basis ? nullptr : t.nzlead, my_lead);
-    if (use_basis && threadIdx.x == 0) __threadfence();
+    // (no fence: the lists are read by later launches on the same stream)
 }
 
 __global__ __launch_bounds__(256) void k_ech_check(fl::Mod md, const FlEchTask *__restrict__ tasks,
