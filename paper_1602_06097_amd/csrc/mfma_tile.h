@@ -344,25 +344,41 @@ __device__ __forceinline__ void gemm_mainloop(const GemmFeed<ONE> &f, uint32_t k
 // row half h (wave / 4 = h) stage half h.  rows_s (the tile's C rows, see
 // gemm_tile_row) must be visible to all threads on entry; callers reusing
 // sOut or rows_s afterwards must synchronise first.
-template <bool ONE, bool BIG>
-__device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombine &lc, const GemmPlanes &g,
-                                              uint32_t n0, const uint32_t *rows_s, uint16_t *sOut, uint32_t wave,
-                                              uint32_t lane, GemmAcc &a) {
+constexpr int kGemmHalf = (BM / 2) * (BN / 4) / kGemmThreads;  // C chunks per thread and half tile
+struct GemmC {
+    uint64_t v[2][kGemmHalf];
+};
+
+// The C tile's values (chunk u of half h: 4 entries of row h (BM / 2) + ch /
+// (BN / 4), ch = tid + u kGemmThreads), with the row of tile row r given by
+// row(r) (0xffffffff: past M).  Every load is issued: chunks outside the
+// tile read C[0].
+template <typename RowOf>
+__device__ __forceinline__ void gemm_cload(const GemmPlanes &g, uint32_t n0, RowOf row, GemmC &c) {
     typedef __attribute__((address_space(1))) const uint64_t gu64;
-    typedef __attribute__((address_space(1))) uint64_t gu64w;
-    const uint32_t tid = threadIdx.x, wm = wave >> 2, wn = wave & 3;
-    constexpr int kHalf = (BM / 2) * (BN / 4) / kGemmThreads;  // chunks per thread and half tile
-    // (every load is issued: chunks outside the tile read C[0])
-    uint64_t cvals[2][kHalf];
+    const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int h = 0; h < 2; h++)
 #pragma unroll
-        for (int u = 0; u < kHalf; u++) {
+        for (int u = 0; u < kGemmHalf; u++) {
             const uint32_t ch = tid + u * kGemmThreads, r = h * (BM / 2) + ch / (BN / 4);
-            const uint32_t orow = rows_s[r], col = n0 + (ch % (BN / 4)) * 4;
+            const uint32_t orow = row(r), col = n0 + (ch % (BN / 4)) * 4;
             const bool ok = orow != 0xffffffffu && col + 4 <= g.N;
-            cvals[h][u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
+            c.v[h][u] = *(gu64 *)(ok ? g.C + (uint64_t)orow * g.ldc + col : g.C);
         }
+}
+
+// PRE: the C tile was loaded by the caller (ahead of the products, into c);
+// otherwise it is loaded here, from the rows in rows_s.
+template <bool ONE, bool BIG, bool PRE = false>
+__device__ __forceinline__ void gemm_epilogue(const fl::Mod &md, const LimbCombine &lc, const GemmPlanes &g,
+                                              uint32_t n0, const uint32_t *rows_s, uint16_t *sOut, uint32_t wave,
+                                              uint32_t lane, GemmAcc &a, GemmC &c) {
+    typedef __attribute__((address_space(1))) uint64_t gu64w;
+    const uint32_t tid = threadIdx.x, wm = wave >> 2, wn = wave & 3;
+    constexpr int kHalf = kGemmHalf;
+    if constexpr (!PRE) gemm_cload(g, n0, [&](uint32_t r) { return rows_s[r]; }, c);
+    uint64_t(&cvals)[2][kHalf] = c.v;
     // the residues, in place of the ll sums
 #pragma unroll
     for (int i = 0; i < 4; i++)
@@ -446,8 +462,9 @@ __device__ __forceinline__ void mfma_gemm_tile(const fl::Mod &md, uint32_t bias,
     f.issue(kbeg, 0);
     f.issue(kbeg + 2 * BK, 1);
     GemmAcc a;
+    GemmC c;
     gemm_mainloop<ONE, false>(f, kbeg, kend, smem, lc, wave, lane, a);
-    gemm_epilogue<ONE, false>(md, lc, g, bx * BN, rows_s, (uint16_t *)smem, wave, lane, a);
+    gemm_epilogue<ONE, false>(md, lc, g, bx * BN, rows_s, (uint16_t *)smem, wave, lane, a, c);
 }
 
 // Rank-k update, k <= 64 KS (Gauss-Jordan panel and block updates, TRSM near
