@@ -1531,10 +1531,10 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             if ((e = hipStreamWaitEvent(stream, aux.ev_far, 0)) != hipSuccess) return e;
             aux.far_pending = false;
         }
-        if ((e = block_update(md, p, tasks, L, B, 0, kBlock, blk->bn_all, blk->bn_mfma, blk->bn_plain,
-                              blk->mfma_rows, at(L.pre_bn_all, B, L.n_all), at(L.pre_bn_mfma, B, L.n_mfma),
-                              at(L.pre_bn_plain, B, L.n_plain), false, kBlkColGroups, stream)) != hipSuccess)
-            return e;
+        // The far part (columns past the next block) needs only the block's
+        // panels, not the next block's update (disjoint columns), so the
+        // second stream starts it first.  (The wait above was enqueued before
+        // ev_far is recorded again.)
         if (blk->bf_all) {
             if ((e = hipEventRecord(aux.ev_near, stream)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(aux.far, aux.ev_near, 0)) != hipSuccess) return e;
@@ -1546,6 +1546,10 @@ hipError_t fl_echelon_batch_panel(uint32_t p, const FlEchTask *tasks, const FlEc
             if ((e = hipEventRecord(aux.ev_far, aux.far)) != hipSuccess) return e;
             aux.far_pending = true;
         }
+        if ((e = block_update(md, p, tasks, L, B, 0, kBlock, blk->bn_all, blk->bn_mfma, blk->bn_plain,
+                              blk->mfma_rows, at(L.pre_bn_all, B, L.n_all), at(L.pre_bn_mfma, B, L.n_mfma),
+                              at(L.pre_bn_plain, B, L.n_plain), false, kBlkColGroups, stream)) != hipSuccess)
+            return e;
     }
     if (g.n_next) {
         FL_PROF("echelon.check", stream,
