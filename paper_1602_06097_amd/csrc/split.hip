@@ -57,6 +57,8 @@ struct SplitDev {
     uint64_t *pivkey;    // [n]
     uint64_t *colscan;   // [n]  flag, then exclusive scan
     uint32_t *colmap;    // [n]
+    uint32_t *cbits;     // [n / 32 + 1] pivot-column flags, 32 columns per word
+    uint32_t *cbase;     // [n / 32 + 1] pivot columns before each word (colscan at its first column)
     // rows
     uint32_t *lead;      // [m]  leading column or kNone
     uint64_t *rowscan;   // [m]  non-pivot flag, then exclusive scan
@@ -132,12 +134,32 @@ __global__ void k_colflag(uint32_t n, SplitDev d) {
 
 __global__ void k_colmap(uint32_t n, SplitDev d, uint32_t *col_perm) {
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || failed(d.errkey)) return;
+    if (failed(d.errkey)) return;
+    {  // the compact map (colmap_of): one word of flags and its base per 32 columns
+        const uint64_t m = __ballot(c < n && d.pivkey[c] != kKeyNone);
+        if ((threadIdx.x & 31) == 0 && c < n) {
+            d.cbits[c >> 5] = (uint32_t)(m >> (threadIdx.x & 32));
+            d.cbase[c >> 5] = (uint32_t)d.colscan[c];
+        }
+    }
+    if (c >= n) return;
     uint32_t npiv = (uint32_t)d.tot[0];
     uint32_t before = (uint32_t)d.colscan[c];
     uint32_t nc = d.pivkey[c] != kKeyNone ? before : npiv + (c - before);
     d.colmap[c] = nc;
     col_perm[nc] = c;
+}
+
+// New column of input column c, from the compact map written by k_colmap
+// (equal to colmap[c]): pivot columns take their rank among the pivot
+// columns, the others follow in order after npiv.  The entries of a row
+// are in increasing column order, so 64 consecutive entries read a few
+// words of the map (a few cache lines) where colmap would take one line per
+// entry.
+__device__ __forceinline__ uint32_t colmap_of(const SplitDev &d, uint32_t c, uint32_t npiv) {
+    const uint32_t w = c >> 5, b = c & 31u, bits = d.cbits[w];
+    const uint32_t lo = d.cbase[w] + (uint32_t)__popc(bits & ((1u << b) - 1u));
+    return (bits >> b) & 1u ? lo : npiv + c - lo;
 }
 
 __device__ __forceinline__ bool is_pivot_row(uint32_t i, const SplitDev &d) {
@@ -187,7 +209,7 @@ __global__ __launch_bounds__(256) void k_count_bd(uint32_t m, const uint64_t *__
         for (int u = 0; u < 4; u++) c[u] = k0 + 64 * u < e ? ci[k0 + 64 * u] : 0;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            const uint32_t nc = d.colmap[c[u]];
+            const uint32_t nc = colmap_of(d, c[u], npiv);
             const bool in = k0 + 64 * u < e;
             cnt += in && nc >= npiv ? 1 : 0;
             if (in && ml_entry(nc, npiv, is_a, pos)) {
@@ -261,7 +283,7 @@ __global__ __launch_bounds__(256) void k_scatter_bd(uint32_t m, F f,
             x[u] = k < e ? v[k] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) nc[u] = d.colmap[c[u]];
+        for (int u = 0; u < 4; u++) nc[u] = colmap_of(d, c[u], npiv);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const bool take = k0 + 64 * u + lane < e && nc[u] >= npiv;
@@ -362,7 +384,7 @@ __global__ __launch_bounds__(256) void k_ml_count(uint32_t m, uint32_t w,
                     for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        const uint32_t nc = d.colmap[c[u]];
+                        const uint32_t nc = colmap_of(d, c[u], npiv);
                         if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
                             nc - w0 < kWinBits)
                             atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
@@ -435,7 +457,7 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
                 for (int u = 0; u < 4; u++) c[u] = k0 + u * blockDim.x < e ? ci[k0 + u * blockDim.x] : 0;
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
-                    const uint32_t nc = d.colmap[c[u]];
+                    const uint32_t nc = colmap_of(d, c[u], npiv);
                     if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
                         nc - w0 < kWinBits)
                         atomicOr(&bits[(nc - w0) >> 5], 1u << ((nc - w0) & 31));
@@ -497,7 +519,7 @@ __global__ __launch_bounds__(256) void k_ml_fill(uint32_t m, uint32_t w, F f,
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
-                    const uint32_t nc = d.colmap[c[u]];
+                    const uint32_t nc = colmap_of(d, c[u], npiv);
                     if (k0 + u * blockDim.x < e && ml_entry(nc, npiv, gi.is_a, r) && nc >= w0 &&
                         nc - w0 < kWinBits) {
                         uint32_t off = nc - w0;
@@ -546,6 +568,8 @@ size_t split_ws_layout(uint32_t m, uint32_t n, uint32_t w, void *ws, SplitDev *d
     t.pivkey = c.take<uint64_t>(n ? n : 1);
     t.colscan = c.take<uint64_t>(n ? n : 1);
     t.colmap = c.take<uint32_t>(n ? n : 1);
+    t.cbits = c.take<uint32_t>((size_t)n / 32 + 1);
+    t.cbase = c.take<uint32_t>((size_t)n / 32 + 1);
     t.lead = c.take<uint32_t>(m ? m : 1);
     t.rowscan = c.take<uint64_t>(m ? m : 1);
     t.rowpos = c.take<uint32_t>(m ? m : 1);
